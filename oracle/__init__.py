@@ -1,0 +1,220 @@
+"""CPU FP64 oracle for the exact thin-disc self-gravity kernel (arXiv 2506.10812).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or runs anything in this directory, and this module never imports the
+product package.  The arithmetic lives in ``sg_oracle.c`` (plain C, double
+precision, OpenMP over target cells); this file only marshals numpy arrays.
+
+Array layout everywhere: ``[fluid][i_r][j_phi]`` with phi fastest, fluid 0 =
+gas, 1 = dust.  Flags: bit 0 excludes the self-cell term.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+EXCLUDE_SELF = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (portable x86-64 AVX2 code, OpenMP)."""
+    cmd = ["gcc", "-O3", "-mavx2", "-mfma", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", _SRC, "-o", _LIB, "-lm"]
+    subprocess.check_call(cmd)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.sg_oracle_F.restype = ctypes.c_double
+        L.sg_oracle_F.argtypes = [ctypes.c_double]
+        L.sg_oracle_dF.restype = ctypes.c_double
+        L.sg_oracle_dF.argtypes = [ctypes.c_double]
+        L.sg_oracle_kernel.restype = ctypes.c_double
+        L.sg_oracle_kernel.argtypes = [ctypes.c_double] * 3
+        L.sg_oracle_conv_kernels.restype = None
+        L.sg_oracle_conv_kernels.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.sg_oracle_self_cell.restype = ctypes.c_double
+        L.sg_oracle_self_cell.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
+        L.sg_oracle_field_pairwise.restype = ctypes.c_int
+        L.sg_oracle_field_pairwise.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _dp, _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, _dp, _dp]
+        L.sg_oracle_field_table.restype = ctypes.c_int
+        L.sg_oracle_field_table.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, ctypes.c_int, _dp]
+        L.sg_oracle_adjoint_sigma.restype = ctypes.c_int
+        L.sg_oracle_adjoint_sigma.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, _dp]
+        L.sg_oracle_threads.restype = ctypes.c_int
+        L.sg_oracle_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _iptr(a):
+    return None if a is None else a.ctypes.data_as(_i64p)
+
+
+def threads() -> int:
+    return int(lib().sg_oracle_threads())
+
+
+def F(x):
+    """e^x [K1(x) - K0(x)] (App. A), elementwise."""
+    x = np.atleast_1d(_d(x))
+    return np.array([lib().sg_oracle_F(float(v)) for v in x.ravel()]).reshape(x.shape)
+
+
+def dF(x):
+    x = np.atleast_1d(_d(x))
+    return np.array([lib().sg_oracle_dF(float(v)) for v in x.ravel()]).reshape(x.shape)
+
+
+def kernel(s, Ha, Hb):
+    """K_ab(s; H_a, H_b), Eq. 'SG force kernel exact' (Sect. 2.2)."""
+    s, Ha, Hb = np.broadcast_arrays(_d(s), _d(Ha), _d(Hb))
+    out = np.empty(s.shape)
+    for idx in np.ndindex(s.shape):
+        out[idx] = lib().sg_oracle_kernel(float(s[idx]), float(Ha[idx]), float(Hb[idx]))
+    return out
+
+
+def conv_kernels(X, phi, ha, hb, which=0):
+    """App. C convolution kernels (K_r, K_phi) at offsets (X, phi).
+
+    which = 0: the kernels; 1: d/dh_a; 2: d/dh_b."""
+    X, phi = np.broadcast_arrays(_d(X), _d(phi))
+    X, phi = _d(X), _d(phi)
+    kr = np.empty(X.shape)
+    kp = np.empty(X.shape)
+    lib().sg_oracle_conv_kernels(X.size, _ptr(X), _ptr(phi), float(ha), float(hb), int(which),
+                                 _ptr(kr), _ptr(kp))
+    return kr, kp
+
+
+def self_cell(ha, hb, du, dphi, which=0):
+    """Principal-value cell average of K_r over the own cell (self term)."""
+    return float(lib().sg_oracle_self_cell(float(ha), float(hb), float(du), float(dphi),
+                                           int(which)))
+
+
+def _targets(targets):
+    if targets is None:
+        return None
+    return np.ascontiguousarray(targets, dtype=np.int64)
+
+
+def field_pairwise(nr, nphi, rmin, rmax, h, sigma, H=None, targets=None, flags=0):
+    """Plain pairwise Cartesian sum.  Returns (g_r, g_phi), each [nf][n_targets]."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    h = _d(np.atleast_1d(h))
+    Hd = None if H is None else _d(H)
+    t = _targets(targets)
+    nt = nr * nphi if t is None else t.size
+    gr = np.empty((nf, nt))
+    gp = np.empty((nf, nt))
+    rc = lib().sg_oracle_field_pairwise(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(Hd),
+                                        _ptr(sigma), nt, _iptr(t), flags, _ptr(gr), _ptr(gp))
+    if rc:
+        raise RuntimeError(f"sg_oracle_field_pairwise failed ({rc})")
+    return gr, gp
+
+
+def field_table_pairs(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0, which=0):
+    """Offset-table (App. C) sum per ordered pair: array [a][b][c][n_targets]."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    h = _d(np.atleast_1d(h))
+    t = _targets(targets)
+    nt = nr * nphi if t is None else t.size
+    out = np.empty((nf, nf, 2, nt))
+    rc = lib().sg_oracle_field_table(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(sigma), nt,
+                                     _iptr(t), flags, which, _ptr(out))
+    if rc:
+        raise RuntimeError(f"sg_oracle_field_table failed ({rc})")
+    return out
+
+
+def field_table(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0):
+    """Offset-table field summed over source fluids: (g_r, g_phi), each [nf][n_t]."""
+    out = field_table_pairs(nr, nphi, rmin, rmax, h, sigma, targets, flags, 0)
+    g = out.sum(axis=0)  # over source fluid a -> [b][c][nt]
+    return g[:, 0, :].copy(), g[:, 1, :].copy()
+
+
+def adjoint_sigma(nr, nphi, rmin, rmax, h, lam_r, lam_phi, kidx=None, flags=0):
+    """dL/dSigma from lam = dL/dg (transposed offset-table sum): [nf][n_k]."""
+    lam_r = _d(lam_r)
+    lam_phi = _d(lam_phi)
+    nf = lam_r.shape[0]
+    N = nr * nphi
+    lam = np.empty((nf, 2, N))
+    lam[:, 0] = lam_r.reshape(nf, N)
+    lam[:, 1] = lam_phi.reshape(nf, N)
+    h = _d(np.atleast_1d(h))
+    k = _targets(kidx)
+    nk = N if k is None else k.size
+    out = np.empty((nf, nk))
+    rc = lib().sg_oracle_adjoint_sigma(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(lam), nk,
+                                       _iptr(k), flags, _ptr(out))
+    if rc:
+        raise RuntimeError(f"sg_oracle_adjoint_sigma failed ({rc})")
+    return out
+
+
+def adjoint_h(nr, nphi, rmin, rmax, h, sigma, lam_r, lam_phi, flags=0):
+    """dL/dh_f for each fluid f from lam = dL/dg, by differentiating every
+    offset-table entry (including the self-cell term) with respect to h_a
+    (source) and h_b (target) and summing lam . (dK (*) Sigma) per pair."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    N = nr * nphi
+    lam = np.stack([_d(lam_r).reshape(nf, N), _d(lam_phi).reshape(nf, N)], axis=1)  # [b][c][N]
+    dh = np.zeros(nf)
+    for which, role in ((1, "a"), (2, "b")):
+        out = field_table_pairs(nr, nphi, rmin, rmax, h, sigma, None, flags, which)
+        for a in range(nf):
+            for b in range(nf):
+                v = float(np.sum(lam[b] * out[a, b]))
+                dh[a if role == "a" else b] += v
+    return dh
+
+
+def grid(nr, nphi, rmin, rmax):
+    """Cell centres (r_i, phi_j) and widths (du, dphi) of the oracle's grid."""
+    du = np.log(rmax / rmin) / nr
+    dphi = 2.0 * np.pi / nphi
+    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * du)
+    phi = (np.arange(nphi) + 0.5) * dphi
+    return r, phi, du, dphi

@@ -1,0 +1,530 @@
+/*
+ * sg_oracle.c -- CPU FP64 reference ("oracle") for the exact thin-disc
+ * self-gravity kernel of Rendon Restrepo, Rometsch, Ziegler & Gressel,
+ * "Self-gravity in thin protoplanetary discs 1" (arXiv 2506.10812).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code, header, table or constant
+ * with the HIP library; both sides only receive the same seeded inputs.
+ *
+ * Everything is plain double precision, written to be checked by eye
+ * against the paper.  Speed is obtained only from OpenMP over target cells
+ * and from a contiguous inner loop; no blocking or reordering of the sums.
+ *
+ * Discrete problem (readings of points the paper leaves open are marked
+ * "reading"):
+ *   grid      log-spaced radial cell edges r_min..r_max (reading: the range
+ *             gives cell edges), centres u_i = ln r_min + (i+1/2) du,
+ *             du = ln(r_max/r_min)/N_r; phi_j = (j+1/2) dphi, dphi = 2 pi/N_phi
+ *             (the log-r x uniform-phi grid of Sect. 5.2 / App. C).
+ *   area      A_i = r_i^2 du dphi (midpoint rule in u; reading).
+ *   field     g^{a->b}(x_i) = - sum_{k != i} Sigma_a[k] A_k K_ab(s_ik) e_s
+ *             (Eq. "volume force 2D" of Sect. 2.2 divided by Sigma_b; the
+ *             target fluid b sits at x_i, the source fluid a at x_k) plus a
+ *             self-cell term (reading: the principal-value cell average of
+ *             the log-polar radial kernel over the own cell; the paper does
+ *             not discuss the k = i term).
+ *   kernel    K_ab = pi^{-1/2} H_ab^{-2} (d/8) e^x [K1(x) - K0(x)],
+ *             x = d^2/8, d = s/H_ab, H_ab^2 = (H_a^2 + H_b^2)/2
+ *             (Eq. "SG force kernel exact" and Eq. "mean root square height"
+ *             of Sect. 2.2; the table of abbreviations drops the squares in
+ *             H_ab, the equation is followed).
+ *
+ * Parity status of each exported function is stated at the function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_SQRT_PI 1.77245385090551602730
+
+/* ------------------------------------------------------------------------
+ * F(x) = e^x [K1(x) - K0(x)]  and  F'(x).
+ *
+ * App. A reaches e^{x/4}[K1 - K0](x/4) through the integral F_1; here the
+ * same function is evaluated from the textbook integral representation
+ * K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt (Abramowitz & Stegun
+ * 9.6.24).  Subtracting nu = 0 from nu = 1 and multiplying by e^x gives the
+ * cancellation-free form
+ *     F(x) = int_0^inf exp(-x c(t)) c(t) dt,   c(t) = cosh t - 1 = 2 sinh^2(t/2),
+ * and, differentiating under the integral,
+ *     F'(x) = - int_0^inf exp(-x c(t)) c(t)^2 dt.
+ * The integrand is even and entire in t and decays double-exponentially,
+ * so the trapezoidal rule converges geometrically.  Step: h = min(1/5,
+ * 2/(5 sqrt x)) keeps both aliasing terms (strip |Im t| < pi/2, and the
+ * Gaussian width 1/sqrt(x) at large x) below e^-49.  Cut-off T solves
+ * x c(T) = 60.  Parity pinned against mpmath Bessel values in the tests.
+ * ------------------------------------------------------------------------ */
+static void orc_F_dF(double x, double *F, double *dF)
+{
+    double h = 0.2;
+    if (0.4 / sqrt(x) < h) h = 0.4 / sqrt(x);
+    double T = 2.0 * asinh(sqrt(30.0 / x));
+    long n = (long)ceil(T / h);
+    double sF = 0.0, sD = 0.0;
+    for (long k = 1; k <= n; ++k) {
+        double sh = sinh(0.5 * (double)k * h);
+        double c = 2.0 * sh * sh;
+        double e = exp(-x * c);
+        sF += e * c;
+        sD += e * c * c;
+    }
+    *F = h * sF;          /* the t = 0 node carries weight h/2 and value 0 */
+    if (dF) *dF = -h * sD;
+}
+
+double sg_oracle_F(double x)
+{
+    double F;
+    orc_F_dF(x, &F, NULL);
+    return F;
+}
+
+double sg_oracle_dF(double x)
+{
+    double F, dF;
+    orc_F_dF(x, &F, &dF);
+    return dF;
+}
+
+/* Exact kernel K_ab(s; H_a, H_b), Eq. "SG force kernel exact" (Sect. 2.2),
+ * with H_ab from Eq. "mean root square height".  Parity pinned against the
+ * vertical double integral of Eq. "SG force kernel general" (brute-force
+ * quadrature in the tests), the small-d limit of Sect. 3.4, the razor-thin
+ * limit of Sect. 4 and the planet special case of Sect. 4. */
+double sg_oracle_kernel(double s, double Ha, double Hb)
+{
+    double Hab2 = 0.5 * (Ha * Ha + Hb * Hb);
+    double d = s / sqrt(Hab2);
+    double x = d * d / 8.0;
+    return (1.0 / ORC_SQRT_PI) / Hab2 * (d / 8.0) * sg_oracle_F(x);
+}
+
+/* ------------------------------------------------------------------------
+ * Convolution-form kernels of App. C (H_f = h_f r):
+ *   h_ab^2   = (h_a^2 e^{-X} + h_b^2 e^{X}) / 2        (App. C; the printed
+ *              "H_ab/(r r')" lacks a square, the right-hand side is used)
+ *   d_ab^2   = 2 (cosh X - cos phi) / h_ab^2
+ *   L_ab     = sqrt(pi) (d^2/8) F(d^2/8)
+ *   K_r      = L/(pi d^2) [e^{-X}/h_ab^2]^{3/2} (e^X - cos phi)
+ *   K_phi    = L/(pi d^2) [e^{-X}/h_ab^2]^{3/2} sin phi
+ * X = u_target - u_source, phi = phi_target - phi_source.  With these, the
+ * field is a pure convolution in (u, phi):
+ *   g_r(u,phi) = - int Sigma_a(u',phi') K_r(u-u', phi-phi') du' dphi'.
+ * cosh X - cos phi is evaluated as 2 sinh^2(X/2) + 2 sin^2(phi/2) and
+ * e^X - cos phi as expm1(X) + 2 sin^2(phi/2) (identities; no cancellation).
+ *
+ * which = 0: (K_r, K_phi); 1: d/dh_a of both; 2: d/dh_b of both.
+ * Derivative: with G = K h^3/F (independent of h), x = (cosh X - cos phi)
+ * /(4 h^2), dK/d(h^2) = G (h^2)^{-5/2} [-x F'(x) - 3/2 F(x)], and
+ * d(h^2)/dh_a = h_a e^{-X}, d(h^2)/dh_b = h_b e^{X}.
+ * Parity pinned against the pairwise Cartesian sum (tests) and, for the
+ * derivatives, against central differences of which = 0.
+ * ------------------------------------------------------------------------ */
+static void orc_conv(double X, double phi, double ha, double hb, int which,
+                     double *Kr, double *Kphi)
+{
+    double h2 = 0.5 * (ha * ha * exp(-X) + hb * hb * exp(X));
+    double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
+    double cosh_m_cos = 2.0 * sx * sx + 2.0 * sp * sp;
+    double eX_m_cos = expm1(X) + 2.0 * sp * sp;
+    double d2 = 2.0 * cosh_m_cos / h2;
+    double x = d2 / 8.0;
+    double F, dF;
+    orc_F_dF(x, &F, &dF);
+    if (which == 0) {
+        double L = ORC_SQRT_PI * x * F;
+        double pref = L / (ORC_PI * d2) * pow(exp(-X) / h2, 1.5);
+        *Kr = pref * eX_m_cos;
+        *Kphi = pref * sin(phi);
+        return;
+    }
+    /* G = e^{-3X/2} / (8 sqrt(pi)) times the angular factor */
+    double G = exp(-1.5 * X) / (8.0 * ORC_SQRT_PI);
+    double dK_dh2 = G * pow(h2, -2.5) * (-x * dF - 1.5 * F);
+    double dh2 = (which == 1) ? ha * exp(-X) : hb * exp(X);
+    *Kr = dK_dh2 * dh2 * eX_m_cos;
+    *Kphi = dK_dh2 * dh2 * sin(phi);
+}
+
+void sg_oracle_conv_kernels(int64_t n, const double *X, const double *phi,
+                            double ha, double hb, int which,
+                            double *Kr, double *Kphi)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) orc_conv(X[i], phi[i], ha, hb, which, &Kr[i], &Kphi[i]);
+}
+
+/* ------------------------------------------------------------------------
+ * Self-cell term (reading; the paper is silent on k = i).
+ * Kbar = (1/(du dphi)) PV-int over the own cell [-du/2,du/2]x[-dphi/2,dphi/2]
+ * of K_r(X, phi).  K_r is even in phi; its 1/rho singularity is odd in X,
+ * so the X-symmetrised integrand S = (K_r(X,phi) + K_r(-X,phi))/2 is
+ * bounded and Kbar = (1/(a b)) int_0^a int_0^b S, a = du/2, b = dphi/2.
+ * The quarter cell is split along its diagonal into two triangles with a
+ * vertex at the singular corner and integrated in polar coordinates about
+ * that corner (the Jacobian rho removes the direction-dependent jump) by
+ * 48 x 48-point Gauss-Legendre rules.  The integrand in rho is
+ * rho S0(theta) + O(rho^3 ln rho), for which the rule is accurate to ~1e-12.
+ * Parity pinned by brute-force midpoint sums with Richardson extrapolation
+ * and by the closed-form small-cell limit (tests).  which: as orc_conv.
+ * ------------------------------------------------------------------------ */
+#define ORC_GL_N 48
+static double orc_gl_x[ORC_GL_N], orc_gl_w[ORC_GL_N];
+static int orc_gl_ready = 0;
+
+/* Gauss-Legendre nodes on [0,1] by Newton iteration on P_n (textbook). */
+static void orc_legendre(int n, double z, double *p, double *dp)
+{
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    *p = p1;
+    *dp = n * (z * p1 - p0) / (z * z - 1.0);
+}
+
+static void orc_gl_init(void)
+{
+    if (orc_gl_ready) return;
+    const int n = ORC_GL_N;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(ORC_PI * (i + 0.75) / (n + 0.5)), p, dp;
+        for (int it = 0; it < 100; ++it) {
+            orc_legendre(n, z, &p, &dp);
+            double dz = p / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        orc_legendre(n, z, &p, &dp);
+        /* map [-1,1] -> [0,1]: node (1-z)/2, weight w/2 with w = 2/((1-z^2) P_n'^2) */
+        orc_gl_x[i] = 0.5 * (1.0 - z);
+        orc_gl_w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+    orc_gl_ready = 1;
+}
+
+static double orc_sym_Kr(double X, double phi, double ha, double hb, int which)
+{
+    double k1, k2, t;
+    orc_conv(X, phi, ha, hb, which, &k1, &t);
+    orc_conv(-X, phi, ha, hb, which, &k2, &t);
+    return 0.5 * (k1 + k2);
+}
+
+double sg_oracle_self_cell(double ha, double hb, double du, double dphi, int which)
+{
+    orc_gl_init();
+    const double a = 0.5 * du, b = 0.5 * dphi;
+    const double thc = atan2(b, a);
+    double total = 0.0;
+    for (int tri = 0; tri < 2; ++tri) {
+        double th0 = tri == 0 ? 0.0 : thc;
+        double th1 = tri == 0 ? thc : 0.5 * ORC_PI;
+        double acc = 0.0;
+        for (int i = 0; i < ORC_GL_N; ++i) {
+            double th = th0 + (th1 - th0) * orc_gl_x[i];
+            double c = cos(th), s = sin(th);
+            double rmax = tri == 0 ? a / c : b / s;
+            double inner = 0.0;
+            for (int j = 0; j < ORC_GL_N; ++j) {
+                double rho = rmax * orc_gl_x[j];
+                inner += orc_gl_w[j] * rho * orc_sym_Kr(rho * c, rho * s, ha, hb, which);
+            }
+            acc += orc_gl_w[i] * inner * rmax;
+        }
+        total += acc * (th1 - th0);
+    }
+    return total / (a * b);
+}
+
+/* ------------------------------------------------------------------------
+ * Grid helpers (log r x uniform phi).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int nr, nphi;
+    double du, dphi, lnrmin;
+} orc_grid;
+
+static orc_grid orc_make_grid(int nr, int nphi, double rmin, double rmax)
+{
+    orc_grid g;
+    g.nr = nr;
+    g.nphi = nphi;
+    g.lnrmin = log(rmin);
+    g.du = log(rmax / rmin) / nr;
+    g.dphi = 2.0 * ORC_PI / nphi;
+    return g;
+}
+static double orc_r(const orc_grid *g, int i) { return exp(g->lnrmin + (i + 0.5) * g->du); }
+static double orc_phi(const orc_grid *g, int j) { return (j + 0.5) * g->dphi; }
+
+#define ORC_FLAG_EXCLUDE_SELF 1u
+
+/* small direct-mapped memo of self-cell values keyed on (ha, hb) bits */
+typedef struct {
+    double ha, hb, v;
+    int used;
+} orc_memo;
+
+static double orc_self_memo(orc_memo *m, int nm, double ha, double hb, double du, double dphi)
+{
+    uint64_t ka, kb;
+    memcpy(&ka, &ha, 8);
+    memcpy(&kb, &hb, 8);
+    uint64_t key = (ka * 0x9E3779B97F4A7C15ull) ^ (kb + (ka >> 7));
+    orc_memo *e = &m[key % (uint64_t)nm];
+    if (e->used && e->ha == ha && e->hb == hb) return e->v;
+    double v = sg_oracle_self_cell(ha, hb, du, dphi, 0);
+    e->ha = ha;
+    e->hb = hb;
+    e->v = v;
+    e->used = 1;
+    return v;
+}
+
+/* ------------------------------------------------------------------------
+ * Pairwise (plain definition) field.
+ * For each requested target cell i and target fluid b:
+ *   G = - sum_a sum_{k != i} Sigma_a[k] A_k K_ab(|x_i - x_k|; H_a[k], H_b[i])
+ *         (x_i - x_k)/|x_i - x_k|          (Cartesian vectors)
+ *   g_r = G . e_r(phi_i),  g_phi = G . e_phi(phi_i)
+ *   plus, unless excluded, the self term
+ *   g_r += - du dphi sum_a Sigma_a[i] Kbar_r^{ab}(h_a = H_a[i]/r_i, h_b = H_b[i]/r_i).
+ * H == NULL means H_f = h[f] r.  Layout: arrays [fluid][i_r][j_phi].
+ * Outputs gr, gphi: [n_fluids][n_targets].
+ * Parity pinned by Newton's third law, axisymmetry, the razor-thin
+ * Newtonian sum, hand-computed two/three-cell systems (tests).
+ * ------------------------------------------------------------------------ */
+int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
+                             const double *h, const double *H, const double *sigma,
+                             int64_t nt, const int64_t *targets, unsigned flags,
+                             double *gr, double *gphi)
+{
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_gl_init();
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    const int64_t N = (int64_t)nr * nphi;
+    double *xs = malloc(sizeof(double) * N), *ys = malloc(sizeof(double) * N);
+    double *A = malloc(sizeof(double) * N), *Hc = malloc(sizeof(double) * nf * N);
+    double *rr = malloc(sizeof(double) * N);
+    if (!xs || !ys || !A || !Hc || !rr) return 2;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nphi; ++j) {
+            int64_t k = (int64_t)i * nphi + j;
+            double r = orc_r(&g, i), p = orc_phi(&g, j);
+            rr[k] = r;
+            xs[k] = r * cos(p);
+            ys[k] = r * sin(p);
+            A[k] = r * r * g.du * g.dphi;
+            for (int f = 0; f < nf; ++f) Hc[f * N + k] = H ? H[f * N + k] : h[f] * r;
+        }
+    const int want_self = !(flags & ORC_FLAG_EXCLUDE_SELF);
+#pragma omp parallel
+    {
+        orc_memo memo[64];
+        memset(memo, 0, sizeof(memo));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < nt; ++t) {
+            int64_t i = targets ? targets[t] : t;
+            double cp = xs[i] / rr[i], sp = ys[i] / rr[i];
+            for (int b = 0; b < nf; ++b) {
+                double Gx = 0.0, Gy = 0.0, gself = 0.0;
+                for (int a = 0; a < nf; ++a) {
+                    const double *Sa = sigma + a * N;
+                    const double *Ha = Hc + a * N;
+                    double Hb = Hc[b * N + i];
+                    for (int64_t k = 0; k < N; ++k) {
+                        if (k == i) continue;
+                        double dx = xs[i] - xs[k], dy = ys[i] - ys[k];
+                        double s = sqrt(dx * dx + dy * dy);
+                        double K = sg_oracle_kernel(s, Ha[k], Hb);
+                        double w = Sa[k] * A[k] * K / s;
+                        Gx -= w * dx;
+                        Gy -= w * dy;
+                    }
+                    if (want_self) {
+                        double ha = Ha[i] / rr[i], hb = Hb / rr[i];
+                        if (!H) {
+                            ha = h[a];
+                            hb = h[b];
+                        }
+                        double kb = orc_self_memo(memo, 64, ha, hb, g.du, g.dphi);
+                        gself -= g.du * g.dphi * Sa[i] * kb;
+                    }
+                }
+                gr[b * nt + t] = Gx * cp + Gy * sp + gself;
+                gphi[b * nt + t] = -Gx * sp + Gy * cp;
+            }
+        }
+    }
+    free(xs);
+    free(ys);
+    free(A);
+    free(Hc);
+    free(rr);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Offset-table (log-polar) field, H_f = h_f r (App. C convolution form):
+ *   out^{a->b}_c[i] = - du dphi sum_{i'} Sigma_a[i'] T_c^{ab}(i_r - i'_r, j - j')
+ * with T_c^{ab}(p, q) = K_c(p du, q dphi) from orc_conv (which = deriv) and
+ * T_r(0,0) = self-cell term (0 when excluded), T_phi(0,0) = 0.
+ * Output out: [a][b][c][n_targets], c = 0 (r), 1 (phi), NOT summed over a,
+ * so that derivatives can be attached to the right pair by the caller.
+ * Parity: equals the pairwise sum (tests, 1e-12) and is the same discrete
+ * problem.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int nr, nphi;
+    double *Tr, *Tp; /* [(2nr-1)][2 nphi], reversed-and-doubled in phi */
+} orc_table;
+
+/* Build T for one pair.  Storage R[p][m] = T(p - (nr-1), (N - (m mod N)) mod N)
+ * for m in [0, 2N), so that T(i_r - i', j - j') = R[i_r - i' + nr - 1][j' - j + N]
+ * and the inner sum over j' reads R contiguously. */
+static int orc_build_table(const orc_grid *g, double ha, double hb, int which, int want_self,
+                           orc_table *t)
+{
+    const int nr = g->nr, np = g->nphi;
+    const int P = 2 * nr - 1;
+    t->nr = nr;
+    t->nphi = np;
+    t->Tr = malloc(sizeof(double) * (size_t)P * 2 * np);
+    t->Tp = malloc(sizeof(double) * (size_t)P * 2 * np);
+    if (!t->Tr || !t->Tp) return 2;
+    double self = want_self ? sg_oracle_self_cell(ha, hb, g->du, g->dphi, which) : 0.0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < P; ++p) {
+        double X = (double)(p - (nr - 1)) * g->du;
+        for (int q = 0; q < np; ++q) {
+            double kr, kp;
+            if (p == nr - 1 && q == 0) {
+                kr = self;
+                kp = 0.0;
+            } else {
+                orc_conv(X, (double)q * g->dphi, ha, hb, which, &kr, &kp);
+            }
+            /* T(p, q) goes to every m with (N - m) mod N == q */
+            int m0 = (np - q) % np;
+            t->Tr[(size_t)p * 2 * np + m0] = kr;
+            t->Tr[(size_t)p * 2 * np + m0 + np] = kr;
+            t->Tp[(size_t)p * 2 * np + m0] = kp;
+            t->Tp[(size_t)p * 2 * np + m0 + np] = kp;
+        }
+    }
+    return 0;
+}
+
+static void orc_free_table(orc_table *t)
+{
+    free(t->Tr);
+    free(t->Tp);
+}
+
+int sg_oracle_field_table(int nr, int nphi, double rmin, double rmax, int nf, const double *h,
+                          const double *sigma, int64_t nt, const int64_t *targets,
+                          unsigned flags, int which, double *out)
+{
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (which < 0 || which > 2) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    const int64_t N = (int64_t)nr * nphi;
+    const double scale = -g.du * g.dphi;
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) {
+            orc_table T;
+            if (orc_build_table(&g, h[a], h[b], which, !(flags & ORC_FLAG_EXCLUDE_SELF), &T))
+                return 2;
+            const double *Sa = sigma + a * N;
+            double *o_r = out + ((size_t)(a * nf + b) * 2 + 0) * nt;
+            double *o_p = out + ((size_t)(a * nf + b) * 2 + 1) * nt;
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t t = 0; t < nt; ++t) {
+                int64_t i = targets ? targets[t] : t;
+                int ir = (int)(i / nphi), j = (int)(i % nphi);
+                double sr = 0.0, sp = 0.0;
+                for (int ip = 0; ip < nr; ++ip) {
+                    const double *row = Sa + (size_t)ip * nphi;
+                    const double *Rr = T.Tr + (size_t)(ir - ip + nr - 1) * 2 * nphi + (nphi - j);
+                    const double *Rp = T.Tp + (size_t)(ir - ip + nr - 1) * 2 * nphi + (nphi - j);
+                    double ar = 0.0, ap = 0.0;
+                    for (int jp = 0; jp < nphi; ++jp) {
+                        ar += row[jp] * Rr[jp];
+                        ap += row[jp] * Rp[jp];
+                    }
+                    sr += ar;
+                    sp += ap;
+                }
+                o_r[t] = scale * sr;
+                o_p[t] = scale * sp;
+            }
+            orc_free_table(&T);
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Adjoint with respect to Sigma (transposed offset-table sum):
+ *   dL/dSigma_a[k] = - du dphi sum_b sum_c sum_i lam_{b,c}[i] T_c^{ab}(i - k)
+ * lam: [b][c][N] (c = 0: dL/dg_r, 1: dL/dg_phi).  Output: [a][n_k].
+ * Parity pinned by central differences of sg_oracle_field_table (exact for
+ * a loss that is quadratic in Sigma) in the tests.
+ * ------------------------------------------------------------------------ */
+int sg_oracle_adjoint_sigma(int nr, int nphi, double rmin, double rmax, int nf, const double *h,
+                            const double *lam, int64_t nk, const int64_t *kidx, unsigned flags,
+                            double *dsigma)
+{
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    const int64_t N = (int64_t)nr * nphi;
+    const double scale = -g.du * g.dphi;
+    for (int64_t t = 0; t < (int64_t)nf * nk; ++t) dsigma[t] = 0.0;
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) {
+            orc_table T;
+            if (orc_build_table(&g, h[a], h[b], 0, !(flags & ORC_FLAG_EXCLUDE_SELF), &T)) return 2;
+            const double *lr = lam + ((size_t)b * 2 + 0) * N;
+            const double *lp = lam + ((size_t)b * 2 + 1) * N;
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t t = 0; t < nk; ++t) {
+                int64_t k = kidx ? kidx[t] : t;
+                int kr = (int)(k / nphi), kj = (int)(k % nphi);
+                double acc = 0.0;
+                for (int ir = 0; ir < nr; ++ir) {
+                    /* T(ir - kr, j - kj) = R[ir - kr + nr - 1][kj - j + N];  as j
+                     * increases the index decreases, so walk it backwards. */
+                    const double *Rr = T.Tr + (size_t)(ir - kr + nr - 1) * 2 * nphi;
+                    const double *Rp = T.Tp + (size_t)(ir - kr + nr - 1) * 2 * nphi;
+                    const double *l1 = lr + (size_t)ir * nphi, *l2 = lp + (size_t)ir * nphi;
+                    double s = 0.0;
+                    for (int j = 0; j < nphi; ++j) {
+                        int m = kj - j + nphi;
+                        s += l1[j] * Rr[m] + l2[j] * Rp[m];
+                    }
+                    acc += s;
+                }
+                dsigma[(size_t)a * nk + t] += scale * acc;
+            }
+            orc_free_table(&T);
+        }
+    return 0;
+}
+
+int sg_oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,392 @@
+"""Pins of the CPU FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each compares the oracle with an
+independent route (arbitrary-precision Bessel functions, brute-force
+quadrature of the vertical double integral, closed-form limits printed in the
+paper, conservation laws, brute-force sub-cell sums, a continuum closed form).
+"""
+import json
+import math
+from fractions import Fraction
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as ss
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+mp.mp.dps = 40
+
+
+def _F_mp(x):
+    x = mp.mpf(x)
+    return mp.e ** x * (mp.besselk(1, x) - mp.besselk(0, x))
+
+
+def _dF_mp(x):
+    x = mp.mpf(x)
+    return mp.e ** x * (2 * mp.besselk(1, x) - 2 * mp.besselk(0, x) - mp.besselk(1, x) / x)
+
+
+# --------------------------------------------------------------------- F(x)
+def test_F_matches_arbitrary_precision_bessel():
+    """F(x) = e^x [K1 - K0](x) (App. A) vs 40-digit mpmath Bessel functions."""
+    for x in np.logspace(-12, 4.6, 45):
+        ref = float(_F_mp(x))
+        assert abs(O.F(x)[0] - ref) <= 2e-15 * ref, x
+
+
+def test_dF_matches_arbitrary_precision_bessel():
+    """F'(x) = e^x [2K1 - 2K0 - K1/x] (derivative of App. A's F) vs mpmath."""
+    for x in np.logspace(-12, 4.6, 45):
+        ref = float(_dF_mp(x))
+        assert abs(O.dF(x)[0] - ref) <= 2e-15 * abs(ref), x
+
+
+# ------------------------------------------------------------------- kernel
+@pytest.mark.parametrize("s,Ha,Hb", [(0.7, 1.0, 1.0), (2.0, 1.0, 0.4), (5.0, 0.3, 1.2),
+                                     (0.35, 0.5, 0.2), (9.0, 1.0, 1.0)])
+def test_kernel_equals_vertical_double_integral(s, Ha, Hb):
+    """Closed form (Sect. 2.2, Eq. 'SG force kernel exact') vs brute-force
+    quadrature of the double integral over z, z' (Eq. 'SG force kernel general')."""
+    # substitute z = Hb u, z' = Ha v: K = s/(2 pi) int int e^{-(u^2+v^2)/2}
+    #                                        / (s^2 + (Hb u - Ha v)^2)^{3/2} du dv
+    f = lambda v, u: math.exp(-0.5 * (u * u + v * v)) / (s * s + (Hb * u - Ha * v) ** 2) ** 1.5
+    val, err = si.dblquad(f, -10, 10, -10, 10, epsabs=0, epsrel=1e-12)
+    ref = s / (2 * math.pi) * val
+    assert abs(O.kernel(s, Ha, Hb) - ref) <= 1e-9 * ref
+
+
+def test_kernel_short_range_limit():
+    """Light-disc singularity (Sect. 3.4): K ~ 1/(sqrt(pi) H s) as d -> 0."""
+    H = 0.05
+    for d in (1e-3, 1e-4, 1e-5):
+        s = d * H
+        k = O.kernel(s, H, H)
+        assert abs(k * math.sqrt(math.pi) * H * s - 1.0) < 3.0 * d * d * abs(math.log(d)) + 1e-13
+
+
+def test_kernel_razor_thin_limit():
+    """H -> 0 gives the flat-disc kernel 1/s^2 (Sect. 4, razor-thin test)."""
+    for s in (0.1, 1.0, 3.0):
+        for H in (1e-4, 1e-6):
+            assert abs(O.kernel(s, H, H) * s * s - 1.0) < 4.0 * (H / s) ** 2 + 1e-14
+
+
+def test_kernel_large_distance_paper_expansion():
+    """The three-term expansion printed in Sect. 5.3 (overflow fix) for x > 50;
+    its error must be the next term, 525/1024 x^-3 relative."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        g = json.load(fh)["large_x_expansion"]
+    c = [float(Fraction(t)) for t in g["coefficients"]]
+    H = 1.0
+    for x in (50.0, 88.0, 300.0, 5000.0):
+        d = math.sqrt(8 * x)
+        s = d * H
+        series = (1 / (2 * math.sqrt(2))) * H ** -2 / d * (c[0] * x ** -0.5 + c[1] * x ** -1.5
+                                                          + c[2] * x ** -2.5)
+        k = O.kernel(s, H, H)
+        rel = (series - k) / k
+        nxt = 525.0 / 1024.0 / x ** 3
+        assert abs(rel - nxt) < 0.05 * nxt + 1e-15, (x, rel, nxt)
+
+
+def test_kernel_planet_special_case():
+    """Planet as a fluid with zero thickness (Sect. 4): with H_a = 0 the kernel
+    reproduces the printed planet-disc force, with c^2 = s^2/(4 H_g^2)."""
+    Hg = 0.07
+    for s in (0.01, 0.05, 0.2, 1.0):
+        c2 = s * s / (4 * Hg * Hg)
+        paper = (1 / s) * math.sqrt(2 / math.pi) / Hg * c2 * float(_F_mp(c2))
+        assert abs(O.kernel(s, 0.0, Hg) - paper) < 1e-13 * paper
+
+
+def test_kernel_dust_ratios():
+    """Dust kernels (Sect. 3.3): K_dd/K_gg -> 1/eta and K_dg/K_gg -> sqrt(2/(1+eta^2))
+    (-> sqrt 2) at d_g << eta; both -> 1 at large distance."""
+    Hg = 1.0
+    for eta in (0.3, 0.1, 0.01):
+        s = 1e-4 * eta
+        kgg = O.kernel(s, Hg, Hg)
+        kdd = O.kernel(s, eta * Hg, eta * Hg)
+        kdg = O.kernel(s, eta * Hg, Hg)
+        assert abs(kdd / kgg * eta - 1) < 2e-3
+        assert abs(kdg / kgg - math.sqrt(2 / (1 + eta * eta))) < 2e-3
+        s = 300.0
+        assert abs(O.kernel(s, eta, eta) / O.kernel(s, 1, 1) - 1) < 1e-4
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        lim = json.load(fh)["dust_gas_short_range_limit"]
+    assert abs(O.kernel(1e-9, 1e-5, 1.0) / O.kernel(1e-9, 1.0, 1.0) - float(lim["value"])) < 1e-6
+
+
+def test_kernel_symmetric_in_fluids():
+    """Newton's third law between two columns (Sect. 2.2): K_ab = K_ba."""
+    for s, a, b in ((0.3, 0.05, 0.01), (2.0, 0.2, 0.9)):
+        assert O.kernel(s, a, b) == pytest.approx(O.kernel(s, b, a), rel=1e-15)
+
+
+def test_conv_kernels_equal_cartesian_projection():
+    """App. C convolution kernels vs the Cartesian kernel times the projection of
+    e_s on e_r, e_phi and the source area factor r'^2 (pure geometry)."""
+    rng = np.random.default_rng(5)
+    ha, hb = 0.05, 0.005
+    u = rng.uniform(-2, 2, 300)
+    up = rng.uniform(-2, 2, 300)
+    ph = rng.uniform(-np.pi, np.pi, 300)
+    kr, kp = O.conv_kernels(u - up, ph, ha, hb)
+    r, rp = np.exp(u), np.exp(up)
+    xt = np.stack([r, np.zeros_like(r)])
+    xs = np.stack([rp * np.cos(-ph), rp * np.sin(-ph)])
+    dv = xt - xs
+    s = np.hypot(dv[0], dv[1])
+    K = O.kernel(s, ha * rp, hb * r)
+    refr = K * dv[0] / s * rp ** 2
+    refp = K * dv[1] / s * rp ** 2
+    np.testing.assert_allclose(kr, refr, rtol=1e-10, atol=1e-12 * np.abs(refr).max())
+    np.testing.assert_allclose(kp, refp, rtol=1e-10, atol=1e-12 * np.abs(refp).max())
+
+
+def test_conv_kernel_h_derivatives_match_central_differences():
+    """d/dh_a and d/dh_b of the App. C kernels vs central differences."""
+    X = np.array([0.02, -0.3, 0.7, 1e-3])
+    phi = np.array([0.01, 0.4, -1.0, 2e-3])
+    ha, hb, e = 0.05, 0.01, 1e-6
+    for which, (da, db) in ((1, (e, 0)), (2, (0, e))):
+        d_r, d_p = O.conv_kernels(X, phi, ha, hb, which)
+        p_r, p_p = O.conv_kernels(X, phi, ha + da, hb + db)
+        m_r, m_p = O.conv_kernels(X, phi, ha - da, hb - db)
+        np.testing.assert_allclose(d_r, (p_r - m_r) / (2 * e), rtol=1e-6)
+        np.testing.assert_allclose(d_p, (p_p - m_p) / (2 * e), rtol=1e-6)
+
+
+# ---------------------------------------------------------------- self cell
+def _self_cell_bruteforce(ha, hb, du, dphi, n):
+    """Midpoint rule on an n x n grid of the X-symmetrised quarter cell."""
+    a, b = du / 2, dphi / 2
+    X = (np.arange(n) + 0.5) * a / n
+    P = (np.arange(n) + 0.5) * b / n
+    XX, PP = np.meshgrid(X, P, indexing="ij")
+    k1, _ = O.conv_kernels(XX.ravel(), PP.ravel(), ha, hb)
+    k2, _ = O.conv_kernels(-XX.ravel(), PP.ravel(), ha, hb)
+    return float(np.mean(0.5 * (k1 + k2)))
+
+
+@pytest.mark.parametrize("ha,hb,du,dphi", [(0.05, 0.05, 0.0395, 0.0491),
+                                            (0.05, 0.005, 0.00314, 0.00307),
+                                            (0.01, 0.05, 0.02, 0.005)])
+def test_self_cell_bruteforce(ha, hb, du, dphi):
+    """Self-cell average (reading: PV cell average of K_r) vs brute-force
+    midpoint sums, Richardson-extrapolated in the sub-cell count."""
+    n1, n2 = 400, 800
+    v1 = _self_cell_bruteforce(ha, hb, du, dphi, n1)
+    v2 = _self_cell_bruteforce(ha, hb, du, dphi, n2)
+    extrap = (4 * v2 - v1) / 3
+    v = O.self_cell(ha, hb, du, dphi)
+    assert abs(v - extrap) < 2e-5 * abs(v), (v, v1, v2, extrap)
+
+
+@pytest.mark.parametrize("ha,hb,du,dphi", [(0.05, 0.05, 1e-6, 1e-6), (0.05, 0.005, 1e-7, 3e-7),
+                                            (0.01, 0.04, 4e-7, 1e-7)])
+def test_self_cell_small_cell_limit(ha, hb, du, dphi):
+    """Closed form of the limit of tiny cells: with h0^2 = (h_a^2+h_b^2)/2 and
+    c = (h_b^2-h_a^2)/(4 h0^2), Kbar -> (1/(sqrt(pi) h0)) [1/2 - (3/2+c) <cos^2>]
+    where <cos^2> is the area mean of X^2/(X^2+phi^2) over the cell."""
+    a, b = du / 2, dphi / 2
+    cos2 = 0.5 + (a * a * math.atan(b / a) - b * b * math.atan(a / b)) / (2 * a * b)
+    h0 = math.sqrt(0.5 * (ha * ha + hb * hb))
+    c = (hb * hb - ha * ha) / (4 * h0 * h0)
+    lim = (0.5 - (1.5 + c) * cos2) / (math.sqrt(math.pi) * h0)
+    v = O.self_cell(ha, hb, du, dphi)
+    assert abs(v - lim) < 1e-3 * abs(lim), (v, lim)
+
+
+def test_self_cell_h_derivatives_match_central_differences():
+    du, dphi = 0.006, 0.006
+    ha, hb, e = 0.05, 0.01, 1e-6
+    for which, (da, db) in ((1, (e, 0)), (2, (0, e))):
+        d = O.self_cell(ha, hb, du, dphi, which)
+        fd = (O.self_cell(ha + da, hb + db, du, dphi) - O.self_cell(ha - da, hb - db, du, dphi)) / (2 * e)
+        assert abs(d - fd) < 1e-6 * abs(fd)
+
+
+# -------------------------------------------------------------- field sums
+def _cart(nr, nphi, rmin, rmax, gr, gp):
+    r, phi, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    P = np.broadcast_to(phi[None, :], (nr, nphi)).ravel()
+    gx = gr * np.cos(P) - gp * np.sin(P)
+    gy = gr * np.sin(P) + gp * np.cos(P)
+    return gx, gy
+
+
+def test_newton_third_law_general_H():
+    """Pairwise symmetry of K (Sect. 2.2) gives zero net force on the whole
+    disc when the self term is excluded, for any per-cell scale heights."""
+    rng = np.random.default_rng(11)
+    nr, nphi, rmin, rmax = 9, 14, 0.3, 2.0
+    r, phi, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    sig = rng.uniform(0.2, 2.0, (2, nr, nphi))
+    H = rng.uniform(0.01, 0.2, (2, nr, nphi))
+    gr, gp = O.field_pairwise(nr, nphi, rmin, rmax, [0, 0], sig, H=H, flags=O.EXCLUDE_SELF)
+    A = (r ** 2 * du * dphi)[:, None] * np.ones((nr, nphi))
+    tot = np.zeros(2)
+    scale = 0.0
+    for b in range(2):
+        gx, gy = _cart(nr, nphi, rmin, rmax, gr[b], gp[b])
+        m = (sig[b] * A).ravel()
+        tot += [np.sum(m * gx), np.sum(m * gy)]
+        scale += np.sum(m * np.hypot(gx, gy))
+    assert np.all(np.abs(tot) < 1e-13 * scale)
+
+
+def test_axisymmetric_disc_has_no_azimuthal_field():
+    nr, nphi, rmin, rmax = 12, 16, 0.2, 2.5
+    r, phi, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    sig = np.stack([np.repeat((1 / r)[:, None], nphi, 1), np.repeat((0.01 * r)[:, None], nphi, 1)])
+    for gr, gp in (O.field_pairwise(nr, nphi, rmin, rmax, [0.05, 0.01], sig),
+                   O.field_table(nr, nphi, rmin, rmax, [0.05, 0.01], sig)):
+        assert np.abs(gp).max() < 1e-13 * np.abs(gr).max()
+        # and every ring is uniform
+        g = gr.reshape(2, nr, nphi)
+        assert np.abs(g - g[:, :, :1]).max() < 1e-13 * np.abs(g).max()
+
+
+def test_phi_shift_equivariance_and_linearity():
+    rng = np.random.default_rng(3)
+    nr, nphi, rmin, rmax = 8, 12, 0.4, 3.0
+    s1 = rng.uniform(0, 1, (2, nr, nphi))
+    s2 = rng.uniform(0, 1, (2, nr, nphi))
+    h = [0.08, 0.02]
+    g1 = np.array(O.field_table(nr, nphi, rmin, rmax, h, s1))
+    g2 = np.array(O.field_table(nr, nphi, rmin, rmax, h, s2))
+    g12 = np.array(O.field_table(nr, nphi, rmin, rmax, h, 2 * s1 - 0.5 * s2))
+    np.testing.assert_allclose(g12, 2 * g1 - 0.5 * g2, rtol=0, atol=1e-13 * np.abs(g1).max())
+    gs = np.array(O.field_table(nr, nphi, rmin, rmax, h, np.roll(s1, 5, axis=2)))
+    np.testing.assert_allclose(gs.reshape(2, 2, nr, nphi), np.roll(g1.reshape(2, 2, nr, nphi), 5, axis=3),
+                               rtol=0, atol=1e-13 * np.abs(g1).max())
+
+
+def test_table_mode_equals_pairwise_sum():
+    """App. C convolution sum == plain pairwise Cartesian sum, bi-fluid,
+    including the self term."""
+    rng = np.random.default_rng(7)
+    nr, nphi, rmin, rmax = 10, 16, 0.3, 2.0
+    sig = rng.uniform(0.5, 1.5, (2, nr, nphi))
+    h = [0.1, 0.03]
+    gr, gp = O.field_pairwise(nr, nphi, rmin, rmax, h, sig)
+    tr, tp = O.field_table(nr, nphi, rmin, rmax, h, sig)
+    assert np.abs(gr - tr).max() < 1e-13 * np.abs(gr).max()
+    assert np.abs(gp - tp).max() < 1e-13 * np.abs(gr).max()
+
+
+def test_razor_thin_field_is_newtonian_sum():
+    """h -> 0: the field is the point-mass Newtonian sum -sum m (x_i-x_k)/s^3."""
+    rng = np.random.default_rng(2)
+    nr, nphi, rmin, rmax = 6, 10, 0.5, 2.0
+    r, phi, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    sig = rng.uniform(0.5, 1.5, (1, nr, nphi))
+    gr, gp = O.field_pairwise(nr, nphi, rmin, rmax, [1e-7], sig, flags=O.EXCLUDE_SELF)
+    R = np.repeat(r, nphi)
+    P = np.tile(phi, nr)
+    x, y = R * np.cos(P), R * np.sin(P)
+    m = sig.ravel() * R ** 2 * du * dphi
+    dx = x[:, None] - x[None, :]
+    dy = y[:, None] - y[None, :]
+    s3 = np.hypot(dx, dy) ** 3
+    np.fill_diagonal(s3, np.inf)
+    Gx = -(m[None, :] * dx / s3).sum(1)
+    Gy = -(m[None, :] * dy / s3).sum(1)
+    ref_r = Gx * np.cos(P) + Gy * np.sin(P)
+    ref_p = -Gx * np.sin(P) + Gy * np.cos(P)
+    assert np.abs(gr[0] - ref_r).max() < 1e-9 * np.abs(ref_r).max()
+    assert np.abs(gp[0] - ref_p).max() < 1e-9 * np.abs(ref_r).max()
+
+
+def test_two_cell_system_by_hand():
+    """Two cells on one ring (N_r = 1, N_phi = 2): the pull of cell 1 on cell 0
+    points from 0 to 1 (attractive, radially inward for cell 0), magnitude
+    Sigma A K(2r), K from 40-digit Bessel functions."""
+    rmin, rmax = 1.0, 1.2
+    r, phi, du, dphi = O.grid(1, 2, rmin, rmax)
+    H = 0.3 * r[0]
+    sig = np.array([[[0.0, 2.0]]])
+    gr, gp = O.field_pairwise(1, 2, rmin, rmax, [0.3], sig, flags=O.EXCLUDE_SELF)
+    s = 2 * r[0]
+    d = s / H
+    x = d * d / 8
+    K = float(1 / mp.sqrt(mp.pi) / H ** 2 * d / 8 * _F_mp(x))
+    A = r[0] ** 2 * du * dphi
+    assert gr[0, 0] == pytest.approx(-2.0 * A * K, rel=1e-14)
+    assert abs(gp[0, 0]) < 1e-15 * abs(gr[0, 0])
+    assert gr[0, 1] == 0.0
+
+
+def test_exponential_disc_continuum_normalisation():
+    """Continuum check of the whole normalisation (G = 1, area element, 2D
+    kernel) against the exponential-disc closed form of Sect. 4.2,
+    g_r = -2 pi Sigma0 y [I0 K0 - I1 K1](y), y = r/(2 r0), at small h.
+    Discretisation and finite thickness leave a few 1e-2 at this grid."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        e = json.load(fh)["exponential_disc_setup"]
+    nr, nphi, h = 256, 512, 0.01
+    rmin, rmax = e["r_in"] / e["r0"], e["r_out"] / e["r0"]   # lengths in units of r0
+    r, phi, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    sig = np.exp(-r)[None, :, None] * np.ones((1, nr, nphi))
+    sel = np.where((r > 0.25) & (r < 4.0))[0][::4]
+    gr, _ = O.field_table(nr, nphi, rmin, rmax, [h], sig, targets=sel * nphi)
+    y = r[sel] / 2
+    ref = -2 * np.pi * y * (ss.i0(y) * ss.k0(y) - ss.i1(y) * ss.k1(y))
+    assert np.all(np.abs(gr[0] / ref - 1) < 3e-2)
+
+
+# ----------------------------------------------------------------- adjoint
+def test_adjoint_sigma_equals_central_differences():
+    """dL/dSigma for L = sum_b sum_c w (g - g*)^2: the oracle's transposed sum vs
+    central differences of the oracle forward (exact, L is quadratic)."""
+    rng = np.random.default_rng(4)
+    nr, nphi, rmin, rmax = 6, 8, 0.3, 2.0
+    h = [0.06, 0.012]
+    sig = rng.uniform(0.5, 1.5, (2, nr, nphi))
+    tgt = np.array(O.field_table(nr, nphi, rmin, rmax, h, rng.uniform(0.5, 1.5, (2, nr, nphi))))
+
+    def loss(s):
+        g = np.array(O.field_table(nr, nphi, rmin, rmax, h, s))
+        return float(np.sum((g - tgt) ** 2))
+
+    g = np.array(O.field_table(nr, nphi, rmin, rmax, h, sig))
+    lam = 2 * (g - tgt)          # [c][b][N]
+    ds = O.adjoint_sigma(nr, nphi, rmin, rmax, h, lam[0], lam[1])
+    e = 1e-3
+    for a, k in ((0, 0), (0, 17), (1, 5), (1, 47)):
+        sp_ = sig.copy()
+        sm_ = sig.copy()
+        sp_.reshape(2, -1)[a, k] += e
+        sm_.reshape(2, -1)[a, k] -= e
+        fd = (loss(sp_) - loss(sm_)) / (2 * e)
+        assert ds[a, k] == pytest.approx(fd, rel=1e-9, abs=1e-12)
+
+
+def test_adjoint_h_equals_central_differences():
+    rng = np.random.default_rng(6)
+    nr, nphi, rmin, rmax = 6, 8, 0.3, 2.0
+    h = np.array([0.06, 0.012])
+    sig = rng.uniform(0.5, 1.5, (2, nr, nphi))
+    tgt = np.array(O.field_table(nr, nphi, rmin, rmax, h * 1.1, sig))
+
+    def loss(hh):
+        g = np.array(O.field_table(nr, nphi, rmin, rmax, hh, sig))
+        return float(np.sum((g - tgt) ** 2))
+
+    g = np.array(O.field_table(nr, nphi, rmin, rmax, h, sig))
+    lam = 2 * (g - tgt)
+    dh = O.adjoint_h(nr, nphi, rmin, rmax, h, sig, lam[0], lam[1])
+    for f in range(2):
+        e = 1e-4 * h[f]
+        hp, hm = h.copy(), h.copy()
+        hp[f] += e
+        hm[f] -= e
+        fd = (loss(hp) - loss(hm)) / (2 * e)
+        assert dh[f] == pytest.approx(fd, rel=1e-6)
