@@ -1,0 +1,231 @@
+"""Benchmark: self-gravity field cells/s of the log-polar FFT path on the
+1024 x 2048 two-fluid disc (gas h = 0.05, dust h = 0.005, all four ordered
+pairs fused), one MI355X.
+
+A step is one sg_field_fft call (phi transform of Sigma, fused u transform /
+spectral multiply / inverse u transform, inverse phi transform) on inputs
+resident in HBM; the kernel spectra are built once beforehand (the paper
+precomputes the kernel once per simulation).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+  python bench.py --copy-calibration   (plain 1 GiB device copy, for scaling
+                                        rocprofv3 FETCH_SIZE / WRITE_SIZE)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SG field cells/s at 1024×2048 bi-fluid; %HBM roofline; rel err vs FP64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass2_bifluid_1024x2048.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_10812_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(nr, nphi, nf):
+    """Algorithmic (compulsory) bytes of each pass of one sg_field_fft call."""
+    ncol = nphi // 2 + 1
+    sig = 4 * nf * nr * nphi                 # Sigma read (float)
+    st = 8 * nf * nr * ncol                  # Sigma~ (complex64 half spectra)
+    spec = 8 * nf * nf * 2 * (nr + 1) * ncol  # kernel spectra, all pairs, both comps
+    gh = 8 * 2 * nf * nr * ncol              # g^ (complex64 half spectra)
+    g = 4 * 2 * nf * nr * nphi               # g_r, g_phi write (float)
+    return {"pass1": sig + st, "pass2": st + spec + gh, "pass3": gh + g,
+            "path": sig + spec + g}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md, not run", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    import paper_2506_10812_amd as sg
+    from paper_2506_10812_amd import torch_ops as T
+    from paper_2506_10812_amd import workloads as W
+
+    w = W.bifluid_fft()
+    nr, nphi, nf = w["n_r"], w["n_phi"], len(w["h"])
+    cells = nr * nphi
+    print(f"bench: building tables for {nr}x{nphi} two-fluid disc", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    F = T.FFTField([w], device=dev)
+    torch.cuda.synchronize()
+    table_s = time.perf_counter() - t0
+    F.set_sigma(0, w["sigma"])
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        F.run()
+    torch.cuda.synchronize()
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        F.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = cells / (ms_step * 1e-3)
+
+    # per-pass durations with HIP events on the launch stream (no graph)
+    reps = max(10, min(args.steps, 200))
+    ms_pass = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
+    pb = pass_bytes(nr, nphi, nf)
+    names = ["pass1", "pass2", "pass3"]
+    dom = int(np.argmax(ms_pass))
+    dom_name = names[dom]
+    achieved = pb[dom_name] / (ms_pass[dom] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel") == dom_name:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom_name, "kernel_ms": round(ms_pass[dom], 5),
+                "algorithmic_bytes": pb[dom_name]}
+
+    # accuracy vs the FP64 oracle on 4096 seeded cells (also the CPU baseline)
+    cpu = None
+    acc = None
+    if not args.no_cpu:
+        import oracle as O
+        idx = W.sample_cells(nr, nphi, 4096)
+        sig32 = F.sigma[0].double().cpu().numpy()
+        print("bench: CPU oracle on 4096 sampled cells", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, targets=idx)
+        cpu_s = time.perf_counter() - t0
+        gr = F.g_r[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
+        gp = F.g_phi[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
+        acc = {f"{['gas', 'dust'][b]}_{c}": float(np.linalg.norm(x[b] - y[b]) / np.linalg.norm(y[b]))
+               for b in range(nf) for c, x, y in (("g_r", gr, rr), ("g_phi", gp, rp))}
+        cpu = {"value": round(len(idx) / cpu_s, 2), "unit": "cells/s", "cores": O.threads(),
+               "kind": "oracle",
+               "sample": f"{len(idx)} seeded cells of the same disc, offset-table FP64 oracle "
+                         f"(includes its table build), {cpu_s:.1f} s"}
+
+    extra = {"table_build_s": round(table_s, 3), "wall_s_timed": round(wall, 3),
+             "ms_per_pass": [round(v, 5) for v in ms_pass],
+             "path_algorithmic_bytes": pb["path"],
+             "path_hbm_frac": round(pb["path"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "rel_rms_vs_fp64_oracle": acc}
+    if not args.no_extra:
+        extra.update(extra_measurements(sg, T, W, dev))
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "cells/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "two-fluid log-polar disc 1024x2048, r in [0.2,5], "
+                                  "h_g=0.05, h_d=0.005, gas spiral + dust clumps, "
+                                  "FFT path, 4 ordered pairs fused",
+                      "n_r": nr, "n_phi": nphi, "fluids": nf, "cells_per_step": cells,
+                      "parallelism": "single GPU"},
+           "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(out))
+
+
+def extra_measurements(sg, T, W, dev):
+    """Secondary numbers: 64-disc batch, adjoint, FP64 direct sum."""
+    import torch
+    res = {}
+    discs = W.batch64()
+    Fb = T.FFTField(discs, device=dev)
+    for i, d in enumerate(discs):
+        Fb.set_sigma(i, d["sigma"])
+    for _ in range(5):
+        Fb.run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = 50
+    e0.record()
+    for _ in range(n):
+        Fb.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    cells = sum(d["n_r"] * d["n_phi"] for d in discs)
+    byts = sum(pass_bytes(d["n_r"], d["n_phi"], 1)["path"] for d in discs)
+    # the same discs one call each (plain single-disc path)
+    singles = [T.FFTField([d], device=dev) for d in discs]
+    for s_, d in zip(singles, discs):
+        s_.set_sigma(0, d["sigma"])
+        s_.run()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        for s_ in singles:
+            s_.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1) / 10
+    res["batch64"] = {"cells": cells, "ms": round(ms, 4), "cells_per_s": round(cells / ms * 1e3, 1),
+                      "path_hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "looped_single_disc_ms": round(ms_loop, 4),
+                      "speedup_vs_looped": round(ms_loop / ms, 3)}
+    del Fb, singles
+    # FP64 direct sum on the 64x128 workload
+    w = W.direct_fp64()
+    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+    s = torch.tensor(w["sigma"], dtype=torch.float64, device=dev)
+    T.direct(g, w["h"], s)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        T.direct(g, w["h"], s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    pairs = (w["n_r"] * w["n_phi"]) ** 2
+    res["direct_fp64_64x128"] = {"ms": round(ms, 4), "pairs_per_s": round(pairs / ms * 1e3, 1)}
+    return res
+
+
+if __name__ == "__main__":
+    main()

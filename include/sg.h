@@ -1,0 +1,212 @@
+/*
+ * sg.h -- C ABI of the MI355X (gfx950) library for the exact thin-disc
+ * self-gravity kernel of arXiv 2506.10812 (Rendon Restrepo, Rometsch,
+ * Ziegler & Gressel, "Self-gravity in thin protoplanetary discs 1").
+ *
+ * The library sums the exact Bessel kernel
+ *     K_ab(s) = pi^{-1/2} H_ab^{-2} (d/8) e^x [K1(x) - K0(x)],  x = d^2/8,
+ *     d = s/H_ab,  H_ab^2 = (H_a^2 + H_b^2)/2          (Sect. 2.2, kernel and
+ *                                                      r.m.s. scale height)
+ * against surface density on a log-r x uniform-phi grid and returns the
+ * in-plane gravitational acceleration of each fluid,
+ *     g_b(x_i) = - sum_a sum_{k != i} Sigma_a[k] A_k K_ab(s_ik) e_s + self term
+ * (Sect. 2.2, the 2D force divided by Sigma_b), projected on e_r and e_phi.
+ *
+ * Conventions shared by every call
+ *   units      G = 1; outputs are accelerations g (not force densities); the
+ *              field is attractive (points towards mass).
+ *   grid       radial cell edges are log-spaced from r_min to r_max; cell
+ *              centres u_i = ln r_min + (i + 1/2) du, du = ln(r_max/r_min)/n_r;
+ *              phi_j = (j + 1/2) dphi, dphi = 2 pi / n_phi; cell area
+ *              A_i = r_i^2 du dphi.
+ *   layout     every device array is row-major [fluid][i_r][j_phi] with phi
+ *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 or 2.
+ *   pairs      (a -> b) is source fluid a acting on target fluid b; a
+ *              two-fluid disc has the four ordered pairs gg, dg, gd, dd
+ *              (Sect. 2.2 lists the four combinations).
+ *   self term  the own-cell contribution is the principal-value average of
+ *              the log-polar radial kernel over the cell (the paper does not
+ *              treat k = i); SG_SELF_CELL_EXCLUDE drops it.
+ *   ownership  every device buffer is allocated and owned by the caller; the
+ *              library reads and writes only the buffers passed in.  The only
+ *              device memory the library owns is a per-signature cache of
+ *              batch descriptors and instantiated HIP graphs (sg_field_fft);
+ *              sg_release() frees it.
+ *   streams    `stream` is a hipStream_t passed as void* (NULL = default
+ *              stream).  Every call is asynchronous on that stream unless
+ *              stated otherwise; buffers must stay valid until it completes.
+ *   errors     calls return an sg_status; arguments are validated before any
+ *              work is enqueued, so a non-SG_OK return (other than
+ *              SG_ERR_HIP) has launched nothing.  No exception crosses the ABI.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sg_status {
+    SG_OK = 0,
+    SG_ERR_ARG = 1,         /* invalid argument (NULL pointer, size, range) */
+    SG_ERR_UNSUPPORTED = 2, /* valid but not supported by this path        */
+    SG_ERR_HIP = 3,         /* a HIP runtime call failed                    */
+    SG_ERR_WORKSPACE = 4,   /* workspace pointer NULL or too small          */
+    SG_ERR_TABLE = 5        /* kernel table does not match the disc         */
+} sg_status;
+
+typedef enum sg_dtype { SG_F32 = 0, SG_F64 = 1 } sg_dtype;
+
+enum {
+    SG_SELF_CELL_EXCLUDE = 1u, /* drop the own-cell term                      */
+    SG_WITH_DH = 2u            /* table also holds d/dh spectra (adjoint)     */
+};
+
+typedef struct sg_grid {
+    int32_t n_r;    /* radial cells                                   */
+    int32_t n_phi;  /* azimuthal cells                                */
+    double r_min;   /* inner edge of the first radial cell (> 0)      */
+    double r_max;   /* outer edge of the last radial cell (> r_min)   */
+} sg_grid;
+
+typedef struct sg_fluids {
+    int32_t n_fluids; /* 1 (gas) or 2 (gas + dust)                         */
+    int32_t pad_;
+    double h[2];      /* aspect ratios h_f = H_f / r (constant per fluid)  */
+} sg_fluids;
+
+/* ---------------------------------------------------------------------
+ * Kernel table (log-polar FFT path, H_f = h_f r).
+ *
+ * App. C writes the radial and azimuthal fields as convolutions in
+ * (u = ln r, phi) with kernels K_r(X, phi), K_phi(X, phi) that depend only
+ * on the offsets when every H_f is proportional to r; Sect. 5.2 notes the
+ * kernel then needs computing only once.  sg_kernel_table samples both
+ * kernels for every ordered pair on the wrapped 2 n_r x n_phi offset grid
+ * (radial zero padding to 2 n_r, Sect. 5.2), puts the self term at offset
+ * (0,0), transforms in double precision and stores the half spectrum
+ * (k_u in [0, n_r], m in [0, n_phi/2]) rounded to float, pre-scaled by
+ * -du dphi / (2 n_r n_phi).  With SG_WITH_DH it also stores the spectra of
+ * dK/dh_a and dK/dh_b for sg_field_adjoint.
+ *
+ * Requirements: n_r and n_phi powers of two with 2 <= n_r <= 2048 and
+ * 4 <= n_phi <= 2048 (SG_ERR_UNSUPPORTED otherwise); h_f > 0.
+ * d_table: device buffer of sg_kernel_table_bytes() bytes, 256-byte aligned,
+ * written completely.  d_ws: device scratch of sg_kernel_table_workspace_bytes()
+ * bytes, contents undefined afterwards.  Asynchronous on `stream`.
+ * The table is position independent: it may be copied, saved and reloaded.
+ * --------------------------------------------------------------------- */
+size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags);
+size_t sg_kernel_table_workspace_bytes(const sg_grid *grid, const sg_fluids *fluids,
+                                       uint32_t flags);
+sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags,
+                          void *d_table, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * One disc for the FFT path.  sigma, g_r, g_phi: float device arrays
+ * [n_fluids][n_r][n_phi]; table: built by sg_kernel_table for the same grid,
+ * fluids and flags (checked on the host from the arguments, not the device).
+ * --------------------------------------------------------------------- */
+typedef struct sg_disc {
+    sg_grid grid;
+    sg_fluids fluids;
+    uint32_t flags;      /* flags the table was built with                 */
+    uint32_t pad_;
+    const float *sigma;  /* device, [F][n_r][n_phi]                        */
+    float *g_r;          /* device, [F][n_r][n_phi], overwritten           */
+    float *g_phi;        /* device, [F][n_r][n_phi], overwritten           */
+    const void *table;   /* device, from sg_kernel_table                   */
+} sg_disc;
+
+/* ---------------------------------------------------------------------
+ * sg_field_fft: g_r, g_phi of every disc in `discs` by the zero-padded
+ * log-polar FFT convolution (App. C convolution form, Sect. 5.2 zero
+ * padding).  Float arithmetic, float accumulation.  All discs of the batch
+ * (any mix of supported sizes, one or two fluids, all four ordered pairs
+ * fused per spectral point) run in one HIP-graph launch of three passes:
+ * phi transform of Sigma, fused u-transform / spectral multiply / inverse
+ * u-transform, inverse phi transform.  The graph and a device copy of the
+ * batch descriptors are cached per (sizes, pointers) signature on the first
+ * call (that call allocates and synchronises once); later calls with the
+ * same signature only launch.  d_ws: sg_field_fft_workspace_bytes(discs, n)
+ * bytes, 256-byte aligned; its address is part of the signature.
+ * n_discs in [1, 4096].  Outputs overwritten.
+ * --------------------------------------------------------------------- */
+size_t sg_field_fft_workspace_bytes(const sg_disc *discs, int n_discs);
+sg_status sg_field_fft(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
+                       void *stream);
+
+/* Same computation as sg_field_fft, enqueued without the graph `reps` times
+ * with HIP events at the boundaries of the three passes on `stream`; waits
+ * for completion (synchronous) and writes the mean duration in milliseconds
+ * of pass 1 (phi transform), pass 2 (u transform + spectral multiply +
+ * inverse u transform) and pass 3 (inverse phi transform) to ms_per_pass[3].
+ * For measurement; reps in [1, 10000]. */
+sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
+                               void *stream, int reps, float *ms_per_pass);
+
+/* ---------------------------------------------------------------------
+ * sg_field_direct: the O(N^2) pairwise sum of the definition (Sect. 2.2,
+ * 2D force through the kernel) for any grid size and general per-cell
+ * scale heights.  d_H: device array [F][n_r][n_phi] of H (same dtype as
+ * sigma), or NULL for H_f = h[f] r.  With per-cell H the self term of cell i
+ * uses h_a = H_a[i]/r_i and h_b = H_b[i]/r_i.  dtype SG_F64: double inputs,
+ * outputs and arithmetic; SG_F32: float inputs, outputs, arithmetic and
+ * accumulation (the self term is computed in double and rounded).
+ * n_r, n_phi >= 1, n_r * n_phi <= 2^26.  h: host array [F], read when
+ * d_H == NULL.  d_ws: sg_field_direct_workspace_bytes() bytes.
+ * --------------------------------------------------------------------- */
+size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
+                                       int per_cell_H);
+sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h,
+                          const void *d_sigma, const void *d_H, void *d_g_r, void *d_g_phi,
+                          sg_dtype dtype, uint32_t flags, void *d_ws, size_t ws_bytes,
+                          void *stream);
+
+/* ---------------------------------------------------------------------
+ * sg_field_adjoint: reverse-mode derivative of sg_field_fft for one disc.
+ * Given lam_r = dL/dg_r and lam_phi = dL/dg_phi (float device arrays
+ * [F][n_r][n_phi]) it returns
+ *   d_dsigma[a][i] = dL/dSigma_a[i]
+ *                  = -du dphi sum_b sum_c sum_j lam_{b,c}[j] K_c^{ab}(j - i)
+ * (the transposed convolution: conjugate kernel spectra) and, when d_dh is
+ * not NULL, d_dh[f] = dL/dh_f (double, device, [F]) by a Parseval reduction
+ * of lam against (dK/dh) (*) Sigma accumulated in double.  d_dh needs a
+ * table built with SG_WITH_DH (SG_ERR_TABLE otherwise).
+ * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
+ * --------------------------------------------------------------------- */
+size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc);
+sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const float *d_lam_phi,
+                           float *d_dsigma, double *d_dh, void *d_ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---------------------------------------------------------------------
+ * Device-side evaluation of F(x) = e^x [K1(x) - K0(x)] (the function of
+ * App. A at argument x) for testing: d_x, d_F device arrays of n values in
+ * `dtype`.  F'(x) too when d_dF is not NULL.
+ * --------------------------------------------------------------------- */
+sg_status sg_eval_F(const void *d_x, void *d_F, void *d_dF, int64_t n, sg_dtype dtype,
+                    void *stream);
+
+/* Self-cell term for a list of (h_a, h_b) pairs on one grid: d_out[i] =
+ * principal-value average of the log-polar radial kernel K_r over the own
+ * cell (double), the value sg_kernel_table places at offset (0,0) before
+ * scaling.  which = 0 for the kernel, 1 for d/dh_a, 2 for d/dh_b.  ha, hb:
+ * HOST arrays of n values, 1 <= n <= 64; d_out: device double array of n. */
+sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, int n, int which,
+                       double *d_out, void *stream);
+
+/* Frees cached graphs and descriptor tables (synchronises the device). */
+void sg_release(void);
+
+const char *sg_status_string(sg_status s);
+int sg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

@@ -169,14 +169,19 @@ void sg_oracle_conv_kernels(int64_t n, const double *X, const double *phi,
  * bounded and Kbar = (1/(a b)) int_0^a int_0^b S, a = du/2, b = dphi/2.
  * The quarter cell is split along its diagonal into two triangles with a
  * vertex at the singular corner and integrated in polar coordinates about
- * that corner (the Jacobian rho removes the direction-dependent jump) by
- * 48 x 48-point Gauss-Legendre rules.  The integrand in rho is
- * rho S0(theta) + O(rho^3 ln rho), for which the rule is accurate to ~1e-12.
+ * that corner (the Jacobian rho removes the direction-dependent jump): 48
+ * Gauss-Legendre nodes in the angle and, in rho, 20 nodes on each of seven
+ * geometrically shrinking panels [0, R 4^-6], [R 4^-(j+1), R 4^-j] (so the
+ * transition of F at rho ~ H inside cells much larger than H is resolved;
+ * the integrand is rho S0(theta) + O(rho^3 ln rho) near the corner).
  * Parity pinned by brute-force midpoint sums with Richardson extrapolation
  * and by the closed-form small-cell limit (tests).  which: as orc_conv.
  * ------------------------------------------------------------------------ */
 #define ORC_GL_N 48
+#define ORC_GLR_N 20
+#define ORC_PANELS 7
 static double orc_gl_x[ORC_GL_N], orc_gl_w[ORC_GL_N];
+static double orc_glr_x[ORC_GLR_N], orc_glr_w[ORC_GLR_N];
 static int orc_gl_ready = 0;
 
 /* Gauss-Legendre nodes on [0,1] by Newton iteration on P_n (textbook). */
@@ -192,10 +197,8 @@ static void orc_legendre(int n, double z, double *p, double *dp)
     *dp = n * (z * p1 - p0) / (z * z - 1.0);
 }
 
-static void orc_gl_init(void)
+static void orc_gl_nodes(int n, double *x, double *w)
 {
-    if (orc_gl_ready) return;
-    const int n = ORC_GL_N;
     for (int i = 0; i < n; ++i) {
         double z = cos(ORC_PI * (i + 0.75) / (n + 0.5)), p, dp;
         for (int it = 0; it < 100; ++it) {
@@ -206,9 +209,16 @@ static void orc_gl_init(void)
         }
         orc_legendre(n, z, &p, &dp);
         /* map [-1,1] -> [0,1]: node (1-z)/2, weight w/2 with w = 2/((1-z^2) P_n'^2) */
-        orc_gl_x[i] = 0.5 * (1.0 - z);
-        orc_gl_w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+        x[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
     }
+}
+
+static void orc_gl_init(void)
+{
+    if (orc_gl_ready) return;
+    orc_gl_nodes(ORC_GL_N, orc_gl_x, orc_gl_w);
+    orc_gl_nodes(ORC_GLR_N, orc_glr_x, orc_glr_w);
     orc_gl_ready = 1;
 }
 
@@ -235,11 +245,18 @@ double sg_oracle_self_cell(double ha, double hb, double du, double dphi, int whi
             double c = cos(th), s = sin(th);
             double rmax = tri == 0 ? a / c : b / s;
             double inner = 0.0;
-            for (int j = 0; j < ORC_GL_N; ++j) {
-                double rho = rmax * orc_gl_x[j];
-                inner += orc_gl_w[j] * rho * orc_sym_Kr(rho * c, rho * s, ha, hb, which);
+            for (int pnl = 0; pnl < ORC_PANELS; ++pnl) {
+                /* panel [lo, hi] in units of rmax: [0, 4^-6], then [4^-(j+1), 4^-j] */
+                double hi = pow(4.0, -(double)(ORC_PANELS - 1 - pnl));
+                double lo = pnl == 0 ? 0.0 : hi / 4.0;
+                double part = 0.0;
+                for (int j = 0; j < ORC_GLR_N; ++j) {
+                    double rho = rmax * (lo + (hi - lo) * orc_glr_x[j]);
+                    part += orc_glr_w[j] * rho * orc_sym_Kr(rho * c, rho * s, ha, hb, which);
+                }
+                inner += part * (hi - lo) * rmax;
             }
-            acc += orc_gl_w[i] * inner * rmax;
+            acc += orc_gl_w[i] * inner;
         }
         total += acc * (th1 - th0);
     }

@@ -1,0 +1,7 @@
+// sg_adjoint.h -- internal entry points of the adjoint.
+#pragma once
+#include "sg_internal.h"
+
+size_t sg_adjoint_ws_bytes(const sg_disc &d);
+sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_p, float *dsig,
+                         double *dh, void *ws, hipStream_t s);

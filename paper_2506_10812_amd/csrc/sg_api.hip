@@ -1,0 +1,203 @@
+// sg_api.hip -- the C ABI (include/sg.h): argument validation, workspace
+// sizing and dispatch.  No device work is enqueued before validation passes.
+#include <math.h>
+
+#include "sg_adjoint.h"
+#include "sg_direct.h"
+#include "sg_fftpath.h"
+#include "sg_table.h"
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+static sg_status check_grid(const sg_grid *g)
+{
+    if (!g) return SG_ERR_ARG;
+    if (g->n_r < 1 || g->n_phi < 1) return SG_ERR_ARG;
+    if (!finite_pos(g->r_min) || !isfinite(g->r_max) || !(g->r_max > g->r_min)) return SG_ERR_ARG;
+    return SG_OK;
+}
+
+static sg_status check_fft_grid(const sg_grid *g)
+{
+    sg_status s = check_grid(g);
+    if (s != SG_OK) return s;
+    if (!sg_is_pow2(g->n_r) || !sg_is_pow2(g->n_phi)) return SG_ERR_UNSUPPORTED;
+    if (g->n_r < 2 || g->n_r > 2048 || g->n_phi < 4 || g->n_phi > 2048) return SG_ERR_UNSUPPORTED;
+    return SG_OK;
+}
+
+static sg_status check_fluids(const sg_fluids *f)
+{
+    if (!f) return SG_ERR_ARG;
+    if (f->n_fluids < 1 || f->n_fluids > 2) return SG_ERR_ARG;
+    for (int i = 0; i < f->n_fluids; ++i)
+        if (!finite_pos(f->h[i])) return SG_ERR_ARG;
+    return SG_OK;
+}
+
+static bool flags_ok(uint32_t flags) { return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH)) == 0; }
+
+extern "C" {
+
+size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
+{
+    if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
+    return sg_table_layout(grid->n_r, grid->n_phi, fluids->n_fluids, flags).total;
+}
+
+size_t sg_kernel_table_workspace_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
+{
+    if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
+    return sg_table_ws_bytes(grid->n_r, grid->n_phi);
+}
+
+sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags,
+                          void *d_table, void *d_ws, size_t ws_bytes, void *stream)
+{
+    sg_status s = check_fft_grid(grid);
+    if (s != SG_OK) return s;
+    if ((s = check_fluids(fluids)) != SG_OK) return s;
+    if (!flags_ok(flags)) return SG_ERR_ARG;
+    if (!d_table || ((uintptr_t)d_table & 255)) return SG_ERR_ARG;
+    if (!d_ws || ws_bytes < sg_table_ws_bytes(grid->n_r, grid->n_phi) || ((uintptr_t)d_ws & 255))
+        return SG_ERR_WORKSPACE;
+    return sg_table_build(grid, fluids, flags, d_table, d_ws, (hipStream_t)stream);
+}
+
+static sg_status check_disc(const sg_disc &d)
+{
+    sg_status s = check_fft_grid(&d.grid);
+    if (s != SG_OK) return s;
+    if ((s = check_fluids(&d.fluids)) != SG_OK) return s;
+    if (!flags_ok(d.flags)) return SG_ERR_ARG;
+    if (!d.sigma || !d.g_r || !d.g_phi || !d.table) return SG_ERR_ARG;
+    if ((uintptr_t)d.table & 255) return SG_ERR_ARG;
+    return SG_OK;
+}
+
+size_t sg_field_fft_workspace_bytes(const sg_disc *discs, int n_discs)
+{
+    if (!discs || n_discs < 1 || n_discs > 4096) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n_discs; ++i) {
+        if (check_disc(discs[i]) != SG_OK) return 0;
+        total += sg_fft_disc_ws_bytes(discs[i]);
+    }
+    return total;
+}
+
+sg_status sg_field_fft(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!discs || n_discs < 1 || n_discs > 4096) return SG_ERR_ARG;
+    size_t need = 0;
+    for (int i = 0; i < n_discs; ++i) {
+        sg_status s = check_disc(discs[i]);
+        if (s != SG_OK) return s;
+        need += sg_fft_disc_ws_bytes(discs[i]);
+    }
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    return sg_fft_run(discs, n_discs, d_ws, (hipStream_t)stream);
+}
+
+sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
+                               void *stream, int reps, float *ms_per_pass)
+{
+    if (!discs || n_discs < 1 || n_discs > 4096 || reps < 1 || reps > 10000 || !ms_per_pass)
+        return SG_ERR_ARG;
+    size_t need = 0;
+    for (int i = 0; i < n_discs; ++i) {
+        sg_status s = check_disc(discs[i]);
+        if (s != SG_OK) return s;
+        need += sg_fft_disc_ws_bytes(discs[i]);
+    }
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    return sg_fft_profile(discs, n_discs, d_ws, (hipStream_t)stream, reps, ms_per_pass);
+}
+
+size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
+                                       int per_cell_H)
+{
+    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    if (dtype != SG_F32 && dtype != SG_F64) return 0;
+    if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return 0;
+    return sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, per_cell_H ? 1 : 0);
+}
+
+sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
+                          const void *d_H, void *d_g_r, void *d_g_phi, sg_dtype dtype,
+                          uint32_t flags, void *d_ws, size_t ws_bytes, void *stream)
+{
+    sg_status s = check_grid(grid);
+    if (s != SG_OK) return s;
+    if (n_fluids < 1 || n_fluids > 2) return SG_ERR_ARG;
+    if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
+    if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
+    if (!d_sigma || !d_g_r || !d_g_phi) return SG_ERR_ARG;
+    if ((flags & ~(uint32_t)SG_SELF_CELL_EXCLUDE) != 0) return SG_ERR_ARG;
+    if (!d_H) {
+        if (!h) return SG_ERR_ARG;
+        for (int f = 0; f < n_fluids; ++f)
+            if (!finite_pos(h[f])) return SG_ERR_ARG;
+    }
+    const size_t need = sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, d_H ? 1 : 0);
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    static const double one[2] = {1.0, 1.0};
+    return sg_direct_launch(grid, n_fluids, d_H ? one : h, d_sigma, d_H, d_g_r, d_g_phi, dtype,
+                            flags, d_ws, (hipStream_t)stream);
+}
+
+size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
+{
+    if (!disc || check_disc(*disc) != SG_OK) return 0;
+    return sg_adjoint_ws_bytes(*disc);
+}
+
+sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const float *d_lam_phi,
+                           float *d_dsigma, double *d_dh, void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!disc) return SG_ERR_ARG;
+    sg_status s = check_disc(*disc);
+    if (s != SG_OK) return s;
+    if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
+    if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
+    if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))
+        return SG_ERR_WORKSPACE;
+    return sg_adjoint_run(*disc, d_lam_r, d_lam_phi, d_dsigma, d_dh, d_ws, (hipStream_t)stream);
+}
+
+sg_status sg_eval_F(const void *d_x, void *d_F, void *d_dF, int64_t n, sg_dtype dtype, void *stream)
+{
+    if (!d_x || !d_F || n < 0 || (dtype != SG_F32 && dtype != SG_F64)) return SG_ERR_ARG;
+    if (n == 0) return SG_OK;
+    return sg_eval_F_launch(d_x, d_F, d_dF, n, dtype, (hipStream_t)stream);
+}
+
+sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, int n, int which,
+                       double *d_out, void *stream)
+{
+    sg_status s = check_grid(grid);
+    if (s != SG_OK) return s;
+    if (!ha || !hb || !d_out || n < 1 || n > SG_SELF_MAX || which < 0 || which > 2) return SG_ERR_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!finite_pos(ha[i]) || !finite_pos(hb[i])) return SG_ERR_ARG;
+    return sg_self_cell_launch(grid, ha, hb, n, which, d_out, (hipStream_t)stream);
+}
+
+void sg_release(void) { sg_fft_release(); }
+
+const char *sg_status_string(sg_status s)
+{
+    switch (s) {
+    case SG_OK: return "SG_OK";
+    case SG_ERR_ARG: return "SG_ERR_ARG: invalid argument";
+    case SG_ERR_UNSUPPORTED: return "SG_ERR_UNSUPPORTED: not supported by this path";
+    case SG_ERR_HIP: return "SG_ERR_HIP: HIP runtime error";
+    case SG_ERR_WORKSPACE: return "SG_ERR_WORKSPACE: workspace missing or too small";
+    case SG_ERR_TABLE: return "SG_ERR_TABLE: kernel table does not match";
+    }
+    return "unknown sg_status";
+}
+
+int sg_version(void) { return 1; }
+
+}  // extern "C"

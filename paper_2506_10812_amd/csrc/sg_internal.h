@@ -1,0 +1,146 @@
+// sg_internal.h -- shared internals of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/sg.h"
+
+#define SG_PI 3.14159265358979323846
+#define SG_SQRT_PI 1.77245385090551602730
+#define SG_SQRT2 1.41421356237309504880
+
+// ---------------------------------------------------------------- complex
+__host__ __device__ inline float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 c_mul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 c_conj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 c_mul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+template <typename R> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename R> using cplx_t = typename cplx_of<R>::type;
+
+template <typename V> __host__ __device__ inline V c_make(double re, double im);
+template <> __host__ __device__ inline float2 c_make<float2>(double re, double im)
+{
+    return make_float2((float)re, (float)im);
+}
+template <> __host__ __device__ inline double2 c_make<double2>(double re, double im)
+{
+    return make_double2(re, im);
+}
+
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V> __host__ __device__ inline V c_mul_mi(V a)
+{
+    V r;
+    if (INV) { r.x = -a.y; r.y = a.x; }
+    else     { r.x = a.y;  r.y = -a.x; }
+    return r;
+}
+
+// ------------------------------------------------------------ table layout
+// Device kernel-table layout (all offsets 256-byte aligned, computable on the
+// host from the arguments alone):
+//   header   sg_table_header
+//   tw_u     float2[2 n_r]       e^{-2 pi i n / (2 n_r)}
+//   tw_phi   float2[n_phi]       e^{-2 pi i n / n_phi}
+//   spec     float2[ncol][npair][2][kk]   scaled half spectra of K_r, K_phi
+//   dspec    float2[ncol][npair][2][2][kk] d/dh_a, d/dh_b spectra (SG_WITH_DH)
+// with ncol = n_phi/2 + 1, kk = n_r + 1, pair = a * n_fluids + b (a source,
+// b target), component 0 = r, 1 = phi.
+#define SG_TABLE_MAGIC 0x31544753u  // "SGT1"
+
+struct sg_table_header {
+    uint32_t magic, version;
+    int32_t n_r, n_phi, n_fluids;
+    uint32_t flags;
+    double h[2];
+    double r_min, r_max;
+    double self_r[4];       // self-cell average per pair (double)
+    double dself_r[4][2];   // its d/dh_a, d/dh_b
+    uint64_t total_bytes;
+};
+
+struct TableLayout {
+    int nr, nphi, nf, npair, ncol, kk;
+    uint32_t flags;
+    size_t off_tw_u, off_tw_phi, off_spec, off_dspec, total;
+};
+
+inline size_t sg_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline TableLayout sg_table_layout(int nr, int nphi, int nf, uint32_t flags)
+{
+    TableLayout L;
+    L.nr = nr;
+    L.nphi = nphi;
+    L.nf = nf;
+    L.npair = nf * nf;
+    L.ncol = nphi / 2 + 1;
+    L.kk = nr + 1;
+    L.flags = flags;
+    size_t o = sg_align256(sizeof(sg_table_header));
+    L.off_tw_u = o;
+    o = sg_align256(o + sizeof(float2) * 2 * (size_t)nr);
+    L.off_tw_phi = o;
+    o = sg_align256(o + sizeof(float2) * (size_t)nphi);
+    L.off_spec = o;
+    o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.npair * 2 * L.kk);
+    L.off_dspec = o;
+    if (flags & SG_WITH_DH) o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.npair * 4 * L.kk);
+    L.total = o;
+    return L;
+}
+
+// Block ("M = 4") layout of the half-spectrum intermediates between the
+// passes: element (m, i) of one field lives at ((m >> 2) * n_r + i) * 4 + (m & 3).
+// One 128-byte cache line therefore holds 4 consecutive columns of 4
+// consecutive rows, written whole by the 4 row jobs of one XCD.
+__host__ __device__ inline size_t sg_blk_index(int m, int i, int nr)
+{
+    return ((size_t)(m >> 2) * nr + i) * 4 + (m & 3);
+}
+__host__ __device__ inline size_t sg_blk_field_elems(int nphi, int nr)
+{
+    return (size_t)((nphi / 2 + 1 + 3) >> 2) * nr * 4;
+}
+
+// XCD-aware remap of workgroup ids: MI355X dispatches consecutive workgroups
+// round-robin over its 8 XCDs.  The remap gives the K workgroups that share
+// cache lines consecutive logical ids on one XCD.  n_wg must be a multiple of
+// 8 K; the result is a bijection on [0, n_wg).
+__device__ inline int sg_xcd_remap(int w, int K)
+{
+    int x = w & 7, s = w >> 3;
+    return (s / K) * 8 * K + x * K + (s % K);
+}
+
+inline int sg_ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+inline bool sg_is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// status helper: returns SG_ERR_HIP from the enclosing function on failure
+#define SG_HIP(call)                                \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return SG_ERR_HIP;    \
+    } while (0)

@@ -1,0 +1,201 @@
+// sg_kfn.h -- device evaluation of F(x) = e^x [K1(x) - K0(x)] and of the
+// exact kernel in its Cartesian and log-polar (App. C) forms.
+//
+// F(x) is the function of App. A (there at argument x/4) that carries the
+// whole distance dependence of the exact kernel (Sect. 2.2):
+//     K_ab(s) = pi^{-1/2} H_ab^{-2} (d/8) F(d^2/8),  d = s/H_ab.
+// Evaluation never forms e^x K1(x) and e^x K0(x) separately at large x (their
+// difference cancels and e^x overflows, the NaN problem noted in Sect. 5.3):
+//   x < 2   power series of I0, I1, K0, K1 (Abramowitz & Stegun 9.6.10,
+//           9.6.11), F = e^x (K1 - K0) (float: x < 1, where the two
+//           cancellations inside K0 and K1 - K0 cost at most a few ulps);
+//   x >= 2  F = sqrt(2) x^{-3/2} J(x)   (float: x >= 1),  J(x) = int_0^inf v^2 e^{-v^2}
+//           (1 + v^2/(2x))^{-1/2} dv, obtained from the integral
+//           representation K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt by
+//           the substitution sinh(t/2) = v / sqrt(2x).  The integrand is even
+//           and analytic for |Im v| < sqrt(2x), so the trapezoidal rule on a
+//           fixed grid converges geometrically: double uses step 1/4 and 26
+//           nodes (error < 1e-20 for x >= 2), float step 1/3 and 15 nodes
+//           (error ~1e-11 for x >= 1).
+//   x >= 32 (float only) the asymptotic series J = (sqrt(pi)/4) sum_n c_n
+//           x^-n, c_0 = 1, c_n = -c_{n-1} (4 n^2 - 1)/(8 n) (term-by-term
+//           integration of the binomial series; its first three terms are the
+//           expansion printed in Sect. 5.3), truncated after c_5.
+// The trapezoidal weights e^{-v_k^2} are computed once per workgroup into LDS
+// by sg_fill_weights() (exp of the node, no stored constants).
+#pragma once
+#include "sg_internal.h"
+
+#define SG_EULER_GAMMA 0.57721566490153286061
+
+template <typename R> struct FQuad;
+template <> struct FQuad<double> {
+    static constexpr int NODES = 26;
+    static constexpr double STEP = 0.25;
+};
+template <> struct FQuad<float> {
+    static constexpr int NODES = 15;
+    static constexpr float STEP = 1.0f / 3.0f;
+};
+
+// w[k-1] = exp(-(k h)^2), k = 1..NODES.  Call from every thread, then sync.
+template <typename R> __device__ inline void sg_fill_weights(R *w)
+{
+    for (int k = threadIdx.x; k < FQuad<R>::NODES; k += blockDim.x) {
+        double v = (k + 1) * (double)FQuad<R>::STEP;
+        w[k] = (R)exp(-v * v);
+    }
+}
+
+// Series branch, x < 2.  NT terms.
+template <typename R, int NT>
+__device__ inline void sg_F_series(R x, R &F, R *dF)
+{
+    const R y = x * x * R(0.25);
+    const R Lg = log(x * R(0.5)) + R(SG_EULER_GAMMA);
+    R tk = R(1), sk = R(1), Hk = R(0);
+    R I0 = R(0), I1s = R(0), K0s = R(0), K1s = R(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const R Hk1 = Hk + R(1) / R(k + 1);
+        I0 += tk;
+        I1s += sk;
+        K0s += Hk * tk;
+        K1s += (Hk + Hk1) * sk;
+        tk *= y / R((k + 1) * (k + 1));
+        sk *= y / R((k + 1) * (k + 2));
+        Hk = Hk1;
+    }
+    const R I1 = x * R(0.5) * I1s;
+    const R K0 = -Lg * I0 + K0s;
+    const R K1 = R(1) / x + Lg * I1 - x * R(0.25) * K1s;
+    const R ex = exp(x);
+    F = ex * (K1 - K0);
+    if (dF) *dF = ex * (R(2) * (K1 - K0) - K1 / x);
+}
+
+// Trapezoidal branch, x >= 2: F = sqrt(2) x^-3/2 J, F' from J' =
+// int v^2 e^{-v^2} v^2/(4x^2) (1 + v^2/(2x))^{-3/2} dv.
+template <typename R>
+__device__ inline void sg_F_quad(R x, const R *w, R &F, R *dF)
+{
+    const R i2x = R(0.5) / x;
+    R J = R(0), Jd = R(0);
+#pragma unroll
+    for (int k = 1; k <= FQuad<R>::NODES; ++k) {
+        const R v2 = R(k * k) * (FQuad<R>::STEP * FQuad<R>::STEP);
+        const R rho = rsqrt(R(1) + v2 * i2x);
+        const R base = w[k - 1] * v2 * rho;
+        J += base;
+        if (dF) Jd += base * rho * rho * v2;
+    }
+    J *= FQuad<R>::STEP;
+    const R rx = rsqrt(x);
+    const R x32 = rx / x;  // x^-3/2
+    F = R(SG_SQRT2) * x32 * J;
+    if (dF) {
+        const R Jp = Jd * FQuad<R>::STEP * R(0.25) / (x * x);
+        *dF = R(SG_SQRT2) * x32 * (Jp - R(1.5) * J / x);
+    }
+}
+
+// Asymptotic branch (float), x >= 32.
+struct AsymCoef {
+    float c[6];
+    constexpr AsymCoef() : c{}
+    {
+        double v = 1.0;
+        c[0] = 1.0f;
+        for (int n = 1; n < 6; ++n) {
+            v = -v * (4.0 * n * n - 1.0) / (8.0 * n);
+            c[n] = (float)v;
+        }
+    }
+};
+
+__device__ inline float sg_F_asym(float x)
+{
+    constexpr AsymCoef C;
+    const float u = 1.0f / x;
+    float s = C.c[5];
+#pragma unroll
+    for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
+    const float J = float(SG_SQRT_PI * 0.25) * s;
+    const float rx = rsqrtf(x);
+    return float(SG_SQRT2) * rx * u * J;
+}
+
+// Full-range evaluators.
+__device__ inline double sg_F64(double x, const double *w)
+{
+    double F;
+    if (x < 2.0) sg_F_series<double, 14>(x, F, nullptr);
+    else sg_F_quad<double>(x, w, F, nullptr);
+    return F;
+}
+
+__device__ inline void sg_F64_dF(double x, const double *w, double &F, double &dF)
+{
+    if (x < 2.0) sg_F_series<double, 14>(x, F, &dF);
+    else sg_F_quad<double>(x, w, F, &dF);
+}
+
+__device__ inline float sg_F32(float x, const float *w)
+{
+    float F;
+    if (x < 1.0f) sg_F_series<float, 8>(x, F, nullptr);
+    else if (x < 32.0f) sg_F_quad<float>(x, w, F, nullptr);
+    else F = sg_F_asym(x);
+    return F;
+}
+
+// ------------------------------------------------------------------------
+// Log-polar (App. C) kernels for H_f = h_f r, double precision:
+//   h^2(X) = (h_a^2 e^{-X} + h_b^2 e^{X}) / 2,  x = (cosh X - cos phi)/(4 h^2),
+//   K_r   = F(x) e^{-3X/2} h^{-3} (e^X - cos phi) / (8 sqrt(pi)),
+//   K_phi = F(x) e^{-3X/2} h^{-3} sin phi / (8 sqrt(pi)),
+// (App. C's L/(pi d^2) [e^{-X}/h^2]^{3/2} with L = sqrt(pi) x F(x), x = d^2/8).
+// cosh X - cos phi = 2 sinh^2(X/2) + 2 sin^2(phi/2) and e^X - cos phi =
+// expm1(X) + 2 sin^2(phi/2) avoid cancellation near the origin.
+// which = 1, 2: derivatives with respect to h_a, h_b:
+//   dK/d(h^2) = K-prefactor (h^2)^{-5/2} [-x F'(x) - 3/2 F(x)],
+//   d(h^2)/dh_a = h_a e^{-X},  d(h^2)/dh_b = h_b e^{X}.
+// sin(phi/2), sin(phi) are passed in so callers can use exact arguments.
+// ------------------------------------------------------------------------
+__device__ inline void sg_conv_kernel64(double X, double sphi_half, double sphi, double ha,
+                                        double hb, int which, const double *w, double &Kr,
+                                        double &Kp)
+{
+    const double eX = exp(X);
+    const double h2 = 0.5 * (ha * ha / eX + hb * hb * eX);
+    const double sxh = sinh(0.5 * X);
+    const double two_s2 = 2.0 * sphi_half * sphi_half;
+    const double cmc = 2.0 * sxh * sxh + two_s2;   // cosh X - cos phi
+    const double emc = expm1(X) + two_s2;          // e^X - cos phi
+    const double x = cmc / (4.0 * h2);
+    const double G = exp(-1.5 * X) * (1.0 / (8.0 * SG_SQRT_PI));
+    if (which == 0) {
+        const double F = sg_F64(x, w);
+        const double pref = F * G / (h2 * sqrt(h2));
+        Kr = pref * emc;
+        Kp = pref * sphi;
+        return;
+    }
+    double F, dF;
+    sg_F64_dF(x, w, F, dF);
+    const double dK = G / (h2 * h2 * sqrt(h2)) * (-x * dF - 1.5 * F);
+    const double dh2 = which == 1 ? ha / eX : hb * eX;
+    Kr = dK * dh2 * emc;
+    Kp = dK * dh2 * sphi;
+}
+
+// X-symmetrised radial kernel used by the self-cell average.
+__device__ inline double sg_sym_kr64(double X, double phi, double ha, double hb, int which,
+                                     const double *w)
+{
+    const double sh = sin(0.5 * phi), s = sin(phi);
+    double k1, k2, t;
+    sg_conv_kernel64(X, sh, s, ha, hb, which, w, k1, t);
+    sg_conv_kernel64(-X, sh, s, ha, hb, which, w, k2, t);
+    return 0.5 * (k1 + k2);
+}

@@ -1,0 +1,136 @@
+// sg_passes.h -- the three device passes of the log-polar FFT convolution
+// (App. C convolution form with the radial zero padding of Sect. 5.2) and the
+// pieces the adjoint reuses.  Float arithmetic throughout.
+//
+// Data flow for one disc (F fluids, n_r x n_phi, NU = 2 n_r):
+//   pass 1  rows:    Sigma (real) --phi FFT--> Sigma~[a][m][i], m <= n_phi/2
+//                    (two real rows per complex transform, Hermitian split)
+//   pass 2  columns: Sigma~[.][m][:] --zero-padded u FFT (length NU)-->
+//                    multiply by the kernel spectra of every ordered pair and
+//                    both components (gg, dg, gd, dd fused) --inverse u FFT,
+//                    first n_r outputs--> g^[b][c][m][i]
+//   pass 3  rows:    g^[b][r][.][i] + i g^[b][phi][.][i] --inverse phi FFT-->
+//                    g_r[b][i][:] + i g_phi[b][i][:]  (two real outputs per
+//                    complex transform)
+// The kernel spectra already carry the factor -du dphi/(2 n_r n_phi), so no
+// pass scales.  Intermediates use the 4-column block layout of sg_blk_index.
+#pragma once
+#include "sg_fft.h"
+
+struct DiscDev {
+    const float *sigma;
+    float *gr, *gp;
+    const float2 *spec;     // [m][pair][c][kk]
+    const float2 *dspec;    // [m][pair][d][c][kk] or null
+    const float2 *tw_u, *tw_phi;
+    float2 *st;             // [F][blk]
+    float2 *gh;             // [F][2][blk]
+    int nr, nphi, nf, pad_;
+};
+
+// A job is (disc index, job index inside the disc); disc < 0 marks padding.
+struct Job {
+    int disc, idx;
+};
+
+// launch shape shared by host and device
+template <int N> struct PassShape {
+    static constexpr int P = FftShape<N>::P;
+    static constexpr int T = FftShape<N>::T;
+    static constexpr int WGS = T > 256 ? T : 256;
+    static constexpr int G = WGS / T;             // transforms per workgroup
+    static constexpr int K = G >= 4 ? 1 : 4 / G;  // workgroups per XCD cluster
+};
+
+template <int N> __device__ inline float2 lds_get(const LdsPlane<float> &pl, int i)
+{
+    const int q = LdsPlane<float>::pad(i);
+    return make_float2(pl.re[q], pl.im[q]);
+}
+
+// ------------------------------------------------------------------ pass 1
+// Forward phi transform of two real rows x1 + i x2 (length N) followed by the
+// Hermitian split
+//   X1[m] = (Z[m] + conj Z[-m]) / 2,  X2[m] = (Z[m] - conj Z[-m]) / (2i),
+// written for m in [0, N/2] to block-layout fields d1 (row i1) and d2 (row i2).
+template <int N>
+__device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1, int i1,
+                                    float2 *d2, int i2, int nr, const float2 *tw, int t,
+                                    LdsPlane<float> pl, bool valid)
+{
+    using S = PassShape<N>;
+    constexpr int P = S::P, T = S::T;
+    float2 z[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        z[p] = valid ? make_float2(x1[t + T * p], x2[t + T * p]) : make_float2(0.f, 0.f);
+    fft<N, false>(z, t, pl, TwTable{tw});
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int q = LdsPlane<float>::pad(t + T * p);
+        pl.re[q] = z[p].x;
+        pl.im[q] = z[p].y;
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int p = 0; p <= P / 2; ++p) {
+            const int m = t + T * p;
+            if (p == P / 2 && t != 0) break;
+            const float2 Z = lds_get<N>(pl, m);
+            const float2 C = lds_get<N>(pl, (N - m) & (N - 1));
+            // conj(C) = (C.x, -C.y)
+            d1[sg_blk_index(m, i1, nr)] = make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y));
+            d2[sg_blk_index(m, i2, nr)] = make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x));
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ pass 3
+// Inverse phi transform of A + i B, where A (row iA) and B (row iB) are half
+// spectra of real rows extended by G[N - m] = conj G[m]; the real and
+// imaginary parts of the result are the two real rows o1, o2.
+template <int N>
+__device__ inline void phi_inv_pair(const float2 *A, int iA, const float2 *B, int iB, int nr,
+                                    const float2 *tw, float *o1, float *o2, int t,
+                                    LdsPlane<float> pl, bool valid)
+{
+    using S = PassShape<N>;
+    constexpr int P = S::P, T = S::T;
+    float2 z[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int m = t + T * p;
+        float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+        if (valid) {
+            if (m <= N / 2) {
+                a = A[sg_blk_index(m, iA, nr)];
+                b = B[sg_blk_index(m, iB, nr)];
+            } else {
+                a = c_conj(A[sg_blk_index(N - m, iA, nr)]);
+                b = c_conj(B[sg_blk_index(N - m, iB, nr)]);
+            }
+        }
+        z[p] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
+    }
+    fft<N, true>(z, t, pl, TwTable{tw});
+    if (valid) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            o1[t + T * p] = z[p].x;
+            o2[t + T * p] = z[p].y;
+        }
+    }
+}
+
+// Kernel-spectrum lookup at u-frequency k (0 <= k < NU) for component c:
+// stored for k <= NU/2; K_r is Hermitian and K_phi anti-Hermitian in k.
+template <int NU>
+__device__ inline float2 kspec(const float2 *col, int k, int c)
+{
+    constexpr int H = NU / 2;
+    if (k <= H) return col[k];
+    const float2 v = col[NU - k];
+    return c == 0 ? make_float2(v.x, -v.y) : make_float2(-v.x, v.y);
+}

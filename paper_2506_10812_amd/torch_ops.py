@@ -1,0 +1,133 @@
+"""PyTorch-facing helpers over the C ABI: device buffers from torch, the
+current stream, and a torch.autograd.Function whose backward is the
+library's hand-written adjoint.  All arithmetic happens in libsg.so."""
+from __future__ import annotations
+
+import torch
+
+from . import (F32, F64, SELF_CELL_EXCLUDE, WITH_DH, field_adjoint, field_adjoint_workspace_bytes,
+               field_direct, field_direct_workspace_bytes, field_fft, field_fft_workspace_bytes,
+               fluids, grid, kernel_table, kernel_table_bytes, kernel_table_workspace_bytes,
+               make_disc)
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+def build_table(g, f, flags=0, device=None):
+    """Kernel table (uint8 device tensor) for grid g, fluids f."""
+    dev = _dev(device)
+    nb = kernel_table_bytes(g, f, flags)
+    if nb == 0:
+        raise ValueError("unsupported grid / fluids for the FFT path")
+    table = torch.empty(nb, dtype=torch.uint8, device=dev)
+    ws = torch.empty(kernel_table_workspace_bytes(g, f, flags), dtype=torch.uint8, device=dev)
+    kernel_table(g, f, flags, table, ws)
+    torch.cuda.current_stream(dev).synchronize()
+    del ws
+    return table
+
+
+class FFTField:
+    """A fixed batch of discs for sg_field_fft with persistent tables,
+    workspace and outputs (so the cached graph keeps stable addresses)."""
+
+    def __init__(self, specs, flags=0, device=None):
+        dev = _dev(device)
+        self.device = dev
+        self.specs = []
+        self.tables, self.sigma, self.g_r, self.g_phi = [], [], [], []
+        self.discs = []
+        for s in specs:
+            g = grid(s["n_r"], s["n_phi"], s["r_min"], s["r_max"])
+            f = fluids(s["h"])
+            nf = len(s["h"])
+            shape = (nf, s["n_r"], s["n_phi"])
+            tab = build_table(g, f, flags, dev)
+            sig = torch.zeros(shape, dtype=torch.float32, device=dev)
+            gr = torch.empty(shape, dtype=torch.float32, device=dev)
+            gp = torch.empty(shape, dtype=torch.float32, device=dev)
+            self.tables.append(tab)
+            self.sigma.append(sig)
+            self.g_r.append(gr)
+            self.g_phi.append(gp)
+            self.discs.append(make_disc(g, f, flags, sig, gr, gp, tab))
+            self.specs.append((g, f))
+        self.ws = torch.empty(max(1, field_fft_workspace_bytes(self.discs)), dtype=torch.uint8,
+                              device=dev)
+
+    def set_sigma(self, i, sigma):
+        self.sigma[i].copy_(torch.as_tensor(sigma, dtype=torch.float32))
+
+    def run(self, stream=None):
+        field_fft(self.discs, self.ws, stream=stream)
+
+
+def direct(g, h, sigma, H=None, flags=0, stream=None):
+    """sg_field_direct on torch tensors (float32 or float64, same dtype)."""
+    dt = F64 if sigma.dtype == torch.float64 else F32
+    nf = sigma.shape[0]
+    gr = torch.empty_like(sigma)
+    gp = torch.empty_like(sigma)
+    ws = torch.empty(field_direct_workspace_bytes(g, nf, dt, H is not None), dtype=torch.uint8,
+                     device=sigma.device)
+    field_direct(g, nf, list(h) if h is not None else None, sigma, H, gr, gp, dt, flags, ws,
+                 stream=stream)
+    return gr, gp
+
+
+class _TableCache:
+    def __init__(self):
+        self.key = None
+        self.table = None
+
+    def get(self, g, hs, flags, device):
+        key = (g.n_r, g.n_phi, g.r_min, g.r_max, tuple(hs), flags, str(device))
+        if key != self.key:
+            self.table = build_table(g, fluids(list(hs)), flags, device)
+            self.key = key
+        return self.table
+
+
+_cache = _TableCache()
+
+
+class SGField(torch.autograd.Function):
+    """g_r, g_phi = SGField.apply(sigma, h, n_r, n_phi, r_min, r_max).
+
+    sigma: float32 CUDA tensor [F][n_r][n_phi]; h: float64 tensor [F] of
+    aspect ratios.  Forward: sg_field_fft.  Backward: sg_field_adjoint
+    (dL/dSigma and dL/dh)."""
+
+    @staticmethod
+    def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max):
+        g = grid(n_r, n_phi, r_min, r_max)
+        hs = [float(v) for v in h.detach().cpu().tolist()]
+        flags = WITH_DH
+        table = _cache.get(g, hs, flags, sigma.device)
+        sigma_c = sigma.detach().contiguous().to(torch.float32)
+        gr = torch.empty_like(sigma_c)
+        gp = torch.empty_like(sigma_c)
+        f = fluids(hs)
+        disc = make_disc(g, f, flags, sigma_c, gr, gp, table)
+        ws = torch.empty(field_fft_workspace_bytes([disc]), dtype=torch.uint8, device=sigma.device)
+        field_fft([disc], ws)
+        ctx.save_for_backward(sigma_c, table)
+        ctx.meta = (g, hs, flags)
+        return gr, gp
+
+    @staticmethod
+    def backward(ctx, lam_r, lam_phi):
+        sigma_c, table = ctx.saved_tensors
+        g, hs, flags = ctx.meta
+        f = fluids(hs)
+        lam_r = (lam_r if lam_r is not None else torch.zeros_like(sigma_c)).contiguous().float()
+        lam_phi = (lam_phi if lam_phi is not None else torch.zeros_like(sigma_c)).contiguous().float()
+        dsig = torch.empty_like(sigma_c)
+        dh = torch.empty(len(hs), dtype=torch.float64, device=sigma_c.device)
+        disc = make_disc(g, f, flags, sigma_c, lam_r, lam_phi, table)  # g_r/g_phi unused
+        ws = torch.empty(field_adjoint_workspace_bytes(disc), dtype=torch.uint8,
+                         device=sigma_c.device)
+        field_adjoint(disc, lam_r, lam_phi, dsig, dh, ws)
+        return dsig, dh, None, None, None, None

@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/sg.h, sizes are computed on the host and
+invalid arguments are rejected before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sg.h")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    libp = os.path.join(ROOT, "paper_2506_10812_amd", "libsg.so")
+    csrc = os.path.join(ROOT, "paper_2506_10812_amd", "csrc")
+    newest = max(os.path.getmtime(os.path.join(csrc, f)) for f in os.listdir(csrc))
+    if not os.path.exists(libp) or os.path.getmtime(libp) < newest:
+        from paper_2506_10812_amd import build
+        build.build()
+    import paper_2506_10812_amd as m
+    return m
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_paths():
+    names = declared_functions()
+    for n in ("sg_kernel_table", "sg_field_direct", "sg_field_fft", "sg_field_adjoint"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(sg):
+    lib = ctypes.CDLL(sg.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(sg.EXPORTED)
+
+
+def test_status_strings(sg):
+    for s in range(6):
+        assert sg.status_string(s).startswith("SG_")
+    assert sg.version() >= 1
+
+
+def test_table_size_is_host_computable(sg):
+    g = sg.grid(1024, 2048, 0.2, 5.0)
+    f = sg.fluids([0.05, 0.005])
+    nb = sg.kernel_table_bytes(g, f, 0)
+    # four ordered pairs x two components x (n_r+1)(n_phi/2+1) complex64 spectra dominate
+    spec = 4 * 2 * 1025 * 1025 * 8
+    assert spec < nb < spec + 64 * 1024
+    nb_dh = sg.kernel_table_bytes(g, f, sg.WITH_DH)
+    assert nb_dh - nb >= 2 * spec
+    assert sg.kernel_table_workspace_bytes(g, f, 0) > 0
+
+
+@pytest.mark.parametrize("nr,nphi", [(3, 8), (8, 12), (1, 8), (4096, 8), (8, 2), (8, 4096)])
+def test_fft_path_rejects_unsupported_grids(sg, nr, nphi):
+    g = sg.grid(nr, nphi, 0.2, 5.0)
+    f = sg.fluids([0.05])
+    assert sg.kernel_table_bytes(g, f, 0) == 0
+    st = sg.lib().sg_kernel_table(ctypes.byref(g), ctypes.byref(f), 0, ctypes.c_void_p(256),
+                                  ctypes.c_void_p(512), 1 << 40, None)
+    assert st == sg.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("h,rmin,rmax", [([0.0], 0.2, 5.0), ([-1.0], 0.2, 5.0),
+                                         ([float("nan")], 0.2, 5.0), ([0.05], 0.0, 5.0),
+                                         ([0.05], 5.0, 0.2)])
+def test_invalid_physics_arguments(sg, h, rmin, rmax):
+    g = sg.grid(16, 32, rmin, rmax)
+    f = sg.fluids(h)
+    st = sg.lib().sg_kernel_table(ctypes.byref(g), ctypes.byref(f), 0, ctypes.c_void_p(256),
+                                  ctypes.c_void_p(512), 1 << 40, None)
+    assert st == sg.ERR_ARG
+
+
+def test_workspace_checks_happen_before_launch(sg):
+    g = sg.grid(16, 32, 0.2, 5.0)
+    f = sg.fluids([0.05])
+    st = sg.lib().sg_kernel_table(ctypes.byref(g), ctypes.byref(f), 0, ctypes.c_void_p(256),
+                                  ctypes.c_void_p(512), 16, None)
+    assert st == sg.ERR_WORKSPACE
+    d = sg.Disc(g, f, 0, 0, 256, 512, 768, 1024)
+    arr = (sg.Disc * 1)(d)
+    need = sg.field_fft_workspace_bytes([d])
+    assert need > 0
+    assert sg.lib().sg_field_fft(arr, 1, ctypes.c_void_p(2048), need - 1, None) == sg.ERR_WORKSPACE
+    assert sg.lib().sg_field_fft(arr, 0, ctypes.c_void_p(2048), need, None) == sg.ERR_ARG
+    assert sg.lib().sg_field_fft(None, 1, ctypes.c_void_p(2048), need, None) == sg.ERR_ARG
+    d.sigma = None
+    arr = (sg.Disc * 1)(d)
+    assert sg.lib().sg_field_fft(arr, 1, ctypes.c_void_p(2048), need, None) == sg.ERR_ARG
+
+
+def test_direct_validation(sg):
+    g = sg.grid(5, 7, 0.2, 5.0)
+    need = sg.field_direct_workspace_bytes(g, 2, sg.F64, False)
+    assert need > 0
+    L = sg.lib()
+    h = (ctypes.c_double * 2)(0.05, 0.01)
+    hp = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+    # bad dtype, bad fluid count, missing h, bad flag, small workspace
+    assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, 7, 0, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 3, hp, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 2, None, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, sg.F64, sg.WITH_DH, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, sg.F64, 0, 1024, need - 1, None) == sg.ERR_WORKSPACE
+    big = sg.grid(1 << 14, 1 << 13, 0.2, 5.0)
+    assert sg.field_direct_workspace_bytes(big, 1, sg.F32, False) == 0
+
+
+def test_adjoint_needs_dh_table(sg):
+    g = sg.grid(16, 32, 0.2, 5.0)
+    f = sg.fluids([0.05])
+    d = sg.Disc(g, f, 0, 0, 256, 512, 768, 1024)
+    need = sg.field_adjoint_workspace_bytes(d)
+    assert need > 0
+    st = sg.lib().sg_field_adjoint(ctypes.byref(d), 256, 512, 768, 1024, 2048, need, None)
+    assert st == sg.ERR_TABLE

@@ -1,0 +1,363 @@
+"""Parity of the HIP library (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances: the FP64 direct sum must agree to 1e-12 (relative RMS and max
+relative to the largest |g|; summation order differs, so not bitwise); every
+float path to 1e-5 relative RMS per fluid and component (the float
+accuracy bound of the build's target), with max-norm bounds stated per test.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_10812_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def T(sg):
+    from paper_2506_10812_amd import torch_ops
+    return torch_ops
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2506_10812_amd import workloads
+    return workloads
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------- F(x)
+def test_device_F64_matches_oracle(sg):
+    say("F64 device vs oracle")
+    x = np.logspace(-12, 4.6, 400)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(xt)
+    dF = torch.empty_like(xt)
+    sg.eval_F(xt, F, dF, sg.F64)
+    torch.cuda.synchronize()
+    ref = O.F(x)
+    dref = O.dF(x)
+    e1 = float(np.max(np.abs(F.cpu().numpy() / ref - 1)))
+    e2 = float(np.max(np.abs(dF.cpu().numpy() / dref - 1)))
+    say(f"  max rel err F {e1:.2e} F' {e2:.2e}")
+    assert e1 < 3e-14 and e2 < 1e-13, (e1, e2)
+
+
+def test_device_F32_matches_oracle(sg):
+    say("F32 device vs oracle")
+    x = np.logspace(-10, 4.6, 400)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    F = torch.empty_like(xt)
+    sg.eval_F(xt, F, None, sg.F32)
+    torch.cuda.synchronize()
+    ref = O.F(xt.double().cpu().numpy())
+    e = float(np.max(np.abs(F.double().cpu().numpy() / ref - 1)))
+    say(f"  max rel err {e:.2e}")
+    assert e < 2e-6, e
+
+
+def test_device_self_cell_matches_oracle(sg):
+    say("self-cell quadrature device vs oracle")
+    g = sg.grid(1024, 2048, 0.2, 5.0)
+    ha = [0.05, 0.005, 0.05, 0.005, 0.01]
+    hb = [0.05, 0.05, 0.005, 0.005, 0.05]
+    du = np.log(5.0 / 0.2) / 1024
+    dphi = 2 * np.pi / 2048
+    for which in (0, 1, 2):
+        out = torch.empty(len(ha), dtype=torch.float64, device="cuda")
+        sg.self_cell(g, ha, hb, which, out)
+        torch.cuda.synchronize()
+        ref = np.array([O.self_cell(a, b, du, dphi, which) for a, b in zip(ha, hb)])
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-11)
+
+
+# ---------------------------------------------------------------- direct
+def test_direct_fp64_64x128_matches_pairwise_oracle(sg, T, W):
+    """The 64 x 128 FP64 direct-sum workload, full field, vs the plain
+    pairwise Cartesian oracle.  Bar: 1e-12 relative RMS of g_r and of the
+    vector field (g_r, g_phi), and 1e-12 of max |g| for the largest error of
+    either component.  (g_phi is ~1% of |g| here; its own relative RMS is
+    bounded by double-precision summation cancellation at ~1e-12 in any
+    summation order, so it is reported, not used as the bar.)"""
+    w = W.direct_fp64()
+    say("direct FP64 64x128 single fluid")
+    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+    s = torch.tensor(w["sigma"], dtype=torch.float64, device="cuda")
+    gr, gp = T.direct(g, w["h"], s)
+    torch.cuda.synchronize()
+    rr, rp = O.field_pairwise(w["n_r"], w["n_phi"], w["r_min"], w["r_max"], w["h"], w["sigma"])
+    gr = gr.cpu().numpy().reshape(1, -1)
+    gp = gp.cpu().numpy().reshape(1, -1)
+    e_r = rel_rms(gr, rr)
+    e_p = rel_rms(gp, rp)
+    e_vec = float(np.sqrt(np.sum((gr - rr) ** 2 + (gp - rp) ** 2) / np.sum(rr ** 2 + rp ** 2)))
+    scale = float(np.sqrt(rr ** 2 + rp ** 2).max())
+    m_r = float(np.abs(gr - rr).max()) / scale
+    m_p = float(np.abs(gp - rp).max()) / scale
+    say(f"  rel-RMS g_r {e_r:.2e} g_phi {e_p:.2e} vector {e_vec:.2e}; max/max|g| {m_r:.2e} {m_p:.2e}")
+    assert e_r < 1e-12 and e_vec < 1e-12 and m_r < 1e-12 and m_p < 1e-12
+
+
+@pytest.mark.parametrize("nr,nphi", [(1, 1), (1, 3), (5, 7), (13, 29)])
+def test_direct_fp64_general_H_two_fluids_ragged(sg, T, nr, nphi):
+    """Per-cell scale heights, two fluids, sizes that are not powers of two
+    (ragged tails of the 256-thread tiles), self term per cell."""
+    say(f"direct FP64 general H {nr}x{nphi}")
+    rng = np.random.default_rng(nr * 100 + nphi)
+    rmin, rmax = 0.3, 2.0
+    sig = rng.uniform(0.2, 2.0, (2, nr, nphi))
+    r, _, _, _ = O.grid(nr, nphi, rmin, rmax)
+    H = rng.uniform(0.01, 0.15, (2, nr, nphi)) * r[None, :, None]
+    g = sg.grid(nr, nphi, rmin, rmax)
+    gr, gp = T.direct(g, None, torch.tensor(sig, device="cuda"), H=torch.tensor(H, device="cuda"))
+    torch.cuda.synchronize()
+    rr, rp = O.field_pairwise(nr, nphi, rmin, rmax, [0, 0], sig, H=H)
+    gr = gr.cpu().numpy().reshape(2, -1)
+    gp = gp.cpu().numpy().reshape(2, -1)
+    scale = float(np.sqrt(rr ** 2 + rp ** 2).max())
+    m_r = float(np.abs(gr - rr).max()) / scale
+    m_p = float(np.abs(gp - rp).max()) / scale
+    say(f"  max/max|g| {m_r:.2e} {m_p:.2e}")
+    assert m_r < 1e-12 and m_p < 1e-12
+
+
+def test_direct_fp64_exclude_self(sg, T):
+    say("direct FP64 without self term")
+    rng = np.random.default_rng(9)
+    nr, nphi = 8, 12
+    sig = rng.uniform(0.2, 2.0, (2, nr, nphi))
+    g = sg.grid(nr, nphi, 0.3, 2.0)
+    gr, gp = T.direct(g, [0.07, 0.02], torch.tensor(sig, device="cuda"), flags=sg.SELF_CELL_EXCLUDE)
+    torch.cuda.synchronize()
+    rr, rp = O.field_pairwise(nr, nphi, 0.3, 2.0, [0.07, 0.02], sig, flags=O.EXCLUDE_SELF)
+    scale = np.abs(rr).max()
+    assert np.abs(gr.cpu().numpy().reshape(2, -1) - rr).max() < 1e-12 * scale
+    assert np.abs(gp.cpu().numpy().reshape(2, -1) - rp).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(64, 128, 1), (24, 40, 2)])
+def test_direct_fp32_matches_oracle(sg, T, nr, nphi, nf):
+    say(f"direct FP32 {nr}x{nphi} nf={nf}")
+    rng = np.random.default_rng(nr + nf)
+    r, _, _, _ = O.grid(nr, nphi, 0.2, 2.5)
+    sig = (1 / r)[None, :, None] * rng.uniform(0.5, 1.5, (nf, nr, nphi))
+    h = [0.05, 0.005][:nf]
+    g = sg.grid(nr, nphi, 0.2, 2.5)
+    gr, gp = T.direct(g, h, torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    sig32 = torch.tensor(sig, dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(nr, nphi, 0.2, 2.5, h, sig32)
+    gr = gr.double().cpu().numpy().reshape(nf, -1)
+    gp = gp.double().cpu().numpy().reshape(nf, -1)
+    for b in range(nf):
+        assert rel_rms(gr[b], rr[b]) < 1e-5
+        assert rel_rms(gp[b], rp[b]) < 1e-5
+
+
+# ---------------------------------------------------------------- table
+def test_kernel_table_matches_numpy_fft_of_oracle_samples(sg, T):
+    """Device FP64 table build vs numpy FP64 FFT of the oracle's own kernel
+    samples on the wrapped offset grid (self term at the origin)."""
+    nr, nphi, rmin, rmax = 16, 32, 0.2, 5.0
+    h = [0.05, 0.01]
+    say("kernel table spectra vs numpy FFT of oracle samples")
+    g = sg.grid(nr, nphi, rmin, rmax)
+    f = sg.fluids(h)
+    tab = T.build_table(g, f, 0)
+    raw = tab.cpu().numpy()
+    _, _, du, dphi = O.grid(nr, nphi, rmin, rmax)
+    off_spec = None
+    # offsets: header, tw_u (2 nr float2), tw_phi (nphi float2), all 256-aligned
+    al = lambda x: (x + 255) // 256 * 256
+    o = al(256)  # header < 256 bytes
+    o = al(o + 8 * 2 * nr)
+    o = al(o + 8 * nphi)
+    off_spec = o
+    ncol, kk = nphi // 2 + 1, nr + 1
+    spec = raw[off_spec:off_spec + 8 * ncol * 4 * 2 * kk].view(np.complex64).reshape(ncol, 4, 2, kk)
+    p = np.arange(2 * nr)
+    X = np.where(p < nr, p, p - 2 * nr) * du
+    q = np.arange(nphi) * dphi
+    XX, QQ = np.meshgrid(X, q, indexing="ij")
+    scale = -du * dphi / (2 * nr * nphi)
+    for a in range(2):
+        for b in range(2):
+            kr, kp = O.conv_kernels(XX.ravel(), QQ.ravel(), h[a], h[b])
+            kr = kr.reshape(2 * nr, nphi)
+            kp = kp.reshape(2 * nr, nphi)
+            kr[nr, :] = 0
+            kp[nr, :] = 0
+            kr[0, 0] = O.self_cell(h[a], h[b], du, dphi)
+            kp[0, 0] = 0
+            for c, K in enumerate((kr, kp)):
+                ref = np.fft.fft2(K)[:nr + 1, :ncol].T * scale  # [m][k]
+                got = spec[:, a * 2 + b, c, :]
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err < 1e-6, (a, b, c, err)
+
+
+# ---------------------------------------------------------------- FFT path
+def _fft_run(T, W, specs, flags=0):
+    F = T.FFTField(specs, flags=flags)
+    for i, s in enumerate(specs):
+        F.set_sigma(i, s["sigma"])
+    F.run()
+    torch.cuda.synchronize()
+    return F
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(2, 4, 1), (4, 8, 2), (8, 16, 1), (16, 64, 2),
+                                        (32, 32, 1), (64, 128, 2), (128, 256, 1), (8, 512, 2)])
+def test_fft_path_full_field_small_grids(sg, T, W, nr, nphi, nf):
+    say(f"fft path full field {nr}x{nphi} nf={nf}")
+    w = W.bifluid_fft(seed=nr + nphi, n_r=nr, n_phi=nphi) if nf == 2 else \
+        W.single_fft(seed=nr + nphi, n_r=nr, n_phi=nphi)
+    F = _fft_run(T, W, [w])
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32)
+    gr = F.g_r[0].double().cpu().numpy().reshape(nf, -1)
+    gp = F.g_phi[0].double().cpu().numpy().reshape(nf, -1)
+    for b in range(nf):
+        assert rel_rms(gr[b], rr[b]) < 1e-5, (b, rel_rms(gr[b], rr[b]))
+        assert rel_rms(gp[b], rp[b]) < 1e-5, (b, rel_rms(gp[b], rp[b]))
+
+
+def test_fft_path_exclude_self(sg, T, W):
+    say("fft path without self term")
+    w = W.bifluid_fft(seed=21, n_r=32, n_phi=64)
+    F = _fft_run(T, W, [w], flags=sg.SELF_CELL_EXCLUDE)
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(32, 64, w["r_min"], w["r_max"], w["h"], sig32, flags=O.EXCLUDE_SELF)
+    gr = F.g_r[0].double().cpu().numpy().reshape(2, -1)
+    for b in range(2):
+        assert rel_rms(gr[b], rr[b]) < 1e-5
+
+
+def _sampled_check(F, i, w, n, tol=1e-5):
+    nr, nphi = w["n_r"], w["n_phi"]
+    idx = np.random.default_rng(7).choice(nr * nphi, size=min(n, nr * nphi), replace=False)
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, targets=idx)
+    nf = len(w["h"])
+    gr = F.g_r[i].double().cpu().numpy().reshape(nf, -1)[:, idx]
+    gp = F.g_phi[i].double().cpu().numpy().reshape(nf, -1)[:, idx]
+    out = []
+    for b in range(nf):
+        er, ep = rel_rms(gr[b], rr[b]), rel_rms(gp[b], rp[b])
+        out.append((er, ep))
+        assert er < tol and ep < tol, (b, er, ep)
+    return out
+
+
+def test_fft_path_single_fluid_512x1024_sampled(sg, T, W):
+    w = W.single_fft()
+    say("fft path 512x1024 single fluid, 4096 sampled cells")
+    F = _fft_run(T, W, [w])
+    say(f"  rel-RMS {_sampled_check(F, 0, w, 4096)}")
+
+
+def test_fft_path_two_fluid_1024x2048_sampled(sg, T, W):
+    w = W.bifluid_fft()
+    say("fft path 1024x2048 two fluids, 4096 sampled cells")
+    F = _fft_run(T, W, [w])
+    say(f"  rel-RMS {_sampled_check(F, 0, w, 4096)}")
+
+
+def test_fft_batch64_equals_single_disc_runs_and_oracle(sg, T, W):
+    discs = W.batch64()
+    say("fft path batch of 64 uneven discs")
+    F = _fft_run(T, W, discs)
+    # batched == each disc alone (same kernels, same arithmetic)
+    for i in (0, 7, 31, 63):
+        Fi = _fft_run(T, W, [discs[i]])
+        assert torch.equal(Fi.g_r[0], F.g_r[i]) and torch.equal(Fi.g_phi[0], F.g_phi[i]), i
+    for i in range(0, 64, 8):
+        _sampled_check(F, i, discs[i], 512)
+
+
+def test_fft_path_repeat_launches_are_identical(sg, T, W):
+    say("fft path graph replays")
+    w = W.bifluid_fft(seed=31, n_r=64, n_phi=128)
+    F = _fft_run(T, W, [w])
+    ref_r = F.g_r[0].clone()
+    for _ in range(3):
+        F.g_r[0].zero_()
+        torch.cuda.synchronize()
+        F.run()
+        torch.cuda.synchronize()
+        assert torch.equal(F.g_r[0], ref_r)
+
+
+# ---------------------------------------------------------------- adjoint
+def _adjoint(sg, T, w, lam_r, lam_p, want_dh=True):
+    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+    f = sg.fluids(w["h"])
+    tab = T.build_table(g, f, sg.WITH_DH)
+    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda")
+    lr = torch.tensor(lam_r, dtype=torch.float32, device="cuda")
+    lp = torch.tensor(lam_p, dtype=torch.float32, device="cuda")
+    ds = torch.empty_like(sig)
+    dh = torch.zeros(len(w["h"]), dtype=torch.float64, device="cuda")
+    disc = sg.make_disc(g, f, sg.WITH_DH, sig, lr, lp, tab)
+    ws = torch.empty(sg.field_adjoint_workspace_bytes(disc), dtype=torch.uint8, device="cuda")
+    sg.field_adjoint(disc, lr, lp, ds, dh if want_dh else None, ws)
+    torch.cuda.synchronize()
+    return ds.double().cpu().numpy(), dh.cpu().numpy()
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(8, 16, 1), (32, 64, 2), (64, 128, 2)])
+def test_adjoint_matches_oracle_full(sg, T, W, nr, nphi, nf):
+    say(f"adjoint full {nr}x{nphi} nf={nf}")
+    w = W.adjoint(n_r=nr, n_phi=nphi)
+    if nf == 1:
+        w["sigma"] = w["sigma"][:1]
+        w["h"] = w["h"][:1]
+    rng = np.random.default_rng(nr)
+    lam_r = rng.normal(size=(nf, nr, nphi))
+    lam_p = rng.normal(size=(nf, nr, nphi))
+    lam_r = torch.tensor(lam_r, dtype=torch.float32).double().numpy()
+    lam_p = torch.tensor(lam_p, dtype=torch.float32).double().numpy()
+    ds, dh = _adjoint(sg, T, w, lam_r, lam_p)
+    ref = O.adjoint_sigma(nr, nphi, w["r_min"], w["r_max"], w["h"], lam_r, lam_p)
+    for a in range(nf):
+        assert rel_rms(ds.reshape(nf, -1)[a], ref[a]) < 1e-5
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    refh = O.adjoint_h(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, lam_r, lam_p)
+    np.testing.assert_allclose(dh, refh, rtol=1e-4)
+
+
+def test_adjoint_256x512_sampled_and_loss_gradient(sg, T, W):
+    """The 256 x 512 two-fluid adjoint workload: L = sum (g_r - g_r*)^2 over
+    both fluids; dL/dSigma on 64 seeded cells per fluid vs the oracle's
+    transposed sum."""
+    w = W.adjoint()
+    nr, nphi = w["n_r"], w["n_phi"]
+    say("adjoint 256x512 two fluids")
+    F = _fft_run(T, W, [w])
+    Ft = _fft_run(T, W, [dict(w, sigma=w["sigma_target"])])
+    lam_r = 2 * (F.g_r[0] - Ft.g_r[0]).double().cpu().numpy()
+    lam_p = np.zeros_like(lam_r)
+    ds, dh = _adjoint(sg, T, w, lam_r, lam_p)
+    idx = np.random.default_rng(8).choice(nr * nphi, 64, replace=False)
+    lr32 = torch.tensor(lam_r, dtype=torch.float32).double().numpy()
+    ref = O.adjoint_sigma(nr, nphi, w["r_min"], w["r_max"], w["h"], lr32, lam_p, kidx=idx)
+    got = ds.reshape(2, -1)[:, idx]
+    for a in range(2):
+        assert rel_rms(got[a], ref[a]) < 1e-4
