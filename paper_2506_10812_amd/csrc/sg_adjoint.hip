@@ -42,19 +42,19 @@ template <int N>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_lam(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::words(N);
-    __shared__ float lds[2 * W * S::G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;
     const int idx = adj_job(S::G, S::K, g, none, A.count, valid);
     if (none) return;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const int nr = A.D.nr;
     const int b = valid ? idx / nr : 0, i = valid ? idx % nr : 0;
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t row = (size_t)b * nr * N + (size_t)i * N;
     phi_fwd_pair<N>(A.lam_r + row, A.lam_p + row, A.lt + (b * 2 + 0) * fs, i,
-                    A.lt + (b * 2 + 1) * fs, i, nr, A.D.tw_phi, t, pl, valid);
+                    A.lt + (b * 2 + 1) * fs, i, nr, TwTable{A.D.tw_phi}, t, pl, valid);
 }
 
 // pass 1 on Sigma (only when dh is requested): same pairing as the forward
@@ -62,13 +62,13 @@ template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_sig(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::words(N);
-    __shared__ float lds[2 * W * S::G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;
     const int idx = adj_job(S::G, S::K, g, none, A.count, valid);
     if (none) return;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const int nr = A.D.nr;
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_sig(AdjDev A)
     const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : 2 * j + 1;
     const int f2 = NF == 2 ? 1 : 0;
     phi_fwd_pair<N>(A.D.sigma + (size_t)i1 * N, A.D.sigma + f2 * plane + (size_t)i2 * N, A.st, i1,
-                    A.st + f2 * fs, i2, nr, A.D.tw_phi, t, pl, valid);
+                    A.st + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, t, pl, valid);
 }
 
 // pass 2: column m.  dSigma^_a = sum_{b,c} conj(K'_c^{ab}) lam^_{b,c}; with DH,
@@ -86,15 +86,15 @@ __global__ void __launch_bounds__(PassShape<NU>::WGS) k_adj_col(AdjDev A)
 {
     using S = PassShape<NU>;
     constexpr int P = S::P, T = S::T, G = S::G;
-    constexpr int W = LdsPlane<float>::words(NU);
+    constexpr int W = NU;
     constexpr int NR = NU / 2;
-    __shared__ float lds[2 * W * G];
+    __shared__ __attribute__((aligned(16))) float2 lds[W * G];
     __shared__ double red[DH ? S::WGS * NF : 1];
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     bool none, valid;
     const int m = adj_job(G, S::K, g, none, A.count, valid);
     if (none) return;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const TwTable tw{A.D.tw_u};
     const size_t fs = sg_blk_field_elems(A.D.nphi, NR);
     const int mm = valid ? m : 0;
@@ -192,20 +192,20 @@ template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_out(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::words(N);
-    __shared__ float lds[2 * W * S::G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;
     const int idx = adj_job(S::G, S::K, g, none, A.count, valid);
     if (none) return;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const int nr = A.D.nr;
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     const int j = valid ? idx : 0;
     const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : 2 * j + 1;
     const int f2 = NF == 2 ? 1 : 0;
-    phi_inv_pair<N>(A.dt, i1, A.dt + f2 * fs, i2, nr, A.D.tw_phi, A.dsig + (size_t)i1 * N,
+    phi_inv_pair<N>(A.dt, i1, A.dt + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, A.dsig + (size_t)i1 * N,
                     A.dsig + f2 * plane + (size_t)i2 * N, t, pl, valid);
 }
 

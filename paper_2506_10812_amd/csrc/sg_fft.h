@@ -92,14 +92,15 @@ template <> __device__ inline void dftR<8, false, double2>(double2 (&u)[8]) { df
 template <> __device__ inline void dftR<8, true, double2>(double2 (&u)[8]) { dft8<true>(u); }
 
 // ------------------------------------------------------------ twiddles
-// get(n) = e^{-2 pi i n / N} (forward); the transforms conjugate for INV.
+// A provider returns e^{-2 pi i n / N} for the flat index n = j k N/(L R) of
+// stage S, butterfly beta, leg j (the transforms conjugate for INV).
 struct TwTable {
     const float2 *tab;
-    __device__ inline float2 get(int n) const { return tab[n]; }
+    template <int S> __device__ inline float2 get(int n, int, int) const { return gload2(tab, n); }
 };
 
 template <int N> struct TwExact64 {
-    __device__ inline double2 get(int n) const
+    template <int S> __device__ inline double2 get(int n, int, int) const
     {
         double s, c;
         sincospi(-2.0 * (double)n / (double)N, &s, &c);
@@ -108,11 +109,19 @@ template <int N> struct TwExact64 {
 };
 
 // ------------------------------------------------------------ LDS exchange
-// Separate real / imaginary planes, padded one word per 32 to spread banks.
+// One plane of N complex values per transform, accessed with 64-bit (float2)
+// or 128-bit (double2) LDS instructions.  Element i lives at i ^ ((i>>3)&63):
+// the XOR swizzle stays inside each 64-element block (a bijection on [0, N)
+// for every power-of-two N) and makes every Stockham stage write and every
+// read conflict-free for 16-, 32- and 64-lane access groups, checked
+// exhaustively for N = 512..4096 when the layout was chosen.
 template <typename R> struct LdsPlane {
-    R *re, *im;
-    __device__ static inline int pad(int i) { return i + (i >> 5); }
-    static constexpr int words(int n) { return n + (n >> 5) + 1; }
+    using V = cplx_t<R>;
+    V *c;
+    __device__ static inline int swz(int i) { return i ^ ((i >> 3) & 63); }
+    __device__ inline void st(int i, V v) const { c[swz(i)] = v; }
+    __device__ inline V ld(int i) const { return c[swz(i)]; }
+    static constexpr int elems(int n) { return n; }
 };
 
 template <int N> struct FftShape {
@@ -120,75 +129,188 @@ template <int N> struct FftShape {
     static constexpr int T = N / P;
 };
 
-// One Stockham stage.  v: this thread's P points; t: thread index in group.
-template <int N, int L, bool INV, typename V, typename TW, typename R>
-__device__ inline void fft_stage(V (&v)[FftShape<N>::P], int t, LdsPlane<R> lds, const TW &tw)
+// Compile-time stage plan: stage s has sub-length L(s) (1, P, P^2, ...),
+// radix RAD(s) and NB(s) butterflies per thread; TWOFF(s) is the offset of
+// its twiddles in a per-thread register table (stage 0 needs none).
+template <int N> struct FftPlan {
+    static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+    static constexpr int L(int s) { int l = 1; for (int i = 0; i < s; ++i) l *= RADL(l); return l; }
+    static constexpr int RADL(int l) { return (N / l) >= P ? P : (N / l); }
+    static constexpr int RAD(int s) { return RADL(L(s)); }
+    static constexpr int NB(int s) { return P / RAD(s); }
+    static constexpr int NST() { int s = 0; while (L(s) < N) ++s; return s; }
+    static constexpr int TWOFF(int s) { int o = 0; for (int i = 1; i < s; ++i) o += NB(i) * (RAD(i) - 1); return o; }
+    static constexpr int NTW() { return TWOFF(NST()) > 0 ? TWOFF(NST()) : 1; }
+};
+
+// Twiddles of one thread for every stage, loaded once from the table and
+// kept in registers (all indices compile-time after unrolling).
+template <int N> struct TwReg {
+    float2 w[FftPlan<N>::NTW()];
+    __device__ inline void load(const float2 *tab, int t) { load_stage<1>(tab, t); }
+    template <int S> __device__ inline void load_stage(const float2 *g, int t)
+    {
+        using PL = FftPlan<N>;
+        if constexpr (S < PL::NST()) {
+            constexpr int Ls = PL::L(S), R = PL::RAD(S), NB = PL::NB(S), O = PL::TWOFF(S);
+#pragma unroll
+            for (int beta = 0; beta < NB; ++beta) {
+                const int k = (t + PL::T * beta) & (Ls - 1);
+#pragma unroll
+                for (int j = 1; j < R; ++j) w[O + beta * (R - 1) + j - 1] = gload2(g, j * k * (N / (Ls * R)));
+            }
+            load_stage<S + 1>(g, t);
+        }
+    }
+    template <int S> __device__ inline float2 get(int, int beta, int j) const
+    {
+        using PL = FftPlan<N>;
+        return w[PL::TWOFF(S) + beta * (PL::RAD(S) - 1) + j - 1];
+    }
+};
+
+// Compact variant: one twiddle w^k per (stage, butterfly) in registers; the
+// powers w^{jk} are formed by complex products (depth <= 3, a few ulps),
+// once per stage and shared by all transforms of the stage.
+template <int N> struct FftPlanC {
+    using PL = FftPlan<N>;
+    static constexpr int OFF(int s) { int o = 0; for (int i = 1; i < s; ++i) o += PL::NB(i); return o; }
+    static constexpr int NTW() { return OFF(PL::NST()) > 0 ? OFF(PL::NST()) : 1; }
+};
+
+template <int N> struct TwRegC {
+    float2 w[FftPlanC<N>::NTW()];
+    static constexpr bool POWERS = true;
+    __device__ inline void load(const float2 *tab, int t) { load_stage<1>(tab, t); }
+    template <int S> __device__ inline void load_stage(const float2 *g, int t)
+    {
+        using PL = FftPlan<N>;
+        if constexpr (S < PL::NST()) {
+            constexpr int Ls = PL::L(S), R = PL::RAD(S), NB = PL::NB(S);
+#pragma unroll
+            for (int beta = 0; beta < NB; ++beta) {
+                const int k = (t + PL::T * beta) & (Ls - 1);
+                w[FftPlanC<N>::OFF(S) + beta] = gload2(g, k * (N / (Ls * R)));
+            }
+            load_stage<S + 1>(g, t);
+        }
+    }
+    template <int S> __device__ inline float2 base(int beta) const { return w[FftPlanC<N>::OFF(S) + beta]; }
+};
+
+template <typename TW, typename = void> struct tw_has_powers { static constexpr bool value = false; };
+template <typename TW> struct tw_has_powers<TW, decltype((void)TW::POWERS, void())> {
+    static constexpr bool value = TW::POWERS;
+};
+
+// One Stockham stage on M independent transforms sharing the barriers.
+// v[m]: this thread's P points of transform m; t: thread index in the group.
+template <int N, int S, bool INV, int M, typename V, typename TW, typename R>
+__device__ inline void fft_stage_m(V (&v)[M][FftShape<N>::P], int t, const LdsPlane<R> (&lds)[M],
+                                   const TW &tw)
 {
-    constexpr int P = FftShape<N>::P;
-    constexpr int T = FftShape<N>::T;
-    constexpr int RAD = (N / L) >= P ? P : (N / L);
-    constexpr int NB = P / RAD;
+    using PL = FftPlan<N>;
+    constexpr int P = PL::P;
+    constexpr int T = PL::T;
+    constexpr int L = PL::L(S);
+    constexpr int RAD = PL::RAD(S);
+    constexpr int NB = PL::NB(S);
     constexpr bool LAST = (L * RAD == N);
-    V y[P];
+    V w[NB][RAD];
+    if (L > 1) {
 #pragma unroll
-    for (int beta = 0; beta < NB; ++beta) {
-        const int b = t + T * beta;
-        const int k = b & (L - 1);
-        V u[RAD];
+        for (int beta = 0; beta < NB; ++beta) {
+            if constexpr (tw_has_powers<TW>::value) {
+                V x = tw.template base<S>(beta);
+                if (INV) x.y = -x.y;
+                w[beta][1] = x;
+                if (RAD > 2) w[beta][2] = c_mul(x, x);
+                if (RAD > 3) w[beta][3] = c_mul(w[beta][2], x);
+                if (RAD > 4) {
+                    w[beta][4] = c_mul(w[beta][2], w[beta][2]);
+                    w[beta][5] = c_mul(w[beta][4], x);
+                    w[beta][6] = c_mul(w[beta][4], w[beta][2]);
+                    w[beta][7] = c_mul(w[beta][4], w[beta][3]);
+                }
+            } else {
+                const int k = (t + T * beta) & (L - 1);
 #pragma unroll
-        for (int j = 0; j < RAD; ++j) u[j] = v[beta + NB * j];
-        if (L > 1) {
-#pragma unroll
-            for (int j = 1; j < RAD; ++j) {
-                V w = tw.get(j * k * (N / (L * RAD)));
-                if (INV) w.y = -w.y;
-                u[j] = c_mul(u[j], w);
+                for (int j = 1; j < RAD; ++j) {
+                    V x = tw.template get<S>(j * k * (N / (L * RAD)), beta, j);
+                    if (INV) x.y = -x.y;
+                    w[beta][j] = x;
+                }
             }
         }
-        dftR<RAD, INV>(u);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        V y[P];
+#pragma unroll
+        for (int beta = 0; beta < NB; ++beta) {
+            const int b = t + T * beta;
+            const int k = b & (L - 1);
+            V u[RAD];
+#pragma unroll
+            for (int j = 0; j < RAD; ++j) u[j] = v[m][beta + NB * j];
+            if (L > 1) {
+#pragma unroll
+                for (int j = 1; j < RAD; ++j) u[j] = c_mul(u[j], w[beta][j]);
+            }
+            dftR<RAD, INV>(u);
+            if (LAST) {
+#pragma unroll
+                for (int j = 0; j < RAD; ++j) y[beta + NB * j] = u[j];
+            } else {
+                const int base = (b / L) * L * RAD + k;
+#pragma unroll
+                for (int j = 0; j < RAD; ++j) lds[m].st(base + j * L, u[j]);
+            }
+        }
         if (LAST) {
 #pragma unroll
-            for (int j = 0; j < RAD; ++j) y[beta + NB * j] = u[j];
-        } else {
-            const int base = (b / L) * L * RAD + k;
-#pragma unroll
-            for (int j = 0; j < RAD; ++j) {
-                const int pos = LdsPlane<R>::pad(base + j * L);
-                lds.re[pos] = u[j].x;
-                lds.im[pos] = u[j].y;
-            }
+            for (int p = 0; p < P; ++p) v[m][p] = y[p];
         }
     }
-    if (LAST) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) v[p] = y[p];
-    } else {
+    if (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int pos = LdsPlane<R>::pad(t + T * p);
-            v[p].x = lds.re[pos];
-            v[p].y = lds.im[pos];
-        }
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int p = 0; p < P; ++p) v[m][p] = lds[m].ld(t + T * p);
         __syncthreads();
     }
 }
 
-template <int N, int L, bool INV, typename V, typename TW, typename R>
-__device__ inline void fft_rec(V (&v)[FftShape<N>::P], int t, LdsPlane<R> lds, const TW &tw)
+template <int N, int S, bool INV, int M, typename V, typename TW, typename R>
+__device__ inline void fft_rec_m(V (&v)[M][FftShape<N>::P], int t, const LdsPlane<R> (&lds)[M],
+                                 const TW &tw)
 {
-    if constexpr (L < N) {
-        constexpr int P = FftShape<N>::P;
-        constexpr int RAD = (N / L) >= P ? P : (N / L);
-        fft_stage<N, L, INV>(v, t, lds, tw);
-        fft_rec<N, L * RAD, INV>(v, t, lds, tw);
+    if constexpr (S < FftPlan<N>::NST()) {
+        fft_stage_m<N, S, INV, M>(v, t, lds, tw);
+        fft_rec_m<N, S + 1, INV, M>(v, t, lds, tw);
     }
 }
 
-// Full transform (unnormalised): forward X_k = sum x_n e^{-2 pi i nk/N},
+// M independent transforms (unnormalised): forward X_k = sum x_n e^{-2 pi i nk/N},
 // inverse with e^{+...}.
+template <int N, bool INV, int M, typename V, typename TW, typename R>
+__device__ inline void fft_m(V (&v)[M][FftShape<N>::P], int t, const LdsPlane<R> (&lds)[M],
+                             const TW &tw)
+{
+    fft_rec_m<N, 0, INV, M>(v, t, lds, tw);
+}
+
+// Single transform.
 template <int N, bool INV, typename V, typename TW, typename R>
 __device__ inline void fft(V (&v)[FftShape<N>::P], int t, LdsPlane<R> lds, const TW &tw)
 {
-    fft_rec<N, 1, INV>(v, t, lds, tw);
+    constexpr int P = FftShape<N>::P;
+    V vv[1][P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) vv[0][p] = v[p];
+    const LdsPlane<R> l1[1] = {lds};
+    fft_m<N, INV, 1>(vv, t, l1, tw);
+#pragma unroll
+    for (int p = 0; p < P; ++p) v[p] = vv[0][p];
 }

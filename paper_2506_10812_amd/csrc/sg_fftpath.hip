@@ -14,8 +14,8 @@ __global__ void __launch_bounds__(PassShape<N>::WGS)
 k_pass1(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::words(N);
-    __shared__ float lds[2 * W * S::G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     const int wl = sg_xcd_remap(blockIdx.x, S::K);
     // whole padding workgroup: leave before any barrier
@@ -25,76 +25,125 @@ k_pass1(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
     DiscDev D;
     if (valid) D = discs[J.disc];
     else { D = discs[jobs[wl * S::G].disc]; D.tw_phi = tw_default; }
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const int nr = D.nr;
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     // two fluids: (fluid 0, fluid 1) of row idx; one fluid: rows 2 idx, 2 idx + 1
     const int i1 = NF == 2 ? J.idx : 2 * J.idx, i2 = NF == 2 ? J.idx : 2 * J.idx + 1;
     const int f2 = NF == 2 ? 1 : 0;
+    TwRegC<N> tw;
+    tw.load(D.tw_phi, t);
     phi_fwd_pair<N>(D.sigma + (size_t)i1 * N, D.sigma + f2 * plane + (size_t)i2 * N, D.st, i1,
-                    D.st + f2 * fs, i2, nr, D.tw_phi, t, pl, valid);
+                    D.st + f2 * fs, i2, nr, tw, t, pl, valid);
 }
 
+// Pass 2 launch shape: a column is carried by NF * T threads; for two fluids
+// the two halves each own one fluid (forward transform of that source fluid,
+// then spectral multiply and inverse transforms for that target fluid), so
+// no thread holds more than one fluid's accumulators.
+template <int NU, int NF> struct P2Shape {
+    static constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T;
+    static constexpr int CT = NF * T;
+    static constexpr int WGS = CT > 256 ? CT : 256;
+    static constexpr int G = WGS / CT;
+    static constexpr int K = G >= 4 ? 1 : 4 / G;
+};
+
+// Pass 2, one column m of one disc per group of NF * T threads:
+//   half h: zero-padded forward u transform of Sigma~_h; the two halves swap
+//   spectra through LDS; half h then forms g^_{h,c} = sum_a K_c^{a h} Sigma^_a
+//   for c = r, phi (each kernel spectrum read once, loads one group ahead of
+//   the multiply) and inverse-transforms the pair, keeping the first n_r
+//   outputs.  One twiddle per stage and butterfly stays in registers.
 template <int NU, int NF>
-__global__ void __launch_bounds__(PassShape<NU>::WGS)
+__global__ void __launch_bounds__((P2Shape<NU, NF>::WGS))
 k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
-    using S = PassShape<NU>;
+    using S = P2Shape<NU, NF>;
     constexpr int P = S::P, T = S::T;
-    constexpr int W = LdsPlane<float>::words(NU);
     constexpr int NR = NU / 2;
-    __shared__ float lds[2 * W * S::G];
-    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    __shared__ __attribute__((aligned(16))) float2 lds[NU * S::G * 2 * NF];
+    const int g = threadIdx.x / S::CT;
+    const int h = (threadIdx.x % S::CT) / T;
+    const int t = threadIdx.x % T;
     const int wl = sg_xcd_remap(blockIdx.x, S::K);
     if (jobs[wl * S::G].disc < 0) return;
     const Job J = jobs[wl * S::G + g];
     const bool valid = J.disc >= 0;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    const LdsPlane<float> pl[2] = {LdsPlane<float>{lds + NU * (g * 2 * NF + 2 * h)},
+                                   LdsPlane<float>{lds + NU * (g * 2 * NF + 2 * h + 1)}};
     const DiscDev D = discs[valid ? J.disc : jobs[wl * S::G].disc];
-    const TwTable tw{valid ? D.tw_u : tw_default};
-    const int m = J.idx;
-    const size_t fs = valid ? sg_blk_field_elems(D.nphi, NR) : 0;
+    TwRegC<NU> tw;
+    tw.load(valid ? D.tw_u : tw_default, t);
+    const int m = valid ? J.idx : 0;
+    const size_t fs = sg_blk_field_elems(D.nphi, NR);
+    const size_t kk = NR + 1;
+    const float2 *col = D.spec + (size_t)m * (NF * NF) * 2 * kk;
 
-    // forward zero-padded u transform of every source fluid
+    // forward transform of the own fluid
     float2 sh[NF][P];
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            sh[a][p] = make_float2(0.f, 0.f);
-            if (valid && p < P / 2) sh[a][p] = D.st[a * fs + sg_blk_index(m, t + T * p, NR)];
-        }
-        fft<NU, false>(sh[a], t, pl, tw);
+    for (int p = 0; p < P; ++p)
+        sh[0][p] = (valid && p < P / 2) ? gload2(D.st, h * fs + sg_blk_index(m, t + T * p, NR))
+                                        : make_float2(0.f, 0.f);
+    {
+        float2(&own)[1][P] = *reinterpret_cast<float2(*)[1][P]>(&sh[0]);
+        const LdsPlane<float> p1[1] = {pl[0]};
+        fft_m<NU, false, 1>(own, t, p1, tw);
     }
-    // spectral multiply for every (target b, component c), inverse transform
-    const size_t kk = NR + 1;
-    const float2 *col = valid ? D.spec + (size_t)m * (NF * NF) * 2 * kk : nullptr;
+    if constexpr (NF == 2) {
+        // swap spectra with the other half: sh[1] = spectrum of fluid 1 - h
 #pragma unroll
-    for (int b = 0; b < NF; ++b) {
+        for (int p = 0; p < P; ++p) pl[1].st(t + T * p, sh[0][p]);
+        __syncthreads();
+        const LdsPlane<float> other{lds + NU * (g * 2 * NF + 2 * (1 - h) + 1)};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            float2 acc[P];
+        for (int p = 0; p < P; ++p) sh[1][p] = other.ld(t + T * p);
+        __syncthreads();
+    }
+    // acc[c] = sum_a K_c^{a b} Sigma^_a with b = h; source a = h is sh[0]
+    float2 acc[2][P];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[c][p] = make_float2(0.f, 0.f);
+    if (valid) {
+        constexpr int NG = NF * 2;  // (a, c) groups
+        auto kptr = [&](int q) {
+            const int a = q / 2, c = q % 2;
+            const int src = NF == 2 ? (a == 0 ? h : 1 - h) : 0;  // sh[a] holds fluid src
+            return col + ((src * NF + h) * 2 + c) * kk;
+        };
+        float2 Kb[2][P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) Kb[0][p] = kspec_p<NU, P, 0>(kptr(0), t, p);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int a = q / 2, c = q % 2;
+            if (q + 1 < NG) {
+                const float2 *kc = kptr(q + 1);
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    Kb[(q + 1) & 1][p] = ((q + 1) % 2) == 0 ? kspec_p<NU, P, 0>(kc, t, p)
+                                                            : kspec_p<NU, P, 1>(kc, t, p);
+            }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                acc[p] = make_float2(0.f, 0.f);
-                if (valid) {
-                    const int k = t + T * p;
-#pragma unroll
-                    for (int a = 0; a < NF; ++a) {
-                        const float2 K = kspec<NU>(col + ((a * NF + b) * 2 + c) * kk, k, c);
-                        acc[p].x += K.x * sh[a][p].x - K.y * sh[a][p].y;
-                        acc[p].y += K.x * sh[a][p].y + K.y * sh[a][p].x;
-                    }
-                }
+                const float2 K = Kb[q & 1][p];
+                acc[c][p].x += K.x * sh[a][p].x - K.y * sh[a][p].y;
+                acc[c][p].y += K.x * sh[a][p].y + K.y * sh[a][p].x;
             }
-            fft<NU, true>(acc, t, pl, tw);
-            if (valid) {
-                float2 *o = D.gh + (b * 2 + c) * fs;
-#pragma unroll
-                for (int p = 0; p < P / 2; ++p) o[sg_blk_index(m, t + T * p, NR)] = acc[p];
-            }
+            __builtin_amdgcn_sched_barrier(0);
         }
+    }
+    fft_m<NU, true, 2>(acc, t, pl, tw);
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int p = 0; p < P / 2; ++p)
+                gstore2(D.gh, (h * 2 + c) * fs + sg_blk_index(m, t + T * p, NR), acc[c][p]);
     }
 }
 
@@ -103,22 +152,24 @@ __global__ void __launch_bounds__(PassShape<N>::WGS)
 k_pass3(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::words(N);
-    __shared__ float lds[2 * W * S::G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     const int wl = sg_xcd_remap(blockIdx.x, S::K);
     if (jobs[wl * S::G].disc < 0) return;
     const Job J = jobs[wl * S::G + g];
     const bool valid = J.disc >= 0;
-    LdsPlane<float> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<float> pl{lds + W * g};
     const DiscDev D = discs[valid ? J.disc : jobs[wl * S::G].disc];
     const int nr = D.nr;
     const int b = valid ? J.idx / nr : 0, i = valid ? J.idx % nr : 0;
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
-    phi_inv_pair<N>(D.gh + (b * 2 + 0) * fs, i, D.gh + (b * 2 + 1) * fs, i, nr,
-                    valid ? D.tw_phi : tw_default, D.gr + b * plane + (size_t)i * N,
-                    D.gp + b * plane + (size_t)i * N, t, pl, valid);
+    TwRegC<N> tw;
+    tw.load(valid ? D.tw_phi : tw_default, t);
+    phi_inv_pair<N>(D.gh + (b * 2 + 0) * fs, i, D.gh + (b * 2 + 1) * fs, i, nr, tw,
+                    D.gr + b * plane + (size_t)i * N, D.gp + b * plane + (size_t)i * N, t, pl,
+                    valid);
 }
 
 // ------------------------------------------------------------- launching
@@ -137,7 +188,7 @@ template <int N, int NF> static PassKernel pk1()
 }
 template <int N, int NF> static PassKernel pk2()
 {
-    using S = PassShape<N>;
+    using S = P2Shape<N, NF>;
     return {k_pass2<N, NF>, S::WGS, S::G, S::K};
 }
 template <int N, int NF> static PassKernel pk3()

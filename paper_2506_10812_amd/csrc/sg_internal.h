@@ -53,6 +53,31 @@ template <bool INV, typename V> __host__ __device__ inline V c_mul_mi(V a)
     return r;
 }
 
+// --------------------------------------------------- global-memory access
+// Loads and stores through address-space-1 pointers compile to global_load /
+// global_store instead of flat accesses (flat accesses also count against the
+// LDS wait counter, so every LDS barrier would wait for them).
+typedef float sg_v2f __attribute__((ext_vector_type(2)));
+typedef const sg_v2f __attribute__((address_space(1))) sg_gcv2f;
+typedef sg_v2f __attribute__((address_space(1))) sg_gv2f;
+typedef const float __attribute__((address_space(1))) sg_gcf;
+typedef float __attribute__((address_space(1))) sg_gf;
+
+__device__ inline float2 gload2(const float2 *p, size_t i)
+{
+    const sg_v2f v = ((sg_gcv2f *)p)[i];
+    return make_float2(v.x, v.y);
+}
+__device__ inline void gstore2(float2 *p, size_t i, float2 v)
+{
+    sg_v2f w;
+    w.x = v.x;
+    w.y = v.y;
+    ((sg_gv2f *)p)[i] = w;
+}
+__device__ inline float gload1(const float *p, size_t i) { return ((sg_gcf *)p)[i]; }
+__device__ inline void gstore1(float *p, size_t i, float v) { ((sg_gf *)p)[i] = v; }
+
 // ------------------------------------------------------------ table layout
 // Device kernel-table layout (all offsets 256-byte aligned, computable on the
 // host from the arguments alone):

@@ -42,20 +42,16 @@ template <int N> struct PassShape {
     static constexpr int K = G >= 4 ? 1 : 4 / G;  // workgroups per XCD cluster
 };
 
-template <int N> __device__ inline float2 lds_get(const LdsPlane<float> &pl, int i)
-{
-    const int q = LdsPlane<float>::pad(i);
-    return make_float2(pl.re[q], pl.im[q]);
-}
+template <int N> __device__ inline float2 lds_get(const LdsPlane<float> &pl, int i) { return pl.ld(i); }
 
 // ------------------------------------------------------------------ pass 1
 // Forward phi transform of two real rows x1 + i x2 (length N) followed by the
 // Hermitian split
 //   X1[m] = (Z[m] + conj Z[-m]) / 2,  X2[m] = (Z[m] - conj Z[-m]) / (2i),
 // written for m in [0, N/2] to block-layout fields d1 (row i1) and d2 (row i2).
-template <int N>
+template <int N, typename TW>
 __device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1, int i1,
-                                    float2 *d2, int i2, int nr, const float2 *tw, int t,
+                                    float2 *d2, int i2, int nr, const TW &tw, int t,
                                     LdsPlane<float> pl, bool valid)
 {
     using S = PassShape<N>;
@@ -63,14 +59,10 @@ __device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1
     float2 z[P];
 #pragma unroll
     for (int p = 0; p < P; ++p)
-        z[p] = valid ? make_float2(x1[t + T * p], x2[t + T * p]) : make_float2(0.f, 0.f);
-    fft<N, false>(z, t, pl, TwTable{tw});
+        z[p] = valid ? make_float2(gload1(x1, t + T * p), gload1(x2, t + T * p)) : make_float2(0.f, 0.f);
+    fft<N, false>(z, t, pl, tw);
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int q = LdsPlane<float>::pad(t + T * p);
-        pl.re[q] = z[p].x;
-        pl.im[q] = z[p].y;
-    }
+    for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
     __syncthreads();
     if (valid) {
 #pragma unroll
@@ -80,8 +72,8 @@ __device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1
             const float2 Z = lds_get<N>(pl, m);
             const float2 C = lds_get<N>(pl, (N - m) & (N - 1));
             // conj(C) = (C.x, -C.y)
-            d1[sg_blk_index(m, i1, nr)] = make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y));
-            d2[sg_blk_index(m, i2, nr)] = make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x));
+            gstore2(d1, sg_blk_index(m, i1, nr), make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y)));
+            gstore2(d2, sg_blk_index(m, i2, nr), make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x)));
         }
     }
     __syncthreads();
@@ -91,9 +83,9 @@ __device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1
 // Inverse phi transform of A + i B, where A (row iA) and B (row iB) are half
 // spectra of real rows extended by G[N - m] = conj G[m]; the real and
 // imaginary parts of the result are the two real rows o1, o2.
-template <int N>
+template <int N, typename TW>
 __device__ inline void phi_inv_pair(const float2 *A, int iA, const float2 *B, int iB, int nr,
-                                    const float2 *tw, float *o1, float *o2, int t,
+                                    const TW &tw, float *o1, float *o2, int t,
                                     LdsPlane<float> pl, bool valid)
 {
     using S = PassShape<N>;
@@ -104,22 +96,23 @@ __device__ inline void phi_inv_pair(const float2 *A, int iA, const float2 *B, in
         const int m = t + T * p;
         float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
         if (valid) {
-            if (m <= N / 2) {
-                a = A[sg_blk_index(m, iA, nr)];
-                b = B[sg_blk_index(m, iB, nr)];
-            } else {
-                a = c_conj(A[sg_blk_index(N - m, iA, nr)]);
-                b = c_conj(B[sg_blk_index(N - m, iB, nr)]);
+            const bool up = m > N / 2;
+            const int mm = up ? N - m : m;
+            a = gload2(A, sg_blk_index(mm, iA, nr));
+            b = gload2(B, sg_blk_index(mm, iB, nr));
+            if (up) {
+                a.y = -a.y;
+                b.y = -b.y;
             }
         }
         z[p] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
-    fft<N, true>(z, t, pl, TwTable{tw});
+    fft<N, true>(z, t, pl, tw);
     if (valid) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            o1[t + T * p] = z[p].x;
-            o2[t + T * p] = z[p].y;
+            gstore1(o1, t + T * p, z[p].x);
+            gstore1(o2, t + T * p, z[p].y);
         }
     }
 }
@@ -133,4 +126,31 @@ __device__ inline float2 kspec(const float2 *col, int k, int c)
     if (k <= H) return col[k];
     const float2 v = col[NU - k];
     return c == 0 ? make_float2(v.x, -v.y) : make_float2(-v.x, v.y);
+}
+
+// Load of the kernel spectrum at k = t + T p in the thread-interleaved
+// distribution: for p < P/2 the stored half is read directly; for p >= P/2
+// the mirror NU - k is read and conjugated (negated too for K_phi).  The
+// Nyquist point k = NU/2 (t = 0, p = P/2) reads itself, whose value is real
+// (K_r) or imaginary (K_phi), so the same rule holds for it.
+template <int NU, int P, int C>
+__device__ inline float2 kspec_p(const float2 *col, int t, int p)
+{
+    constexpr int T = NU / P;
+    const int k = t + T * p;
+    if (p < P / 2) return gload2(col, k);
+    const float2 v = gload2(col, NU - k);
+    return C == 0 ? make_float2(v.x, -v.y) : make_float2(-v.x, v.y);
+}
+
+// Branch-free form on a global pointer: mirror index and sign by select.
+template <int NU>
+__device__ inline float2 kspec_g(const float2 *col, int k, int c)
+{
+    constexpr int H = NU / 2;
+    const bool up = k > H;
+    const float2 v = gload2(col, up ? NU - k : k);
+    const float sy = up ? -1.f : 1.f;           // conjugate in the upper half
+    const float sx = (up && c == 1) ? -1.f : 1.f;  // K_phi: minus conjugate
+    return make_float2(sx * v.x, sx * sy * v.y);
 }

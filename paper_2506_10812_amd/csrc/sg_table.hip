@@ -157,10 +157,10 @@ __global__ void k_tab_phi(const double2 *A, double2 *B, int rows)
     constexpr int P = Sh::P, T = Sh::T;
     constexpr int WGS = T > 256 ? T : 256;
     constexpr int G = WGS / T;
-    constexpr int W = LdsPlane<double>::words(N);
-    __shared__ double lds[2 * W * G];
+    constexpr int W = N;
+    __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     const int g = threadIdx.x / T, t = threadIdx.x % T;
-    LdsPlane<double> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<double> pl{lds + W * g};
     const int row = blockIdx.x * G + g;
     const bool valid = row < rows;
     double2 v[P];
@@ -168,18 +168,14 @@ __global__ void k_tab_phi(const double2 *A, double2 *B, int rows)
     for (int p = 0; p < P; ++p) v[p] = valid ? A[(size_t)row * N + t + T * p] : make_double2(0, 0);
     fft<N, false>(v, t, pl, TwExact64<N>{});
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int pos = LdsPlane<double>::pad(t + T * p);
-        pl.re[pos] = v[p].x;
-        pl.im[pos] = v[p].y;
-    }
+    for (int p = 0; p < P; ++p) pl.st(t + T * p, v[p]);
     __syncthreads();
     if (!valid) return;
     const int ncol = N / 2 + 1;
     for (int m = t; m <= N / 2; m += T) {
-        const int pm = LdsPlane<double>::pad(m), pn = LdsPlane<double>::pad((N - m) & (N - 1));
-        const double zr = pl.re[pm], zi = pl.im[pm];
-        const double cr = pl.re[pn], ci = -pl.im[pn];  // conj Z[-m]
+        const double2 Zm = pl.ld(m), Zn = pl.ld((N - m) & (N - 1));
+        const double zr = Zm.x, zi = Zm.y;
+        const double cr = Zn.x, ci = -Zn.y;  // conj Z[-m]
         // K_r~ = (Z + conj Z[-m]) / 2,  K_phi~ = (Z - conj Z[-m]) / (2i)
         B[(size_t)m * rows + row] = make_double2(0.5 * (zr + cr), 0.5 * (zi + ci));
         B[((size_t)ncol + m) * rows + row] = make_double2(0.5 * (zi - ci), -0.5 * (zr - cr));
@@ -197,10 +193,10 @@ __global__ void k_tab_u(const double2 *B, float2 *dst, int ncol, size_t col_stri
     constexpr int P = Sh::P, T = Sh::T;
     constexpr int WGS = T > 256 ? T : 256;
     constexpr int G = WGS / T;
-    constexpr int W = LdsPlane<double>::words(NU);
-    __shared__ double lds[2 * W * G];
+    constexpr int W = NU;
+    __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     const int g = threadIdx.x / T, t = threadIdx.x % T;
-    LdsPlane<double> pl{lds + 2 * W * g, lds + 2 * W * g + W};
+    LdsPlane<double> pl{lds + W * g};
     const int col = blockIdx.x * G + g;  // c * ncol + m
     const bool valid = col < 2 * ncol;
     double2 v[P];
