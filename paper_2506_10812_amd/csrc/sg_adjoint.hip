@@ -42,7 +42,7 @@ template <int N>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_lam(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;
@@ -62,7 +62,7 @@ template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_sig(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(PassShape<NU>::WGS) k_adj_col(AdjDev A)
 {
     using S = PassShape<NU>;
     constexpr int P = S::P, T = S::T, G = S::G;
-    constexpr int W = NU;
+    constexpr int W = LdsPlane<float>::elems(NU);
     constexpr int NR = NU / 2;
     __shared__ __attribute__((aligned(16))) float2 lds[W * G];
     __shared__ double red[DH ? S::WGS * NF : 1];
@@ -192,7 +192,7 @@ template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_out(AdjDev A)
 {
     using S = PassShape<N>;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     bool none, valid;

@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(PassShape<N>::WGS)
 k_pass1(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
     using S = PassShape<N>;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     const int wl = sg_xcd_remap(blockIdx.x, S::K);
@@ -50,20 +50,31 @@ template <int NU, int NF> struct P2Shape {
     static constexpr int K = G >= 4 ? 1 : 4 / G;
 };
 
-// Pass 2, one column m of one disc per group of NF * T threads:
-//   half h: zero-padded forward u transform of Sigma~_h; the two halves swap
-//   spectra through LDS; half h then forms g^_{h,c} = sum_a K_c^{a h} Sigma^_a
-//   for c = r, phi (each kernel spectrum read once, loads one group ahead of
-//   the multiply) and inverse-transforms the pair, keeping the first n_r
-//   outputs.  One twiddle per stage and butterfly stays in registers.
+// Pass 2, one column job of one disc per group of NF * T threads (half h
+// owns fluid h; NF = 1 has one half):
+//   1. issue all loads at once: Sigma~_h (rows t + T p, p < P/2) and the kernel
+//      spectra for target b = h at the thread's own frequencies
+//      k_lo = t + T j (j < P/2), for every source a and component c; the
+//      spectra arrive while the forward transform runs;
+//   2. zero-padded forward u transform of Sigma~_h;
+//   3. both halves put their natural-order spectra in LDS; thread t reads
+//      Sigma^_a at k_lo and at the mirrors k_hi = NU - k_lo (k_hi = NU/2 for
+//      t = 0, j = 0) for every a.  K(k_hi) is K(k_lo) conjugated (negated
+//      too for K_phi), so every stored spectrum value is loaded exactly once;
+//   4. multiply-accumulate g^_{h,c}(k) = sum_a K_c^{a h}(k) Sigma^_a(k) at the
+//      2 (P/2) frequencies, write them to LDS in natural order and read them
+//      back in the transform distribution;
+//   5. inverse u transforms of the (r, phi) pair; the first n_r outputs are
+//      stored.  One twiddle per stage and butterfly stays in registers.
 template <int NU, int NF>
-__global__ void __launch_bounds__((P2Shape<NU, NF>::WGS))
+__global__ void __launch_bounds__((P2Shape<NU, NF>::WGS)) __attribute__((amdgpu_waves_per_eu(4)))
 k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
     using S = P2Shape<NU, NF>;
-    constexpr int P = S::P, T = S::T;
+    constexpr int P = S::P, T = S::T, H = P / 2;
     constexpr int NR = NU / 2;
-    __shared__ __attribute__((aligned(16))) float2 lds[NU * S::G * 2 * NF];
+    constexpr int W = LdsPlane<float>::elems(NU);
+    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G * 2 * NF];
     const int g = threadIdx.x / S::CT;
     const int h = (threadIdx.x % S::CT) / T;
     const int t = threadIdx.x % T;
@@ -71,79 +82,111 @@ k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
     if (jobs[wl * S::G].disc < 0) return;
     const Job J = jobs[wl * S::G + g];
     const bool valid = J.disc >= 0;
-    const LdsPlane<float> pl[2] = {LdsPlane<float>{lds + NU * (g * 2 * NF + 2 * h)},
-                                   LdsPlane<float>{lds + NU * (g * 2 * NF + 2 * h + 1)}};
+    float2 *base = lds + W * g * 2 * NF;
+    // planes: F_h (forward / output r) and X_h (spectrum / output phi)
+    const LdsPlane<float> pl[2] = {LdsPlane<float>{base + W * (2 * h)},
+                                   LdsPlane<float>{base + W * (2 * h + 1)}};
     const DiscDev D = discs[valid ? J.disc : jobs[wl * S::G].disc];
     TwRegC<NU> tw;
     tw.load(valid ? D.tw_u : tw_default, t);
     const int m = valid ? J.idx : 0;
     const size_t fs = sg_blk_field_elems(D.nphi, NR);
     const size_t kk = NR + 1;
-    const float2 *col = D.spec + (size_t)m * (NF * NF) * 2 * kk;
+    const size_t cstride = (size_t)(NF * NF) * 2 * kk;
+    const float2 *col = D.spec + (size_t)m * cstride;
 
-    // forward transform of the own fluid
-    float2 sh[NF][P];
+    // 1. loads
+    float2 sh[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-        sh[0][p] = (valid && p < P / 2) ? gload2(D.st, h * fs + sg_blk_index(m, t + T * p, NR))
-                                        : make_float2(0.f, 0.f);
+    for (int p = 0; p < P; ++p) {
+        sh[p] = make_float2(0.f, 0.f);
+        if (valid && p < H) {
+            const size_t row = h * fs;
+            sh[p] = gload2(D.st, row + sg_blk_index(m, t + T * p, NR));
+        }
+    }
+    // unique spectrum values K(k_lo) and K(NU/2) of every source fluid
+    float2 K[NF][2][H], KN[NF][2];
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float2 *kc = col + ((a * NF + h) * 2 + c) * kk;
+#pragma unroll
+            for (int j = 0; j < H; ++j) K[a][c][j] = valid ? gload2(kc, t + T * j) : make_float2(0.f, 0.f);
+            KN[a][c] = valid ? gload2(kc, NR) : make_float2(0.f, 0.f);
+        }
+    // 2. forward transform of the own fluid
     {
-        float2(&own)[1][P] = *reinterpret_cast<float2(*)[1][P]>(&sh[0]);
+        float2(&own)[1][P] = *reinterpret_cast<float2(*)[1][P]>(&sh);
         const LdsPlane<float> p1[1] = {pl[0]};
         fft_m<NU, false, 1>(own, t, p1, tw);
     }
-    if constexpr (NF == 2) {
-        // swap spectra with the other half: sh[1] = spectrum of fluid 1 - h
+    // 3. spectra of all fluids at k_lo and k_hi
 #pragma unroll
-        for (int p = 0; p < P; ++p) pl[1].st(t + T * p, sh[0][p]);
-        __syncthreads();
-        const LdsPlane<float> other{lds + NU * (g * 2 * NF + 2 * (1 - h) + 1)};
+    for (int p = 0; p < P; ++p) pl[1].st(t + T * p, sh[p]);
+    __syncthreads();
+    float2 slo[NF][H], shi[NF][H];
 #pragma unroll
-        for (int p = 0; p < P; ++p) sh[1][p] = other.ld(t + T * p);
-        __syncthreads();
+    for (int a = 0; a < NF; ++a) {
+        const LdsPlane<float> X{base + W * (2 * a + 1)};
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int klo = t + T * j;
+            const int khi = (j == 0 && t == 0) ? NR : NU - klo;
+            slo[a][j] = X.ld(klo);
+            shi[a][j] = X.ld(khi);
+        }
     }
-    // acc[c] = sum_a K_c^{a b} Sigma^_a with b = h; source a = h is sh[0]
+    __syncthreads();
+    // 4. multiply-accumulate at k_lo and k_hi, back to the transform distribution
+    float2 olo[2][H], ohi[2][H];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            float2 a1 = make_float2(0.f, 0.f), a2 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int a = 0; a < NF; ++a) {
+                const float2 k1 = K[a][c][j];
+                // mirror: conj (K_r) or minus conj (K_phi); Nyquist reads K(NU/2)
+                float2 k2 = (j == 0 && t == 0) ? KN[a][c] : k1;
+                k2 = c == 0 ? make_float2(k2.x, -k2.y) : make_float2(-k2.x, k2.y);
+                const float2 lo = slo[a][j], hi = shi[a][j];
+                a1.x += k1.x * lo.x - k1.y * lo.y;
+                a1.y += k1.x * lo.y + k1.y * lo.x;
+                a2.x += k2.x * hi.x - k2.y * hi.y;
+                a2.y += k2.x * hi.y + k2.y * hi.x;
+            }
+            olo[c][j] = a1;
+            ohi[c][j] = a2;
+        }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int klo = t + T * j;
+            const int khi = (j == 0 && t == 0) ? NR : NU - klo;
+            pl[c].st(klo, olo[c][j]);
+            pl[c].st(khi, ohi[c][j]);
+        }
+    __syncthreads();
     float2 acc[2][P];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int p = 0; p < P; ++p) acc[c][p] = make_float2(0.f, 0.f);
-    if (valid) {
-        constexpr int NG = NF * 2;  // (a, c) groups
-        auto kptr = [&](int q) {
-            const int a = q / 2, c = q % 2;
-            const int src = NF == 2 ? (a == 0 ? h : 1 - h) : 0;  // sh[a] holds fluid src
-            return col + ((src * NF + h) * 2 + c) * kk;
-        };
-        float2 Kb[2][P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) Kb[0][p] = kspec_p<NU, P, 0>(kptr(0), t, p);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-            const int a = q / 2, c = q % 2;
-            if (q + 1 < NG) {
-                const float2 *kc = kptr(q + 1);
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-                    Kb[(q + 1) & 1][p] = ((q + 1) % 2) == 0 ? kspec_p<NU, P, 0>(kc, t, p)
-                                                            : kspec_p<NU, P, 1>(kc, t, p);
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const float2 K = Kb[q & 1][p];
-                acc[c][p].x += K.x * sh[a][p].x - K.y * sh[a][p].y;
-                acc[c][p].y += K.x * sh[a][p].y + K.y * sh[a][p].x;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
+        for (int p = 0; p < P; ++p) acc[c][p] = pl[c].ld(t + T * p);
+    __syncthreads();
+    // 5. inverse pair, first n_r outputs
     fft_m<NU, true, 2>(acc, t, pl, tw);
     if (valid) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int p = 0; p < P / 2; ++p)
-                gstore2(D.gh, (h * 2 + c) * fs + sg_blk_index(m, t + T * p, NR), acc[c][p]);
+            for (int p = 0; p < H; ++p) {
+                const size_t o = (h * 2 + c) * fs;
+                gstore2(D.gh, o + sg_blk_index(m, t + T * p, NR), acc[c][p]);
+            }
     }
 }
 
@@ -152,7 +195,7 @@ __global__ void __launch_bounds__(PassShape<N>::WGS)
 k_pass3(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
 {
     using S = PassShape<N>;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
     const int wl = sg_xcd_remap(blockIdx.x, S::K);

@@ -157,7 +157,7 @@ __global__ void k_tab_phi(const double2 *A, double2 *B, int rows)
     constexpr int P = Sh::P, T = Sh::T;
     constexpr int WGS = T > 256 ? T : 256;
     constexpr int G = WGS / T;
-    constexpr int W = N;
+    constexpr int W = LdsPlane<double>::elems(N);
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     LdsPlane<double> pl{lds + W * g};
@@ -193,7 +193,7 @@ __global__ void k_tab_u(const double2 *B, float2 *dst, int ncol, size_t col_stri
     constexpr int P = Sh::P, T = Sh::T;
     constexpr int WGS = T > 256 ? T : 256;
     constexpr int G = WGS / T;
-    constexpr int W = NU;
+    constexpr int W = LdsPlane<double>::elems(NU);
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     LdsPlane<double> pl{lds + W * g};
