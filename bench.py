@@ -10,6 +10,9 @@ precomputes the kernel once per simulation).  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
   python bench.py --copy-calibration   (plain 1 GiB device copy, for scaling
                                         rocprofv3 FETCH_SIZE / WRITE_SIZE)
+  python bench.py --summarize-rocprof DIR
+        (CPU only) turns the rocprofv3 CSV output of PROFILE_COMMANDS, run
+        with DIR as their output root, into the text summaries in profiles/
 """
 import argparse
 import hashlib
@@ -24,6 +27,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "SG field cells/s at 1024×2048 bi-fluid; %HBM roofline; rel err vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass2_bifluid_1024x2048.json")
+DOMINANT_KERNEL = "k_pass2<2048, 2>"   # pass 2 of the two-fluid 1024 x 2048 disc
+PASS_KERNELS = {"pass1": "k_pass1<2048, 2>", "pass2": "k_pass2<2048, 2>",
+                "pass3": "k_pass3<2048, 2>"}
+
+# The rocprofv3 runs behind profiles/ (run from /tmp with TMPDIR=/tmp; {out}
+# is the output root, {repo} the repository).  Counter runs are separate
+# (one TCC counter group each) and never combined with tracing.
+PROFILE_COMMANDS = {
+    "kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/kt -o run -- "
+          "python3 {repo}/bench.py --steps 50 --warmup 10 --no-cpu --no-extra",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/fetch -o run -- "
+             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/write -o run -- "
+             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra",
+    "cfetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/cfetch -o run -- "
+              "python3 {repo}/bench.py --copy-calibration",
+    "cwrite": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cwrite -o run -- "
+              "python3 {repo}/bench.py --copy-calibration",
+}
+COPY_BYTES = 4 << 28   # --copy-calibration copies 2^28 floats
 
 
 def kernel_source_hash():
@@ -48,6 +71,83 @@ def pass_bytes(nr, nphi, nf):
             "path": sig + spec + g}
 
 
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"bench.py: no *{suffix} under {d}")
+    with open(files[0], newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _counter_mean(d, kernel, counter):
+    """Mean per-dispatch value (KiB) of one counter over the dispatches of a kernel."""
+    vals = [float(r["Counter_Value"]) for r in _csv_rows(d, "_counter_collection.csv")
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"bench.py: no {counter} rows for {kernel} under {d}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def summarize_rocprof(out):
+    """Writes profiles/kernels_bifluid_1024x2048.md and the pass-2 traffic files."""
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    cmd = {k: v.format(out="<out>", repo="<repo>") for k, v in PROFILE_COMMANDS.items()}
+    stats = _csv_rows(os.path.join(out, "kt"), "_kernel_stats.csv")
+    lines = ["# Kernel time, two-fluid 1024x2048 FFT path (bench.py workload)", "",
+             "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output "
+             "root):", "", "    " + cmd["kt"], "",
+             "Each step is one graph launch of the three passes; the run also launches the "
+             "passes outside the graph for bench.py's per-pass event timing.", "",
+             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share (%) |",
+             "|---|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    cf, _ = _counter_mean(os.path.join(out, "cfetch"), "copyBuffer", "FETCH_SIZE")
+    cw, _ = _counter_mean(os.path.join(out, "cwrite"), "copyBuffer", "WRITE_SIZE")
+    f_scale = COPY_BYTES / (cf * 1024.0)
+    w_scale = COPY_BYTES / (cw * 1024.0)
+    fk, nf_ = _counter_mean(os.path.join(out, "fetch"), DOMINANT_KERNEL, "FETCH_SIZE")
+    wk, nw_ = _counter_mean(os.path.join(out, "write"), DOMINANT_KERNEL, "WRITE_SIZE")
+    read_b = fk * 1024.0 * f_scale
+    write_b = wk * 1024.0 * w_scale
+    alg = pass_bytes(1024, 2048, 2)["pass2"]
+    tr = {"kernel": "pass2", "kernel_name": DOMINANT_KERNEL,
+          "kernel_source_hash": kernel_source_hash(),
+          "fetch_size_kib": round(fk, 1), "write_size_kib": round(wk, 1),
+          "dispatches": [nf_, nw_],
+          "copy_fetch_kib_per_gib": round(cf, 1), "copy_write_kib_per_gib": round(cw, 1),
+          "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+          "bytes_read": round(read_b), "bytes_written": round(write_b),
+          "bytes_per_launch": round(read_b + write_b), "algorithmic_bytes": alg,
+          "commands": [cmd["fetch"], cmd["write"], cmd["cfetch"], cmd["cwrite"]]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(tr, fh, indent=1)
+        fh.write("\n")
+    md = ["# HBM traffic of pass 2, two-fluid 1024x2048 (bench.py workload)", "",
+          "Commands (from /tmp, TMPDIR=/tmp):", ""] + \
+         ["    " + cmd[k] for k in ("fetch", "write", "cfetch", "cwrite")] + \
+         ["", f"Copy calibration (1 GiB device copy): FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE "
+              f"{cw:.1f} KiB per launch, so FETCH_SIZE is scaled by {f_scale:.4f} and "
+              f"WRITE_SIZE by {w_scale:.4f}.", "",
+          f"`{DOMINANT_KERNEL}` per launch (mean of {nf_} / {nw_} dispatches): FETCH_SIZE "
+          f"{fk:.1f} KiB -> {read_b / 1e6:.2f} MB read, WRITE_SIZE {wk:.1f} KiB -> "
+          f"{write_b / 1e6:.2f} MB written; total {(read_b + write_b) / 1e6:.2f} MB against "
+          f"{alg / 1e6:.2f} MB algorithmic ({(read_b + write_b) / alg:.3f}x).", "",
+          f"Kernel sources hash: {tr['kernel_source_hash']}."]
+    with open(os.path.join(prof, "traffic_pass2_bifluid_1024x2048.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(tr))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +156,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--summarize-rocprof", metavar="DIR")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(args.summarize_rocprof)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md, not run", file=sys.stderr)
@@ -129,14 +233,14 @@ def main():
                 "kernel": dom_name, "kernel_ms": round(ms_pass[dom], 5),
                 "algorithmic_bytes": pb[dom_name]}
 
-    # accuracy vs the FP64 oracle on 4096 seeded cells (also the CPU baseline)
+    # accuracy vs the FP64 oracle on 16384 seeded cells (also the CPU baseline)
     cpu = None
     acc = None
     if not args.no_cpu:
         import oracle as O
-        idx = W.sample_cells(nr, nphi, 4096)
+        idx = W.sample_cells(nr, nphi, 16384)
         sig32 = F.sigma[0].double().cpu().numpy()
-        print("bench: CPU oracle on 4096 sampled cells", file=sys.stderr, flush=True)
+        print(f"bench: CPU oracle on {len(idx)} sampled cells", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, targets=idx)
         cpu_s = time.perf_counter() - t0
