@@ -9,33 +9,79 @@
 #include "sg_passes.h"
 
 // ---------------------------------------------------------------- kernels
+// Passes 1 and 3 are persistent: workgroup b takes workgroup jobs
+// w = sg_xcd_remap(b, K), w + gridDim.x, ... < nj, and issues the loads of its
+// next job before it transforms the current one, so that the memory traffic
+// of one job overlaps the arithmetic of the previous one.  gridDim.x is a
+// multiple of 8 K (a whole number of XCD clusters).  Twiddles depend only on
+// the transform length, so one table serves every disc of a launch.
+
+// Pass 1: job = one row pair (two fluids: row idx of each; one fluid: rows
+// 2 idx and 2 idx + 1).  Job state is kept as wave-uniform scalars (disc,
+// first job, valid count) and addresses are rebuilt from them where needed.
+template <int N, int NF>
+__device__ inline void p1_rows(int idx, int &i1, int &i2)
+{
+    i1 = NF == 2 ? idx : 2 * idx;
+    i2 = NF == 2 ? idx : 2 * idx + 1;
+}
+
+template <int N, int NF>
+__device__ inline void p1_issue(const DiscDev *D, int idx, int t, float2 (&z)[FftShape<N>::P])
+{
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+    int i1, i2;
+    p1_rows<N, NF>(idx, i1, i2);
+    const uint32_t o1 = (uint32_t)i1 * N + t;
+    const uint32_t o2 = (NF == 2 ? (uint32_t)D->nr * N : 0u) + (uint32_t)i2 * N + t;
+    const float *x = D->sigma;
+#pragma unroll
+    for (int p = 0; p < P; ++p) z[p] = make_float2(gld1(x, o1 + T * p), gld1(x, o2 + T * p));
+}
+
 template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS)
-k_pass1(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
+k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::elems(N);
+    constexpr int P = S::P, W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
-    const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
-    const int wl = sg_xcd_remap(blockIdx.x, S::K);
-    // whole padding workgroup: leave before any barrier
-    if (jobs[wl * S::G].disc < 0) return;
-    const Job J = jobs[wl * S::G + g];
-    const bool valid = J.disc >= 0;
-    DiscDev D;
-    if (valid) D = discs[J.disc];
-    else { D = discs[jobs[wl * S::G].disc]; D.tw_phi = tw_default; }
-    LdsPlane<float> pl{lds + W * g};
-    const int nr = D.nr;
-    const size_t fs = sg_blk_field_elems(N, nr);
-    const size_t plane = (size_t)nr * N;
-    // two fluids: (fluid 0, fluid 1) of row idx; one fluid: rows 2 idx, 2 idx + 1
-    const int i1 = NF == 2 ? J.idx : 2 * J.idx, i2 = NF == 2 ? J.idx : 2 * J.idx + 1;
-    const int f2 = NF == 2 ? 1 : 0;
+    const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
+    int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    if (w >= nj) return;
+    const LdsPlane<float> pl{lds + W * g};
     TwRegC<N> tw;
-    tw.load(D.tw_phi, t);
-    phi_fwd_pair<N>(D.sigma + (size_t)i1 * N, D.sigma + f2 * plane + (size_t)i2 * N, D.st, i1,
-                    D.st + f2 * fs, i2, nr, tw, t, pl, valid);
+    tw.load(twp, t0);
+    int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
+    float2 nx[P];
+    p1_issue<N, NF>(discs + cd, g < cn ? cb + g : cb, t0, nx);
+    for (;;) {
+        const int t = sg_opaque(t0);
+        float2 z[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) z[p] = nx[p];
+        const int wn = w + gridDim.x;
+        const bool more = wn < nj;
+        int nd = cd, nb = cb, nn = cn;
+        if (more) {
+            nd = sg_uniform(wj[wn].disc);
+            nb = sg_uniform(wj[wn].base);
+            nn = sg_uniform(wj[wn].n);
+            p1_issue<N, NF>(discs + nd, g < nn ? nb + g : nb, t, nx);
+        }
+        {
+            const DiscDev *D = discs + cd;
+            int i1, i2;
+            p1_rows<N, NF>(g < cn ? cb + g : cb, i1, i2);
+            const size_t fs = sg_blk_field_elems(N, D->nr);
+            p1_finish<N>(z, D->st, i1, D->st + (NF == 2 ? fs : 0), i2, D->nr, tw, t, pl, g < cn);
+        }
+        if (!more) break;
+        w = wn;
+        cd = nd;
+        cb = nb;
+        cn = nn;
+    }
 }
 
 // Pass 2 launch shape: a column is carried by NF * T threads; for two fluids
@@ -50,25 +96,48 @@ template <int NU, int NF> struct P2Shape {
     static constexpr int K = G >= 4 ? 1 : 4 / G;
 };
 
-// Pass 2, one column job of one disc per group of NF * T threads (half h
-// owns fluid h; NF = 1 has one half):
-//   1. issue all loads at once: Sigma~_h (rows t + T p, p < P/2) and the kernel
-//      spectra for target b = h at the thread's own frequencies
-//      k_lo = t + T j (j < P/2), for every source a and component c; the
-//      spectra arrive while the forward transform runs;
-//   2. zero-padded forward u transform of Sigma~_h;
-//   3. both halves put their natural-order spectra in LDS; thread t reads
+// Loads of pass-2 column job m for half h: Sigma~_h at rows t + T p (p < P/2;
+// the upper half of the padded column is zero) and the unique kernel-spectrum
+// values K(k_lo), k_lo = t + T j (j < P/2), and K(NU/2) of every source a.
+template <int NU, int NF>
+__device__ inline void p2_issue(const DiscDev *D, int m, int h, int t, float2 (&sh)[FftShape<NU>::P / 2],
+                                float2 (&K)[NF][2][FftShape<NU>::P / 2], float2 (&KN)[NF][2])
+{
+    constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T, H = P / 2, NR = NU / 2;
+    constexpr uint32_t kk = NR + 1;
+    const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
+    const float2 *st = D->st;
+    const float2 *spec = D->spec;
+#pragma unroll
+    for (int p = 0; p < H; ++p) sh[p] = gld2(st, h * fs + (uint32_t)sg_blk_index(m, t + T * p, NR));
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const uint32_t o = (((uint32_t)m * (NF * NF) + a * NF + h) * 2 + cc) * kk;
+#pragma unroll
+            for (int j = 0; j < H; ++j) K[a][cc][j] = gld2(spec, o + t + T * j);
+            KN[a][cc] = gld2(spec, o + NR);
+        }
+}
+
+// Pass 2, one column job m in [0, n_phi/2] per group of NF * T threads (half
+// h owns fluid h; NF = 1 has one half); one workgroup job per workgroup (the
+// spectra of a column are too many registers to load one job ahead):
+//   1. issue all loads: Sigma~_h and the kernel spectra; the spectra arrive
+//      while the zero-padded forward u transform of Sigma~_h runs;
+//   2. both halves put their natural-order spectra in LDS; thread t reads
 //      Sigma^_a at k_lo and at the mirrors k_hi = NU - k_lo (k_hi = NU/2 for
 //      t = 0, j = 0) for every a.  K(k_hi) is K(k_lo) conjugated (negated
 //      too for K_phi), so every stored spectrum value is loaded exactly once;
-//   4. multiply-accumulate g^_{h,c}(k) = sum_a K_c^{a h}(k) Sigma^_a(k) at the
-//      2 (P/2) frequencies, write them to LDS in natural order and read them
-//      back in the transform distribution;
-//   5. inverse u transforms of the (r, phi) pair; the first n_r outputs are
-//      stored.  One twiddle per stage and butterfly stays in registers.
+//   3. multiply-accumulate g^_{h,c}(k) = sum_a K_c^{a h}(k) Sigma^_a(k) at the
+//      2 (P/2) frequencies;
+//   4. the products go to LDS in natural order and come back in the
+//      transform distribution; inverse u transforms of the (r, phi) pair; the
+//      first n_r outputs are stored.
 template <int NU, int NF>
 __global__ void __launch_bounds__((P2Shape<NU, NF>::WGS)) __attribute__((amdgpu_waves_per_eu(4)))
-k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
+k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu)
 {
     using S = P2Shape<NU, NF>;
     constexpr int P = S::P, T = S::T, H = P / 2;
@@ -78,53 +147,31 @@ k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
     const int g = threadIdx.x / S::CT;
     const int h = (threadIdx.x % S::CT) / T;
     const int t = threadIdx.x % T;
-    const int wl = sg_xcd_remap(blockIdx.x, S::K);
-    if (jobs[wl * S::G].disc < 0) return;
-    const Job J = jobs[wl * S::G + g];
-    const bool valid = J.disc >= 0;
+    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    if (w >= nj) return;
     float2 *base = lds + W * g * 2 * NF;
     // planes: F_h (forward / output r) and X_h (spectrum / output phi)
     const LdsPlane<float> pl[2] = {LdsPlane<float>{base + W * (2 * h)},
                                    LdsPlane<float>{base + W * (2 * h + 1)}};
-    const DiscDev D = discs[valid ? J.disc : jobs[wl * S::G].disc];
-    TwRegC<NU> tw;
-    tw.load(valid ? D.tw_u : tw_default, t);
-    const int m = valid ? J.idx : 0;
-    const size_t fs = sg_blk_field_elems(D.nphi, NR);
-    const size_t kk = NR + 1;
-    const size_t cstride = (size_t)(NF * NF) * 2 * kk;
-    const float2 *col = D.spec + (size_t)m * cstride;
-
+    const int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
+    const DiscDev *D = discs + cd;
+    const int m = g < cn ? cb + g : cb;
     // 1. loads
-    float2 sh[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        sh[p] = make_float2(0.f, 0.f);
-        if (valid && p < H) {
-            const size_t row = h * fs;
-            sh[p] = gload2(D.st, row + sg_blk_index(m, t + T * p, NR));
-        }
-    }
-    // unique spectrum values K(k_lo) and K(NU/2) of every source fluid
-    float2 K[NF][2][H], KN[NF][2];
-#pragma unroll
-    for (int a = 0; a < NF; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const float2 *kc = col + ((a * NF + h) * 2 + c) * kk;
-#pragma unroll
-            for (int j = 0; j < H; ++j) K[a][c][j] = valid ? gload2(kc, t + T * j) : make_float2(0.f, 0.f);
-            KN[a][c] = valid ? gload2(kc, NR) : make_float2(0.f, 0.f);
-        }
-    // 2. forward transform of the own fluid
+    float2 sh[H], K[NF][2][H], KN[NF][2];
+    p2_issue<NU, NF>(D, m, h, t, sh, K, KN);
+    TwRegC<NU> tw;
+    tw.load(twu, t);
+    // forward transform of the own fluid
     {
-        float2(&own)[1][P] = *reinterpret_cast<float2(*)[1][P]>(&sh);
-        const LdsPlane<float> p1[1] = {pl[0]};
-        fft_m<NU, false, 1>(own, t, p1, tw);
-    }
-    // 3. spectra of all fluids at k_lo and k_hi
+        float2 v[1][P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) pl[1].st(t + T * p, sh[p]);
+        for (int p = 0; p < P; ++p) v[0][p] = p < H ? sh[p] : make_float2(0.f, 0.f);
+        const LdsPlane<float> p1[1] = {pl[0]};
+        fft_m<NU, false, 1>(v, t, p1, tw);
+        // 2. spectra of all fluids at k_lo and k_hi
+#pragma unroll
+        for (int p = 0; p < P; ++p) pl[1].st(t + T * p, v[0][p]);
+    }
     __syncthreads();
     float2 slo[NF][H], shi[NF][H];
 #pragma unroll
@@ -139,105 +186,138 @@ k_pass2(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
         }
     }
     __syncthreads();
-    // 4. multiply-accumulate at k_lo and k_hi, back to the transform distribution
+    // 3. multiply-accumulate at k_lo and k_hi
     float2 olo[2][H], ohi[2][H];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
         for (int j = 0; j < H; ++j) {
             float2 a1 = make_float2(0.f, 0.f), a2 = make_float2(0.f, 0.f);
 #pragma unroll
             for (int a = 0; a < NF; ++a) {
-                const float2 k1 = K[a][c][j];
+                const float2 k1 = K[a][cc][j];
                 // mirror: conj (K_r) or minus conj (K_phi); Nyquist reads K(NU/2)
-                float2 k2 = (j == 0 && t == 0) ? KN[a][c] : k1;
-                k2 = c == 0 ? make_float2(k2.x, -k2.y) : make_float2(-k2.x, k2.y);
+                float2 k2 = (j == 0 && t == 0) ? KN[a][cc] : k1;
+                k2 = cc == 0 ? make_float2(k2.x, -k2.y) : make_float2(-k2.x, k2.y);
                 const float2 lo = slo[a][j], hi = shi[a][j];
                 a1.x += k1.x * lo.x - k1.y * lo.y;
                 a1.y += k1.x * lo.y + k1.y * lo.x;
                 a2.x += k2.x * hi.x - k2.y * hi.y;
                 a2.y += k2.x * hi.y + k2.y * hi.x;
             }
-            olo[c][j] = a1;
-            ohi[c][j] = a2;
+            olo[cc][j] = a1;
+            ohi[cc][j] = a2;
         }
+    // 4. back to the transform distribution, inverse pair, first n_r outputs
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
         for (int j = 0; j < H; ++j) {
             const int klo = t + T * j;
             const int khi = (j == 0 && t == 0) ? NR : NU - klo;
-            pl[c].st(klo, olo[c][j]);
-            pl[c].st(khi, ohi[c][j]);
+            pl[cc].st(klo, olo[cc][j]);
+            pl[cc].st(khi, ohi[cc][j]);
         }
     __syncthreads();
     float2 acc[2][P];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-        for (int p = 0; p < P; ++p) acc[c][p] = pl[c].ld(t + T * p);
+        for (int p = 0; p < P; ++p) acc[cc][p] = pl[cc].ld(t + T * p);
     __syncthreads();
-    // 5. inverse pair, first n_r outputs
     fft_m<NU, true, 2>(acc, t, pl, tw);
-    if (valid) {
+    if (g < cn) {
+        const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-            for (int p = 0; p < H; ++p) {
-                const size_t o = (h * 2 + c) * fs;
-                gstore2(D.gh, o + sg_blk_index(m, t + T * p, NR), acc[c][p]);
-            }
+            for (int p = 0; p < H; ++p)
+                gst2(D->gh, (h * 2 + cc) * fs + (uint32_t)sg_blk_index(m, t + T * p, NR), acc[cc][p]);
     }
+}
+
+// Pass 3: job = (target fluid b, row i): inverse phi transform of
+// g^_r + i g^_phi, whose real and imaginary parts are g_r and g_phi.
+template <int N>
+__device__ inline void p3_issue(const DiscDev *D, int idx, int t, float2 (&a)[FftShape<N>::P],
+                                float2 (&b)[FftShape<N>::P])
+{
+    const int nr = D->nr;
+    const int bf = idx / nr, i = idx % nr;
+    const size_t fs = sg_blk_field_elems(N, nr);
+    const float2 *A = D->gh + (size_t)(bf * 2) * fs;
+    p3_load<N>(A, i, A + fs, i, nr, a, b, t);
 }
 
 template <int N, int NF>
 __global__ void __launch_bounds__(PassShape<N>::WGS)
-k_pass3(const DiscDev *discs, const Job *jobs, const float2 *tw_default)
+k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp)
 {
     using S = PassShape<N>;
-    constexpr int W = LdsPlane<float>::elems(N);
+    constexpr int P = S::P, W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
-    const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
-    const int wl = sg_xcd_remap(blockIdx.x, S::K);
-    if (jobs[wl * S::G].disc < 0) return;
-    const Job J = jobs[wl * S::G + g];
-    const bool valid = J.disc >= 0;
-    LdsPlane<float> pl{lds + W * g};
-    const DiscDev D = discs[valid ? J.disc : jobs[wl * S::G].disc];
-    const int nr = D.nr;
-    const int b = valid ? J.idx / nr : 0, i = valid ? J.idx % nr : 0;
-    const size_t fs = sg_blk_field_elems(N, nr);
-    const size_t plane = (size_t)nr * N;
+    const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
+    int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    if (w >= nj) return;
+    const LdsPlane<float> pl{lds + W * g};
     TwRegC<N> tw;
-    tw.load(valid ? D.tw_phi : tw_default, t);
-    phi_inv_pair<N>(D.gh + (b * 2 + 0) * fs, i, D.gh + (b * 2 + 1) * fs, i, nr, tw,
-                    D.gr + b * plane + (size_t)i * N, D.gp + b * plane + (size_t)i * N, t, pl,
-                    valid);
+    tw.load(twp, t0);
+    int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
+    float2 a[P], b[P];
+    p3_issue<N>(discs + cd, g < cn ? cb + g : cb, t0, a, b);
+    for (;;) {
+        const int t = sg_opaque(t0);
+        float2 z[P];
+        p3_combine<N>(a, b, z, t);
+        const int wn = w + gridDim.x;
+        const bool more = wn < nj;
+        int nd = cd, nb = cb, nn = cn;
+        if (more) {
+            nd = sg_uniform(wj[wn].disc);
+            nb = sg_uniform(wj[wn].base);
+            nn = sg_uniform(wj[wn].n);
+            p3_issue<N>(discs + nd, g < nn ? nb + g : nb, t, a, b);
+        }
+        {
+            const DiscDev *D = discs + cd;
+            const int idx = g < cn ? cb + g : cb;
+            const int nr = D->nr;
+            const size_t plane = (size_t)nr * N;
+            const size_t o = (size_t)(idx / nr) * plane + (size_t)(idx % nr) * N;
+            p3_finish<N>(z, tw, D->gr + o, D->gp + o, t, pl, g < cn);
+        }
+        if (!more) break;
+        w = wn;
+        cd = nd;
+        cb = nb;
+        cn = nn;
+    }
 }
 
 // ------------------------------------------------------------- launching
 
-using KernelFn = void (*)(const DiscDev *, const Job *, const float2 *);
+using KernelFn = void (*)(const DiscDev *, const WJob *, int, const float2 *);
 
 struct PassKernel {
     KernelFn fn;
     int wgs, G, K;
+    bool persistent;  // loops over workgroup jobs (else one per workgroup)
 };
 
 template <int N, int NF> static PassKernel pk1()
 {
     using S = PassShape<N>;
-    return {k_pass1<N, NF>, S::WGS, S::G, S::K};
+    return {k_pass1<N, NF>, S::WGS, S::G, S::K, true};
 }
 template <int N, int NF> static PassKernel pk2()
 {
     using S = P2Shape<N, NF>;
-    return {k_pass2<N, NF>, S::WGS, S::G, S::K};
+    return {k_pass2<N, NF>, S::WGS, S::G, S::K, false};
 }
 template <int N, int NF> static PassKernel pk3()
 {
     using S = PassShape<N>;
-    return {k_pass3<N, NF>, S::WGS, S::G, S::K};
+    return {k_pass3<N, NF>, S::WGS, S::G, S::K, true};
 }
 
 #define SG_SIZE_CASES(F, NF)                                                                      \
@@ -254,7 +334,6 @@ template <int N, int NF> static PassKernel pk3()
 
 static bool pass_kernel(int pass, int n, int nf, PassKernel &out)
 {
-    PassKernel k{nullptr, 0, 0, 0};
     auto pick = [&]() -> PassKernel {
         if (pass == 1) {
             if (nf == 1) switch (n) { SG_SIZE_CASES(pk1, 1) }
@@ -266,25 +345,25 @@ static bool pass_kernel(int pass, int n, int nf, PassKernel &out)
             if (nf == 1) switch (n) { SG_SIZE_CASES(pk3, 1) }
             else switch (n) { SG_SIZE_CASES(pk3, 2) }
         }
-        return PassKernel{nullptr, 0, 0, 0};
+        return PassKernel{nullptr, 0, 0, 0, false};
     };
-    k = pick();
-    out = k;
-    return k.fn != nullptr;
+    out = pick();
+    return out.fn != nullptr;
 }
 
 // ------------------------------------------------------------- batch plan
 struct Launch {
     PassKernel k;
-    size_t job_off;   // offset (in Job units) into the job table
-    int nwg;
-    size_t tw_disc;   // disc whose twiddles serve padding groups
+    size_t wj_off;    // offset (in WJob units) into the workgroup-job table
+    int nj;           // workgroup jobs of this launch
+    int grid;         // workgroups (a multiple of 8 K)
+    const float2 *tw; // twiddles of this launch's transform length
     int pass;
 };
 
 struct Plan {
     std::vector<DiscDev> discs;
-    std::vector<Job> jobs;
+    std::vector<WJob> wjobs;
     std::vector<Launch> launches;
 };
 
@@ -293,6 +372,36 @@ size_t sg_fft_disc_ws_bytes(const sg_disc &d)
     const size_t fs = sg_blk_field_elems(d.grid.n_phi, d.grid.n_r);
     return sg_align256(sizeof(float2) * fs * d.fluids.n_fluids) +
            sg_align256(sizeof(float2) * fs * 2 * d.fluids.n_fluids);
+}
+
+// Jobs of one disc in a pass: pass 1 row pairs, pass 2 columns m <= n_phi/2,
+// pass 3 (target fluid, row) pairs.
+static int pass_jobs(const sg_disc &d, int pass)
+{
+    const int nf = d.fluids.n_fluids;
+    if (pass == 1) return nf == 2 ? d.grid.n_r : d.grid.n_r / 2;
+    if (pass == 2) return d.grid.n_phi / 2 + 1;
+    return nf * d.grid.n_r;
+}
+
+// Grid of a launch: whole XCD clusters of 8 K workgroups.  A persistent
+// kernel gets its resident workgroups per CU times the CU count (at least one
+// cluster, at most the work available); the others one workgroup per job.
+static int launch_grid(const PassKernel &k, int nj)
+{
+    const int cluster = 8 * k.K;
+    const int need = (nj + cluster - 1) / cluster * cluster;
+    if (!k.persistent) return need;
+    int dev = 0, ncu = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k.fn, k.wgs, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    int grid = per_cu * ncu / cluster * cluster;
+    if (grid < cluster) grid = cluster;
+    return grid < need ? grid : need;
 }
 
 static void build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
@@ -330,29 +439,23 @@ static void build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
         for (auto &kv : classes) {
             PassKernel k;
             pass_kernel(pass, kv.first.first, kv.first.second, k);
-            const int nf = kv.first.second;
-            std::vector<Job> list;
+            std::vector<WJob> list;
             for (int di : kv.second) {
-                const sg_disc &d = discs[di];
-                int cnt;
-                if (pass == 1) cnt = nf == 2 ? d.grid.n_r : d.grid.n_r / 2;
-                else if (pass == 2) cnt = d.grid.n_phi / 2 + 1;
-                else cnt = nf * d.grid.n_r;
-                for (int j = 0; j < cnt; ++j) list.push_back({di, j});
-                // keep each disc's jobs aligned to whole XCD clusters of
-                // G*K jobs so that cache-line sharing stays inside one disc
-                const size_t unit = (size_t)k.G * k.K;
-                while (list.size() % unit) list.push_back({-1, 0});
+                const int cnt = pass_jobs(discs[di], pass);
+                for (int b = 0; b < cnt; b += k.G) list.push_back({di, b, std::min(k.G, cnt - b), 0});
+                // keep each disc's workgroup jobs aligned to whole clusters of
+                // K so that cache-line sharing stays inside one disc
+                while (list.size() % k.K) list.push_back({di, 0, 0, 0});
             }
-            const size_t per_round = (size_t)k.G * 8 * k.K;
-            while (list.size() % per_round) list.push_back({-1, 0});
             Launch La;
             La.k = k;
-            La.job_off = P.jobs.size();
-            La.nwg = (int)(list.size() / k.G);
-            La.tw_disc = kv.second[0];
+            La.wj_off = P.wjobs.size();
+            La.nj = (int)list.size();
+            La.grid = launch_grid(k, La.nj);
+            const DiscDev &D0 = P.discs[kv.second[0]];
+            La.tw = pass == 2 ? D0.tw_u : D0.tw_phi;
             La.pass = pass;
-            P.jobs.insert(P.jobs.end(), list.begin(), list.end());
+            P.wjobs.insert(P.wjobs.end(), list.begin(), list.end());
             P.launches.push_back(La);
         }
     }
@@ -388,14 +491,20 @@ static std::vector<uint64_t> signature(const sg_disc *discs, int n, void *ws)
     return k;
 }
 
-static sg_status enqueue(const Cached &C, hipStream_t s)
+static sg_status launch(const Cached &C, const Launch &L, hipStream_t s)
 {
     const DiscDev *dd = (const DiscDev *)C.dmem;
-    const Job *jj = (const Job *)((const char *)C.dmem + sg_align256(sizeof(DiscDev) * C.plan.discs.size()));
+    const WJob *wj = (const WJob *)((const char *)C.dmem + sg_align256(sizeof(DiscDev) * C.plan.discs.size()));
+    hipLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), 0, s, dd, wj + L.wj_off, L.nj, L.tw);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+static sg_status enqueue(const Cached &C, hipStream_t s)
+{
     for (const Launch &L : C.plan.launches) {
-        const float2 *twd = L.pass == 2 ? C.plan.discs[L.tw_disc].tw_u : C.plan.discs[L.tw_disc].tw_phi;
-        hipLaunchKernelGGL(L.k.fn, dim3(L.nwg), dim3(L.k.wgs), 0, s, dd, jj + L.job_off, twd);
-        SG_HIP(hipGetLastError());
+        const sg_status st = launch(C, L, s);
+        if (st != SG_OK) return st;
     }
     return SG_OK;
 }
@@ -416,14 +525,14 @@ sg_status sg_fft_run(const sg_disc *discs, int n, void *ws, hipStream_t s)
         C = new Cached;
         build_plan(discs, n, (char *)ws, C->plan);
         const size_t bd = sg_align256(sizeof(DiscDev) * n);
-        const size_t bytes = bd + sizeof(Job) * C->plan.jobs.size();
+        const size_t bytes = bd + sizeof(WJob) * C->plan.wjobs.size();
         if (hipMalloc(&C->dmem, bytes) != hipSuccess) {
             delete C;
             return SG_ERR_HIP;
         }
         if (hipMemcpy(C->dmem, C->plan.discs.data(), sizeof(DiscDev) * n, hipMemcpyHostToDevice) !=
                 hipSuccess ||
-            hipMemcpy((char *)C->dmem + bd, C->plan.jobs.data(), sizeof(Job) * C->plan.jobs.size(),
+            hipMemcpy((char *)C->dmem + bd, C->plan.wjobs.data(), sizeof(WJob) * C->plan.wjobs.size(),
                       hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(C->dmem);
             delete C;
@@ -477,8 +586,6 @@ sg_status sg_fft_profile(const sg_disc *discs, int n, void *ws, hipStream_t s, i
         std::lock_guard<std::mutex> lk(g_mu);
         C = g_cache[signature(discs, n, ws)];
     }
-    const DiscDev *dd = (const DiscDev *)C->dmem;
-    const Job *jj = (const Job *)((const char *)C->dmem + sg_align256(sizeof(DiscDev) * C->plan.discs.size()));
     std::vector<hipEvent_t> ev(4 * reps);
     for (auto &e : ev) SG_HIP(hipEventCreate(&e));
     for (int r = 0; r < reps; ++r) {
@@ -486,9 +593,8 @@ sg_status sg_fft_profile(const sg_disc *discs, int n, void *ws, hipStream_t s, i
         for (int pass = 1; pass <= 3; ++pass) {
             for (const Launch &L : C->plan.launches) {
                 if (L.pass != pass) continue;
-                const float2 *twd = L.pass == 2 ? C->plan.discs[L.tw_disc].tw_u : C->plan.discs[L.tw_disc].tw_phi;
-                hipLaunchKernelGGL(L.k.fn, dim3(L.nwg), dim3(L.k.wgs), 0, s, dd, jj + L.job_off, twd);
-                SG_HIP(hipGetLastError());
+                const sg_status st = launch(*C, L, s);
+                if (st != SG_OK) return st;
             }
             SG_HIP(hipEventRecord(ev[4 * r + pass], s));
         }

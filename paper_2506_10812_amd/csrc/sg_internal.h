@@ -78,6 +78,39 @@ __device__ inline void gstore2(float2 *p, size_t i, float2 v)
 __device__ inline float gload1(const float *p, size_t i) { return ((sg_gcf *)p)[i]; }
 __device__ inline void gstore1(float *p, size_t i, float v) { ((sg_gf *)p)[i] = v; }
 
+// The same with a 32-bit element offset from a (usually wave-uniform) base:
+// the byte offset is formed in 32 bits, so the access can use the scalar
+// base + vector offset addressing form.  Callers keep every buffer addressed
+// this way below 4 GiB (the FFT path's largest buffer is a few hundred MB).
+__device__ inline float2 gld2(const float2 *p, uint32_t i)
+{
+    const sg_v2f v = *(sg_gcv2f *)((const char *)p + (i << 3));
+    return make_float2(v.x, v.y);
+}
+__device__ inline void gst2(float2 *p, uint32_t i, float2 v)
+{
+    sg_v2f w;
+    w.x = v.x;
+    w.y = v.y;
+    *(sg_gv2f *)((char *)p + (i << 3)) = w;
+}
+__device__ inline float gld1(const float *p, uint32_t i) { return *(sg_gcf *)((const char *)p + (i << 2)); }
+__device__ inline void gst1(float *p, uint32_t i, float v) { *(sg_gf *)((char *)p + (i << 2)) = v; }
+
+// Forces a value that is equal in all lanes into a scalar register.
+__device__ inline int sg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Returns v unchanged but opaque to the optimiser (an empty asm statement
+// that claims to modify its register).  Persistent loops pass their lane
+// index through it at the top of every iteration, so that the many
+// lane-dependent addresses of the transforms are recomputed where they are
+// used instead of being hoisted out of the loop and held in registers.
+__device__ inline int sg_opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // ------------------------------------------------------------ table layout
 // Device kernel-table layout (all offsets 256-byte aligned, computable on the
 // host from the arguments alone):

@@ -33,6 +33,13 @@ struct Job {
     int disc, idx;
 };
 
+// Workgroup job of the persistent passes: groups g < n of the workgroup take
+// jobs base + g of disc `disc`; groups g >= n (and all groups when n = 0)
+// repeat job `base` without storing, so every load address stays valid.
+struct WJob {
+    int disc, base, n, pad_;
+};
+
 // launch shape shared by host and device
 template <int N> struct PassShape {
     static constexpr int P = FftShape<N>::P;
@@ -42,24 +49,30 @@ template <int N> struct PassShape {
     static constexpr int K = G >= 4 ? 1 : 4 / G;  // workgroups per XCD cluster
 };
 
-template <int N> __device__ inline float2 lds_get(const LdsPlane<float> &pl, int i) { return pl.ld(i); }
-
 // ------------------------------------------------------------------ pass 1
 // Forward phi transform of two real rows x1 + i x2 (length N) followed by the
 // Hermitian split
 //   X1[m] = (Z[m] + conj Z[-m]) / 2,  X2[m] = (Z[m] - conj Z[-m]) / (2i),
 // written for m in [0, N/2] to block-layout fields d1 (row i1) and d2 (row i2).
-template <int N, typename TW>
-__device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1, int i1,
-                                    float2 *d2, int i2, int nr, const TW &tw, int t,
-                                    LdsPlane<float> pl, bool valid)
+//
+// The loads are split from the transform so that a persistent kernel can
+// issue the next job's loads before transforming the current one.  Loads are
+// unconditional: padding groups pass valid addresses, and only the stores
+// depend on `valid`.
+template <int N>
+__device__ inline void p1_load(const float *x1, const float *x2, float2 (&z)[FftShape<N>::P], int t)
 {
-    using S = PassShape<N>;
-    constexpr int P = S::P, T = S::T;
-    float2 z[P];
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-        z[p] = valid ? make_float2(gload1(x1, t + T * p), gload1(x2, t + T * p)) : make_float2(0.f, 0.f);
+    for (int p = 0; p < P; ++p) z[p] = make_float2(gload1(x1, t + T * p), gload1(x2, t + T * p));
+}
+
+template <int N, typename TW>
+__device__ inline void p1_finish(float2 (&z)[FftShape<N>::P], float2 *d1, int i1, float2 *d2,
+                                 int i2, int nr, const TW &tw, int t, LdsPlane<float> pl,
+                                 bool valid)
+{
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
     fft<N, false>(z, t, pl, tw);
 #pragma unroll
     for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
@@ -69,52 +82,89 @@ __device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1
         for (int p = 0; p <= P / 2; ++p) {
             const int m = t + T * p;
             if (p == P / 2 && t != 0) break;
-            const float2 Z = lds_get<N>(pl, m);
-            const float2 C = lds_get<N>(pl, (N - m) & (N - 1));
+            const float2 Z = pl.ld(m);
+            const float2 C = pl.ld((N - m) & (N - 1));
             // conj(C) = (C.x, -C.y)
-            gstore2(d1, sg_blk_index(m, i1, nr), make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y)));
-            gstore2(d2, sg_blk_index(m, i2, nr), make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x)));
+            const float2 v1 = make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y));
+            const float2 v2 = make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x));
+            gst2(d1, (uint32_t)sg_blk_index(m, i1, nr), v1);
+            gst2(d2, (uint32_t)sg_blk_index(m, i2, nr), v2);
         }
     }
     __syncthreads();
 }
 
+template <int N, typename TW>
+__device__ inline void phi_fwd_pair(const float *x1, const float *x2, float2 *d1, int i1,
+                                    float2 *d2, int i2, int nr, const TW &tw, int t,
+                                    LdsPlane<float> pl, bool valid)
+{
+    float2 z[FftShape<N>::P];
+    p1_load<N>(x1, x2, z, t);
+    p1_finish<N>(z, d1, i1, d2, i2, nr, tw, t, pl, valid);
+}
+
 // ------------------------------------------------------------------ pass 3
 // Inverse phi transform of A + i B, where A (row iA) and B (row iB) are half
 // spectra of real rows extended by G[N - m] = conj G[m]; the real and
-// imaginary parts of the result are the two real rows o1, o2.
+// imaginary parts of the result are the two real rows o1, o2.  Loads, their
+// combination and the transform are separate steps for the same reason as
+// in pass 1.
+template <int N>
+__device__ inline void p3_load(const float2 *A, int iA, const float2 *B, int iB, int nr,
+                               float2 (&a)[FftShape<N>::P], float2 (&b)[FftShape<N>::P], int t)
+{
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int m = t + T * p;
+        const int mm = m > N / 2 ? N - m : m;
+        a[p] = gld2(A, (uint32_t)sg_blk_index(mm, iA, nr));
+        b[p] = gld2(B, (uint32_t)sg_blk_index(mm, iB, nr));
+    }
+}
+
+template <int N>
+__device__ inline void p3_combine(const float2 (&a)[FftShape<N>::P], const float2 (&b)[FftShape<N>::P],
+                                  float2 (&z)[FftShape<N>::P], int t)
+{
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int m = t + T * p;
+        float2 x = a[p], y = b[p];
+        const float s = m > N / 2 ? -1.f : 1.f;  // upper half: conjugate of the mirror
+        x.y *= s;
+        y.y *= s;
+        z[p] = make_float2(x.x - y.y, x.y + y.x);  // x + i y
+    }
+}
+
+template <int N, typename TW>
+__device__ inline void p3_finish(float2 (&z)[FftShape<N>::P], const TW &tw, float *o1, float *o2,
+                                 int t, LdsPlane<float> pl, bool valid)
+{
+    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+    fft<N, true>(z, t, pl, tw);
+    if (valid) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            gst1(o1, t + T * p, z[p].x);
+            gst1(o2, t + T * p, z[p].y);
+        }
+    }
+}
+
 template <int N, typename TW>
 __device__ inline void phi_inv_pair(const float2 *A, int iA, const float2 *B, int iB, int nr,
                                     const TW &tw, float *o1, float *o2, int t,
                                     LdsPlane<float> pl, bool valid)
 {
-    using S = PassShape<N>;
-    constexpr int P = S::P, T = S::T;
-    float2 z[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int m = t + T * p;
-        float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
-        if (valid) {
-            const bool up = m > N / 2;
-            const int mm = up ? N - m : m;
-            a = gload2(A, sg_blk_index(mm, iA, nr));
-            b = gload2(B, sg_blk_index(mm, iB, nr));
-            if (up) {
-                a.y = -a.y;
-                b.y = -b.y;
-            }
-        }
-        z[p] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
-    }
-    fft<N, true>(z, t, pl, tw);
-    if (valid) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            gstore1(o1, t + T * p, z[p].x);
-            gstore1(o2, t + T * p, z[p].y);
-        }
-    }
+    constexpr int P = FftShape<N>::P;
+    float2 a[P], b[P], z[P];
+    p3_load<N>(A, iA, B, iB, nr, a, b, t);
+    p3_combine<N>(a, b, z, t);
+    p3_finish<N>(z, tw, o1, o2, t, pl, valid);
 }
 
 // Kernel-spectrum lookup at u-frequency k (0 <= k < NU) for component c:
