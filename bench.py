@@ -156,6 +156,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
     args = ap.parse_args()
     if args.summarize_rocprof:
@@ -196,6 +197,10 @@ def main():
     table_s = time.perf_counter() - t0
     F.set_sigma(0, w["sigma"])
     stream = torch.cuda.current_stream()
+    # untuned per-pass times, then the autotuner (part of the library's normal
+    # use: once per batch shape); the timed steps run the tuned plan
+    ms_untuned = sg.field_fft_profile(F.discs, F.ws, 20, stream=stream)
+    tuned = F.tune(stream=stream) if not args.no_tune else []
 
     for _ in range(args.warmup):
         F.run()
@@ -255,6 +260,9 @@ def main():
 
     extra = {"table_build_s": round(table_s, 3), "wall_s_timed": round(wall, 3),
              "ms_per_pass": [round(v, 5) for v in ms_pass],
+             "ms_per_pass_untuned": [round(v, 5) for v in ms_untuned],
+             "tuned": [{k: r[k] for k in ("pass", "length", "small_radix_first", "wg_per_cu", "cluster",
+                                          "candidates", "rejected")} for r in tuned],
              "path_algorithmic_bytes": pb["path"],
              "path_hbm_frac": round(pb["path"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "rel_rms_vs_fp64_oracle": acc}
@@ -282,18 +290,25 @@ def extra_measurements(sg, T, W, dev):
     Fb = T.FFTField(discs, device=dev)
     for i, d in enumerate(discs):
         Fb.set_sigma(i, d["sigma"])
-    for _ in range(5):
-        Fb.run()
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    n = 50
-    e0.record()
-    for _ in range(n):
-        Fb.run()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / n
+
+    def timed(fn, n):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_untuned = timed(Fb.run, 50)
+    t0 = time.perf_counter()
+    Fb.tune()
+    tune_s = time.perf_counter() - t0
+    ms = timed(Fb.run, 50)
     cells = sum(d["n_r"] * d["n_phi"] for d in discs)
     byts = sum(pass_bytes(d["n_r"], d["n_phi"], 1)["path"] for d in discs)
     # the same discs one call each (plain single-disc path)
@@ -309,7 +324,8 @@ def extra_measurements(sg, T, W, dev):
     e1.record()
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / 10
-    res["batch64"] = {"cells": cells, "ms": round(ms, 4), "cells_per_s": round(cells / ms * 1e3, 1),
+    res["batch64"] = {"cells": cells, "ms": round(ms, 4), "ms_untuned": round(ms_untuned, 4),
+                      "tune_s": round(tune_s, 2), "cells_per_s": round(cells / ms * 1e3, 1),
                       "path_hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "looped_single_disc_ms": round(ms_loop, 4),
                       "speedup_vs_looped": round(ms_loop / ms, 3)}

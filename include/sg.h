@@ -149,6 +149,43 @@ sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, si
                                void *stream, int reps, float *ms_per_pass);
 
 /* ---------------------------------------------------------------------
+ * sg_field_fft_tune: autotuner of the batched FFT path.  For every launch
+ * class of the batch (one pass over the discs that share a transform length
+ * and a fluid count) it runs the default launch as the reference, then every
+ * candidate: radix order of the transforms (small radix last or first, where
+ * the length is not a power of 8), resident workgroups per CU of the
+ * persistent row passes (1, 2, 3, 4, 6, 8 or all that fit) and XCD cluster
+ * size (1, 2, 4 or 8 workgroups sharing cache lines).  A candidate is timed
+ * only if its output matches the reference (relative RMS <= 1e-5 over the
+ * class's output buffers); the fastest wins.  Choices are cached per class
+ * shape for the life of the process (and in the text file named by the
+ * environment variable SG_TUNE_CACHE, if set, read on the first tuning call
+ * and rewritten after each); later sg_field_fft calls of any batch with the
+ * same class shapes use them.  Synchronous; allocates temporary device
+ * memory; releases the cached graphs.  On return the outputs hold a complete
+ * sg_field_fft result.  results (may be NULL) receives up to `capacity`
+ * entries, one per class in pass order; *n_results (may be NULL) the number
+ * of classes.  Arguments as for sg_field_fft.
+ * --------------------------------------------------------------------- */
+typedef struct sg_tune_result {
+    int32_t pass;              /* 1, 2, 3 */
+    int32_t length;            /* transform length of the class */
+    int32_t n_fluids;
+    int32_t n_jobs;            /* workgroup jobs of the chosen launch */
+    int32_t small_radix_first; /* chosen radix order */
+    int32_t wg_per_cu;         /* chosen resident workgroups per CU, 0 = all that fit */
+    int32_t cluster;           /* chosen XCD cluster size */
+    int32_t candidates;        /* candidates tried besides the reference */
+    int32_t rejected;          /* candidates that failed the output check */
+    float rel_best;            /* relative RMS of the choice against the reference */
+    float ms_default;          /* mean launch time of the reference */
+    float ms_best;             /* mean launch time of the choice */
+} sg_tune_result;
+
+sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
+                            void *stream, sg_tune_result *results, int capacity, int *n_results);
+
+/* ---------------------------------------------------------------------
  * sg_field_direct: the O(N^2) pairwise sum of the definition (Sect. 2.2,
  * 2D force through the kernel) for any grid size and general per-cell
  * scale heights.  d_H: device array [F][n_r][n_phi] of H (same dtype as

@@ -42,6 +42,12 @@ class Disc(ctypes.Structure):
                 ("g_phi", ctypes.c_void_p), ("table", ctypes.c_void_p)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "pass_", "length", "n_fluids", "n_jobs", "small_radix_first", "wg_per_cu", "cluster",
+        "candidates", "rejected")] + [(n, ctypes.c_float) for n in ("rel_best", "ms_default", "ms_best")]
+
+
 def grid(n_r, n_phi, r_min, r_max) -> Grid:
     return Grid(int(n_r), int(n_phi), float(r_min), float(r_max))
 
@@ -68,6 +74,8 @@ def _load():
         "sg_field_fft_workspace_bytes": (sz, [DP, i32]),
         "sg_field_fft": (i32, [DP, i32, vp, sz, vp]),
         "sg_field_fft_profile": (i32, [DP, i32, vp, sz, vp, i32, ctypes.POINTER(ctypes.c_float)]),
+        "sg_field_fft_tune": (i32, [DP, i32, vp, sz, vp, ctypes.POINTER(TuneResult), i32,
+                                    ctypes.POINTER(ctypes.c_int)]),
         "sg_field_direct_workspace_bytes": (sz, [GP, i32, i32, i32]),
         "sg_field_direct": (i32, [GP, i32, dp, vp, vp, vp, vp, i32, u32, vp, sz, vp]),
         "sg_field_adjoint_workspace_bytes": (sz, [DP]),
@@ -88,7 +96,7 @@ def _load():
 _lib = _load()
 EXPORTED = (
     "sg_kernel_table_bytes", "sg_kernel_table_workspace_bytes", "sg_kernel_table",
-    "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile",
+    "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile", "sg_field_fft_tune",
     "sg_field_direct_workspace_bytes",
     "sg_field_direct", "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_eval_F",
     "sg_self_cell", "sg_release", "sg_status_string", "sg_version")
@@ -181,6 +189,22 @@ def field_fft_profile(discs, ws, reps, ws_bytes=None, stream=None):
     _check(_lib.sg_field_fft_profile(arr, len(discs), _ptr(ws), ws_bytes, _stream(stream), reps, ms),
            "sg_field_fft_profile")
     return [float(v) for v in ms]
+
+
+def field_fft_tune(discs, ws, ws_bytes=None, stream=None, capacity=256):
+    """Autotunes the batch's launch classes; returns one dict per class."""
+    arr = _disc_array(discs)
+    ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    res = (TuneResult * capacity)()
+    n = ctypes.c_int(0)
+    _check(_lib.sg_field_fft_tune(arr, len(discs), _ptr(ws), ws_bytes, _stream(stream), res, capacity,
+                                  ctypes.byref(n)), "sg_field_fft_tune")
+    out = []
+    for r in res[:min(n.value, capacity)]:
+        d = {k: getattr(r, k) for k, _ in TuneResult._fields_}
+        d["pass"] = d.pop("pass_")
+        out.append(d)
+    return out
 
 
 def field_direct(g: Grid, n_fluids, h, sigma, H, g_r, g_phi, dtype, flags, ws, ws_bytes=None,

@@ -114,6 +114,21 @@ sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, si
     return sg_fft_profile(discs, n_discs, d_ws, (hipStream_t)stream, reps, ms_per_pass);
 }
 
+sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
+                            void *stream, sg_tune_result *results, int capacity, int *n_results)
+{
+    if (!discs || n_discs < 1 || n_discs > 4096 || capacity < 0 || (capacity > 0 && !results))
+        return SG_ERR_ARG;
+    size_t need = 0;
+    for (int i = 0; i < n_discs; ++i) {
+        sg_status s = check_disc(discs[i]);
+        if (s != SG_OK) return s;
+        need += sg_fft_disc_ws_bytes(discs[i]);
+    }
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    return sg_fft_tune(discs, n_discs, d_ws, (hipStream_t)stream, results, capacity, n_results);
+}
+
 size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
                                        int per_cell_H)
 {

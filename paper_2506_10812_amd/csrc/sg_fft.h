@@ -132,14 +132,22 @@ template <int N> struct FftShape {
     static constexpr int T = N / P;
 };
 
-// Compile-time stage plan: stage s has sub-length L(s) (1, P, P^2, ...),
-// radix RAD(s) and NB(s) butterflies per thread; TWOFF(s) is the offset of
-// its twiddles in a per-thread register table (stage 0 needs none).
-template <int N> struct FftPlan {
+// Compile-time stage plan: stage s has sub-length L(s), radix RAD(s) and
+// NB(s) butterflies per thread; TWOFF(s) is the offset of its twiddles in a
+// per-thread register table (stage 0 needs none).  When N is not a power of
+// P, one stage has the smaller radix N / P^k: the last one by default, the
+// first one (which needs no twiddles) when SF is set.
+template <int N, bool SF = false> struct FftPlan {
     static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
-    static constexpr int L(int s) { int l = 1; for (int i = 0; i < s; ++i) l *= RADL(l); return l; }
-    static constexpr int RADL(int l) { return (N / l) >= P ? P : (N / l); }
-    static constexpr int RAD(int s) { return RADL(L(s)); }
+    static constexpr int SMALL() { int r = N; while (r >= P) r /= P; return r; }  // 1 if none
+    static constexpr int L(int s) { int l = 1; for (int i = 0; i < s; ++i) l *= RAD(i); return l; }
+    static constexpr int RAD(int s)
+    {
+        if (SF && SMALL() > 1) return s == 0 ? SMALL() : P;
+        int l = 1;
+        for (int i = 0; i < s; ++i) l *= (N / l) >= P ? P : (N / l);
+        return (N / l) >= P ? P : (N / l);
+    }
     static constexpr int NB(int s) { return P / RAD(s); }
     static constexpr int NST() { int s = 0; while (L(s) < N) ++s; return s; }
     static constexpr int TWOFF(int s) { int o = 0; for (int i = 1; i < s; ++i) o += NB(i) * (RAD(i) - 1); return o; }
@@ -175,30 +183,37 @@ template <int N> struct TwReg {
 // Compact variant: one twiddle w^k per (stage, butterfly) in registers; the
 // powers w^{jk} are formed by complex products (depth <= 3, a few ulps),
 // once per stage and shared by all transforms of the stage.
-template <int N> struct FftPlanC {
-    using PL = FftPlan<N>;
+template <int N, bool SF = false> struct FftPlanC {
+    using PL = FftPlan<N, SF>;
     static constexpr int OFF(int s) { int o = 0; for (int i = 1; i < s; ++i) o += PL::NB(i); return o; }
     static constexpr int NTW() { return OFF(PL::NST()) > 0 ? OFF(PL::NST()) : 1; }
 };
 
-template <int N> struct TwRegC {
-    float2 w[FftPlanC<N>::NTW()];
+template <int N, bool SF = false> struct TwRegC {
+    using Plan = FftPlan<N, SF>;
+    float2 w[FftPlanC<N, SF>::NTW()];
     static constexpr bool POWERS = true;
     __device__ inline void load(const float2 *tab, int t) { load_stage<1>(tab, t); }
     template <int S> __device__ inline void load_stage(const float2 *g, int t)
     {
-        using PL = FftPlan<N>;
+        using PL = Plan;
         if constexpr (S < PL::NST()) {
             constexpr int Ls = PL::L(S), R = PL::RAD(S), NB = PL::NB(S);
 #pragma unroll
             for (int beta = 0; beta < NB; ++beta) {
                 const int k = (t + PL::T * beta) & (Ls - 1);
-                w[FftPlanC<N>::OFF(S) + beta] = gload2(g, k * (N / (Ls * R)));
+                w[FftPlanC<N, SF>::OFF(S) + beta] = gload2(g, k * (N / (Ls * R)));
             }
             load_stage<S + 1>(g, t);
         }
     }
-    template <int S> __device__ inline float2 base(int beta) const { return w[FftPlanC<N>::OFF(S) + beta]; }
+    template <int S> __device__ inline float2 base(int beta) const { return w[FftPlanC<N, SF>::OFF(S) + beta]; }
+};
+
+// Stage plan of a twiddle provider: its own Plan type, else the default.
+template <typename TW, int N, typename = void> struct plan_of { using type = FftPlan<N>; };
+template <typename TW, int N> struct plan_of<TW, N, decltype((void)sizeof(typename TW::Plan), void())> {
+    using type = typename TW::Plan;
 };
 
 template <typename TW, typename = void> struct tw_has_powers { static constexpr bool value = false; };
@@ -212,7 +227,7 @@ template <int N, int S, bool INV, int M, typename V, typename TW, typename R>
 __device__ inline void fft_stage_m(V (&v)[M][FftShape<N>::P], int t, const LdsPlane<R> (&lds)[M],
                                    const TW &tw)
 {
-    using PL = FftPlan<N>;
+    using PL = typename plan_of<TW, N>::type;
     constexpr int P = PL::P;
     constexpr int T = PL::T;
     constexpr int L = PL::L(S);
@@ -227,9 +242,9 @@ __device__ inline void fft_stage_m(V (&v)[M][FftShape<N>::P], int t, const LdsPl
                 V x = tw.template base<S>(beta);
                 if (INV) x.y = -x.y;
                 w[beta][1] = x;
-                if (RAD > 2) w[beta][2] = c_mul(x, x);
-                if (RAD > 3) w[beta][3] = c_mul(w[beta][2], x);
-                if (RAD > 4) {
+                if constexpr (RAD > 2) w[beta][2] = c_mul(x, x);
+                if constexpr (RAD > 3) w[beta][3] = c_mul(w[beta][2], x);
+                if constexpr (RAD > 4) {
                     w[beta][4] = c_mul(w[beta][2], w[beta][2]);
                     w[beta][5] = c_mul(w[beta][4], x);
                     w[beta][6] = c_mul(w[beta][4], w[beta][2]);
@@ -290,7 +305,7 @@ template <int N, int S, bool INV, int M, typename V, typename TW, typename R>
 __device__ inline void fft_rec_m(V (&v)[M][FftShape<N>::P], int t, const LdsPlane<R> (&lds)[M],
                                  const TW &tw)
 {
-    if constexpr (S < FftPlan<N>::NST()) {
+    if constexpr (S < plan_of<TW, N>::type::NST()) {
         fft_stage_m<N, S, INV, M>(v, t, lds, tw);
         fft_rec_m<N, S + 1, INV, M>(v, t, lds, tw);
     }

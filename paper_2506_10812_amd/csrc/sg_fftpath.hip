@@ -1,6 +1,9 @@
 // sg_fftpath.hip -- sg_field_fft: batched three-pass log-polar FFT
 // convolution, one HIP graph per batch signature.
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <tuple>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -13,8 +16,10 @@
 // w = sg_xcd_remap(b, K), w + gridDim.x, ... < nj, and issues the loads of its
 // next job before it transforms the current one, so that the memory traffic
 // of one job overlaps the arithmetic of the previous one.  gridDim.x is a
-// multiple of 8 K (a whole number of XCD clusters).  Twiddles depend only on
-// the transform length, so one table serves every disc of a launch.
+// multiple of 8 K (a whole number of XCD clusters of K workgroups that share
+// cache lines).  Twiddles depend only on the transform length, so one table
+// serves every disc of a launch.  SF selects the radix order of the
+// transforms (small radix first); SF and K are tuning parameters.
 
 // Pass 1: job = one row pair (two fluids: row idx of each; one fluid: rows
 // 2 idx and 2 idx + 1).  Job state is kept as wave-uniform scalars (disc,
@@ -39,18 +44,18 @@ __device__ inline void p1_issue(const DiscDev *D, int idx, int t, float2 (&z)[Ff
     for (int p = 0; p < P; ++p) z[p] = make_float2(gld1(x, o1 + T * p), gld1(x, o2 + T * p));
 }
 
-template <int N, int NF>
+template <int N, int NF, bool SF>
 __global__ void __launch_bounds__(PassShape<N>::WGS)
-k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp)
+k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
     using S = PassShape<N>;
     constexpr int P = S::P, W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
-    int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
     const LdsPlane<float> pl{lds + W * g};
-    TwRegC<N> tw;
+    TwRegC<N, SF> tw;
     tw.load(twp, t0);
     int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
     float2 nx[P];
@@ -135,9 +140,9 @@ __device__ inline void p2_issue(const DiscDev *D, int m, int h, int t, float2 (&
 //   4. the products go to LDS in natural order and come back in the
 //      transform distribution; inverse u transforms of the (r, phi) pair; the
 //      first n_r outputs are stored.
-template <int NU, int NF>
+template <int NU, int NF, bool SF>
 __global__ void __launch_bounds__((P2Shape<NU, NF>::WGS)) __attribute__((amdgpu_waves_per_eu(4)))
-k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu)
+k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
 {
     using S = P2Shape<NU, NF>;
     constexpr int P = S::P, T = S::T, H = P / 2;
@@ -147,7 +152,7 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu)
     const int g = threadIdx.x / S::CT;
     const int h = (threadIdx.x % S::CT) / T;
     const int t = threadIdx.x % T;
-    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
     float2 *base = lds + W * g * 2 * NF;
     // planes: F_h (forward / output r) and X_h (spectrum / output phi)
@@ -159,7 +164,7 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu)
     // 1. loads
     float2 sh[H], K[NF][2][H], KN[NF][2];
     p2_issue<NU, NF>(D, m, h, t, sh, K, KN);
-    TwRegC<NU> tw;
+    TwRegC<NU, SF> tw;
     tw.load(twu, t);
     // forward transform of the own fluid
     {
@@ -249,18 +254,18 @@ __device__ inline void p3_issue(const DiscDev *D, int idx, int t, float2 (&a)[Ff
     p3_load<N>(A, i, A + fs, i, nr, a, b, t);
 }
 
-template <int N, int NF>
+template <int N, int NF, bool SF>
 __global__ void __launch_bounds__(PassShape<N>::WGS)
-k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp)
+k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
     using S = PassShape<N>;
     constexpr int P = S::P, W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
-    int w = sg_uniform(sg_xcd_remap(blockIdx.x, S::K));
+    int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
     const LdsPlane<float> pl{lds + W * g};
-    TwRegC<N> tw;
+    TwRegC<N, SF> tw;
     tw.load(twp, t0);
     int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
     float2 a[P], b[P];
@@ -296,64 +301,80 @@ k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp)
 
 // ------------------------------------------------------------- launching
 
-using KernelFn = void (*)(const DiscDev *, const WJob *, int, const float2 *);
+using KernelFn = void (*)(const DiscDev *, const WJob *, int, const float2 *, int);
 
 struct PassKernel {
     KernelFn fn;
-    int wgs, G, K;
+    int wgs, G, K;    // K: default XCD cluster size
     bool persistent;  // loops over workgroup jobs (else one per workgroup)
 };
 
-template <int N, int NF> static PassKernel pk1()
+template <int N, int NF, bool SF> static PassKernel pk1()
 {
     using S = PassShape<N>;
-    return {k_pass1<N, NF>, S::WGS, S::G, S::K, true};
+    return {k_pass1<N, NF, SF>, S::WGS, S::G, S::K, true};
 }
-template <int N, int NF> static PassKernel pk2()
+template <int N, int NF, bool SF> static PassKernel pk2()
 {
     using S = P2Shape<N, NF>;
-    return {k_pass2<N, NF>, S::WGS, S::G, S::K, false};
+    return {k_pass2<N, NF, SF>, S::WGS, S::G, S::K, false};
 }
-template <int N, int NF> static PassKernel pk3()
+template <int N, int NF, bool SF> static PassKernel pk3()
 {
     using S = PassShape<N>;
-    return {k_pass3<N, NF>, S::WGS, S::G, S::K, true};
+    return {k_pass3<N, NF, SF>, S::WGS, S::G, S::K, true};
 }
 
-#define SG_SIZE_CASES(F, NF)                                                                      \
-    case 4: return F<4, NF>();                                                                     \
-    case 8: return F<8, NF>();                                                                     \
-    case 16: return F<16, NF>();                                                                   \
-    case 32: return F<32, NF>();                                                                   \
-    case 64: return F<64, NF>();                                                                   \
-    case 128: return F<128, NF>();                                                                 \
-    case 256: return F<256, NF>();                                                                 \
-    case 512: return F<512, NF>();                                                                 \
-    case 1024: return F<1024, NF>();                                                               \
-    case 2048: return F<2048, NF>();
-
-static bool pass_kernel(int pass, int n, int nf, PassKernel &out)
+template <bool SF> static PassKernel pick_kernel(int pass, int n, int nf)
 {
-    auto pick = [&]() -> PassKernel {
-        if (pass == 1) {
-            if (nf == 1) switch (n) { SG_SIZE_CASES(pk1, 1) }
-            else switch (n) { SG_SIZE_CASES(pk1, 2) }
-        } else if (pass == 2) {
-            if (nf == 1) switch (n) { SG_SIZE_CASES(pk2, 1) case 4096: return pk2<4096, 1>(); }
-            else switch (n) { SG_SIZE_CASES(pk2, 2) case 4096: return pk2<4096, 2>(); }
-        } else {
-            if (nf == 1) switch (n) { SG_SIZE_CASES(pk3, 1) }
-            else switch (n) { SG_SIZE_CASES(pk3, 2) }
-        }
-        return PassKernel{nullptr, 0, 0, 0, false};
-    };
-    out = pick();
+#define SG_CASE(F, L) \
+    case L: return nf == 1 ? F<L, 1, SF>() : F<L, 2, SF>();
+#define SG_SIZES(F)                                                                               \
+    SG_CASE(F, 4) SG_CASE(F, 8) SG_CASE(F, 16) SG_CASE(F, 32) SG_CASE(F, 64) SG_CASE(F, 128)      \
+    SG_CASE(F, 256) SG_CASE(F, 512) SG_CASE(F, 1024) SG_CASE(F, 2048)
+    if (pass == 1) {
+        switch (n) { SG_SIZES(pk1) }
+    } else if (pass == 2) {
+        switch (n) { SG_SIZES(pk2) SG_CASE(pk2, 4096) }
+    } else {
+        switch (n) { SG_SIZES(pk3) }
+    }
+#undef SG_SIZES
+#undef SG_CASE
+    return PassKernel{nullptr, 0, 0, 0, false};
+}
+
+static bool pass_kernel(int pass, int n, int nf, bool sf, PassKernel &out)
+{
+    out = sf ? pick_kernel<true>(pass, n, nf) : pick_kernel<false>(pass, n, nf);
     return out.fn != nullptr;
 }
 
+// Radix order has a choice only when the length is not a power of 8.
+static bool has_small_radix(int n)
+{
+    while (n >= 8) n /= 8;
+    return n > 1;
+}
+
 // ------------------------------------------------------------- batch plan
+// Tuning parameters of one launch: radix order, resident workgroups per CU of
+// a persistent pass (0: as many as fit), XCD cluster size (0: the default).
+struct Variant {
+    int sf = 0, occ = 0, K = 0;
+};
+
+// A launch class: one pass over the discs sharing a transform length and a
+// fluid count.
+struct ClassSpec {
+    int pass, len, nf;
+    std::vector<int> discs;
+};
+
 struct Launch {
     PassKernel k;
+    Variant v;
+    int K;            // cluster size in use
     size_t wj_off;    // offset (in WJob units) into the workgroup-job table
     int nj;           // workgroup jobs of this launch
     int grid;         // workgroups (a multiple of 8 K)
@@ -384,27 +405,106 @@ static int pass_jobs(const sg_disc &d, int pass)
     return nf * d.grid.n_r;
 }
 
-// Grid of a launch: whole XCD clusters of 8 K workgroups.  A persistent
-// kernel gets its resident workgroups per CU times the CU count (at least one
-// cluster, at most the work available); the others one workgroup per job.
-static int launch_grid(const PassKernel &k, int nj)
+static int device_cus()
 {
-    const int cluster = 8 * k.K;
-    const int need = (nj + cluster - 1) / cluster * cluster;
-    if (!k.persistent) return need;
-    int dev = 0, ncu = 0, per_cu = 0;
+    int dev = 0, ncu = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
         ncu = 256;
+    return ncu;
+}
+
+static int resident_per_cu(const PassKernel &k)
+{
+    int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k.fn, k.wgs, 0) != hipSuccess ||
         per_cu <= 0)
         per_cu = 1;
-    int grid = per_cu * ncu / cluster * cluster;
+    return per_cu;
+}
+
+// Grid of a launch: whole XCD clusters of 8 K workgroups.  A persistent
+// kernel gets occ (or all that fit) resident workgroups per CU times the CU
+// count, at least one cluster and at most the work available; the others
+// one workgroup per job.
+static int launch_grid(const PassKernel &k, int nj, int K, int occ)
+{
+    const int cluster = 8 * K;
+    const int need = (nj + cluster - 1) / cluster * cluster;
+    if (!k.persistent) return need;
+    const int fit = resident_per_cu(k);
+    const int per_cu = occ > 0 && occ < fit ? occ : fit;
+    int grid = per_cu * device_cus() / cluster * cluster;
     if (grid < cluster) grid = cluster;
     return grid < need ? grid : need;
 }
 
-static void build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
+// Workgroup jobs of a class: G jobs per workgroup job, each disc padded to a
+// whole number of clusters of K workgroup jobs so that cache-line sharing
+// stays inside one disc.
+static void class_wjobs(const sg_disc *discs, const ClassSpec &c, int G, int K, std::vector<WJob> &out)
+{
+    out.clear();
+    for (int di : c.discs) {
+        const int cnt = pass_jobs(discs[di], c.pass);
+        for (int b = 0; b < cnt; b += G) out.push_back({di, b, std::min(G, cnt - b), 0});
+        while (out.size() % K) out.push_back({di, 0, 0, 0});
+    }
+}
+
+static std::vector<ClassSpec> plan_classes(const sg_disc *discs, int n)
+{
+    std::vector<ClassSpec> out;
+    for (int pass = 1; pass <= 3; ++pass) {
+        std::map<std::pair<int, int>, std::vector<int>> classes;
+        for (int i = 0; i < n; ++i) {
+            const int len = pass == 2 ? 2 * discs[i].grid.n_r : discs[i].grid.n_phi;
+            classes[{len, discs[i].fluids.n_fluids}].push_back(i);
+        }
+        for (auto &kv : classes) out.push_back({pass, kv.first.first, kv.first.second, kv.second});
+    }
+    return out;
+}
+
+// Tuned variants, keyed by (pass, length, fluids, shape hash of the class).
+using TuneKey = std::tuple<int, int, int, uint64_t>;
+static std::map<TuneKey, Variant> g_tuned;
+
+static TuneKey tune_key(const sg_disc *discs, const ClassSpec &c)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the disc shapes
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int di : c.discs) {
+        mix((uint64_t)discs[di].grid.n_r);
+        mix((uint64_t)discs[di].grid.n_phi);
+    }
+    return TuneKey{c.pass, c.len, c.nf, h};
+}
+
+static bool make_launch(const sg_disc *discs, const Plan &P, const ClassSpec &c, Variant v, Launch &La,
+                        std::vector<WJob> &wj)
+{
+    PassKernel k;
+    if (!pass_kernel(c.pass, c.len, c.nf, v.sf != 0, k)) return false;
+    La.k = k;
+    La.v = v;
+    La.K = v.K > 0 ? v.K : k.K;
+    class_wjobs(discs, c, k.G, La.K, wj);
+    La.nj = (int)wj.size();
+    La.grid = launch_grid(k, La.nj, La.K, v.occ);
+    const DiscDev &D0 = P.discs[c.discs[0]];
+    La.tw = c.pass == 2 ? D0.tw_u : D0.tw_phi;
+    La.pass = c.pass;
+    La.wj_off = 0;
+    return true;
+}
+
+static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
 {
     P.discs.resize(n);
     size_t off = 0;
@@ -429,36 +529,24 @@ static void build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
         D.nf = d.fluids.n_fluids;
         D.pad_ = 0;
     }
-    // one launch per (pass, transform length, fluid count); jobs in disc order
-    for (int pass = 1; pass <= 3; ++pass) {
-        std::map<std::pair<int, int>, std::vector<int>> classes;
-        for (int i = 0; i < n; ++i) {
-            const int len = pass == 2 ? 2 * discs[i].grid.n_r : discs[i].grid.n_phi;
-            classes[{len, discs[i].fluids.n_fluids}].push_back(i);
-        }
-        for (auto &kv : classes) {
-            PassKernel k;
-            pass_kernel(pass, kv.first.first, kv.first.second, k);
-            std::vector<WJob> list;
-            for (int di : kv.second) {
-                const int cnt = pass_jobs(discs[di], pass);
-                for (int b = 0; b < cnt; b += k.G) list.push_back({di, b, std::min(k.G, cnt - b), 0});
-                // keep each disc's workgroup jobs aligned to whole clusters of
-                // K so that cache-line sharing stays inside one disc
-                while (list.size() % k.K) list.push_back({di, 0, 0, 0});
-            }
-            Launch La;
-            La.k = k;
-            La.wj_off = P.wjobs.size();
-            La.nj = (int)list.size();
-            La.grid = launch_grid(k, La.nj);
-            const DiscDev &D0 = P.discs[kv.second[0]];
-            La.tw = pass == 2 ? D0.tw_u : D0.tw_phi;
-            La.pass = pass;
-            P.wjobs.insert(P.wjobs.end(), list.begin(), list.end());
-            P.launches.push_back(La);
-        }
+}
+
+// One launch per class, with the tuned variant where one is known.
+static bool build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
+{
+    fill_discs(discs, n, ws, P);
+    std::vector<WJob> wj;
+    for (const ClassSpec &c : plan_classes(discs, n)) {
+        Variant v;
+        auto it = g_tuned.find(tune_key(discs, c));
+        if (it != g_tuned.end()) v = it->second;
+        Launch La;
+        if (!make_launch(discs, P, c, v, La, wj)) return false;
+        La.wj_off = P.wjobs.size();
+        P.wjobs.insert(P.wjobs.end(), wj.begin(), wj.end());
+        P.launches.push_back(La);
     }
+    return true;
 }
 
 struct Cached {
@@ -491,19 +579,22 @@ static std::vector<uint64_t> signature(const sg_disc *discs, int n, void *ws)
     return k;
 }
 
-static sg_status launch(const Cached &C, const Launch &L, hipStream_t s)
+static sg_status launch_one(const DiscDev *dd, const WJob *wj, const Launch &L, hipStream_t s)
 {
-    const DiscDev *dd = (const DiscDev *)C.dmem;
-    const WJob *wj = (const WJob *)((const char *)C.dmem + sg_align256(sizeof(DiscDev) * C.plan.discs.size()));
-    hipLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), 0, s, dd, wj + L.wj_off, L.nj, L.tw);
+    hipLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), 0, s, dd, wj + L.wj_off, L.nj, L.tw, L.K);
     SG_HIP(hipGetLastError());
     return SG_OK;
+}
+
+static const WJob *cached_wjobs(const Cached &C)
+{
+    return (const WJob *)((const char *)C.dmem + sg_align256(sizeof(DiscDev) * C.plan.discs.size()));
 }
 
 static sg_status enqueue(const Cached &C, hipStream_t s)
 {
     for (const Launch &L : C.plan.launches) {
-        const sg_status st = launch(C, L, s);
+        const sg_status st = launch_one((const DiscDev *)C.dmem, cached_wjobs(C), L, s);
         if (st != SG_OK) return st;
     }
     return SG_OK;
@@ -515,50 +606,70 @@ static bool use_graph()
     return !(e && e[0] == '1');
 }
 
+static void destroy(Cached *C)
+{
+    if (C->exec) (void)hipGraphExecDestroy(C->exec);
+    if (C->graph) (void)hipGraphDestroy(C->graph);
+    if (C->dmem) (void)hipFree(C->dmem);
+    delete C;
+}
+
+// Plan, device tables and graph of a batch signature (built on first use).
+// Caller holds g_mu.
+static sg_status get_cached(const sg_disc *discs, int n, void *ws, Cached *&out)
+{
+    auto key = signature(discs, n, ws);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        out = it->second;
+        return SG_OK;
+    }
+    Cached *C = new Cached;
+    if (!build_plan(discs, n, (char *)ws, C->plan)) {
+        delete C;
+        return SG_ERR_UNSUPPORTED;
+    }
+    const size_t bd = sg_align256(sizeof(DiscDev) * n);
+    const size_t bytes = bd + sizeof(WJob) * C->plan.wjobs.size();
+    if (hipMalloc(&C->dmem, bytes) != hipSuccess) {
+        delete C;
+        return SG_ERR_HIP;
+    }
+    if (hipMemcpy(C->dmem, C->plan.discs.data(), sizeof(DiscDev) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char *)C->dmem + bd, C->plan.wjobs.data(), sizeof(WJob) * C->plan.wjobs.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        destroy(C);
+        return SG_ERR_HIP;
+    }
+    if (use_graph()) {
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            destroy(C);
+            return SG_ERR_HIP;
+        }
+        bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        sg_status st = ok ? enqueue(*C, cs) : SG_ERR_HIP;
+        hipGraph_t gph = nullptr;
+        ok = hipStreamEndCapture(cs, &gph) == hipSuccess && ok && st == SG_OK;
+        if (ok) ok = hipGraphInstantiate(&C->exec, gph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipStreamDestroy(cs);
+        C->graph = gph;
+        if (!ok) {
+            destroy(C);
+            return SG_ERR_HIP;
+        }
+    }
+    g_cache[key] = C;
+    out = C;
+    return SG_OK;
+}
+
 sg_status sg_fft_run(const sg_disc *discs, int n, void *ws, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto key = signature(discs, n, ws);
-    Cached *C;
-    auto it = g_cache.find(key);
-    if (it == g_cache.end()) {
-        C = new Cached;
-        build_plan(discs, n, (char *)ws, C->plan);
-        const size_t bd = sg_align256(sizeof(DiscDev) * n);
-        const size_t bytes = bd + sizeof(WJob) * C->plan.wjobs.size();
-        if (hipMalloc(&C->dmem, bytes) != hipSuccess) {
-            delete C;
-            return SG_ERR_HIP;
-        }
-        if (hipMemcpy(C->dmem, C->plan.discs.data(), sizeof(DiscDev) * n, hipMemcpyHostToDevice) !=
-                hipSuccess ||
-            hipMemcpy((char *)C->dmem + bd, C->plan.wjobs.data(), sizeof(WJob) * C->plan.wjobs.size(),
-                      hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(C->dmem);
-            delete C;
-            return SG_ERR_HIP;
-        }
-        if (use_graph()) {
-            hipStream_t cs;
-            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SG_ERR_HIP;
-            bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            sg_status st = ok ? enqueue(*C, cs) : SG_ERR_HIP;
-            hipGraph_t gph = nullptr;
-            ok = hipStreamEndCapture(cs, &gph) == hipSuccess && ok && st == SG_OK;
-            if (ok) ok = hipGraphInstantiate(&C->exec, gph, nullptr, nullptr, 0) == hipSuccess;
-            (void)hipStreamDestroy(cs);
-            if (!ok) {
-                if (gph) (void)hipGraphDestroy(gph);
-                (void)hipFree(C->dmem);
-                delete C;
-                return SG_ERR_HIP;
-            }
-            C->graph = gph;
-        }
-        g_cache[key] = C;
-    } else {
-        C = it->second;
-    }
+    Cached *C = nullptr;
+    const sg_status st = get_cached(discs, n, ws, C);
+    if (st != SG_OK) return st;
     if (C->exec) {
         SG_HIP(hipGraphLaunch(C->exec, s));
         return SG_OK;
@@ -571,56 +682,305 @@ sg_status sg_fft_run(const sg_disc *discs, int n, void *ws, hipStream_t s)
 // each pass (ms[0..2]).
 sg_status sg_fft_profile(const sg_disc *discs, int n, void *ws, hipStream_t s, int reps, float *ms)
 {
-    Cached *C;
-    {
-        // make sure the plan exists (first call builds it, like sg_fft_run)
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto key = signature(discs, n, ws);
-        auto it = g_cache.find(key);
-        if (it == g_cache.end()) C = nullptr;
-        else C = it->second;
-    }
-    if (!C) {
-        sg_status st = sg_fft_run(discs, n, ws, s);
-        if (st != SG_OK) return st;
-        std::lock_guard<std::mutex> lk(g_mu);
-        C = g_cache[signature(discs, n, ws)];
-    }
-    std::vector<hipEvent_t> ev(4 * reps);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Cached *C = nullptr;
+    sg_status st = get_cached(discs, n, ws, C);
+    if (st != SG_OK) return st;
+    std::vector<hipEvent_t> ev(4 * reps, nullptr);
     for (auto &e : ev) SG_HIP(hipEventCreate(&e));
-    for (int r = 0; r < reps; ++r) {
+    for (int r = 0; r < reps && st == SG_OK; ++r) {
         SG_HIP(hipEventRecord(ev[4 * r], s));
-        for (int pass = 1; pass <= 3; ++pass) {
-            for (const Launch &L : C->plan.launches) {
-                if (L.pass != pass) continue;
-                const sg_status st = launch(*C, L, s);
-                if (st != SG_OK) return st;
-            }
+        for (int pass = 1; pass <= 3 && st == SG_OK; ++pass) {
+            for (const Launch &L : C->plan.launches)
+                if (L.pass == pass && st == SG_OK) st = launch_one((const DiscDev *)C->dmem, cached_wjobs(*C), L, s);
             SG_HIP(hipEventRecord(ev[4 * r + pass], s));
         }
     }
-    SG_HIP(hipEventSynchronize(ev[4 * reps - 1]));
+    if (st == SG_OK) st = hipEventSynchronize(ev[4 * reps - 1]) == hipSuccess ? SG_OK : SG_ERR_HIP;
     for (int p = 0; p < 3; ++p) ms[p] = 0.f;
-    for (int r = 0; r < reps; ++r)
+    for (int r = 0; r < reps && st == SG_OK; ++r)
         for (int p = 0; p < 3; ++p) {
             float t = 0.f;
-            SG_HIP(hipEventElapsedTime(&t, ev[4 * r + p], ev[4 * r + p + 1]));
+            if (hipEventElapsedTime(&t, ev[4 * r + p], ev[4 * r + p + 1]) != hipSuccess) st = SG_ERR_HIP;
             ms[p] += t / reps;
         }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    return SG_OK;
+    return st;
+}
+
+static void release_locked()
+{
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g_cache) destroy(kv.second);
+    g_cache.clear();
 }
 
 void sg_fft_release()
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    (void)hipDeviceSynchronize();
-    for (auto &kv : g_cache) {
-        Cached *C = kv.second;
-        if (C->exec) (void)hipGraphExecDestroy(C->exec);
-        if (C->graph) (void)hipGraphDestroy(C->graph);
-        if (C->dmem) (void)hipFree(C->dmem);
-        delete C;
+    release_locked();
+}
+
+// ------------------------------------------------------------- autotuner
+// Relative RMS difference of two float buffers: acc[0] += sum (a - b)^2,
+// acc[1] += sum b^2 (double, one atomic pair per workgroup).
+__global__ void __launch_bounds__(256) k_cmp(const float *a, const float *b, size_t n, double *acc)
+{
+    __shared__ double red[2][256];
+    double d2 = 0.0, b2 = 0.0;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double x = a[i], y = b[i];
+        d2 += (x - y) * (x - y);
+        b2 += y * y;
     }
-    g_cache.clear();
+    red[0][threadIdx.x] = d2;
+    red[1][threadIdx.x] = b2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&acc[0], red[0][0]);
+        atomicAdd(&acc[1], red[1][0]);
+    }
+}
+
+// Output buffers of a class: (pointer, float count) per written region.
+static void class_outputs(const sg_disc *discs, const Plan &P, const ClassSpec &c,
+                          std::vector<std::pair<float *, size_t>> &out)
+{
+    out.clear();
+    for (int di : c.discs) {
+        const DiscDev &D = P.discs[di];
+        const size_t fs = sg_blk_field_elems(D.nphi, D.nr);
+        const size_t cells = (size_t)D.nr * D.nphi * D.nf;
+        if (c.pass == 1) out.push_back({(float *)D.st, 2 * fs * D.nf});
+        else if (c.pass == 2) out.push_back({(float *)D.gh, 4 * fs * D.nf});
+        else {
+            out.push_back({D.gr, cells});
+            out.push_back({D.gp, cells});
+        }
+    }
+    (void)discs;
+}
+
+namespace {
+struct TuneScratch {
+    void *dd = nullptr;   // DiscDev array
+    void *wj = nullptr;   // WJob table of the candidate
+    size_t wj_cap = 0;
+    float *ref = nullptr; // reference outputs of the class
+    size_t ref_cap = 0;
+    double *acc = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (dd) (void)hipFree(dd);
+        if (wj) (void)hipFree(wj);
+        if (ref) (void)hipFree(ref);
+        if (acc) (void)hipFree(acc);
+    }
+};
+}  // namespace
+
+static sg_status tune_upload_wj(TuneScratch &S, const std::vector<WJob> &wj)
+{
+    const size_t bytes = sizeof(WJob) * wj.size();
+    if (bytes > S.wj_cap) {
+        if (S.wj) (void)hipFree(S.wj);
+        S.wj = nullptr;
+        SG_HIP(hipMalloc(&S.wj, bytes));
+        S.wj_cap = bytes;
+    }
+    SG_HIP(hipMemcpy(S.wj, wj.data(), bytes, hipMemcpyHostToDevice));
+    return SG_OK;
+}
+
+static sg_status tune_time(TuneScratch &S, const Launch &L, hipStream_t s, int reps, float &ms)
+{
+    for (int r = 0; r < 2; ++r)
+        if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, L, s) != SG_OK) return SG_ERR_HIP;
+    SG_HIP(hipEventRecord(S.e0, s));
+    for (int r = 0; r < reps; ++r)
+        if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, L, s) != SG_OK) return SG_ERR_HIP;
+    SG_HIP(hipEventRecord(S.e1, s));
+    SG_HIP(hipEventSynchronize(S.e1));
+    SG_HIP(hipEventElapsedTime(&ms, S.e0, S.e1));
+    ms /= reps;
+    return SG_OK;
+}
+
+static sg_status tune_compare(TuneScratch &S, const std::vector<std::pair<float *, size_t>> &outs,
+                              hipStream_t s, double &rel)
+{
+    SG_HIP(hipMemsetAsync(S.acc, 0, 2 * sizeof(double), s));
+    size_t off = 0;
+    for (const auto &o : outs) {
+        const int grid = (int)std::min<size_t>((o.second + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_cmp, dim3(grid), dim3(256), 0, s, o.first, S.ref + off, o.second, S.acc);
+        SG_HIP(hipGetLastError());
+        off += o.second;
+    }
+    double h[2] = {0.0, 0.0};
+    SG_HIP(hipMemcpyAsync(h, S.acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
+    rel = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] > 0.0 ? 1.0 : 0.0);
+    if (!(rel == rel)) rel = 1.0;  // NaN
+    return SG_OK;
+}
+
+static void load_tune_file();
+static void save_tune_file();
+
+sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_tune_result *res, int cap,
+                      int *nres)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file();
+    int count = 0;
+    TuneScratch S;
+    Plan P;
+    fill_discs(discs, n, (char *)ws, P);
+    SG_HIP(hipMalloc(&S.dd, sizeof(DiscDev) * n));
+    SG_HIP(hipMemcpy(S.dd, P.discs.data(), sizeof(DiscDev) * n, hipMemcpyHostToDevice));
+    SG_HIP(hipMalloc(&S.acc, 2 * sizeof(double)));
+    SG_HIP(hipEventCreate(&S.e0));
+    SG_HIP(hipEventCreate(&S.e1));
+    const int reps = 10;
+    std::vector<WJob> wj;
+    std::vector<std::pair<float *, size_t>> outs;
+    for (const ClassSpec &c : plan_classes(discs, n)) {
+        // reference: the default variant
+        Launch L0;
+        if (!make_launch(discs, P, c, Variant{}, L0, wj)) return SG_ERR_UNSUPPORTED;
+        sg_status st = tune_upload_wj(S, wj);
+        if (st != SG_OK) return st;
+        if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, L0, s) != SG_OK) return SG_ERR_HIP;
+        class_outputs(discs, P, c, outs);
+        size_t total = 0;
+        for (const auto &o : outs) total += o.second;
+        if (total > S.ref_cap) {
+            if (S.ref) (void)hipFree(S.ref);
+            S.ref = nullptr;
+            SG_HIP(hipMalloc(&S.ref, total * sizeof(float)));
+            S.ref_cap = total;
+        }
+        size_t off = 0;
+        for (const auto &o : outs) {
+            SG_HIP(hipMemcpyAsync(S.ref + off, o.first, o.second * sizeof(float), hipMemcpyDeviceToDevice, s));
+            off += o.second;
+        }
+        float ms0 = 0.f;
+        st = tune_time(S, L0, s, reps, ms0);
+        if (st != SG_OK) return st;
+        // candidates
+        PassKernel k0;
+        pass_kernel(c.pass, c.len, c.nf, false, k0);
+        const int fit = k0.persistent ? resident_per_cu(k0) : 0;
+        std::vector<int> occs = {0};
+        if (k0.persistent)
+            for (int o : {1, 2, 3, 4, 6, 8})
+                if (o < fit) occs.push_back(o);
+        Variant best;
+        float ms_best = ms0;
+        double rel_best = 0.0;
+        int ncand = 0, nrej = 0;
+        for (int sf = 0; sf <= (has_small_radix(c.len) ? 1 : 0); ++sf)
+            for (int occ : occs)
+                for (int K : {1, 2, 4, 8}) {
+                    const Variant v{sf, occ, K};
+                    Launch L;
+                    if (!make_launch(discs, P, c, v, L, wj)) continue;
+                    if (L.K == L0.K && sf == 0 && occ == 0) continue;  // the reference itself
+                    ++ncand;
+                    st = tune_upload_wj(S, wj);
+                    if (st != SG_OK) return st;
+                    if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, L, s) != SG_OK) return SG_ERR_HIP;
+                    double rel = 1.0;
+                    st = tune_compare(S, outs, s, rel);
+                    if (st != SG_OK) return st;
+                    if (rel > 1e-5) {  // a candidate must reproduce the reference first
+                        ++nrej;
+                        continue;
+                    }
+                    float ms = 0.f;
+                    st = tune_time(S, L, s, reps, ms);
+                    if (st != SG_OK) return st;
+                    if (ms < ms_best) {
+                        ms_best = ms;
+                        best = v;
+                        rel_best = rel;
+                    }
+                }
+        // leave the class's outputs as the chosen variant writes them
+        Launch Lb;
+        make_launch(discs, P, c, best, Lb, wj);
+        st = tune_upload_wj(S, wj);
+        if (st != SG_OK) return st;
+        if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, Lb, s) != SG_OK) return SG_ERR_HIP;
+        SG_HIP(hipStreamSynchronize(s));
+        g_tuned[tune_key(discs, c)] = best;
+        if (res && count < cap) {
+            sg_tune_result &r = res[count];
+            r.pass = c.pass;
+            r.length = c.len;
+            r.n_fluids = c.nf;
+            r.n_jobs = Lb.nj;
+            r.small_radix_first = best.sf;
+            r.wg_per_cu = best.occ;
+            r.cluster = Lb.K;
+            r.candidates = ncand;
+            r.rejected = nrej;
+            r.rel_best = (float)rel_best;
+            r.ms_default = ms0;
+            r.ms_best = ms_best;
+        }
+        ++count;
+    }
+    if (nres) *nres = count;
+    // cached plans were built before this tuning: rebuild on next use
+    release_locked();
+    save_tune_file();
+    return SG_OK;
+}
+
+// Optional persistent cache: SG_TUNE_CACHE names a text file with one line
+// "pass length fluids shape_hash sf occ K" per tuned class; read once, and
+// rewritten after every tuning call.
+static bool g_tune_file_loaded = false;
+
+static void load_tune_file()
+{
+    if (g_tune_file_loaded) return;
+    g_tune_file_loaded = true;
+    const char *path = getenv("SG_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    int pass, len, nf, sf, occ, K;
+    unsigned long long h;
+    while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &occ, &K) == 7)
+        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && occ >= 0 && occ <= 64 &&
+            (K == 0 || K == 1 || K == 2 || K == 4 || K == 8))
+            g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, occ, K};
+    fclose(f);
+}
+
+static void save_tune_file()
+{
+    const char *path = getenv("SG_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    for (const auto &kv : g_tuned)
+        fprintf(f, "%d %d %d %llx %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                std::get<2>(kv.first), (unsigned long long)std::get<3>(kv.first), kv.second.sf, kv.second.occ,
+                kv.second.K);
+    fclose(f);
 }

@@ -6,6 +6,7 @@ from __future__ import annotations
 import torch
 
 from . import (F32, F64, SELF_CELL_EXCLUDE, WITH_DH, field_adjoint, field_adjoint_workspace_bytes,
+               field_fft_tune,
                field_direct, field_direct_workspace_bytes, field_fft, field_fft_workspace_bytes,
                fluids, grid, kernel_table, kernel_table_bytes, kernel_table_workspace_bytes,
                make_disc)
@@ -62,6 +63,10 @@ class FFTField:
 
     def run(self, stream=None):
         field_fft(self.discs, self.ws, stream=stream)
+
+    def tune(self, stream=None):
+        """Autotunes this batch (sg_field_fft_tune); later runs use the choices."""
+        return field_fft_tune(self.discs, self.ws, stream=stream)
 
 
 def direct(g, h, sigma, H=None, flags=0, stream=None):
