@@ -28,6 +28,17 @@ struct AdjDev {
     int count;      // jobs of the launch
 };
 
+// Launch shape of the adjoint kernels: one transform per T threads, at least
+// 256 threads per workgroup, XCD clusters of K workgroups sharing the 32-byte
+// tile columns of the intermediates.
+template <int N> struct AdjShape {
+    static constexpr int P = FftShape<N>::P;
+    static constexpr int T = FftShape<N>::T;
+    static constexpr int WGS = T > 256 ? T : 256;
+    static constexpr int G = WGS / T;
+    static constexpr int K = G >= 4 ? 1 : 4 / G;
+};
+
 __device__ inline int adj_job(int G, int K, int g, bool &whole_invalid, int count, bool &valid)
 {
     const int wl = sg_xcd_remap(blockIdx.x, K);
@@ -39,9 +50,9 @@ __device__ inline int adj_job(int G, int K, int g, bool &whole_invalid, int coun
 
 // pass 1 on lam: job (b, i): z = lam_r[b][i] + i lam_phi[b][i]
 template <int N>
-__global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_lam(AdjDev A)
+__global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_lam(AdjDev A)
 {
-    using S = PassShape<N>;
+    using S = AdjShape<N>;
     constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
@@ -59,9 +70,9 @@ __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_lam(AdjDev A)
 
 // pass 1 on Sigma (only when dh is requested): same pairing as the forward
 template <int N, int NF>
-__global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_sig(AdjDev A)
+__global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_sig(AdjDev A)
 {
-    using S = PassShape<N>;
+    using S = AdjShape<N>;
     constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
@@ -82,9 +93,9 @@ __global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_sig(AdjDev A)
 // pass 2: column m.  dSigma^_a = sum_{b,c} conj(K'_c^{ab}) lam^_{b,c}; with DH,
 // also the Parseval partials of lam^ against D' Sigma^ for this column.
 template <int NU, int NF, bool DH>
-__global__ void __launch_bounds__(PassShape<NU>::WGS) k_adj_col(AdjDev A)
+__global__ void __launch_bounds__(AdjShape<NU>::WGS) k_adj_col(AdjDev A)
 {
-    using S = PassShape<NU>;
+    using S = AdjShape<NU>;
     constexpr int P = S::P, T = S::T, G = S::G;
     constexpr int W = LdsPlane<float>::elems(NU);
     constexpr int NR = NU / 2;
@@ -189,9 +200,9 @@ __global__ void __launch_bounds__(PassShape<NU>::WGS) k_adj_col(AdjDev A)
 
 // pass 3: inverse phi transform of dSigma~ pairs (as the forward pass 1 pairing)
 template <int N, int NF>
-__global__ void __launch_bounds__(PassShape<N>::WGS) k_adj_out(AdjDev A)
+__global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_out(AdjDev A)
 {
-    using S = PassShape<N>;
+    using S = AdjShape<N>;
     constexpr int W = LdsPlane<float>::elems(N);
     __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
     const int g = threadIdx.x / S::T, t = threadIdx.x % S::T;
@@ -237,7 +248,7 @@ size_t sg_adjoint_ws_bytes(const sg_disc &d)
 
 template <int N> static int nwg_for(int count)
 {
-    using S = PassShape<N>;
+    using S = AdjShape<N>;
     int nwg = (count + S::G - 1) / S::G;
     const int q = 8 * S::K;
     return (nwg + q - 1) / q * q;
@@ -248,27 +259,27 @@ static sg_status adj_launch(AdjDev A, bool dh, double *d_dh, int ncol, hipStream
 {
     const int nr = A.D.nr;
     A.count = NF * nr;
-    hipLaunchKernelGGL(k_adj_lam<NPHI>, dim3(nwg_for<NPHI>(A.count)), dim3(PassShape<NPHI>::WGS), 0,
+    hipLaunchKernelGGL(k_adj_lam<NPHI>, dim3(nwg_for<NPHI>(A.count)), dim3(AdjShape<NPHI>::WGS), 0,
                        s, A);
     SG_HIP(hipGetLastError());
     const int pairs = NF == 2 ? nr : nr / 2;
     if (dh) {
         A.count = pairs;
         hipLaunchKernelGGL((k_adj_sig<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)),
-                           dim3(PassShape<NPHI>::WGS), 0, s, A);
+                           dim3(AdjShape<NPHI>::WGS), 0, s, A);
         SG_HIP(hipGetLastError());
     }
     A.count = ncol;
     if (dh)
         hipLaunchKernelGGL((k_adj_col<NU, NF, true>), dim3(nwg_for<NU>(ncol)),
-                           dim3(PassShape<NU>::WGS), 0, s, A);
+                           dim3(AdjShape<NU>::WGS), 0, s, A);
     else
         hipLaunchKernelGGL((k_adj_col<NU, NF, false>), dim3(nwg_for<NU>(ncol)),
-                           dim3(PassShape<NU>::WGS), 0, s, A);
+                           dim3(AdjShape<NU>::WGS), 0, s, A);
     SG_HIP(hipGetLastError());
     A.count = pairs;
     hipLaunchKernelGGL((k_adj_out<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)),
-                       dim3(PassShape<NPHI>::WGS), 0, s, A);
+                       dim3(AdjShape<NPHI>::WGS), 0, s, A);
     SG_HIP(hipGetLastError());
     if (dh) {
         hipLaunchKernelGGL(k_adj_dh_reduce, dim3(1), dim3(256), 0, s, A.part, ncol, NF, d_dh);

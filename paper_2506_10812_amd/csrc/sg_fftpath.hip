@@ -12,80 +12,92 @@
 #include "sg_passes.h"
 
 // ---------------------------------------------------------------- kernels
-// Passes 1 and 3 are persistent: workgroup b takes workgroup jobs
-// w = sg_xcd_remap(b, K), w + gridDim.x, ... < nj, and issues the loads of its
-// next job before it transforms the current one, so that the memory traffic
-// of one job overlaps the arithmetic of the previous one.  gridDim.x is a
-// multiple of 8 K (a whole number of XCD clusters of K workgroups that share
-// cache lines).  Twiddles depend only on the transform length, so one table
-// serves every disc of a launch.  SF selects the radix order of the
-// transforms (small radix first); SF and K are tuning parameters.
+// Workgroup b takes workgroup job w = sg_xcd_remap(b, K); gridDim.x is a
+// multiple of 8 K (a whole number of XCD clusters of K consecutive workgroup
+// jobs).  Twiddles depend only on the transform length, so one table serves
+// every disc of a launch.  SF selects the radix order of the transforms
+// (small radix first); SF and K are tuning parameters.
+//
+// Passes 1 and 3 give each workgroup whole row quads and move the
+// intermediates tile by tile (sg_blk_index): elements 2l and 2l+1 of a tile
+// are one 16-byte access, 8 lanes cover a tile, and the values are exchanged
+// with the transforms through each group's LDS plane.
 
-// Pass 1: job = one row pair (two fluids: row idx of each; one fluid: rows
-// 2 idx and 2 idx + 1).  Job state is kept as wave-uniform scalars (disc,
-// first job, valid count) and addresses are rebuilt from them where needed.
-template <int N, int NF>
-__device__ inline void p1_rows(int idx, int &i1, int &i2)
-{
-    i1 = NF == 2 ? idx : 2 * idx;
-    i2 = NF == 2 ? idx : 2 * idx + 1;
-}
-
-template <int N, int NF>
-__device__ inline void p1_issue(const DiscDev *D, int idx, int t, float2 (&z)[FftShape<N>::P])
-{
-    constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
-    int i1, i2;
-    p1_rows<N, NF>(idx, i1, i2);
-    const uint32_t o1 = (uint32_t)i1 * N + t;
-    const uint32_t o2 = (NF == 2 ? (uint32_t)D->nr * N : 0u) + (uint32_t)i2 * N + t;
-    const float *x = D->sigma;
-#pragma unroll
-    for (int p = 0; p < P; ++p) z[p] = make_float2(gld1(x, o1 + T * p), gld1(x, o2 + T * p));
-}
+// Pass 1: group g takes job base + g = (fluid f, row pair j): rows 2j and
+// 2j + 1 of fluid f as the real and imaginary parts of one complex transform.
+// Two jobs fill a row quad, so a workgroup has G >= 2 groups (even).
+// Padding rows (row counts below 4) read the last real row.
+template <int N> struct P1Shape {
+    static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+    static constexpr int WGS = 2 * T > 256 ? 2 * T : 256;
+    static constexpr int G = WGS / T;
+    static constexpr int K = 1;
+};
 
 template <int N, int NF, bool SF>
-__global__ void __launch_bounds__(PassShape<N>::WGS)
+__global__ void __launch_bounds__(P1Shape<N>::WGS)
 k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
-    using S = PassShape<N>;
-    constexpr int P = S::P, W = LdsPlane<float>::elems(N);
-    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
-    const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
-    int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
+    using S = P1Shape<N>;
+    constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<float>::elems(N);
+    constexpr int NG = (N / 2 + 1 + 3) / 4;  // column groups (tiles per row quad)
+    __shared__ __attribute__((aligned(16))) float2 lds[W * G];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
+    const int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
+    const DiscDev *D = discs + cd;
+    const int nr = D->nr, half = sg_blk_rows(nr) / 2;  // row pairs per fluid
     const LdsPlane<float> pl{lds + W * g};
     TwRegC<N, SF> tw;
-    tw.load(twp, t0);
-    int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
-    float2 nx[P];
-    p1_issue<N, NF>(discs + cd, g < cn ? cb + g : cb, t0, nx);
-    for (;;) {
-        const int t = sg_opaque(t0);
-        float2 z[P];
+    tw.load(twp, t);
+    // 1. two real rows as one complex transform
+    float2 z[P];
+    {
+        const int idx = g < cn ? cb + g : cb;
+        const int f = idx / half, j = idx % half;
+        const uint32_t o = (uint32_t)f * nr * N + t;
+        const uint32_t o1 = o + (uint32_t)min(2 * j, nr - 1) * N;
+        const uint32_t o2 = o + (uint32_t)min(2 * j + 1, nr - 1) * N;
 #pragma unroll
-        for (int p = 0; p < P; ++p) z[p] = nx[p];
-        const int wn = w + gridDim.x;
-        const bool more = wn < nj;
-        int nd = cd, nb = cb, nn = cn;
-        if (more) {
-            nd = sg_uniform(wj[wn].disc);
-            nb = sg_uniform(wj[wn].base);
-            nn = sg_uniform(wj[wn].n);
-            p1_issue<N, NF>(discs + nd, g < nn ? nb + g : nb, t, nx);
+        for (int p = 0; p < P; ++p) z[p] = make_float2(gld1(D->sigma, o1 + T * p), gld1(D->sigma, o2 + T * p));
+    }
+    fft<N, false>(z, t, pl, tw);
+#pragma unroll
+    for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
+    __syncthreads();
+    // 2. Hermitian split in place: slot m <- X1[m], slot N - m <- X2[m]
+    //    (0 < m < N/2); slots 0 and N/2 keep Z = X1 + i X2 (both real there)
+#pragma unroll
+    for (int p = 0; p < P / 2; ++p) {
+        const int m = t + T * p;
+        if (m == 0) continue;
+        const float2 Z = pl.ld(m), C = pl.ld(N - m);
+        pl.st(m, make_float2(0.5f * (Z.x + C.x), 0.5f * (Z.y - C.y)));
+        pl.st(N - m, make_float2(0.5f * (Z.y + C.y), -0.5f * (Z.x - C.x)));
+    }
+    __syncthreads();
+    // 3. tile stores: row quad k of the workgroup = jobs cb + 2k, cb + 2k + 1
+    //    (one fluid); its row r comes from group 2k + r/2, X1 (r even) or X2
+    const size_t fs = sg_blk_field_elems(N, nr);
+    for (int e = threadIdx.x; e < (G / 2) * NG * 8; e += S::WGS) {
+        const int k = e / (NG * 8), q = (e / 8) % NG, l = e & 7;
+        if (2 * k >= cn) continue;
+        const int j0 = cb + 2 * k;
+        const int f = j0 / half, i0 = 2 * (j0 % half);
+        const int c = 4 * q + (l >> 1), r0 = 2 * (l & 1);
+        // rows r0 and r0 + 1: X1 and X2 of group 2k + r0/2
+        const LdsPlane<float> X{lds + W * (2 * k + (r0 >> 1))};
+        float2 v0 = make_float2(0.f, 0.f), v1 = make_float2(0.f, 0.f);
+        if (c == 0 || c == N / 2) {
+            const float2 Z = X.ld(c);
+            v0 = make_float2(Z.x, 0.f);
+            v1 = make_float2(Z.y, 0.f);
+        } else if (c < N / 2) {
+            v0 = X.ld(c);
+            v1 = X.ld(N - c);
         }
-        {
-            const DiscDev *D = discs + cd;
-            int i1, i2;
-            p1_rows<N, NF>(g < cn ? cb + g : cb, i1, i2);
-            const size_t fs = sg_blk_field_elems(N, D->nr);
-            p1_finish<N>(z, D->st, i1, D->st + (NF == 2 ? fs : 0), i2, D->nr, tw, t, pl, g < cn);
-        }
-        if (!more) break;
-        w = wn;
-        cd = nd;
-        cb = nb;
-        cn = nn;
+        gst2x2(D->st + f * fs + sg_blk_tile(q, i0, nr) + 2 * l, v0, v1);
     }
 }
 
@@ -241,61 +253,64 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     }
 }
 
-// Pass 3: job = (target fluid b, row i): inverse phi transform of
-// g^_r + i g^_phi, whose real and imaginary parts are g_r and g_phi.
-template <int N>
-__device__ inline void p3_issue(const DiscDev *D, int idx, int t, float2 (&a)[FftShape<N>::P],
-                                float2 (&b)[FftShape<N>::P])
-{
-    const int nr = D->nr;
-    const int bf = idx / nr, i = idx % nr;
-    const size_t fs = sg_blk_field_elems(N, nr);
-    const float2 *A = D->gh + (size_t)(bf * 2) * fs;
-    p3_load<N>(A, i, A + fs, i, nr, a, b, t);
-}
-
+// Pass 3: group g takes job base + g = (target fluid b, row i): inverse phi
+// transform of g^_r + i g^_phi, whose real and imaginary parts are g_r and
+// g_phi.  The half spectra arrive tile by tile and are expanded into each
+// group's plane: z[m] = A[m] + i B[m], z[N - m] = conj A[m] + i conj B[m].
 template <int N, int NF, bool SF>
 __global__ void __launch_bounds__(PassShape<N>::WGS)
 k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
     using S = PassShape<N>;
-    constexpr int P = S::P, W = LdsPlane<float>::elems(N);
-    __shared__ __attribute__((aligned(16))) float2 lds[W * S::G];
-    const int g = threadIdx.x / S::T, t0 = threadIdx.x % S::T;
-    int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
+    constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<float>::elems(N);
+    constexpr int NG = (N / 2 + 1 + 3) / 4;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * G];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
+    const int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
+    const DiscDev *D = discs + cd;
+    const int nr = D->nr, nrp = sg_blk_rows(nr);
+    const size_t fs = sg_blk_field_elems(N, nr);
+    // 1. tile loads of the row quads into the planes
+    for (int e = threadIdx.x; e < (G / 4) * NG * 8; e += S::WGS) {
+        const int k = e / (NG * 8), q = (e / 8) % NG, l = e & 7;
+        if (4 * k >= cn) continue;
+        const int j0 = cb + 4 * k;  // first job of the quad: same fluid for all 4
+        const int b = j0 / nrp, i0 = j0 % nrp;
+        const float2 *A = D->gh + (size_t)(b * 2) * fs + sg_blk_tile(q, i0, nr) + 2 * l;
+        float2 va[2], vb[2];
+        gld2x2(A, va[0], va[1]);
+        gld2x2(A + fs, vb[0], vb[1]);
+        const int c = 4 * q + (l >> 1), r0 = 2 * (l & 1);
+        if (c > N / 2) continue;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float2 a = va[u], bb = vb[u];
+            const LdsPlane<float> X{lds + W * (4 * k + r0 + u)};
+            X.st(c, make_float2(a.x - bb.y, a.y + bb.x));
+            if (c != 0 && c != N / 2) X.st(N - c, make_float2(a.x + bb.y, bb.x - a.y));
+        }
+    }
+    __syncthreads();
     const LdsPlane<float> pl{lds + W * g};
+    float2 z[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
+    __syncthreads();
     TwRegC<N, SF> tw;
-    tw.load(twp, t0);
-    int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
-    float2 a[P], b[P];
-    p3_issue<N>(discs + cd, g < cn ? cb + g : cb, t0, a, b);
-    for (;;) {
-        const int t = sg_opaque(t0);
-        float2 z[P];
-        p3_combine<N>(a, b, z, t);
-        const int wn = w + gridDim.x;
-        const bool more = wn < nj;
-        int nd = cd, nb = cb, nn = cn;
-        if (more) {
-            nd = sg_uniform(wj[wn].disc);
-            nb = sg_uniform(wj[wn].base);
-            nn = sg_uniform(wj[wn].n);
-            p3_issue<N>(discs + nd, g < nn ? nb + g : nb, t, a, b);
+    tw.load(twp, t);
+    // 2. inverse transform, two real rows out
+    fft<N, true>(z, t, pl, tw);
+    const int idx = cb + g;
+    const int b = idx / nrp, i = idx % nrp;
+    if (g < cn && i < nr) {
+        const size_t o = (size_t)b * nr * N + (size_t)i * N;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            gst1(D->gr + o, t + T * p, z[p].x);
+            gst1(D->gp + o, t + T * p, z[p].y);
         }
-        {
-            const DiscDev *D = discs + cd;
-            const int idx = g < cn ? cb + g : cb;
-            const int nr = D->nr;
-            const size_t plane = (size_t)nr * N;
-            const size_t o = (size_t)(idx / nr) * plane + (size_t)(idx % nr) * N;
-            p3_finish<N>(z, tw, D->gr + o, D->gp + o, t, pl, g < cn);
-        }
-        if (!more) break;
-        w = wn;
-        cd = nd;
-        cb = nb;
-        cn = nn;
     }
 }
 
@@ -311,8 +326,8 @@ struct PassKernel {
 
 template <int N, int NF, bool SF> static PassKernel pk1()
 {
-    using S = PassShape<N>;
-    return {k_pass1<N, NF, SF>, S::WGS, S::G, S::K, true};
+    using S = P1Shape<N>;
+    return {k_pass1<N, NF, SF>, S::WGS, S::G, S::K, false};
 }
 template <int N, int NF, bool SF> static PassKernel pk2()
 {
@@ -322,7 +337,7 @@ template <int N, int NF, bool SF> static PassKernel pk2()
 template <int N, int NF, bool SF> static PassKernel pk3()
 {
     using S = PassShape<N>;
-    return {k_pass3<N, NF, SF>, S::WGS, S::G, S::K, true};
+    return {k_pass3<N, NF, SF>, S::WGS, S::G, S::K, false};
 }
 
 template <bool SF> static PassKernel pick_kernel(int pass, int n, int nf)
@@ -395,14 +410,14 @@ size_t sg_fft_disc_ws_bytes(const sg_disc &d)
            sg_align256(sizeof(float2) * fs * 2 * d.fluids.n_fluids);
 }
 
-// Jobs of one disc in a pass: pass 1 row pairs, pass 2 columns m <= n_phi/2,
-// pass 3 (target fluid, row) pairs.
+// Jobs of one disc in a pass: pass 1 (fluid, row pair), pass 2 columns m <= n_phi/2,
+// pass 3 (target fluid, row) pairs; rows padded to sg_blk_rows.
 static int pass_jobs(const sg_disc &d, int pass)
 {
-    const int nf = d.fluids.n_fluids;
-    if (pass == 1) return nf == 2 ? d.grid.n_r : d.grid.n_r / 2;
+    const int nf = d.fluids.n_fluids, nrp = sg_blk_rows(d.grid.n_r);
+    if (pass == 1) return nf * nrp / 2;
     if (pass == 2) return d.grid.n_phi / 2 + 1;
-    return nf * d.grid.n_r;
+    return nf * nrp;
 }
 
 static int device_cus()

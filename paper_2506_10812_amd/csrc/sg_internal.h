@@ -97,6 +97,26 @@ __device__ inline void gst2(float2 *p, uint32_t i, float2 v)
 __device__ inline float gld1(const float *p, uint32_t i) { return *(sg_gcf *)((const char *)p + (i << 2)); }
 __device__ inline void gst1(float *p, uint32_t i, float v) { *(sg_gf *)((char *)p + (i << 2)) = v; }
 
+// 16-byte access of two consecutive complex values (16-byte aligned).
+typedef float sg_v4f __attribute__((ext_vector_type(4)));
+typedef const sg_v4f __attribute__((address_space(1))) sg_gcv4f;
+typedef sg_v4f __attribute__((address_space(1))) sg_gv4f;
+__device__ inline void gld2x2(const float2 *p, float2 &a, float2 &b)
+{
+    const sg_v4f v = *(sg_gcv4f *)p;
+    a = make_float2(v.x, v.y);
+    b = make_float2(v.z, v.w);
+}
+__device__ inline void gst2x2(float2 *p, float2 a, float2 b)
+{
+    sg_v4f v;
+    v.x = a.x;
+    v.y = a.y;
+    v.z = b.x;
+    v.w = b.y;
+    *(sg_gv4f *)p = v;
+}
+
 // Forces a value that is equal in all lanes into a scalar register.
 __device__ inline int sg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -165,17 +185,26 @@ inline TableLayout sg_table_layout(int nr, int nphi, int nf, uint32_t flags)
     return L;
 }
 
-// Block ("M = 4") layout of the half-spectrum intermediates between the
-// passes: element (m, i) of one field lives at ((m >> 2) * n_r + i) * 4 + (m & 3).
-// One 128-byte cache line therefore holds 4 consecutive columns of 4
-// consecutive rows, written whole by the 4 row jobs of one XCD.
+// Tiled layout of the half-spectrum intermediates between the passes: tiles
+// of 4 columns x 4 rows (128 bytes), each column's 4 rows contiguous inside
+// the tile, and the tiles of one 4-column group following each other down
+// the rows.  A column job of pass 2 then reads and writes 32 contiguous bytes
+// per 4 rows, and a workgroup of 4 consecutive rows in passes 1 and 3 moves
+// whole tiles.  Row counts below 4 are padded to 4 (the padding rows are
+// written by pass 1 and never read as data).
+__host__ __device__ inline int sg_blk_rows(int nr) { return nr < 4 ? 4 : nr; }
 __host__ __device__ inline size_t sg_blk_index(int m, int i, int nr)
 {
-    return ((size_t)(m >> 2) * nr + i) * 4 + (m & 3);
+    return ((size_t)(m >> 2) * sg_blk_rows(nr) + (i & ~3)) * 4 + (m & 3) * 4 + (i & 3);
+}
+// first element of tile (column group q, rows i0 .. i0 + 3), i0 % 4 == 0
+__host__ __device__ inline size_t sg_blk_tile(int q, int i0, int nr)
+{
+    return ((size_t)q * sg_blk_rows(nr) + i0) * 4;
 }
 __host__ __device__ inline size_t sg_blk_field_elems(int nphi, int nr)
 {
-    return (size_t)((nphi / 2 + 1 + 3) >> 2) * nr * 4;
+    return (size_t)((nphi / 2 + 1 + 3) >> 2) * sg_blk_rows(nr) * 4;
 }
 
 // XCD-aware remap of workgroup ids: MI355X dispatches consecutive workgroups

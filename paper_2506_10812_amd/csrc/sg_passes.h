@@ -13,7 +13,7 @@
 //                    g_r[b][i][:] + i g_phi[b][i][:]  (two real outputs per
 //                    complex transform)
 // The kernel spectra already carry the factor -du dphi/(2 n_r n_phi), so no
-// pass scales.  Intermediates use the 4-column block layout of sg_blk_index.
+// pass scales.  Intermediates use the tiled layout of sg_blk_index.
 #pragma once
 #include "sg_fft.h"
 
@@ -41,12 +41,14 @@ struct WJob {
 };
 
 // launch shape shared by host and device
+// (passes 1 and 3: G >= 4 rows per workgroup, a multiple of 4; the adjoint's
+// row passes use the same shape)
 template <int N> struct PassShape {
     static constexpr int P = FftShape<N>::P;
     static constexpr int T = FftShape<N>::T;
-    static constexpr int WGS = T > 256 ? T : 256;
-    static constexpr int G = WGS / T;             // transforms per workgroup
-    static constexpr int K = G >= 4 ? 1 : 4 / G;  // workgroups per XCD cluster
+    static constexpr int WGS = 4 * T > 256 ? 4 * T : 256;
+    static constexpr int G = WGS / T;  // transforms per workgroup
+    static constexpr int K = 1;        // workgroups per XCD cluster
 };
 
 // ------------------------------------------------------------------ pass 1
