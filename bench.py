@@ -261,7 +261,7 @@ def main():
     extra = {"table_build_s": round(table_s, 3), "wall_s_timed": round(wall, 3),
              "ms_per_pass": [round(v, 5) for v in ms_pass],
              "ms_per_pass_untuned": [round(v, 5) for v in ms_untuned],
-             "tuned": [{k: r[k] for k in ("pass", "length", "small_radix_first", "wg_per_cu", "cluster",
+             "tuned": [{k: r[k] for k in ("pass", "length", "small_radix_first", "groups_per_wg", "cluster",
                                           "candidates", "rejected")} for r in tuned],
              "path_algorithmic_bytes": pb["path"],
              "path_hbm_frac": round(pb["path"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -153,9 +153,9 @@ sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, si
  * class of the batch (one pass over the discs that share a transform length
  * and a fluid count) it runs the default launch as the reference, then every
  * candidate: radix order of the transforms (small radix last or first, where
- * the length is not a power of 8), resident workgroups per CU of the
- * persistent row passes (1, 2, 3, 4, 6, 8 or all that fit) and XCD cluster
- * size (1, 2, 4 or 8 workgroups sharing cache lines).  A candidate is timed
+ * the length is not a power of 8), tile shape (the default number of
+ * transforms per workgroup or twice it, up to 1024 threads) and XCD cluster
+ * size (1, 2, 4 or 8 consecutive workgroups on one XCD).  A candidate is timed
  * only if its output matches the reference (relative RMS <= 1e-5 over the
  * class's output buffers); the fastest wins.  Choices are cached per class
  * shape for the life of the process (and in the text file named by the
@@ -173,7 +173,7 @@ typedef struct sg_tune_result {
     int32_t n_fluids;
     int32_t n_jobs;            /* workgroup jobs of the chosen launch */
     int32_t small_radix_first; /* chosen radix order */
-    int32_t wg_per_cu;         /* chosen resident workgroups per CU, 0 = all that fit */
+    int32_t groups_per_wg;     /* chosen transforms per workgroup */
     int32_t cluster;           /* chosen XCD cluster size */
     int32_t candidates;        /* candidates tried besides the reference */
     int32_t rejected;          /* candidates that failed the output check */

@@ -44,7 +44,7 @@ class Disc(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "pass_", "length", "n_fluids", "n_jobs", "small_radix_first", "wg_per_cu", "cluster",
+        "pass_", "length", "n_fluids", "n_jobs", "small_radix_first", "groups_per_wg", "cluster",
         "candidates", "rejected")] + [(n, ctypes.c_float) for n in ("rel_best", "ms_default", "ms_best")]
 
 

@@ -27,18 +27,18 @@
 // 2j + 1 of fluid f as the real and imaginary parts of one complex transform.
 // Two jobs fill a row quad, so a workgroup has G >= 2 groups (even).
 // Padding rows (row counts below 4) read the last real row.
-template <int N> struct P1Shape {
+template <int N, int GM> struct P1Shape {
     static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
-    static constexpr int WGS = 2 * T > 256 ? 2 * T : 256;
-    static constexpr int G = WGS / T;
+    static constexpr int G = GM * (256 / T > 2 ? 256 / T : 2);
+    static constexpr int WGS = G * T;
     static constexpr int K = 1;
 };
 
-template <int N, int NF, bool SF>
-__global__ void __launch_bounds__(P1Shape<N>::WGS)
+template <int N, int NF, bool SF, int GM>
+__global__ void __launch_bounds__((P1Shape<N, GM>::WGS))
 k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
-    using S = P1Shape<N>;
+    using S = P1Shape<N, GM>;
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<float>::elems(N);
     constexpr int NG = (N / 2 + 1 + 3) / 4;  // column groups (tiles per row quad)
     __shared__ __attribute__((aligned(16))) float2 lds[W * G];
@@ -105,11 +105,11 @@ k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 // the two halves each own one fluid (forward transform of that source fluid,
 // then spectral multiply and inverse transforms for that target fluid), so
 // no thread holds more than one fluid's accumulators.
-template <int NU, int NF> struct P2Shape {
+template <int NU, int NF, int GM> struct P2Shape {
     static constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T;
     static constexpr int CT = NF * T;
-    static constexpr int WGS = CT > 256 ? CT : 256;
-    static constexpr int G = WGS / CT;
+    static constexpr int G = GM * (256 / CT > 1 ? 256 / CT : 1);
+    static constexpr int WGS = G * CT;
     static constexpr int K = G >= 4 ? 1 : 4 / G;
 };
 
@@ -152,11 +152,11 @@ __device__ inline void p2_issue(const DiscDev *D, int m, int h, int t, float2 (&
 //   4. the products go to LDS in natural order and come back in the
 //      transform distribution; inverse u transforms of the (r, phi) pair; the
 //      first n_r outputs are stored.
-template <int NU, int NF, bool SF>
-__global__ void __launch_bounds__((P2Shape<NU, NF>::WGS)) __attribute__((amdgpu_waves_per_eu(4)))
+template <int NU, int NF, bool SF, int GM>
+__global__ void __launch_bounds__((P2Shape<NU, NF, GM>::WGS)) __attribute__((amdgpu_waves_per_eu(4)))
 k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
 {
-    using S = P2Shape<NU, NF>;
+    using S = P2Shape<NU, NF, GM>;
     constexpr int P = S::P, T = S::T, H = P / 2;
     constexpr int NR = NU / 2;
     constexpr int W = LdsPlane<float>::elems(NU);
@@ -257,11 +257,11 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
 // transform of g^_r + i g^_phi, whose real and imaginary parts are g_r and
 // g_phi.  The half spectra arrive tile by tile and are expanded into each
 // group's plane: z[m] = A[m] + i B[m], z[N - m] = conj A[m] + i conj B[m].
-template <int N, int NF, bool SF>
-__global__ void __launch_bounds__(PassShape<N>::WGS)
+template <int N, int NF, bool SF, int GM>
+__global__ void __launch_bounds__((PassShape<N, GM>::WGS))
 k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
 {
-    using S = PassShape<N>;
+    using S = PassShape<N, GM>;
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<float>::elems(N);
     constexpr int NG = (N / 2 + 1 + 3) / 4;
     __shared__ __attribute__((aligned(16))) float2 lds[W * G];
@@ -321,29 +321,32 @@ using KernelFn = void (*)(const DiscDev *, const WJob *, int, const float2 *, in
 struct PassKernel {
     KernelFn fn;
     int wgs, G, K;    // K: default XCD cluster size
-    bool persistent;  // loops over workgroup jobs (else one per workgroup)
 };
 
-template <int N, int NF, bool SF> static PassKernel pk1()
+// Shapes above 1024 threads do not exist (null kernel).
+template <int N, int NF, bool SF, int GM> static PassKernel pk1()
 {
-    using S = P1Shape<N>;
-    return {k_pass1<N, NF, SF>, S::WGS, S::G, S::K, false};
+    using S = P1Shape<N, GM>;
+    if constexpr (S::WGS > 1024) return PassKernel{nullptr, 0, 0, 0};
+    else return {k_pass1<N, NF, SF, GM>, S::WGS, S::G, S::K};
 }
-template <int N, int NF, bool SF> static PassKernel pk2()
+template <int N, int NF, bool SF, int GM> static PassKernel pk2()
 {
-    using S = P2Shape<N, NF>;
-    return {k_pass2<N, NF, SF>, S::WGS, S::G, S::K, false};
+    using S = P2Shape<N, NF, GM>;
+    if constexpr (S::WGS > 1024) return PassKernel{nullptr, 0, 0, 0};
+    else return {k_pass2<N, NF, SF, GM>, S::WGS, S::G, S::K};
 }
-template <int N, int NF, bool SF> static PassKernel pk3()
+template <int N, int NF, bool SF, int GM> static PassKernel pk3()
 {
-    using S = PassShape<N>;
-    return {k_pass3<N, NF, SF>, S::WGS, S::G, S::K, false};
+    using S = PassShape<N, GM>;
+    if constexpr (S::WGS > 1024) return PassKernel{nullptr, 0, 0, 0};
+    else return {k_pass3<N, NF, SF, GM>, S::WGS, S::G, S::K};
 }
 
-template <bool SF> static PassKernel pick_kernel(int pass, int n, int nf)
+template <bool SF, int GM> static PassKernel pick_kernel(int pass, int n, int nf)
 {
 #define SG_CASE(F, L) \
-    case L: return nf == 1 ? F<L, 1, SF>() : F<L, 2, SF>();
+    case L: return nf == 1 ? F<L, 1, SF, GM>() : F<L, 2, SF, GM>();
 #define SG_SIZES(F)                                                                               \
     SG_CASE(F, 4) SG_CASE(F, 8) SG_CASE(F, 16) SG_CASE(F, 32) SG_CASE(F, 64) SG_CASE(F, 128)      \
     SG_CASE(F, 256) SG_CASE(F, 512) SG_CASE(F, 1024) SG_CASE(F, 2048)
@@ -356,12 +359,13 @@ template <bool SF> static PassKernel pick_kernel(int pass, int n, int nf)
     }
 #undef SG_SIZES
 #undef SG_CASE
-    return PassKernel{nullptr, 0, 0, 0, false};
+    return PassKernel{nullptr, 0, 0, 0};
 }
 
-static bool pass_kernel(int pass, int n, int nf, bool sf, PassKernel &out)
+static bool pass_kernel(int pass, int n, int nf, bool sf, int gm, PassKernel &out)
 {
-    out = sf ? pick_kernel<true>(pass, n, nf) : pick_kernel<false>(pass, n, nf);
+    if (gm == 2) out = sf ? pick_kernel<true, 2>(pass, n, nf) : pick_kernel<false, 2>(pass, n, nf);
+    else out = sf ? pick_kernel<true, 1>(pass, n, nf) : pick_kernel<false, 1>(pass, n, nf);
     return out.fn != nullptr;
 }
 
@@ -373,10 +377,10 @@ static bool has_small_radix(int n)
 }
 
 // ------------------------------------------------------------- batch plan
-// Tuning parameters of one launch: radix order, resident workgroups per CU of
-// a persistent pass (0: as many as fit), XCD cluster size (0: the default).
+// Tuning parameters of one launch: radix order, tile shape (transforms per
+// workgroup times gm), XCD cluster size (0: the default).
 struct Variant {
-    int sf = 0, occ = 0, K = 0;
+    int sf = 0, gm = 1, K = 0;
 };
 
 // A launch class: one pass over the discs sharing a transform length and a
@@ -420,38 +424,12 @@ static int pass_jobs(const sg_disc &d, int pass)
     return nf * nrp;
 }
 
-static int device_cus()
-{
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-        ncu = 256;
-    return ncu;
-}
-
-static int resident_per_cu(const PassKernel &k)
-{
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k.fn, k.wgs, 0) != hipSuccess ||
-        per_cu <= 0)
-        per_cu = 1;
-    return per_cu;
-}
-
-// Grid of a launch: whole XCD clusters of 8 K workgroups.  A persistent
-// kernel gets occ (or all that fit) resident workgroups per CU times the CU
-// count, at least one cluster and at most the work available; the others
-// one workgroup per job.
-static int launch_grid(const PassKernel &k, int nj, int K, int occ)
+// Grid of a launch: whole XCD clusters of 8 K workgroups, one per
+// workgroup job.
+static int launch_grid(int nj, int K)
 {
     const int cluster = 8 * K;
-    const int need = (nj + cluster - 1) / cluster * cluster;
-    if (!k.persistent) return need;
-    const int fit = resident_per_cu(k);
-    const int per_cu = occ > 0 && occ < fit ? occ : fit;
-    int grid = per_cu * device_cus() / cluster * cluster;
-    if (grid < cluster) grid = cluster;
-    return grid < need ? grid : need;
+    return (nj + cluster - 1) / cluster * cluster;
 }
 
 // Workgroup jobs of a class: G jobs per workgroup job, each disc padded to a
@@ -505,13 +483,13 @@ static bool make_launch(const sg_disc *discs, const Plan &P, const ClassSpec &c,
                         std::vector<WJob> &wj)
 {
     PassKernel k;
-    if (!pass_kernel(c.pass, c.len, c.nf, v.sf != 0, k)) return false;
+    if (!pass_kernel(c.pass, c.len, c.nf, v.sf != 0, v.gm, k)) return false;
     La.k = k;
     La.v = v;
     La.K = v.K > 0 ? v.K : k.K;
     class_wjobs(discs, c, k.G, La.K, wj);
     La.nj = (int)wj.size();
-    La.grid = launch_grid(k, La.nj, La.K, v.occ);
+    La.grid = launch_grid(La.nj, La.K);
     const DiscDev &D0 = P.discs[c.discs[0]];
     La.tw = c.pass == 2 ? D0.tw_u : D0.tw_phi;
     La.pass = c.pass;
@@ -895,24 +873,17 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
         st = tune_time(S, L0, s, reps, ms0);
         if (st != SG_OK) return st;
         // candidates
-        PassKernel k0;
-        pass_kernel(c.pass, c.len, c.nf, false, k0);
-        const int fit = k0.persistent ? resident_per_cu(k0) : 0;
-        std::vector<int> occs = {0};
-        if (k0.persistent)
-            for (int o : {1, 2, 3, 4, 6, 8})
-                if (o < fit) occs.push_back(o);
         Variant best;
         float ms_best = ms0;
         double rel_best = 0.0;
         int ncand = 0, nrej = 0;
         for (int sf = 0; sf <= (has_small_radix(c.len) ? 1 : 0); ++sf)
-            for (int occ : occs)
+            for (int gm = 1; gm <= 2; ++gm)
                 for (int K : {1, 2, 4, 8}) {
-                    const Variant v{sf, occ, K};
+                    const Variant v{sf, gm, K};
                     Launch L;
-                    if (!make_launch(discs, P, c, v, L, wj)) continue;
-                    if (L.K == L0.K && sf == 0 && occ == 0) continue;  // the reference itself
+                    if (!make_launch(discs, P, c, v, L, wj)) continue;  // shape does not exist
+                    if (L.K == L0.K && sf == 0 && gm == 1) continue;      // the reference itself
                     ++ncand;
                     st = tune_upload_wj(S, wj);
                     if (st != SG_OK) return st;
@@ -948,7 +919,7 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
             r.n_fluids = c.nf;
             r.n_jobs = Lb.nj;
             r.small_radix_first = best.sf;
-            r.wg_per_cu = best.occ;
+            r.groups_per_wg = Lb.k.G;
             r.cluster = Lb.K;
             r.candidates = ncand;
             r.rejected = nrej;
@@ -966,7 +937,7 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
 }
 
 // Optional persistent cache: SG_TUNE_CACHE names a text file with one line
-// "pass length fluids shape_hash sf occ K" per tuned class; read once, and
+// "pass length fluids shape_hash sf gm K" per tuned class; read once, and
 // rewritten after every tuning call.
 static bool g_tune_file_loaded = false;
 
@@ -978,12 +949,12 @@ static void load_tune_file()
     if (!path || !path[0]) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    int pass, len, nf, sf, occ, K;
+    int pass, len, nf, sf, gm, K;
     unsigned long long h;
-    while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &occ, &K) == 7)
-        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && occ >= 0 && occ <= 64 &&
+    while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &gm, &K) == 7)
+        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 2 &&
             (K == 0 || K == 1 || K == 2 || K == 4 || K == 8))
-            g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, occ, K};
+            g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, gm, K};
     fclose(f);
 }
 
@@ -995,7 +966,7 @@ static void save_tune_file()
     if (!f) return;
     for (const auto &kv : g_tuned)
         fprintf(f, "%d %d %d %llx %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                std::get<2>(kv.first), (unsigned long long)std::get<3>(kv.first), kv.second.sf, kv.second.occ,
+                std::get<2>(kv.first), (unsigned long long)std::get<3>(kv.first), kv.second.sf, kv.second.gm,
                 kv.second.K);
     fclose(f);
 }

@@ -120,17 +120,6 @@ __device__ inline void gst2x2(float2 *p, float2 a, float2 b)
 // Forces a value that is equal in all lanes into a scalar register.
 __device__ inline int sg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Returns v unchanged but opaque to the optimiser (an empty asm statement
-// that claims to modify its register).  Persistent loops pass their lane
-// index through it at the top of every iteration, so that the many
-// lane-dependent addresses of the transforms are recomputed where they are
-// used instead of being hoisted out of the loop and held in registers.
-__device__ inline int sg_opaque(int v)
-{
-    asm volatile("" : "+v"(v));
-    return v;
-}
-
 // ------------------------------------------------------------ table layout
 // Device kernel-table layout (all offsets 256-byte aligned, computable on the
 // host from the arguments alone):

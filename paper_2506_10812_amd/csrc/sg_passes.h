@@ -33,22 +33,22 @@ struct Job {
     int disc, idx;
 };
 
-// Workgroup job of the persistent passes: groups g < n of the workgroup take
+// Workgroup job of the passes: groups g < n of the workgroup take
 // jobs base + g of disc `disc`; groups g >= n (and all groups when n = 0)
 // repeat job `base` without storing, so every load address stays valid.
 struct WJob {
     int disc, base, n, pad_;
 };
 
-// launch shape shared by host and device
-// (passes 1 and 3: G >= 4 rows per workgroup, a multiple of 4; the adjoint's
-// row passes use the same shape)
-template <int N> struct PassShape {
+// Launch shape of pass 3, shared by host and device: G transforms (rows) per
+// workgroup, a multiple of 4 and at least 256 threads, times the tile-shape
+// factor GM (a tuning parameter); K: default XCD cluster size.
+template <int N, int GM = 1> struct PassShape {
     static constexpr int P = FftShape<N>::P;
     static constexpr int T = FftShape<N>::T;
-    static constexpr int WGS = 4 * T > 256 ? 4 * T : 256;
-    static constexpr int G = WGS / T;  // transforms per workgroup
-    static constexpr int K = 1;        // workgroups per XCD cluster
+    static constexpr int G = GM * (256 / T > 4 ? 256 / T : 4);
+    static constexpr int WGS = G * T;
+    static constexpr int K = 1;
 };
 
 // ------------------------------------------------------------------ pass 1
@@ -57,10 +57,8 @@ template <int N> struct PassShape {
 //   X1[m] = (Z[m] + conj Z[-m]) / 2,  X2[m] = (Z[m] - conj Z[-m]) / (2i),
 // written for m in [0, N/2] to block-layout fields d1 (row i1) and d2 (row i2).
 //
-// The loads are split from the transform so that a persistent kernel can
-// issue the next job's loads before transforming the current one.  Loads are
-// unconditional: padding groups pass valid addresses, and only the stores
-// depend on `valid`.
+// Loads are unconditional (padding groups pass valid addresses) so that they
+// are all in flight at once; only the stores depend on `valid`.
 template <int N>
 __device__ inline void p1_load(const float *x1, const float *x2, float2 (&z)[FftShape<N>::P], int t)
 {
