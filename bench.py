@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "SG field cells/s at 1024×2048 bi-fluid; %HBM roofline; rel err vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass2_bifluid_1024x2048.json")
-DOMINANT_KERNEL = "k_pass2<2048, 2>"   # pass 2 of the two-fluid 1024 x 2048 disc
-PASS_KERNELS = {"pass1": "k_pass1<2048, 2>", "pass2": "k_pass2<2048, 2>",
-                "pass3": "k_pass3<2048, 2>"}
+# pass 2 of the two-fluid 1024 x 2048 disc, any tuned variant (radix order,
+# tile shape); the summaries use the variant launched most often, which is
+# the one the tuned plan runs
+DOMINANT_PREFIX = "k_pass2<2048, 2,"
 
 # The rocprofv3 runs behind profiles/ (run from /tmp with TMPDIR=/tmp; {out}
 # is the output root, {repo} the repository).  Counter runs are separate
@@ -71,6 +72,17 @@ def pass_bytes(nr, nphi, nf):
             "path": sig + spec + g}
 
 
+def pass2_kernel_name(nr, nf, tuned):
+    """Kernel name of the pass-2 variant the (tuned) plan runs for this disc."""
+    nu = 2 * nr
+    sf, gm = False, 1
+    for r in tuned:
+        if r["pass"] == 2 and r["length"] == nu and r["n_fluids"] == nf:
+            g_default = max(1, 256 // (nf * max(1, nu // 8)))
+            sf, gm = bool(r["small_radix_first"]), r["groups_per_wg"] // g_default
+    return f"k_pass2<{nu}, {nf}, {'true' if sf else 'false'}, {gm}>"
+
+
 def _csv_rows(d, suffix):
     import csv
     import glob
@@ -82,12 +94,18 @@ def _csv_rows(d, suffix):
 
 
 def _counter_mean(d, kernel, counter):
-    """Mean per-dispatch value (KiB) of one counter over the dispatches of a kernel."""
-    vals = [float(r["Counter_Value"]) for r in _csv_rows(d, "_counter_collection.csv")
-            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
-    if not vals:
+    """Mean per-dispatch value (KiB) of one counter over the dispatches of a kernel
+    (the most frequent kernel whose name starts with `kernel`)."""
+    rows = [r for r in _csv_rows(d, "_counter_collection.csv")
+            if r["Kernel_Name"].replace("void ", "").startswith(kernel) and r["Counter_Name"] == counter]
+    if not rows:
         raise SystemExit(f"bench.py: no {counter} rows for {kernel} under {d}")
-    return sum(vals) / len(vals), len(vals)
+    names = {}
+    for r in rows:
+        names[r["Kernel_Name"]] = names.get(r["Kernel_Name"], 0) + 1
+    top = max(names, key=names.get)
+    vals = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == top]
+    return sum(vals) / len(vals), len(vals), top.split("(")[0].replace("void ", "")
 
 
 def summarize_rocprof(out):
@@ -111,16 +129,18 @@ def summarize_rocprof(out):
     with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
-    cf, _ = _counter_mean(os.path.join(out, "cfetch"), "copyBuffer", "FETCH_SIZE")
-    cw, _ = _counter_mean(os.path.join(out, "cwrite"), "copyBuffer", "WRITE_SIZE")
+    cf, _, _ = _counter_mean(os.path.join(out, "cfetch"), "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    cw, _, _ = _counter_mean(os.path.join(out, "cwrite"), "__amd_rocclr_copyBuffer", "WRITE_SIZE")
     f_scale = COPY_BYTES / (cf * 1024.0)
     w_scale = COPY_BYTES / (cw * 1024.0)
-    fk, nf_ = _counter_mean(os.path.join(out, "fetch"), DOMINANT_KERNEL, "FETCH_SIZE")
-    wk, nw_ = _counter_mean(os.path.join(out, "write"), DOMINANT_KERNEL, "WRITE_SIZE")
+    fk, nf_, kname = _counter_mean(os.path.join(out, "fetch"), DOMINANT_PREFIX, "FETCH_SIZE")
+    wk, nw_, kname_w = _counter_mean(os.path.join(out, "write"), DOMINANT_PREFIX, "WRITE_SIZE")
+    if kname_w != kname:
+        raise SystemExit(f"bench.py: FETCH and WRITE runs ran different variants ({kname}, {kname_w})")
     read_b = fk * 1024.0 * f_scale
     write_b = wk * 1024.0 * w_scale
     alg = pass_bytes(1024, 2048, 2)["pass2"]
-    tr = {"kernel": "pass2", "kernel_name": DOMINANT_KERNEL,
+    tr = {"kernel": "pass2", "kernel_name": kname,
           "kernel_source_hash": kernel_source_hash(),
           "fetch_size_kib": round(fk, 1), "write_size_kib": round(wk, 1),
           "dispatches": [nf_, nw_],
@@ -138,7 +158,7 @@ def summarize_rocprof(out):
          ["", f"Copy calibration (1 GiB device copy): FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE "
               f"{cw:.1f} KiB per launch, so FETCH_SIZE is scaled by {f_scale:.4f} and "
               f"WRITE_SIZE by {w_scale:.4f}.", "",
-          f"`{DOMINANT_KERNEL}` per launch (mean of {nf_} / {nw_} dispatches): FETCH_SIZE "
+          f"`{kname}` per launch (mean of {nf_} / {nw_} dispatches): FETCH_SIZE "
           f"{fk:.1f} KiB -> {read_b / 1e6:.2f} MB read, WRITE_SIZE {wk:.1f} KiB -> "
           f"{write_b / 1e6:.2f} MB written; total {(read_b + write_b) / 1e6:.2f} MB against "
           f"{alg / 1e6:.2f} MB algorithmic ({(read_b + write_b) / alg:.3f}x).", "",
@@ -231,11 +251,15 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
+        # every variant of the pass moves the same bytes (radix order and tile
+        # shape change the arithmetic order only), so the counters of any
+        # variant of this build describe the timed one
         if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel") == dom_name:
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom_name, "kernel_ms": round(ms_pass[dom], 5),
+                "kernel": dom_name, "kernel_name": pass2_kernel_name(nr, nf, tuned) if dom == 1 else None,
+                "kernel_ms": round(ms_pass[dom], 5),
                 "algorithmic_bytes": pb[dom_name]}
 
     # accuracy vs the FP64 oracle on 16384 seeded cells (also the CPU baseline)

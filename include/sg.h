@@ -139,12 +139,14 @@ size_t sg_field_fft_workspace_bytes(const sg_disc *discs, int n_discs);
 sg_status sg_field_fft(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
                        void *stream);
 
-/* Same computation as sg_field_fft, enqueued without the graph `reps` times
- * with HIP events at the boundaries of the three passes on `stream`; waits
- * for completion (synchronous) and writes the mean duration in milliseconds
- * of pass 1 (phi transform), pass 2 (u transform + spectral multiply +
- * inverse u transform) and pass 3 (inverse phi transform) to ms_per_pass[3].
- * For measurement; reps in [1, 10000]. */
+/* Per-pass timing of the sg_field_fft launches (no graph): one complete run,
+ * then pass 1's launches `reps` times back to back, then pass 2's, then
+ * pass 3's, with HIP events between the groups on `stream`; waits for
+ * completion (synchronous) and writes the mean milliseconds per launch of
+ * pass 1 (phi transform), pass 2 (u transform + spectral multiply + inverse
+ * u transform) and pass 3 (inverse phi transform) to ms_per_pass[3].  The
+ * outputs hold a complete result afterwards.  For measurement; reps in
+ * [1, 10000]. */
 sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
                                void *stream, int reps, float *ms_per_pass);
 

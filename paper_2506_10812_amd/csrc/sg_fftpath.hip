@@ -670,33 +670,35 @@ sg_status sg_fft_run(const sg_disc *discs, int n, void *ws, hipStream_t s)
     return enqueue(*C, s);
 }
 
-// Per-pass timing: enqueue the passes (no graph) `reps` times with HIP events
-// at the pass boundaries on `s`, wait, and return the mean milliseconds of
-// each pass (ms[0..2]).
+// Per-pass timing: each pass's launches are enqueued `reps` times back to
+// back between two HIP events on `s` (no graph), after one untimed complete
+// run; ms[p] is the mean milliseconds per launch of pass p + 1 (all of its
+// launch classes).  Back-to-back launches of the same pass leave each one's
+// duration with only the launch gap added, which is what a kernel trace
+// reports per dispatch.
 sg_status sg_fft_profile(const sg_disc *discs, int n, void *ws, hipStream_t s, int reps, float *ms)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     Cached *C = nullptr;
     sg_status st = get_cached(discs, n, ws, C);
     if (st != SG_OK) return st;
-    std::vector<hipEvent_t> ev(4 * reps, nullptr);
+    st = enqueue(*C, s);
+    if (st != SG_OK) return st;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     for (auto &e : ev) SG_HIP(hipEventCreate(&e));
-    for (int r = 0; r < reps && st == SG_OK; ++r) {
-        SG_HIP(hipEventRecord(ev[4 * r], s));
-        for (int pass = 1; pass <= 3 && st == SG_OK; ++pass) {
+    for (int pass = 1; pass <= 3 && st == SG_OK; ++pass) {
+        if (pass == 1 && hipEventRecord(ev[0], s) != hipSuccess) st = SG_ERR_HIP;
+        for (int r = 0; r < reps && st == SG_OK; ++r)
             for (const Launch &L : C->plan.launches)
                 if (L.pass == pass && st == SG_OK) st = launch_one((const DiscDev *)C->dmem, cached_wjobs(*C), L, s);
-            SG_HIP(hipEventRecord(ev[4 * r + pass], s));
-        }
+        if (st == SG_OK && hipEventRecord(ev[pass], s) != hipSuccess) st = SG_ERR_HIP;
     }
-    if (st == SG_OK) st = hipEventSynchronize(ev[4 * reps - 1]) == hipSuccess ? SG_OK : SG_ERR_HIP;
-    for (int p = 0; p < 3; ++p) ms[p] = 0.f;
-    for (int r = 0; r < reps && st == SG_OK; ++r)
-        for (int p = 0; p < 3; ++p) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, ev[4 * r + p], ev[4 * r + p + 1]) != hipSuccess) st = SG_ERR_HIP;
-            ms[p] += t / reps;
-        }
+    if (st == SG_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = SG_ERR_HIP;
+    for (int p = 0; p < 3 && st == SG_OK; ++p) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[p], ev[p + 1]) != hipSuccess) st = SG_ERR_HIP;
+        ms[p] = t / reps;
+    }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return st;
 }
