@@ -239,6 +239,20 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     value = cells / (ms_step * 1e-3)
 
+    # cold steps: a 512 MB buffer is rewritten between launches, evicting the
+    # caches (incl. the 256 MB Infinity Cache); median of single-launch times
+    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(30):
+        flush.fill_(1.0)
+        e0.record(stream)
+        F.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    del flush
+    cold_ms = float(np.median(cold))
+
     # per-pass durations with HIP events on the launch stream (no graph)
     reps = max(10, min(args.steps, 200))
     ms_pass = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
@@ -283,6 +297,8 @@ def main():
                          f"(includes its table build), {cpu_s:.1f} s"}
 
     extra = {"table_build_s": round(table_s, 3), "wall_s_timed": round(wall, 3),
+             "cold_ms_per_step_median": round(cold_ms, 5),
+             "cold_cells_per_s": round(cells / (cold_ms * 1e-3), 1),
              "ms_per_pass": [round(v, 5) for v in ms_pass],
              "ms_per_pass_untuned": [round(v, 5) for v in ms_untuned],
              "tuned": [{k: r[k] for k in ("pass", "length", "small_radix_first", "groups_per_wg", "cluster",
@@ -354,6 +370,22 @@ def extra_measurements(sg, T, W, dev):
                       "looped_single_disc_ms": round(ms_loop, 4),
                       "speedup_vs_looped": round(ms_loop / ms, 3)}
     del Fb, singles
+    # adjoint on the 256x512 two-fluid workload: dL/dSigma and dL/dh
+    wa = W.adjoint()
+    ga = sg.grid(wa["n_r"], wa["n_phi"], wa["r_min"], wa["r_max"])
+    fa = sg.fluids(wa["h"])
+    tab = T.build_table(ga, fa, sg.WITH_DH, dev)
+    sig = torch.tensor(wa["sigma"], dtype=torch.float32, device=dev)
+    lr = torch.randn_like(sig)
+    lp = torch.randn_like(sig)
+    ds = torch.empty_like(sig)
+    dh = torch.zeros(len(wa["h"]), dtype=torch.float64, device=dev)
+    disc = sg.make_disc(ga, fa, sg.WITH_DH, sig, lr, lp, tab)
+    wsa = torch.empty(sg.field_adjoint_workspace_bytes(disc), dtype=torch.uint8, device=dev)
+    ms_adj = timed(lambda: sg.field_adjoint(disc, lr, lp, ds, dh, wsa), 50)
+    res["adjoint_256x512"] = {"ms": round(ms_adj, 4),
+                              "cells_per_s": round(wa["n_r"] * wa["n_phi"] / ms_adj * 1e3, 1)}
+    del tab, sig, lr, lp, ds, dh, wsa
     # FP64 direct sum on the 64x128 workload
     w = W.direct_fp64()
     g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])

@@ -131,7 +131,9 @@ typedef struct sg_disc {
  * u-transform, inverse phi transform.  The graph and a device copy of the
  * batch descriptors are cached per (sizes, pointers) signature on the first
  * call (that call allocates and synchronises once); later calls with the
- * same signature only launch.  d_ws: sg_field_fft_workspace_bytes(discs, n)
+ * same signature only launch.  At most 256 signatures are kept; a new one
+ * beyond that releases the least recently used (after a device
+ * synchronisation).  d_ws: sg_field_fft_workspace_bytes(discs, n)
  * bytes, 256-byte aligned; its address is part of the signature.
  * n_discs in [1, 4096].  Outputs overwritten.
  * --------------------------------------------------------------------- */

@@ -546,11 +546,18 @@ struct Cached {
     void *dmem = nullptr;      // descriptors + jobs on the device
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    uint64_t last_use = 0;
     Plan plan;
 };
 
+// At most SG_CACHE_MAX signatures keep their plan and graph; beyond that the
+// least recently used one is released (after a device synchronisation, so it
+// is idle).  Callers that pass new buffers on every call (one-off outputs)
+// therefore cannot grow the cache without bound.
+#define SG_CACHE_MAX 256
 static std::mutex g_mu;
 static std::map<std::vector<uint64_t>, Cached *> g_cache;
+static uint64_t g_tick = 0;
 
 static std::vector<uint64_t> signature(const sg_disc *discs, int n, void *ws)
 {
@@ -615,9 +622,19 @@ static sg_status get_cached(const sg_disc *discs, int n, void *ws, Cached *&out)
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         out = it->second;
+        out->last_use = ++g_tick;
         return SG_OK;
     }
+    if (g_cache.size() >= SG_CACHE_MAX) {
+        auto lru = g_cache.begin();
+        for (auto jt = g_cache.begin(); jt != g_cache.end(); ++jt)
+            if (jt->second->last_use < lru->second->last_use) lru = jt;
+        SG_HIP(hipDeviceSynchronize());
+        destroy(lru->second);
+        g_cache.erase(lru);
+    }
     Cached *C = new Cached;
+    C->last_use = ++g_tick;
     if (!build_plan(discs, n, (char *)ws, C->plan)) {
         delete C;
         return SG_ERR_UNSUPPORTED;

@@ -305,6 +305,28 @@ def test_fft_path_repeat_launches_are_identical(sg, T, W):
         assert torch.equal(F.g_r[0], ref_r)
 
 
+def test_fft_path_graph_cache_is_bounded(sg, T, W):
+    say("fft path: 300 signatures (fresh outputs each call), cache keeps 256")
+    w = W.bifluid_fft(seed=33, n_r=16, n_phi=32)
+    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+    f = sg.fluids(w["h"])
+    tab = T.build_table(g, f)
+    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda")
+    ref = None
+    keep = []  # distinct buffers, so that every call is a new signature
+    for k in range(300):
+        gr, gp = torch.empty_like(sig), torch.empty_like(sig)
+        disc = sg.make_disc(g, f, 0, sig, gr, gp, tab)
+        ws = torch.empty(sg.field_fft_workspace_bytes([disc]), dtype=torch.uint8, device="cuda")
+        keep.append((gr, gp, ws))
+        sg.field_fft([disc], ws)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (gr.clone(), gp.clone())
+        else:
+            assert torch.equal(gr, ref[0]) and torch.equal(gp, ref[1]), k
+
+
 # ---------------------------------------------------------------- adjoint
 def _adjoint(sg, T, w, lam_r, lam_p, want_dh=True):
     g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
