@@ -62,8 +62,20 @@ typedef enum sg_dtype { SG_F32 = 0, SG_F64 = 1 } sg_dtype;
 
 enum {
     SG_SELF_CELL_EXCLUDE = 1u, /* drop the own-cell term                      */
-    SG_WITH_DH = 2u            /* table also holds d/dh spectra (adjoint)     */
+    SG_WITH_DH = 2u,           /* table also holds d/dh spectra (adjoint)     */
+    SG_INDIRECT = 4u           /* add the indirect term (see below)           */
 };
+
+/* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
+ * fluid also receives the acceleration -sum_a grad Phi_{a,ind} of the frame
+ * centred on the star,
+ *   g_r  += -(A cos phi + B sin phi),   g_phi += -(-A sin phi + B cos phi),
+ *   A + i B = sum_a sqrt(2) sum_k Sigma_a[k] A_k K_a(d_k) e^{i phi_k},
+ *   K_a(d) = pi^{-1/2} H_a^{-2} (d/4) e^{d^2/4} [K1 - K0](d^2/4),
+ *   d_k = r_k / H_a at the source cell,
+ * with the cell measure A_k = r_k^2 du dphi.  Accepted by sg_kernel_table
+ * (no effect on the table), sg_field_fft and sg_field_direct; sg_field_adjoint
+ * returns SG_ERR_UNSUPPORTED for it. */
 
 typedef struct sg_grid {
     int32_t n_r;    /* radial cells                                   */
@@ -196,9 +208,11 @@ sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_
  * sigma), or NULL for H_f = h[f] r.  With per-cell H the self term of cell i
  * uses h_a = H_a[i]/r_i and h_b = H_b[i]/r_i.  dtype SG_F64: double inputs,
  * outputs and arithmetic; SG_F32: float inputs, outputs, arithmetic and
- * accumulation (the self term is computed in double and rounded).
- * n_r, n_phi >= 1, n_r * n_phi <= 2^26.  h: host array [F], read when
- * d_H == NULL.  d_ws: sg_field_direct_workspace_bytes() bytes.
+ * accumulation (the self term and the indirect term are computed in double
+ * and rounded).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (with the source
+ * cell's own H in K_a).  n_r, n_phi >= 1, n_r * n_phi <= 2^26.  h: host
+ * array [F], read when d_H == NULL.  d_ws: sg_field_direct_workspace_bytes()
+ * bytes.
  * --------------------------------------------------------------------- */
 size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
                                        int per_cell_H);

@@ -67,6 +67,10 @@ def lib():
         L.sg_oracle_adjoint_sigma.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, _dp]
+        L.sg_oracle_indirect.restype = ctypes.c_int
+        L.sg_oracle_indirect.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _dp, _dp, _dp, _dp]
         L.sg_oracle_threads.restype = ctypes.c_int
         L.sg_oracle_threads.argtypes = []
         _lib = L
@@ -209,6 +213,29 @@ def adjoint_h(nr, nphi, rmin, rmax, h, sigma, lam_r, lam_phi, flags=0):
                 v = float(np.sum(lam[b] * out[a, b]))
                 dh[a if role == "a" else b] += v
     return dh
+
+
+def indirect(nr, nphi, rmin, rmax, h, sigma, H=None):
+    """Indirect-term sums (A_a, B_a) per source fluid: array [nf][2]."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    h = _d(np.atleast_1d(h))
+    Hd = None if H is None else _d(H)
+    AB = np.empty((nf, 2))
+    rc = lib().sg_oracle_indirect(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(Hd), _ptr(sigma), _ptr(AB))
+    if rc:
+        raise RuntimeError(f"sg_oracle_indirect failed ({rc})")
+    return AB
+
+
+def indirect_field(nr, nphi, AB):
+    """Acceleration -sum_a grad Phi_{a,ind} (the same for every target fluid),
+    from the per-fluid sums of `indirect`: (g_r, g_phi), each [nr * nphi]."""
+    A, B = np.asarray(AB).sum(axis=0)
+    phi = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
+    gr = -(A * np.cos(phi) + B * np.sin(phi))
+    gp = -(-A * np.sin(phi) + B * np.cos(phi))
+    return np.tile(gr, nr), np.tile(gp, nr)
 
 
 def grid(nr, nphi, rmin, rmax):

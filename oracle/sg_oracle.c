@@ -309,6 +309,49 @@ static double orc_self_memo(orc_memo *m, int nm, double ha, double hb, double du
 }
 
 /* ------------------------------------------------------------------------
+ * Indirect term (Sect. 5.4 "Indirect term" and the appendix of the same
+ * name): the pull of fluid a on the star, in the form derived there,
+ *   A_a = sqrt(2) sum_k Sigma_a[k] A_k K_a(d_k) cos(phi_k),
+ *   B_a = sqrt(2) sum_k Sigma_a[k] A_k K_a(d_k) sin(phi_k),
+ *   K_a(d) = pi^{-1/2} H_a^{-2} (d/4) e^{d^2/4} [K1 - K0](d^2/4),
+ *   d_k = r_k / H_a(x_k)  (H_a = h_a r unless per-cell H is given),
+ * i.e. the disc integral of the appendix with the cell masses Sigma A_k of
+ * the area reading.  The gradient of the indirect potential is then
+ *   grad Phi_a = (A_a cos phi + B_a sin phi) e_r + (-A_a sin phi + B_a cos phi) e_phi.
+ * Output AB[2a] = A_a, AB[2a+1] = B_a.  Parity pinned by the vertical
+ * integral of the appendix's first line (brute-force quadrature), the
+ * equality sqrt(2) K_a = K_ab with H_b = 0, a one-cell disc, axisymmetry,
+ * rotation equivariance and the point-mass limit with its next term (tests).
+ * ------------------------------------------------------------------------ */
+int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const double *h,
+                       const double *H, const double *sigma, double *AB)
+{
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    const int64_t N = (int64_t)nr * nphi;
+    for (int a = 0; a < nf; ++a) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < nr; ++i) {
+            const double r = orc_r(&g, i);
+            const double area = r * r * g.du * g.dphi;
+            for (int j = 0; j < nphi; ++j) {
+                const int64_t k = (int64_t)a * N + (int64_t)i * nphi + j;
+                const double Hk = H ? H[k] : h[a] * r;
+                const double d = r / Hk;
+                const double Ka = (1.0 / ORC_SQRT_PI) / (Hk * Hk) * (d / 4.0) * sg_oracle_F(d * d / 4.0);
+                const double w = sqrt(2.0) * sigma[k] * area * Ka;
+                const double ph = orc_phi(&g, j);
+                sa += w * cos(ph);
+                sb += w * sin(ph);
+            }
+        }
+        AB[2 * a] = sa;
+        AB[2 * a + 1] = sb;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Pairwise (plain definition) field.
  * For each requested target cell i and target fluid b:
  *   G = - sum_a sum_{k != i} Sigma_a[k] A_k K_ab(|x_i - x_k|; H_a[k], H_b[i])

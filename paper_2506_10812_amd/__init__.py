@@ -18,6 +18,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE, ERR_TABLE = range(6)
 F32, F64 = 0, 1
 SELF_CELL_EXCLUDE = 1
 WITH_DH = 2
+INDIRECT = 4
 
 
 class SGError(RuntimeError):

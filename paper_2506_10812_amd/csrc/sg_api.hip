@@ -35,7 +35,10 @@ static sg_status check_fluids(const sg_fluids *f)
     return SG_OK;
 }
 
-static bool flags_ok(uint32_t flags) { return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH)) == 0; }
+static bool flags_ok(uint32_t flags)
+{
+    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH | SG_INDIRECT)) == 0;
+}
 
 extern "C" {
 
@@ -148,7 +151,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
     if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
     if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
     if (!d_sigma || !d_g_r || !d_g_phi) return SG_ERR_ARG;
-    if ((flags & ~(uint32_t)SG_SELF_CELL_EXCLUDE) != 0) return SG_ERR_ARG;
+    if ((flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT)) != 0) return SG_ERR_ARG;
     if (!d_H) {
         if (!h) return SG_ERR_ARG;
         for (int f = 0; f < n_fluids; ++f)
@@ -174,6 +177,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
+    if (disc->flags & SG_INDIRECT) return SG_ERR_UNSUPPORTED;
     if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
     if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))
         return SG_ERR_WORKSPACE;

@@ -19,7 +19,8 @@
 // per-source quantity is wave-uniform (scalar loads); the source rows are
 // split over blockIdx.y when there are too few targets to fill 256 CUs, and
 // the per-split partial sums are reduced in a fixed order by a second kernel
-// that also adds the self term (deterministic; no atomics).
+// that also adds the self term and, with SG_INDIRECT, the indirect term
+// (deterministic; no atomics).
 #include "sg_direct.h"
 #include "sg_kfn.h"
 #include "sg_table.h"
@@ -127,13 +128,77 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
     }
 }
 
+// Indirect term (SG_INDIRECT; Sect. 5.4 and the appendix "Indirect term"):
+//   A + i B = sum_a sqrt(2) sum_k Sigma_a[k] A_k K_a(d_k) e^{i phi_k},
+//   K_a(d) = pi^{-1/2} H_a^{-2} (d/4) F(d^2/4),  d_k = r_k / H_a[k],
+// in double for both precisions (a reduction over the cells, like the self
+// term).  Block b sums a fixed strided set of cells and the blocks' sums are
+// added in order by one thread, so the result is deterministic.
+#define SG_IND_BLOCKS 1024
+template <typename T>
+__global__ void __launch_bounds__(256) k_indirect_part(int nr, int nphi, int nf, double lnrmin, double du,
+                                                       double dphi, const double *h, const T *sigma,
+                                                       const T *H, double2 *part)
+{
+    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double ra[256], rb[256];
+    sg_fill_weights<double>(wq);
+    __syncthreads();
+    const int64_t N = (int64_t)nr * nphi, total = nf * N;
+    double sa = 0.0, sb = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        const int a = (int)(k / N);
+        const int64_t cell = k % N;
+        const int ir = (int)(cell / nphi), j = (int)(cell % nphi);
+        const double r = exp(lnrmin + (ir + 0.5) * du);
+        const double Hk = H ? (double)H[k] : h[a] * r;
+        const double d = r / Hk;
+        const double Ka = 1.0 / (SG_SQRT_PI * Hk * Hk) * (0.25 * d) * sg_F64(0.25 * d * d, wq);
+        const double w = SG_SQRT2 * (double)sigma[k] * r * r * du * dphi * Ka;
+        double sp, cp;
+        sincos((j + 0.5) * dphi, &sp, &cp);
+        sa += w * cp;
+        sb += w * sp;
+    }
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ra[threadIdx.x] += ra[threadIdx.x + o];
+            rb[threadIdx.x] += rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(ra[0], rb[0]);
+}
+
+__global__ void k_indirect_fin(const double2 *part, int n, double2 *AB)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < n; ++i) {
+        a += part[i].x;
+        b += part[i].y;
+    }
+    *AB = make_double2(a, b);
+}
+
 template <typename T, int NF>
 __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double *self,
-                                int percell, int with_self, const T *sigma, double dudphi, T *gr,
-                                T *gp)
+                                int percell, int with_self, const T *sigma, double dudphi,
+                                const double2 *ind, int nphi, T *gr, T *gp)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= N) return;
+    double ir = 0.0, ip = 0.0;  // indirect acceleration at this cell (all targets)
+    if (ind) {
+        const double2 AB = *ind;
+        double sp, cp;
+        sincos(((double)(t % nphi) + 0.5) * (2.0 * SG_PI / nphi), &sp, &cp);
+        ir = -(AB.x * cp + AB.y * sp);
+        ip = -(-AB.x * sp + AB.y * cp);
+    }
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
         T sr = T(0), sp = T(0);
@@ -150,6 +215,10 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
                 st -= dudphi * (double)sigma[a * N + t] * kb;
             }
             sr += (T)st;
+        }
+        if (ind) {
+            sr += (T)ir;
+            sp += (T)ip;
         }
         gr[b * N + t] = sr;
         gp[b * N + t] = sp;
@@ -180,6 +249,7 @@ size_t sg_direct_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += sg_align256(sizeof(double) * nf * nf * (percell ? N : 1));
     o += sg_align256(es * (size_t)S * nf * 2 * N);
     o += sg_align256(sizeof(double) * 2);
+    o += sg_align256(sizeof(double2) * (SG_IND_BLOCKS + 1));
     return o;
 }
 
@@ -211,6 +281,8 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : 1));
     T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 2 * N);
     double *dh = (double *)take(sizeof(double) * 2);
+    double2 *ipart = (double2 *)take(sizeof(double2) * (SG_IND_BLOCKS + 1));
+    double2 *iab = ipart + SG_IND_BLOCKS;
 
     // h lives on the host: pass through a kernel argument copy in device memory
     // is avoided by writing it with a fill kernel.
@@ -247,6 +319,15 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
         }
         SG_HIP(hipGetLastError());
     }
+    const bool ind = (flags & SG_INDIRECT) != 0;
+    if (ind) {
+        int64_t nb = (nf * N + 255) / 256;
+        if (nb > SG_IND_BLOCKS) nb = SG_IND_BLOCKS;
+        hipLaunchKernelGGL(k_indirect_part<T>, dim3((unsigned)nb), dim3(256), 0, s, nr, nphi, nf, lnrmin,
+                           du, dphi, (const double *)dh, sigma, H, ipart);
+        hipLaunchKernelGGL(k_indirect_fin, dim3(1), dim3(64), 0, s, (const double2 *)ipart, (int)nb, iab);
+        SG_HIP(hipGetLastError());
+    }
     DirectArgs<T> A;
     A.nr = nr;
     A.nphi = nphi;
@@ -265,12 +346,13 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     else hipLaunchKernelGGL((k_direct<T, 2>), grid, dim3(256), 0, s, A);
     SG_HIP(hipGetLastError());
     const unsigned nb = (unsigned)((N + 255) / 256);
+    const double2 *indp = ind ? (const double2 *)iab : nullptr;
     if (nf == 1)
         hipLaunchKernelGGL((k_direct_reduce<T, 1>), dim3(nb), dim3(256), 0, s, partial, S, N, self,
-                           percell, with_self, sigma, du * dphi, gr, gp);
+                           percell, with_self, sigma, du * dphi, indp, nphi, gr, gp);
     else
         hipLaunchKernelGGL((k_direct_reduce<T, 2>), dim3(nb), dim3(256), 0, s, partial, S, N, self,
-                           percell, with_self, sigma, du * dphi, gr, gp);
+                           percell, with_self, sigma, du * dphi, indp, nphi, gr, gp);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

@@ -1,6 +1,7 @@
 // sg_fftpath.hip -- sg_field_fft: batched three-pass log-polar FFT
 // convolution, one HIP graph per batch signature.
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <tuple>
@@ -178,6 +179,43 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     p2_issue<NU, NF>(D, m, h, t, sh, K, KN);
     TwRegC<NU, SF> tw;
     tw.load(twu, t);
+    // SG_INDIRECT: the workgroup holding column m = 1 also forms the star's
+    // pull A + i B = sum_a c_a e^{i dphi/2} conj(sum_rows Sigma~_a[row][1])
+    // (c_a: table header) and adds its m = 1 coefficients to g^ of every
+    // target (see ind_add below).  Uniform branch: the whole workgroup takes
+    // part in the reduction.
+    float2 dr = make_float2(0.f, 0.f), dp = make_float2(0.f, 0.f);
+    const bool ind = (D->flags & SG_INDIRECT) && cb <= 1 && 1 < cb + cn;
+    if (ind) {
+        float2 ps = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int p = 0; p < H; ++p) ps = c_add(ps, sh[p]);
+        float2 *red = lds;  // the planes are not in use yet
+        red[threadIdx.x] = ps;
+        __syncthreads();
+        for (int o = T / 2; o > 0; o >>= 1) {
+            if (t < o) red[threadIdx.x] = c_add(red[threadIdx.x], red[threadIdx.x + o]);
+            __syncthreads();
+        }
+        if (m == 1) {
+            const double half = SG_PI / D->nphi;  // dphi / 2
+            const double ce = cos(half), se = sin(half);
+            double A = 0.0, B = 0.0;
+#pragma unroll
+            for (int a = 0; a < NF; ++a) {
+                const float2 S = red[g * S::CT + a * T];
+                const double ca = D->ind[a];
+                // c_a e^{i dphi/2} conj(S)
+                A += ca * (ce * S.x + se * S.y);
+                B += ca * (se * S.x - ce * S.y);
+            }
+            // m = 1 coefficients of -(A cos phi + B sin phi) and
+            // -(-A sin phi + B cos phi): -(A - iB) e^{i dphi/2}/2, -(B + iA) e^{i dphi/2}/2
+            dr = make_float2((float)(-0.5 * (A * ce + B * se)), (float)(-0.5 * (A * se - B * ce)));
+            dp = make_float2((float)(-0.5 * (B * ce - A * se)), (float)(-0.5 * (B * se + A * ce)));
+        }
+        __syncthreads();
+    }
     // forward transform of the own fluid
     {
         float2 v[1][P];
@@ -243,6 +281,13 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
         for (int p = 0; p < P; ++p) acc[cc][p] = pl[cc].ld(t + T * p);
     __syncthreads();
     fft_m<NU, true, 2>(acc, t, pl, tw);
+    if (ind && m == 1) {
+#pragma unroll
+        for (int p = 0; p < H; ++p) {
+            acc[0][p] = c_add(acc[0][p], dr);
+            acc[1][p] = c_add(acc[1][p], dp);
+        }
+    }
     if (g < cn) {
         const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
 #pragma unroll
@@ -520,7 +565,8 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.nr = d.grid.n_r;
         D.nphi = d.grid.n_phi;
         D.nf = d.fluids.n_fluids;
-        D.pad_ = 0;
+        D.ind = (const double *)(tb + offsetof(sg_table_header, ind_coef));
+        D.flags = d.flags;
     }
 }
 

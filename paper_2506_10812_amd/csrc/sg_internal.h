@@ -140,6 +140,7 @@ struct sg_table_header {
     double r_min, r_max;
     double self_r[4];       // self-cell average per pair (double)
     double dself_r[4][2];   // its d/dh_a, d/dh_b
+    double ind_coef[2];     // indirect term: sqrt(2) K_a A_k / r_k^2 per source fluid
     uint64_t total_bytes;
 };
 

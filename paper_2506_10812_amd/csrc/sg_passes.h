@@ -25,7 +25,9 @@ struct DiscDev {
     const float2 *tw_u, *tw_phi;
     float2 *st;             // [F][blk]
     float2 *gh;             // [F][2][blk]
-    int nr, nphi, nf, pad_;
+    const double *ind;      // table header: indirect-term coefficients [F]
+    int nr, nphi, nf;
+    uint32_t flags;
 };
 
 // A job is (disc index, job index inside the disc); disc < 0 marks padding.

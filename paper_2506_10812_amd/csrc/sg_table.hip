@@ -214,10 +214,28 @@ __global__ void k_tab_u(const double2 *B, float2 *dst, int ncol, size_t col_stri
     }
 }
 
+// Header, including the indirect-term coefficient of each source fluid: with
+// H_a = h_a r the star's kernel has d = 1/h_a at every cell, so
+//   sqrt(2) K_a A_k = sqrt(2) pi^{-1/2} h_a^{-3} / 4 F(1 / (4 h_a^2)) du dphi
+// (times Sigma_a[k] e^{i phi_k} in the sum), the same for all cells.
 __global__ void k_header(sg_table_header *hd, sg_table_header proto, const double *selfbuf,
                          int npair, int with_dh)
 {
     sg_table_header h = proto;
+    double w[FQuad<double>::NODES];
+    for (int k = 0; k < FQuad<double>::NODES; ++k) {
+        const double v = (k + 1) * FQuad<double>::STEP;
+        w[k] = exp(-v * v);
+    }
+    const double du = log(proto.r_max / proto.r_min) / proto.n_r;
+    const double dphi = 2.0 * SG_PI / proto.n_phi;
+    for (int a = 0; a < 2; ++a) {
+        h.ind_coef[a] = 0.0;
+        if (a < proto.n_fluids) {
+            const double ha = proto.h[a];
+            h.ind_coef[a] = SG_SQRT2 / SG_SQRT_PI / (4.0 * ha * ha * ha) * sg_F64(0.25 / (ha * ha), w) * du * dphi;
+        }
+    }
     for (int p = 0; p < npair; ++p) {
         h.self_r[p] = selfbuf[p];
         if (with_dh) {

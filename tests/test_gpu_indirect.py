@@ -1,0 +1,121 @@
+"""The indirect term (SG_INDIRECT) through the C ABI against the CPU FP64
+oracle: FFT path (float, 1e-5 relative RMS per fluid and component, and the
+indirect part alone to 1e-5), direct path in double (1e-12 of max |g|) and in
+float, general per-cell H, and the adjoint's refusal."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_10812_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def T(sg):
+    from paper_2506_10812_amd import torch_ops
+    return torch_ops
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2506_10812_amd import workloads
+    return workloads
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _lopsided(w, seed):
+    """The workload's Sigma times an m = 1 lopsidedness, so that the disc pulls
+    the star (an axisymmetric disc has no indirect term)."""
+    rng = np.random.default_rng(seed)
+    nphi = w["n_phi"]
+    phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    w = dict(w)
+    w["sigma"] = w["sigma"] * (1 + 0.3 * np.cos(phi - rng.uniform(0, 2 * np.pi)))[None, None, :]
+    return w
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(16, 32, 1), (32, 64, 2), (64, 128, 2), (4, 8, 2)])
+def test_fft_path_indirect_full_field(sg, T, nr, nphi, nf, W):
+    print(f"indirect term, fft path {nr}x{nphi} nf={nf}", flush=True)
+    base = W.bifluid_fft(seed=nr + 7, n_r=nr, n_phi=nphi) if nf == 2 else \
+        W.single_fft(seed=nr + 7, n_r=nr, n_phi=nphi)
+    w = _lopsided(base, nr)
+    F0 = T.FFTField([w])
+    F1 = T.FFTField([w], flags=sg.INDIRECT)
+    for F in (F0, F1):
+        F.set_sigma(0, w["sigma"])
+        F.run()
+    torch.cuda.synchronize()
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32)
+    AB = O.indirect(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32)
+    ir, ip = O.indirect_field(nr, nphi, AB)
+    gr = F1.g_r[0].double().cpu().numpy().reshape(nf, -1)
+    gp = F1.g_phi[0].double().cpu().numpy().reshape(nf, -1)
+    dr = gr - F0.g_r[0].double().cpu().numpy().reshape(nf, -1)
+    dp = gp - F0.g_phi[0].double().cpu().numpy().reshape(nf, -1)
+    scale = max(np.abs(rr).max(), np.abs(rp).max())
+    for b in range(nf):
+        assert rel_rms(gr[b], rr[b] + ir) < 1e-5, (b, rel_rms(gr[b], rr[b] + ir))
+        assert rel_rms(gp[b], rp[b] + ip) < 1e-5, (b, rel_rms(gp[b], rp[b] + ip))
+        # the indirect part alone (float rounding of g bounds it)
+        assert np.abs(dr[b] - ir).max() < 1e-5 * scale + 1e-5 * np.abs(ir).max()
+        assert np.abs(dp[b] - ip).max() < 1e-5 * scale + 1e-5 * np.abs(ip).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_direct_indirect_general_H(sg, T, dtype):
+    print(f"indirect term, direct path {dtype}, per-cell H", flush=True)
+    nr, nphi, nf = 12, 20, 2
+    rng = np.random.default_rng(17)
+    rmin, rmax = 0.3, 3.0
+    sig = rng.uniform(0.1, 1.0, (nf, nr, nphi))
+    du = np.log(rmax / rmin) / nr
+    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * du)
+    H = (np.array([0.06, 0.02])[:, None, None] * r[None, :, None]) * rng.uniform(0.7, 1.3, (nf, nr, nphi))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    sig_t = torch.tensor(sig, dtype=tdt, device="cuda")
+    H_t = torch.tensor(H, dtype=tdt, device="cuda")
+    g = sg.grid(nr, nphi, rmin, rmax)
+    gr, gp = T.direct(g, None, sig_t, H=H_t, flags=sg.INDIRECT)
+    torch.cuda.synchronize()
+    sig_in = sig_t.double().cpu().numpy()
+    H_in = H_t.double().cpu().numpy()
+    rr, rp = O.field_pairwise(nr, nphi, rmin, rmax, [0.0, 0.0], sig_in, H=H_in)
+    AB = O.indirect(nr, nphi, rmin, rmax, [0.0, 0.0], sig_in, H=H_in)
+    ir, ip = O.indirect_field(nr, nphi, AB)
+    got_r = gr.double().cpu().numpy().reshape(nf, -1)
+    got_p = gp.double().cpu().numpy().reshape(nf, -1)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for b in range(nf):
+        want_r, want_p = rr[b] + ir, rp[b] + ip
+        scale = max(np.abs(want_r).max(), np.abs(want_p).max())
+        err = max(np.abs(got_r[b] - want_r).max(), np.abs(got_p[b] - want_p).max()) / scale
+        assert err < tol, (b, err)
+
+
+def test_adjoint_refuses_indirect(sg, T, W):
+    w = W.adjoint(n_r=8, n_phi=16)
+    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+    f = sg.fluids(w["h"])
+    tab = T.build_table(g, f, sg.WITH_DH | sg.INDIRECT)
+    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda")
+    lam = torch.ones_like(sig)
+    ds = torch.empty_like(sig)
+    disc = sg.make_disc(g, f, sg.WITH_DH | sg.INDIRECT, sig, lam, lam, tab)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sg.SGError):
+        sg.field_adjoint(disc, lam, lam, ds, None, ws)

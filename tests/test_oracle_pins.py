@@ -390,3 +390,83 @@ def test_adjoint_h_equals_central_differences():
         hm[f] -= e
         fd = (loss(hp) - loss(hm)) / (2 * e)
         assert dh[f] == pytest.approx(fd, rel=1e-6)
+
+
+# ------------------------------------------------------------ indirect term
+def _grid_np(nr, nphi, rmin, rmax):
+    du = math.log(rmax / rmin) / nr
+    r = np.exp(math.log(rmin) + (np.arange(nr) + 0.5) * du)
+    phi = (np.arange(nphi) + 0.5) * (2 * math.pi / nphi)
+    return r, phi, du, 2 * math.pi / nphi
+
+
+@pytest.mark.parametrize("r,H", [(1.0, 0.05), (0.3, 0.1), (2.0, 0.4), (1.0, 2.0)])
+def test_indirect_kernel_equals_vertical_integral(r, H):
+    """The star's pull by a vertically Gaussian column (first line of the
+    indirect-term appendix): r' int e^{-z^2/2H^2}/(sqrt(2 pi) H) (r'^2+z^2)^{-3/2} dz,
+    by brute-force quadrature, equals the oracle's sqrt(2) K_a for a one-cell disc."""
+    nr, nphi, rmin = 1, 1, r / math.exp(0.5e-3)
+    rmax = r * math.exp(0.5e-3)
+    sig = np.ones((1, 1, 1))
+    AB = O.indirect(nr, nphi, rmin, rmax, [H / r], sig)
+    rc, phi, du, dphi = _grid_np(nr, nphi, rmin, rmax)
+    mass = rc[0] ** 2 * du * dphi
+    I, _ = si.quad(lambda z: math.exp(-0.5 * (z / H) ** 2) / (math.sqrt(2 * math.pi) * H)
+                   * (rc[0] ** 2 + z * z) ** -1.5, -np.inf, np.inf, epsabs=0, epsrel=1e-13, limit=400)
+    ref = mass * rc[0] * I
+    got = math.hypot(AB[0, 0], AB[0, 1])
+    assert abs(got / ref - 1) < 1e-11, (got, ref)
+    assert abs(math.atan2(AB[0, 1], AB[0, 0]) - phi[0]) < 1e-12
+
+
+def test_indirect_kernel_is_pair_kernel_with_point_target():
+    """sqrt(2) K_a(d_a) equals the pair kernel K_ab(s = r'; H_a, H_b = 0) (the
+    star has no thickness): one-cell disc at several radii and heights."""
+    rng = np.random.default_rng(11)
+    for _ in range(8):
+        nr, nphi = 3, 5
+        rmin, rmax = rng.uniform(0.2, 1.0), rng.uniform(2.0, 6.0)
+        h = rng.uniform(0.01, 0.5)
+        i, j = rng.integers(nr), rng.integers(nphi)
+        sig = np.zeros((1, nr, nphi))
+        sig[0, i, j] = 1.0
+        AB = O.indirect(nr, nphi, rmin, rmax, [h], sig)
+        r, phi, du, dphi = _grid_np(nr, nphi, rmin, rmax)
+        ref = r[i] ** 2 * du * dphi * O.kernel(r[i], h * r[i], 0.0)[0]
+        assert abs(AB[0, 0] - ref * math.cos(phi[j])) < 1e-13 * ref
+        assert abs(AB[0, 1] - ref * math.sin(phi[j])) < 1e-13 * ref
+
+
+def test_indirect_vanishes_for_axisymmetric_disc_and_rotates():
+    nr, nphi = 16, 32
+    r, phi, _, _ = _grid_np(nr, nphi, 0.2, 5.0)
+    sig = np.broadcast_to((r ** -1.0)[:, None], (nr, nphi))[None].copy()
+    AB = O.indirect(nr, nphi, 0.2, 5.0, [0.05], sig)
+    scale = O.indirect(nr, nphi, 0.2, 5.0, [0.05], np.abs(sig) * (np.cos(phi) > 0))[0, 0]
+    assert np.all(np.abs(AB) < 1e-13 * scale)
+    # rotation by s cells multiplies A + iB by exp(i s dphi)
+    rng = np.random.default_rng(3)
+    sig = rng.uniform(0.5, 1.5, (2, nr, nphi))
+    s = 5
+    a = O.indirect(nr, nphi, 0.2, 5.0, [0.05, 0.01], sig)
+    b = O.indirect(nr, nphi, 0.2, 5.0, [0.05, 0.01], np.roll(sig, s, axis=2))
+    za = a[:, 0] + 1j * a[:, 1]
+    zb = b[:, 0] + 1j * b[:, 1]
+    np.testing.assert_allclose(zb, za * np.exp(1j * s * 2 * math.pi / nphi), rtol=1e-12)
+
+
+@pytest.mark.parametrize("h", [0.02, 0.005])
+def test_indirect_point_mass_limit_and_next_term(h):
+    """Thin-disc limit: sqrt(2) K_a -> 1/r'^2 (Newtonian point masses), with the
+    relative correction -3/8 / x + 45/128 / x^2 at x = 1/(4 h^2) (the printed
+    large-x expansion of Sect. 5.3 applied to the star's kernel)."""
+    nr, nphi = 12, 24
+    rng = np.random.default_rng(5)
+    sig = rng.uniform(0.0, 1.0, (1, nr, nphi))
+    r, phi, du, dphi = _grid_np(nr, nphi, 0.3, 3.0)
+    AB = O.indirect(nr, nphi, 0.3, 3.0, [h], sig)
+    m = sig[0] * (r ** 2)[:, None] * du * dphi
+    newton = np.array([(m * np.cos(phi) / (r ** 2)[:, None]).sum(), (m * np.sin(phi) / (r ** 2)[:, None]).sum()])
+    x = 1 / (4 * h * h)
+    corr = 1 - 3 / 8 / x + 45 / 128 / x ** 2
+    np.testing.assert_allclose(AB[0], newton * corr, rtol=3 * (525 / 1024) / x ** 3 + 1e-13)
