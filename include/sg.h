@@ -222,6 +222,39 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h,
                           void *stream);
 
 /* ---------------------------------------------------------------------
+ * sg_potential_direct: the conservative 2D potential of Sect. 5.5 (appendix
+ * "Conservative force"), summed directly:
+ *   Phi_b(x_i) = sum_a sum_{k != i} Sigma_a[k] A_k P_ab(|x_i - x_k|)
+ *              + sum_a Sigma_a[i] int_{own cell} P_ab dA,
+ *   P_ab(s)    = -e^y K0(y) / (2 sqrt(pi) H_ab),  y = s^2 / (8 H_ab^2),
+ * with H_ab^2 = (H_a^2 + H_b^2)/2 from the source cell's H_a and the
+ * target cell's H_b (the own-cell integral, a reading, uses the cell's
+ * H_a and H_b).  The paper derives Phi for spatially constant H, where
+ * -grad Phi_ab is the field of sg_field_direct; pass d_H filled with
+ * constants for that case (d_H == NULL uses H_f = h[f] r).  d_pot: device
+ * array [F][n_r][n_phi] of sigma's dtype.  Float: float arithmetic and
+ * accumulation, self integrals in double.  flags: SG_SELF_CELL_EXCLUDE.
+ * Sizes and workspace as for sg_field_direct.
+ * --------------------------------------------------------------------- */
+size_t sg_potential_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
+                                           int per_cell_H);
+sg_status sg_potential_direct(const sg_grid *grid, int n_fluids, const double *h,
+                              const void *d_sigma, const void *d_H, void *d_pot, sg_dtype dtype,
+                              uint32_t flags, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * sg_hsg: self-gravitating scale heights (Sect. 2.1, stratification
+ * parameters) for the H input of sg_field_direct / sg_potential_direct:
+ *   H_f^sg = sqrt(2/pi) H_f f(Qt),  Qt = (sum_f 1/Q_f)^-1,
+ *   f(x) = pi/(4x) [sqrt(1 + 8 x^2/pi) - 1],
+ * H_f the thermal (gas) or diffusive (dust) scale height, Q_f the Toomre
+ * parameter c_f Omega_K / (pi G Sigma_f) of each fluid.  Device double
+ * arrays [n_fluids][n] (n cells); Q_f > 0.  Double arithmetic.
+ * --------------------------------------------------------------------- */
+sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, double *d_Hsg,
+                 void *stream);
+
+/* ---------------------------------------------------------------------
  * sg_field_adjoint: reverse-mode derivative of sg_field_fft for one disc.
  * Given lam_r = dL/dg_r and lam_phi = dL/dg_phi (float device arrays
  * [F][n_r][n_phi]) it returns
@@ -245,6 +278,11 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
  * --------------------------------------------------------------------- */
 sg_status sg_eval_F(const void *d_x, void *d_F, void *d_dF, int64_t n, sg_dtype dtype,
                     void *stream);
+
+/* Device-side evaluation of G0(y) = e^y K0(y) (the kernel of the
+ * conservative potential, sg_potential_direct) for testing: d_x, d_G device
+ * arrays of n values in `dtype`. */
+sg_status sg_eval_G0(const void *d_x, void *d_G, int64_t n, sg_dtype dtype, void *stream);
 
 /* Self-cell term for a list of (h_a, h_b) pairs on one grid: d_out[i] =
  * principal-value average of the log-polar radial kernel K_r over the own

@@ -67,6 +67,22 @@ def lib():
         L.sg_oracle_adjoint_sigma.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, _dp]
+        L.sg_oracle_G0.restype = ctypes.c_double
+        L.sg_oracle_G0.argtypes = [ctypes.c_double]
+        L.sg_oracle_potential_kernel.restype = ctypes.c_double
+        L.sg_oracle_potential_kernel.argtypes = [ctypes.c_double] * 3
+        L.sg_oracle_potential_self.restype = ctypes.c_double
+        L.sg_oracle_potential_self.argtypes = [ctypes.c_double] * 5
+        L.sg_oracle_potential_pairwise.restype = ctypes.c_int
+        L.sg_oracle_potential_pairwise.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            _dp, _dp, _dp, ctypes.c_int64, _i64p, ctypes.c_uint, _dp]
+        L.sg_oracle_point_fields.restype = ctypes.c_int
+        L.sg_oracle_point_fields.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+            ctypes.c_double, _dp, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.sg_oracle_hsg.restype = None
+        L.sg_oracle_hsg.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, _dp]
         L.sg_oracle_indirect.restype = ctypes.c_int
         L.sg_oracle_indirect.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -213,6 +229,61 @@ def adjoint_h(nr, nphi, rmin, rmax, h, sigma, lam_r, lam_phi, flags=0):
                 v = float(np.sum(lam[b] * out[a, b]))
                 dh[a if role == "a" else b] += v
     return dh
+
+
+def G0(y):
+    """e^y K0(y) (vectorised)."""
+    y = np.atleast_1d(np.asarray(y, dtype=np.float64))
+    L = lib()
+    return np.array([L.sg_oracle_G0(float(v)) for v in y.ravel()]).reshape(y.shape)
+
+
+def potential_kernel(s, Ha, Hb):
+    return np.array([lib().sg_oracle_potential_kernel(float(v), float(Ha), float(Hb))
+                     for v in np.atleast_1d(s)])
+
+
+def potential_self(r, Ha, Hb, du, dphi):
+    return lib().sg_oracle_potential_self(float(r), float(Ha), float(Hb), float(du), float(dphi))
+
+
+def potential_pairwise(nr, nphi, rmin, rmax, h, sigma, H=None, targets=None, flags=0):
+    """Potential at cell centres per target fluid: array [nf][n_targets]."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    h = _d(np.atleast_1d(h))
+    Hd = None if H is None else _d(H)
+    t = _targets(targets)
+    nt = nr * nphi if t is None else t.size
+    pot = np.empty((nf, nt))
+    rc = lib().sg_oracle_potential_pairwise(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(Hd), _ptr(sigma),
+                                            nt, _iptr(t), flags, _ptr(pot))
+    if rc:
+        raise RuntimeError(f"sg_oracle_potential_pairwise failed ({rc})")
+    return pot
+
+
+def point_fields(nr, nphi, rmin, rmax, Ha, Hb, sigma, px, py):
+    """(Phi, g_x, g_y) of one source fluid at arbitrary points, constant H."""
+    sigma = _d(sigma)
+    px = _d(px)
+    py = _d(py)
+    n = px.size
+    pot, gx, gy = np.empty(n), np.empty(n), np.empty(n)
+    rc = lib().sg_oracle_point_fields(nr, nphi, rmin, rmax, Ha, Hb, _ptr(sigma), n, _ptr(px), _ptr(py),
+                                      _ptr(pot), _ptr(gx), _ptr(gy))
+    if rc:
+        raise RuntimeError(f"sg_oracle_point_fields failed ({rc})")
+    return pot, gx, gy
+
+
+def hsg(H, Q):
+    """Self-gravitating scale heights from H [F][n] and Toomre parameters Q [F][n]."""
+    H = _d(np.atleast_2d(H))
+    Q = _d(np.atleast_2d(Q))
+    out = np.empty_like(H)
+    lib().sg_oracle_hsg(H.shape[1], H.shape[0], _ptr(H), _ptr(Q), _ptr(out))
+    return out
 
 
 def indirect(nr, nphi, rmin, rmax, h, sigma, H=None):

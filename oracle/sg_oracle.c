@@ -309,6 +309,192 @@ static double orc_self_memo(orc_memo *m, int nm, double ha, double hb, double du
 }
 
 /* ------------------------------------------------------------------------
+ * Conservative potential (Sect. 5.5 and the appendix "Conservative force"):
+ * for spatially constant H_a, H_b the field of fluid a on fluid b is
+ * -grad Phi_ab with
+ *   Phi_ab(x) = sum over the disc of Sigma_a A P_ab(|x - x'|),
+ *   P_ab(s)   = - e^y K0(y) / (2 sqrt(pi) H_ab),  y = d^2/8,  d = s/H_ab.
+ * e^y K0(y) is evaluated like F: from K_0(y) = int_0^inf exp(-y cosh t) dt
+ * (Abramowitz & Stegun 9.6.24), G0(y) = int_0^inf exp(-y c(t)) dt with the
+ * same trapezoidal rule (the t = 0 node has value 1 and weight h/2).
+ * Parity pinned against mpmath Bessel values, the Newtonian limit -1/s and
+ * the gradient: -grad Phi equals the pairwise field (tests).
+ * ------------------------------------------------------------------------ */
+double sg_oracle_G0(double y)
+{
+    double h = 0.2;
+    if (0.4 / sqrt(y) < h) h = 0.4 / sqrt(y);
+    double T = 2.0 * asinh(sqrt(30.0 / y));
+    long n = (long)ceil(T / h);
+    double sum = 0.5;
+    for (long k = 1; k <= n; ++k) {
+        double sh = sinh(0.5 * (double)k * h);
+        sum += exp(-y * 2.0 * sh * sh);
+    }
+    return h * sum;
+}
+
+double sg_oracle_potential_kernel(double s, double Ha, double Hb)
+{
+    double Hab = sqrt(0.5 * (Ha * Ha + Hb * Hb));
+    double d = s / Hab;
+    return -sg_oracle_G0(d * d / 8.0) / (2.0 * ORC_SQRT_PI * Hab);
+}
+
+/* Self term of the potential (reading: the paper does not treat k = i): the
+ * integral of P_ab(|x_i - x'|) over the own cell, x' = r e^X (cos phi,
+ * sin phi) relative to the centre direction, |x_i - x'|^2 =
+ * r^2 e^X (4 sinh^2(X/2) + 4 sin^2(phi/2)), dA' = r^2 e^{2X} dX dphi,
+ * |X| <= du/2, |phi| <= dphi/2, with the cell's own H_a, H_b.  The log
+ * singularity at the centre is integrated in polar coordinates about it
+ * (four quadrants, two triangles each, as the force self term). */
+static double orc_pot_integrand(double X, double phi, double r, double Ha, double Hb)
+{
+    double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
+    double s = r * sqrt(exp(X) * 4.0 * (sx * sx + sp * sp));
+    return sg_oracle_potential_kernel(s, Ha, Hb) * r * r * exp(2.0 * X);
+}
+
+double sg_oracle_potential_self(double r, double Ha, double Hb, double du, double dphi)
+{
+    orc_gl_init();
+    const double a = 0.5 * du, b = 0.5 * dphi;
+    const double thc = atan2(b, a);
+    double total = 0.0;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {  /* X < 0 and X > 0; phi: even, doubled */
+        for (int tri = 0; tri < 2; ++tri) {
+            double th0 = tri == 0 ? 0.0 : thc;
+            double th1 = tri == 0 ? thc : 0.5 * ORC_PI;
+            double acc = 0.0;
+            for (int i = 0; i < ORC_GL_N; ++i) {
+                double th = th0 + (th1 - th0) * orc_gl_x[i];
+                double c = cos(th), sn = sin(th);
+                double rmax = tri == 0 ? a / c : b / sn;
+                double inner = 0.0;
+                for (int pnl = 0; pnl < ORC_PANELS; ++pnl) {
+                    double hi = pow(4.0, -(double)(ORC_PANELS - 1 - pnl));
+                    double lo = pnl == 0 ? 0.0 : hi / 4.0;
+                    double part = 0.0;
+                    for (int j = 0; j < ORC_GLR_N; ++j) {
+                        double rho = rmax * (lo + (hi - lo) * orc_glr_x[j]);
+                        part += orc_glr_w[j] * rho * orc_pot_integrand(sgn * rho * c, rho * sn, r, Ha, Hb);
+                    }
+                    inner += part * (hi - lo) * rmax;
+                }
+                acc += orc_gl_w[i] * inner;
+            }
+            total += 2.0 * acc * (th1 - th0);
+        }
+    }
+    return total;
+}
+
+/* Potential at cell centres, per target fluid b:
+ *   Phi_b(i) = sum_a sum_{k != i} Sigma_a[k] A_k P_ab(s_ik; H_a[k], H_b[i])
+ *            + sum_a Sigma_a[i] (self integral with H_a[i], H_b[i]),
+ * the self part unless excluded (flag bit 0).  H == NULL: H_f = h[f] r
+ * (for which -grad Phi is not the field; the gradient identity needs
+ * constant H).  Output pot: [n_fluids][n_targets]. */
+int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
+                                 const double *h, const double *H, const double *sigma,
+                                 int64_t nt, const int64_t *targets, unsigned flags, double *pot)
+{
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    const int64_t N = (int64_t)nr * nphi;
+    for (int64_t ti = 0; ti < nt; ++ti)
+        if (targets && (targets[ti] < 0 || targets[ti] >= N)) return 2;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t ti = 0; ti < nt; ++ti) {
+        const int64_t i = targets ? targets[ti] : ti;
+        const int ir = (int)(i / nphi), jr = (int)(i % nphi);
+        const double ri = orc_r(&g, ir), pi_ = orc_phi(&g, jr);
+        const double xi = ri * cos(pi_), yi = ri * sin(pi_);
+        for (int b = 0; b < nf; ++b) {
+            const double Hb = H ? H[(int64_t)b * N + i] : h[b] * ri;
+            double acc = 0.0;
+            for (int a = 0; a < nf; ++a) {
+                for (int kr = 0; kr < nr; ++kr) {
+                    const double rk = orc_r(&g, kr);
+                    const double area = rk * rk * g.du * g.dphi;
+                    for (int kp = 0; kp < nphi; ++kp) {
+                        const int64_t k = (int64_t)kr * nphi + kp;
+                        if (k == i) continue;
+                        const double pk = orc_phi(&g, kp);
+                        const double dx = xi - rk * cos(pk), dy = yi - rk * sin(pk);
+                        const double Ha = H ? H[(int64_t)a * N + k] : h[a] * rk;
+                        acc += sigma[(int64_t)a * N + k] * area *
+                               sg_oracle_potential_kernel(sqrt(dx * dx + dy * dy), Ha, Hb);
+                    }
+                }
+                if (!(flags & ORC_FLAG_EXCLUDE_SELF)) {
+                    const double Ha = H ? H[(int64_t)a * N + i] : h[a] * ri;
+                    acc += sigma[(int64_t)a * N + i] * sg_oracle_potential_self(ri, Ha, Hb, g.du, g.dphi);
+                }
+            }
+            pot[(int64_t)b * nt + ti] = acc;
+        }
+    }
+    return 0;
+}
+
+/* Potential and Cartesian field of one source fluid at arbitrary points
+ * (px, py), constant H_a (source) and H_b (target), summed over all source
+ * cells (points must not coincide with a cell centre):
+ *   Phi(p) = sum_k Sigma[k] A_k P_ab(|p - x_k|),
+ *   g(p)   = - sum_k Sigma[k] A_k K_ab(|p - x_k|) (p - x_k)/|p - x_k|.
+ * For the gradient identity -grad Phi = g of the conservative case. */
+int sg_oracle_point_fields(int nr, int nphi, double rmin, double rmax, double Ha, double Hb,
+                           const double *sigma, int64_t np, const double *px, const double *py,
+                           double *pot, double *gx, double *gy)
+{
+    if (nr < 1 || nphi < 1 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < np; ++q) {
+        double P = 0.0, X = 0.0, Y = 0.0;
+        for (int kr = 0; kr < nr; ++kr) {
+            const double rk = orc_r(&g, kr);
+            const double area = rk * rk * g.du * g.dphi;
+            for (int kp = 0; kp < nphi; ++kp) {
+                const double pk = orc_phi(&g, kp);
+                const double dx = px[q] - rk * cos(pk), dy = py[q] - rk * sin(pk);
+                const double s = sqrt(dx * dx + dy * dy);
+                const double m = sigma[(int64_t)kr * nphi + kp] * area;
+                P += m * sg_oracle_potential_kernel(s, Ha, Hb);
+                const double K = sg_oracle_kernel(s, Ha, Hb);
+                X -= m * K * dx / s;
+                Y -= m * K * dy / s;
+            }
+        }
+        pot[q] = P;
+        gx[q] = X;
+        gy[q] = Y;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Self-gravitating scale heights (Sect. 2.1, stratification parameters):
+ *   H_f^sg = sqrt(2/pi) H_f f(Qt),  Qt = (sum_f 1/Q_f)^-1,
+ *   f(x) = pi/(4x) [sqrt(1 + 8 x^2/pi) - 1],
+ * written out as printed (no rearrangement).  Arrays [F][n].  Parity pinned
+ * by the limits f -> sqrt(pi/2) (no self-gravity: H^sg -> H) and f ~ x
+ * (strong self-gravity), and by f being the positive root of
+ * (2x/pi) f^2 + f - x = 0 (tests).
+ * ------------------------------------------------------------------------ */
+void sg_oracle_hsg(int64_t n, int nf, const double *H, const double *Q, double *Hsg)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double inv = 0.0;
+        for (int f = 0; f < nf; ++f) inv += 1.0 / Q[(int64_t)f * n + i];
+        double x = 1.0 / inv;
+        double fx = ORC_PI / (4.0 * x) * (sqrt(1.0 + 8.0 * x * x / ORC_PI) - 1.0);
+        for (int f = 0; f < nf; ++f) Hsg[(int64_t)f * n + i] = sqrt(2.0 / ORC_PI) * H[(int64_t)f * n + i] * fx;
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Indirect term (Sect. 5.4 "Indirect term" and the appendix of the same
  * name): the pull of fluid a on the star, in the form derived there,
  *   A_a = sqrt(2) sum_k Sigma_a[k] A_k K_a(d_k) cos(phi_k),

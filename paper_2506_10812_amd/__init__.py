@@ -82,6 +82,10 @@ def _load():
         "sg_field_adjoint_workspace_bytes": (sz, [DP]),
         "sg_field_adjoint": (i32, [DP, vp, vp, vp, vp, vp, sz, vp]),
         "sg_eval_F": (i32, [vp, vp, vp, i64, i32, vp]),
+        "sg_eval_G0": (i32, [vp, vp, i64, i32, vp]),
+        "sg_hsg": (i32, [i64, i32, vp, vp, vp, vp]),
+        "sg_potential_direct_workspace_bytes": (sz, [GP, i32, i32, i32]),
+        "sg_potential_direct": (i32, [GP, i32, dp, vp, vp, vp, i32, u32, vp, sz, vp]),
         "sg_self_cell": (i32, [GP, dp, dp, i32, i32, vp, vp]),
         "sg_release": (None, []),
         "sg_status_string": (ctypes.c_char_p, [i32]),
@@ -99,7 +103,8 @@ EXPORTED = (
     "sg_kernel_table_bytes", "sg_kernel_table_workspace_bytes", "sg_kernel_table",
     "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile", "sg_field_fft_tune",
     "sg_field_direct_workspace_bytes",
-    "sg_field_direct", "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_eval_F",
+    "sg_field_direct", "sg_potential_direct_workspace_bytes", "sg_potential_direct",
+    "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_eval_F", "sg_eval_G0", "sg_hsg",
     "sg_self_cell", "sg_release", "sg_status_string", "sg_version")
 
 
@@ -216,6 +221,30 @@ def field_direct(g: Grid, n_fluids, h, sigma, H, g_r, g_phi, dtype, flags, ws, w
                                 ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,
                                 _ptr(sigma), _ptr(H), _ptr(g_r), _ptr(g_phi), dtype, flags,
                                 _ptr(ws), ws_bytes, _stream(stream)), "sg_field_direct")
+
+
+def potential_direct_workspace_bytes(g: Grid, n_fluids, dtype, per_cell_H) -> int:
+    return int(_lib.sg_potential_direct_workspace_bytes(ctypes.byref(g), n_fluids, dtype,
+                                                        1 if per_cell_H else 0))
+
+
+def potential_direct(g: Grid, n_fluids, h, sigma, H, pot, dtype, flags, ws, ws_bytes=None, stream=None):
+    harr = (ctypes.c_double * 2)(*([float(v) for v in h] + [0.0] * (2 - len(h)))) if h is not None else None
+    ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.sg_potential_direct(ctypes.byref(g), n_fluids,
+                                    ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,
+                                    _ptr(sigma), _ptr(H), _ptr(pot), dtype, flags, _ptr(ws), ws_bytes,
+                                    _stream(stream)), "sg_potential_direct")
+
+
+def hsg(H, Q, out, stream=None):
+    """sg_hsg on [F][n] float64 device tensors."""
+    nf, n = H.shape
+    _check(_lib.sg_hsg(n, nf, _ptr(H), _ptr(Q), _ptr(out), _stream(stream)), "sg_hsg")
+
+
+def eval_G0(x, G, dtype, stream=None):
+    _check(_lib.sg_eval_G0(_ptr(x), _ptr(G), x.numel(), dtype, _stream(stream)), "sg_eval_G0")
 
 
 def field_adjoint(disc: Disc, lam_r, lam_phi, dsigma, dh, ws, ws_bytes=None, stream=None):

@@ -141,6 +141,50 @@ size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dty
     return sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, per_cell_H ? 1 : 0);
 }
 
+size_t sg_potential_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
+                                           int per_cell_H)
+{
+    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    if (dtype != SG_F32 && dtype != SG_F64) return 0;
+    return sg_potential_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, per_cell_H ? 1 : 0);
+}
+
+sg_status sg_potential_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
+                              const void *d_H, void *d_pot, sg_dtype dtype, uint32_t flags, void *d_ws,
+                              size_t ws_bytes, void *stream)
+{
+    sg_status s = check_grid(grid);
+    if (s != SG_OK) return s;
+    if (n_fluids < 1 || n_fluids > 2) return SG_ERR_ARG;
+    if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
+    if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
+    if (!d_sigma || !d_pot) return SG_ERR_ARG;
+    if ((flags & ~(uint32_t)SG_SELF_CELL_EXCLUDE) != 0) return SG_ERR_ARG;
+    if (!d_H) {
+        if (!h) return SG_ERR_ARG;
+        for (int f = 0; f < n_fluids; ++f)
+            if (!finite_pos(h[f])) return SG_ERR_ARG;
+    }
+    const size_t need = sg_potential_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, d_H ? 1 : 0);
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    return sg_potential_launch(grid, n_fluids, d_H ? nullptr : h, d_sigma, d_H, d_pot, dtype, flags, d_ws,
+                               (hipStream_t)stream);
+}
+
+sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, double *d_Hsg, void *stream)
+{
+    if (n < 0 || n_fluids < 1 || n_fluids > 2 || !d_H || !d_Q || !d_Hsg) return SG_ERR_ARG;
+    if (n == 0) return SG_OK;
+    return sg_hsg_launch(n, n_fluids, d_H, d_Q, d_Hsg, (hipStream_t)stream);
+}
+
+sg_status sg_eval_G0(const void *d_x, void *d_G, int64_t n, sg_dtype dtype, void *stream)
+{
+    if (!d_x || !d_G || n < 0 || (dtype != SG_F32 && dtype != SG_F64)) return SG_ERR_ARG;
+    if (n == 0) return SG_OK;
+    return sg_eval_G0_launch(d_x, d_G, n, dtype, (hipStream_t)stream);
+}
+
 sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
                           const void *d_H, void *d_g_r, void *d_g_phi, sg_dtype dtype,
                           uint32_t flags, void *d_ws, size_t ws_bytes, void *stream)

@@ -225,6 +225,112 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
     }
 }
 
+// --------------------------------------------------------------- potential
+// Conservative potential (Sect. 5.5, appendix "Conservative force"):
+//   Phi_b(i) = sum_a sum_{k != i} Sigma_a[k] A_k P_ab(s_ik),
+//   P_ab(s) = -e^y K0(y) / (2 sqrt(pi) H_ab),  y = s^2/(8 H_ab^2),
+// H_ab from the source cell's H_a and the target cell's H_b; the own cell
+// adds Sigma_a[i] times the cell integral of P_ab (k_pot_self).  Same
+// layout and splitting as the field sum; one accumulator per target fluid.
+template <typename T> __device__ inline T sg_G0_any(T x, const T *w);
+template <> __device__ inline double sg_G0_any<double>(double x, const double *w) { return sg_G0_64(x, w); }
+template <> __device__ inline float sg_G0_any<float>(float x, const float *w) { return sg_G0_32(x, w); }
+
+template <typename T, int NF>
+__global__ void __launch_bounds__(256) k_potential(DirectArgs<T> A)
+{
+    __shared__ T wq[FQuad<T>::NODES];
+    sg_fill_weights<T>(wq);
+    __syncthreads();
+    const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (t >= A.N) return;
+    const int nphi = A.nphi, nr = A.nr;
+    const int ir = (int)(t / nphi), j = (int)(t % nphi);
+    const T ri = A.rrow[ir];
+    T hb2[NF], acc[NF];
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+        hb2[b] = A.H2[b * A.N + t];
+        acc[b] = T(0);
+    }
+    const T c2 = T(-0.5 / SG_SQRT_PI);
+    const int r0 = blockIdx.y * A.rps;
+    const int r1 = min(nr, r0 + A.rps);
+    for (int kr = r0; kr < r1; ++kr) {
+        const int p = ir - kr + nr - 1;
+        const T SX = A.sx[p];
+        const T rr = ri * A.rrow[kr];
+        const int64_t kbase = (int64_t)kr * nphi;
+        for (int l = 0; l < nphi; ++l) {
+            const int64_t k = kbase + l;
+            int q = j - l;
+            q += q < 0 ? nphi : 0;
+            const T s2 = rr * (SX + A.sph[q]);
+            const bool self = (k == t);
+#pragma unroll
+            for (int a = 0; a < NF; ++a) {
+                const T m = A.mass[a * A.N + k] * c2;
+                const T ha2 = A.H2[a * A.N + k];
+#pragma unroll
+                for (int b = 0; b < NF; ++b) {
+                    const T H2ab = T(0.5) * (ha2 + hb2[b]);
+                    const T y = s2 * T(0.125) / H2ab;
+                    const T G = self ? T(0) : sg_G0_any<T>(self ? T(1) : y, wq);
+                    acc[b] += m * G * rsqrt(H2ab);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NF; ++b) A.partial[((int64_t)(blockIdx.y * NF + b)) * A.N + t] = acc[b];
+}
+
+template <typename T, int NF>
+__global__ void k_potential_reduce(const T *partial, int S, int64_t N, int nphi, const double *self,
+                                   int per_row, int with_self, const T *sigma, T *pot)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int64_t si = per_row ? t / nphi : t;
+    const int64_t per = per_row ? N / nphi : N;
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+        T sum = T(0);
+        for (int s = 0; s < S; ++s) sum += partial[((int64_t)(s * NF + b)) * N + t];
+        if (with_self) {
+            double st = 0.0;
+#pragma unroll
+            for (int a = 0; a < NF; ++a) st += (double)sigma[a * N + t] * self[(int64_t)(a * NF + b) * per + si];
+            sum += (T)st;
+        }
+        pot[b * N + t] = sum;
+    }
+}
+
+// -------------------------------------------- self-gravitating scale heights
+// H_f^sg = sqrt(2/pi) H_f f(Qt), Qt = (sum_f 1/Q_f)^-1 (Sect. 2.1), with
+// f(x) = pi/(4x) [sqrt(1 + 8x^2/pi) - 1] evaluated as the equal
+// 2x / (sqrt(1 + 8x^2/pi) + 1), which does not cancel at small x.
+__global__ void k_hsg(int64_t n, int nf, const double *H, const double *Q, double *Hsg)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double inv = 0.0;
+        for (int f = 0; f < nf; ++f) inv += 1.0 / Q[f * n + i];
+        const double x = 1.0 / inv;
+        const double fx = 2.0 * x / (sqrt(1.0 + 8.0 * x * x / SG_PI) + 1.0);
+        for (int f = 0; f < nf; ++f) Hsg[f * n + i] = sqrt(2.0 / SG_PI) * H[f * n + i] * fx;
+    }
+}
+
+sg_status sg_hsg_launch(int64_t n, int nf, const double *H, const double *Q, double *Hsg, hipStream_t s)
+{
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_hsg, dim3((unsigned)nb), dim3(256), 0, s, n, nf, H, Q, Hsg);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
 // ------------------------------------------------------------------- host
 static int direct_splits(int nr, int64_t N)
 {
@@ -355,6 +461,111 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
                            percell, with_self, sigma, du * dphi, indp, nphi, gr, gp);
     SG_HIP(hipGetLastError());
     return SG_OK;
+}
+
+size_t sg_potential_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
+{
+    const size_t es = dt == SG_F64 ? 8 : 4;
+    const int64_t N = (int64_t)nr * nphi;
+    const int S = direct_splits(nr, N);
+    size_t o = 0;
+    o += sg_align256(es * nr);
+    o += 2 * sg_align256(es * (2 * (size_t)nr - 1));
+    o += 2 * sg_align256(es * nphi);
+    o += 2 * sg_align256(es * nf * N);
+    o += sg_align256(sizeof(double) * nf * nf * (percell ? N : nr));
+    o += sg_align256(es * (size_t)S * nf * N);
+    o += sg_align256(sizeof(double) * 2);
+    return o;
+}
+
+template <typename T>
+static sg_status potential_run(const sg_grid *g, int nf, const double *h, const T *sigma, const T *H,
+                               T *pot, uint32_t flags, void *ws, hipStream_t s)
+{
+    const int nr = g->n_r, nphi = g->n_phi;
+    const int64_t N = (int64_t)nr * nphi;
+    const double du = log(g->r_max / g->r_min) / nr;
+    const double dphi = 2.0 * SG_PI / nphi;
+    const double lnrmin = log(g->r_min);
+    const int S = direct_splits(nr, N);
+    const int rps = (nr + S - 1) / S;
+    char *o = (char *)ws;
+    auto take = [&](size_t bytes) {
+        char *p = o;
+        o += sg_align256(bytes);
+        return p;
+    };
+    T *rrow = (T *)take(sizeof(T) * nr);
+    T *sx = (T *)take(sizeof(T) * (2 * (size_t)nr - 1));
+    T *ex = (T *)take(sizeof(T) * (2 * (size_t)nr - 1));
+    T *sph = (T *)take(sizeof(T) * nphi);
+    T *snp = (T *)take(sizeof(T) * nphi);
+    T *mass = (T *)take(sizeof(T) * nf * N);
+    T *H2 = (T *)take(sizeof(T) * nf * N);
+    const int percell = H != nullptr;
+    double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : nr));
+    T *partial = (T *)take(sizeof(T) * (size_t)S * nf * N);
+    double *dh = (double *)take(sizeof(double) * 2);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh, (int64_t)1, h ? h[0] : 0.0);
+    if (nf > 1) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + 1, (int64_t)1, h ? h[1] : 0.0);
+    SG_HIP(hipGetLastError());
+    {
+        int64_t work = nf * N > 2 * nr ? nf * N : 2 * nr;
+        if (work < nphi) work = nphi;
+        int64_t nb = (work + 255) / 256;
+        if (nb > 65536) nb = 65536;
+        hipLaunchKernelGGL(k_direct_prep<T>, dim3((unsigned)nb), dim3(256), 0, s, nr, nphi, nf,
+                           lnrmin, du, dphi, (const double *)dh, sigma, H, rrow, sx, ex, sph, snp,
+                           mass, H2);
+        SG_HIP(hipGetLastError());
+    }
+    const int with_self = !(flags & SG_SELF_CELL_EXCLUDE);
+    if (with_self) {
+        GLNodes gl;
+        sg_gl_nodes(gl);
+        const int64_t items = (int64_t)nf * nf * (percell ? N : nr);
+        hipLaunchKernelGGL(k_pot_self<T>, dim3((unsigned)items), dim3(256), 0, s, H, (const double *)dh, nf,
+                           nr, nphi, lnrmin, du, dphi, percell ? 0 : 1, self, gl);
+        SG_HIP(hipGetLastError());
+    }
+    DirectArgs<T> A;
+    A.nr = nr;
+    A.nphi = nphi;
+    A.rps = rps;
+    A.N = N;
+    A.rrow = rrow;
+    A.sx = sx;
+    A.ex = ex;
+    A.sph = sph;
+    A.snp = snp;
+    A.mass = mass;
+    A.H2 = H2;
+    A.partial = partial;
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)S);
+    if (nf == 1) hipLaunchKernelGGL((k_potential<T, 1>), grid, dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_potential<T, 2>), grid, dim3(256), 0, s, A);
+    SG_HIP(hipGetLastError());
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    if (nf == 1)
+        hipLaunchKernelGGL((k_potential_reduce<T, 1>), dim3(nb), dim3(256), 0, s, partial, S, N, nphi, self,
+                           percell ? 0 : 1, with_self, sigma, pot);
+    else
+        hipLaunchKernelGGL((k_potential_reduce<T, 2>), dim3(nb), dim3(256), 0, s, partial, S, N, nphi, self,
+                           percell ? 0 : 1, with_self, sigma, pot);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+sg_status sg_potential_launch(const sg_grid *g, int nf, const double *h, const void *sigma,
+                              const void *H, void *pot, sg_dtype dt, uint32_t flags, void *ws,
+                              hipStream_t s)
+{
+    if (dt == SG_F64)
+        return potential_run<double>(g, nf, h, (const double *)sigma, (const double *)H, (double *)pot,
+                                     flags, ws, s);
+    return potential_run<float>(g, nf, h, (const float *)sigma, (const float *)H, (float *)pot, flags,
+                                ws, s);
 }
 
 sg_status sg_direct_launch(const sg_grid *g, int nf, const double *h, const void *sigma,

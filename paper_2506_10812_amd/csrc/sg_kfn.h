@@ -150,6 +150,73 @@ __device__ inline float sg_F32(float x, const float *w)
 }
 
 // ------------------------------------------------------------------------
+// G0(x) = e^x K0(x), the kernel of the conservative potential (Sect. 5.5,
+// appendix "Conservative force"): P_ab(s) = -G0(d^2/8) / (2 sqrt(pi) H_ab).
+//   x < 2 (float: x < 1)  A&S series of I0 and K0, G0 = e^x K0;
+//   x >= 2 (float: 1 <= x < 32)  G0 = sqrt(2/x) int_0^inf e^{-v^2}
+//        (1 + v^2/(2x))^{-1/2} dv (the same substitution as for F; the
+//        trapezoid's v = 0 node has value 1 and weight STEP/2);
+//   x >= 32 (float)  sqrt(pi/(2x)) sum_n a_n x^-n, a_0 = 1,
+//        a_n = -a_{n-1} (2n - 1)^2 / (8 n), through a_5.
+// ------------------------------------------------------------------------
+template <typename R, int NT> __device__ inline R sg_G0_series(R x)
+{
+    const R y = x * x * R(0.25);
+    const R Lg = log(x * R(0.5)) + R(SG_EULER_GAMMA);
+    R tk = R(1), Hk = R(0), I0 = R(0), K0s = R(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        I0 += tk;
+        K0s += Hk * tk;
+        tk *= y / R((k + 1) * (k + 1));
+        Hk += R(1) / R(k + 1);
+    }
+    return exp(x) * (-Lg * I0 + K0s);
+}
+
+template <typename R> __device__ inline R sg_G0_quad(R x, const R *w)
+{
+    const R i2x = R(0.5) / x;
+    R acc = R(0.5);
+#pragma unroll
+    for (int k = 1; k <= FQuad<R>::NODES; ++k) {
+        const R v2 = R(k * k) * (FQuad<R>::STEP * FQuad<R>::STEP);
+        acc += w[k - 1] * rsqrt(R(1) + v2 * i2x);
+    }
+    return acc * FQuad<R>::STEP * sqrt(R(2) / x);
+}
+
+struct AsymCoefG0 {
+    float c[6];
+    constexpr AsymCoefG0() : c{}
+    {
+        double v = 1.0;
+        c[0] = 1.0f;
+        for (int n = 1; n < 6; ++n) {
+            v = -v * (2.0 * n - 1.0) * (2.0 * n - 1.0) / (8.0 * n);
+            c[n] = (float)v;
+        }
+    }
+};
+
+__device__ inline double sg_G0_64(double x, const double *w)
+{
+    return x < 2.0 ? sg_G0_series<double, 14>(x) : sg_G0_quad<double>(x, w);
+}
+
+__device__ inline float sg_G0_32(float x, const float *w)
+{
+    if (x < 1.0f) return sg_G0_series<float, 8>(x);
+    if (x < 32.0f) return sg_G0_quad<float>(x, w);
+    constexpr AsymCoefG0 C;
+    const float u = 1.0f / x;
+    float s = C.c[5];
+#pragma unroll
+    for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
+    return sqrtf(float(SG_PI * 0.5) * u) * s;
+}
+
+// ------------------------------------------------------------------------
 // Log-polar (App. C) kernels for H_f = h_f r, double precision:
 //   h^2(X) = (h_a^2 e^{-X} + h_b^2 e^{X}) / 2,  x = (cosh X - cos phi)/(4 h^2),
 //   K_r   = F(x) e^{-3X/2} h^{-3} (e^X - cos phi) / (8 sqrt(pi)),

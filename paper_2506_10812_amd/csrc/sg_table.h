@@ -24,9 +24,13 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
 sg_status sg_self_cell_launch(const sg_grid *grid, const double *ha, const double *hb, int n,
                               int which, double *d_out, hipStream_t s);
 sg_status sg_eval_F_launch(const void *x, void *F, void *dF, int64_t n, sg_dtype dt, hipStream_t s);
+sg_status sg_eval_G0_launch(const void *x, void *G, int64_t n, sg_dtype dt, hipStream_t s);
 
 __global__ void k_self_cell(SelfItems items, double *out, double du, double dphi, GLNodes gl);
 template <typename T>
 __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double lnrmin, double du,
                                     double dphi, double *out, GLNodes gl);
+template <typename T>
+__global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi, double lnrmin,
+                           double du, double dphi, int per_row, double *out, GLNodes gl);
 __global__ void k_fill_f64(double *p, int64_t n, double v);

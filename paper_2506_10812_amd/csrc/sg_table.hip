@@ -118,6 +118,78 @@ template __global__ void k_self_cell_percell<float>(const float *, int, int, int
 template __global__ void k_self_cell_percell<double>(const double *, int, int, int, double, double,
                                                      double, double *, GLNodes);
 
+// Own-cell integral of the potential kernel (reading: the paper does not
+// treat k = i): int P_ab(|x_i - x'|) dA' over the cell, x' = r e^X (cos phi,
+// sin phi) relative to the centre direction, |x_i - x'|^2 = r^2 e^X
+// (4 sinh^2(X/2) + 4 sin^2(phi/2)), dA' = r^2 e^{2X} dX dphi; even in phi,
+// so 2 x (X >= 0 and X <= 0 halves) over [0,a]x[0,b] with the same Duffy
+// rule as the force self term (the singularity is logarithmic).
+__device__ inline double pot_integrand(double X, double phi, double r, double Hab, const double *wq)
+{
+    const double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
+    const double s2 = r * r * exp(X) * 4.0 * (sx * sx + sp * sp);
+    const double y = s2 / (8.0 * Hab * Hab);
+    return -sg_G0_64(y, wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
+}
+
+__device__ inline double pot_self_partial(double r, double Hab, double a, double b, const GLNodes &gl,
+                                          const double *wq)
+{
+    constexpr int NX = SG_PANELS * SG_GLX_N;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < NX * SG_GL_N; idx += blockDim.x) {
+        const int ix = idx / SG_GL_N, j = idx % SG_GL_N;
+        const int pnl = ix / SG_GLX_N, i = ix % SG_GLX_N;
+        const double hi = ldexp(1.0, -2 * (SG_PANELS - 1 - pnl));
+        const double lo = pnl == 0 ? 0.0 : 0.25 * hi;
+        const double xi = lo + (hi - lo) * gl.xr[i];
+        const double eta = gl.x[j];
+        const double wgt = (hi - lo) * gl.wr[i] * gl.w[j] * xi * a * b;
+        double f = 0.0;
+        for (int sg = -1; sg <= 1; sg += 2)
+            f += pot_integrand(sg * a * xi, b * xi * eta, r, Hab, wq) +
+                 pot_integrand(sg * a * xi * eta, b * xi, r, Hab, wq);
+        acc += 2.0 * wgt * f;
+    }
+    return acc;
+}
+
+// Item = (pair, row) when per_row (H_f = h_f r: depends on the row only),
+// else (pair, cell) with the caller's H at that cell.
+template <typename T>
+__global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi, double lnrmin,
+                           double du, double dphi, int per_row, double *out, GLNodes gl)
+{
+    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double red[256];
+    sg_fill_weights<double>(wq);
+    __syncthreads();
+    const int64_t N = (int64_t)nr * nphi, per = per_row ? nr : N;
+    const int64_t item = blockIdx.x;
+    if (item >= (int64_t)nf * nf * per) return;
+    const int pair = (int)(item / per);
+    const int64_t c = item % per;
+    const int fa = pair / nf, fb = pair % nf;
+    const int ir = per_row ? (int)c : (int)(c / nphi);
+    const double r = exp(lnrmin + (ir + 0.5) * du);
+    double Ha, Hb;
+    if (per_row) {
+        Ha = h[fa] * r;
+        Hb = h[fb] * r;
+    } else {
+        Ha = (double)H[fa * N + c];
+        Hb = (double)H[fb * N + c];
+    }
+    const double Hab = sqrt(0.5 * (Ha * Ha + Hb * Hb));
+    const double acc = pot_self_partial(r, Hab, 0.5 * du, 0.5 * dphi, gl, wq);
+    const double tot = block_sum256(acc, red);
+    if (threadIdx.x == 0) out[item] = tot;
+}
+template __global__ void k_pot_self<float>(const float *, const double *, int, int, int, double, double,
+                                           double, int, double *, GLNodes);
+template __global__ void k_pot_self<double>(const double *, const double *, int, int, int, double, double,
+                                            double, int, double *, GLNodes);
+
 __global__ void k_fill_f64(double *p, int64_t n, double v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -264,6 +336,18 @@ __global__ void k_eval_F(const T *x, T *F, T *dF, int64_t n)
         F[i] = sg_F32(x[i], wq);
         if (dF) dF[i] = 0.0f;
     }
+}
+
+template <typename T>
+__global__ void k_eval_G0(const T *x, T *G, int64_t n)
+{
+    __shared__ T wq[FQuad<T>::NODES];
+    sg_fill_weights<T>(wq);
+    __syncthreads();
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (sizeof(T) == 8) G[i] = sg_G0_64(x[i], wq);
+    else G[i] = sg_G0_32(x[i], wq);
 }
 
 // ------------------------------------------------------------------- host
@@ -492,6 +576,19 @@ sg_status sg_self_cell_launch(const sg_grid *grid, const double *ha, const doubl
     const double du = log(grid->r_max / grid->r_min) / grid->n_r;
     const double dphi = 2.0 * SG_PI / grid->n_phi;
     hipLaunchKernelGGL(k_self_cell, dim3(n), dim3(256), 0, s, items, d_out, du, dphi, gl);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+sg_status sg_eval_G0_launch(const void *x, void *G, int64_t n, sg_dtype dt, hipStream_t s)
+{
+    const int64_t nb = (n + 255) / 256;
+    if (dt == SG_F64)
+        hipLaunchKernelGGL(k_eval_G0<double>, dim3((unsigned)nb), dim3(256), 0, s, (const double *)x,
+                           (double *)G, n);
+    else
+        hipLaunchKernelGGL(k_eval_G0<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float *)x,
+                           (float *)G, n);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

@@ -6,7 +6,7 @@ from __future__ import annotations
 import torch
 
 from . import (F32, F64, SELF_CELL_EXCLUDE, WITH_DH, field_adjoint, field_adjoint_workspace_bytes,
-               field_fft_tune,
+               field_fft_tune, potential_direct, potential_direct_workspace_bytes,
                field_direct, field_direct_workspace_bytes, field_fft, field_fft_workspace_bytes,
                fluids, grid, kernel_table, kernel_table_bytes, kernel_table_workspace_bytes,
                make_disc)
@@ -80,6 +80,17 @@ def direct(g, h, sigma, H=None, flags=0, stream=None):
     field_direct(g, nf, list(h) if h is not None else None, sigma, H, gr, gp, dt, flags, ws,
                  stream=stream)
     return gr, gp
+
+
+def potential(g, h, sigma, H=None, flags=0, stream=None):
+    """sg_potential_direct on torch tensors (float32 or float64)."""
+    dt = F64 if sigma.dtype == torch.float64 else F32
+    nf = sigma.shape[0]
+    pot = torch.empty_like(sigma)
+    ws = torch.empty(potential_direct_workspace_bytes(g, nf, dt, H is not None), dtype=torch.uint8,
+                     device=sigma.device)
+    potential_direct(g, nf, list(h) if h is not None else None, sigma, H, pot, dt, flags, ws, stream=stream)
+    return pot
 
 
 class _TableCache:

@@ -470,3 +470,118 @@ def test_indirect_point_mass_limit_and_next_term(h):
     x = 1 / (4 * h * h)
     corr = 1 - 3 / 8 / x + 45 / 128 / x ** 2
     np.testing.assert_allclose(AB[0], newton * corr, rtol=3 * (525 / 1024) / x ** 3 + 1e-13)
+
+
+# ------------------------------------------------------ conservative potential
+def test_G0_matches_arbitrary_precision_bessel():
+    """e^y K0(y) (kernel of the conservative potential) vs 40-digit mpmath."""
+    ys = np.logspace(-12, 4.6, 40)
+    got = O.G0(ys)
+    for y, v in zip(ys, got):
+        ref = float(mp.e ** mp.mpf(y) * mp.besselk(0, mp.mpf(y)))
+        assert abs(v - ref) <= 3e-15 * ref, (y, v, ref)
+
+
+def test_potential_kernel_newtonian_limit():
+    """s >> H: P_ab -> -1/s with the asymptotic correction of e^y K0(y),
+    sqrt(pi/(2y)) (1 - 1/(8y) + 9/(128 y^2)), y = s^2/(8 H_ab^2)."""
+    for s, Ha, Hb in [(1.0, 0.01, 0.02), (3.0, 0.05, 0.05), (0.5, 0.003, 0.001)]:
+        Hab = math.sqrt(0.5 * (Ha * Ha + Hb * Hb))
+        y = s * s / (8 * Hab * Hab)
+        want = -1.0 / s * (1 - 1 / (8 * y) + 9 / (128 * y * y))
+        got = O.potential_kernel([s], Ha, Hb)[0]
+        assert abs(got / want - 1) < 2 * 225 / 3072 / y ** 3 + 1e-14, (s, got, want)
+
+
+def test_potential_gradient_is_the_field_for_constant_H():
+    """Constant H_a, H_b: -grad Phi_ab equals the pairwise field of the exact
+    force kernel (the conservative case of Sect. 5.5), by central differences
+    at points off the cell centres."""
+    nr, nphi, rmin, rmax = 6, 12, 0.5, 2.0
+    rng = np.random.default_rng(21)
+    sig = rng.uniform(0.2, 1.0, (nr, nphi))
+    for Ha, Hb in [(0.08, 0.08), (0.1, 0.03)]:
+        ang = rng.uniform(0, 2 * math.pi, 6)
+        rad = rng.uniform(0.6, 1.9, 6)
+        px, py = rad * np.cos(ang), rad * np.sin(ang)
+        _, gx, gy = O.point_fields(nr, nphi, rmin, rmax, Ha, Hb, sig, px, py)
+        eps = 1e-5
+        pxp, _, _ = O.point_fields(nr, nphi, rmin, rmax, Ha, Hb, sig, px + eps, py)
+        pxm, _, _ = O.point_fields(nr, nphi, rmin, rmax, Ha, Hb, sig, px - eps, py)
+        pyp, _, _ = O.point_fields(nr, nphi, rmin, rmax, Ha, Hb, sig, px, py + eps)
+        pym, _, _ = O.point_fields(nr, nphi, rmin, rmax, Ha, Hb, sig, px, py - eps)
+        fx = -(pxp - pxm) / (2 * eps)
+        fy = -(pyp - pym) / (2 * eps)
+        scale = np.hypot(gx, gy).max()
+        assert np.abs(fx - gx).max() < 1e-7 * scale
+        assert np.abs(fy - gy).max() < 1e-7 * scale
+
+
+@pytest.mark.parametrize("r,Ha,Hb,du,dphi", [(1.0, 0.05, 0.05, 0.02, 0.05), (0.4, 0.02, 0.006, 0.05, 0.1),
+                                             (2.0, 0.5, 0.3, 0.1, 0.2)])
+def test_potential_self_term_independent_quadrature(r, Ha, Hb, du, dphi):
+    """Own-cell integral of P_ab by scipy's adaptive quadrature in polar
+    coordinates about the centre of the (X, phi) cell (an independent rule)."""
+    def f(X, phi):
+        s = r * math.sqrt(math.exp(X) * 4 * (math.sinh(0.5 * X) ** 2 + math.sin(0.5 * phi) ** 2))
+        return O.potential_kernel([s], Ha, Hb)[0] * r * r * math.exp(2 * X)
+    a, b = du / 2, dphi / 2
+    total = 0.0
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            # quadrant split at its diagonal; polar about the corner
+            th_c = math.atan2(b, a)
+            for th0, th1, edge in ((0, th_c, "a"), (th_c, math.pi / 2, "b")):
+                def inner(th):
+                    c, s_ = math.cos(th), math.sin(th)
+                    rmax = a / c if edge == "a" else b / s_
+                    v, _ = si.quad(lambda rho: rho * f(sx * rho * c, sy * rho * s_), 0, rmax,
+                                   epsabs=0, epsrel=1e-12, limit=200, points=[rmax * 1e-3])
+                    return v
+                v, _ = si.quad(inner, th0, th1, epsabs=0, epsrel=1e-11, limit=200)
+                total += v
+    got = O.potential_self(r, Ha, Hb, du, dphi)
+    assert abs(got / total - 1) < 1e-9, (got, total)
+
+
+def test_potential_reciprocity_general_H():
+    """sum_i m_b[i] Phi^{a->b}(i) = sum_k m_a[k] Phi^{b->a}(k) (the pair
+    potential is symmetric in the two cells), self terms excluded."""
+    nr, nphi, rmin, rmax = 5, 9, 0.4, 2.5
+    rng = np.random.default_rng(8)
+    sig = rng.uniform(0.1, 1.0, (2, nr, nphi))
+    du = math.log(rmax / rmin) / nr
+    r = np.exp(math.log(rmin) + (np.arange(nr) + 0.5) * du)
+    H = rng.uniform(0.02, 0.2, (2, nr, nphi))
+    area = (r ** 2 * du * 2 * math.pi / nphi)[:, None] * np.ones((1, nphi))
+
+    def pot_from(a):
+        s = np.zeros_like(sig)
+        s[a] = sig[a]
+        return O.potential_pairwise(nr, nphi, rmin, rmax, [0, 0], s, H=H, flags=O.EXCLUDE_SELF)
+    pa = pot_from(0)  # field of fluid 0 at both fluids
+    pb = pot_from(1)
+    w01 = (sig[1] * area).ravel() @ pa[1]
+    w10 = (sig[0] * area).ravel() @ pb[0]
+    assert abs(w01 - w10) < 1e-13 * abs(w01)
+
+
+# ------------------------------------------------- self-gravitating heights
+def test_hsg_limits_and_defining_quadratic():
+    """H^sg = sqrt(2/pi) H f(Qt) (Sect. 2.1): f -> sqrt(pi/2) without
+    self-gravity (Q -> inf: H^sg -> H), f ~ x for strong self-gravity, and
+    f is the positive root of (2x/pi) f^2 + f - x = 0."""
+    H = np.array([[0.05, 0.05, 0.05], [0.01, 0.01, 0.01]])
+    big = O.hsg(H, np.full((2, 3), 1e9))
+    np.testing.assert_allclose(big, H, rtol=1e-8)
+    Q = np.array([[1e-4, 2e-4, 5e-4], [1e-3, 1e-3, 1e-3]])
+    x = 1 / (1 / Q[0] + 1 / Q[1])
+    small = O.hsg(H, Q)
+    np.testing.assert_allclose(small / (math.sqrt(2 / math.pi) * H), np.broadcast_to(x, (2, 3)), rtol=1e-6)
+    rng = np.random.default_rng(4)
+    Q = rng.uniform(0.1, 10, (2, 50))
+    H = rng.uniform(0.01, 0.1, (2, 50))
+    f = O.hsg(H, Q) / (math.sqrt(2 / math.pi) * H)
+    x = 1 / (1 / Q[0] + 1 / Q[1])
+    np.testing.assert_allclose(2 * x / math.pi * f[0] ** 2 + f[0] - x, 0, atol=1e-13)
+    np.testing.assert_allclose(f[0], f[1], rtol=1e-15)
