@@ -34,14 +34,16 @@ DOMINANT_PREFIX = "k_pass2<2048, 2,"
 
 # The rocprofv3 runs behind profiles/ (run from /tmp with TMPDIR=/tmp; {out}
 # is the output root, {repo} the repository).  Counter runs are separate
-# (one TCC counter group each) and never combined with tracing.
+# (one TCC counter group each) and never combined with tracing; they run the
+# untuned plan so that both see the same pass-2 variant (all variants move
+# the same bytes).
 PROFILE_COMMANDS = {
     "kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/kt -o run -- "
           "python3 {repo}/bench.py --steps 50 --warmup 10 --no-cpu --no-extra",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/fetch -o run -- "
-             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra",
+             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra --no-tune",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/write -o run -- "
-             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra",
+             "python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra --no-tune",
     "cfetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/cfetch -o run -- "
               "python3 {repo}/bench.py --copy-calibration",
     "cwrite": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cwrite -o run -- "
