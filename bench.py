@@ -324,10 +324,63 @@ def main():
     print(json.dumps(out))
 
 
+def ss_bytes(nr, nphi, nf):
+    """Algorithmic HBM bytes of the semi-spectral middle pass: the radial
+    operators (F^2 n_r n_rt complex64 per mode), one read of the Sigma~
+    column of every source and one write of g^_r, g^_phi."""
+    ncol = nphi // 2 + 1
+    nrt = nr + (nr & 1)
+    return 8 * ncol * (nf * nf * nr * nrt + nf * nr + 2 * nf * nr)
+
+
+def semispectral_measurement(sg, T, W, dev, steps=20):
+    """The App. D flaring disc (gas, H/r = 0.05 (r/r_0)^0.25) on the
+    semi-spectral path at 1200 x 2048: table build, step time and the middle
+    pass against the HBM roofline (its parity is a test)."""
+    import torch
+    w = W.flaring()
+    nr, nphi, nf = w["n_r"], w["n_phi"], w["sigma"].shape[0]
+    S = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], nf, device=dev)
+    S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+    S.refresh(w["H"])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.refresh(w["H"])
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    S.release_workspace()
+    for _ in range(3):
+        S.run()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        S.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ms_pass = sg.field_fft_profile([S.disc], S.ws, 10)
+    mid = ss_bytes(nr, nphi, nf)
+    ach = mid / (ms_pass[1] * 1e-3) / 1e9
+    out = {"workload": f"App. D flaring gas disc {nr}x{nphi}, r in [20,250], p=0.25",
+           "table_bytes": sg.ss_table_bytes(S.g, nf), "table_build_ms": round(build_ms, 2),
+           "ms_per_step": round(ms, 4), "cells_per_s": round(nr * nphi / ms * 1e3, 1),
+           "ms_per_pass": [round(v, 4) for v in ms_pass],
+           "middle_pass": {"bound": "hbm", "algorithmic_bytes": mid, "achieved": round(ach, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
+    del S
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_measurements(sg, T, W, dev):
-    """Secondary numbers: 64-disc batch, adjoint, FP64 direct sum."""
+    """Secondary numbers: 64-disc batch, adjoint, FP64 direct sum, the
+    semi-spectral path."""
     import torch
     res = {}
+    res["semi_spectral_flaring_1200x2048"] = semispectral_measurement(sg, T, W, dev)
     discs = W.batch64()
     Fb = T.FFTField(discs, device=dev)
     for i, d in enumerate(discs):

@@ -63,7 +63,8 @@ typedef enum sg_dtype { SG_F32 = 0, SG_F64 = 1 } sg_dtype;
 enum {
     SG_SELF_CELL_EXCLUDE = 1u, /* drop the own-cell term                      */
     SG_WITH_DH = 2u,           /* table also holds d/dh spectra (adjoint)     */
-    SG_INDIRECT = 4u           /* add the indirect term (see below)           */
+    SG_INDIRECT = 4u,          /* add the indirect term (see below)           */
+    SG_SEMI_SPECTRAL = 8u      /* disc uses a semi-spectral table (below)     */
 };
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
@@ -118,9 +119,51 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
                           void *d_table, void *d_ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Semi-spectral table (any scale height profile H_f(r)).
+ *
+ * Sect. 5.2 pairs an FFT in azimuth with a direct sum in radius, at cost
+ * N_r N_phi log N_phi + N_phi N_r^2, to drop the H/r = const condition of
+ * the full FFT method (App. D shows what that condition costs).  Between
+ * source ring i' and target ring i the kernel depends on the azimuths only
+ * through their difference, so each azimuthal mode m decouples into an
+ * n_r x n_r radial operator per ordered fluid pair.  sg_ss_table samples
+ * the App. C convolution-form kernels with h_a = H_a(r_i')/r_i' at the
+ * source ring and h_b = H_b(r_i)/r_i at the target ring (so that
+ * H_ab^2 = (H_a(r_i')^2 + H_b(r_i)^2)/2, the definition of Sect. 2.2),
+ * puts the own-cell average (h = H/r of the ring) at zero offset, transforms
+ * every ring pair in azimuth in double precision and stores the operators
+ * rounded to float.  Refreshing H every few steps (Sect. 5.2) means calling
+ * it again into the same table.
+ *
+ * d_H: device double [n_fluids][n_r], H_f at the ring centres r_i
+ * (r_i = r_min e^{(i + 1/2) du}), every value > 0 (not checked on the
+ * device).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (the indirect term,
+ * with K_a at d = r_i'/H_a(r_i'), folded into mode 1 of the table; no cost
+ * at solve time).  Grid: n_phi a power of two in [4, 2048], n_r in
+ * [1, 2048], any n_r.  Size: 8 (n_phi/2 + 1) F^2 n_r (n_r rounded up to
+ * even) bytes plus a few KB; d_table 256-byte aligned, written completely.
+ * d_ws: sg_ss_table_workspace_bytes() bytes (<= about 130 MB), contents
+ * undefined afterwards.  Asynchronous on `stream`.  The table is position
+ * independent.
+ *
+ * Solve with sg_field_fft: a disc whose flags hold SG_SEMI_SPECTRAL (plus
+ * the flags the table was built with) and whose table is an sg_ss_table
+ * runs the phi transforms of the FFT path and, in place of the u-transform
+ * pass, one pass over the radial operators; fluids.h is not used.  Such
+ * discs mix freely with FFT-path discs in one batch.  sg_field_adjoint
+ * returns SG_ERR_UNSUPPORTED for them.
+ * --------------------------------------------------------------------- */
+size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids);
+size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids);
+sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint32_t flags,
+                      void *d_table, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
  * One disc for the FFT path.  sigma, g_r, g_phi: float device arrays
  * [n_fluids][n_r][n_phi]; table: built by sg_kernel_table for the same grid,
- * fluids and flags (checked on the host from the arguments, not the device).
+ * fluids and flags (checked on the host from the arguments, not the device),
+ * or, with SG_SEMI_SPECTRAL in flags, by sg_ss_table for the same grid and
+ * fluid count.
  * --------------------------------------------------------------------- */
 typedef struct sg_disc {
     sg_grid grid;

@@ -19,6 +19,7 @@ F32, F64 = 0, 1
 SELF_CELL_EXCLUDE = 1
 WITH_DH = 2
 INDIRECT = 4
+SEMI_SPECTRAL = 8
 
 
 class SGError(RuntimeError):
@@ -72,6 +73,9 @@ def _load():
         "sg_kernel_table_bytes": (sz, [GP, FP, u32]),
         "sg_kernel_table_workspace_bytes": (sz, [GP, FP, u32]),
         "sg_kernel_table": (i32, [GP, FP, u32, vp, vp, sz, vp]),
+        "sg_ss_table_bytes": (sz, [GP, i32]),
+        "sg_ss_table_workspace_bytes": (sz, [GP, i32]),
+        "sg_ss_table": (i32, [GP, i32, vp, u32, vp, vp, sz, vp]),
         "sg_field_fft_workspace_bytes": (sz, [DP, i32]),
         "sg_field_fft": (i32, [DP, i32, vp, sz, vp]),
         "sg_field_fft_profile": (i32, [DP, i32, vp, sz, vp, i32, ctypes.POINTER(ctypes.c_float)]),
@@ -101,6 +105,7 @@ def _load():
 _lib = _load()
 EXPORTED = (
     "sg_kernel_table_bytes", "sg_kernel_table_workspace_bytes", "sg_kernel_table",
+    "sg_ss_table_bytes", "sg_ss_table_workspace_bytes", "sg_ss_table",
     "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile", "sg_field_fft_tune",
     "sg_field_direct_workspace_bytes",
     "sg_field_direct", "sg_potential_direct_workspace_bytes", "sg_potential_direct",
@@ -151,6 +156,14 @@ def kernel_table_workspace_bytes(g: Grid, f: Fluids, flags: int = 0) -> int:
     return int(_lib.sg_kernel_table_workspace_bytes(ctypes.byref(g), ctypes.byref(f), flags))
 
 
+def ss_table_bytes(g: Grid, n_fluids: int) -> int:
+    return int(_lib.sg_ss_table_bytes(ctypes.byref(g), int(n_fluids)))
+
+
+def ss_table_workspace_bytes(g: Grid, n_fluids: int) -> int:
+    return int(_lib.sg_ss_table_workspace_bytes(ctypes.byref(g), int(n_fluids)))
+
+
 def _disc_array(discs):
     arr = (Disc * len(discs))(*discs)
     return arr
@@ -175,6 +188,13 @@ def kernel_table(g: Grid, f: Fluids, flags, table, ws, ws_bytes=None, stream=Non
     ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
     _check(_lib.sg_kernel_table(ctypes.byref(g), ctypes.byref(f), flags, _ptr(table), _ptr(ws),
                                 ws_bytes, _stream(stream)), "sg_kernel_table")
+
+
+def ss_table(g: Grid, n_fluids, H, flags, table, ws, ws_bytes=None, stream=None):
+    """H: device float64 [n_fluids][n_r], the scale heights at the ring centres."""
+    ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.sg_ss_table(ctypes.byref(g), int(n_fluids), _ptr(H), flags, _ptr(table), _ptr(ws),
+                            ws_bytes, _stream(stream)), "sg_ss_table")
 
 
 def make_disc(g: Grid, f: Fluids, flags, sigma, g_r, g_phi, table) -> Disc:

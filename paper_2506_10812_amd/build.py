@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsg.so")
-SOURCES = ["sg_api.hip", "sg_table.hip", "sg_direct.hip", "sg_fftpath.hip", "sg_adjoint.hip"]
+SOURCES = ["sg_api.hip", "sg_table.hip", "sg_direct.hip", "sg_fftpath.hip", "sg_adjoint.hip",
+           "sg_semispec.hip"]
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code

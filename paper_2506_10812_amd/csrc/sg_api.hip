@@ -5,6 +5,7 @@
 #include "sg_adjoint.h"
 #include "sg_direct.h"
 #include "sg_fftpath.h"
+#include "sg_semispec.h"
 #include "sg_table.h"
 
 static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
@@ -40,6 +41,21 @@ static bool flags_ok(uint32_t flags)
     return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH | SG_INDIRECT)) == 0;
 }
 
+// Semi-spectral path: n_phi a power of two in [4, 2048], 1 <= n_r <= 2048.
+static sg_status check_ss_grid(const sg_grid *g)
+{
+    sg_status s = check_grid(g);
+    if (s != SG_OK) return s;
+    if (!sg_is_pow2(g->n_phi) || g->n_phi < 4 || g->n_phi > 2048) return SG_ERR_UNSUPPORTED;
+    if (g->n_r > sg_ss_max_nr()) return SG_ERR_UNSUPPORTED;
+    return SG_OK;
+}
+
+static bool ss_flags_ok(uint32_t flags)
+{
+    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL)) == 0;
+}
+
 extern "C" {
 
 size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
@@ -67,8 +83,42 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
     return sg_table_build(grid, fluids, flags, d_table, d_ws, (hipStream_t)stream);
 }
 
+size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids)
+{
+    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids).total;
+}
+
+size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids)
+{
+    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    return sg_ss_ws_bytes(grid->n_r, grid->n_phi, n_fluids);
+}
+
+sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint32_t flags, void *d_table,
+                      void *d_ws, size_t ws_bytes, void *stream)
+{
+    sg_status s = check_ss_grid(grid);
+    if (s != SG_OK) return s;
+    if (n_fluids < 1 || n_fluids > 2 || !d_H) return SG_ERR_ARG;
+    if (!ss_flags_ok(flags)) return SG_ERR_ARG;
+    if (!d_table || ((uintptr_t)d_table & 255)) return SG_ERR_ARG;
+    if (!d_ws || ws_bytes < sg_ss_ws_bytes(grid->n_r, grid->n_phi, n_fluids) || ((uintptr_t)d_ws & 255))
+        return SG_ERR_WORKSPACE;
+    return sg_ss_table_build(grid, n_fluids, d_H, flags, d_table, d_ws, (hipStream_t)stream);
+}
+
 static sg_status check_disc(const sg_disc &d)
 {
+    if (d.flags & SG_SEMI_SPECTRAL) {
+        sg_status s = check_ss_grid(&d.grid);
+        if (s != SG_OK) return s;
+        if (d.fluids.n_fluids < 1 || d.fluids.n_fluids > 2) return SG_ERR_ARG;
+        if (!ss_flags_ok(d.flags)) return SG_ERR_ARG;
+        if (!d.sigma || !d.g_r || !d.g_phi || !d.table) return SG_ERR_ARG;
+        if ((uintptr_t)d.table & 255) return SG_ERR_ARG;
+        return SG_OK;
+    }
     sg_status s = check_fft_grid(&d.grid);
     if (s != SG_OK) return s;
     if ((s = check_fluids(&d.fluids)) != SG_OK) return s;
@@ -210,7 +260,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
 
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
 {
-    if (!disc || check_disc(*disc) != SG_OK) return 0;
+    if (!disc || check_disc(*disc) != SG_OK || (disc->flags & SG_SEMI_SPECTRAL)) return 0;
     return sg_adjoint_ws_bytes(*disc);
 }
 
@@ -221,7 +271,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
-    if (disc->flags & SG_INDIRECT) return SG_ERR_UNSUPPORTED;
+    if (disc->flags & (SG_INDIRECT | SG_SEMI_SPECTRAL)) return SG_ERR_UNSUPPORTED;
     if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
     if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))
         return SG_ERR_WORKSPACE;

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sg_fftpath.h"
+#include "sg_semispec.h"
 #include "sg_passes.h"
 
 // ---------------------------------------------------------------- kernels
@@ -366,6 +367,8 @@ using KernelFn = void (*)(const DiscDev *, const WJob *, int, const float2 *, in
 struct PassKernel {
     KernelFn fn;
     int wgs, G, K;    // K: default XCD cluster size
+    int tb = 0;       // semi-spectral pass: target rows per workgroup job
+    int lds_per_row = 0, lds_fixed = 0;  // its dynamic LDS: per radial row, fixed
 };
 
 // Shapes above 1024 threads do not exist (null kernel).
@@ -407,6 +410,15 @@ template <bool SF, int GM> static PassKernel pick_kernel(int pass, int n, int nf
     return PassKernel{nullptr, 0, 0, 0};
 }
 
+// Semi-spectral middle pass (variant = gm: 1, 2, 3).
+static bool ss_pass_kernel(int nf, int gm, PassKernel &out)
+{
+    SsPassInfo k;
+    if (!sg_ss_pass_kernel(nf, gm, k)) return false;
+    out = PassKernel{k.fn, k.wgs, 1, 1, k.tb, k.lds_per_row, k.lds_fixed};
+    return true;
+}
+
 static bool pass_kernel(int pass, int n, int nf, bool sf, int gm, PassKernel &out)
 {
     if (gm == 2) out = sf ? pick_kernel<true, 2>(pass, n, nf) : pick_kernel<false, 2>(pass, n, nf);
@@ -429,9 +441,10 @@ struct Variant {
 };
 
 // A launch class: one pass over the discs sharing a transform length and a
-// fluid count.
+// fluid count; the middle pass of semi-spectral discs (ss) forms classes of
+// its own, keyed by n_r (len).
 struct ClassSpec {
-    int pass, len, nf;
+    int pass, len, nf, ss;
     std::vector<int> discs;
 };
 
@@ -444,6 +457,7 @@ struct Launch {
     int grid;         // workgroups (a multiple of 8 K)
     const float2 *tw; // twiddles of this launch's transform length
     int pass;
+    size_t lds;       // dynamic LDS bytes
 };
 
 struct Plan {
@@ -459,13 +473,17 @@ size_t sg_fft_disc_ws_bytes(const sg_disc &d)
            sg_align256(sizeof(float2) * fs * 2 * d.fluids.n_fluids);
 }
 
-// Jobs of one disc in a pass: pass 1 (fluid, row pair), pass 2 columns m <= n_phi/2,
-// pass 3 (target fluid, row) pairs; rows padded to sg_blk_rows.
-static int pass_jobs(const sg_disc &d, int pass)
+// Jobs of one disc in a pass: pass 1 (fluid, row pair), pass 2 columns m <= n_phi/2
+// (semi-spectral: (m, target fluid, block of tb target rows)), pass 3 (target
+// fluid, row) pairs; rows padded to sg_blk_rows.
+static int pass_jobs(const sg_disc &d, int pass, int tb)
 {
     const int nf = d.fluids.n_fluids, nrp = sg_blk_rows(d.grid.n_r);
     if (pass == 1) return nf * nrp / 2;
-    if (pass == 2) return d.grid.n_phi / 2 + 1;
+    if (pass == 2) {
+        if (d.flags & SG_SEMI_SPECTRAL) return (d.grid.n_phi / 2 + 1) * nf * ((d.grid.n_r + tb - 1) / tb);
+        return d.grid.n_phi / 2 + 1;
+    }
     return nf * nrp;
 }
 
@@ -480,11 +498,11 @@ static int launch_grid(int nj, int K)
 // Workgroup jobs of a class: G jobs per workgroup job, each disc padded to a
 // whole number of clusters of K workgroup jobs so that cache-line sharing
 // stays inside one disc.
-static void class_wjobs(const sg_disc *discs, const ClassSpec &c, int G, int K, std::vector<WJob> &out)
+static void class_wjobs(const sg_disc *discs, const ClassSpec &c, int G, int K, int tb, std::vector<WJob> &out)
 {
     out.clear();
     for (int di : c.discs) {
-        const int cnt = pass_jobs(discs[di], c.pass);
+        const int cnt = pass_jobs(discs[di], c.pass, tb);
         for (int b = 0; b < cnt; b += G) out.push_back({di, b, std::min(G, cnt - b), 0});
         while (out.size() % K) out.push_back({di, 0, 0, 0});
     }
@@ -494,12 +512,14 @@ static std::vector<ClassSpec> plan_classes(const sg_disc *discs, int n)
 {
     std::vector<ClassSpec> out;
     for (int pass = 1; pass <= 3; ++pass) {
-        std::map<std::pair<int, int>, std::vector<int>> classes;
+        std::map<std::tuple<int, int, int>, std::vector<int>> classes;
         for (int i = 0; i < n; ++i) {
-            const int len = pass == 2 ? 2 * discs[i].grid.n_r : discs[i].grid.n_phi;
-            classes[{len, discs[i].fluids.n_fluids}].push_back(i);
+            const int ss = pass == 2 && (discs[i].flags & SG_SEMI_SPECTRAL) ? 1 : 0;
+            const int len = pass == 2 ? (ss ? discs[i].grid.n_r : 2 * discs[i].grid.n_r) : discs[i].grid.n_phi;
+            classes[{ss, len, discs[i].fluids.n_fluids}].push_back(i);
         }
-        for (auto &kv : classes) out.push_back({pass, kv.first.first, kv.first.second, kv.second});
+        for (auto &kv : classes)
+            out.push_back({pass, std::get<1>(kv.first), std::get<2>(kv.first), std::get<0>(kv.first), kv.second});
     }
     return out;
 }
@@ -521,18 +541,30 @@ static TuneKey tune_key(const sg_disc *discs, const ClassSpec &c)
         mix((uint64_t)discs[di].grid.n_r);
         mix((uint64_t)discs[di].grid.n_phi);
     }
+    if (c.ss) mix(0x5353ull);
     return TuneKey{c.pass, c.len, c.nf, h};
+}
+
+// Default variant of a class: semi-spectral classes pick the middle-pass
+// shape by n_r; the FFT passes start from the plain shape.
+static Variant default_variant(const ClassSpec &c)
+{
+    Variant v;
+    if (c.ss) v.gm = sg_ss_default_variant(c.len);
+    return v;
 }
 
 static bool make_launch(const sg_disc *discs, const Plan &P, const ClassSpec &c, Variant v, Launch &La,
                         std::vector<WJob> &wj)
 {
     PassKernel k;
-    if (!pass_kernel(c.pass, c.len, c.nf, v.sf != 0, v.gm, k)) return false;
+    if (c.ss ? !ss_pass_kernel(c.nf, v.gm, k) : !pass_kernel(c.pass, c.len, c.nf, v.sf != 0, v.gm, k))
+        return false;
     La.k = k;
     La.v = v;
     La.K = v.K > 0 ? v.K : k.K;
-    class_wjobs(discs, c, k.G, La.K, wj);
+    La.lds = c.ss ? (size_t)k.lds_per_row * c.len + k.lds_fixed : 0;
+    class_wjobs(discs, c, k.G, La.K, k.tb, wj);
     La.nj = (int)wj.size();
     La.grid = launch_grid(La.nj, La.K);
     const DiscDev &D0 = P.discs[c.discs[0]];
@@ -548,16 +580,26 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         const sg_disc &d = discs[i];
-        const TableLayout L = sg_table_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, d.flags);
         const char *tb = (const char *)d.table;
         DiscDev &D = P.discs[i];
         D.sigma = d.sigma;
         D.gr = d.g_r;
         D.gp = d.g_phi;
-        D.spec = (const float2 *)(tb + L.off_spec);
-        D.dspec = (d.flags & SG_WITH_DH) ? (const float2 *)(tb + L.off_dspec) : nullptr;
-        D.tw_u = (const float2 *)(tb + L.off_tw_u);
-        D.tw_phi = (const float2 *)(tb + L.off_tw_phi);
+        if (d.flags & SG_SEMI_SPECTRAL) {
+            const SsLayout L = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids);
+            D.spec = (const float2 *)(tb + L.off_coef);
+            D.dspec = nullptr;
+            D.tw_u = nullptr;
+            D.tw_phi = (const float2 *)(tb + L.off_tw_phi);
+            D.ind = nullptr;
+        } else {
+            const TableLayout L = sg_table_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, d.flags);
+            D.spec = (const float2 *)(tb + L.off_spec);
+            D.dspec = (d.flags & SG_WITH_DH) ? (const float2 *)(tb + L.off_dspec) : nullptr;
+            D.tw_u = (const float2 *)(tb + L.off_tw_u);
+            D.tw_phi = (const float2 *)(tb + L.off_tw_phi);
+            D.ind = (const double *)(tb + offsetof(sg_table_header, ind_coef));
+        }
         const size_t fs = sg_blk_field_elems(d.grid.n_phi, d.grid.n_r);
         D.st = (float2 *)(ws + off);
         D.gh = (float2 *)(ws + off + sg_align256(sizeof(float2) * fs * d.fluids.n_fluids));
@@ -565,7 +607,6 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.nr = d.grid.n_r;
         D.nphi = d.grid.n_phi;
         D.nf = d.fluids.n_fluids;
-        D.ind = (const double *)(tb + offsetof(sg_table_header, ind_coef));
         D.flags = d.flags;
     }
 }
@@ -576,7 +617,7 @@ static bool build_plan(const sg_disc *discs, int n, char *ws, Plan &P)
     fill_discs(discs, n, ws, P);
     std::vector<WJob> wj;
     for (const ClassSpec &c : plan_classes(discs, n)) {
-        Variant v;
+        Variant v = default_variant(c);
         auto it = g_tuned.find(tune_key(discs, c));
         if (it != g_tuned.end()) v = it->second;
         Launch La;
@@ -627,7 +668,8 @@ static std::vector<uint64_t> signature(const sg_disc *discs, int n, void *ws)
 
 static sg_status launch_one(const DiscDev *dd, const WJob *wj, const Launch &L, hipStream_t s)
 {
-    hipLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), 0, s, dd, wj + L.wj_off, L.nj, L.tw, L.K);
+    hipLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), (unsigned)L.lds, s, dd, wj + L.wj_off, L.nj, L.tw,
+                       L.K);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -916,7 +958,8 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
     for (const ClassSpec &c : plan_classes(discs, n)) {
         // reference: the default variant
         Launch L0;
-        if (!make_launch(discs, P, c, Variant{}, L0, wj)) return SG_ERR_UNSUPPORTED;
+        const Variant v0 = default_variant(c);
+        if (!make_launch(discs, P, c, v0, L0, wj)) return SG_ERR_UNSUPPORTED;
         sg_status st = tune_upload_wj(S, wj);
         if (st != SG_OK) return st;
         if (launch_one((const DiscDev *)S.dd, (const WJob *)S.wj, L0, s) != SG_OK) return SG_ERR_HIP;
@@ -938,17 +981,17 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
         st = tune_time(S, L0, s, reps, ms0);
         if (st != SG_OK) return st;
         // candidates
-        Variant best;
+        Variant best = v0;
         float ms_best = ms0;
         double rel_best = 0.0;
         int ncand = 0, nrej = 0;
-        for (int sf = 0; sf <= (has_small_radix(c.len) ? 1 : 0); ++sf)
-            for (int gm = 1; gm <= 2; ++gm)
+        for (int sf = 0; sf <= (!c.ss && has_small_radix(c.len) ? 1 : 0); ++sf)
+            for (int gm = 1; gm <= (c.ss ? 3 : 2); ++gm)
                 for (int K : {1, 2, 4, 8}) {
                     const Variant v{sf, gm, K};
                     Launch L;
                     if (!make_launch(discs, P, c, v, L, wj)) continue;  // shape does not exist
-                    if (L.K == L0.K && sf == 0 && gm == 1) continue;      // the reference itself
+                    if (L.K == L0.K && sf == v0.sf && gm == v0.gm) continue;  // the reference itself
                     ++ncand;
                     st = tune_upload_wj(S, wj);
                     if (st != SG_OK) return st;
@@ -984,7 +1027,7 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
             r.n_fluids = c.nf;
             r.n_jobs = Lb.nj;
             r.small_radix_first = best.sf;
-            r.groups_per_wg = Lb.k.G;
+            r.groups_per_wg = c.ss ? Lb.v.gm : Lb.k.G;
             r.cluster = Lb.K;
             r.candidates = ncand;
             r.rejected = nrej;
@@ -1017,7 +1060,7 @@ static void load_tune_file()
     int pass, len, nf, sf, gm, K;
     unsigned long long h;
     while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &gm, &K) == 7)
-        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 2 &&
+        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 3 &&
             (K == 0 || K == 1 || K == 2 || K == 4 || K == 8))
             g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, gm, K};
     fclose(f);

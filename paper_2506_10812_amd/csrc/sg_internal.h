@@ -175,14 +175,58 @@ inline TableLayout sg_table_layout(int nr, int nphi, int nf, uint32_t flags)
     return L;
 }
 
+// Semi-spectral table layout (sg_ss_table; H_f any function of r):
+//   header   sg_ss_header
+//   tw_phi   float2[n_phi]       e^{-2 pi i n / n_phi}
+//   coef     float2[ncol][F][F][n_r][nrt]
+// indexed [m][b (target fluid)][a (source fluid)][i' (source row)][i (target
+// row)]; element (t_r, t_phi) is the radial operator of mode m: g^_r gets
+// t_r Sigma~ and g^_phi gets i t_phi Sigma~.  nrt = n_r rounded up to even
+// (the padding target column is zero), so target pairs are 16-byte aligned.
+#define SG_SS_MAGIC 0x31535347u  // "GSS1"
+
+struct sg_ss_header {
+    uint32_t magic, version;
+    int32_t n_r, n_phi, n_fluids;
+    uint32_t flags;
+    double r_min, r_max;
+    uint64_t total_bytes;
+};
+
+struct SsLayout {
+    int nr, nphi, nf, ncol, nrt;
+    size_t slice;   // float2 elements per (m, b, a)
+    size_t rows;    // F * F * n_r * nrt: (b, a, i', i) rows of one mode
+    size_t off_tw_phi, off_coef, total;
+};
+
+inline SsLayout sg_ss_layout(int nr, int nphi, int nf)
+{
+    SsLayout L;
+    L.nr = nr;
+    L.nphi = nphi;
+    L.nf = nf;
+    L.ncol = nphi / 2 + 1;
+    L.nrt = (nr + 1) & ~1;
+    L.slice = (size_t)nr * L.nrt;
+    L.rows = (size_t)nf * nf * L.slice;
+    size_t o = sg_align256(sizeof(sg_ss_header));
+    L.off_tw_phi = o;
+    o = sg_align256(o + sizeof(float2) * (size_t)nphi);
+    L.off_coef = o;
+    o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.rows);
+    L.total = o;
+    return L;
+}
+
 // Tiled layout of the half-spectrum intermediates between the passes: tiles
 // of 4 columns x 4 rows (128 bytes), each column's 4 rows contiguous inside
 // the tile, and the tiles of one 4-column group following each other down
 // the rows.  A column job of pass 2 then reads and writes 32 contiguous bytes
 // per 4 rows, and a workgroup of 4 consecutive rows in passes 1 and 3 moves
-// whole tiles.  Row counts below 4 are padded to 4 (the padding rows are
-// written by pass 1 and never read as data).
-__host__ __device__ inline int sg_blk_rows(int nr) { return nr < 4 ? 4 : nr; }
+// whole tiles.  Row counts are padded to a multiple of 4 (the padding rows
+// are written by pass 1 and never read as data).
+__host__ __device__ inline int sg_blk_rows(int nr) { return (nr + 3) & ~3; }
 __host__ __device__ inline size_t sg_blk_index(int m, int i, int nr)
 {
     return ((size_t)(m >> 2) * sg_blk_rows(nr) + (i & ~3)) * 4 + (m & 3) * 4 + (i & 3);

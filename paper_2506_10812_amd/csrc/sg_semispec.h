@@ -1,0 +1,21 @@
+// sg_semispec.h -- internal entry points of the semi-spectral path.
+#pragma once
+#include "sg_passes.h"
+
+// Middle pass of a semi-spectral disc (replaces pass 2 of the FFT path):
+// fn has the pass-kernel signature; a workgroup of wgs threads takes one job
+// (column m, target fluid b, block of tb target rows) and needs
+// lds_per_row * n_r + lds_fixed bytes of dynamic LDS.
+struct SsPassInfo {
+    void (*fn)(const DiscDev *, const WJob *, int, const float2 *, int);
+    int wgs, tb, lds_per_row, lds_fixed;
+};
+
+// variant 1, 2, 3: (targets per lane, row splits) = (2, 4), (2, 1), (4, 1)
+bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out);
+int sg_ss_default_variant(int nr);
+int sg_ss_max_nr();
+
+size_t sg_ss_ws_bytes(int nr, int nphi, int nf);
+sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint32_t flags, void *d_table,
+                            void *d_ws, hipStream_t s);

@@ -1,0 +1,411 @@
+// sg_semispec.hip -- the semi-spectral solver: azimuthal FFT plus a direct
+// radial sum per azimuthal mode (Sect. 5.2), for scale heights that are any
+// function of radius (it lifts the H = h r condition of the full log-polar
+// FFT, whose cost App. D quantifies).
+//
+// With H_a = H_a(r) the kernel between source ring i' and target ring i
+// still depends on the azimuths only through phi = phi_target - phi_source,
+// so for every ring pair the field is a circular convolution in phi:
+//   g_c^{b}(i, j) = - du dphi sum_a sum_i' sum_j' Sigma_a(i', j')
+//                   K_c(X_ii', (j - j') dphi; h_a = H_a(r_i')/r_i', h_b = H_b(r_i)/r_i)
+// with X_ii' = u_i - u_i' and K_c the convolution-form kernels of App. C
+// (there with constant h; the pair enters them only through
+// h_ab^2 = (h_a^2 e^{-X} + h_b^2 e^X)/2 = H_ab^2 / (r r'), so the same
+// formulas hold ring by ring).  In phi-Fourier space mode m decouples:
+//   g^_c^{b}(m, i) = sum_a sum_i' T_c^{ab}(m, i, i') Sigma~_a(m, i'),
+// an n_r x n_r operator per (m, pair).  K_r is even and K_phi odd in phi, so
+// T_r is real and T_phi = i t_phi with t_phi real.
+//
+// Table (sg_ss_table, double precision, rounded to float at the end):
+//   1. self-cell averages Kbar_r per (pair, ring) with h = H/r at the ring
+//      (offset X = 0, phi = 0; zero with SG_SELF_CELL_EXCLUDE);
+//   2. per row (b, a, i', i): samples K_r + i K_phi at phi = q dphi for
+//      q <= n_phi/2, mirrored (K_r even, K_phi odd), one complex transform,
+//      T_r(m) = (Z[m] + Z[-m])/2, t_phi(m) = (Z[-m] - Z[m])/2 (real parts),
+//      scaled by -du dphi / n_phi (the inverse transform of the last pass is
+//      unnormalised); rows are written [row][m] to a chunk buffer;
+//   3. a tiled transpose moves each chunk to the [m][row] table layout.
+// SG_INDIRECT folds the indirect term (Sect. 5.4 and its appendix) into
+// mode 1: in the same convolution form it is Sigma convolved with
+//   r_i'^2 sqrt(2) K_a(d_i') (cos phi, -sin phi),  d_i' = r_i' / H_a(r_i'),
+// whose transform at m = 1 adds r_i'^2 sqrt(2) K_a(d) n_phi / 2 to both T_r
+// and t_phi before scaling.
+//
+// Solve (sg_field_fft with discs flagged SG_SEMI_SPECTRAL): pass 1 and pass 3
+// of the FFT path (phi transforms), and k_ss_pass in place of pass 2.
+#include "sg_kfn.h"
+#include "sg_semispec.h"
+#include "sg_table.h"
+
+// ------------------------------------------------------------ table: rows
+struct SsRowArgs {
+    int nr, nrt, nf, excl, ind;
+    double lnrmin, du, dphi;
+};
+
+template <int N> struct SsRowShape {
+    static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
+    static constexpr int WGS = T > 256 ? T : 256;
+    static constexpr int G = WGS / T;
+};
+
+// One group of T threads per row R = r0 + row of the (b, a, i', i) order
+// (i fastest).  out: [nrows][ncol] float2 (T_r, t_phi), m = 0 .. N/2.
+template <int N>
+__global__ void __launch_bounds__(SsRowShape<N>::WGS)
+k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows, float2 *out)
+{
+    using S = SsRowShape<N>;
+    constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
+    constexpr int NC = N / 2 + 1;
+    __shared__ __attribute__((aligned(16))) double2 lds[W * G];
+    __shared__ double wq[FQuad<double>::NODES];
+    sg_fill_weights<double>(wq);
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const LdsPlane<double> pl{lds + W * g};
+    const int row = blockIdx.x * G + g;
+    const bool valid = row < nrows;
+    const size_t R = r0 + (size_t)(valid ? row : 0);
+    const int i = (int)(R % A.nrt);
+    size_t rest = R / A.nrt;
+    const int ip = (int)(rest % A.nr);
+    rest /= A.nr;
+    const int a = (int)(rest % A.nf), b = (int)(rest / A.nf);
+    const bool live = valid && i < A.nr;  // padding target column stays zero
+    const int ic = i < A.nr ? i : A.nr - 1;
+    const double ri = exp(A.lnrmin + (ic + 0.5) * A.du);
+    const double rp = exp(A.lnrmin + (ip + 0.5) * A.du);
+    const double ha = H[a * A.nr + ip] / rp, hb = H[b * A.nr + ic] / ri;
+    const double X = (double)(ic - ip) * A.du;
+    __syncthreads();
+    // 1. samples q in [0, N/2], mirrored into the upper half
+#pragma unroll 1
+    for (int q = t; q <= N / 2; q += T) {
+        double kr = 0.0, kp = 0.0;
+        if (ic == ip && q == 0) {
+            kr = A.excl ? 0.0 : self[(size_t)(a * A.nf + b) * A.nr + ic];
+        } else {
+            sg_conv_kernel64(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, 0, wq, kr, kp);
+        }
+        pl.st(q, make_double2(kr, kp));
+        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
+    }
+    __syncthreads();
+    double2 z[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
+    __syncthreads();
+    // 2. transform; Z = T_r - t_phi at m and T_r + t_phi at -m
+    fft<N, false>(z, t, pl, TwExact64<N>{});
+#pragma unroll
+    for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
+    __syncthreads();
+    if (!valid) return;
+    const double scale = -A.du * A.dphi / N;
+    double ind = 0.0;
+    if (A.ind) {
+        // r'^2 sqrt(2) K_a(d) n_phi / 2 (the convolution-form samples carry the
+        // cell measure r'^2), K_a(d) = pi^{-1/2} H^{-2} (d/4) F(d^2/4)
+        const double Ha = H[a * A.nr + ip], d = rp / Ha;
+        ind = rp * rp * SG_SQRT2 * (1.0 / SG_SQRT_PI) / (Ha * Ha) * (0.25 * d) * sg_F64(0.25 * d * d, wq) *
+              (0.5 * N);
+    }
+    float2 *o = out + (size_t)row * NC;
+    for (int m = t; m < NC; m += T) {
+        float2 v = make_float2(0.f, 0.f);
+        if (live) {
+            const double zm = pl.ld(m).x, zn = pl.ld((N - m) & (N - 1)).x;
+            double tr = 0.5 * (zm + zn), tp = 0.5 * (zn - zm);
+            if (m == 1) {
+                tr += ind;
+                tp += ind;
+            }
+            v = make_float2((float)(scale * tr), (float)(scale * tp));
+        }
+        gstore2(o, m, v);
+    }
+}
+
+// ------------------------------------------------------- table: transpose
+// src [nrows][ncol] -> dst[m * rows_total + r0 + row], 32 x 32 tiles.
+__global__ void __launch_bounds__(256)
+k_ss_transpose(const float2 *src, int nrows, int ncol, float2 *dst, size_t rows_total, size_t r0)
+{
+    __shared__ float2 tile[32][33];
+    const int rb = blockIdx.x * 32, mb = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int r = rb + k, m = mb + tx;
+        if (r < nrows && m < ncol) tile[k][tx] = gload2(src, (size_t)r * ncol + m);
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int m = mb + k, r = rb + tx;
+        if (r < nrows && m < ncol) gstore2(dst, (size_t)m * rows_total + r0 + r, tile[tx][k]);
+    }
+}
+
+__global__ void k_ss_header(sg_ss_header *hd, sg_ss_header proto)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *hd = proto;
+}
+
+// ------------------------------------------------------------- table: host
+#define SG_SS_CHUNK_BYTES ((size_t)128 << 20)
+#define SG_SS_MAX_NR 2048
+
+int sg_ss_max_nr() { return SG_SS_MAX_NR; }
+
+static size_t ss_chunk_rows(const SsLayout &L)
+{
+    const size_t per = sizeof(float2) * (size_t)L.ncol;
+    size_t rows = SG_SS_CHUNK_BYTES / per;
+    rows = rows / 32 * 32;
+    if (rows < 32) rows = 32;
+    return rows < L.rows ? rows : L.rows;
+}
+
+size_t sg_ss_ws_bytes(int nr, int nphi, int nf)
+{
+    const SsLayout L = sg_ss_layout(nr, nphi, nf);
+    return sg_align256(sizeof(double) * (size_t)nf * nf * nr) +
+           sg_align256(sizeof(float2) * L.ncol * ss_chunk_rows(L));
+}
+
+template <int N>
+static void launch_ss_rows(const double *H, const double *self, const SsRowArgs &A, size_t r0, int nrows,
+                           float2 *out, hipStream_t s)
+{
+    using S = SsRowShape<N>;
+    hipLaunchKernelGGL(k_ss_rows<N>, dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self, A, r0,
+                       nrows, out);
+}
+
+static bool dispatch_ss_rows(int nphi, const double *H, const double *self, const SsRowArgs &A, size_t r0,
+                             int nrows, float2 *out, hipStream_t s)
+{
+    switch (nphi) {
+    case 4: launch_ss_rows<4>(H, self, A, r0, nrows, out, s); return true;
+    case 8: launch_ss_rows<8>(H, self, A, r0, nrows, out, s); return true;
+    case 16: launch_ss_rows<16>(H, self, A, r0, nrows, out, s); return true;
+    case 32: launch_ss_rows<32>(H, self, A, r0, nrows, out, s); return true;
+    case 64: launch_ss_rows<64>(H, self, A, r0, nrows, out, s); return true;
+    case 128: launch_ss_rows<128>(H, self, A, r0, nrows, out, s); return true;
+    case 256: launch_ss_rows<256>(H, self, A, r0, nrows, out, s); return true;
+    case 512: launch_ss_rows<512>(H, self, A, r0, nrows, out, s); return true;
+    case 1024: launch_ss_rows<1024>(H, self, A, r0, nrows, out, s); return true;
+    case 2048: launch_ss_rows<2048>(H, self, A, r0, nrows, out, s); return true;
+    default: return false;
+    }
+}
+
+sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint32_t flags, void *d_table,
+                            void *d_ws, hipStream_t s)
+{
+    const int nr = grid->n_r, nphi = grid->n_phi;
+    const SsLayout L = sg_ss_layout(nr, nphi, nf);
+    const double du = log(grid->r_max / grid->r_min) / nr;
+    const double dphi = 2.0 * SG_PI / nphi;
+    char *tb = (char *)d_table;
+    double *self = (double *)d_ws;
+    float2 *chunk = (float2 *)((char *)d_ws + sg_align256(sizeof(double) * (size_t)nf * nf * nr));
+    const bool excl = (flags & SG_SELF_CELL_EXCLUDE) != 0;
+
+    hipLaunchKernelGGL(k_twiddles, dim3((nphi + 255) / 256), dim3(256), 0, s, (float2 *)nullptr, 0,
+                       (float2 *)(tb + L.off_tw_phi), nphi);
+    SG_HIP(hipGetLastError());
+    if (!excl) {
+        // one item per (pair, ring): the per-cell kernel with one cell per ring
+        GLNodes gl;
+        sg_gl_nodes(gl);
+        hipLaunchKernelGGL(k_self_cell_percell<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1,
+                           log(grid->r_min), du, dphi, self, gl);
+        SG_HIP(hipGetLastError());
+    }
+    SsRowArgs A;
+    A.nr = nr;
+    A.nrt = L.nrt;
+    A.nf = nf;
+    A.excl = excl ? 1 : 0;
+    A.ind = (flags & SG_INDIRECT) ? 1 : 0;
+    A.lnrmin = log(grid->r_min);
+    A.du = du;
+    A.dphi = dphi;
+    const size_t crows = ss_chunk_rows(L);
+    float2 *coef = (float2 *)(tb + L.off_coef);
+    for (size_t r0 = 0; r0 < L.rows; r0 += crows) {
+        const int n = (int)std::min(crows, L.rows - r0);
+        if (!dispatch_ss_rows(nphi, d_H, self, A, r0, n, chunk, s)) return SG_ERR_UNSUPPORTED;
+        SG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ss_transpose, dim3((n + 31) / 32, (L.ncol + 31) / 32), dim3(256), 0, s, chunk, n,
+                           L.ncol, coef, L.rows, r0);
+        SG_HIP(hipGetLastError());
+    }
+    sg_ss_header proto{};
+    proto.magic = SG_SS_MAGIC;
+    proto.version = 1;
+    proto.n_r = nr;
+    proto.n_phi = nphi;
+    proto.n_fluids = nf;
+    proto.flags = flags | SG_SEMI_SPECTRAL;
+    proto.r_min = grid->r_min;
+    proto.r_max = grid->r_max;
+    proto.total_bytes = L.total;
+    hipLaunchKernelGGL(k_ss_header, dim3(1), dim3(1), 0, s, (sg_ss_header *)tb, proto);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+// ------------------------------------------------------------ middle pass
+// 16-byte load of two consecutive complex values at element offset i of a
+// wave-uniform base (i even).
+__device__ inline void ss_ld4(const float2 *p, uint32_t i, float2 &x, float2 &y)
+{
+    const sg_v4f v = *(sg_gcv4f *)((const char *)p + (i << 3));
+    x = make_float2(v.x, v.y);
+    y = make_float2(v.z, v.w);
+}
+
+// Workgroup job (disc, m, b, target block): 256 threads in S row splits of
+// LN = 256 / S lanes; lane l owns targets i0 .. i0 + V - 1, i0 = block TB +
+// V l (TB = LN V), and split s sums the source rows i' = s (mod S) of every
+// source fluid; the splits are combined through LDS.  Sigma~_a(m, .) of all
+// sources is staged in LDS first (broadcast reads in the sum).  The operator
+// rows are streamed once: this pass is bound by reading the table.
+template <int NF, int V, int S>
+__global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJob *wj, int nj, const float2 *,
+                                                 int kc)
+{
+    extern __shared__ __attribute__((aligned(16))) float2 ssh[];
+    constexpr int LN = 256 / S, TB = LN * V, U = 8;
+    static_assert(V % 2 == 0, "targets per lane come in 16-byte pairs");
+    const int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
+    if (w >= nj) return;
+    if (sg_uniform(wj[w].n) == 0) return;  // cluster padding
+    const int cd = sg_uniform(wj[w].disc), idx = sg_uniform(wj[w].base);
+    const DiscDev *D = discs + cd;
+    const int nr = D->nr, nrt = (nr + 1) & ~1, nb = (nr + TB - 1) / TB;
+    const int blk = idx % nb, mb = idx / nb, b = mb % NF, m = mb / NF;
+    const size_t fs = sg_blk_field_elems(D->nphi, nr);
+    for (int e = threadIdx.x; e < NF * nr; e += 256) {
+        const int a = e / nr, ip = e - a * nr;
+        ssh[e] = gld2(D->st + a * fs, (uint32_t)sg_blk_index(m, ip, nr));
+    }
+    __syncthreads();
+    const int ln = threadIdx.x % LN, sp = threadIdx.x / LN;
+    const int i0 = blk * TB + V * ln;
+    // column of each target pair; pairs past the last row read column 0
+    uint32_t col[V / 2];
+#pragma unroll
+    for (int v = 0; v < V; v += 2) col[v / 2] = i0 + v < nr ? (uint32_t)(i0 + v) : 0u;
+    float2 ar[V], ap[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ar[v] = ap[v] = make_float2(0.f, 0.f);
+    const size_t slice = (size_t)nr * nrt;
+    for (int a = 0; a < NF; ++a) {
+        const float2 *Tm = D->spec + ((size_t)(m * NF + b) * NF + a) * slice;
+        const float2 *sa = ssh + a * nr;
+        int ip = sp;
+        for (; ip + S * (U - 1) < nr; ip += S * U) {
+            float2 t[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < V; v += 2)
+                    ss_ld4(Tm, (uint32_t)(ip + S * u) * nrt + col[v / 2], t[u][v], t[u][v + 1]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float2 s = sa[ip + S * u];
+#pragma unroll
+                for (int v = 0; v < V; v += 2) {
+                    // t = (T_r, t_phi) of targets i0 + v, i0 + v + 1
+                    ar[v].x += t[u][v].x * s.x;
+                    ar[v].y += t[u][v].x * s.y;
+                    ap[v].x += t[u][v].y * s.x;
+                    ap[v].y += t[u][v].y * s.y;
+                    ar[v + 1].x += t[u][v + 1].x * s.x;
+                    ar[v + 1].y += t[u][v + 1].x * s.y;
+                    ap[v + 1].x += t[u][v + 1].y * s.x;
+                    ap[v + 1].y += t[u][v + 1].y * s.y;
+                }
+            }
+        }
+        for (; ip < nr; ip += S) {
+            const float2 s = sa[ip];
+#pragma unroll
+            for (int v = 0; v < V; v += 2) {
+                float2 x, y;
+                ss_ld4(Tm, (uint32_t)ip * nrt + col[v / 2], x, y);
+                ar[v].x += x.x * s.x;
+                ar[v].y += x.x * s.y;
+                ap[v].x += x.y * s.x;
+                ap[v].y += x.y * s.y;
+                ar[v + 1].x += y.x * s.x;
+                ar[v + 1].y += y.x * s.y;
+                ap[v + 1].x += y.y * s.x;
+                ap[v + 1].y += y.y * s.y;
+            }
+        }
+    }
+    if constexpr (S > 1) {
+        // combine the row splits: partials after the staged column
+        float2 *red = ssh + ((NF * nr + 1) & ~1);
+        if (sp > 0) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                red[((sp - 1) * LN + ln) * 2 * V + 2 * v] = ar[v];
+                red[((sp - 1) * LN + ln) * 2 * V + 2 * v + 1] = ap[v];
+            }
+        }
+        __syncthreads();
+        if (sp > 0) return;
+#pragma unroll
+        for (int k = 0; k < S - 1; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float2 x = red[(k * LN + ln) * 2 * V + 2 * v], y = red[(k * LN + ln) * 2 * V + 2 * v + 1];
+                ar[v].x += x.x;
+                ar[v].y += x.y;
+                ap[v].x += y.x;
+                ap[v].y += y.y;
+            }
+    }
+    float2 *gr = D->gh + (size_t)(b * 2) * fs, *gp = gr + fs;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = i0 + v;
+        if (i < nr) {
+            const uint32_t o = (uint32_t)sg_blk_index(m, i, nr);
+            gst2(gr, o, ar[v]);
+            gst2(gp, o, make_float2(-ap[v].y, ap[v].x));  // i t_phi Sigma~
+        }
+    }
+}
+
+template <int NF, int V, int S> static SsPassInfo ss_info()
+{
+    constexpr int LN = 256 / S;
+    SsPassInfo k;
+    k.fn = k_ss_pass<NF, V, S>;
+    k.wgs = 256;
+    k.tb = LN * V;
+    k.lds_per_row = NF * (int)sizeof(float2);
+    // column padded to an even count, then the split partials
+    k.lds_fixed = (int)sizeof(float2) * (1 + (S > 1 ? (S - 1) * LN * 2 * V : 0));
+    return k;
+}
+
+bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out)
+{
+    if (nf != 1 && nf != 2) return false;
+    switch (variant) {
+    case 1: out = nf == 1 ? ss_info<1, 2, 4>() : ss_info<2, 2, 4>(); return true;
+    case 2: out = nf == 1 ? ss_info<1, 2, 1>() : ss_info<2, 2, 1>(); return true;
+    case 3: out = nf == 1 ? ss_info<1, 4, 1>() : ss_info<2, 4, 1>(); return true;
+    default: return false;
+    }
+}
+
+// Narrow radial grids split the source rows (enough workgroups per mode);
+// wide ones stream whole operator rows per workgroup.
+int sg_ss_default_variant(int nr) { return nr >= 768 ? 3 : (nr >= 384 ? 2 : 1); }

@@ -26,6 +26,7 @@ sg_status sg_self_cell_launch(const sg_grid *grid, const double *ha, const doubl
 sg_status sg_eval_F_launch(const void *x, void *F, void *dF, int64_t n, sg_dtype dt, hipStream_t s);
 sg_status sg_eval_G0_launch(const void *x, void *G, int64_t n, sg_dtype dt, hipStream_t s);
 
+__global__ void k_twiddles(float2 *tw_u, int nu, float2 *tw_phi, int nphi);
 __global__ void k_self_cell(SelfItems items, double *out, double du, double dphi, GLNodes gl);
 template <typename T>
 __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double lnrmin, double du,

@@ -5,11 +5,12 @@ from __future__ import annotations
 
 import torch
 
-from . import (F32, F64, SELF_CELL_EXCLUDE, WITH_DH, field_adjoint, field_adjoint_workspace_bytes,
-               field_fft_tune, potential_direct, potential_direct_workspace_bytes,
-               field_direct, field_direct_workspace_bytes, field_fft, field_fft_workspace_bytes,
-               fluids, grid, kernel_table, kernel_table_bytes, kernel_table_workspace_bytes,
-               make_disc)
+from . import (F32, F64, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, field_adjoint,
+               field_adjoint_workspace_bytes, field_fft_tune, potential_direct,
+               potential_direct_workspace_bytes, field_direct, field_direct_workspace_bytes, field_fft,
+               field_fft_workspace_bytes, fluids, grid, kernel_table, kernel_table_bytes,
+               kernel_table_workspace_bytes, make_disc, ss_table, ss_table_bytes,
+               ss_table_workspace_bytes)
 
 
 def _dev(device):
@@ -67,6 +68,47 @@ class FFTField:
     def tune(self, stream=None):
         """Autotunes this batch (sg_field_fft_tune); later runs use the choices."""
         return field_fft_tune(self.discs, self.ws, stream=stream)
+
+
+class SemiSpectral:
+    """One disc on the semi-spectral path (any H_f(r)): a persistent table,
+    Sigma and outputs.  refresh(H) rebuilds the radial operators for new
+    scale heights in place (the cached graph stays valid); run() solves."""
+
+    def __init__(self, n_r, n_phi, r_min, r_max, n_fluids, flags=0, device=None):
+        dev = _dev(device)
+        self.device = dev
+        self.g = grid(n_r, n_phi, r_min, r_max)
+        self.nf = int(n_fluids)
+        self.flags = int(flags) & ~SEMI_SPECTRAL
+        nb = ss_table_bytes(self.g, self.nf)
+        if nb == 0:
+            raise ValueError("unsupported grid for the semi-spectral path")
+        self.table = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.tws = None
+        shape = (self.nf, n_r, n_phi)
+        self.sigma = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.g_r = torch.empty(shape, dtype=torch.float32, device=dev)
+        self.g_phi = torch.empty(shape, dtype=torch.float32, device=dev)
+        self.disc = make_disc(self.g, fluids([1.0] * self.nf), self.flags | SEMI_SPECTRAL, self.sigma,
+                              self.g_r, self.g_phi, self.table)
+        self.ws = torch.empty(max(1, field_fft_workspace_bytes([self.disc])), dtype=torch.uint8,
+                              device=dev)
+
+    def refresh(self, H, stream=None):
+        """H: [n_fluids][n_r] scale heights at the ring centres (any dtype)."""
+        Hd = torch.as_tensor(H, dtype=torch.float64).to(self.device).contiguous()
+        if self.tws is None:
+            self.tws = torch.empty(ss_table_workspace_bytes(self.g, self.nf), dtype=torch.uint8,
+                                   device=self.device)
+        self._H = Hd
+        ss_table(self.g, self.nf, Hd, self.flags, self.table, self.tws, stream=stream)
+
+    def release_workspace(self):
+        self.tws = None
+
+    def run(self, stream=None):
+        field_fft([self.disc], self.ws, stream=stream)
 
 
 def direct(g, h, sigma, H=None, flags=0, stream=None):

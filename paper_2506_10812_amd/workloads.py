@@ -21,6 +21,17 @@ H/r constant for the FFT method, Sect. 4 and Sect. 5.2):
   adjoint       256 x 512 two-fluid, h_g = 0.05, h_d = 0.01 (H_d = 0.2 H_g); target
                 Sigma* with the bifluid_fft recipe (seed A), evaluation
                 Sigma = Sigma* (1 + 0.1 U(-1,1)) (seed B)
+  flaring       the App. D setup for the semi-spectral path: r in [20, 250] (AU),
+                r_0 = 100, Sigma = (r/r_0)^-1.5 (1 + 0.1 cos(2 phi - 4 ln r))
+                (1 + 0.01 U(-1,1)); gas H_g/r = 0.05 (r/r_0)^p (power-law flaring)
+                times sqrt(1 - 0.95 exp(-((r - r_0)/w)^2)) when a temperature gap of
+                width w is asked for; optional dust with H_d = eta H_g and the
+                clumpy recipe of bifluid_fft.  Default 1200 x 2048 (App. D uses
+                1200 x 2800; the azimuthal transforms take powers of two).
+  exponential   the Sect. 4.3 validation disc: Sigma = Sigma_0 exp(-r/r_0), Sigma_0 = 200,
+                r_0 = 250, r in [0.01, 2500] (AU), axisymmetric; H/r^q = h with q = 1
+                (H = h r, the FFT path) or q = 0 (H = h constant, the semi-spectral
+                path).  The paper uses 1200 x 2800.
 """
 from __future__ import annotations
 
@@ -114,3 +125,32 @@ def sample_cells(n_r, n_phi, n, seed=7):
     rng = np.random.default_rng(seed)
     N = n_r * n_phi
     return np.sort(rng.choice(N, size=min(n, N), replace=False)).astype(np.int64)
+
+
+def flaring(seed=8, n_r=1200, n_phi=2048, p=0.25, gap_w=None, n_fluids=1, eta=0.1):
+    """Per-ring scale heights H [n_fluids][n_r] and Sigma [n_fluids][n_r][n_phi]."""
+    rng = np.random.default_rng(seed)
+    r_min, r_max, r0 = 20.0, 250.0, 100.0
+    r, phi = centres(n_r, n_phi, r_min, r_max)
+    R, P = np.meshgrid(r, phi, indexing="ij")
+    gas = (R / r0) ** -1.5 * (1 + 0.1 * np.cos(2 * P - 4 * np.log(R)))
+    gas = gas * (1 + 0.01 * rng.uniform(-1, 1, gas.shape))
+    h = 0.05 * (r / r0) ** p
+    if gap_w is not None:
+        h = h * np.sqrt(1 - 0.95 * np.exp(-((r - r0) / gap_w) ** 2))
+    H = [h * r]
+    sig = [gas]
+    if n_fluids == 2:
+        sig.append(_clumpy_dust(gas, rng))
+        H.append(eta * h * r)
+    return dict(name="flaring", n_r=n_r, n_phi=n_phi, r_min=r_min, r_max=r_max, p=p, gap_w=gap_w,
+                H=np.stack(H), sigma=np.stack(sig))
+
+
+def exponential(n_r=1024, n_phi=2048, h=0.001, q=1):
+    """Axisymmetric exponential disc; H [1][n_r] per ring (h r^q)."""
+    r_min, r_max, r0, sig0 = 0.01, 2500.0, 250.0, 200.0
+    r, _ = centres(n_r, n_phi, r_min, r_max)
+    sig = np.repeat((sig0 * np.exp(-r / r0))[:, None], n_phi, axis=1)
+    return dict(name="exponential", n_r=n_r, n_phi=n_phi, r_min=r_min, r_max=r_max, r0=r0,
+                sigma0=sig0, h=[h], q=q, H=(h * r ** q)[None, :], sigma=sig[None])

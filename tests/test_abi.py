@@ -124,3 +124,43 @@ def test_adjoint_needs_dh_table(sg):
     assert need > 0
     st = sg.lib().sg_field_adjoint(ctypes.byref(d), 256, 512, 768, 1024, 2048, need, None)
     assert st == sg.ERR_TABLE
+
+
+def test_semispectral_sizes_and_validation(sg):
+    """sg_ss_table sizes are host-computable for any n_r; unsupported grids,
+    bad flags and short workspaces are refused before any launch; semi-spectral
+    discs pass the FFT-path checks with their own grid rules."""
+    L = sg.lib()
+    for nr in (1, 2, 37, 1200, 2048):
+        g = sg.grid(nr, 64, 20.0, 250.0)
+        nrt = nr + (nr & 1)
+        core = 33 * 4 * nr * nrt * 8
+        nb = sg.ss_table_bytes(g, 2)
+        assert core < nb < core + 4096, (nr, nb)
+        assert sg.ss_table_workspace_bytes(g, 2) > 0
+    for nr, nphi in ((2049, 64), (16, 2), (16, 12), (16, 4096), (0, 64)):
+        assert sg.ss_table_bytes(sg.grid(nr, nphi, 20.0, 250.0), 1) == 0
+    g = sg.grid(37, 32, 20.0, 250.0)
+    need = sg.ss_table_workspace_bytes(g, 2)
+    call = lambda nf, H, flags, tab, ws, n: L.sg_ss_table(ctypes.byref(g), nf, H, flags, tab, ws, n, None)
+    assert call(2, 256, 0, 512, 1024, need - 1) == sg.ERR_WORKSPACE
+    assert call(2, None, 0, 512, 1024, need) == sg.ERR_ARG
+    assert call(3, 256, 0, 512, 1024, need) == sg.ERR_ARG
+    assert call(2, 256, sg.WITH_DH, 512, 1024, need) == sg.ERR_ARG
+    assert call(2, 256, 0, 520, 1024, need) == sg.ERR_ARG  # table alignment
+    bad = sg.grid(37, 48, 20.0, 250.0)
+    assert L.sg_ss_table(ctypes.byref(bad), 1, 256, 0, 512, 1024, 1 << 40, None) == sg.ERR_UNSUPPORTED
+    # discs: odd n_r passes only with SG_SEMI_SPECTRAL; h is not read
+    f = sg.fluids([0.05, 0.01])
+    f.h[0] = -1.0
+    d = sg.Disc(g, f, sg.SEMI_SPECTRAL, 0, 256, 512, 768, 1024)
+    assert sg.field_fft_workspace_bytes([d]) > 0
+    d.flags = 0
+    assert sg.field_fft_workspace_bytes([d]) == 0
+    d.flags = sg.SEMI_SPECTRAL | sg.WITH_DH
+    assert sg.field_fft_workspace_bytes([d]) == 0
+    d.flags = sg.SEMI_SPECTRAL | sg.INDIRECT | sg.SELF_CELL_EXCLUDE
+    assert sg.field_fft_workspace_bytes([d]) > 0
+    # no adjoint for semi-spectral discs
+    assert sg.field_adjoint_workspace_bytes(d) == 0
+    assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, None, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED

@@ -1,0 +1,222 @@
+"""Semi-spectral path (sg_ss_table, then sg_field_fft on discs flagged
+SG_SEMI_SPECTRAL) through the C ABI against the CPU FP64 oracle's plain
+pairwise sum with the per-ring scale heights broadcast to every cell.
+
+The method is exact for the discrete sum (azimuthal transforms of a circular
+convolution, direct radial sums), so the bound is the float one used for the
+FFT path: 1e-5 relative RMS per fluid and component, and 1e-4 of max |g| in
+the max norm.  Workloads: the App. D flaring setup (power-law flaring,
+temperature gap), scaled down so that the oracle finishes in seconds, with
+ragged row counts (odd n_r, blocks of 128 and 1024 target rows cut short)."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_10812_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def T(sg):
+    from paper_2506_10812_amd import torch_ops
+    return torch_ops
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2506_10812_amd import workloads
+    return workloads
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_ss(T, w, flags=0):
+    nf = w["sigma"].shape[0]
+    S = T.SemiSpectral(w["n_r"], w["n_phi"], w["r_min"], w["r_max"], nf, flags)
+    S.refresh(w["H"])
+    S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+    S.run()
+    torch.cuda.synchronize()
+    return S, S.g_r.cpu().numpy().astype(np.float64), S.g_phi.cpu().numpy().astype(np.float64)
+
+
+def oracle_field(w, flags=0, targets=None):
+    """Pairwise sum with H_f(r_i) at every cell of ring i; float32-rounded Sigma."""
+    nf, nr, nphi = w["sigma"].shape
+    sig = w["sigma"].astype(np.float32).astype(np.float64)
+    Hc = np.repeat(w["H"][:, :, None], nphi, axis=2)
+    return O.field_pairwise(nr, nphi, w["r_min"], w["r_max"], [0.0] * nf, sig, H=Hc, targets=targets,
+                            flags=flags & O.EXCLUDE_SELF)
+
+
+def check(gr, gp, rr, rp, nf, rms=1e-5, mx=1e-4):
+    gr = gr.reshape(nf, -1)
+    gp = gp.reshape(nf, -1)
+    scale = float(np.sqrt(rr ** 2 + rp ** 2).max())
+    for f in range(nf):
+        er, ep = rel_rms(gr[f], rr[f]), rel_rms(gp[f], rp[f])
+        mr = float(np.abs(gr[f] - rr[f]).max()) / scale
+        mp = float(np.abs(gp[f] - rp[f]).max()) / scale
+        say(f"  fluid {f}: rel-RMS g_r {er:.2e} g_phi {ep:.2e}; max/max|g| {mr:.2e} {mp:.2e}")
+        assert er < rms and ep < rms and mr < mx and mp < mx, (f, er, ep, mr, mp)
+
+
+@pytest.mark.parametrize("nr,nphi,nf,p,gap", [
+    (37, 32, 2, 0.25, None),     # odd n_r: padded target column and row quad
+    (1, 4, 1, 0.5, None),        # one ring, smallest transform
+    (5, 8, 2, 0.125, None),
+    (64, 64, 1, 0.0, 20.0),      # temperature gap only
+    (130, 16, 2, 0.5, 10.0),     # second block of 128 target rows cut short
+])
+def test_semispectral_matches_pairwise_oracle(sg, T, W, nr, nphi, nf, p, gap):
+    say(f"semi-spectral {nr}x{nphi} nf={nf} p={p} gap={gap}")
+    w = W.flaring(seed=nr + nphi, n_r=nr, n_phi=nphi, p=p, gap_w=gap, n_fluids=nf)
+    _, gr, gp = run_ss(T, w)
+    rr, rp = oracle_field(w)
+    check(gr, gp, rr, rp, nf)
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(300, 32, 2), (700, 16, 1), (1024, 64, 2)])
+def test_semispectral_wide_grids_sampled(sg, T, W, nr, nphi, nf):
+    """The three middle-pass shapes (row splits, whole-row streaming with 2 and
+    4 targets per lane) at sizes where the oracle computes sampled cells."""
+    say(f"semi-spectral sampled {nr}x{nphi} nf={nf}")
+    w = W.flaring(seed=nr, n_r=nr, n_phi=nphi, p=0.25, gap_w=15.0, n_fluids=nf)
+    _, gr, gp = run_ss(T, w)
+    cells = W.sample_cells(nr, nphi, 48, seed=nr)
+    cells = np.unique(np.concatenate([cells, [0, nr * nphi - 1]]))
+    rr, rp = oracle_field(w, targets=cells)
+    gr = gr.reshape(nf, -1)[:, cells]
+    gp = gp.reshape(nf, -1)[:, cells]
+    check(gr, gp, rr, rp, nf, rms=2e-5)
+
+
+def test_semispectral_equals_fft_path_for_constant_h(sg, T, W):
+    """With H_f = h_f r both paths compute the same discrete sum."""
+    say("semi-spectral vs FFT path, H = h r")
+    wf = W.bifluid_fft(seed=11, n_r=64, n_phi=128)
+    F = T.FFTField([wf])
+    F.set_sigma(0, wf["sigma"])
+    F.run()
+    r, _, _, _ = O.grid(64, 128, wf["r_min"], wf["r_max"])
+    w = dict(wf)
+    w["H"] = np.stack([h * r for h in wf["h"]])
+    _, gr, gp = run_ss(T, w)
+    torch.cuda.synchronize()
+    fr = F.g_r[0].cpu().numpy().astype(np.float64)
+    fp = F.g_phi[0].cpu().numpy().astype(np.float64)
+    for f in range(2):
+        er, ep = rel_rms(gr[f], fr[f]), rel_rms(gp[f], fp[f])
+        say(f"  fluid {f}: rel-RMS g_r {er:.2e} g_phi {ep:.2e}")
+        assert er < 1e-5 and ep < 1e-5
+
+
+def test_semispectral_exclude_self(sg, T, W):
+    say("semi-spectral without the self term")
+    w = W.flaring(seed=3, n_r=24, n_phi=32, p=0.25, n_fluids=2)
+    _, gr, gp = run_ss(T, w, flags=sg.SELF_CELL_EXCLUDE)
+    rr, rp = oracle_field(w, flags=O.EXCLUDE_SELF)
+    check(gr, gp, rr, rp, 2)
+
+
+@pytest.mark.parametrize("nr,nphi,nf", [(20, 32, 2), (33, 16, 1)])
+def test_semispectral_indirect(sg, T, W, nr, nphi, nf):
+    """SG_INDIRECT folded into mode 1 of the table, against the oracle's
+    pairwise sum plus its indirect field (per-cell H in K_a)."""
+    say(f"semi-spectral indirect {nr}x{nphi} nf={nf}")
+    w = W.flaring(seed=nr + 1, n_r=nr, n_phi=nphi, p=0.25, n_fluids=nf)
+    phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    w["sigma"] = w["sigma"] * (1 + 0.3 * np.cos(phi - 1.0))[None, None, :]
+    _, gr, gp = run_ss(T, w, flags=sg.INDIRECT)
+    rr, rp = oracle_field(w)
+    sig = w["sigma"].astype(np.float32).astype(np.float64)
+    Hc = np.repeat(w["H"][:, :, None], nphi, axis=2)
+    AB = O.indirect(nr, nphi, w["r_min"], w["r_max"], [0.0] * nf, sig, H=Hc)
+    ir, ip = O.indirect_field(nr, nphi, AB)
+    check(gr, gp, rr + ir[None, :], rp + ip[None, :], nf)
+    # the indirect part alone
+    _, hr, hp = run_ss(T, w)
+    dr = (gr - hr).reshape(nf, -1)
+    dp = (gp - hp).reshape(nf, -1)
+    for f in range(nf):
+        er, ep = rel_rms(dr[f], ir), rel_rms(dp[f], ip)
+        say(f"  indirect part fluid {f}: rel-RMS {er:.2e} {ep:.2e}")
+        assert er < 1e-4 and ep < 1e-4
+
+
+def test_semispectral_refresh_in_place(sg, T, W):
+    """A second sg_ss_table into the same table (new H, same buffers: the
+    cached graph is reused) gives the field of the new H."""
+    say("semi-spectral refresh of H in place")
+    w1 = W.flaring(seed=5, n_r=40, n_phi=32, p=0.0, n_fluids=2)
+    w2 = W.flaring(seed=5, n_r=40, n_phi=32, p=0.5, gap_w=20.0, n_fluids=2)
+    S, gr1, gp1 = run_ss(T, w1)
+    check(gr1, gp1, *oracle_field(w1), 2)
+    S.refresh(w2["H"])
+    S.run()
+    torch.cuda.synchronize()
+    gr2 = S.g_r.cpu().numpy().astype(np.float64)
+    gp2 = S.g_phi.cpu().numpy().astype(np.float64)
+    check(gr2, gp2, *oracle_field(w2), 2)
+    assert rel_rms(gr2, gr1) > 1e-3
+
+
+def test_semispectral_mixed_batch(sg, T, W):
+    """A semi-spectral disc and an FFT-path disc in one sg_field_fft call give
+    what each gives alone."""
+    say("mixed batch: semi-spectral + FFT path")
+    wss = W.flaring(seed=9, n_r=50, n_phi=64, p=0.25, n_fluids=2)
+    wff = W.bifluid_fft(seed=12, n_r=32, n_phi=64)
+    S, gr_s, gp_s = run_ss(T, wss)
+    F = T.FFTField([wff])
+    F.set_sigma(0, wff["sigma"])
+    F.run()
+    torch.cuda.synchronize()
+    ref_f = (F.g_r[0].cpu().numpy().copy(), F.g_phi[0].cpu().numpy().copy())
+    S.g_r.zero_()
+    F.g_r[0].zero_()
+    ws = torch.empty(sg.field_fft_workspace_bytes([S.disc, F.discs[0]]), dtype=torch.uint8, device="cuda")
+    sg.field_fft([S.disc, F.discs[0]], ws)
+    torch.cuda.synchronize()
+    for a, b in ((S.g_r.cpu().numpy(), gr_s), (S.g_phi.cpu().numpy(), gp_s),
+                 (F.g_r[0].cpu().numpy(), ref_f[0]), (F.g_phi[0].cpu().numpy(), ref_f[1])):
+        e = rel_rms(a.astype(np.float64), b.astype(np.float64))
+        say(f"  batch vs alone rel-RMS {e:.2e}")
+        assert e < 1e-6
+
+
+def test_semispectral_tuner(sg, T, W):
+    """The autotuner's candidates for the middle pass (three shapes x four
+    cluster sizes) must reproduce the default before being timed; the tuned
+    launch still matches the oracle."""
+    say("semi-spectral autotuner")
+    w = W.flaring(seed=21, n_r=300, n_phi=16, p=0.25, n_fluids=2)
+    S, _, _ = run_ss(T, w)
+    res = sg.field_fft_tune([S.disc], S.ws)
+    mid = [r for r in res if r["pass"] == 2]
+    say(f"  {mid}")
+    assert len(mid) == 1 and mid[0]["length"] == 300
+    assert mid[0]["rejected"] == 0 and mid[0]["candidates"] >= 10
+    S.g_r.zero_()
+    S.run()
+    torch.cuda.synchronize()
+    cells = W.sample_cells(300, 16, 40, seed=2)
+    rr, rp = oracle_field(w, targets=cells)
+    check(S.g_r.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64),
+          S.g_phi.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64), rr, rp, 2, rms=2e-5)

@@ -1,0 +1,87 @@
+"""Validation against closed forms at the paper's resolution (Sect. 4.3): the
+razor-thin exponential disc, whose radial acceleration is known exactly
+(Freeman's disc): g_r = -2 pi G Sigma_0 y [I0(y) K0(y) - I1(y) K1(y)],
+y = r/(2 r_0).  The exact Bessel kernel tends to the razor-thin one as H -> 0,
+and the paper finds the relative error levelling off near 1e-4 for small
+aspect ratios.  Run on the FFT path (H = h r, q = 1) and on the
+semi-spectral path (H constant, q = 0), as the paper does with its two codes.
+The comparison uses y in [0.05, 2.5]: the field vanishes at y = 0 (relative
+error meaningless there, as the paper notes) and the grid's outer edge at
+y = 5 truncates the disc."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+special = pytest.importorskip("scipy.special")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_10812_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def T(sg):
+    from paper_2506_10812_amd import torch_ops
+    return torch_ops
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2506_10812_amd import workloads
+    return workloads
+
+
+def freeman(r, r0, sig0):
+    y = r / (2 * r0)
+    # I_n(y) K_n(y) = i_ne(y) k_ne(y): the exponential scalings cancel
+    b = special.i0e(y) * special.k0e(y) - special.i1e(y) * special.k1e(y)
+    return -2 * np.pi * sig0 * y * b, y
+
+
+def errors(w, gr):
+    r = np.exp(np.log(w["r_min"]) + (np.arange(w["n_r"]) + 0.5) * np.log(w["r_max"] / w["r_min"]) / w["n_r"])
+    ref, y = freeman(r, w["r0"], w["sigma0"])
+    prof = gr.reshape(w["n_r"], w["n_phi"]).mean(axis=1)
+    spread = float(np.abs(gr.reshape(w["n_r"], w["n_phi"]) - prof[:, None]).max() / np.abs(ref).max())
+    sel = (y >= 0.05) & (y <= 2.5)
+    rel = np.abs(prof[sel] - ref[sel]) / np.abs(ref[sel])
+    return float(np.median(rel)), float(rel.max()), spread
+
+
+@pytest.mark.parametrize("h,med_bar,max_bar", [(0.01, 2e-2, 5e-2), (0.001, 1e-3, 5e-3)])
+def test_exponential_disc_fft_path(sg, T, W, h, med_bar, max_bar):
+    print(f"exponential disc, FFT path, H = {h} r, 1024x2048", flush=True)
+    w = W.exponential(h=h, q=1)
+    F = T.FFTField([dict(w, h=[h])])
+    F.set_sigma(0, w["sigma"])
+    F.run()
+    torch.cuda.synchronize()
+    med, mx, spread = errors(w, F.g_r[0][0].double().cpu().numpy())
+    print(f"  relative error vs Freeman: median {med:.2e} max {mx:.2e}; azimuthal spread {spread:.1e}",
+          flush=True)
+    assert spread < 1e-5
+    assert med < med_bar and mx < max_bar
+
+
+@pytest.mark.parametrize("H,med_bar,max_bar", [(0.01, 1e-3, 5e-3)])
+def test_exponential_disc_semispectral(sg, T, W, H, med_bar, max_bar):
+    """The paper's N_r = 1200 (any n_r on this path), constant H (q = 0)."""
+    print(f"exponential disc, semi-spectral, H = {H}, 1200x2048", flush=True)
+    w = W.exponential(n_r=1200, n_phi=2048, h=H, q=0)
+    S = T.SemiSpectral(w["n_r"], w["n_phi"], w["r_min"], w["r_max"], 1)
+    S.refresh(w["H"])
+    S.release_workspace()
+    S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+    S.run()
+    torch.cuda.synchronize()
+    med, mx, spread = errors(w, S.g_r[0].double().cpu().numpy())
+    print(f"  relative error vs Freeman: median {med:.2e} max {mx:.2e}; azimuthal spread {spread:.1e}",
+          flush=True)
+    assert spread < 1e-5
+    assert med < med_bar and mx < max_bar
