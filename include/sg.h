@@ -164,16 +164,29 @@ sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint
  * fluids and flags (checked on the host from the arguments, not the device),
  * or, with SG_SEMI_SPECTRAL in flags, by sg_ss_table for the same grid and
  * fluid count.
+ *
+ * Species sharing kernels (Sect. 5.2, multi-fluid case): the kernels depend
+ * on the scale heights only, so species with a common scale height share
+ * one kernel group; the paper's example is gas plus two dust species of
+ * equal H_d (four kernels, six convolutions).  With n_species = S in
+ * [1, 8], sigma holds S species [S][n_r][n_phi] and species s belongs to
+ * group species_group[s] < n_fluids (the fluids of sg_fluids are then the
+ * kernel groups); each group's source density is the sum of its species
+ * (formed while the densities are read), and g_r, g_phi [n_fluids][...]
+ * are per group: every species of a group receives that group's
+ * acceleration.  n_species = 0: one density per fluid, species_group
+ * unused.  sg_field_adjoint returns SG_ERR_UNSUPPORTED for S > 0.
  * --------------------------------------------------------------------- */
 typedef struct sg_disc {
     sg_grid grid;
     sg_fluids fluids;
     uint32_t flags;      /* flags the table was built with                 */
-    uint32_t pad_;
-    const float *sigma;  /* device, [F][n_r][n_phi]                        */
+    int32_t n_species;   /* 0, or species summed into kernel groups (above) */
+    const float *sigma;  /* device, [F][n_r][n_phi] (or [S][n_r][n_phi])   */
     float *g_r;          /* device, [F][n_r][n_phi], overwritten           */
     float *g_phi;        /* device, [F][n_r][n_phi], overwritten           */
-    const void *table;   /* device, from sg_kernel_table                   */
+    const void *table;   /* device, from sg_kernel_table or sg_ss_table    */
+    uint8_t species_group[8]; /* kernel group of each species              */
 } sg_disc;
 
 /* ---------------------------------------------------------------------

@@ -40,8 +40,9 @@ class Fluids(ctypes.Structure):
 
 class Disc(ctypes.Structure):
     _fields_ = [("grid", Grid), ("fluids", Fluids), ("flags", ctypes.c_uint32),
-                ("pad_", ctypes.c_uint32), ("sigma", ctypes.c_void_p), ("g_r", ctypes.c_void_p),
-                ("g_phi", ctypes.c_void_p), ("table", ctypes.c_void_p)]
+                ("n_species", ctypes.c_int32), ("sigma", ctypes.c_void_p), ("g_r", ctypes.c_void_p),
+                ("g_phi", ctypes.c_void_p), ("table", ctypes.c_void_p),
+                ("species_group", ctypes.c_uint8 * 8)]
 
 
 class TuneResult(ctypes.Structure):
@@ -197,8 +198,12 @@ def ss_table(g: Grid, n_fluids, H, flags, table, ws, ws_bytes=None, stream=None)
                             ws_bytes, _stream(stream)), "sg_ss_table")
 
 
-def make_disc(g: Grid, f: Fluids, flags, sigma, g_r, g_phi, table) -> Disc:
-    return Disc(g, f, flags, 0, _ptr(sigma), _ptr(g_r), _ptr(g_phi), _ptr(table))
+def make_disc(g: Grid, f: Fluids, flags, sigma, g_r, g_phi, table, species_group=None) -> Disc:
+    """species_group: kernel group of each species of sigma ([S][n_r][n_phi]),
+    or None for one density per fluid."""
+    sp = list(species_group) if species_group is not None else []
+    grp = (ctypes.c_uint8 * 8)(*(sp + [0] * (8 - len(sp))))
+    return Disc(g, f, flags, len(sp), _ptr(sigma), _ptr(g_r), _ptr(g_phi), _ptr(table), grp)
 
 
 def field_fft(discs, ws, ws_bytes=None, stream=None):

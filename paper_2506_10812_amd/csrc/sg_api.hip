@@ -108,8 +108,19 @@ sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint
     return sg_ss_table_build(grid, n_fluids, d_H, flags, d_table, d_ws, (hipStream_t)stream);
 }
 
+// Species summed into kernel groups: 0 (one density per fluid) or 1..8
+// species, each in a group < n_fluids.
+static bool species_ok(const sg_disc &d)
+{
+    if (d.n_species < 0 || d.n_species > 8) return false;
+    for (int s = 0; s < d.n_species; ++s)
+        if (d.species_group[s] >= d.fluids.n_fluids) return false;
+    return true;
+}
+
 static sg_status check_disc(const sg_disc &d)
 {
+    if (!species_ok(d)) return SG_ERR_ARG;
     if (d.flags & SG_SEMI_SPECTRAL) {
         sg_status s = check_ss_grid(&d.grid);
         if (s != SG_OK) return s;
@@ -260,7 +271,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
 
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
 {
-    if (!disc || check_disc(*disc) != SG_OK || (disc->flags & SG_SEMI_SPECTRAL)) return 0;
+    if (!disc || check_disc(*disc) != SG_OK || (disc->flags & SG_SEMI_SPECTRAL) || disc->n_species) return 0;
     return sg_adjoint_ws_bytes(*disc);
 }
 
@@ -271,7 +282,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
-    if (disc->flags & (SG_INDIRECT | SG_SEMI_SPECTRAL)) return SG_ERR_UNSUPPORTED;
+    if ((disc->flags & (SG_INDIRECT | SG_SEMI_SPECTRAL)) || disc->n_species != 0) return SG_ERR_UNSUPPORTED;
     if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
     if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))
         return SG_ERR_WORKSPACE;

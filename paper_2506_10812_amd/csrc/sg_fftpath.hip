@@ -53,16 +53,32 @@ k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
     const LdsPlane<float> pl{lds + W * g};
     TwRegC<N, SF> tw;
     tw.load(twp, t);
-    // 1. two real rows as one complex transform
+    // 1. two real rows as one complex transform (with species: the sum of
+    //    the group's species rows, in species order)
     float2 z[P];
     {
         const int idx = g < cn ? cb + g : cb;
         const int f = idx / half, j = idx % half;
-        const uint32_t o = (uint32_t)f * nr * N + t;
-        const uint32_t o1 = o + (uint32_t)min(2 * j, nr - 1) * N;
-        const uint32_t o2 = o + (uint32_t)min(2 * j + 1, nr - 1) * N;
+        const uint32_t r1 = (uint32_t)min(2 * j, nr - 1) * N + t;
+        const uint32_t r2 = (uint32_t)min(2 * j + 1, nr - 1) * N + t;
+        if (sg_uniform(D->ns) == 0) {
+            const uint32_t o = (uint32_t)f * nr * N;
 #pragma unroll
-        for (int p = 0; p < P; ++p) z[p] = make_float2(gld1(D->sigma, o1 + T * p), gld1(D->sigma, o2 + T * p));
+            for (int p = 0; p < P; ++p)
+                z[p] = make_float2(gld1(D->sigma, o + r1 + T * p), gld1(D->sigma, o + r2 + T * p));
+        } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p) z[p] = make_float2(0.f, 0.f);
+            const int cnt = D->gcount[f];
+            for (int k = 0; k < cnt; ++k) {
+                const uint32_t o = (uint32_t)D->gsp[f][k] * nr * N;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    z[p].x += gld1(D->sigma, o + r1 + T * p);
+                    z[p].y += gld1(D->sigma, o + r2 + T * p);
+                }
+            }
+        }
     }
     fft<N, false>(z, t, pl, tw);
 #pragma unroll
@@ -608,6 +624,12 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.nphi = d.grid.n_phi;
         D.nf = d.fluids.n_fluids;
         D.flags = d.flags;
+        D.ns = d.n_species;
+        D.gcount[0] = D.gcount[1] = 0;
+        for (int s = 0; s < d.n_species; ++s) {
+            const int gp = d.species_group[s];
+            D.gsp[gp][D.gcount[gp]++] = (uint8_t)s;
+        }
     }
 }
 
@@ -658,6 +680,9 @@ static std::vector<uint64_t> signature(const sg_disc *discs, int n, void *ws)
         const sg_disc &d = discs[i];
         k.push_back(((uint64_t)d.grid.n_r << 32) | (uint32_t)d.grid.n_phi);
         k.push_back(((uint64_t)d.fluids.n_fluids << 32) | d.flags);
+        uint64_t sp = (uint64_t)(uint32_t)d.n_species;
+        for (int s = 0; s < 8 && s < d.n_species; ++s) sp |= (uint64_t)d.species_group[s] << (8 + 4 * s);
+        k.push_back(sp);
         k.push_back((uint64_t)(uintptr_t)d.sigma);
         k.push_back((uint64_t)(uintptr_t)d.g_r);
         k.push_back((uint64_t)(uintptr_t)d.g_phi);

@@ -28,6 +28,9 @@ struct DiscDev {
     const double *ind;      // table header: indirect-term coefficients [F]
     int nr, nphi, nf;
     uint32_t flags;
+    int ns;                 // species summed into groups (0: one density per fluid)
+    int gcount[2];          // species of each group
+    uint8_t gsp[2][8];      // their indices
 };
 
 // A job is (disc index, job index inside the disc); disc < 0 marks padding.

@@ -36,6 +36,9 @@ class FFTField:
     workspace and outputs (so the cached graph keeps stable addresses)."""
 
     def __init__(self, specs, flags=0, device=None):
+        """specs: dicts with n_r, n_phi, r_min, r_max, h (one aspect ratio per
+        kernel group) and optionally species_group (kernel group of each
+        species; Sigma then holds one density per species)."""
         dev = _dev(device)
         self.device = dev
         self.specs = []
@@ -45,16 +48,18 @@ class FFTField:
             g = grid(s["n_r"], s["n_phi"], s["r_min"], s["r_max"])
             f = fluids(s["h"])
             nf = len(s["h"])
+            groups = s.get("species_group")
             shape = (nf, s["n_r"], s["n_phi"])
             tab = build_table(g, f, flags, dev)
-            sig = torch.zeros(shape, dtype=torch.float32, device=dev)
+            ns = len(groups) if groups is not None else nf
+            sig = torch.zeros((ns, s["n_r"], s["n_phi"]), dtype=torch.float32, device=dev)
             gr = torch.empty(shape, dtype=torch.float32, device=dev)
             gp = torch.empty(shape, dtype=torch.float32, device=dev)
             self.tables.append(tab)
             self.sigma.append(sig)
             self.g_r.append(gr)
             self.g_phi.append(gp)
-            self.discs.append(make_disc(g, f, flags, sig, gr, gp, tab))
+            self.discs.append(make_disc(g, f, flags, sig, gr, gp, tab, groups))
             self.specs.append((g, f))
         self.ws = torch.empty(max(1, field_fft_workspace_bytes(self.discs)), dtype=torch.uint8,
                               device=dev)
@@ -75,7 +80,7 @@ class SemiSpectral:
     Sigma and outputs.  refresh(H) rebuilds the radial operators for new
     scale heights in place (the cached graph stays valid); run() solves."""
 
-    def __init__(self, n_r, n_phi, r_min, r_max, n_fluids, flags=0, device=None):
+    def __init__(self, n_r, n_phi, r_min, r_max, n_fluids, flags=0, device=None, species_group=None):
         dev = _dev(device)
         self.device = dev
         self.g = grid(n_r, n_phi, r_min, r_max)
@@ -87,11 +92,12 @@ class SemiSpectral:
         self.table = torch.empty(nb, dtype=torch.uint8, device=dev)
         self.tws = None
         shape = (self.nf, n_r, n_phi)
-        self.sigma = torch.zeros(shape, dtype=torch.float32, device=dev)
+        ns = len(species_group) if species_group is not None else self.nf
+        self.sigma = torch.zeros((ns, n_r, n_phi), dtype=torch.float32, device=dev)
         self.g_r = torch.empty(shape, dtype=torch.float32, device=dev)
         self.g_phi = torch.empty(shape, dtype=torch.float32, device=dev)
         self.disc = make_disc(self.g, fluids([1.0] * self.nf), self.flags | SEMI_SPECTRAL, self.sigma,
-                              self.g_r, self.g_phi, self.table)
+                              self.g_r, self.g_phi, self.table, species_group)
         self.ws = torch.empty(max(1, field_fft_workspace_bytes([self.disc])), dtype=torch.uint8,
                               device=dev)
 

@@ -164,3 +164,59 @@ def test_semispectral_sizes_and_validation(sg):
     # no adjoint for semi-spectral discs
     assert sg.field_adjoint_workspace_bytes(d) == 0
     assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, None, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED
+
+
+def test_struct_layouts_match_the_header(sg, tmp_path):
+    """The ctypes mirrors of sg_grid, sg_fluids, sg_disc and sg_tune_result
+    have the C layout (sizes and field offsets from a program built against
+    include/sg.h with the host compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = {"sg_grid": ("n_r", "n_phi", "r_min", "r_max"),
+              "sg_fluids": ("n_fluids", "h"),
+              "sg_disc": ("grid", "fluids", "flags", "n_species", "sigma", "g_r", "g_phi", "table",
+                          "species_group"),
+              "sg_tune_result": ("pass", "length", "cluster", "rel_best", "ms_best")}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for t, fs in fields.items():
+        lines.append(f'printf("{t} sizeof %zu\\n", sizeof({t}));')
+        for f in fs:
+            lines.append(f'printf("{t} {f} %zu\\n", offsetof({t}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, str(src), "-o", str(exe)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        t, f, v = ln.split()
+        got[(t, f)] = int(v)
+    mirror = {"sg_grid": sg.Grid, "sg_fluids": sg.Fluids, "sg_disc": sg.Disc, "sg_tune_result": sg.TuneResult}
+    for t, cls in mirror.items():
+        assert got[(t, "sizeof")] == ctypes.sizeof(cls), t
+        for f in fields[t]:
+            name = "pass_" if f == "pass" else f
+            assert got[(t, f)] == getattr(cls, name).offset, (t, f)
+
+
+def test_species_validation(sg):
+    g = sg.grid(16, 32, 0.2, 5.0)
+    f = sg.fluids([0.05, 0.005])
+    ok = sg.make_disc(g, f, 0, 256, 512, 768, 1024, species_group=[0, 1, 1])
+    assert ok.n_species == 3 and sg.field_fft_workspace_bytes([ok]) > 0
+    assert sg.field_fft_workspace_bytes([sg.make_disc(g, f, 0, 256, 512, 768, 1024, [0, 2])]) == 0
+    many = sg.make_disc(g, f, 0, 256, 512, 768, 1024, [0] * 8)
+    assert sg.field_fft_workspace_bytes([many]) > 0
+    many.n_species = 9
+    assert sg.field_fft_workspace_bytes([many]) == 0
+    many.n_species = -1
+    assert sg.field_fft_workspace_bytes([many]) == 0
+    one = sg.make_disc(g, sg.fluids([0.05]), 0, 256, 512, 768, 1024, [0, 1])
+    assert sg.field_fft_workspace_bytes([one]) == 0
+    # no adjoint for species discs
+    assert sg.field_adjoint_workspace_bytes(ok) == 0
+    assert sg.lib().sg_field_adjoint(ctypes.byref(ok), 256, 512, 768, None, 2048, 1 << 30,
+                                     None) == sg.ERR_UNSUPPORTED
