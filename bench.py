@@ -324,13 +324,12 @@ def main():
     print(json.dumps(out))
 
 
-def ss_bytes(nr, nphi, nf):
-    """Algorithmic HBM bytes of the semi-spectral middle pass: the radial
-    operators (F^2 n_r n_rt complex64 per mode), one read of the Sigma~
-    column of every source and one write of g^_r, g^_phi."""
-    ncol = nphi // 2 + 1
-    nrt = nr + (nr & 1)
-    return 8 * ncol * (nf * nf * nr * nrt + nf * nr + 2 * nf * nr)
+def ss_bytes(sg, g, nf, flags=0):
+    """Algorithmic HBM bytes of the semi-spectral middle pass: the stored
+    radial operators (the table, banded modes included), one read of the
+    Sigma~ column of every source and one write of g^_r, g^_phi."""
+    ncol = g.n_phi // 2 + 1
+    return sg.ss_table_bytes(g, nf, flags) + 8 * ncol * 3 * nf * g.n_r
 
 
 def semispectral_measurement(sg, T, W, dev, steps=20):
@@ -362,7 +361,7 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     ms_pass = sg.field_fft_profile([S.disc], S.ws, 10)
-    mid = ss_bytes(nr, nphi, nf)
+    mid = ss_bytes(sg, S.g, nf)
     ach = mid / (ms_pass[1] * 1e-3) / 1e9
     out = {"workload": f"App. D flaring gas disc {nr}x{nphi}, r in [20,250], p=0.25",
            "table_bytes": sg.ss_table_bytes(S.g, nf), "table_build_ms": round(build_ms, 2),

@@ -64,7 +64,8 @@ enum {
     SG_SELF_CELL_EXCLUDE = 1u, /* drop the own-cell term                      */
     SG_WITH_DH = 2u,           /* table also holds d/dh spectra (adjoint)     */
     SG_INDIRECT = 4u,          /* add the indirect term (see below)           */
-    SG_SEMI_SPECTRAL = 8u      /* disc uses a semi-spectral table (below)     */
+    SG_SEMI_SPECTRAL = 8u,     /* disc uses a semi-spectral table (below)     */
+    SG_SS_FULL = 16u           /* semi-spectral: keep every operator entry    */
 };
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
@@ -135,13 +136,24 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * rounded to float.  Refreshing H every few steps (Sect. 5.2) means calling
  * it again into the same table.
  *
+ * Banded modes: the kernels are analytic in phi for |Im phi| < |X|
+ * (X = u_i - u_i'), so the mode-m coupling of two rings decays like
+ * e^{-m |X|}.  Mode m keeps only the ring pairs with |i - i'| <= w_m,
+ * w_m = ceil(30 ln 2 / (m du)) (the dropped couplings are below about 2^-30
+ * of the axisymmetric coupling of the same pair), and is stored as 2 w_m + 1
+ * diagonals when 4 w_m + 2 <= n_r; m = 0 and wider modes are stored whole.
+ * On fine radial grids this shrinks the table and the solve's traffic from
+ * N_phi N_r^2 towards N_phi N_r log N_phi.  SG_SS_FULL stores every mode
+ * whole (the exact operators).
+ *
  * d_H: device double [n_fluids][n_r], H_f at the ring centres r_i
  * (r_i = r_min e^{(i + 1/2) du}), every value > 0 (not checked on the
  * device).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (the indirect term,
  * with K_a at d = r_i'/H_a(r_i'), folded into mode 1 of the table; no cost
- * at solve time).  Grid: n_phi a power of two in [4, 2048], n_r in
- * [1, 2048], any n_r.  Size: 8 (n_phi/2 + 1) F^2 n_r (n_r rounded up to
- * even) bytes plus a few KB; d_table 256-byte aligned, written completely.
+ * at solve time), SG_SS_FULL.  Grid: n_phi a power of two in [4, 2048], n_r
+ * in [1, 2048], any n_r.  Size: sg_ss_table_bytes() (at most
+ * 8 (n_phi/2 + 1) F^2 n_r n_rt bytes, n_rt = n_r rounded up to even, plus a
+ * few KB); d_table 256-byte aligned, written completely.
  * d_ws: sg_ss_table_workspace_bytes() bytes (<= about 130 MB), contents
  * undefined afterwards.  Asynchronous on `stream`.  The table is position
  * independent.
@@ -153,7 +165,7 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * discs mix freely with FFT-path discs in one batch.  sg_field_adjoint
  * returns SG_ERR_UNSUPPORTED for them.
  * --------------------------------------------------------------------- */
-size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids);
+size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids, uint32_t flags);
 size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids);
 sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint32_t flags,
                       void *d_table, void *d_ws, size_t ws_bytes, void *stream);

@@ -20,6 +20,7 @@ SELF_CELL_EXCLUDE = 1
 WITH_DH = 2
 INDIRECT = 4
 SEMI_SPECTRAL = 8
+SS_FULL = 16
 
 
 class SGError(RuntimeError):
@@ -74,7 +75,7 @@ def _load():
         "sg_kernel_table_bytes": (sz, [GP, FP, u32]),
         "sg_kernel_table_workspace_bytes": (sz, [GP, FP, u32]),
         "sg_kernel_table": (i32, [GP, FP, u32, vp, vp, sz, vp]),
-        "sg_ss_table_bytes": (sz, [GP, i32]),
+        "sg_ss_table_bytes": (sz, [GP, i32, u32]),
         "sg_ss_table_workspace_bytes": (sz, [GP, i32]),
         "sg_ss_table": (i32, [GP, i32, vp, u32, vp, vp, sz, vp]),
         "sg_field_fft_workspace_bytes": (sz, [DP, i32]),
@@ -157,8 +158,8 @@ def kernel_table_workspace_bytes(g: Grid, f: Fluids, flags: int = 0) -> int:
     return int(_lib.sg_kernel_table_workspace_bytes(ctypes.byref(g), ctypes.byref(f), flags))
 
 
-def ss_table_bytes(g: Grid, n_fluids: int) -> int:
-    return int(_lib.sg_ss_table_bytes(ctypes.byref(g), int(n_fluids)))
+def ss_table_bytes(g: Grid, n_fluids: int, flags: int = 0) -> int:
+    return int(_lib.sg_ss_table_bytes(ctypes.byref(g), int(n_fluids), int(flags)))
 
 
 def ss_table_workspace_bytes(g: Grid, n_fluids: int) -> int:

@@ -53,7 +53,7 @@ static sg_status check_ss_grid(const sg_grid *g)
 
 static bool ss_flags_ok(uint32_t flags)
 {
-    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL)) == 0;
+    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL | SG_SS_FULL)) == 0;
 }
 
 extern "C" {
@@ -83,10 +83,10 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
     return sg_table_build(grid, fluids, flags, d_table, d_ws, (hipStream_t)stream);
 }
 
-size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids)
+size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids, uint32_t flags)
 {
-    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
-    return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids).total;
+    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2 || !ss_flags_ok(flags)) return 0;
+    return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids, sg_ss_du(*grid), (flags & SG_SS_FULL) != 0).total;
 }
 
 size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids)

@@ -579,7 +579,12 @@ static bool make_launch(const sg_disc *discs, const Plan &P, const ClassSpec &c,
     La.k = k;
     La.v = v;
     La.K = v.K > 0 ? v.K : k.K;
-    La.lds = c.ss ? (size_t)k.lds_per_row * c.len + k.lds_fixed : 0;
+    La.lds = 0;
+    if (c.ss) {  // the longest staged column of the class's modes (fill_discs: ss_cap)
+        int cs = 0;
+        for (int di : c.discs) cs = std::max(cs, P.discs[di].ss_cap);
+        La.lds = (size_t)k.lds_per_row * cs + k.lds_fixed;
+    }
     class_wjobs(discs, c, k.G, La.K, k.tb, wj);
     La.nj = (int)wj.size();
     La.grid = launch_grid(La.nj, La.K);
@@ -601,9 +606,16 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.sigma = d.sigma;
         D.gr = d.g_r;
         D.gp = d.g_phi;
+        D.modes = nullptr;
+        D.ss_cap = 0;
         if (d.flags & SG_SEMI_SPECTRAL) {
-            const SsLayout L = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids);
+            // staged column of the widest banded mode of this grid (the band
+            // rule without SG_SS_FULL, so that any table of the grid fits)
+            const SsLayout B = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, sg_ss_du(d.grid), false);
+            D.ss_cap = d.grid.n_r + (B.max_w >= 0 ? 2 * B.max_w + 4 : 0);
+            const SsLayout L = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, 1.0, true);
             D.spec = (const float2 *)(tb + L.off_coef);
+            D.modes = (const SsMode *)(tb + L.off_modes);
             D.dspec = nullptr;
             D.tw_u = nullptr;
             D.tw_phi = (const float2 *)(tb + L.off_tw_phi);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -178,29 +179,59 @@ inline TableLayout sg_table_layout(int nr, int nphi, int nf, uint32_t flags)
 // Semi-spectral table layout (sg_ss_table; H_f any function of r):
 //   header   sg_ss_header
 //   tw_phi   float2[n_phi]       e^{-2 pi i n / n_phi}
-//   coef     float2[ncol][F][F][n_r][nrt]
-// indexed [m][b (target fluid)][a (source fluid)][i' (source row)][i (target
-// row)]; element (t_r, t_phi) is the radial operator of mode m: g^_r gets
-// t_r Sigma~ and g^_phi gets i t_phi Sigma~.  nrt = n_r rounded up to even
-// (the padding target column is zero), so target pairs are 16-byte aligned.
+//   modes    SsMode[ncol]        where each mode's operators start, its band
+//   coef     the operators of m = 0, 1, ..., n_phi/2 in order, each
+//              full:   float2[F][F][n_r][nrt]      [b][a][i'][i]
+//              banded: float2[F][F][2w+1][nrt]     [b][a][d][i], i' = i + d - w
+// (b target fluid, a source fluid, i' source row, i target row).  Element
+// (t_r, t_phi) is the radial operator of mode m: g^_r gets t_r Sigma~ and
+// g^_phi gets i t_phi Sigma~.  nrt = n_r rounded up to even (the padding
+// target column is zero), so target pairs are 16-byte aligned.  Banded
+// entries whose source row falls outside the grid are zero.
+//
+// Band of mode m: the kernels are analytic in phi within |Im phi| < |X|
+// (X = u_i - u_i'; their only singularity, s = 0, sits at phi = +-i X), so
+// the mode-m coupling of two rings falls off like e^{-m |X|}; entries with
+// m |X| > SG_SS_BAND_L (about 2^-30 of the axisymmetric coupling) are
+// dropped.  w = ceil(L / (m du)); a mode is stored banded when
+// 4 w + 2 <= n_r, full otherwise (and always with SG_SS_FULL, and for m = 0).
 #define SG_SS_MAGIC 0x31535347u  // "GSS1"
+#define SG_SS_BAND_L 20.794415416798359  // 30 ln 2
 
 struct sg_ss_header {
     uint32_t magic, version;
     int32_t n_r, n_phi, n_fluids;
     uint32_t flags;
-    double r_min, r_max;
+    double r_min, r_max, du;
     uint64_t total_bytes;
 };
 
-struct SsLayout {
-    int nr, nphi, nf, ncol, nrt;
-    size_t slice;   // float2 elements per (m, b, a)
-    size_t rows;    // F * F * n_r * nrt: (b, a, i', i) rows of one mode
-    size_t off_tw_phi, off_coef, total;
+struct SsMode {
+    uint64_t off;     // first float2 of the mode in coef
+    int32_t w;        // band half-width (banded modes)
+    int32_t banded;
 };
 
-inline SsLayout sg_ss_layout(int nr, int nphi, int nf)
+__host__ __device__ inline int sg_ss_band(int m, int nr, double du, bool full)
+{
+    if (full || m == 0 || nr < 2) return nr - 1;
+    const double w = ceil(SG_SS_BAND_L / ((double)m * du));
+    return w >= (double)(nr - 1) ? nr - 1 : (int)w;
+}
+__host__ __device__ inline bool sg_ss_is_banded(int w, int nr) { return 4 * w + 2 <= nr; }
+
+struct SsLayout {
+    int nr, nphi, nf, ncol, nrt;
+    bool full;
+    double du;
+    size_t rows;        // F * F * n_r * nrt: (b, a, i', i) rows of one full mode
+    size_t coef_elems;  // float2 elements of all modes
+    int max_w;          // widest band of a banded mode (-1: none banded)
+    size_t off_tw_phi, off_modes, off_coef, total;
+};
+
+// Host-side: sizes and offsets (du = ln(r_max/r_min)/n_r as the build uses it).
+inline SsLayout sg_ss_layout(int nr, int nphi, int nf, double du, bool full)
 {
     SsLayout L;
     L.nr = nr;
@@ -208,16 +239,29 @@ inline SsLayout sg_ss_layout(int nr, int nphi, int nf)
     L.nf = nf;
     L.ncol = nphi / 2 + 1;
     L.nrt = (nr + 1) & ~1;
-    L.slice = (size_t)nr * L.nrt;
-    L.rows = (size_t)nf * nf * L.slice;
+    L.full = full;
+    L.du = du;
+    L.rows = (size_t)nf * nf * nr * L.nrt;
+    L.coef_elems = 0;
+    L.max_w = -1;
+    for (int m = 0; m < L.ncol; ++m) {
+        const int w = sg_ss_band(m, nr, du, full);
+        const bool b = sg_ss_is_banded(w, nr);
+        L.coef_elems += (size_t)nf * nf * (b ? 2 * w + 1 : nr) * L.nrt;
+        if (b && w > L.max_w) L.max_w = w;
+    }
     size_t o = sg_align256(sizeof(sg_ss_header));
     L.off_tw_phi = o;
     o = sg_align256(o + sizeof(float2) * (size_t)nphi);
+    L.off_modes = o;
+    o = sg_align256(o + sizeof(SsMode) * (size_t)L.ncol);
     L.off_coef = o;
-    o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.rows);
+    o = sg_align256(o + sizeof(float2) * L.coef_elems);
     L.total = o;
     return L;
 }
+
+inline double sg_ss_du(const sg_grid &g) { return log(g.r_max / g.r_min) / g.n_r; }
 
 // Tiled layout of the half-spectrum intermediates between the passes: tiles
 // of 4 columns x 4 rows (128 bytes), each column's 4 rows contiguous inside

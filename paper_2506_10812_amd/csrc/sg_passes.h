@@ -28,6 +28,8 @@ struct DiscDev {
     const double *ind;      // table header: indirect-term coefficients [F]
     int nr, nphi, nf;
     uint32_t flags;
+    const SsMode *modes;    // semi-spectral table: mode descriptors
+    int ss_cap;             // staged column capacity of the launch's LDS
     int ns;                 // species summed into groups (0: one density per fluid)
     int gcount[2];          // species of each group
     uint8_t gsp[2][8];      // their indices

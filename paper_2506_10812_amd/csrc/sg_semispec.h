@@ -5,7 +5,8 @@
 // Middle pass of a semi-spectral disc (replaces pass 2 of the FFT path):
 // fn has the pass-kernel signature; a workgroup of wgs threads takes one job
 // (column m, target fluid b, block of tb target rows) and needs
-// lds_per_row * n_r + lds_fixed bytes of dynamic LDS.
+// lds_per_row * c + lds_fixed bytes of dynamic LDS, c the longest staged
+// column of a mode (n_r, or n_r + 2 w + 4 for a banded mode).
 struct SsPassInfo {
     void (*fn)(const DiscDev *, const WJob *, int, const float2 *, int);
     int wgs, tb, lds_per_row, lds_fixed;

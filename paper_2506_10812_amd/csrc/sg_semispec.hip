@@ -24,7 +24,10 @@
 //      T_r(m) = (Z[m] + Z[-m])/2, t_phi(m) = (Z[-m] - Z[m])/2 (real parts),
 //      scaled by -du dphi / n_phi (the inverse transform of the last pass is
 //      unnormalised); rows are written [row][m] to a chunk buffer;
-//   3. a tiled transpose moves each chunk to the [m][row] table layout.
+//   3. a tiled transpose moves each chunk into the table: full modes keep
+//      every (i', i) entry, banded modes the diagonals |i' - i| <= w (the
+//      band rule is in sg_internal.h; dropped couplings are below about
+//      2^-30 of the axisymmetric one, and SG_SS_FULL keeps every entry).
 // SG_INDIRECT folds the indirect term (Sect. 5.4 and its appendix) into
 // mode 1: in the same convolution form it is Sigma convolved with
 //   r_i'^2 sqrt(2) K_a(d_i') (cos phi, -sin phi),  d_i' = r_i' / H_a(r_i'),
@@ -127,9 +130,12 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
 }
 
 // ------------------------------------------------------- table: transpose
-// src [nrows][ncol] -> dst[m * rows_total + r0 + row], 32 x 32 tiles.
+// src [nrows][ncol] (rows r0 + row of the (b, a, i', i) order) into the
+// modes' layouts, 32 x 32 tiles: for a fixed mode consecutive rows are
+// consecutive target columns in both layouts.
 __global__ void __launch_bounds__(256)
-k_ss_transpose(const float2 *src, int nrows, int ncol, float2 *dst, size_t rows_total, size_t r0)
+k_ss_scatter(const float2 *src, int nrows, int ncol, float2 *coef, const SsMode *modes, size_t r0, int nr,
+             int nrt)
 {
     __shared__ float2 tile[32][33];
     const int rb = blockIdx.x * 32, mb = blockIdx.y * 32;
@@ -139,10 +145,51 @@ k_ss_transpose(const float2 *src, int nrows, int ncol, float2 *dst, size_t rows_
         if (r < nrows && m < ncol) tile[k][tx] = gload2(src, (size_t)r * ncol + m);
     }
     __syncthreads();
+    const int r = rb + tx;
+    if (r >= nrows) return;
+    const size_t R = r0 + r;
+    const int i = (int)(R % nrt);
+    const size_t rest = R / nrt;
+    const int ip = (int)(rest % nr);
+    const size_t pair = rest / nr;  // b * F + a
     for (int k = ty; k < 32; k += 8) {
-        const int m = mb + k, r = rb + tx;
-        if (r < nrows && m < ncol) gstore2(dst, (size_t)m * rows_total + r0 + r, tile[tx][k]);
+        const int m = mb + k;
+        if (m >= ncol) break;
+        const SsMode md = modes[m];
+        size_t dst;
+        if (md.banded) {
+            const int d = ip - i + md.w;
+            if (d < 0 || d > 2 * md.w) continue;
+            dst = md.off + (pair * (2 * md.w + 1) + d) * nrt + i;
+        } else {
+            dst = md.off + (pair * nr + ip) * nrt + i;
+        }
+        gstore2(coef, dst, tile[tx][k]);
     }
+}
+
+// Mode descriptors (one thread; the same band rule as the host layout, with
+// the host's du).
+__global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, double du, int full)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t off = 0;
+    for (int m = 0; m < ncol; ++m) {
+        const int w = sg_ss_band(m, nr, du, full != 0);
+        const bool b = sg_ss_is_banded(w, nr);
+        SsMode md;
+        md.off = off;
+        md.w = w;
+        md.banded = b ? 1 : 0;
+        modes[m] = md;
+        off += (uint64_t)nf * nf * (b ? 2 * w + 1 : nr) * nrt;
+    }
+}
+
+__global__ void k_ss_zero(float2 *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        gstore2(p, i, make_float2(0.f, 0.f));
 }
 
 __global__ void k_ss_header(sg_ss_header *hd, sg_ss_header proto)
@@ -167,7 +214,7 @@ static size_t ss_chunk_rows(const SsLayout &L)
 
 size_t sg_ss_ws_bytes(int nr, int nphi, int nf)
 {
-    const SsLayout L = sg_ss_layout(nr, nphi, nf);
+    const SsLayout L = sg_ss_layout(nr, nphi, nf, 1.0, true);
     return sg_align256(sizeof(double) * (size_t)nf * nf * nr) +
            sg_align256(sizeof(float2) * L.ncol * ss_chunk_rows(L));
 }
@@ -203,8 +250,9 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
                             void *d_ws, hipStream_t s)
 {
     const int nr = grid->n_r, nphi = grid->n_phi;
-    const SsLayout L = sg_ss_layout(nr, nphi, nf);
-    const double du = log(grid->r_max / grid->r_min) / nr;
+    const double du = sg_ss_du(*grid);
+    const bool full = (flags & SG_SS_FULL) != 0;
+    const SsLayout L = sg_ss_layout(nr, nphi, nf, du, full);
     const double dphi = 2.0 * SG_PI / nphi;
     char *tb = (char *)d_table;
     double *self = (double *)d_ws;
@@ -214,6 +262,14 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     hipLaunchKernelGGL(k_twiddles, dim3((nphi + 255) / 256), dim3(256), 0, s, (float2 *)nullptr, 0,
                        (float2 *)(tb + L.off_tw_phi), nphi);
     SG_HIP(hipGetLastError());
+    SsMode *modes = (SsMode *)(tb + L.off_modes);
+    hipLaunchKernelGGL(k_ss_modes, dim3(1), dim3(64), 0, s, modes, L.ncol, nr, L.nrt, nf, du, full ? 1 : 0);
+    SG_HIP(hipGetLastError());
+    float2 *coef = (float2 *)(tb + L.off_coef);
+    if (L.max_w >= 0) {  // banded modes: entries the scatter does not reach stay zero
+        hipLaunchKernelGGL(k_ss_zero, dim3(2048), dim3(256), 0, s, coef, L.coef_elems);
+        SG_HIP(hipGetLastError());
+    }
     if (!excl) {
         // one item per (pair, ring): the per-cell kernel with one cell per ring
         GLNodes gl;
@@ -232,13 +288,12 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     A.du = du;
     A.dphi = dphi;
     const size_t crows = ss_chunk_rows(L);
-    float2 *coef = (float2 *)(tb + L.off_coef);
     for (size_t r0 = 0; r0 < L.rows; r0 += crows) {
         const int n = (int)std::min(crows, L.rows - r0);
         if (!dispatch_ss_rows(nphi, d_H, self, A, r0, n, chunk, s)) return SG_ERR_UNSUPPORTED;
         SG_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ss_transpose, dim3((n + 31) / 32, (L.ncol + 31) / 32), dim3(256), 0, s, chunk, n,
-                           L.ncol, coef, L.rows, r0);
+        hipLaunchKernelGGL(k_ss_scatter, dim3((n + 31) / 32, (L.ncol + 31) / 32), dim3(256), 0, s, chunk, n,
+                           L.ncol, coef, (const SsMode *)modes, r0, nr, L.nrt);
         SG_HIP(hipGetLastError());
     }
     sg_ss_header proto{};
@@ -250,6 +305,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     proto.flags = flags | SG_SEMI_SPECTRAL;
     proto.r_min = grid->r_min;
     proto.r_max = grid->r_max;
+    proto.du = du;
     proto.total_bytes = L.total;
     hipLaunchKernelGGL(k_ss_header, dim3(1), dim3(1), 0, s, (sg_ss_header *)tb, proto);
     SG_HIP(hipGetLastError());
@@ -268,10 +324,13 @@ __device__ inline void ss_ld4(const float2 *p, uint32_t i, float2 &x, float2 &y)
 
 // Workgroup job (disc, m, b, target block): 256 threads in S row splits of
 // LN = 256 / S lanes; lane l owns targets i0 .. i0 + V - 1, i0 = block TB +
-// V l (TB = LN V), and split s sums the source rows i' = s (mod S) of every
-// source fluid; the splits are combined through LDS.  Sigma~_a(m, .) of all
-// sources is staged in LDS first (broadcast reads in the sum).  The operator
-// rows are streamed once: this pass is bound by reading the table.
+// V l (TB = LN V), and split s sums the operator rows k = s (mod S) of every
+// source fluid (source rows of a full mode, diagonals of a banded one); the
+// splits are combined through LDS.  Sigma~_a(m, .) of all sources is staged
+// in LDS first (a banded mode's column with w zeros on either side, so that
+// target i reads source i + d - w at padded index i + d).  The operator rows
+// are streamed once with 16-byte loads, U rows in flight: this pass is bound
+// by reading the table.
 template <int NF, int V, int S>
 __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJob *wj, int nj, const float2 *,
                                                  int kc)
@@ -287,69 +346,73 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
     const int nr = D->nr, nrt = (nr + 1) & ~1, nb = (nr + TB - 1) / TB;
     const int blk = idx % nb, mb = idx / nb, b = mb % NF, m = mb / NF;
     const size_t fs = sg_blk_field_elems(D->nphi, nr);
-    for (int e = threadIdx.x; e < NF * nr; e += 256) {
-        const int a = e / nr, ip = e - a * nr;
-        ssh[e] = gld2(D->st + a * fs, (uint32_t)sg_blk_index(m, ip, nr));
+    const SsMode md = D->modes[m];
+    const bool banded = sg_uniform(md.banded) != 0;
+    const int bw = banded ? sg_uniform(md.w) : 0;
+    const int cs = banded ? nr + 2 * bw + 4 : nr;   // staged column length per source
+    const int nk = banded ? 2 * bw + 1 : nr;        // operator rows per (b, a)
+    if (cs > D->ss_cap) return;  // table not built for this grid: never overrun the LDS
+    for (int e = threadIdx.x; e < NF * cs; e += 256) {
+        const int a = e / cs, ip = e - a * cs - bw;
+        ssh[e] = (ip >= 0 && ip < nr) ? gld2(D->st + a * fs, (uint32_t)sg_blk_index(m, ip, nr))
+                                      : make_float2(0.f, 0.f);
     }
     __syncthreads();
     const int ln = threadIdx.x % LN, sp = threadIdx.x / LN;
     const int i0 = blk * TB + V * ln;
-    // column of each target pair; pairs past the last row read column 0
+    // column of each target pair (pairs past the last row read column 0) and
+    // each target's staged index (targets past the last row read index 0)
     uint32_t col[V / 2];
+    int ie[V];
 #pragma unroll
     for (int v = 0; v < V; v += 2) col[v / 2] = i0 + v < nr ? (uint32_t)(i0 + v) : 0u;
+#pragma unroll
+    for (int v = 0; v < V; ++v) ie[v] = i0 + v < nr ? i0 + v : 0;
     float2 ar[V], ap[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ar[v] = ap[v] = make_float2(0.f, 0.f);
-    const size_t slice = (size_t)nr * nrt;
+    const float2 *C = D->spec + md.off;
     for (int a = 0; a < NF; ++a) {
-        const float2 *Tm = D->spec + ((size_t)(m * NF + b) * NF + a) * slice;
-        const float2 *sa = ssh + a * nr;
-        int ip = sp;
-        for (; ip + S * (U - 1) < nr; ip += S * U) {
+        const float2 *Tm = C + (size_t)(b * NF + a) * nk * nrt;
+        const float2 *sa = ssh + a * cs;
+        int k = sp;
+        for (; k + S * (U - 1) < nk; k += S * U) {
             float2 t[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int v = 0; v < V; v += 2)
-                    ss_ld4(Tm, (uint32_t)(ip + S * u) * nrt + col[v / 2], t[u][v], t[u][v + 1]);
+                    ss_ld4(Tm, (uint32_t)(k + S * u) * nrt + col[v / 2], t[u][v], t[u][v + 1]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const float2 s = sa[ip + S * u];
 #pragma unroll
-                for (int v = 0; v < V; v += 2) {
-                    // t = (T_r, t_phi) of targets i0 + v, i0 + v + 1
+                for (int v = 0; v < V; ++v) {
+                    // full: source row k (all targets); banded: diagonal k
+                    const float2 s = banded ? sa[ie[v] + k + S * u] : sa[k + S * u];
                     ar[v].x += t[u][v].x * s.x;
                     ar[v].y += t[u][v].x * s.y;
                     ap[v].x += t[u][v].y * s.x;
                     ap[v].y += t[u][v].y * s.y;
-                    ar[v + 1].x += t[u][v + 1].x * s.x;
-                    ar[v + 1].y += t[u][v + 1].x * s.y;
-                    ap[v + 1].x += t[u][v + 1].y * s.x;
-                    ap[v + 1].y += t[u][v + 1].y * s.y;
                 }
             }
         }
-        for (; ip < nr; ip += S) {
-            const float2 s = sa[ip];
+        for (; k < nk; k += S) {
+            float2 t[V];
 #pragma unroll
-            for (int v = 0; v < V; v += 2) {
-                float2 x, y;
-                ss_ld4(Tm, (uint32_t)ip * nrt + col[v / 2], x, y);
-                ar[v].x += x.x * s.x;
-                ar[v].y += x.x * s.y;
-                ap[v].x += x.y * s.x;
-                ap[v].y += x.y * s.y;
-                ar[v + 1].x += y.x * s.x;
-                ar[v + 1].y += y.x * s.y;
-                ap[v + 1].x += y.y * s.x;
-                ap[v + 1].y += y.y * s.y;
+            for (int v = 0; v < V; v += 2) ss_ld4(Tm, (uint32_t)k * nrt + col[v / 2], t[v], t[v + 1]);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float2 s = banded ? sa[ie[v] + k] : sa[k];
+                ar[v].x += t[v].x * s.x;
+                ar[v].y += t[v].x * s.y;
+                ap[v].x += t[v].y * s.x;
+                ap[v].y += t[v].y * s.y;
             }
         }
     }
     if constexpr (S > 1) {
-        // combine the row splits: partials after the staged column
-        float2 *red = ssh + ((NF * nr + 1) & ~1);
+        // combine the row splits: partials after the staged columns
+        float2 *red = ssh + ((NF * cs + 1) & ~1);
         if (sp > 0) {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -360,10 +423,10 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
         __syncthreads();
         if (sp > 0) return;
 #pragma unroll
-        for (int k = 0; k < S - 1; ++k)
+        for (int q = 0; q < S - 1; ++q)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const float2 x = red[(k * LN + ln) * 2 * V + 2 * v], y = red[(k * LN + ln) * 2 * V + 2 * v + 1];
+                const float2 x = red[(q * LN + ln) * 2 * V + 2 * v], y = red[(q * LN + ln) * 2 * V + 2 * v + 1];
                 ar[v].x += x.x;
                 ar[v].y += x.y;
                 ap[v].x += y.x;

@@ -86,7 +86,7 @@ class SemiSpectral:
         self.g = grid(n_r, n_phi, r_min, r_max)
         self.nf = int(n_fluids)
         self.flags = int(flags) & ~SEMI_SPECTRAL
-        nb = ss_table_bytes(self.g, self.nf)
+        nb = ss_table_bytes(self.g, self.nf, self.flags)
         if nb == 0:
             raise ValueError("unsupported grid for the semi-spectral path")
         self.table = torch.empty(nb, dtype=torch.uint8, device=dev)

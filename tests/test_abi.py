@@ -135,11 +135,12 @@ def test_semispectral_sizes_and_validation(sg):
         g = sg.grid(nr, 64, 20.0, 250.0)
         nrt = nr + (nr & 1)
         core = 33 * 4 * nr * nrt * 8
-        nb = sg.ss_table_bytes(g, 2)
+        nb = sg.ss_table_bytes(g, 2, sg.SS_FULL)
         assert core < nb < core + 4096, (nr, nb)
         assert sg.ss_table_workspace_bytes(g, 2) > 0
     for nr, nphi in ((2049, 64), (16, 2), (16, 12), (16, 4096), (0, 64)):
         assert sg.ss_table_bytes(sg.grid(nr, nphi, 20.0, 250.0), 1) == 0
+    assert sg.ss_table_bytes(sg.grid(16, 64, 20.0, 250.0), 1, sg.WITH_DH) == 0
     g = sg.grid(37, 32, 20.0, 250.0)
     need = sg.ss_table_workspace_bytes(g, 2)
     call = lambda nf, H, flags, tab, ws, n: L.sg_ss_table(ctypes.byref(g), nf, H, flags, tab, ws, n, None)
@@ -220,3 +221,30 @@ def test_species_validation(sg):
     assert sg.field_adjoint_workspace_bytes(ok) == 0
     assert sg.lib().sg_field_adjoint(ctypes.byref(ok), 256, 512, 768, None, 2048, 1 << 30,
                                      None) == sg.ERR_UNSUPPORTED
+
+
+
+def test_semispectral_band_sizes(sg):
+    """Banded modes: m >= 1 keeps |i - i'| <= w_m = ceil(30 ln 2 / (m du)) and is
+    stored as 2 w_m + 1 diagonals when 4 w_m + 2 <= n_r; SG_SS_FULL and coarse
+    grids keep every mode whole."""
+    import math
+    for nr, nphi, nf, rmin, rmax in ((1200, 2048, 1, 20.0, 250.0), (1024, 2048, 2, 0.2, 5.0),
+                                     (256, 128, 2, 20.0, 250.0), (37, 32, 2, 20.0, 250.0)):
+        g = sg.grid(nr, nphi, rmin, rmax)
+        du = math.log(rmax / rmin) / nr
+        nrt = nr + (nr & 1)
+        elems = 0
+        for m in range(nphi // 2 + 1):
+            w = nr - 1 if m == 0 else min(nr - 1, math.ceil(30 * math.log(2) / (m * du)))
+            elems += nf * nf * ((2 * w + 1) if 4 * w + 2 <= nr else nr) * nrt
+        full = (nphi // 2 + 1) * nf * nf * nr * nrt
+        nb = sg.ss_table_bytes(g, nf)
+        nbf = sg.ss_table_bytes(g, nf, sg.SS_FULL)
+        assert 8 * elems < nb < 8 * elems + 64 * 1024, (nr, nphi)
+        assert 8 * full < nbf < 8 * full + 64 * 1024, (nr, nphi)
+        if nr >= 256:
+            assert nb < nbf
+    # the App. D gas disc: about a tenth of the full operators
+    g = sg.grid(1200, 2048, 20.0, 250.0)
+    assert sg.ss_table_bytes(g, 1) < 0.15 * sg.ss_table_bytes(g, 1, sg.SS_FULL)

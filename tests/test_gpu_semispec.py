@@ -92,10 +92,11 @@ def test_semispectral_matches_pairwise_oracle(sg, T, W, nr, nphi, nf, p, gap):
     check(gr, gp, rr, rp, nf)
 
 
-@pytest.mark.parametrize("nr,nphi,nf", [(300, 32, 2), (700, 16, 1), (1024, 64, 2)])
+@pytest.mark.parametrize("nr,nphi,nf", [(300, 32, 2), (700, 16, 1), (1024, 64, 2), (512, 256, 2)])
 def test_semispectral_wide_grids_sampled(sg, T, W, nr, nphi, nf):
     """The three middle-pass shapes (row splits, whole-row streaming with 2 and
-    4 targets per lane) at sizes where the oracle computes sampled cells."""
+    4 targets per lane) at sizes where the oracle computes sampled cells; at
+    512 x 256 the modes m >= 33 are banded."""
     say(f"semi-spectral sampled {nr}x{nphi} nf={nf}")
     w = W.flaring(seed=nr, n_r=nr, n_phi=nphi, p=0.25, gap_w=15.0, n_fluids=nf)
     _, gr, gp = run_ss(T, w)
@@ -220,3 +221,26 @@ def test_semispectral_tuner(sg, T, W):
     rr, rp = oracle_field(w, targets=cells)
     check(S.g_r.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64),
           S.g_phi.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64), rr, rp, 2, rms=2e-5)
+
+
+def test_semispectral_banded_equals_full(sg, T, W):
+    """n_r = 256 over [20, 250] AU (du ~ 0.0099): modes m >= 34 keep only
+    |i - i'| <= w_m; with clumpy dust (power at high m) the banded operators
+    give the field of the full operators (SG_SS_FULL) to float rounding."""
+    print("semi-spectral banded vs full operators, 256x128", flush=True)
+    w = W.flaring(seed=31, n_r=256, n_phi=128, p=0.25, n_fluids=2)
+    Sb, gb_r, gb_p = run_ss(T, w)
+    Sf, gf_r, gf_p = run_ss(T, w, flags=sg.SS_FULL)
+    nb = sg.ss_table_bytes(Sb.g, 2)
+    nf = sg.ss_table_bytes(Sf.g, 2, sg.SS_FULL)
+    print(f"  table {nb / 1e6:.1f} MB banded, {nf / 1e6:.1f} MB full", flush=True)
+    assert nb < 0.8 * nf
+    scale = float(np.sqrt(gf_r ** 2 + gf_p ** 2).max())
+    for f in range(2):
+        er, ep = rel_rms(gb_r[f], gf_r[f]), rel_rms(gb_p[f], gf_p[f])
+        mx = float(max(np.abs(gb_r[f] - gf_r[f]).max(), np.abs(gb_p[f] - gf_p[f]).max())) / scale
+        print(f"  fluid {f}: rel-RMS {er:.2e} {ep:.2e}, max/max|g| {mx:.2e}", flush=True)
+        assert er < 1e-6 and ep < 1e-6 and mx < 1e-6
+    cells = W.sample_cells(256, 128, 48, seed=5)
+    rr, rp = oracle_field(w, targets=cells)
+    check(gb_r.reshape(2, -1)[:, cells], gb_p.reshape(2, -1)[:, cells], rr, rp, 2)
