@@ -10,6 +10,8 @@ precomputes the kernel once per simulation).  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
   python bench.py --copy-calibration   (plain 1 GiB device copy, for scaling
                                         rocprofv3 FETCH_SIZE / WRITE_SIZE)
+  python bench.py --semispectral       (only the semi-spectral App. D measurement,
+                                        one JSON line; for its kernel trace)
   python bench.py --summarize-rocprof DIR
         (CPU only) turns the rocprofv3 CSV output of PROFILE_COMMANDS, run
         with DIR as their output root, into the text summaries in profiles/
@@ -48,6 +50,8 @@ PROFILE_COMMANDS = {
               "python3 {repo}/bench.py --copy-calibration",
     "cwrite": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cwrite -o run -- "
               "python3 {repo}/bench.py --copy-calibration",
+    "ss_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/ss_kt -o run -- "
+             "python3 {repo}/bench.py --semispectral",
 }
 COPY_BYTES = 4 << 28   # --copy-calibration copies 2^28 floats
 
@@ -167,6 +171,24 @@ def summarize_rocprof(out):
           f"Kernel sources hash: {tr['kernel_source_hash']}."]
     with open(os.path.join(prof, "traffic_pass2_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
+    ss_dir = os.path.join(out, "ss_kt")
+    if os.path.isdir(ss_dir):
+        stats = _csv_rows(ss_dir, "_kernel_stats.csv")
+        lines = ["# Kernel time, semi-spectral path, App. D flaring gas disc 1200x2048", "",
+                 "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output "
+                 "root):", "", "    " + cmd["ss_kt"], "",
+                 "The run builds the radial operators twice (k_ss_rows, k_ss_scatter, self cells), "
+                 "tunes the batch, then times solves (k_pass1, k_ss_pass, k_pass3) and per-pass "
+                 "launches.", "",
+                 "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share (%) |",
+                 "|---|---|---|---|---|---|"]
+        for r in stats:
+            name = r["Name"].split("(")[0].replace("void ", "")
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                         f"{float(r['Percentage']):.2f} |")
+        with open(os.path.join(prof, "kernels_semispectral_flaring_1200x2048.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
     print(json.dumps(tr))
 
 
@@ -180,6 +202,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
+    ap.add_argument("--semispectral", action="store_true")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
@@ -208,6 +231,10 @@ def main():
     import paper_2506_10812_amd as sg
     from paper_2506_10812_amd import torch_ops as T
     from paper_2506_10812_amd import workloads as W
+
+    if args.semispectral:
+        print(json.dumps(semispectral_measurement(sg, T, W, dev)))
+        return
 
     w = W.bifluid_fft()
     nr, nphi, nf = w["n_r"], w["n_phi"], len(w["h"])
@@ -351,6 +378,8 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     torch.cuda.synchronize()
     build_ms = e0.elapsed_time(e1)
     S.release_workspace()
+    ms_untuned = sg.field_fft_profile([S.disc], S.ws, 10)
+    tuned = sg.field_fft_tune([S.disc], S.ws)
     for _ in range(3):
         S.run()
     torch.cuda.synchronize()
@@ -367,6 +396,8 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
            "table_bytes": sg.ss_table_bytes(S.g, nf), "table_build_ms": round(build_ms, 2),
            "ms_per_step": round(ms, 4), "cells_per_s": round(nr * nphi / ms * 1e3, 1),
            "ms_per_pass": [round(v, 4) for v in ms_pass],
+           "ms_per_pass_untuned": [round(v, 4) for v in ms_untuned],
+           "middle_pass_shape": [r["groups_per_wg"] for r in tuned if r["pass"] == 2],
            "middle_pass": {"bound": "hbm", "algorithmic_bytes": mid, "achieved": round(ach, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
     del S

@@ -65,7 +65,8 @@ enum {
     SG_WITH_DH = 2u,           /* table also holds d/dh spectra (adjoint)     */
     SG_INDIRECT = 4u,          /* add the indirect term (see below)           */
     SG_SEMI_SPECTRAL = 8u,     /* disc uses a semi-spectral table (below)     */
-    SG_SS_FULL = 16u           /* semi-spectral: keep every operator entry    */
+    SG_SS_FULL = 16u,          /* semi-spectral: keep every operator entry    */
+    SG_POTENTIAL = 32u         /* semi-spectral: operators of the potential   */
 };
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
@@ -150,13 +151,24 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * (r_i = r_min e^{(i + 1/2) du}), every value > 0 (not checked on the
  * device).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (the indirect term,
  * with K_a at d = r_i'/H_a(r_i'), folded into mode 1 of the table; no cost
- * at solve time), SG_SS_FULL.  Grid: n_phi a power of two in [4, 2048], n_r
+ * at solve time), SG_SS_FULL, SG_POTENTIAL (below).  Grid: n_phi a power
+ * of two in [4, 2048], n_r
  * in [1, 2048], any n_r.  Size: sg_ss_table_bytes() (at most
  * 8 (n_phi/2 + 1) F^2 n_r n_rt bytes, n_rt = n_r rounded up to even, plus a
  * few KB); d_table 256-byte aligned, written completely.
  * d_ws: sg_ss_table_workspace_bytes() bytes (<= about 130 MB), contents
  * undefined afterwards.  Asynchronous on `stream`.  The table is position
  * independent.
+ *
+ * SG_POTENTIAL: the table holds the operators of the potential of Sect. 5.5
+ * and the appendix "Conservative force" instead of the field's,
+ *   Phi_b(x_i) = sum_a sum_k Sigma_a[k] A_k P_ab(s_ik),
+ *   P_ab(s) = -e^y K0(y) / (2 sqrt(pi) H_ab),  y = s^2 / (8 H_ab^2),
+ * with the own-cell integral of P_ab (cell's ring H) unless excluded; a disc
+ * with this table receives Phi in g_r (g_phi holds only the rounding of the
+ * inverse transform, about 1e-7 of |Phi|).  With constant H
+ * (the case the paper derives) -grad Phi is the field; not combinable with
+ * SG_INDIRECT.
  *
  * Solve with sg_field_fft: a disc whose flags hold SG_SEMI_SPECTRAL (plus
  * the flags the table was built with) and whose table is an sg_ss_table
@@ -239,7 +251,13 @@ sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, si
  * candidate: radix order of the transforms (small radix last or first, where
  * the length is not a power of 8), tile shape (the default number of
  * transforms per workgroup or twice it, up to 1024 threads) and XCD cluster
- * size (1, 2, 4 or 8 consecutive workgroups on one XCD).  A candidate is timed
+ * size (1, 2, 4 or 8 consecutive workgroups on one XCD); for the middle pass
+ * of semi-spectral discs (a class of its own per n_r and fluid count,
+ * length = n_r) the shape is one of four (1: four row splits, 2 targets per
+ * lane, non-temporal operator loads, the default; 2, 3: whole operator rows
+ * with 2 or 4 targets per lane; 4: as 1 with ordinary loads) times the
+ * cluster size.
+ * A candidate is timed
  * only if its output matches the reference (relative RMS <= 1e-5 over the
  * class's output buffers); the fastest wins.  Choices are cached per class
  * shape for the life of the process (and in the text file named by the
@@ -257,7 +275,8 @@ typedef struct sg_tune_result {
     int32_t n_fluids;
     int32_t n_jobs;            /* workgroup jobs of the chosen launch */
     int32_t small_radix_first; /* chosen radix order */
-    int32_t groups_per_wg;     /* chosen transforms per workgroup */
+    int32_t groups_per_wg;     /* chosen transforms per workgroup (middle
+                                  pass of semi-spectral discs: the shape) */
     int32_t cluster;           /* chosen XCD cluster size */
     int32_t candidates;        /* candidates tried besides the reference */
     int32_t rejected;          /* candidates that failed the output check */

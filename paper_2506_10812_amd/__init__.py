@@ -21,6 +21,7 @@ WITH_DH = 2
 INDIRECT = 4
 SEMI_SPECTRAL = 8
 SS_FULL = 16
+POTENTIAL = 32
 
 
 class SGError(RuntimeError):

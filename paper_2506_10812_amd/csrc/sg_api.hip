@@ -53,7 +53,9 @@ static sg_status check_ss_grid(const sg_grid *g)
 
 static bool ss_flags_ok(uint32_t flags)
 {
-    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL | SG_SS_FULL)) == 0;
+    if ((flags & SG_POTENTIAL) && (flags & SG_INDIRECT)) return false;
+    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL | SG_SS_FULL |
+                                SG_POTENTIAL)) == 0;
 }
 
 extern "C" {

@@ -580,9 +580,13 @@ static bool make_launch(const sg_disc *discs, const Plan &P, const ClassSpec &c,
     La.v = v;
     La.K = v.K > 0 ? v.K : k.K;
     La.lds = 0;
-    if (c.ss) {  // the longest staged column of the class's modes (fill_discs: ss_cap)
+    if (c.ss) {  // the longest staged column: a full mode's n_r or a banded mode's window
         int cs = 0;
-        for (int di : c.discs) cs = std::max(cs, P.discs[di].ss_cap);
+        for (int di : c.discs) {
+            const DiscDev &D = P.discs[di];
+            cs = std::max(cs, D.nr);
+            if (D.ss_wmax >= 0) cs = std::max(cs, k.tb + 2 * D.ss_wmax + 4);
+        }
         La.lds = (size_t)k.lds_per_row * cs + k.lds_fixed;
     }
     class_wjobs(discs, c, k.G, La.K, k.tb, wj);
@@ -607,12 +611,12 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.gr = d.g_r;
         D.gp = d.g_phi;
         D.modes = nullptr;
-        D.ss_cap = 0;
+        D.ss_wmax = -1;
         if (d.flags & SG_SEMI_SPECTRAL) {
             // staged column of the widest banded mode of this grid (the band
             // rule without SG_SS_FULL, so that any table of the grid fits)
             const SsLayout B = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, sg_ss_du(d.grid), false);
-            D.ss_cap = d.grid.n_r + (B.max_w >= 0 ? 2 * B.max_w + 4 : 0);
+            D.ss_wmax = B.max_w;
             const SsLayout L = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, 1.0, true);
             D.spec = (const float2 *)(tb + L.off_coef);
             D.modes = (const SsMode *)(tb + L.off_modes);
@@ -1023,7 +1027,7 @@ sg_status sg_fft_tune(const sg_disc *discs, int n, void *ws, hipStream_t s, sg_t
         double rel_best = 0.0;
         int ncand = 0, nrej = 0;
         for (int sf = 0; sf <= (!c.ss && has_small_radix(c.len) ? 1 : 0); ++sf)
-            for (int gm = 1; gm <= (c.ss ? 3 : 2); ++gm)
+            for (int gm = 1; gm <= (c.ss ? 4 : 2); ++gm)
                 for (int K : {1, 2, 4, 8}) {
                     const Variant v{sf, gm, K};
                     Launch L;
@@ -1097,7 +1101,7 @@ static void load_tune_file()
     int pass, len, nf, sf, gm, K;
     unsigned long long h;
     while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &gm, &K) == 7)
-        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 3 &&
+        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 4 &&
             (K == 0 || K == 1 || K == 2 || K == 4 || K == 8))
             g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, gm, K};
     fclose(f);

@@ -29,7 +29,7 @@ struct DiscDev {
     int nr, nphi, nf;
     uint32_t flags;
     const SsMode *modes;    // semi-spectral table: mode descriptors
-    int ss_cap;             // staged column capacity of the launch's LDS
+    int ss_wmax;            // widest band of the grid's banded modes (-1: none)
     int ns;                 // species summed into groups (0: one density per fluid)
     int gcount[2];          // species of each group
     uint8_t gsp[2][8];      // their indices

@@ -12,7 +12,8 @@ struct SsPassInfo {
     int wgs, tb, lds_per_row, lds_fixed;
 };
 
-// variant 1, 2, 3: (targets per lane, row splits) = (2, 4), (2, 1), (4, 1)
+// variant 1, 2, 3: (targets per lane, row splits) = (2, 4), (2, 1), (4, 1),
+// 1 with non-temporal operator loads; variant 4: as 1 with ordinary loads
 bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out);
 int sg_ss_default_variant(int nr);
 int sg_ss_max_nr();

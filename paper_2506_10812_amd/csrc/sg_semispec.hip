@@ -34,6 +34,13 @@
 // whose transform at m = 1 adds r_i'^2 sqrt(2) K_a(d) n_phi / 2 to both T_r
 // and t_phi before scaling.
 //
+// SG_POTENTIAL builds the operators of the potential instead (Sect. 5.5 and
+// the appendix on the conservative force): Phi_b(i, j) = sum Sigma_a A_i'
+// P_ab(s), P_ab = -e^y K0(y) / (2 sqrt(pi) H_ab), y = s^2 / (8 H_ab^2), with
+// the own-cell integral of P at zero offset.  P is even in phi, so T_r carries
+// its real spectrum and t_phi = 0: the solve writes Phi to g_r (and rounding
+// noise of the inverse transform to g_phi).
+//
 // Solve (sg_field_fft with discs flagged SG_SEMI_SPECTRAL): pass 1 and pass 3
 // of the FFT path (phi transforms), and k_ss_pass in place of pass 2.
 #include "sg_kfn.h"
@@ -42,7 +49,7 @@
 
 // ------------------------------------------------------------ table: rows
 struct SsRowArgs {
-    int nr, nrt, nf, excl, ind;
+    int nr, nrt, nf, excl, ind, pot;
     double lnrmin, du, dphi;
 };
 
@@ -87,6 +94,12 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
         double kr = 0.0, kp = 0.0;
         if (ic == ip && q == 0) {
             kr = A.excl ? 0.0 : self[(size_t)(a * A.nf + b) * A.nr + ic];
+        } else if (A.pot) {
+            // -r'^2 P_ab(s), so that the common scale -du dphi / N gives A_i' P / N
+            const double sx = sinh(0.5 * X), sp = sinpi((double)q / N);
+            const double s2 = 4.0 * ri * rp * (sx * sx + sp * sp);
+            const double Ha = ha * rp, Hb = hb * ri, Hab2 = 0.5 * (Ha * Ha + Hb * Hb);
+            kr = rp * rp * sg_G0_64(s2 / (8.0 * Hab2), wq) / (2.0 * SG_SQRT_PI * sqrt(Hab2));
         } else {
             sg_conv_kernel64(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, 0, wq, kr, kp);
         }
@@ -118,7 +131,7 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
         float2 v = make_float2(0.f, 0.f);
         if (live) {
             const double zm = pl.ld(m).x, zn = pl.ld((N - m) & (N - 1)).x;
-            double tr = 0.5 * (zm + zn), tp = 0.5 * (zn - zm);
+            double tr = 0.5 * (zm + zn), tp = A.pot ? 0.0 : 0.5 * (zn - zm);
             if (m == 1) {
                 tr += ind;
                 tp += ind;
@@ -184,6 +197,12 @@ __global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, dou
         modes[m] = md;
         off += (uint64_t)nf * nf * (b ? 2 * w + 1 : nr) * nrt;
     }
+}
+
+__global__ void k_ss_scale(double *p, int n, double f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] *= f;
 }
 
 __global__ void k_ss_zero(float2 *p, size_t n)
@@ -270,12 +289,22 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
         hipLaunchKernelGGL(k_ss_zero, dim3(2048), dim3(256), 0, s, coef, L.coef_elems);
         SG_HIP(hipGetLastError());
     }
+    const bool pot = (flags & SG_POTENTIAL) != 0;
     if (!excl) {
-        // one item per (pair, ring): the per-cell kernel with one cell per ring
+        // one item per (pair, ring): the per-cell quadratures with one cell per ring
         GLNodes gl;
         sg_gl_nodes(gl);
-        hipLaunchKernelGGL(k_self_cell_percell<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1,
-                           log(grid->r_min), du, dphi, self, gl);
+        if (pot) {
+            hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, (const double *)nullptr,
+                               nf, nr, 1, log(grid->r_min), du, dphi, 0, self, gl);
+            SG_HIP(hipGetLastError());
+            // own-cell integral I of P: the sample -I / (du dphi) scales to I / N
+            hipLaunchKernelGGL(k_ss_scale, dim3((nf * nf * nr + 255) / 256), dim3(256), 0, s, self, nf * nf * nr,
+                               -1.0 / (du * dphi));
+        } else {
+            hipLaunchKernelGGL(k_self_cell_percell<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1,
+                               log(grid->r_min), du, dphi, self, gl);
+        }
         SG_HIP(hipGetLastError());
     }
     SsRowArgs A;
@@ -284,6 +313,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     A.nf = nf;
     A.excl = excl ? 1 : 0;
     A.ind = (flags & SG_INDIRECT) ? 1 : 0;
+    A.pot = pot ? 1 : 0;
     A.lnrmin = log(grid->r_min);
     A.du = du;
     A.dphi = dphi;
@@ -314,10 +344,15 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
 
 // ------------------------------------------------------------ middle pass
 // 16-byte load of two consecutive complex values at element offset i of a
-// wave-uniform base (i even).
+// wave-uniform base (i even); NT: non-temporal (the operators are read once
+// per solve, so they need not displace Sigma~ and g^ in the caches).
+template <bool NT>
 __device__ inline void ss_ld4(const float2 *p, uint32_t i, float2 &x, float2 &y)
 {
-    const sg_v4f v = *(sg_gcv4f *)((const char *)p + (i << 3));
+    const sg_gcv4f *q = (const sg_gcv4f *)((const char *)p + (i << 3));
+    sg_v4f v;
+    if constexpr (NT) v = __builtin_nontemporal_load(q);
+    else v = *q;
     x = make_float2(v.x, v.y);
     y = make_float2(v.z, v.w);
 }
@@ -326,12 +361,13 @@ __device__ inline void ss_ld4(const float2 *p, uint32_t i, float2 &x, float2 &y)
 // LN = 256 / S lanes; lane l owns targets i0 .. i0 + V - 1, i0 = block TB +
 // V l (TB = LN V), and split s sums the operator rows k = s (mod S) of every
 // source fluid (source rows of a full mode, diagonals of a banded one); the
-// splits are combined through LDS.  Sigma~_a(m, .) of all sources is staged
-// in LDS first (a banded mode's column with w zeros on either side, so that
-// target i reads source i + d - w at padded index i + d).  The operator rows
+// splits are combined through LDS.  Sigma~_a(m, .) is staged in LDS first:
+// the whole column for a full mode; for a banded mode the window of sources
+// the block's targets reach, from blk TB - w (zero outside the grid), so
+// that target i0 + v reads source i0 + v + d - w at window index V l + v + d.  The operator rows
 // are streamed once with 16-byte loads, U rows in flight: this pass is bound
 // by reading the table.
-template <int NF, int V, int S>
+template <int NF, int V, int S, bool NT>
 __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJob *wj, int nj, const float2 *,
                                                  int kc)
 {
@@ -349,11 +385,14 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
     const SsMode md = D->modes[m];
     const bool banded = sg_uniform(md.banded) != 0;
     const int bw = banded ? sg_uniform(md.w) : 0;
-    const int cs = banded ? nr + 2 * bw + 4 : nr;   // staged column length per source
+    // staged sources: a full mode's whole column, a banded mode's window
+    // [blk TB - w, blk TB + TB + w + 4) (zero outside the grid)
+    const int cs = banded ? TB + 2 * bw + 4 : nr;
     const int nk = banded ? 2 * bw + 1 : nr;        // operator rows per (b, a)
-    if (cs > D->ss_cap) return;  // table not built for this grid: never overrun the LDS
+    const int base = banded ? blk * TB - bw : 0;
+    if (banded && bw > D->ss_wmax) return;  // table not built for this grid: never overrun the LDS
     for (int e = threadIdx.x; e < NF * cs; e += 256) {
-        const int a = e / cs, ip = e - a * cs - bw;
+        const int a = e / cs, ip = e - a * cs + base;
         ssh[e] = (ip >= 0 && ip < nr) ? gld2(D->st + a * fs, (uint32_t)sg_blk_index(m, ip, nr))
                                       : make_float2(0.f, 0.f);
     }
@@ -367,7 +406,7 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
 #pragma unroll
     for (int v = 0; v < V; v += 2) col[v / 2] = i0 + v < nr ? (uint32_t)(i0 + v) : 0u;
 #pragma unroll
-    for (int v = 0; v < V; ++v) ie[v] = i0 + v < nr ? i0 + v : 0;
+    for (int v = 0; v < V; ++v) ie[v] = i0 + v < nr ? V * ln + v : 0;
     float2 ar[V], ap[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ar[v] = ap[v] = make_float2(0.f, 0.f);
@@ -382,7 +421,7 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int v = 0; v < V; v += 2)
-                    ss_ld4(Tm, (uint32_t)(k + S * u) * nrt + col[v / 2], t[u][v], t[u][v + 1]);
+                    ss_ld4<NT>(Tm, (uint32_t)(k + S * u) * nrt + col[v / 2], t[u][v], t[u][v + 1]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -399,7 +438,7 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
         for (; k < nk; k += S) {
             float2 t[V];
 #pragma unroll
-            for (int v = 0; v < V; v += 2) ss_ld4(Tm, (uint32_t)k * nrt + col[v / 2], t[v], t[v + 1]);
+            for (int v = 0; v < V; v += 2) ss_ld4<NT>(Tm, (uint32_t)k * nrt + col[v / 2], t[v], t[v + 1]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float2 s = banded ? sa[ie[v] + k] : sa[k];
@@ -445,11 +484,11 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
     }
 }
 
-template <int NF, int V, int S> static SsPassInfo ss_info()
+template <int NF, int V, int S, bool NT = false> static SsPassInfo ss_info()
 {
     constexpr int LN = 256 / S;
     SsPassInfo k;
-    k.fn = k_ss_pass<NF, V, S>;
+    k.fn = k_ss_pass<NF, V, S, NT>;
     k.wgs = 256;
     k.tb = LN * V;
     k.lds_per_row = NF * (int)sizeof(float2);
@@ -462,13 +501,16 @@ bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out)
 {
     if (nf != 1 && nf != 2) return false;
     switch (variant) {
-    case 1: out = nf == 1 ? ss_info<1, 2, 4>() : ss_info<2, 2, 4>(); return true;
+    case 1: out = nf == 1 ? ss_info<1, 2, 4, true>() : ss_info<2, 2, 4, true>(); return true;
     case 2: out = nf == 1 ? ss_info<1, 2, 1>() : ss_info<2, 2, 1>(); return true;
     case 3: out = nf == 1 ? ss_info<1, 4, 1>() : ss_info<2, 4, 1>(); return true;
+    case 4: out = nf == 1 ? ss_info<1, 2, 4>() : ss_info<2, 2, 4>(); return true;
     default: return false;
     }
 }
 
-// Narrow radial grids split the source rows (enough workgroups per mode);
-// wide ones stream whole operator rows per workgroup.
-int sg_ss_default_variant(int nr) { return nr >= 768 ? 3 : (nr >= 384 ? 2 : 1); }
+// Row splits with 128 targets per job and non-temporal operator loads
+// measured fastest on every grid tried (256 x 512 to 1200 x 2048: many jobs
+// per mode, short banded windows, Sigma~ and g^ kept in the caches); the
+// autotuner tries the other shapes.
+int sg_ss_default_variant(int) { return 1; }

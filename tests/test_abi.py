@@ -148,6 +148,7 @@ def test_semispectral_sizes_and_validation(sg):
     assert call(2, None, 0, 512, 1024, need) == sg.ERR_ARG
     assert call(3, 256, 0, 512, 1024, need) == sg.ERR_ARG
     assert call(2, 256, sg.WITH_DH, 512, 1024, need) == sg.ERR_ARG
+    assert call(2, 256, sg.POTENTIAL | sg.INDIRECT, 512, 1024, need) == sg.ERR_ARG
     assert call(2, 256, 0, 520, 1024, need) == sg.ERR_ARG  # table alignment
     bad = sg.grid(37, 48, 20.0, 250.0)
     assert L.sg_ss_table(ctypes.byref(bad), 1, 256, 0, 512, 1024, 1 << 40, None) == sg.ERR_UNSUPPORTED

@@ -94,8 +94,8 @@ def test_semispectral_matches_pairwise_oracle(sg, T, W, nr, nphi, nf, p, gap):
 
 @pytest.mark.parametrize("nr,nphi,nf", [(300, 32, 2), (700, 16, 1), (1024, 64, 2), (512, 256, 2)])
 def test_semispectral_wide_grids_sampled(sg, T, W, nr, nphi, nf):
-    """The three middle-pass shapes (row splits, whole-row streaming with 2 and
-    4 targets per lane) at sizes where the oracle computes sampled cells; at
+    """Grids up to 1024 rows (blocks of 128 target rows cut short, several
+    jobs per mode) at sizes where the oracle computes sampled cells; at
     512 x 256 the modes m >= 33 are banded."""
     say(f"semi-spectral sampled {nr}x{nphi} nf={nf}")
     w = W.flaring(seed=nr, n_r=nr, n_phi=nphi, p=0.25, gap_w=15.0, n_fluids=nf)
@@ -203,9 +203,10 @@ def test_semispectral_mixed_batch(sg, T, W):
 
 
 def test_semispectral_tuner(sg, T, W):
-    """The autotuner's candidates for the middle pass (three shapes x four
-    cluster sizes) must reproduce the default before being timed; the tuned
-    launch still matches the oracle."""
+    """The autotuner's candidates for the middle pass (row splits, whole-row
+    streaming with 2 or 4 targets per lane, non-temporal loads; x four cluster
+    sizes) must reproduce the default before being timed; the tuned launch
+    still matches the oracle."""
     say("semi-spectral autotuner")
     w = W.flaring(seed=21, n_r=300, n_phi=16, p=0.25, n_fluids=2)
     S, _, _ = run_ss(T, w)
@@ -213,7 +214,7 @@ def test_semispectral_tuner(sg, T, W):
     mid = [r for r in res if r["pass"] == 2]
     say(f"  {mid}")
     assert len(mid) == 1 and mid[0]["length"] == 300
-    assert mid[0]["rejected"] == 0 and mid[0]["candidates"] >= 10
+    assert mid[0]["rejected"] == 0 and mid[0]["candidates"] >= 14
     S.g_r.zero_()
     S.run()
     torch.cuda.synchronize()
