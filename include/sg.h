@@ -175,7 +175,7 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * runs the phi transforms of the FFT path and, in place of the u-transform
  * pass, one pass over the radial operators; fluids.h is not used.  Such
  * discs mix freely with FFT-path discs in one batch.  sg_field_adjoint
- * returns SG_ERR_UNSUPPORTED for them.
+ * gives their dL/dSigma (not dL/dH).
  * --------------------------------------------------------------------- */
 size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids, uint32_t flags);
 size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids);
@@ -351,6 +351,11 @@ sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, 
  * not NULL, d_dh[f] = dL/dh_f (double, device, [F]) by a Parseval reduction
  * of lam against (dK/dh) (*) Sigma accumulated in double.  d_dh needs a
  * table built with SG_WITH_DH (SG_ERR_TABLE otherwise).
+ * Semi-spectral discs: d_dsigma = M^T lam with the stored radial operators
+ * transposed mode by mode (the folded indirect term and SG_POTENTIAL
+ * operators included); d_dh must be NULL (SG_ERR_UNSUPPORTED otherwise).
+ * Discs with n_species > 0, and FFT-path discs with SG_INDIRECT, return
+ * SG_ERR_UNSUPPORTED.
  * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
  * --------------------------------------------------------------------- */
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc);

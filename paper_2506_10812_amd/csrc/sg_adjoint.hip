@@ -13,6 +13,13 @@
 // dK/dh_b (to the target fluid b), self term included.  The sum over the full
 // 2D spectrum is taken over the stored half (m <= n_phi/2) with weight 2 for
 // 0 < m < n_phi/2 (the three spectra are Hermitian), accumulated in double.
+//
+// Semi-spectral discs: the middle step is per azimuthal mode, g^(m) =
+// M(m) Sigma~(m) with M = T_r (real) for g_r and i t_phi for g_phi, so its
+// transpose is dSigma~_a(m, i') = sum_{b,i} [T_r lam~_r^b(m, i) - i t_phi
+// lam~_phi^b(m, i)] (T at (m, b, a, i, i')): the same operators read once,
+// summed over targets instead of sources (k_ss_adj_full, k_ss_adj_band);
+// the phi transforms are those of the FFT-path adjoint.
 #include "sg_adjoint.h"
 #include "sg_fftpath.h"
 #include "sg_passes.h"
@@ -198,6 +205,103 @@ __global__ void __launch_bounds__(AdjShape<NU>::WGS) k_adj_col(AdjDev A)
     }
 }
 
+// ------------------------------------------------- semi-spectral middle step
+// Full modes m < m0: job (m, a, block of 16 source rows i'), four rows per
+// wave; lanes run over the targets i (two per lane, 16-byte operator loads
+// along the stored row i'), lam~^b(m, .) of both components staged in LDS
+// (zero beyond n_r), one wave reduction per row at the end.
+__device__ inline float sg_wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NF>
+__global__ void __launch_bounds__(256) k_ss_adj_full(AdjDev A, int m0)
+{
+    constexpr int RB = 16, RW = 4;
+    __shared__ __attribute__((aligned(16))) float2 lam[2][2048 + 128];
+    const int nr = A.D.nr, nrt = (nr + 1) & ~1, nb = (nr + RB - 1) / RB;
+    const int job = blockIdx.x;
+    if (job >= m0 * NF * nb) return;
+    const int blk = job % nb, a = (job / nb) % NF, m = job / (nb * NF);
+    const size_t fs = sg_blk_field_elems(A.D.nphi, nr);
+    const SsMode md = A.D.modes[m];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int span = (nrt + 127) / 128 * 128;  // staged targets, zero beyond n_r
+    float2 acc[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) acc[q] = make_float2(0.f, 0.f);
+    for (int b = 0; b < NF; ++b) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 2 * span; e += 256) {
+            const int c = e / span, i = e - c * span;
+            lam[c][i] = i < nr ? A.lt[(b * 2 + c) * fs + sg_blk_index(m, i, nr)] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        const float2 *C = A.D.spec + md.off + (size_t)(b * NF + a) * nr * nrt;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int ip = min(blk * RB + wv * RW + q, nr - 1);
+            const float2 *row = C + (size_t)ip * nrt;
+            for (int i = 2 * lane; i < span; i += 128) {
+                const int ic = i < nrt ? i : 0;
+                float2 t0, t1;  // (T_r, t_phi) of targets i, i + 1
+                gld2x2(row + ic, t0, t1);
+                const float2 r0 = lam[0][i], r1 = lam[0][i + 1], p0 = lam[1][i], p1 = lam[1][i + 1];
+                acc[q].x += t0.x * r0.x + t0.y * p0.y + t1.x * r1.x + t1.y * p1.y;
+                acc[q].y += t0.x * r0.y - t0.y * p0.x + t1.x * r1.y - t1.y * p1.x;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        const float x = sg_wave_sum(acc[q].x), y = sg_wave_sum(acc[q].y);
+        const int ip = blk * RB + wv * RW + q;
+        if (lane == 0 && ip < nr) A.dt[a * fs + sg_blk_index(m, ip, nr)] = make_float2(x, y);
+    }
+}
+
+// Banded modes m >= m0: job (m, a, block of 256 source rows), one row i' per
+// thread: dSigma~(i') = sum_d T[d][i' + w - d] lam~(i' + w - d), the
+// diagonal d read lane-consecutively, lam~ from a zero-padded LDS window.
+template <int NF>
+__global__ void __launch_bounds__(256) k_ss_adj_band(AdjDev A, int m0, int ncol)
+{
+    __shared__ __attribute__((aligned(16))) float2 lam[2][256 + 2 * 512 + 2];
+    const int nr = A.D.nr, nrt = (nr + 1) & ~1, nb = (nr + 255) / 256;
+    const int job = blockIdx.x;
+    if (job >= (ncol - m0) * NF * nb) return;
+    const int blk = job % nb, a = (job / nb) % NF, m = m0 + job / (nb * NF);
+    const size_t fs = sg_blk_field_elems(A.D.nphi, nr);
+    const SsMode md = A.D.modes[m];
+    const int w = md.w, nd = 2 * w + 1, win = 256 + 2 * w;
+    if (w > 512) return;  // not a banded mode of a supported grid
+    const int ip = blk * 256 + threadIdx.x, base = blk * 256 - w;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 0; b < NF; ++b) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 2 * win; e += 256) {
+            const int c = e / win, i = base + (e - c * win);
+            lam[c][e - c * win] = (i >= 0 && i < nr) ? A.lt[(b * 2 + c) * fs + sg_blk_index(m, i, nr)]
+                                                     : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        const float2 *C = A.D.spec + md.off + (size_t)(b * NF + a) * nd * nrt;
+        for (int d = 0; d < nd; ++d) {
+            const int i = ip + w - d;                     // target of diagonal d
+            const int ic = (i >= 0 && i < nrt) ? i : 0;   // lam~ is zero there
+            const float2 t = gload2(C, (size_t)d * nrt + ic);
+            const int k = threadIdx.x + 2 * w - d;        // window index of i
+            const float2 r = lam[0][k], p = lam[1][k];
+            acc.x += t.x * r.x + t.y * p.y;
+            acc.y += t.x * r.y - t.y * p.x;
+        }
+    }
+    if (ip < nr) A.dt[a * fs + sg_blk_index(m, ip, nr)] = acc;
+}
+
 // pass 3: inverse phi transform of dSigma~ pairs (as the forward pass 1 pairing)
 template <int N, int NF>
 __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_out(AdjDev A)
@@ -214,7 +318,8 @@ __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_out(AdjDev A)
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     const int j = valid ? idx : 0;
-    const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : 2 * j + 1;
+    // one fluid: rows 2j, 2j + 1 (an odd last row pairs with itself)
+    const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : min(2 * j + 1, nr - 1);
     const int f2 = NF == 2 ? 1 : 0;
     phi_inv_pair<N>(A.dt, i1, A.dt + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, A.dsig + (size_t)i1 * N,
                     A.dsig + f2 * plane + (size_t)i2 * N, t, pl, valid);
@@ -307,6 +412,48 @@ static sg_status adj_nu(int nu, AdjDev A, bool dh, double *d_dh, int ncol, hipSt
     return SG_ERR_UNSUPPORTED;
 }
 
+// Semi-spectral disc: lam transform, the two middle kernels, inverse transform.
+template <int NPHI, int NF>
+static sg_status adj_ss_launch(AdjDev A, int m0, int ncol, hipStream_t s)
+{
+    const int nr = A.D.nr;
+    A.count = NF * nr;
+    hipLaunchKernelGGL(k_adj_lam<NPHI>, dim3(nwg_for<NPHI>(A.count)), dim3(AdjShape<NPHI>::WGS), 0, s, A);
+    SG_HIP(hipGetLastError());
+    if (m0 > 0) {
+        hipLaunchKernelGGL(k_ss_adj_full<NF>, dim3(m0 * NF * ((nr + 15) / 16)), dim3(256), 0, s, A, m0);
+        SG_HIP(hipGetLastError());
+    }
+    if (m0 < ncol) {
+        hipLaunchKernelGGL(k_ss_adj_band<NF>, dim3((ncol - m0) * NF * ((nr + 255) / 256)), dim3(256), 0, s, A, m0,
+                           ncol);
+        SG_HIP(hipGetLastError());
+    }
+    const int pairs = NF == 2 ? nr : (nr + 1) / 2;
+    A.count = pairs;
+    hipLaunchKernelGGL((k_adj_out<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)), dim3(AdjShape<NPHI>::WGS), 0, s, A);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+template <int NF>
+static sg_status adj_ss_phi(int nphi, AdjDev A, int m0, int ncol, hipStream_t s)
+{
+    switch (nphi) {
+    case 4: return adj_ss_launch<4, NF>(A, m0, ncol, s);
+    case 8: return adj_ss_launch<8, NF>(A, m0, ncol, s);
+    case 16: return adj_ss_launch<16, NF>(A, m0, ncol, s);
+    case 32: return adj_ss_launch<32, NF>(A, m0, ncol, s);
+    case 64: return adj_ss_launch<64, NF>(A, m0, ncol, s);
+    case 128: return adj_ss_launch<128, NF>(A, m0, ncol, s);
+    case 256: return adj_ss_launch<256, NF>(A, m0, ncol, s);
+    case 512: return adj_ss_launch<512, NF>(A, m0, ncol, s);
+    case 1024: return adj_ss_launch<1024, NF>(A, m0, ncol, s);
+    case 2048: return adj_ss_launch<2048, NF>(A, m0, ncol, s);
+    }
+    return SG_ERR_UNSUPPORTED;
+}
+
 template <int NF>
 static sg_status adj_phi(int nphi, int nu, AdjDev A, bool dh, double *d_dh, int ncol, hipStream_t s)
 {
@@ -329,6 +476,29 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
                          double *dh, void *ws, hipStream_t s)
 {
     const int nr = d.grid.n_r, nphi = d.grid.n_phi, nf = d.fluids.n_fluids;
+    if (d.flags & SG_SEMI_SPECTRAL) {
+        const bool full = (d.flags & SG_SS_FULL) != 0;
+        const SsLayout L = sg_ss_layout(nr, nphi, nf, sg_ss_du(d.grid), full);
+        const char *tb = (const char *)d.table;
+        AdjDev A{};
+        A.D.spec = (const float2 *)(tb + L.off_coef);
+        A.D.modes = (const SsMode *)(tb + L.off_modes);
+        A.D.tw_phi = (const float2 *)(tb + L.off_tw_phi);
+        A.D.nr = nr;
+        A.D.nphi = nphi;
+        A.D.nf = nf;
+        A.lam_r = lam_r;
+        A.lam_p = lam_p;
+        A.dsig = dsig;
+        const size_t fs = sg_blk_field_elems(nphi, nr);
+        A.lt = (float2 *)ws;
+        A.dt = (float2 *)((char *)ws + sg_align256(sizeof(float2) * fs * 2 * nf));
+        // full modes first (the band shrinks with m), then the banded ones
+        int m0 = 0;
+        while (m0 < L.ncol && !sg_ss_is_banded(sg_ss_band(m0, nr, L.du, full), nr)) ++m0;
+        if (nf == 1) return adj_ss_phi<1>(nphi, A, m0, L.ncol, s);
+        return adj_ss_phi<2>(nphi, A, m0, L.ncol, s);
+    }
     const TableLayout L = sg_table_layout(nr, nphi, nf, d.flags);
     const char *tb = (const char *)d.table;
     AdjDev A{};

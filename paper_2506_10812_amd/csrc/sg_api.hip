@@ -273,7 +273,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
 
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
 {
-    if (!disc || check_disc(*disc) != SG_OK || (disc->flags & SG_SEMI_SPECTRAL) || disc->n_species) return 0;
+    if (!disc || check_disc(*disc) != SG_OK || disc->n_species) return 0;
     return sg_adjoint_ws_bytes(*disc);
 }
 
@@ -284,8 +284,13 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
-    if ((disc->flags & (SG_INDIRECT | SG_SEMI_SPECTRAL)) || disc->n_species != 0) return SG_ERR_UNSUPPORTED;
-    if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
+    if (disc->n_species != 0) return SG_ERR_UNSUPPORTED;
+    if (disc->flags & SG_SEMI_SPECTRAL) {
+        if (d_dh) return SG_ERR_UNSUPPORTED;  // dL/dSigma only
+    } else {
+        if (disc->flags & SG_INDIRECT) return SG_ERR_UNSUPPORTED;
+        if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
+    }
     if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))
         return SG_ERR_WORKSPACE;
     return sg_adjoint_run(*disc, d_lam_r, d_lam_phi, d_dsigma, d_dh, d_ws, (hipStream_t)stream);

@@ -163,9 +163,9 @@ def test_semispectral_sizes_and_validation(sg):
     assert sg.field_fft_workspace_bytes([d]) == 0
     d.flags = sg.SEMI_SPECTRAL | sg.INDIRECT | sg.SELF_CELL_EXCLUDE
     assert sg.field_fft_workspace_bytes([d]) > 0
-    # no adjoint for semi-spectral discs
-    assert sg.field_adjoint_workspace_bytes(d) == 0
-    assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, None, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED
+    # semi-spectral adjoint: dL/dSigma only
+    assert sg.field_adjoint_workspace_bytes(d) > 0
+    assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, 4096, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED
 
 
 def test_struct_layouts_match_the_header(sg, tmp_path):
