@@ -110,3 +110,48 @@ def test_exponential_disc_first_order_convergence(sg, T, W):
         meds.append(med)
     for a, b in zip(meds, meds[1:]):
         assert 1.6 < a / b < 2.5, meds
+
+
+def test_appD_constant_h_error_grows_with_flaring(sg, T, W):
+    """App. D: the full FFT method needs H/r constant; on a flaring disc its
+    field differs from the semi-spectral reference computed with the true
+    H(r), more so the stronger the flaring, while a temperature gap only
+    matters near the gap.  Power-law disc Sigma ~ r^-1.5 on [20, 250] AU,
+    512 x 1024; FFT path with h = 0.05 against the semi-spectral path with
+    H/r = 0.05 (r/100)^p (and with the gap factor)."""
+    nr, nphi = 512, 1024
+    base = W.flaring(seed=1, n_r=nr, n_phi=nphi, p=0.0)
+    sig = base["sigma"].copy()
+    r = np.exp(np.log(base["r_min"]) + (np.arange(nr) + 0.5) * np.log(base["r_max"] / base["r_min"]) / nr)
+    sig[:] = (r / 100.0)[None, :, None] ** -1.5  # axisymmetric power-law disc
+    F = T.FFTField([dict(base, h=[0.05])])
+    F.set_sigma(0, sig)
+    F.run()
+    torch.cuda.synchronize()
+    g_fft = F.g_r[0][0].double().cpu().numpy().mean(axis=1)
+
+    def err(p, gap):
+        w = W.flaring(seed=1, n_r=nr, n_phi=nphi, p=p, gap_w=gap)
+        S = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], 1)
+        S.refresh(w["H"])
+        S.sigma.copy_(torch.tensor(sig, dtype=torch.float32))
+        S.run()
+        torch.cuda.synchronize()
+        g = S.g_r[0].double().cpu().numpy().mean(axis=1)
+        rel = np.abs(g_fft - g) / np.abs(g)
+        keep = np.abs(g) > 0.05 * np.abs(g).max()  # away from the zero of g_r
+        return rel, keep
+
+    med = {}
+    for p in (0.125, 0.25, 0.5):
+        rel, keep = err(p, None)
+        med[p] = float(np.median(rel[keep]))
+        print(f"  flaring p = {p}: median relative difference {med[p]:.2e}, max {rel[keep].max():.2e}",
+              flush=True)
+    assert med[0.125] < med[0.25] < med[0.5]
+    rel, keep = err(0.0, 10.0)
+    near = keep & (np.abs(r - 100.0) < 30.0)
+    far = keep & (np.abs(r - 100.0) > 60.0)
+    print(f"  gap w = 10: max near the gap {rel[near].max():.2e}, median far from it {np.median(rel[far]):.2e}",
+          flush=True)
+    assert rel[near].max() > 10 * np.median(rel[far])
