@@ -7,7 +7,9 @@ product package.  The arithmetic lives in ``sg_oracle.c`` (plain C, double
 precision, OpenMP over target cells); this file only marshals numpy arrays.
 
 Array layout everywhere: ``[fluid][i_r][j_phi]`` with phi fastest, fluid 0 =
-gas, 1 = dust.  Flags: bit 0 excludes the self-cell term.
+gas, 1 = dust.  Flags: bit 0 excludes the self-cell term; bit 1 selects a
+uniform radial grid (centres r_min + (i + 1/2) dr, cell areas r_i dr dphi)
+instead of the log-spaced one.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ _SRC = os.path.join(_HERE, "sg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXCLUDE_SELF = 1
+LINEAR_R = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -73,6 +76,10 @@ def lib():
         L.sg_oracle_potential_kernel.argtypes = [ctypes.c_double] * 3
         L.sg_oracle_potential_self.restype = ctypes.c_double
         L.sg_oracle_potential_self.argtypes = [ctypes.c_double] * 5
+        L.sg_oracle_potential_self_range.restype = ctypes.c_double
+        L.sg_oracle_potential_self_range.argtypes = [ctypes.c_double] * 6
+        L.sg_oracle_self_cell_range.restype = ctypes.c_double
+        L.sg_oracle_self_cell_range.argtypes = [ctypes.c_double] * 5
         L.sg_oracle_potential_pairwise.restype = ctypes.c_int
         L.sg_oracle_potential_pairwise.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -86,7 +93,7 @@ def lib():
         L.sg_oracle_indirect.restype = ctypes.c_int
         L.sg_oracle_indirect.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-            _dp, _dp, _dp, _dp]
+            _dp, _dp, _dp, ctypes.c_uint, _dp]
         L.sg_oracle_threads.restype = ctypes.c_int
         L.sg_oracle_threads.argtypes = []
         _lib = L
@@ -247,6 +254,18 @@ def potential_self(r, Ha, Hb, du, dphi):
     return lib().sg_oracle_potential_self(float(r), float(Ha), float(Hb), float(du), float(dphi))
 
 
+def potential_self_range(r, Ha, Hb, xlo, xhi, dphi):
+    """Own-cell integral of P over X = ln(r'/r) in [xlo, xhi], |phi| <= dphi/2."""
+    return lib().sg_oracle_potential_self_range(float(r), float(Ha), float(Hb), float(xlo), float(xhi),
+                                                float(dphi))
+
+
+def self_cell_range(ha, hb, xlo, xhi, dphi):
+    """Own-cell integral I of K_r over X in [xlo, xhi], |phi| <= dphi/2 (the
+    field's own-cell term is -Sigma I)."""
+    return lib().sg_oracle_self_cell_range(float(ha), float(hb), float(xlo), float(xhi), float(dphi))
+
+
 def potential_pairwise(nr, nphi, rmin, rmax, h, sigma, H=None, targets=None, flags=0):
     """Potential at cell centres per target fluid: array [nf][n_targets]."""
     sigma = _d(sigma)
@@ -286,14 +305,15 @@ def hsg(H, Q):
     return out
 
 
-def indirect(nr, nphi, rmin, rmax, h, sigma, H=None):
+def indirect(nr, nphi, rmin, rmax, h, sigma, H=None, flags=0):
     """Indirect-term sums (A_a, B_a) per source fluid: array [nf][2]."""
     sigma = _d(sigma)
     nf = sigma.shape[0]
     h = _d(np.atleast_1d(h))
     Hd = None if H is None else _d(H)
     AB = np.empty((nf, 2))
-    rc = lib().sg_oracle_indirect(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(Hd), _ptr(sigma), _ptr(AB))
+    rc = lib().sg_oracle_indirect(nr, nphi, rmin, rmax, nf, _ptr(h), _ptr(Hd), _ptr(sigma), flags,
+                                  _ptr(AB))
     if rc:
         raise RuntimeError(f"sg_oracle_indirect failed ({rc})")
     return AB
@@ -309,10 +329,14 @@ def indirect_field(nr, nphi, AB):
     return np.tile(gr, nr), np.tile(gp, nr)
 
 
-def grid(nr, nphi, rmin, rmax):
-    """Cell centres (r_i, phi_j) and widths (du, dphi) of the oracle's grid."""
-    du = np.log(rmax / rmin) / nr
+def grid(nr, nphi, rmin, rmax, flags=0):
+    """Cell centres (r_i, phi_j) and widths (du, dphi) of the oracle's grid
+    (with LINEAR_R: (r_i, phi_j, dr, dphi))."""
     dphi = 2.0 * np.pi / nphi
-    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * du)
     phi = (np.arange(nphi) + 0.5) * dphi
+    if flags & LINEAR_R:
+        dr = (rmax - rmin) / nr
+        return rmin + (np.arange(nr) + 0.5) * dr, phi, dr, dphi
+    du = np.log(rmax / rmin) / nr
+    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * du)
     return r, phi, du, dphi

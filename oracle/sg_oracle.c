@@ -264,45 +264,139 @@ double sg_oracle_self_cell(double ha, double hb, double du, double dphi, int whi
 }
 
 /* ------------------------------------------------------------------------
- * Grid helpers (log r x uniform phi).
+ * Own-cell integral over an X range that need not be symmetric (the cells of
+ * a uniform radial grid, reading "linear radial grids"):
+ *   I = int_{xlo}^{xhi} int_{-dphi/2}^{dphi/2} K_r(X, phi) dX dphi
+ * (K_r of orc_conv, which carries the measure r'^2; the field's own-cell
+ * term is -Sigma I).  K_r behaves like 1/rho at the origin, which is
+ * integrable, so each side X > 0 and X < 0 is integrated on its own: polar
+ * coordinates about the origin over [0, a] x [0, b] (two triangles split at
+ * the diagonal, geometric radial panels as above), doubled for phi < 0
+ * (K_r is even in phi).  For xlo = -xhi it equals du dphi times
+ * sg_oracle_self_cell (test).
+ * ------------------------------------------------------------------------ */
+static double orc_quadrant(double a, double b, double ha, double hb, int sgn, int which)
+{
+    const double thc = atan2(b, a);
+    double total = 0.0;
+    for (int tri = 0; tri < 2; ++tri) {
+        double th0 = tri == 0 ? 0.0 : thc;
+        double th1 = tri == 0 ? thc : 0.5 * ORC_PI;
+        double acc = 0.0;
+        for (int i = 0; i < ORC_GL_N; ++i) {
+            double th = th0 + (th1 - th0) * orc_gl_x[i];
+            double c = cos(th), sn = sin(th);
+            double rmax = tri == 0 ? a / c : b / sn;
+            double inner = 0.0;
+            for (int pnl = 0; pnl < ORC_PANELS; ++pnl) {
+                double hi = pow(4.0, -(double)(ORC_PANELS - 1 - pnl));
+                double lo = pnl == 0 ? 0.0 : hi / 4.0;
+                double part = 0.0;
+                for (int j = 0; j < ORC_GLR_N; ++j) {
+                    double rho = rmax * (lo + (hi - lo) * orc_glr_x[j]);
+                    double kr, kp;
+                    orc_conv(sgn * rho * c, rho * sn, ha, hb, which, &kr, &kp);
+                    part += orc_glr_w[j] * rho * kr;
+                }
+                inner += part * (hi - lo) * rmax;
+            }
+            acc += orc_gl_w[i] * inner;
+        }
+        total += acc * (th1 - th0);
+    }
+    return total;
+}
+
+double sg_oracle_self_cell_range(double ha, double hb, double xlo, double xhi, double dphi)
+{
+    orc_gl_init();
+    const double b = 0.5 * dphi;
+    double I = 0.0;
+    if (xhi > 0.0) I += orc_quadrant(xhi, b, ha, hb, 1, 0);
+    if (xlo < 0.0) I += orc_quadrant(-xlo, b, ha, hb, -1, 0);
+    return 2.0 * I;
+}
+
+/* ------------------------------------------------------------------------
+ * Grid helpers: log r (the default) or uniform r (ORC_FLAG_LINEAR_R; the
+ * semi-spectral method allows linear radial grids, Sect. 5.2, and NIRVANA's
+ * tests use one, Sect. 4.1) x uniform phi.  Uniform r: edges r_min + k dr,
+ * centres r_min + (i + 1/2) dr, cell measure r_i dr dphi (the exact area
+ * of the annular sector); its own cell spans X = ln(r/r_i) in
+ * [ln(1 - dr/(2 r_i)), ln(1 + dr/(2 r_i))].
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int nr, nphi;
-    double du, dphi, lnrmin;
+    int nr, nphi, linear;
+    double du, dphi, lnrmin, rmin, dr;
 } orc_grid;
 
-static orc_grid orc_make_grid(int nr, int nphi, double rmin, double rmax)
+#define ORC_FLAG_EXCLUDE_SELF 1u
+#define ORC_FLAG_LINEAR_R 2u
+
+static orc_grid orc_make_grid_f(int nr, int nphi, double rmin, double rmax, unsigned flags)
 {
     orc_grid g;
     g.nr = nr;
     g.nphi = nphi;
+    g.linear = (flags & ORC_FLAG_LINEAR_R) != 0;
     g.lnrmin = log(rmin);
     g.du = log(rmax / rmin) / nr;
+    g.rmin = rmin;
+    g.dr = (rmax - rmin) / nr;
     g.dphi = 2.0 * ORC_PI / nphi;
     return g;
 }
-static double orc_r(const orc_grid *g, int i) { return exp(g->lnrmin + (i + 0.5) * g->du); }
+static orc_grid orc_make_grid(int nr, int nphi, double rmin, double rmax)
+{
+    return orc_make_grid_f(nr, nphi, rmin, rmax, 0u);
+}
+static double orc_r(const orc_grid *g, int i)
+{
+    return g->linear ? g->rmin + (i + 0.5) * g->dr : exp(g->lnrmin + (i + 0.5) * g->du);
+}
 static double orc_phi(const orc_grid *g, int j) { return (j + 0.5) * g->dphi; }
-
-#define ORC_FLAG_EXCLUDE_SELF 1u
+static double orc_area(const orc_grid *g, int i)
+{
+    const double r = orc_r(g, i);
+    return g->linear ? r * g->dr * g->dphi : r * r * g->du * g->dphi;
+}
+/* X range of the own cell of ring i */
+static void orc_cell_x(const orc_grid *g, int i, double *xlo, double *xhi)
+{
+    if (!g->linear) {
+        *xlo = -0.5 * g->du;
+        *xhi = 0.5 * g->du;
+        return;
+    }
+    const double r = orc_r(g, i);
+    *xlo = log1p(-0.5 * g->dr / r);
+    *xhi = log1p(0.5 * g->dr / r);
+}
 
 /* small direct-mapped memo of self-cell values keyed on (ha, hb) bits */
 typedef struct {
-    double ha, hb, v;
+    double ha, hb, xlo, v;
     int used;
 } orc_memo;
 
-static double orc_self_memo(orc_memo *m, int nm, double ha, double hb, double du, double dphi)
+/* Own-cell integral I (see sg_oracle_self_cell_range) of a cell with the
+ * given X range, memoised on (ha, hb, xlo); log cells (xlo = -du/2) use the
+ * symmetric average, I = du dphi Kbar. */
+static double orc_self_memo(orc_memo *m, int nm, double ha, double hb, double xlo, double xhi,
+                            double dphi, int linear)
 {
-    uint64_t ka, kb;
+    uint64_t ka, kb, kx;
     memcpy(&ka, &ha, 8);
     memcpy(&kb, &hb, 8);
-    uint64_t key = (ka * 0x9E3779B97F4A7C15ull) ^ (kb + (ka >> 7));
+    memcpy(&kx, &xlo, 8);
+    uint64_t key = (ka * 0x9E3779B97F4A7C15ull) ^ (kb + (ka >> 7)) ^ (kx * 0xC2B2AE3D27D4EB4Full);
     orc_memo *e = &m[key % (uint64_t)nm];
-    if (e->used && e->ha == ha && e->hb == hb) return e->v;
-    double v = sg_oracle_self_cell(ha, hb, du, dphi, 0);
+    if (e->used && e->ha == ha && e->hb == hb && e->xlo == xlo) return e->v;
+    double v = linear ? sg_oracle_self_cell_range(ha, hb, xlo, xhi, dphi)
+                      : (xhi - xlo) * dphi * sg_oracle_self_cell(ha, hb, xhi - xlo, dphi, 0);
     e->ha = ha;
     e->hb = hb;
+    e->xlo = xlo;
     e->v = v;
     e->used = 1;
     return v;
@@ -355,13 +449,17 @@ static double orc_pot_integrand(double X, double phi, double r, double Ha, doubl
     return sg_oracle_potential_kernel(s, Ha, Hb) * r * r * exp(2.0 * X);
 }
 
-double sg_oracle_potential_self(double r, double Ha, double Hb, double du, double dphi)
+/* Own-cell integral over X in [xlo, xhi] (the two sides of X = 0 separately;
+ * xlo = -du/2, xhi = du/2 for a log cell). */
+double sg_oracle_potential_self_range(double r, double Ha, double Hb, double xlo, double xhi, double dphi)
 {
     orc_gl_init();
-    const double a = 0.5 * du, b = 0.5 * dphi;
-    const double thc = atan2(b, a);
+    const double b = 0.5 * dphi;
     double total = 0.0;
     for (int sgn = -1; sgn <= 1; sgn += 2) {  /* X < 0 and X > 0; phi: even, doubled */
+        const double a = sgn > 0 ? xhi : -xlo;
+        if (!(a > 0.0)) continue;
+        const double thc = atan2(b, a);
         for (int tri = 0; tri < 2; ++tri) {
             double th0 = tri == 0 ? 0.0 : thc;
             double th1 = tri == 0 ? thc : 0.5 * ORC_PI;
@@ -389,6 +487,11 @@ double sg_oracle_potential_self(double r, double Ha, double Hb, double du, doubl
     return total;
 }
 
+double sg_oracle_potential_self(double r, double Ha, double Hb, double du, double dphi)
+{
+    return sg_oracle_potential_self_range(r, Ha, Hb, -0.5 * du, 0.5 * du, dphi);
+}
+
 /* Potential at cell centres, per target fluid b:
  *   Phi_b(i) = sum_a sum_{k != i} Sigma_a[k] A_k P_ab(s_ik; H_a[k], H_b[i])
  *            + sum_a Sigma_a[i] (self integral with H_a[i], H_b[i]),
@@ -400,7 +503,7 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
                                  int64_t nt, const int64_t *targets, unsigned flags, double *pot)
 {
     if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
-    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     for (int64_t ti = 0; ti < nt; ++ti)
         if (targets && (targets[ti] < 0 || targets[ti] >= N)) return 2;
@@ -416,7 +519,7 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
             for (int a = 0; a < nf; ++a) {
                 for (int kr = 0; kr < nr; ++kr) {
                     const double rk = orc_r(&g, kr);
-                    const double area = rk * rk * g.du * g.dphi;
+                    const double area = orc_area(&g, kr);
                     for (int kp = 0; kp < nphi; ++kp) {
                         const int64_t k = (int64_t)kr * nphi + kp;
                         if (k == i) continue;
@@ -429,7 +532,9 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
                 }
                 if (!(flags & ORC_FLAG_EXCLUDE_SELF)) {
                     const double Ha = H ? H[(int64_t)a * N + i] : h[a] * ri;
-                    acc += sigma[(int64_t)a * N + i] * sg_oracle_potential_self(ri, Ha, Hb, g.du, g.dphi);
+                    double xlo, xhi;
+                    orc_cell_x(&g, ir, &xlo, &xhi);
+                    acc += sigma[(int64_t)a * N + i] * sg_oracle_potential_self_range(ri, Ha, Hb, xlo, xhi, g.dphi);
                 }
             }
             pot[(int64_t)b * nt + ti] = acc;
@@ -510,16 +615,16 @@ void sg_oracle_hsg(int64_t n, int nf, const double *H, const double *Q, double *
  * rotation equivariance and the point-mass limit with its next term (tests).
  * ------------------------------------------------------------------------ */
 int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const double *h,
-                       const double *H, const double *sigma, double *AB)
+                       const double *H, const double *sigma, unsigned flags, double *AB)
 {
     if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
-    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     for (int a = 0; a < nf; ++a) {
         double sa = 0.0, sb = 0.0;
         for (int i = 0; i < nr; ++i) {
             const double r = orc_r(&g, i);
-            const double area = r * r * g.du * g.dphi;
+            const double area = orc_area(&g, i);
             for (int j = 0; j < nphi; ++j) {
                 const int64_t k = (int64_t)a * N + (int64_t)i * nphi + j;
                 const double Hk = H ? H[k] : h[a] * r;
@@ -544,7 +649,9 @@ int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const
  *         (x_i - x_k)/|x_i - x_k|          (Cartesian vectors)
  *   g_r = G . e_r(phi_i),  g_phi = G . e_phi(phi_i)
  *   plus, unless excluded, the self term
- *   g_r += - du dphi sum_a Sigma_a[i] Kbar_r^{ab}(h_a = H_a[i]/r_i, h_b = H_b[i]/r_i).
+ *   g_r += - du dphi sum_a Sigma_a[i] Kbar_r^{ab}(h_a = H_a[i]/r_i, h_b = H_b[i]/r_i)
+ *   (on a uniform radial grid, ORC_FLAG_LINEAR_R: - sum_a Sigma_a[i] I^{ab}
+ *   with I the own-cell integral of sg_oracle_self_cell_range).
  * H == NULL means H_f = h[f] r.  Layout: arrays [fluid][i_r][j_phi].
  * Outputs gr, gphi: [n_fluids][n_targets].
  * Parity pinned by Newton's third law, axisymmetry, the razor-thin
@@ -557,7 +664,7 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
 {
     if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
     orc_gl_init();
-    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     double *xs = malloc(sizeof(double) * N), *ys = malloc(sizeof(double) * N);
     double *A = malloc(sizeof(double) * N), *Hc = malloc(sizeof(double) * nf * N);
@@ -570,7 +677,7 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
             rr[k] = r;
             xs[k] = r * cos(p);
             ys[k] = r * sin(p);
-            A[k] = r * r * g.du * g.dphi;
+            A[k] = orc_area(&g, i);
             for (int f = 0; f < nf; ++f) Hc[f * N + k] = H ? H[f * N + k] : h[f] * r;
         }
     const int want_self = !(flags & ORC_FLAG_EXCLUDE_SELF);
@@ -603,8 +710,9 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
                             ha = h[a];
                             hb = h[b];
                         }
-                        double kb = orc_self_memo(memo, 64, ha, hb, g.du, g.dphi);
-                        gself -= g.du * g.dphi * Sa[i] * kb;
+                        double xlo, xhi;
+                        orc_cell_x(&g, (int)(i / nphi), &xlo, &xhi);
+                        gself -= Sa[i] * orc_self_memo(memo, 64, ha, hb, xlo, xhi, g.dphi, g.linear);
                     }
                 }
                 gr[b * nt + t] = Gx * cp + Gy * sp + gself;

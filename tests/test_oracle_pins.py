@@ -585,3 +585,84 @@ def test_hsg_limits_and_defining_quadratic():
     x = 1 / (1 / Q[0] + 1 / Q[1])
     np.testing.assert_allclose(2 * x / math.pi * f[0] ** 2 + f[0] - x, 0, atol=1e-13)
     np.testing.assert_allclose(f[0], f[1], rtol=1e-15)
+
+
+# ------------------------------------------------------- uniform radial grid
+@pytest.mark.parametrize("ha,hb,du,dphi", [(0.05, 0.02, 0.01, 0.003), (0.1, 0.1, 0.2, 0.1),
+                                           (0.01, 0.03, 0.05, 0.2)])
+def test_self_cell_range_symmetric_equals_cell_average(ha, hb, du, dphi):
+    """The one-sided quadrature of the own-cell integral over [-du/2, du/2]
+    equals du dphi times the X-symmetrised average (two different rules)."""
+    got = O.self_cell_range(ha, hb, -du / 2, du / 2, dphi)
+    ref = du * dphi * O.self_cell(ha, hb, du, dphi)
+    assert abs(got / ref - 1) < 1e-11
+
+
+@pytest.mark.parametrize("ha,hb,delta,dphi", [(0.05, 0.05, 0.02, 0.01), (0.02, 0.1, 0.1, 0.05)])
+def test_self_cell_range_asymmetric_strip(ha, hb, delta, dphi):
+    """A uniform-grid cell spans X in [ln(1 - delta), ln(1 + delta)]: its own-cell
+    integral is the symmetric part over |X| <= ln(1 + delta) plus the regular
+    strip ln(1 - delta) <= X <= -ln(1 + delta), which scipy's adaptive dblquad
+    integrates from the convolution kernels directly."""
+    xlo, xhi = math.log1p(-delta), math.log1p(delta)
+    sym = O.self_cell_range(ha, hb, -xhi, xhi, dphi)
+
+    def f(phi, X):
+        return O.conv_kernels(np.array([X]), np.array([phi]), ha, hb)[0][0]
+    strip, _ = si.dblquad(f, xlo, -xhi, -dphi / 2, dphi / 2, epsabs=0, epsrel=1e-11)
+    got = O.self_cell_range(ha, hb, xlo, xhi, dphi)
+    assert abs(got - (sym + strip)) < 1e-10 * abs(got)
+
+
+def test_potential_self_range_asymmetric_strip():
+    """The same decomposition for the potential's own-cell integral."""
+    r, Ha, Hb, delta, dphi = 1.5, 0.05, 0.08, 0.03, 0.02
+    xlo, xhi = math.log1p(-delta), math.log1p(delta)
+    sym = O.potential_self_range(r, Ha, Hb, -xhi, xhi, dphi)
+
+    def f(phi, X):
+        s = r * math.sqrt(math.exp(X) * 4 * (math.sinh(0.5 * X) ** 2 + math.sin(0.5 * phi) ** 2))
+        return O.potential_kernel([s], Ha, Hb)[0] * r * r * math.exp(2 * X)
+    strip, _ = si.dblquad(f, xlo, -xhi, -dphi / 2, dphi / 2, epsabs=0, epsrel=1e-11)
+    got = O.potential_self_range(r, Ha, Hb, xlo, xhi, dphi)
+    assert abs(got - (sym + strip)) < 1e-10 * abs(got)
+    assert O.potential_self_range(r, Ha, Hb, -0.01, 0.01, dphi) == O.potential_self(r, Ha, Hb, 0.02, dphi)
+
+
+def test_newton_third_law_uniform_radial_grid():
+    """Zero net force on the whole disc on a uniform radial grid (cell areas
+    r_i dr dphi), self term excluded, per-cell scale heights."""
+    rng = np.random.default_rng(12)
+    nr, nphi, rmin, rmax = 8, 13, 0.5, 2.5
+    r, phi, dr, dphi = O.grid(nr, nphi, rmin, rmax, O.LINEAR_R)
+    assert np.allclose(np.diff(r), dr)
+    sig = rng.uniform(0.2, 2.0, (2, nr, nphi))
+    H = rng.uniform(0.01, 0.2, (2, nr, nphi))
+    gr, gp = O.field_pairwise(nr, nphi, rmin, rmax, [0, 0], sig, H=H, flags=O.EXCLUDE_SELF | O.LINEAR_R)
+    A = (r * dr * dphi)[:, None] * np.ones((nr, nphi))
+    tot = np.zeros(2)
+    scale = 0.0
+    P = np.broadcast_to(phi[None, :], (nr, nphi)).ravel()
+    for b in range(2):
+        gx = gr[b] * np.cos(P) - gp[b] * np.sin(P)
+        gy = gr[b] * np.sin(P) + gp[b] * np.cos(P)
+        m = (sig[b] * A).ravel()
+        tot += [np.sum(m * gx), np.sum(m * gy)]
+        scale += np.sum(m * np.hypot(gx, gy))
+    assert np.all(np.abs(tot) < 1e-13 * scale)
+
+
+def test_two_cell_system_uniform_grid_by_hand():
+    """Two cells on one ring of a uniform radial grid: the pull is
+    Sigma A K(2 r) with the sector area A = r dr dphi and r the arithmetic
+    centre of the ring."""
+    rmin, rmax = 1.0, 1.2
+    r = 1.1
+    H = 0.3 * r
+    sig = np.array([[[0.0, 2.0]]])
+    gr, gp = O.field_pairwise(1, 2, rmin, rmax, [0.3], sig, flags=O.EXCLUDE_SELF | O.LINEAR_R)
+    d = 2 * r / H
+    K = float(1 / mp.sqrt(mp.pi) / H ** 2 * d / 8 * _F_mp(d * d / 8))
+    A = ((rmax ** 2 - rmin ** 2) / 2) * math.pi  # half the annulus
+    assert gr[0, 0] == pytest.approx(-2.0 * A * K, rel=1e-14)
+    assert gr[0, 1] == 0.0
