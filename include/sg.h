@@ -66,7 +66,8 @@ enum {
     SG_INDIRECT = 4u,          /* add the indirect term (see below)           */
     SG_SEMI_SPECTRAL = 8u,     /* disc uses a semi-spectral table (below)     */
     SG_SS_FULL = 16u,          /* semi-spectral: keep every operator entry    */
-    SG_POTENTIAL = 32u         /* semi-spectral: operators of the potential   */
+    SG_POTENTIAL = 32u,        /* semi-spectral: operators of the potential   */
+    SG_LINEAR_R = 64u          /* semi-spectral: uniform radial grid          */
 };
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
@@ -159,6 +160,16 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * d_ws: sg_ss_table_workspace_bytes() bytes (<= about 130 MB), contents
  * undefined afterwards.  Asynchronous on `stream`.  The table is position
  * independent.
+ *
+ * SG_LINEAR_R: the radial grid is uniform instead of log-spaced (the
+ * semi-spectral method allows linear radial grids, Sect. 5.2; NIRVANA's
+ * tests use one, Sect. 4.1): edges r_min + k dr, dr = (r_max - r_min)/n_r,
+ * centres r_i = r_min + (i + 1/2) dr, cell areas A_i = r_i dr dphi (the
+ * exact sector areas); d_H holds H_f at these centres; the own-cell terms
+ * integrate the cell's own X = ln(r'/r_i) range, [ln(1 - dr/(2 r_i)),
+ * ln(1 + dr/(2 r_i))]; the band rule uses the smallest log spacing of
+ * adjacent centres (at the outer edge).  The solve itself does not depend
+ * on the radii.  Discs built from such a table carry SG_LINEAR_R too.
  *
  * SG_POTENTIAL: the table holds the operators of the potential of Sect. 5.5
  * and the appendix "Conservative force" instead of the field's,

@@ -22,6 +22,7 @@ INDIRECT = 4
 SEMI_SPECTRAL = 8
 SS_FULL = 16
 POTENTIAL = 32
+LINEAR_R = 64
 
 
 class SGError(RuntimeError):

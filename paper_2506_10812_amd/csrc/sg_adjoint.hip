@@ -478,7 +478,7 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
     const int nr = d.grid.n_r, nphi = d.grid.n_phi, nf = d.fluids.n_fluids;
     if (d.flags & SG_SEMI_SPECTRAL) {
         const bool full = (d.flags & SG_SS_FULL) != 0;
-        const SsLayout L = sg_ss_layout(nr, nphi, nf, sg_ss_du(d.grid), full);
+        const SsLayout L = sg_ss_layout(nr, nphi, nf, sg_ss_du(d.grid, d.flags), full);
         const char *tb = (const char *)d.table;
         AdjDev A{};
         A.D.spec = (const float2 *)(tb + L.off_coef);

@@ -55,7 +55,7 @@ static bool ss_flags_ok(uint32_t flags)
 {
     if ((flags & SG_POTENTIAL) && (flags & SG_INDIRECT)) return false;
     return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL | SG_SS_FULL |
-                                SG_POTENTIAL)) == 0;
+                                SG_POTENTIAL | SG_LINEAR_R)) == 0;
 }
 
 extern "C" {
@@ -88,7 +88,7 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
 size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids, uint32_t flags)
 {
     if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2 || !ss_flags_ok(flags)) return 0;
-    return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids, sg_ss_du(*grid), (flags & SG_SS_FULL) != 0).total;
+    return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids, sg_ss_du(*grid, flags), (flags & SG_SS_FULL) != 0).total;
 }
 
 size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids)

@@ -615,7 +615,7 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         if (d.flags & SG_SEMI_SPECTRAL) {
             // staged column of the widest banded mode of this grid (the band
             // rule without SG_SS_FULL, so that any table of the grid fits)
-            const SsLayout B = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, sg_ss_du(d.grid), false);
+            const SsLayout B = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, sg_ss_du(d.grid, d.flags), false);
             D.ss_wmax = B.max_w;
             const SsLayout L = sg_ss_layout(d.grid.n_r, d.grid.n_phi, d.fluids.n_fluids, 1.0, true);
             D.spec = (const float2 *)(tb + L.off_coef);

@@ -261,7 +261,15 @@ inline SsLayout sg_ss_layout(int nr, int nphi, int nf, double du, bool full)
     return L;
 }
 
-inline double sg_ss_du(const sg_grid &g) { return log(g.r_max / g.r_min) / g.n_r; }
+// Log spacing of the band rule: du of a log grid; on a uniform radial grid
+// (SG_LINEAR_R) the smallest log spacing of adjacent centres (outer edge).
+inline double sg_ss_du(const sg_grid &g, uint32_t flags)
+{
+    if (!(flags & SG_LINEAR_R)) return log(g.r_max / g.r_min) / g.n_r;
+    if (g.n_r < 2) return 1.0;
+    const double dr = (g.r_max - g.r_min) / g.n_r;
+    return log((g.r_max - 0.5 * dr) / (g.r_max - 1.5 * dr));
+}
 
 // Tiled layout of the half-spectrum intermediates between the passes: tiles
 // of 4 columns x 4 rows (128 bytes), each column's 4 rows contiguous inside

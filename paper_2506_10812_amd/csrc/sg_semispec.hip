@@ -49,8 +49,8 @@
 
 // ------------------------------------------------------------ table: rows
 struct SsRowArgs {
-    int nr, nrt, nf, excl, ind, pot;
-    double lnrmin, du, dphi;
+    int nr, nrt, nf, excl, ind, pot, lin;
+    double lnrmin, du, dphi, rmin, dr;  // du: log grid; rmin, dr: uniform radial grid
 };
 
 template <int N> struct SsRowShape {
@@ -83,10 +83,10 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     const int a = (int)(rest % A.nf), b = (int)(rest / A.nf);
     const bool live = valid && i < A.nr;  // padding target column stays zero
     const int ic = i < A.nr ? i : A.nr - 1;
-    const double ri = exp(A.lnrmin + (ic + 0.5) * A.du);
-    const double rp = exp(A.lnrmin + (ip + 0.5) * A.du);
+    const double ri = A.lin ? A.rmin + (ic + 0.5) * A.dr : exp(A.lnrmin + (ic + 0.5) * A.du);
+    const double rp = A.lin ? A.rmin + (ip + 0.5) * A.dr : exp(A.lnrmin + (ip + 0.5) * A.du);
     const double ha = H[a * A.nr + ip] / rp, hb = H[b * A.nr + ic] / ri;
-    const double X = (double)(ic - ip) * A.du;
+    const double X = A.lin ? log(ri / rp) : (double)(ic - ip) * A.du;
     __syncthreads();
     // 1. samples q in [0, N/2], mirrored into the upper half
 #pragma unroll 1
@@ -117,7 +117,9 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
     __syncthreads();
     if (!valid) return;
-    const double scale = -A.du * A.dphi / N;
+    // the samples carry r'^2 (the log-grid measure per du dphi); the source
+    // cell's measure is r'^2 wgt dphi with wgt = du, or dr / r' on a uniform grid
+    const double scale = -(A.lin ? A.dr / rp : A.du) * A.dphi / N;
     double ind = 0.0;
     if (A.ind) {
         // r'^2 sqrt(2) K_a(d) n_phi / 2 (the convolution-form samples carry the
@@ -199,6 +201,71 @@ __global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, dou
     }
 }
 
+// Own-cell terms on a uniform radial grid, one item per (pair, ring): the
+// cell spans X = ln(r'/r) in [ln(1 - dr/(2r)), ln(1 + dr/(2r))], no longer
+// symmetric, so each side of X = 0 is integrated on its own (the integrand
+// is integrable: ~1/rho for the field, logarithmic for the potential) with
+// the Duffy triangles and geometric panels of the log-cell quadrature, and
+// doubled for phi < 0 (both kernels are even in phi).  Output: the table
+// sample I / (wgt dphi) (field, I = int K_r dX dphi) or -I / (wgt dphi)
+// (potential, I = int P dA'), wgt = dr / r.
+__global__ void __launch_bounds__(256)
+k_ss_self_lin(const double *H, int nf, int nr, double rmin, double dr, double dphi, int pot, double *out,
+              GLNodes gl)
+{
+    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double red[256];
+    sg_fill_weights<double>(wq);
+    __syncthreads();
+    const int item = blockIdx.x;
+    if (item >= nf * nf * nr) return;
+    const int pair = item / nr, ir = item % nr, fa = pair / nf, fb = pair % nf;
+    const double r = rmin + (ir + 0.5) * dr;
+    const double Ha = H[fa * nr + ir], Hb = H[fb * nr + ir];
+    const double ha = Ha / r, hb = Hb / r, Hab = sqrt(0.5 * (Ha * Ha + Hb * Hb));
+    const double b = 0.5 * dphi;
+    constexpr int NX = SG_PANELS * SG_GLX_N;
+    double acc = 0.0;
+    for (int sd = 0; sd < 2; ++sd) {
+        const double sgn = sd == 0 ? 1.0 : -1.0;
+        const double a = sd == 0 ? log1p(0.5 * dr / r) : -log1p(-0.5 * dr / r);
+        for (int idx = threadIdx.x; idx < NX * SG_GL_N; idx += blockDim.x) {
+            const int ix = idx / SG_GL_N, j = idx % SG_GL_N;
+            const int pnl = ix / SG_GLX_N, i = ix % SG_GLX_N;
+            const double hi = ldexp(1.0, -2 * (SG_PANELS - 1 - pnl));
+            const double lo = pnl == 0 ? 0.0 : 0.25 * hi;
+            const double xi = lo + (hi - lo) * gl.xr[i];
+            const double eta = gl.x[j];
+            const double wgt = (hi - lo) * gl.wr[i] * gl.w[j] * xi * a * b;
+            double f = 0.0;
+            for (int tri = 0; tri < 2; ++tri) {
+                const double X = sgn * (tri == 0 ? a * xi : a * xi * eta);
+                const double phi = tri == 0 ? b * xi * eta : b * xi;
+                if (pot) {
+                    const double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
+                    const double s2 = r * r * exp(X) * 4.0 * (sx * sx + sp * sp);
+                    f += -sg_G0_64(s2 / (8.0 * Hab * Hab), wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
+                } else {
+                    double kr, kp;
+                    sg_conv_kernel64(X, sin(0.5 * phi), sin(phi), ha, hb, 0, wq, kr, kp);
+                    f += kr;
+                }
+            }
+            acc += wgt * f;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double I = 2.0 * red[0], w = (dr / r) * dphi;
+        out[item] = pot ? -I / w : I / w;
+    }
+}
+
 __global__ void k_ss_scale(double *p, int n, double f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,8 +336,10 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
                             void *d_ws, hipStream_t s)
 {
     const int nr = grid->n_r, nphi = grid->n_phi;
-    const double du = sg_ss_du(*grid);
+    const double du = sg_ss_du(*grid, flags);  // band rule (and log-grid spacing)
     const bool full = (flags & SG_SS_FULL) != 0;
+    const bool lin = (flags & SG_LINEAR_R) != 0;
+    const double dr = (grid->r_max - grid->r_min) / nr;
     const SsLayout L = sg_ss_layout(nr, nphi, nf, du, full);
     const double dphi = 2.0 * SG_PI / nphi;
     char *tb = (char *)d_table;
@@ -294,7 +363,10 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
         // one item per (pair, ring): the per-cell quadratures with one cell per ring
         GLNodes gl;
         sg_gl_nodes(gl);
-        if (pot) {
+        if (lin) {
+            hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, grid->r_min, dr,
+                               dphi, pot ? 1 : 0, self, gl);
+        } else if (pot) {
             hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, (const double *)nullptr,
                                nf, nr, 1, log(grid->r_min), du, dphi, 0, self, gl);
             SG_HIP(hipGetLastError());
@@ -317,6 +389,9 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     A.lnrmin = log(grid->r_min);
     A.du = du;
     A.dphi = dphi;
+    A.lin = lin ? 1 : 0;
+    A.rmin = grid->r_min;
+    A.dr = dr;
     const size_t crows = ss_chunk_rows(L);
     for (size_t r0 = 0; r0 < L.rows; r0 += crows) {
         const int n = (int)std::min(crows, L.rows - r0);

@@ -27,7 +27,9 @@ H/r constant for the FFT method, Sect. 4 and Sect. 5.2):
                 times sqrt(1 - 0.95 exp(-((r - r_0)/w)^2)) when a temperature gap of
                 width w is asked for; optional dust with H_d = eta H_g and the
                 clumpy recipe of bifluid_fft.  Default 1200 x 2048 (App. D uses
-                1200 x 2800; the azimuthal transforms take powers of two).
+                1200 x 2800; the azimuthal transforms take powers of two).  With
+                linear_r the radial grid is uniform (centres r_min + (i + 1/2) dr), as in
+                the NIRVANA runs of the paper.
   exponential   the Sect. 4.3 validation disc: Sigma = Sigma_0 exp(-r/r_0), Sigma_0 = 200,
                 r_0 = 250, r in [0.01, 2500] (AU), axisymmetric; H/r^q = h with q = 1
                 (H = h r, the FFT path) or q = 0 (H = h constant, the semi-spectral
@@ -127,11 +129,13 @@ def sample_cells(n_r, n_phi, n, seed=7):
     return np.sort(rng.choice(N, size=min(n, N), replace=False)).astype(np.int64)
 
 
-def flaring(seed=8, n_r=1200, n_phi=2048, p=0.25, gap_w=None, n_fluids=1, eta=0.1):
+def flaring(seed=8, n_r=1200, n_phi=2048, p=0.25, gap_w=None, n_fluids=1, eta=0.1, linear_r=False):
     """Per-ring scale heights H [n_fluids][n_r] and Sigma [n_fluids][n_r][n_phi]."""
     rng = np.random.default_rng(seed)
     r_min, r_max, r0 = 20.0, 250.0, 100.0
     r, phi = centres(n_r, n_phi, r_min, r_max)
+    if linear_r:
+        r = r_min + (np.arange(n_r) + 0.5) * (r_max - r_min) / n_r
     R, P = np.meshgrid(r, phi, indexing="ij")
     gas = (R / r0) ** -1.5 * (1 + 0.1 * np.cos(2 * P - 4 * np.log(R)))
     gas = gas * (1 + 0.01 * rng.uniform(-1, 1, gas.shape))
@@ -144,7 +148,7 @@ def flaring(seed=8, n_r=1200, n_phi=2048, p=0.25, gap_w=None, n_fluids=1, eta=0.
         sig.append(_clumpy_dust(gas, rng))
         H.append(eta * h * r)
     return dict(name="flaring", n_r=n_r, n_phi=n_phi, r_min=r_min, r_max=r_max, p=p, gap_w=gap_w,
-                H=np.stack(H), sigma=np.stack(sig))
+                linear_r=linear_r, H=np.stack(H), sigma=np.stack(sig))
 
 
 def exponential(n_r=1024, n_phi=2048, h=0.001, q=1):
