@@ -152,9 +152,12 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * (r_i = r_min e^{(i + 1/2) du}), every value > 0 (not checked on the
  * device).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (the indirect term,
  * with K_a at d = r_i'/H_a(r_i'), folded into mode 1 of the table; no cost
- * at solve time), SG_SS_FULL, SG_POTENTIAL (below).  Grid: n_phi a power
- * of two in [4, 2048], n_r
- * in [1, 2048], any n_r.  Size: sg_ss_table_bytes() (at most
+ * at solve time), SG_SS_FULL, SG_POTENTIAL, SG_LINEAR_R (below).  Grid:
+ * n_phi a power of two in [4, 2048], n_r in [1, 2048], any n_r.  n_fluids:
+ * 1 to 4 scale-height groups (the multi-fluid case of Sect. 5.2; n_r <= 1024
+ * beyond two), d_H then [n_fluids][n_r], the operators covering all
+ * n_fluids^2 ordered pairs; a disc's fluids.n_fluids is that count (its h
+ * is not read).  Size: sg_ss_table_bytes() (at most
  * 8 (n_phi/2 + 1) F^2 n_r n_rt bytes, n_rt = n_r rounded up to even, plus a
  * few KB); d_table 256-byte aligned, written completely.
  * d_ws: sg_ss_table_workspace_bytes() bytes (<= about 130 MB), contents

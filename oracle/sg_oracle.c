@@ -502,7 +502,7 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
                                  const double *h, const double *H, const double *sigma,
                                  int64_t nt, const int64_t *targets, unsigned flags, double *pot)
 {
-    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     for (int64_t ti = 0; ti < nt; ++ti)
@@ -617,7 +617,7 @@ void sg_oracle_hsg(int64_t n, int nf, const double *H, const double *Q, double *
 int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const double *h,
                        const double *H, const double *sigma, unsigned flags, double *AB)
 {
-    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     for (int a = 0; a < nf; ++a) {
@@ -662,7 +662,7 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
                              int64_t nt, const int64_t *targets, unsigned flags,
                              double *gr, double *gphi)
 {
-    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     orc_gl_init();
     orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
@@ -789,7 +789,7 @@ int sg_oracle_field_table(int nr, int nphi, double rmin, double rmax, int nf, co
                           const double *sigma, int64_t nt, const int64_t *targets,
                           unsigned flags, int which, double *out)
 {
-    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     if (which < 0 || which > 2) return 1;
     orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
     const int64_t N = (int64_t)nr * nphi;
@@ -838,7 +838,7 @@ int sg_oracle_adjoint_sigma(int nr, int nphi, double rmin, double rmax, int nf, 
                             const double *lam, int64_t nk, const int64_t *kidx, unsigned flags,
                             double *dsigma)
 {
-    if (nr < 1 || nphi < 1 || nf < 1 || nf > 2 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
     const int64_t N = (int64_t)nr * nphi;
     const double scale = -g.du * g.dphi;

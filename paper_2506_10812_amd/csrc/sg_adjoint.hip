@@ -318,11 +318,22 @@ __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_out(AdjDev A)
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     const int j = valid ? idx : 0;
-    // one fluid: rows 2j, 2j + 1 (an odd last row pairs with itself)
-    const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : min(2 * j + 1, nr - 1);
-    const int f2 = NF == 2 ? 1 : 0;
-    phi_inv_pair<N>(A.dt, i1, A.dt + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, A.dsig + (size_t)i1 * N,
-                    A.dsig + f2 * plane + (size_t)i2 * N, t, pl, valid);
+    // jobs: fluid pairs (2p, 2p + 1) row by row, then for an odd fluid count
+    // the last fluid's rows 2j, 2j + 1 (an odd last row pairs with itself)
+    const int paired = (NF / 2) * nr;
+    int f1, f2, i1, i2;
+    if (j < paired) {
+        f1 = 2 * (j / nr);
+        f2 = f1 + 1;
+        i1 = i2 = j % nr;
+    } else {
+        const int q = j - paired;
+        f1 = f2 = NF - 1;
+        i1 = 2 * q;
+        i2 = min(2 * q + 1, nr - 1);
+    }
+    phi_inv_pair<N>(A.dt + f1 * fs, i1, A.dt + f2 * fs, i2, nr, TwTable{A.D.tw_phi},
+                    A.dsig + f1 * plane + (size_t)i1 * N, A.dsig + f2 * plane + (size_t)i2 * N, t, pl, valid);
 }
 
 __global__ void k_adj_dh_reduce(const double *part, int ncol, int nf, double *dh)
@@ -429,7 +440,7 @@ static sg_status adj_ss_launch(AdjDev A, int m0, int ncol, hipStream_t s)
                            ncol);
         SG_HIP(hipGetLastError());
     }
-    const int pairs = NF == 2 ? nr : (nr + 1) / 2;
+    const int pairs = (NF / 2) * nr + (NF % 2 ? (nr + 1) / 2 : 0);
     A.count = pairs;
     hipLaunchKernelGGL((k_adj_out<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)), dim3(AdjShape<NPHI>::WGS), 0, s, A);
     SG_HIP(hipGetLastError());
@@ -496,8 +507,13 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
         // full modes first (the band shrinks with m), then the banded ones
         int m0 = 0;
         while (m0 < L.ncol && !sg_ss_is_banded(sg_ss_band(m0, nr, L.du, full), nr)) ++m0;
-        if (nf == 1) return adj_ss_phi<1>(nphi, A, m0, L.ncol, s);
-        return adj_ss_phi<2>(nphi, A, m0, L.ncol, s);
+        switch (nf) {
+        case 1: return adj_ss_phi<1>(nphi, A, m0, L.ncol, s);
+        case 2: return adj_ss_phi<2>(nphi, A, m0, L.ncol, s);
+        case 3: return adj_ss_phi<3>(nphi, A, m0, L.ncol, s);
+        case 4: return adj_ss_phi<4>(nphi, A, m0, L.ncol, s);
+        }
+        return SG_ERR_UNSUPPORTED;
     }
     const TableLayout L = sg_table_layout(nr, nphi, nf, d.flags);
     const char *tb = (const char *)d.table;

@@ -51,6 +51,13 @@ static sg_status check_ss_grid(const sg_grid *g)
     return SG_OK;
 }
 
+// Semi-spectral fluid (scale-height group) count: 1..4, and n_r <= 1024
+// beyond two groups (the middle pass stages every group's column in LDS).
+static bool ss_fluids_ok(const sg_grid *g, int nf)
+{
+    return nf >= 1 && nf <= 4 && (nf <= 2 || g->n_r <= 1024);
+}
+
 static bool ss_flags_ok(uint32_t flags)
 {
     if ((flags & SG_POTENTIAL) && (flags & SG_INDIRECT)) return false;
@@ -87,13 +94,13 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
 
 size_t sg_ss_table_bytes(const sg_grid *grid, int n_fluids, uint32_t flags)
 {
-    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2 || !ss_flags_ok(flags)) return 0;
+    if (check_ss_grid(grid) != SG_OK || !ss_fluids_ok(grid, n_fluids) || !ss_flags_ok(flags)) return 0;
     return sg_ss_layout(grid->n_r, grid->n_phi, n_fluids, sg_ss_du(*grid, flags), (flags & SG_SS_FULL) != 0).total;
 }
 
 size_t sg_ss_table_workspace_bytes(const sg_grid *grid, int n_fluids)
 {
-    if (check_ss_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    if (check_ss_grid(grid) != SG_OK || !ss_fluids_ok(grid, n_fluids)) return 0;
     return sg_ss_ws_bytes(grid->n_r, grid->n_phi, n_fluids);
 }
 
@@ -102,7 +109,8 @@ sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint
 {
     sg_status s = check_ss_grid(grid);
     if (s != SG_OK) return s;
-    if (n_fluids < 1 || n_fluids > 2 || !d_H) return SG_ERR_ARG;
+    if (n_fluids < 1 || n_fluids > 4 || !d_H) return SG_ERR_ARG;
+    if (!ss_fluids_ok(grid, n_fluids)) return SG_ERR_UNSUPPORTED;
     if (!ss_flags_ok(flags)) return SG_ERR_ARG;
     if (!d_table || ((uintptr_t)d_table & 255)) return SG_ERR_ARG;
     if (!d_ws || ws_bytes < sg_ss_ws_bytes(grid->n_r, grid->n_phi, n_fluids) || ((uintptr_t)d_ws & 255))
@@ -126,7 +134,8 @@ static sg_status check_disc(const sg_disc &d)
     if (d.flags & SG_SEMI_SPECTRAL) {
         sg_status s = check_ss_grid(&d.grid);
         if (s != SG_OK) return s;
-        if (d.fluids.n_fluids < 1 || d.fluids.n_fluids > 2) return SG_ERR_ARG;
+        if (d.fluids.n_fluids < 1 || d.fluids.n_fluids > 4) return SG_ERR_ARG;
+        if (!ss_fluids_ok(&d.grid, d.fluids.n_fluids)) return SG_ERR_UNSUPPORTED;
         if (!ss_flags_ok(d.flags)) return SG_ERR_ARG;
         if (!d.sigma || !d.g_r || !d.g_phi || !d.table) return SG_ERR_ARG;
         if ((uintptr_t)d.table & 255) return SG_ERR_ARG;

@@ -641,7 +641,7 @@ static void fill_discs(const sg_disc *discs, int n, char *ws, Plan &P)
         D.nf = d.fluids.n_fluids;
         D.flags = d.flags;
         D.ns = d.n_species;
-        D.gcount[0] = D.gcount[1] = 0;
+        D.gcount[0] = D.gcount[1] = D.gcount[2] = D.gcount[3] = 0;
         for (int s = 0; s < d.n_species; ++s) {
             const int gp = d.species_group[s];
             D.gsp[gp][D.gcount[gp]++] = (uint8_t)s;
@@ -1101,7 +1101,7 @@ static void load_tune_file()
     int pass, len, nf, sf, gm, K;
     unsigned long long h;
     while (fscanf(f, "%d %d %d %llx %d %d %d", &pass, &len, &nf, &h, &sf, &gm, &K) == 7)
-        if (pass >= 1 && pass <= 3 && (nf == 1 || nf == 2) && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 4 &&
+        if (pass >= 1 && pass <= 3 && nf >= 1 && nf <= 4 && sf >= 0 && sf <= 1 && gm >= 1 && gm <= 4 &&
             (K == 0 || K == 1 || K == 2 || K == 4 || K == 8))
             g_tuned[TuneKey{pass, len, nf, (uint64_t)h}] = Variant{sf, gm, K};
     fclose(f);

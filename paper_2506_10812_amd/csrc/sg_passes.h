@@ -31,8 +31,8 @@ struct DiscDev {
     const SsMode *modes;    // semi-spectral table: mode descriptors
     int ss_wmax;            // widest band of the grid's banded modes (-1: none)
     int ns;                 // species summed into groups (0: one density per fluid)
-    int gcount[2];          // species of each group
-    uint8_t gsp[2][8];      // their indices
+    int gcount[4];          // species of each group
+    uint8_t gsp[4][8];      // their indices
 };
 
 // A job is (disc index, job index inside the disc); disc < 0 marks padding.

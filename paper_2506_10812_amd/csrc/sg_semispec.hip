@@ -572,14 +572,24 @@ template <int NF, int V, int S, bool NT = false> static SsPassInfo ss_info()
     return k;
 }
 
+template <int NF> static bool ss_variant(int variant, SsPassInfo &out)
+{
+    switch (variant) {
+    case 1: out = ss_info<NF, 2, 4, true>(); return true;
+    case 2: out = ss_info<NF, 2, 1>(); return true;
+    case 3: out = ss_info<NF, 4, 1>(); return true;
+    case 4: out = ss_info<NF, 2, 4>(); return true;
+    default: return false;
+    }
+}
+
 bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out)
 {
-    if (nf != 1 && nf != 2) return false;
-    switch (variant) {
-    case 1: out = nf == 1 ? ss_info<1, 2, 4, true>() : ss_info<2, 2, 4, true>(); return true;
-    case 2: out = nf == 1 ? ss_info<1, 2, 1>() : ss_info<2, 2, 1>(); return true;
-    case 3: out = nf == 1 ? ss_info<1, 4, 1>() : ss_info<2, 4, 1>(); return true;
-    case 4: out = nf == 1 ? ss_info<1, 2, 4>() : ss_info<2, 2, 4>(); return true;
+    switch (nf) {
+    case 1: return ss_variant<1>(variant, out);
+    case 2: return ss_variant<2>(variant, out);
+    case 3: return ss_variant<3>(variant, out);
+    case 4: return ss_variant<4>(variant, out);
     default: return false;
     }
 }

@@ -5,7 +5,9 @@ from __future__ import annotations
 
 import torch
 
-from . import (F32, F64, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, field_adjoint,
+import ctypes
+
+from . import (F32, F64, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, Fluids, field_adjoint,
                field_adjoint_workspace_bytes, field_fft_tune, potential_direct,
                potential_direct_workspace_bytes, field_direct, field_direct_workspace_bytes, field_fft,
                field_fft_workspace_bytes, fluids, grid, kernel_table, kernel_table_bytes,
@@ -96,8 +98,10 @@ class SemiSpectral:
         self.sigma = torch.zeros((ns, n_r, n_phi), dtype=torch.float32, device=dev)
         self.g_r = torch.empty(shape, dtype=torch.float32, device=dev)
         self.g_phi = torch.empty(shape, dtype=torch.float32, device=dev)
-        self.disc = make_disc(self.g, fluids([1.0] * self.nf), self.flags | SEMI_SPECTRAL, self.sigma,
-                              self.g_r, self.g_phi, self.table, species_group)
+        # the fluid count only (up to four groups here; h is not read)
+        fl = Fluids(self.nf, 0, (ctypes.c_double * 2)(0.0, 0.0))
+        self.disc = make_disc(self.g, fl, self.flags | SEMI_SPECTRAL, self.sigma, self.g_r, self.g_phi,
+                              self.table, species_group)
         self.ws = torch.empty(max(1, field_fft_workspace_bytes([self.disc])), dtype=torch.uint8,
                               device=dev)
 

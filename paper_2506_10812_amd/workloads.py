@@ -26,7 +26,8 @@ H/r constant for the FFT method, Sect. 4 and Sect. 5.2):
                 (1 + 0.01 U(-1,1)); gas H_g/r = 0.05 (r/r_0)^p (power-law flaring)
                 times sqrt(1 - 0.95 exp(-((r - r_0)/w)^2)) when a temperature gap of
                 width w is asked for; optional dust with H_d = eta H_g and the
-                clumpy recipe of bifluid_fft.  Default 1200 x 2048 (App. D uses
+                clumpy recipe of bifluid_fft (up to three dust groups, eta, 3 eta
+                and eta/3, each with its own seeded clumps).  Default 1200 x 2048 (App. D uses
                 1200 x 2800; the azimuthal transforms take powers of two).  With
                 linear_r the radial grid is uniform (centres r_min + (i + 1/2) dr), as in
                 the NIRVANA runs of the paper.
@@ -144,9 +145,9 @@ def flaring(seed=8, n_r=1200, n_phi=2048, p=0.25, gap_w=None, n_fluids=1, eta=0.
         h = h * np.sqrt(1 - 0.95 * np.exp(-((r - r0) / gap_w) ** 2))
     H = [h * r]
     sig = [gas]
-    if n_fluids == 2:
+    for f in range(1, n_fluids):  # dust groups: eta, 3 eta, eta / 3
         sig.append(_clumpy_dust(gas, rng))
-        H.append(eta * h * r)
+        H.append(eta * (1.0, 3.0, 1.0 / 3.0)[f - 1] * h * r)
     return dict(name="flaring", n_r=n_r, n_phi=n_phi, r_min=r_min, r_max=r_max, p=p, gap_w=gap_w,
                 linear_r=linear_r, H=np.stack(H), sigma=np.stack(sig))
 

@@ -146,7 +146,11 @@ def test_semispectral_sizes_and_validation(sg):
     call = lambda nf, H, flags, tab, ws, n: L.sg_ss_table(ctypes.byref(g), nf, H, flags, tab, ws, n, None)
     assert call(2, 256, 0, 512, 1024, need - 1) == sg.ERR_WORKSPACE
     assert call(2, None, 0, 512, 1024, need) == sg.ERR_ARG
-    assert call(3, 256, 0, 512, 1024, need) == sg.ERR_ARG
+    assert call(5, 256, 0, 512, 1024, need) == sg.ERR_ARG
+    # up to four scale-height groups on this path (n_r <= 1024 beyond two)
+    assert sg.ss_table_bytes(g, 4) > 2 * sg.ss_table_bytes(g, 2)
+    assert sg.ss_table_bytes(sg.grid(1025, 64, 20.0, 250.0), 3) == 0
+    assert sg.ss_table_bytes(sg.grid(1025, 64, 20.0, 250.0), 2) > 0
     assert call(2, 256, sg.WITH_DH, 512, 1024, need) == sg.ERR_ARG
     assert call(2, 256, sg.POTENTIAL | sg.INDIRECT, 512, 1024, need) == sg.ERR_ARG
     assert call(2, 256, 0, 520, 1024, need) == sg.ERR_ARG  # table alignment

@@ -317,3 +317,62 @@ def test_semispectral_uniform_grid_banded(sg, T, W):
     rhs = float((ds.double() * Sb.sigma.double()).sum())
     scale = float((lam_r.double().abs() * Sb.g_r.double().abs()).sum())
     assert abs(lhs - rhs) < 1e-5 * scale
+
+
+# ------------------------------------------------- more scale-height groups
+@pytest.mark.parametrize("nr,nphi,nf,lin", [(24, 16, 3, False), (17, 32, 4, False), (20, 16, 3, True)])
+def test_semispectral_three_and_four_groups(sg, T, W, nr, nphi, nf, lin):
+    """Gas plus two or three dust groups of different scale heights (all
+    n_fluids^2 ordered pairs), against the pairwise oracle; the adjoint's
+    transpose identity with the odd-count output pairing."""
+    say(f"semi-spectral {nf} groups {nr}x{nphi} uniform={lin}")
+    w = W.flaring(seed=nr * nf, n_r=nr, n_phi=nphi, p=0.25, n_fluids=nf, linear_r=lin)
+    S, gr, gp = run_ss(T, w, flags=sg.LINEAR_R if lin else 0)
+    rr, rp = (oracle_field_lin if lin else oracle_field)(w)
+    check(gr, gp, rr, rp, nf)
+    g = torch.Generator(device="cpu").manual_seed(nf)
+    lam_r = torch.randn(S.g_r.shape, generator=g).cuda()
+    lam_p = torch.randn(S.g_r.shape, generator=g).cuda()
+    ds = torch.empty_like(S.sigma)
+    ws = torch.empty(sg.field_adjoint_workspace_bytes(S.disc), dtype=torch.uint8, device="cuda")
+    sg.field_adjoint(S.disc, lam_r, lam_p, ds, None, ws)
+    torch.cuda.synchronize()
+    lhs = float((lam_r.double() * S.g_r.double()).sum() + (lam_p.double() * S.g_phi.double()).sum())
+    rhs = float((ds.double() * S.sigma.double()).sum())
+    scale = float((lam_r.double().abs() * S.g_r.double().abs()).sum())
+    say(f"  adjoint transpose identity diff/scale {abs(lhs - rhs) / scale:.1e}")
+    assert abs(lhs - rhs) < 1e-5 * scale
+
+
+def test_semispectral_four_groups_potential_and_species(sg, T, W):
+    say("semi-spectral 4 groups: potential; species summed into 4 groups")
+    w = W.flaring(seed=2, n_r=16, n_phi=16, p=0.25, n_fluids=4)
+    nf, nr, nphi = w["sigma"].shape
+    Hc = np.repeat(w["H"][:, :, None], nphi, axis=2)
+    _, pot, _ = run_ss(T, w, flags=sg.POTENTIAL)
+    ref = O.potential_pairwise(nr, nphi, w["r_min"], w["r_max"], [0.0] * nf,
+                               w["sigma"].astype(np.float32).astype(np.float64), H=Hc)
+    for f in range(nf):
+        assert rel_rms(pot.reshape(nf, -1)[f], ref[f]) < 1e-5
+    groups = (0, 3, 1, 2, 3, 1)
+    rng = np.random.default_rng(4)
+    sp = np.zeros((len(groups), nr, nphi), dtype=np.float32)
+    for gi in range(nf):
+        members = [s for s, g in enumerate(groups) if g == gi]
+        wts = rng.uniform(0.2, 1.0, (len(members), nr, nphi))
+        wts /= wts.sum(axis=0)
+        for k, s in enumerate(members):
+            sp[s] = (w["sigma"][gi] * wts[k]).astype(np.float32)
+    sums = np.zeros((nf, nr, nphi), dtype=np.float32)
+    for s, g in enumerate(groups):
+        sums[g] = sums[g] + sp[s]
+    A = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], nf, species_group=groups)
+    A.refresh(w["H"])
+    A.sigma.copy_(torch.tensor(sp))
+    A.run()
+    B = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], nf)
+    B.refresh(w["H"])
+    B.sigma.copy_(torch.tensor(sums))
+    B.run()
+    torch.cuda.synchronize()
+    assert torch.equal(A.g_r, B.g_r) and torch.equal(A.g_phi, B.g_phi)
