@@ -370,8 +370,8 @@ k_pass3(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
         const size_t o = (size_t)b * nr * N + (size_t)i * N;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            gst1(D->gr + o, t + T * p, z[p].x);
-            gst1(D->gp + o, t + T * p, z[p].y);
+            gst1nt(D->gr + o, t + T * p, z[p].x);  // outputs: streamed past the caches
+            gst1nt(D->gp + o, t + T * p, z[p].y);
         }
     }
 }

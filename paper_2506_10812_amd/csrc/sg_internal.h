@@ -96,6 +96,12 @@ __device__ inline void gst2(float2 *p, uint32_t i, float2 v)
     *(sg_gv2f *)((char *)p + (i << 3)) = w;
 }
 __device__ inline float gld1(const float *p, uint32_t i) { return *(sg_gcf *)((const char *)p + (i << 2)); }
+// Non-temporal store: for outputs written once and not read back by the
+// library (they need not displace the intermediates in the caches).
+__device__ inline void gst1nt(float *p, uint32_t i, float v)
+{
+    __builtin_nontemporal_store(v, (sg_gf *)((char *)p + (i << 2)));
+}
 __device__ inline void gst1(float *p, uint32_t i, float v) { *(sg_gf *)((char *)p + (i << 2)) = v; }
 
 // 16-byte access of two consecutive complex values (16-byte aligned).

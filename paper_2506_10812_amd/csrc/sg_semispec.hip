@@ -442,12 +442,12 @@ __device__ inline void ss_ld4(const float2 *p, uint32_t i, float2 &x, float2 &y)
 // that target i0 + v reads source i0 + v + d - w at window index V l + v + d.  The operator rows
 // are streamed once with 16-byte loads, U rows in flight: this pass is bound
 // by reading the table.
-template <int NF, int V, int S, bool NT>
+template <int NF, int V, int S, bool NT, int U>
 __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJob *wj, int nj, const float2 *,
                                                  int kc)
 {
     extern __shared__ __attribute__((aligned(16))) float2 ssh[];
-    constexpr int LN = 256 / S, TB = LN * V, U = 8;
+    constexpr int LN = 256 / S, TB = LN * V;
     static_assert(V % 2 == 0, "targets per lane come in 16-byte pairs");
     const int w = sg_uniform(sg_xcd_remap(blockIdx.x, kc));
     if (w >= nj) return;
@@ -559,11 +559,11 @@ __global__ void __launch_bounds__(256) k_ss_pass(const DiscDev *discs, const WJo
     }
 }
 
-template <int NF, int V, int S, bool NT = false> static SsPassInfo ss_info()
+template <int NF, int V, int S, bool NT = false, int U = 8> static SsPassInfo ss_info()
 {
     constexpr int LN = 256 / S;
     SsPassInfo k;
-    k.fn = k_ss_pass<NF, V, S, NT>;
+    k.fn = k_ss_pass<NF, V, S, NT, U>;
     k.wgs = 256;
     k.tb = LN * V;
     k.lds_per_row = NF * (int)sizeof(float2);
