@@ -378,6 +378,29 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
                            void *stream);
 
 /* ---------------------------------------------------------------------
+ * sg_ss_grad_H: derivative of L with respect to the ring scale heights of
+ * a semi-spectral disc (Sect. 5.2 operators with h_a = H_a(r_i')/r_i' at
+ * the source ring and h_b = H_b(r_i)/r_i at the target ring), for
+ * dL/dg_r = lam_r, dL/dg_phi = lam_phi (float device [F][n_r][n_phi]):
+ *   d_dH[f][i] = dL/dH_f(r_i)   (double, device, [F][n_r]).
+ * Every operator entry is differentiated through both of its scale heights
+ * (the kernels' h derivatives, the own-cell integral's derivatives, and the
+ * folded indirect term through H_a at the source ring) and contracted with
+ * the phi spectra of lam and Sigma, mode by mode, in double; the derivative
+ * operators are sampled and transformed on the fly and never stored, so a
+ * call costs about twice a table build.  d_H: the H the disc's table was
+ * built from.  disc->table supplies the phi twiddles only.  Discs without
+ * SG_SEMI_SPECTRAL, with SG_POTENTIAL or with n_species > 0 return
+ * SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
+ * 256-byte aligned.  Asynchronous; the result is summed with device
+ * atomics, so its last bits vary from call to call.
+ * --------------------------------------------------------------------- */
+size_t sg_ss_grad_H_workspace_bytes(const sg_disc *disc);
+sg_status sg_ss_grad_H(const sg_disc *disc, const double *d_H, const float *d_lam_r,
+                       const float *d_lam_phi, double *d_dH, void *d_ws, size_t ws_bytes,
+                       void *stream);
+
+/* ---------------------------------------------------------------------
  * Device-side evaluation of F(x) = e^x [K1(x) - K0(x)] (the function of
  * App. A at argument x) for testing: d_x, d_F device arrays of n values in
  * `dtype`.  F'(x) too when d_dF is not NULL.

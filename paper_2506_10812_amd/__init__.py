@@ -89,6 +89,8 @@ def _load():
         "sg_field_direct": (i32, [GP, i32, dp, vp, vp, vp, vp, i32, u32, vp, sz, vp]),
         "sg_field_adjoint_workspace_bytes": (sz, [DP]),
         "sg_field_adjoint": (i32, [DP, vp, vp, vp, vp, vp, sz, vp]),
+        "sg_ss_grad_H_workspace_bytes": (sz, [DP]),
+        "sg_ss_grad_H": (i32, [DP, vp, vp, vp, vp, vp, sz, vp]),
         "sg_eval_F": (i32, [vp, vp, vp, i64, i32, vp]),
         "sg_eval_G0": (i32, [vp, vp, i64, i32, vp]),
         "sg_hsg": (i32, [i64, i32, vp, vp, vp, vp]),
@@ -113,7 +115,8 @@ EXPORTED = (
     "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile", "sg_field_fft_tune",
     "sg_field_direct_workspace_bytes",
     "sg_field_direct", "sg_potential_direct_workspace_bytes", "sg_potential_direct",
-    "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_eval_F", "sg_eval_G0", "sg_hsg",
+    "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_ss_grad_H_workspace_bytes",
+    "sg_ss_grad_H", "sg_eval_F", "sg_eval_G0", "sg_hsg",
     "sg_self_cell", "sg_release", "sg_status_string", "sg_version")
 
 
@@ -185,6 +188,10 @@ def field_direct_workspace_bytes(g: Grid, n_fluids: int, dtype: int, per_cell_H:
 
 def field_adjoint_workspace_bytes(disc: Disc) -> int:
     return int(_lib.sg_field_adjoint_workspace_bytes(ctypes.byref(disc)))
+
+
+def ss_grad_H_workspace_bytes(disc: Disc) -> int:
+    return int(_lib.sg_ss_grad_H_workspace_bytes(ctypes.byref(disc)))
 
 
 # ------------------------------------------------------------------ calls
@@ -280,6 +287,13 @@ def field_adjoint(disc: Disc, lam_r, lam_phi, dsigma, dh, ws, ws_bytes=None, str
     _check(_lib.sg_field_adjoint(ctypes.byref(disc), _ptr(lam_r), _ptr(lam_phi), _ptr(dsigma),
                                  _ptr(dh), _ptr(ws), ws_bytes, _stream(stream)),
            "sg_field_adjoint")
+
+
+def ss_grad_H(disc: Disc, H, lam_r, lam_phi, dH, ws, ws_bytes=None, stream=None):
+    ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.sg_ss_grad_H(ctypes.byref(disc), _ptr(H), _ptr(lam_r), _ptr(lam_phi), _ptr(dH),
+                             _ptr(ws), ws_bytes, _stream(stream)),
+           "sg_ss_grad_H")
 
 
 def eval_F(x, F, dF=None, dtype=F64, stream=None):

@@ -305,6 +305,31 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     return sg_adjoint_run(*disc, d_lam_r, d_lam_phi, d_dsigma, d_dh, d_ws, (hipStream_t)stream);
 }
 
+static bool ss_grad_ok(const sg_disc *d)
+{
+    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL) && !(d->flags & SG_POTENTIAL) &&
+           d->n_species == 0;
+}
+
+size_t sg_ss_grad_H_workspace_bytes(const sg_disc *disc)
+{
+    if (!ss_grad_ok(disc)) return 0;
+    return sg_ss_grad_ws_bytes(disc->grid.n_r, disc->grid.n_phi, disc->fluids.n_fluids);
+}
+
+sg_status sg_ss_grad_H(const sg_disc *disc, const double *d_H, const float *d_lam_r, const float *d_lam_phi,
+                       double *d_dH, void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!disc) return SG_ERR_ARG;
+    sg_status s = check_disc(*disc);
+    if (s != SG_OK) return s;
+    if (!d_H || !d_lam_r || !d_lam_phi || !d_dH) return SG_ERR_ARG;
+    if (!ss_grad_ok(disc)) return SG_ERR_UNSUPPORTED;
+    const size_t need = sg_ss_grad_ws_bytes(disc->grid.n_r, disc->grid.n_phi, disc->fluids.n_fluids);
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
+    return sg_ss_grad_run(*disc, d_H, d_lam_r, d_lam_phi, d_dH, d_ws, (hipStream_t)stream);
+}
+
 sg_status sg_eval_F(const void *d_x, void *d_F, void *d_dF, int64_t n, sg_dtype dtype, void *stream)
 {
     if (!d_x || !d_F || n < 0 || (dtype != SG_F32 && dtype != SG_F64)) return SG_ERR_ARG;

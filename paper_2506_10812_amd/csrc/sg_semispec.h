@@ -19,5 +19,8 @@ int sg_ss_default_variant(int nr);
 int sg_ss_max_nr();
 
 size_t sg_ss_ws_bytes(int nr, int nphi, int nf);
+size_t sg_ss_grad_ws_bytes(int nr, int nphi, int nf);
+sg_status sg_ss_grad_run(const sg_disc &d, const double *d_H, const float *lam_r, const float *lam_p, double *dH,
+                         void *d_ws, hipStream_t s);
 sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint32_t flags, void *d_table,
                             void *d_ws, hipStream_t s);

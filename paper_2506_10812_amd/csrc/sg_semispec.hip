@@ -208,10 +208,11 @@ __global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, dou
 // the Duffy triangles and geometric panels of the log-cell quadrature, and
 // doubled for phi < 0 (both kernels are even in phi).  Output: the table
 // sample I / (wgt dphi) (field, I = int K_r dX dphi) or -I / (wgt dphi)
-// (potential, I = int P dA'), wgt = dr / r.
+// (potential, I = int P dA'), wgt = dr / r; which = 1, 2: the field's
+// derivatives with respect to h_a, h_b instead.
 __global__ void __launch_bounds__(256)
-k_ss_self_lin(const double *H, int nf, int nr, double rmin, double dr, double dphi, int pot, double *out,
-              GLNodes gl)
+k_ss_self_lin(const double *H, int nf, int nr, double rmin, double dr, double dphi, int pot, int which,
+              double *out, GLNodes gl)
 {
     __shared__ double wq[FQuad<double>::NODES];
     __shared__ double red[256];
@@ -247,7 +248,7 @@ k_ss_self_lin(const double *H, int nf, int nr, double rmin, double dr, double dp
                     f += -sg_G0_64(s2 / (8.0 * Hab * Hab), wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
                 } else {
                     double kr, kp;
-                    sg_conv_kernel64(X, sin(0.5 * phi), sin(phi), ha, hb, 0, wq, kr, kp);
+                    sg_conv_kernel64(X, sin(0.5 * phi), sin(phi), ha, hb, which, wq, kr, kp);
                     f += kr;
                 }
             }
@@ -365,7 +366,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
         sg_gl_nodes(gl);
         if (lin) {
             hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, grid->r_min, dr,
-                               dphi, pot ? 1 : 0, self, gl);
+                               dphi, pot ? 1 : 0, 0, self, gl);
         } else if (pot) {
             hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, (const double *)nullptr,
                                nf, nr, 1, log(grid->r_min), du, dphi, 0, self, gl);
@@ -599,3 +600,269 @@ bool sg_ss_pass_kernel(int nf, int variant, SsPassInfo &out)
 // per mode, short banded windows, Sigma~ and g^ kept in the caches); the
 // autotuner tries the other shapes.
 int sg_ss_default_variant(int) { return 1; }
+
+// ------------------------------------------------ dL/dH (gradient in H(r))
+// For L with dL/dg_r = lam_r, dL/dg_phi = lam_phi, the derivative with
+// respect to the ring scale heights follows from differentiating every
+// operator entry: T^{ab}(m, i, i') depends on h_a = H_a(r_i')/r_i' (source)
+// and h_b = H_b(r_i)/r_i (target), the own-cell entry on both at its ring,
+// and mode 1 on H_a(r_i') through the folded indirect term.  Since g is the
+// inverse transform of the per-mode products,
+//   dL/dtheta = sum_m w_m Re[conj(lam~_r) dT_r Sigma~ + conj(lam~_phi) i dt_phi Sigma~]
+// (w_m = 1 for m = 0, n_phi/2 and 2 otherwise: the stored half of a
+// Hermitian spectrum), accumulated per (b, a, i', i) row and added to
+// dL/dh_a(i') and dL/dh_b(i) in double; finally dL/dH = (dL/dh) / r.  The
+// derivative rows are sampled and transformed on the fly (the table's own
+// construction with the kernels' h derivatives), never stored.
+
+// Half spectra of lam rows (b, i) (r and phi parts) and of Sigma row pairs.
+template <int N>
+__global__ void __launch_bounds__(SsRowShape<N>::WGS)
+k_ssg_phi(const float *lam_r, const float *lam_p, const float *sigma, const float2 *tw, float2 *lt, float2 *st,
+          int nr, int nf)
+{
+    using S = SsRowShape<N>;
+    constexpr int T = S::T, G = S::G, W = LdsPlane<float>::elems(N);
+    __shared__ __attribute__((aligned(16))) float2 lds[W * G];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int hp = (nr + 1) / 2, nl = nf * nr, count = nl + nf * hp;
+    const int idx = blockIdx.x * G + g;
+    const bool valid = idx < count;
+    const int j = valid ? idx : 0;
+    const size_t fs = sg_blk_field_elems(N, nr);
+    const LdsPlane<float> pl{lds + W * g};
+    const float *x1, *x2;
+    float2 *d1, *d2;
+    int i1, i2;
+    if (j < nl) {
+        const int b = j / nr, i = j % nr;
+        x1 = lam_r + ((size_t)b * nr + i) * N;
+        x2 = lam_p + ((size_t)b * nr + i) * N;
+        d1 = lt + (size_t)(2 * b) * fs;
+        d2 = d1 + fs;
+        i1 = i2 = i;
+    } else {
+        const int q = j - nl, a = q / hp, jj = q % hp;
+        i1 = 2 * jj;
+        i2 = min(2 * jj + 1, nr - 1);
+        x1 = sigma + ((size_t)a * nr + i1) * N;
+        x2 = sigma + ((size_t)a * nr + i2) * N;
+        d1 = d2 = st + (size_t)a * fs;
+    }
+    phi_fwd_pair<N>(x1, x2, d1, i1, d2, i2, nr, TwTable{tw}, t, pl, valid);
+}
+
+// One group of T threads per (b, a, i', i) row: for which = 1 (d/dh_a,
+// source) and 2 (d/dh_b, target) the derivative samples are transformed as
+// in k_ss_rows and contracted with lam~ and Sigma~ of the row's mode column.
+template <int N>
+__global__ void __launch_bounds__(SsRowShape<N>::WGS)
+k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, const float2 *st, size_t r0,
+           int nrows, double *dldh)
+{
+    using S = SsRowShape<N>;
+    constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
+    constexpr int NC = N / 2 + 1;
+    __shared__ __attribute__((aligned(16))) double2 lds[W * G];
+    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double red[S::WGS];
+    sg_fill_weights<double>(wq);
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const LdsPlane<double> pl{lds + W * g};
+    const int row = blockIdx.x * G + g;
+    const bool valid = row < nrows;
+    const size_t R = r0 + (size_t)(valid ? row : 0);
+    const int i = (int)(R % A.nrt);
+    size_t rest = R / A.nrt;
+    const int ip = (int)(rest % A.nr);
+    rest /= A.nr;
+    const int a = (int)(rest % A.nf), b = (int)(rest / A.nf);
+    const bool live = valid && i < A.nr;
+    const int ic = i < A.nr ? i : A.nr - 1;
+    const double ri = A.lin ? A.rmin + (ic + 0.5) * A.dr : exp(A.lnrmin + (ic + 0.5) * A.du);
+    const double rp = A.lin ? A.rmin + (ip + 0.5) * A.dr : exp(A.lnrmin + (ip + 0.5) * A.du);
+    const double ha = H[a * A.nr + ip] / rp, hb = H[b * A.nr + ic] / ri;
+    const double X = A.lin ? log(ri / rp) : (double)(ic - ip) * A.du;
+    const double scale = -(A.lin ? A.dr / rp : A.du) * A.dphi / N;
+    const uint32_t fs = (uint32_t)sg_blk_field_elems(N, A.nr);
+    __syncthreads();
+    double part[2] = {0.0, 0.0};
+    for (int which = 1; which <= 2; ++which) {
+#pragma unroll 1
+        for (int q = t; q <= N / 2; q += T) {
+            double kr = 0.0, kp = 0.0;
+            if (ic == ip && q == 0) {
+                kr = A.excl ? 0.0 : dself[(size_t)(which - 1) * A.nf * A.nf * A.nr + (size_t)(a * A.nf + b) * A.nr + ic];
+            } else {
+                sg_conv_kernel64(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, which, wq, kr, kp);
+            }
+            pl.st(q, make_double2(kr, kp));
+            if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
+        }
+        __syncthreads();
+        double2 z[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
+        __syncthreads();
+        fft<N, false>(z, t, pl, TwExact64<N>{});
+#pragma unroll
+        for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
+        __syncthreads();
+        double dind = 0.0;
+        if (A.ind && which == 1) {
+            // d/dh_a of r'^2 sqrt(2) K_a(r'/H_a) n_phi / 2, H_a = h_a r':
+            // dK_a/dH = pi^{-1/2} r' / (4 H^4) (-3 F(x) - 2 x F'(x)), x = r'^2 / (4 H^2)
+            const double Ha = ha * rp, x = rp * rp / (4.0 * Ha * Ha);
+            double F, dF;
+            sg_F64_dF(x, wq, F, dF);
+            const double dK = (1.0 / SG_SQRT_PI) * rp / (4.0 * Ha * Ha * Ha * Ha) * (-3.0 * F - 2.0 * x * dF);
+            dind = rp * rp * SG_SQRT2 * dK * rp * (0.5 * N);
+        }
+        double acc = 0.0;
+        if (live) {
+            for (int m = t; m < NC; m += T) {
+                const double zm = pl.ld(m).x, zn = pl.ld((N - m) & (N - 1)).x;
+                double tr = 0.5 * (zm + zn), tp = 0.5 * (zn - zm);
+                if (m == 1) {
+                    tr += dind;
+                    tp += dind;
+                }
+                tr *= scale;
+                tp *= scale;
+                const uint32_t oi = (uint32_t)sg_blk_index(m, ic, A.nr), op = (uint32_t)sg_blk_index(m, ip, A.nr);
+                const float2 lr = gld2(lt, (uint32_t)(2 * b) * fs + oi), lp = gld2(lt, (uint32_t)(2 * b + 1) * fs + oi);
+                const float2 sv = gld2(st, (uint32_t)a * fs + op);
+                const double wm = (m == 0 || m == N / 2) ? 1.0 : 2.0;
+                // Re[conj(lr) tr s] + Re[conj(lp) i tp s]
+                acc += wm * (tr * ((double)lr.x * sv.x + (double)lr.y * sv.y) +
+                             tp * (-(double)lp.x * sv.y + (double)lp.y * sv.x));
+            }
+        }
+        part[which - 1] = acc;
+        __syncthreads();
+    }
+    // per-group sums, then one atomic per row and derivative
+    for (int d = 0; d < 2; ++d) {
+        red[threadIdx.x] = part[d];
+        __syncthreads();
+        for (int o = T / 2; o > 0; o >>= 1) {
+            if (t < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (t == 0 && live) atomicAdd(d == 0 ? &dldh[a * A.nr + ip] : &dldh[b * A.nr + ic], red[threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_ssg_finish(double *dldh, int nf, int nr, SsRowArgs A, double *dH)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nf * nr) return;
+    const int i = k % nr;
+    const double r = A.lin ? A.rmin + (i + 0.5) * A.dr : exp(A.lnrmin + (i + 0.5) * A.du);
+    dH[k] = dldh[k] / r;
+}
+
+__global__ void k_ssg_zero(double *p, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0.0;
+}
+
+struct SsGradWs {
+    size_t lt, st, dself, dldh, total;
+};
+
+static SsGradWs ssg_ws(int nr, int nphi, int nf)
+{
+    const size_t fs = sg_blk_field_elems(nphi, nr);
+    SsGradWs w;
+    w.lt = 0;
+    w.st = sg_align256(sizeof(float2) * fs * 2 * nf);
+    w.dself = w.st + sg_align256(sizeof(float2) * fs * nf);
+    w.dldh = w.dself + sg_align256(sizeof(double) * 2 * nf * nf * nr);
+    w.total = w.dldh + sg_align256(sizeof(double) * nf * nr);
+    return w;
+}
+
+size_t sg_ss_grad_ws_bytes(int nr, int nphi, int nf) { return ssg_ws(nr, nphi, nf).total; }
+
+template <int N>
+static void launch_ssg(const double *H, const double *dself, const SsRowArgs &A, const float *lam_r,
+                       const float *lam_p, const float *sigma, const float2 *tw, float2 *lt, float2 *st,
+                       double *dldh, hipStream_t s)
+{
+    using S = SsRowShape<N>;
+    const int nphi_jobs = A.nf * A.nr + A.nf * ((A.nr + 1) / 2);
+    hipLaunchKernelGGL(k_ssg_phi<N>, dim3((nphi_jobs + S::G - 1) / S::G), dim3(S::WGS), 0, s, lam_r, lam_p,
+                       sigma, tw, lt, st, A.nr, A.nf);
+    const size_t rows = (size_t)A.nf * A.nf * A.nr * A.nrt;
+    const size_t chunk = (size_t)1 << 22;
+    for (size_t r0 = 0; r0 < rows; r0 += chunk) {
+        const int n = (int)std::min(chunk, rows - r0);
+        hipLaunchKernelGGL(k_ssg_rows<N>, dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself, A, lt, st, r0,
+                           n, dldh);
+    }
+}
+
+sg_status sg_ss_grad_run(const sg_disc &d, const double *d_H, const float *lam_r, const float *lam_p, double *dH,
+                         void *d_ws, hipStream_t s)
+{
+    const sg_grid *grid = &d.grid;
+    const int nr = grid->n_r, nphi = grid->n_phi, nf = d.fluids.n_fluids;
+    const uint32_t flags = d.flags;
+    const bool lin = (flags & SG_LINEAR_R) != 0;
+    const SsLayout L = sg_ss_layout(nr, nphi, nf, sg_ss_du(*grid, flags), (flags & SG_SS_FULL) != 0);
+    const float2 *tw = (const float2 *)((const char *)d.table + L.off_tw_phi);
+    const SsGradWs W = ssg_ws(nr, nphi, nf);
+    char *ws = (char *)d_ws;
+    float2 *lt = (float2 *)(ws + W.lt), *st = (float2 *)(ws + W.st);
+    double *dself = (double *)(ws + W.dself), *dldh = (double *)(ws + W.dldh);
+    const double dphi = 2.0 * SG_PI / nphi;
+    SsRowArgs A;
+    A.nr = nr;
+    A.nrt = L.nrt;
+    A.nf = nf;
+    A.excl = (flags & SG_SELF_CELL_EXCLUDE) ? 1 : 0;
+    A.ind = (flags & SG_INDIRECT) ? 1 : 0;
+    A.pot = 0;
+    A.lin = lin ? 1 : 0;
+    A.lnrmin = log(grid->r_min);
+    A.du = log(grid->r_max / grid->r_min) / nr;
+    A.dphi = dphi;
+    A.rmin = grid->r_min;
+    A.dr = (grid->r_max - grid->r_min) / nr;
+    hipLaunchKernelGGL(k_ssg_zero, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf * nr);
+    SG_HIP(hipGetLastError());
+    if (!A.excl) {
+        GLNodes gl;
+        sg_gl_nodes(gl);
+        for (int which = 1; which <= 2; ++which) {
+            double *out = dself + (size_t)(which - 1) * nf * nf * nr;
+            if (lin)
+                hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, grid->r_min,
+                                   A.dr, dphi, 0, which, out, gl);
+            else
+                hipLaunchKernelGGL(k_self_cell_ring, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, A.lnrmin,
+                                   A.du, dphi, which, out, gl);
+            SG_HIP(hipGetLastError());
+        }
+    }
+    switch (nphi) {
+    case 4: launch_ssg<4>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 8: launch_ssg<8>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 16: launch_ssg<16>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 32: launch_ssg<32>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 64: launch_ssg<64>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 128: launch_ssg<128>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 256: launch_ssg<256>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 512: launch_ssg<512>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 1024: launch_ssg<1024>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 2048: launch_ssg<2048>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    default: return SG_ERR_UNSUPPORTED;
+    }
+    SG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ssg_finish, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf, nr, A, dH);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}

@@ -28,6 +28,8 @@ sg_status sg_eval_G0_launch(const void *x, void *G, int64_t n, sg_dtype dt, hipS
 
 __global__ void k_twiddles(float2 *tw_u, int nu, float2 *tw_phi, int nphi);
 __global__ void k_self_cell(SelfItems items, double *out, double du, double dphi, GLNodes gl);
+__global__ void k_self_cell_ring(const double *H, int nf, int nr, double lnrmin, double du, double dphi, int which,
+                                 double *out, GLNodes gl);
 template <typename T>
 __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double lnrmin, double du,
                                     double dphi, double *out, GLNodes gl);

@@ -113,6 +113,26 @@ __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double
     const double tot = block_sum256(acc, red);
     if (threadIdx.x == 0) out[item] = tot;
 }
+// Per-ring variant with a derivative selector for the semi-spectral
+// gradient: item = (pair, ring), h = H[f][ring] / r; which = 0: Kbar,
+// 1: dKbar/dh_a, 2: dKbar/dh_b.
+__global__ void k_self_cell_ring(const double *H, int nf, int nr, double lnrmin, double du, double dphi, int which,
+                                 double *out, GLNodes gl)
+{
+    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double red[256];
+    sg_fill_weights<double>(wq);
+    __syncthreads();
+    const int item = blockIdx.x;
+    if (item >= nf * nf * nr) return;
+    const int pair = item / nr, ir = item % nr;
+    const int fa = pair / nf, fb = pair % nf;
+    const double r = exp(lnrmin + (ir + 0.5) * du);
+    const double acc = self_cell_partial(H[fa * nr + ir] / r, H[fb * nr + ir] / r, which, 0.5 * du, 0.5 * dphi, gl, wq);
+    const double tot = block_sum256(acc, red);
+    if (threadIdx.x == 0) out[item] = tot;
+}
+
 template __global__ void k_self_cell_percell<float>(const float *, int, int, int, double, double,
                                                     double, double *, GLNodes);
 template __global__ void k_self_cell_percell<double>(const double *, int, int, int, double, double,
