@@ -390,6 +390,30 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     ms_pass = sg.field_fft_profile([S.disc], S.ws, 10)
+    # reverse mode: dL/dSigma (transposed operators) and dL/dH(r) (derivative
+    # operators sampled on the fly), for seeded lam of the output's shape
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    lam_r = torch.randn(S.g_r.shape, generator=gen).to(dev)
+    lam_p = torch.randn(S.g_r.shape, generator=gen).to(dev)
+    dsig = torch.empty_like(S.sigma)
+    aws = torch.empty(sg.field_adjoint_workspace_bytes(S.disc), dtype=torch.uint8, device=dev)
+    Hd = torch.tensor(w["H"], dtype=torch.float64, device=dev)
+    dH = torch.empty_like(Hd)
+    gws = torch.empty(sg.ss_grad_H_workspace_bytes(S.disc), dtype=torch.uint8, device=dev)
+
+    def rev_ms(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    adj_ms = rev_ms(lambda: sg.field_adjoint(S.disc, lam_r, lam_p, dsig, None, aws), 10)
+    grad_ms = rev_ms(lambda: sg.ss_grad_H(S.disc, Hd, lam_r, lam_p, dH, gws), 3)
+    del aws, gws
     mid = ss_bytes(sg, S.g, nf)
     ach = mid / (ms_pass[1] * 1e-3) / 1e9
     out = {"workload": f"App. D flaring gas disc {nr}x{nphi}, r in [20,250], p=0.25",
@@ -398,6 +422,7 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
            "ms_per_pass": [round(v, 4) for v in ms_pass],
            "ms_per_pass_untuned": [round(v, 4) for v in ms_untuned],
            "middle_pass_shape": [r["groups_per_wg"] for r in tuned if r["pass"] == 2],
+           "adjoint_dsigma_ms": round(adj_ms, 4), "grad_H_ms": round(grad_ms, 2),
            "middle_pass": {"bound": "hbm", "algorithmic_bytes": mid, "achieved": round(ach, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
     del S

@@ -213,7 +213,8 @@ sg_status sg_ss_table(const sg_grid *grid, int n_fluids, const double *d_H, uint
  * (formed while the densities are read), and g_r, g_phi [n_fluids][...]
  * are per group: every species of a group receives that group's
  * acceleration.  n_species = 0: one density per fluid, species_group
- * unused.  sg_field_adjoint returns SG_ERR_UNSUPPORTED for S > 0.
+ * unused.  sg_field_adjoint of a species disc returns one dL/dSigma per
+ * species (that of its group).
  * --------------------------------------------------------------------- */
 typedef struct sg_disc {
     sg_grid grid;
@@ -368,7 +369,11 @@ sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, 
  * Semi-spectral discs: d_dsigma = M^T lam with the stored radial operators
  * transposed mode by mode (the folded indirect term and SG_POTENTIAL
  * operators included); d_dh must be NULL (SG_ERR_UNSUPPORTED otherwise).
- * Discs with n_species > 0, and FFT-path discs with SG_INDIRECT, return
+ * Species discs (n_species = S > 0): lam is per group [F][n_r][n_phi] and
+ * d_dsigma per species [S][n_r][n_phi], each species receiving its
+ * group's dL/dSigma (the forward sums a group's species before the
+ * transform); d_dh is taken at the group densities, summed in the
+ * forward's order.  FFT-path discs with SG_INDIRECT return
  * SG_ERR_UNSUPPORTED.
  * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
  * --------------------------------------------------------------------- */

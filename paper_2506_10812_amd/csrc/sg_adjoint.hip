@@ -354,12 +354,85 @@ __global__ void k_adj_dh_reduce(const double *part, int ncol, int nf, double *dh
 }
 
 // ------------------------------------------------------------------- host
-size_t sg_adjoint_ws_bytes(const sg_disc &d)
+static size_t adj_base_bytes(const sg_disc &d)
 {
     const int nf = d.fluids.n_fluids;
     const size_t fs = sg_blk_field_elems(d.grid.n_phi, d.grid.n_r);
     return sg_align256(sizeof(float2) * fs * 2 * nf) + sg_align256(sizeof(float2) * fs * nf) * 2 +
            sg_align256(sizeof(double) * (d.grid.n_phi / 2 + 1) * nf);
+}
+
+// Species discs add the group densities and the group dL/dSigma after the
+// group run's workspace.
+size_t sg_adjoint_ws_bytes(const sg_disc &d)
+{
+    size_t b = adj_base_bytes(d);
+    if (d.n_species) b += 2 * sg_align256(sizeof(float) * d.fluids.n_fluids * (size_t)d.grid.n_r * d.grid.n_phi);
+    return b;
+}
+
+// ------------------------------------------------------------- species
+// The forward sums each group's species rows (in species order, from zero)
+// before the transform, so every species of a group has that group's
+// dL/dSigma, and dL/dh sees the group sums, formed here in the same order
+// so that they equal the forward's bit for bit.
+struct SpeciesMap {
+    int ns, nf;
+    int gcount[4];
+    uint8_t gsp[4][8];
+    uint8_t group[8];
+};
+
+__global__ void k_species_sum(const float *sig, SpeciesMap M, size_t cells, float *gsig)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)M.nf * cells) return;
+    const int f = (int)(k / cells);
+    const size_t c = k % cells;
+    float acc = 0.f;
+    for (int j = 0; j < M.gcount[f]; ++j) acc += sig[(size_t)M.gsp[f][j] * cells + c];
+    gsig[k] = acc;
+}
+
+__global__ void k_species_bcast(const float *gds, SpeciesMap M, size_t cells, float *dsig)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)M.ns * cells) return;
+    const int s = (int)(k / cells);
+    dsig[k] = gds[(size_t)M.group[s] * cells + k % cells];
+}
+
+static sg_status adjoint_species(const sg_disc &d, const float *lam_r, const float *lam_p, float *dsig,
+                                 double *dh, void *ws, hipStream_t s)
+{
+    const int nf = d.fluids.n_fluids;
+    const size_t cells = (size_t)d.grid.n_r * d.grid.n_phi;
+    char *extra = (char *)ws + adj_base_bytes(d);
+    float *gsig = (float *)extra;
+    float *gds = (float *)(extra + sg_align256(sizeof(float) * nf * cells));
+    SpeciesMap M{};
+    M.ns = d.n_species;
+    M.nf = nf;
+    for (int sp = 0; sp < d.n_species; ++sp) {
+        const int g = d.species_group[sp];
+        M.group[sp] = (uint8_t)g;
+        M.gsp[g][M.gcount[g]++] = (uint8_t)sp;
+    }
+    sg_disc g = d;
+    g.n_species = 0;
+    g.sigma = gsig;
+    if (dh) {
+        const size_t n = (size_t)nf * cells;
+        hipLaunchKernelGGL(k_species_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.sigma, M, cells,
+                           gsig);
+        SG_HIP(hipGetLastError());
+    }
+    const sg_status st = sg_adjoint_run(g, lam_r, lam_p, gds, dh, ws, s);
+    if (st != SG_OK) return st;
+    const size_t n = (size_t)d.n_species * cells;
+    hipLaunchKernelGGL(k_species_bcast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gds, M, cells, dsig);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
 }
 
 template <int N> static int nwg_for(int count)
@@ -487,6 +560,7 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
                          double *dh, void *ws, hipStream_t s)
 {
     const int nr = d.grid.n_r, nphi = d.grid.n_phi, nf = d.fluids.n_fluids;
+    if (d.n_species) return adjoint_species(d, lam_r, lam_p, dsig, dh, ws, s);
     if (d.flags & SG_SEMI_SPECTRAL) {
         const bool full = (d.flags & SG_SS_FULL) != 0;
         const SsLayout L = sg_ss_layout(nr, nphi, nf, sg_ss_du(d.grid, d.flags), full);

@@ -282,7 +282,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
 
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
 {
-    if (!disc || check_disc(*disc) != SG_OK || disc->n_species) return 0;
+    if (!disc || check_disc(*disc) != SG_OK) return 0;
     return sg_adjoint_ws_bytes(*disc);
 }
 
@@ -293,7 +293,6 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
-    if (disc->n_species != 0) return SG_ERR_UNSUPPORTED;
     if (disc->flags & SG_SEMI_SPECTRAL) {
         if (d_dh) return SG_ERR_UNSUPPORTED;  // dL/dSigma only
     } else {

@@ -170,6 +170,24 @@ def test_semispectral_sizes_and_validation(sg):
     # semi-spectral adjoint: dL/dSigma only
     assert sg.field_adjoint_workspace_bytes(d) > 0
     assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, 4096, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED
+    # dL/dH(r): semi-spectral discs without SG_POTENTIAL or species only
+    need = sg.ss_grad_H_workspace_bytes(d)
+    assert need > 0
+    G = L.sg_ss_grad_H
+    assert G(ctypes.byref(d), None, 512, 768, 4096, 8192, need, None) == sg.ERR_ARG
+    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, need - 1, None) == sg.ERR_WORKSPACE
+    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8200, need, None) == sg.ERR_WORKSPACE
+    d.flags = sg.SEMI_SPECTRAL | sg.POTENTIAL
+    assert sg.ss_grad_H_workspace_bytes(d) == 0
+    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED
+    fft = sg.make_disc(sg.grid(16, 32, 0.2, 5.0), sg.fluids([0.05]), 0, 256, 512, 768, 1024)
+    assert sg.ss_grad_H_workspace_bytes(fft) == 0
+    assert G(ctypes.byref(fft), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED
+    d.flags = sg.SEMI_SPECTRAL
+    d.n_species = 2
+    d.species_group[0], d.species_group[1] = 0, 1
+    assert sg.field_fft_workspace_bytes([d]) > 0
+    assert sg.ss_grad_H_workspace_bytes(d) == 0
 
 
 def test_struct_layouts_match_the_header(sg, tmp_path):
@@ -222,10 +240,14 @@ def test_species_validation(sg):
     assert sg.field_fft_workspace_bytes([many]) == 0
     one = sg.make_disc(g, sg.fluids([0.05]), 0, 256, 512, 768, 1024, [0, 1])
     assert sg.field_fft_workspace_bytes([one]) == 0
-    # no adjoint for species discs
-    assert sg.field_adjoint_workspace_bytes(ok) == 0
-    assert sg.lib().sg_field_adjoint(ctypes.byref(ok), 256, 512, 768, None, 2048, 1 << 30,
-                                     None) == sg.ERR_UNSUPPORTED
+    # species adjoint: the group run's workspace plus the group densities and
+    # the group dL/dSigma (2 x 16 x 32 floats each, 256-byte aligned)
+    grp = sg.make_disc(g, f, 0, 256, 512, 768, 1024)
+    assert sg.field_adjoint_workspace_bytes(ok) == sg.field_adjoint_workspace_bytes(grp) + 2 * 4096
+    assert sg.lib().sg_field_adjoint(ctypes.byref(ok), 256, 512, None, None, 2048, 1 << 30,
+                                     None) == sg.ERR_ARG
+    assert sg.lib().sg_field_adjoint(ctypes.byref(ok), 256, 512, 768, None, 2048,
+                                     sg.field_adjoint_workspace_bytes(ok) - 1, None) == sg.ERR_WORKSPACE
 
 
 

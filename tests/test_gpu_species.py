@@ -114,3 +114,72 @@ def test_species_semispectral_with_indirect(sg, T, W):
         er, ep = rel_rms(gr[f], rr[f] + ir), rel_rms(gp[f], rp[f] + ip)
         print(f"  group {f}: rel-RMS {er:.2e} {ep:.2e}", flush=True)
         assert er < 1e-5 and ep < 1e-5
+
+
+def adjoint(sg, disc, lam_r, lam_p, dsig_shape, n_dh):
+    ds = torch.empty(dsig_shape, dtype=torch.float32, device="cuda")
+    dh = torch.empty(n_dh, dtype=torch.float64, device="cuda") if n_dh else None
+    ws = torch.empty(sg.field_adjoint_workspace_bytes(disc), dtype=torch.uint8, device="cuda")
+    sg.field_adjoint(disc, lam_r, lam_p, ds, dh, ws)
+    torch.cuda.synchronize()
+    return ds, dh
+
+
+def test_species_adjoint_fft_path(sg, T, W):
+    """Species adjoint: every species gets its group's dL/dSigma and dL/dh is
+    that of the group densities (bitwise equal to the group disc's adjoint,
+    whose own parity with the oracle is tested elsewhere), plus the transpose
+    identity <lam, g(Sigma_species)> = sum_s <dL/dSigma_s, Sigma_s> (1e-5)."""
+    groups = (0, 1, 1, 0, 1)
+    nr, nphi = 32, 64
+    print(f"species adjoint {groups} fft path {nr}x{nphi}", flush=True)
+    w = W.bifluid_fft(seed=9, n_r=nr, n_phi=nphi)
+    sig = species_of(w, groups, 5)
+    Fs = T.FFTField([dict(w, species_group=list(groups))], flags=sg.WITH_DH)
+    Fs.sigma[0].copy_(torch.tensor(sig))
+    Fs.run()
+    Fg = T.FFTField([w], flags=sg.WITH_DH)
+    sums = group_sums(sig, groups, 2)
+    Fg.sigma[0].copy_(torch.tensor(sums))
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    lam_r = torch.randn((2, nr, nphi), generator=gen).cuda()
+    lam_p = torch.randn((2, nr, nphi), generator=gen).cuda()
+    ds, dh = adjoint(sg, Fs.discs[0], lam_r, lam_p, (len(groups), nr, nphi), 2)
+    dg, dhg = adjoint(sg, Fg.discs[0], lam_r, lam_p, (2, nr, nphi), 2)
+    for s, g in enumerate(groups):
+        assert torch.equal(ds[s], dg[g]), s
+    assert torch.equal(dh, dhg), (dh, dhg)
+    lhs = float((lam_r.double() * Fs.g_r[0].double()).sum() + (lam_p.double() * Fs.g_phi[0].double()).sum())
+    rhs = float((ds.double() * Fs.sigma[0].double()).sum())
+    print(f"  <lam, g> {lhs:.8e}  <dL/dSigma, Sigma> {rhs:.8e}", flush=True)
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+
+
+def test_species_adjoint_semispectral(sg, T, W):
+    """As above on a semi-spectral disc with the indirect term (dL/dSigma)."""
+    groups = (1, 0, 1, 1)
+    nr, nphi = 21, 32
+    print(f"species adjoint {groups} semi-spectral {nr}x{nphi}", flush=True)
+    w = W.flaring(seed=6, n_r=nr, n_phi=nphi, p=0.25, n_fluids=2)
+    phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    w["sigma"] = w["sigma"] * (1 + 0.3 * np.cos(phi - 2.0))[None, None, :]
+    sig = species_of(w, groups, 8)
+    S = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], 2, flags=sg.INDIRECT, species_group=groups)
+    S.refresh(w["H"])
+    S.sigma.copy_(torch.tensor(sig))
+    S.run()
+    G = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], 2, flags=sg.INDIRECT)
+    G.refresh(w["H"])
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cpu").manual_seed(12)
+    lam_r = torch.randn((2, nr, nphi), generator=gen).cuda()
+    lam_p = torch.randn((2, nr, nphi), generator=gen).cuda()
+    ds, _ = adjoint(sg, S.disc, lam_r, lam_p, (len(groups), nr, nphi), 0)
+    dg, _ = adjoint(sg, G.disc, lam_r, lam_p, (2, nr, nphi), 0)
+    for s, g in enumerate(groups):
+        assert torch.equal(ds[s], dg[g]), s
+    lhs = float((lam_r.double() * S.g_r.double()).sum() + (lam_p.double() * S.g_phi.double()).sum())
+    rhs = float((ds.double() * S.sigma.double()).sum())
+    print(f"  <lam, g> {lhs:.8e}  <dL/dSigma, Sigma> {rhs:.8e}", flush=True)
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
