@@ -114,6 +114,12 @@ k_pass1(const DiscDev *discs, const WJob *wj, int nj, const float2 *twp, int kc)
         } else if (c < N / 2) {
             v0 = X.ld(c);
             v1 = X.ld(N - c);
+        } else if (c == N / 2 + 1) {
+            // spare slot: the real columns 0 and N/2 packed as X[0] + i X[N/2]
+            // (pass 2 transforms them as one column)
+            const float2 Z0 = X.ld(0), ZN = X.ld(N / 2);
+            v0 = make_float2(Z0.x, ZN.x);
+            v1 = make_float2(Z0.y, ZN.y);
         }
         gst2x2(D->st + f * fs + sg_blk_tile(q, i0, nr) + 2 * l, v0, v1);
     }
@@ -134,6 +140,10 @@ template <int NU, int NF, int GM> struct P2Shape {
 // Loads of pass-2 column job m for half h: Sigma~_h at rows t + T p (p < P/2;
 // the upper half of the padded column is zero) and the unique kernel-spectrum
 // values K(k_lo), k_lo = t + T j (j < P/2), and K(NU/2) of every source a.
+// Job 0 is the pair of the real columns 0 and n_phi/2: pass 1 stores their
+// packed Sigma~[0] + i Sigma~[n_phi/2] in column slot n_phi/2 + 1, and the
+// table holds (K0 + KN)/2 and (K0 - KN)/2 (K_r of the two columns) in that
+// slot's K_r and K_phi places, so the job loads from slot n_phi/2 + 1.
 template <int NU, int NF>
 __device__ inline void p2_issue(const DiscDev *D, int m, int h, int t, float2 (&sh)[FftShape<NU>::P / 2],
                                 float2 (&K)[NF][2][FftShape<NU>::P / 2], float2 (&KN)[NF][2])
@@ -191,9 +201,10 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     const int cd = sg_uniform(wj[w].disc), cb = sg_uniform(wj[w].base), cn = sg_uniform(wj[w].n);
     const DiscDev *D = discs + cd;
     const int m = g < cn ? cb + g : cb;
+    const bool pr = m == 0;  // columns 0 and n_phi/2 as one job
     // 1. loads
     float2 sh[H], K[NF][2][H], KN[NF][2];
-    p2_issue<NU, NF>(D, m, h, t, sh, K, KN);
+    p2_issue<NU, NF>(D, pr ? D->nphi / 2 + 1 : m, h, t, sh, K, KN);
     TwRegC<NU, SF> tw;
     tw.load(twu, t);
     // SG_INDIRECT: the workgroup holding column m = 1 also forms the star's
@@ -258,24 +269,43 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
         }
     }
     __syncthreads();
-    // 3. multiply-accumulate at k_lo and k_hi
+    // 3. multiply-accumulate at k_lo and k_hi.  The pair job (columns 0 and
+    // n_phi/2, both real in phi): Z = S0 + i SN with S0(k) = (Z(k) + conj
+    // Z(-k))/2 and SN(k) = (Z(k) - conj Z(-k))/(2i), so the packed product is
+    // Y = K0 S0 + i KN SN = A Z(k) + B conj Z(-k), A, B = (K0 +- KN)/2 (K_r of
+    // the two columns; A(-k) = conj A(k), and likewise B).  Plane 0 is A Z, a
+    // regular r product.  Plane 1 runs the phi product with B, giving
+    // a1 = B Z(k_lo) and a2 = -conj(B) Z(k_hi); B conj Z(-k) is then
+    // -conj(a2) at k_lo and conj(a1) at k_hi (at k_lo = 0, k_hi = NU/2, where
+    // B is real and each frequency is its own mirror, conj(a1) and
+    // -conj(a2)).  Both parts go to plane 0, whose inverse transform is then
+    // y = g0 + i gN.
     float2 olo[2][H], ohi[2][H];
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
         for (int j = 0; j < H; ++j) {
+            const bool ny = j == 0 && t == 0;
             float2 a1 = make_float2(0.f, 0.f), a2 = make_float2(0.f, 0.f);
 #pragma unroll
             for (int a = 0; a < NF; ++a) {
                 const float2 k1 = K[a][cc][j];
                 // mirror: conj (K_r) or minus conj (K_phi); Nyquist reads K(NU/2)
-                float2 k2 = (j == 0 && t == 0) ? KN[a][cc] : k1;
+                float2 k2 = ny ? KN[a][cc] : k1;
                 k2 = cc == 0 ? make_float2(k2.x, -k2.y) : make_float2(-k2.x, k2.y);
                 const float2 lo = slo[a][j], hi = shi[a][j];
                 a1.x += k1.x * lo.x - k1.y * lo.y;
                 a1.y += k1.x * lo.y + k1.y * lo.x;
                 a2.x += k2.x * hi.x - k2.y * hi.y;
                 a2.y += k2.x * hi.y + k2.y * hi.x;
+            }
+            if (cc == 1 && pr) {
+                // added to plane 0 (one inverse transform gives y); plane 1 stays zero
+                const float2 c1 = make_float2(a1.x, -a1.y), c2 = make_float2(-a2.x, a2.y);
+                olo[0][j] = c_add(olo[0][j], ny ? c1 : c2);
+                ohi[0][j] = c_add(ohi[0][j], ny ? c2 : c1);
+                a1 = make_float2(0.f, 0.f);
+                a2 = make_float2(0.f, 0.f);
             }
             olo[cc][j] = a1;
             ohi[cc][j] = a2;
@@ -307,11 +337,27 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     }
     if (g < cn) {
         const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
+        if (pr) {
+            // y = g0 + i gN; the phi outputs of both columns are zero
+            const int mh = D->nphi / 2;
+            const uint32_t orr = (h * 2) * fs, op = (h * 2 + 1) * fs;
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
+            for (int p = 0; p < H; ++p) {
+                const float2 y = acc[0][p];
+                const uint32_t i0 = (uint32_t)sg_blk_index(0, t + T * p, NR);
+                const uint32_t i1 = (uint32_t)sg_blk_index(mh, t + T * p, NR);
+                gst2(D->gh, orr + i0, make_float2(y.x, 0.f));
+                gst2(D->gh, orr + i1, make_float2(y.y, 0.f));
+                gst2(D->gh, op + i0, make_float2(0.f, 0.f));
+                gst2(D->gh, op + i1, make_float2(0.f, 0.f));
+            }
+        } else {
 #pragma unroll
-            for (int p = 0; p < H; ++p)
-                gst2(D->gh, (h * 2 + cc) * fs + (uint32_t)sg_blk_index(m, t + T * p, NR), acc[cc][p]);
+            for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                for (int p = 0; p < H; ++p)
+                    gst2(D->gh, (h * 2 + cc) * fs + (uint32_t)sg_blk_index(m, t + T * p, NR), acc[cc][p]);
+        }
     }
 }
 
@@ -498,7 +544,7 @@ static int pass_jobs(const sg_disc &d, int pass, int tb)
     if (pass == 1) return nf * nrp / 2;
     if (pass == 2) {
         if (d.flags & SG_SEMI_SPECTRAL) return (d.grid.n_phi / 2 + 1) * nf * ((d.grid.n_r + tb - 1) / tb);
-        return d.grid.n_phi / 2 + 1;
+        return d.grid.n_phi / 2;  // job 0 carries columns 0 and n_phi/2
     }
     return nf * nrp;
 }

@@ -175,7 +175,8 @@ inline TableLayout sg_table_layout(int nr, int nphi, int nf, uint32_t flags)
     L.off_tw_phi = o;
     o = sg_align256(o + sizeof(float2) * (size_t)nphi);
     L.off_spec = o;
-    o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.npair * 2 * L.kk);
+    // columns m = 0 .. n_phi/2, then the pair column (K0 + KN)/2, (K0 - KN)/2
+    o = sg_align256(o + sizeof(float2) * (size_t)(L.ncol + 1) * L.npair * 2 * L.kk);
     L.off_dspec = o;
     if (flags & SG_WITH_DH) o = sg_align256(o + sizeof(float2) * (size_t)L.ncol * L.npair * 4 * L.kk);
     L.total = o;

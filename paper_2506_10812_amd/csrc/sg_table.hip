@@ -306,6 +306,23 @@ __global__ void k_tab_u(const double2 *B, float2 *dst, int ncol, size_t col_stri
     }
 }
 
+// The pair column after the last one: for the FFT pass that transforms the
+// two real columns m = 0 and n_phi/2 as one complex column, A = (K0 + KN)/2
+// in the K_r place and B = (K0 - KN)/2 in the K_phi place, from K_r of
+// column 0 (K0) and of column n_phi/2 (KN), for every pair and k.
+__global__ void k_pair_col(float2 *spec, int ncol, int npair, int kk)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npair * kk) return;
+    const int pair = e / kk, k = e % kk;
+    const size_t cs = (size_t)npair * 2 * kk;
+    const float2 k0 = spec[(size_t)pair * 2 * kk + k];
+    const float2 kn = spec[(size_t)(ncol - 1) * cs + (size_t)pair * 2 * kk + k];
+    float2 *o = spec + (size_t)ncol * cs + (size_t)pair * 2 * kk;
+    o[k] = make_float2(0.5f * (k0.x + kn.x), 0.5f * (k0.y + kn.y));
+    o[kk + k] = make_float2(0.5f * (k0.x - kn.x), 0.5f * (k0.y - kn.y));
+}
+
 // Header, including the indirect-term coefficient of each source fluid: with
 // H_a = h_a r the star's kernel has d = 1/h_a at every cell, so
 //   sqrt(2) K_a A_k = sqrt(2) pi^{-1/2} h_a^{-3} / 4 F(1 / (4 h_a^2)) du dphi
@@ -563,6 +580,9 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
                 SG_HIP(hipGetLastError());
             }
         }
+    hipLaunchKernelGGL(k_pair_col, dim3((L.npair * L.kk + 255) / 256), dim3(256), 0, s, spec, L.ncol, L.npair,
+                       L.kk);
+    SG_HIP(hipGetLastError());
     sg_table_header proto{};
     proto.magic = SG_TABLE_MAGIC;
     proto.version = 1;

@@ -191,7 +191,7 @@ def test_kernel_table_matches_numpy_fft_of_oracle_samples(sg, T):
     o = al(o + 8 * nphi)
     off_spec = o
     ncol, kk = nphi // 2 + 1, nr + 1
-    spec = raw[off_spec:off_spec + 8 * ncol * 4 * 2 * kk].view(np.complex64).reshape(ncol, 4, 2, kk)
+    spec = raw[off_spec:off_spec + 8 * (ncol + 1) * 4 * 2 * kk].view(np.complex64).reshape(ncol + 1, 4, 2, kk)
     p = np.arange(2 * nr)
     X = np.where(p < nr, p, p - 2 * nr) * du
     q = np.arange(nphi) * dphi
@@ -208,9 +208,13 @@ def test_kernel_table_matches_numpy_fft_of_oracle_samples(sg, T):
             kp[0, 0] = 0
             for c, K in enumerate((kr, kp)):
                 ref = np.fft.fft2(K)[:nr + 1, :ncol].T * scale  # [m][k]
-                got = spec[:, a * 2 + b, c, :]
+                got = spec[:ncol, a * 2 + b, c, :]
                 err = np.abs(got - ref).max() / np.abs(ref).max()
                 assert err < 1e-6, (a, b, c, err)
+    # the pair column: (K0 + KN)/2 and (K0 - KN)/2 of K_r, columns 0 and n_phi/2
+    k0, kn = spec[0, :, 0, :], spec[ncol - 1, :, 0, :]
+    assert np.array_equal(spec[ncol, :, 0, :], ((k0 + kn) * np.float32(0.5)).astype(np.complex64))
+    assert np.array_equal(spec[ncol, :, 1, :], ((k0 - kn) * np.float32(0.5)).astype(np.complex64))
 
 
 # ---------------------------------------------------------------- FFT path
