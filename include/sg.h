@@ -20,7 +20,10 @@
  *              phi_j = (j + 1/2) dphi, dphi = 2 pi / n_phi; cell area
  *              A_i = r_i^2 du dphi.
  *   layout     every device array is row-major [fluid][i_r][j_phi] with phi
- *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 or 2.
+ *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 or 2
+ *              on the FFT path (sg_fluids), 1 to 4 scale-height groups on
+ *              the semi-spectral path and in the direct sums and sg_hsg
+ *              (the multi-fluid case of Sect. 5.2: all F^2 ordered pairs).
  *   pairs      (a -> b) is source fluid a acting on target fluid b; a
  *              two-fluid disc has the four ordered pairs gg, dg, gd, dd
  *              (Sect. 2.2 lists the four combinations).
@@ -312,9 +315,9 @@ sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_
  * outputs and arithmetic; SG_F32: float inputs, outputs, arithmetic and
  * accumulation (the self term and the indirect term are computed in double
  * and rounded).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (with the source
- * cell's own H in K_a).  n_r, n_phi >= 1, n_r * n_phi <= 2^26.  h: host
- * array [F], read when d_H == NULL.  d_ws: sg_field_direct_workspace_bytes()
- * bytes.
+ * cell's own H in K_a).  n_r, n_phi >= 1, n_r * n_phi <= 2^26.  F (the
+ * fluid count) 1 to 4.  h: host array [F], read when d_H == NULL.  d_ws:
+ * sg_field_direct_workspace_bytes() bytes.
  * --------------------------------------------------------------------- */
 size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
                                        int per_cell_H);
@@ -351,7 +354,8 @@ sg_status sg_potential_direct(const sg_grid *grid, int n_fluids, const double *h
  *   f(x) = pi/(4x) [sqrt(1 + 8 x^2/pi) - 1],
  * H_f the thermal (gas) or diffusive (dust) scale height, Q_f the Toomre
  * parameter c_f Omega_K / (pi G Sigma_f) of each fluid.  Device double
- * arrays [n_fluids][n] (n cells); Q_f > 0.  Double arithmetic.
+ * arrays [n_fluids][n] (n cells), n_fluids 1 to 4; Q_f > 0.  Double
+ * arithmetic.
  * --------------------------------------------------------------------- */
 sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, double *d_Hsg,
                  void *stream);

@@ -250,7 +250,7 @@ def field_fft_tune(discs, ws, ws_bytes=None, stream=None, capacity=256):
 
 def field_direct(g: Grid, n_fluids, h, sigma, H, g_r, g_phi, dtype, flags, ws, ws_bytes=None,
                  stream=None):
-    harr = (ctypes.c_double * 2)(*([float(v) for v in h] + [0.0] * (2 - len(h)))) if h is not None else None
+    harr = (ctypes.c_double * 4)(*([float(v) for v in h] + [0.0] * (4 - len(h)))) if h is not None else None
     ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
     _check(_lib.sg_field_direct(ctypes.byref(g), n_fluids,
                                 ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,
@@ -264,7 +264,7 @@ def potential_direct_workspace_bytes(g: Grid, n_fluids, dtype, per_cell_H) -> in
 
 
 def potential_direct(g: Grid, n_fluids, h, sigma, H, pot, dtype, flags, ws, ws_bytes=None, stream=None):
-    harr = (ctypes.c_double * 2)(*([float(v) for v in h] + [0.0] * (2 - len(h)))) if h is not None else None
+    harr = (ctypes.c_double * 4)(*([float(v) for v in h] + [0.0] * (4 - len(h)))) if h is not None else None
     ws_bytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
     _check(_lib.sg_potential_direct(ctypes.byref(g), n_fluids,
                                     ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,

@@ -207,7 +207,7 @@ sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_
 size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
                                        int per_cell_H)
 {
-    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 4) return 0;
     if (dtype != SG_F32 && dtype != SG_F64) return 0;
     if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return 0;
     return sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, per_cell_H ? 1 : 0);
@@ -216,7 +216,7 @@ size_t sg_field_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dty
 size_t sg_potential_direct_workspace_bytes(const sg_grid *grid, int n_fluids, sg_dtype dtype,
                                            int per_cell_H)
 {
-    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 2) return 0;
+    if (check_grid(grid) != SG_OK || n_fluids < 1 || n_fluids > 4) return 0;
     if (dtype != SG_F32 && dtype != SG_F64) return 0;
     return sg_potential_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, per_cell_H ? 1 : 0);
 }
@@ -227,7 +227,7 @@ sg_status sg_potential_direct(const sg_grid *grid, int n_fluids, const double *h
 {
     sg_status s = check_grid(grid);
     if (s != SG_OK) return s;
-    if (n_fluids < 1 || n_fluids > 2) return SG_ERR_ARG;
+    if (n_fluids < 1 || n_fluids > 4) return SG_ERR_ARG;
     if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
     if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
     if (!d_sigma || !d_pot) return SG_ERR_ARG;
@@ -245,7 +245,7 @@ sg_status sg_potential_direct(const sg_grid *grid, int n_fluids, const double *h
 
 sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, double *d_Hsg, void *stream)
 {
-    if (n < 0 || n_fluids < 1 || n_fluids > 2 || !d_H || !d_Q || !d_Hsg) return SG_ERR_ARG;
+    if (n < 0 || n_fluids < 1 || n_fluids > 4 || !d_H || !d_Q || !d_Hsg) return SG_ERR_ARG;
     if (n == 0) return SG_OK;
     return sg_hsg_launch(n, n_fluids, d_H, d_Q, d_Hsg, (hipStream_t)stream);
 }
@@ -263,7 +263,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
 {
     sg_status s = check_grid(grid);
     if (s != SG_OK) return s;
-    if (n_fluids < 1 || n_fluids > 2) return SG_ERR_ARG;
+    if (n_fluids < 1 || n_fluids > 4) return SG_ERR_ARG;
     if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
     if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
     if (!d_sigma || !d_g_r || !d_g_phi) return SG_ERR_ARG;
@@ -275,7 +275,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
     }
     const size_t need = sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, d_H ? 1 : 0);
     if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
-    static const double one[2] = {1.0, 1.0};
+    static const double one[4] = {1.0, 1.0, 1.0, 1.0};
     return sg_direct_launch(grid, n_fluids, d_H ? one : h, d_sigma, d_H, d_g_r, d_g_phi, dtype,
                             flags, d_ws, (hipStream_t)stream);
 }

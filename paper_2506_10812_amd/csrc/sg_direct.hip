@@ -354,7 +354,7 @@ size_t sg_direct_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += 2 * sg_align256(es * nf * N);
     o += sg_align256(sizeof(double) * nf * nf * (percell ? N : 1));
     o += sg_align256(es * (size_t)S * nf * 2 * N);
-    o += sg_align256(sizeof(double) * 2);
+    o += sg_align256(sizeof(double) * 4);
     o += sg_align256(sizeof(double2) * (SG_IND_BLOCKS + 1));
     return o;
 }
@@ -386,14 +386,13 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     const int percell = H != nullptr;
     double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : 1));
     T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 2 * N);
-    double *dh = (double *)take(sizeof(double) * 2);
+    double *dh = (double *)take(sizeof(double) * 4);
     double2 *ipart = (double2 *)take(sizeof(double2) * (SG_IND_BLOCKS + 1));
     double2 *iab = ipart + SG_IND_BLOCKS;
 
     // h lives on the host: pass through a kernel argument copy in device memory
     // is avoided by writing it with a fill kernel.
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh, (int64_t)1, h[0]);
-    if (nf > 1) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + 1, (int64_t)1, h[1]);
+    for (int f = 0; f < nf; ++f) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + f, (int64_t)1, h[f]);
     SG_HIP(hipGetLastError());
     {
         int64_t work = nf * N > 2 * nr ? nf * N : 2 * nr;
@@ -448,17 +447,25 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     A.H2 = H2;
     A.partial = partial;
     dim3 grid((unsigned)((N + 255) / 256), (unsigned)S);
-    if (nf == 1) hipLaunchKernelGGL((k_direct<T, 1>), grid, dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_direct<T, 2>), grid, dim3(256), 0, s, A);
+    switch (nf) {
+    case 1: hipLaunchKernelGGL((k_direct<T, 1>), grid, dim3(256), 0, s, A); break;
+    case 2: hipLaunchKernelGGL((k_direct<T, 2>), grid, dim3(256), 0, s, A); break;
+    case 3: hipLaunchKernelGGL((k_direct<T, 3>), grid, dim3(256), 0, s, A); break;
+    default: hipLaunchKernelGGL((k_direct<T, 4>), grid, dim3(256), 0, s, A); break;
+    }
     SG_HIP(hipGetLastError());
     const unsigned nb = (unsigned)((N + 255) / 256);
     const double2 *indp = ind ? (const double2 *)iab : nullptr;
-    if (nf == 1)
-        hipLaunchKernelGGL((k_direct_reduce<T, 1>), dim3(nb), dim3(256), 0, s, partial, S, N, self,
-                           percell, with_self, sigma, du * dphi, indp, nphi, gr, gp);
-    else
-        hipLaunchKernelGGL((k_direct_reduce<T, 2>), dim3(nb), dim3(256), 0, s, partial, S, N, self,
-                           percell, with_self, sigma, du * dphi, indp, nphi, gr, gp);
+#define SG_RED(NF)                                                                                      \
+    hipLaunchKernelGGL((k_direct_reduce<T, NF>), dim3(nb), dim3(256), 0, s, partial, S, N, self, percell,  \
+                       with_self, sigma, du * dphi, indp, nphi, gr, gp)
+    switch (nf) {
+    case 1: SG_RED(1); break;
+    case 2: SG_RED(2); break;
+    case 3: SG_RED(3); break;
+    default: SG_RED(4); break;
+    }
+#undef SG_RED
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -475,7 +482,7 @@ size_t sg_potential_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += 2 * sg_align256(es * nf * N);
     o += sg_align256(sizeof(double) * nf * nf * (percell ? N : nr));
     o += sg_align256(es * (size_t)S * nf * N);
-    o += sg_align256(sizeof(double) * 2);
+    o += sg_align256(sizeof(double) * 4);
     return o;
 }
 
@@ -506,9 +513,9 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
     const int percell = H != nullptr;
     double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : nr));
     T *partial = (T *)take(sizeof(T) * (size_t)S * nf * N);
-    double *dh = (double *)take(sizeof(double) * 2);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh, (int64_t)1, h ? h[0] : 0.0);
-    if (nf > 1) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + 1, (int64_t)1, h ? h[1] : 0.0);
+    double *dh = (double *)take(sizeof(double) * 4);
+    for (int f = 0; f < nf; ++f)
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + f, (int64_t)1, h ? h[f] : 0.0);
     SG_HIP(hipGetLastError());
     {
         int64_t work = nf * N > 2 * nr ? nf * N : 2 * nr;
@@ -543,16 +550,24 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
     A.H2 = H2;
     A.partial = partial;
     dim3 grid((unsigned)((N + 255) / 256), (unsigned)S);
-    if (nf == 1) hipLaunchKernelGGL((k_potential<T, 1>), grid, dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_potential<T, 2>), grid, dim3(256), 0, s, A);
+    switch (nf) {
+    case 1: hipLaunchKernelGGL((k_potential<T, 1>), grid, dim3(256), 0, s, A); break;
+    case 2: hipLaunchKernelGGL((k_potential<T, 2>), grid, dim3(256), 0, s, A); break;
+    case 3: hipLaunchKernelGGL((k_potential<T, 3>), grid, dim3(256), 0, s, A); break;
+    default: hipLaunchKernelGGL((k_potential<T, 4>), grid, dim3(256), 0, s, A); break;
+    }
     SG_HIP(hipGetLastError());
     const unsigned nb = (unsigned)((N + 255) / 256);
-    if (nf == 1)
-        hipLaunchKernelGGL((k_potential_reduce<T, 1>), dim3(nb), dim3(256), 0, s, partial, S, N, nphi, self,
-                           percell ? 0 : 1, with_self, sigma, pot);
-    else
-        hipLaunchKernelGGL((k_potential_reduce<T, 2>), dim3(nb), dim3(256), 0, s, partial, S, N, nphi, self,
-                           percell ? 0 : 1, with_self, sigma, pot);
+#define SG_PRED(NF)                                                                                      \
+    hipLaunchKernelGGL((k_potential_reduce<T, NF>), dim3(nb), dim3(256), 0, s, partial, S, N, nphi, self, \
+                       percell ? 0 : 1, with_self, sigma, pot)
+    switch (nf) {
+    case 1: SG_PRED(1); break;
+    case 2: SG_PRED(2); break;
+    case 3: SG_PRED(3); break;
+    default: SG_PRED(4); break;
+    }
+#undef SG_PRED
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

@@ -105,11 +105,17 @@ def test_direct_validation(sg):
     need = sg.field_direct_workspace_bytes(g, 2, sg.F64, False)
     assert need > 0
     L = sg.lib()
-    h = (ctypes.c_double * 2)(0.05, 0.01)
+    h = (ctypes.c_double * 5)(0.05, 0.01, 0.02, 0.03, 0.04)
     hp = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
-    # bad dtype, bad fluid count, missing h, bad flag, small workspace
+    # bad dtype, bad fluid count (1 to 4 scale-height groups), missing h, bad flag, small workspace
     assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, 7, 0, 1024, need, None) == sg.ERR_ARG
-    assert L.sg_field_direct(ctypes.byref(g), 3, hp, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 5, hp, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
+    assert L.sg_field_direct(ctypes.byref(g), 0, hp, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
+    assert sg.field_direct_workspace_bytes(g, 4, sg.F64, False) > need
+    assert sg.field_direct_workspace_bytes(g, 5, sg.F64, False) == 0
+    assert sg.potential_direct_workspace_bytes(g, 4, sg.F32, True) > 0
+    assert sg.potential_direct_workspace_bytes(g, 5, sg.F32, True) == 0
+    assert L.sg_hsg(10, 5, 256, 512, 768, None) == sg.ERR_ARG
     assert L.sg_field_direct(ctypes.byref(g), 2, None, 256, None, 512, 768, sg.F64, 0, 1024, need, None) == sg.ERR_ARG
     assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, sg.F64, sg.WITH_DH, 1024, need, None) == sg.ERR_ARG
     assert L.sg_field_direct(ctypes.byref(g), 2, hp, 256, None, 512, 768, sg.F64, 0, 1024, need - 1, None) == sg.ERR_WORKSPACE

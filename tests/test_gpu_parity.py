@@ -387,3 +387,57 @@ def test_adjoint_256x512_sampled_and_loss_gradient(sg, T, W):
     got = ds.reshape(2, -1)[:, idx]
     for a in range(2):
         assert rel_rms(got[a], ref[a]) < 1e-4
+
+
+# ------------------------------------------------- three and four groups
+@pytest.mark.parametrize("nr,nphi,nf,per_cell,flags", [(7, 9, 3, True, 0), (6, 8, 4, False, 0),
+                                                       (5, 12, 4, True, 4), (9, 5, 3, False, 1)])
+def test_direct_fp64_three_and_four_groups(sg, T, nr, nphi, nf, per_cell, flags):
+    """The multi-fluid case of Sect. 5.2 beyond gas + dust: all nf^2 ordered
+    pairs, per-cell or h r scale heights, the indirect term or no own cell,
+    ragged sizes, against the oracle's pairwise sum (1e-12 of max|g|)."""
+    say(f"direct FP64 {nf} groups {nr}x{nphi} per_cell={per_cell} flags={flags}")
+    rng = np.random.default_rng(nr * 10 + nf)
+    rmin, rmax = 0.3, 2.0
+    sig = rng.uniform(0.2, 2.0, (nf, nr, nphi))
+    h = [0.07, 0.02, 0.01, 0.035][:nf]
+    r, _, _, _ = O.grid(nr, nphi, rmin, rmax)
+    H = rng.uniform(0.01, 0.15, (nf, nr, nphi)) * r[None, :, None] if per_cell else None
+    g = sg.grid(nr, nphi, rmin, rmax)
+    gr, gp = T.direct(g, None if per_cell else h, torch.tensor(sig, device="cuda"),
+                      H=torch.tensor(H, device="cuda") if per_cell else None, flags=flags)
+    torch.cuda.synchronize()
+    rr, rp = O.field_pairwise(nr, nphi, rmin, rmax, [0.0] * nf if per_cell else h, sig, H=H,
+                              flags=O.EXCLUDE_SELF if flags & 1 else 0)
+    if flags & 4:
+        ir, ip = O.indirect_field(nr, nphi, O.indirect(nr, nphi, rmin, rmax, [0.0] * nf if per_cell else h,
+                                                       sig, H=H))
+        rr = rr + ir[None, :]
+        rp = rp + ip[None, :]
+    gr = gr.cpu().numpy().reshape(nf, -1)
+    gp = gp.cpu().numpy().reshape(nf, -1)
+    scale = float(np.sqrt(rr ** 2 + rp ** 2).max())
+    m_r = float(np.abs(gr - rr).max()) / scale
+    m_p = float(np.abs(gp - rp).max()) / scale
+    say(f"  max/max|g| {m_r:.2e} {m_p:.2e}")
+    assert m_r < 1e-12 and m_p < 1e-12
+
+
+def test_direct_fp32_four_groups(sg, T):
+    nr, nphi, nf = 20, 24, 4
+    say(f"direct FP32 {nf} groups {nr}x{nphi}")
+    rng = np.random.default_rng(77)
+    r, _, _, _ = O.grid(nr, nphi, 0.2, 2.5)
+    sig = (1 / r)[None, :, None] * rng.uniform(0.5, 1.5, (nf, nr, nphi))
+    h = [0.05, 0.005, 0.02, 0.01]
+    g = sg.grid(nr, nphi, 0.2, 2.5)
+    gr, gp = T.direct(g, h, torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    sig32 = torch.tensor(sig, dtype=torch.float32).double().numpy()
+    rr, rp = O.field_pairwise(nr, nphi, 0.2, 2.5, h, sig32)
+    gr = gr.double().cpu().numpy().reshape(nf, -1)
+    gp = gp.double().cpu().numpy().reshape(nf, -1)
+    for b in range(nf):
+        say(f"  group {b}: rel-RMS {rel_rms(gr[b], rr[b]):.2e} {rel_rms(gp[b], rp[b]):.2e}")
+        assert rel_rms(gr[b], rr[b]) < 1e-5
+        assert rel_rms(gp[b], rp[b]) < 1e-5

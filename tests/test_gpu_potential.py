@@ -112,3 +112,45 @@ def test_hsg_matches_oracle(sg):
     torch.cuda.synchronize()
     e1 = 8 * Q[0] ** 2 / np.pi
     assert np.all(np.abs(one.cpu().numpy() / O.hsg(H[:1], Q[:1]) - 1) < 1e-14 + 8 * np.finfo(float).eps * (1 + 1 / e1))
+
+
+@pytest.mark.parametrize("nr,nphi,nf,const_H", [(9, 11, 3, False), (8, 12, 4, True)])
+def test_potential_three_and_four_groups(sg, T, nr, nphi, nf, const_H):
+    """All nf^2 ordered pairs of the potential, against the oracle (1e-12)."""
+    print(f"potential f64 {nf} groups {nr}x{nphi} constH={const_H}", flush=True)
+    rng = np.random.default_rng(nr + 7 * nf)
+    rmin, rmax = 0.4, 2.5
+    sig = rng.uniform(0.1, 1.0, (nf, nr, nphi))
+    h = [0.05, 0.01, 0.03, 0.02][:nf]
+    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * np.log(rmax / rmin) / nr)
+    if const_H:
+        H = np.array([0.08, 0.03, 0.05, 0.02][:nf])[:, None, None] * np.ones((nf, nr, nphi))
+    else:
+        H = rng.uniform(0.02, 0.12, (nf, nr, nphi)) * r[None, :, None]
+    g = sg.grid(nr, nphi, rmin, rmax)
+    pot = T.potential(g, None, torch.tensor(sig, dtype=torch.float64, device="cuda"),
+                      H=torch.tensor(H, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    want = O.potential_pairwise(nr, nphi, rmin, rmax, h, sig, H=H)
+    got = pot.double().cpu().numpy().reshape(nf, -1)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"  max err / max|Phi| {err:.2e}", flush=True)
+    assert err < 1e-12, err
+
+
+def test_hsg_four_groups(sg):
+    """Qt sums 1/Q over all groups; every group's H is scaled by f(Qt)."""
+    rng = np.random.default_rng(19)
+    H = rng.uniform(0.005, 0.2, (4, 500))
+    Q = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), (4, 500)))
+    Ht = torch.tensor(H, dtype=torch.float64, device="cuda")
+    Qt = torch.tensor(Q, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(Ht)
+    sg.hsg(Ht, Qt, out)
+    torch.cuda.synchronize()
+    want = O.hsg(H, Q)
+    # the oracle's printed form loses about eps/e at small x (see above)
+    x = 1 / (1 / Q).sum(axis=0)
+    e = 8 * x * x / np.pi
+    tol = 1e-14 + 8 * np.finfo(float).eps * (1 + 1 / e)
+    assert np.all(np.abs(out.cpu().numpy() / want - 1) < tol[None, :])
