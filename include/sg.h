@@ -70,7 +70,7 @@ enum {
     SG_SEMI_SPECTRAL = 8u,     /* disc uses a semi-spectral table (below)     */
     SG_SS_FULL = 16u,          /* semi-spectral: keep every operator entry    */
     SG_POTENTIAL = 32u,        /* semi-spectral: operators of the potential   */
-    SG_LINEAR_R = 64u          /* semi-spectral: uniform radial grid          */
+    SG_LINEAR_R = 64u          /* uniform radial grid (semi-spectral, direct) */
 };
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
@@ -315,7 +315,9 @@ sg_status sg_field_fft_tune(const sg_disc *discs, int n_discs, void *d_ws, size_
  * outputs and arithmetic; SG_F32: float inputs, outputs, arithmetic and
  * accumulation (the self term and the indirect term are computed in double
  * and rounded).  flags: SG_SELF_CELL_EXCLUDE, SG_INDIRECT (with the source
- * cell's own H in K_a).  n_r, n_phi >= 1, n_r * n_phi <= 2^26.  F (the
+ * cell's own H in K_a), SG_LINEAR_R (uniform radial grid: centres
+ * r_min + (i + 1/2) dr, sector areas r dr dphi, one-sided own-cell
+ * integrals, as on the semi-spectral path).  n_r, n_phi >= 1, n_r * n_phi <= 2^26.  F (the
  * fluid count) 1 to 4.  h: host array [F], read when d_H == NULL.  d_ws:
  * sg_field_direct_workspace_bytes() bytes.
  * --------------------------------------------------------------------- */

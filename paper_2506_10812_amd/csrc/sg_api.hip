@@ -267,7 +267,7 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
     if (dtype != SG_F32 && dtype != SG_F64) return SG_ERR_ARG;
     if ((int64_t)grid->n_r * grid->n_phi > ((int64_t)1 << 26)) return SG_ERR_UNSUPPORTED;
     if (!d_sigma || !d_g_r || !d_g_phi) return SG_ERR_ARG;
-    if ((flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT)) != 0) return SG_ERR_ARG;
+    if ((flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_LINEAR_R)) != 0) return SG_ERR_ARG;
     if (!d_H) {
         if (!h) return SG_ERR_ARG;
         for (int f = 0; f < n_fluids; ++f)

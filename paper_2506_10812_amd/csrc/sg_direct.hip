@@ -12,7 +12,10 @@
 //   g_r  -= Sigma_a[k] A_k (K/s) r_k (expm1(X) + 2 sin^2(phi/2)),
 //   g_phi -= Sigma_a[k] A_k (K/s) r_k sin phi.
 // The offset factors depend only on (i_r - k_r) and (j - l) and are tabulated
-// once per call in double (rounded for the float path).
+// once per call in double (rounded for the float path).  On a uniform radial
+// grid (SG_LINEAR_R: centres r_min + (i + 1/2) dr, sector areas r dr dphi)
+// the radial factors 4 sinh^2(X/2) = (r_i - r_k)^2 / (r_i r_k) and
+// expm1(X) = (r_i - r_k) / r_k are formed per source row instead.
 //
 // Layout: one thread per target cell (256 per workgroup), all target fluids
 // in registers; the source loop runs over whole radial rows so every
@@ -27,20 +30,27 @@
 
 template <typename T> struct DirectArgs {
     int nr, nphi, rps;   // rows per split
+    int lin;             // uniform radial grid
     int64_t N;
     const T *rrow, *sx, *ex, *sph, *snp, *mass, *H2;
     T *partial;
 };
 
+// Ring radius: log grid (lin = 0) or uniform grid (a = r_min, b = dr).
+__device__ inline double dir_radius(int lin, double lnrmin, double du, double rmin, double dr, int i)
+{
+    return lin ? rmin + (i + 0.5) * dr : exp(lnrmin + (i + 0.5) * du);
+}
+
 template <typename T>
 __global__ void k_direct_prep(int nr, int nphi, int nf, double lnrmin, double du, double dphi,
                               const double *h, const T *sigma, const T *H, T *rrow, T *sx, T *ex,
-                              T *sph, T *snp, T *mass, T *H2)
+                              T *sph, T *snp, T *mass, T *H2, int lin, double rmin, double dr, double *Hd)
 {
     const int64_t N = (int64_t)nr * nphi;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < nr; i += stride) rrow[i] = (T)exp(lnrmin + (i + 0.5) * du);
+    for (int64_t i = tid; i < nr; i += stride) rrow[i] = (T)dir_radius(lin, lnrmin, du, rmin, dr, (int)i);
     for (int64_t p = tid; p < 2 * nr - 1; p += stride) {
         const double X = (double)(p - (nr - 1)) * du;
         const double s = sinh(0.5 * X);
@@ -55,13 +65,17 @@ __global__ void k_direct_prep(int nr, int nphi, int nf, double lnrmin, double du
     for (int64_t k = tid; k < nf * N; k += stride) {
         const int64_t cell = k % N;
         const int ir = (int)(cell / nphi);
-        const double r = exp(lnrmin + (ir + 0.5) * du);
-        mass[k] = (T)((double)sigma[k] * r * r * du * dphi);
+        const double r = dir_radius(lin, lnrmin, du, rmin, dr, ir);
+        mass[k] = (T)((double)sigma[k] * (lin ? r * dr : r * r * du) * dphi);
         double Hk;
         if (H) Hk = (double)H[k];
         else Hk = h[k / N] * r;
         H2[k] = (T)(Hk * Hk);
+        if (lin && H) Hd[k] = Hk;  // double H per cell for the own-cell integrals
     }
+    if (lin && !H)  // double H per ring
+        for (int64_t k = tid; k < (int64_t)nf * nr; k += stride)
+            Hd[k] = h[k / nr] * dir_radius(1, 0.0, 0.0, rmin, dr, (int)(k % nr));
 }
 
 template <typename T> __device__ inline T sg_F_any(T x, const T *w);
@@ -90,9 +104,17 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
     const int r0 = blockIdx.y * A.rps;
     const int r1 = min(nr, r0 + A.rps);
     for (int kr = r0; kr < r1; ++kr) {
-        const int p = ir - kr + nr - 1;
-        const T SX = A.sx[p], EX = A.ex[p];
         const T rk = A.rrow[kr];
+        T SX, EX;
+        if (A.lin) {
+            const T d = ri - rk;
+            SX = d * d / (ri * rk);
+            EX = d / rk;
+        } else {
+            const int p = ir - kr + nr - 1;
+            SX = A.sx[p];
+            EX = A.ex[p];
+        }
         const T rr = ri * rk;
         const int64_t kbase = (int64_t)kr * nphi;
         for (int l = 0; l < nphi; ++l) {
@@ -138,7 +160,8 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
 template <typename T>
 __global__ void __launch_bounds__(256) k_indirect_part(int nr, int nphi, int nf, double lnrmin, double du,
                                                        double dphi, const double *h, const T *sigma,
-                                                       const T *H, double2 *part)
+                                                       const T *H, double2 *part, int lin, double rmin,
+                                                       double dr)
 {
     __shared__ double wq[FQuad<double>::NODES];
     __shared__ double ra[256], rb[256];
@@ -150,11 +173,11 @@ __global__ void __launch_bounds__(256) k_indirect_part(int nr, int nphi, int nf,
         const int a = (int)(k / N);
         const int64_t cell = k % N;
         const int ir = (int)(cell / nphi), j = (int)(cell % nphi);
-        const double r = exp(lnrmin + (ir + 0.5) * du);
+        const double r = dir_radius(lin, lnrmin, du, rmin, dr, ir);
         const double Hk = H ? (double)H[k] : h[a] * r;
         const double d = r / Hk;
         const double Ka = 1.0 / (SG_SQRT_PI * Hk * Hk) * (0.25 * d) * sg_F64(0.25 * d * d, wq);
-        const double w = SG_SQRT2 * (double)sigma[k] * r * r * du * dphi * Ka;
+        const double w = SG_SQRT2 * (double)sigma[k] * (lin ? r * dr : r * r * du) * dphi * Ka;
         double sp, cp;
         sincos((j + 0.5) * dphi, &sp, &cp);
         sa += w * cp;
@@ -184,10 +207,14 @@ __global__ void k_indirect_fin(const double2 *part, int n, double2 *AB)
     *AB = make_double2(a, b);
 }
 
+// self: per pair (log grid, H = h r), per cell (percell = 1) or, on a
+// uniform grid without per-cell H, per ring (percell = 2); the own-cell
+// values are cell averages per (du dphi), or per (dr / r_i) dphi on a
+// uniform grid (lin; rmin, dr give r_i).
 template <typename T, int NF>
 __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double *self,
                                 int percell, int with_self, const T *sigma, double dudphi,
-                                const double2 *ind, int nphi, T *gr, T *gp)
+                                const double2 *ind, int nphi, T *gr, T *gp, int lin, double rmin, double dr)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= N) return;
@@ -207,12 +234,17 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
             sp += partial[((int64_t)(s * NF + b) * 2 + 1) * N + t];
         }
         if (with_self) {
+            const int ir = (int)(t / nphi);
+            const double w = lin ? dr / (rmin + (ir + 0.5) * dr) * (2.0 * SG_PI / nphi) : dudphi;
+            const int64_t nring = N / nphi;
             double st = 0.0;
 #pragma unroll
             for (int a = 0; a < NF; ++a) {
                 const int pair = a * NF + b;
-                const double kb = percell ? self[(int64_t)pair * N + t] : self[pair];
-                st -= dudphi * (double)sigma[a * N + t] * kb;
+                const double kb = percell == 1   ? self[(int64_t)pair * N + t]
+                                  : percell == 2 ? self[(int64_t)pair * nring + ir]
+                                                 : self[pair];
+                st -= w * (double)sigma[a * N + t] * kb;
             }
             sr += (T)st;
         }
@@ -352,7 +384,7 @@ size_t sg_direct_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += 2 * sg_align256(es * (2 * (size_t)nr - 1));
     o += 2 * sg_align256(es * nphi);
     o += 2 * sg_align256(es * nf * N);
-    o += sg_align256(sizeof(double) * nf * nf * (percell ? N : 1));
+    o += sg_align256(sizeof(double) * nf * nf * (percell ? N : nr));
     o += sg_align256(es * (size_t)S * nf * 2 * N);
     o += sg_align256(sizeof(double) * 4);
     o += sg_align256(sizeof(double2) * (SG_IND_BLOCKS + 1));
@@ -368,6 +400,8 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     const double du = log(g->r_max / g->r_min) / nr;
     const double dphi = 2.0 * SG_PI / nphi;
     const double lnrmin = log(g->r_min);
+    const int lin = (flags & SG_LINEAR_R) ? 1 : 0;
+    const double dr = (g->r_max - g->r_min) / nr;
     const int S = direct_splits(nr, N);
     const int rps = (nr + S - 1) / S;
     char *o = (char *)ws;
@@ -384,8 +418,11 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     T *mass = (T *)take(sizeof(T) * nf * N);
     T *H2 = (T *)take(sizeof(T) * nf * N);
     const int percell = H != nullptr;
-    double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : 1));
+    double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : nr));
     T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 2 * N);
+    // uniform grid: double H for the own-cell integrals, per cell or per ring,
+    // in the partial-sum buffer (at least nf N doubles; written before the sum)
+    double *Hd = (double *)partial;
     double *dh = (double *)take(sizeof(double) * 4);
     double2 *ipart = (double2 *)take(sizeof(double2) * (SG_IND_BLOCKS + 1));
     double2 *iab = ipart + SG_IND_BLOCKS;
@@ -401,14 +438,19 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
         if (nb > 65536) nb = 65536;
         hipLaunchKernelGGL(k_direct_prep<T>, dim3((unsigned)nb), dim3(256), 0, s, nr, nphi, nf,
                            lnrmin, du, dphi, (const double *)dh, sigma, H, rrow, sx, ex, sph, snp,
-                           mass, H2);
+                           mass, H2, lin, g->r_min, dr, Hd);
         SG_HIP(hipGetLastError());
     }
     const int with_self = !(flags & SG_SELF_CELL_EXCLUDE);
     if (with_self) {
         GLNodes gl;
         sg_gl_nodes(gl);
-        if (percell) {
+        if (lin) {
+            const int per = percell ? nphi : 1;
+            const int64_t items = (int64_t)nf * nf * nr * per;
+            hipLaunchKernelGGL(k_ss_self_lin, dim3((unsigned)items), dim3(256), 0, s, (const double *)Hd, nf, nr,
+                               per, g->r_min, dr, dphi, 0, 0, self, gl);
+        } else if (percell) {
             const int64_t items = (int64_t)nf * nf * N;
             hipLaunchKernelGGL(k_self_cell_percell<T>, dim3((unsigned)items), dim3(256), 0, s, H, nf,
                                nr, nphi, lnrmin, du, dphi, self, gl);
@@ -429,7 +471,7 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
         int64_t nb = (nf * N + 255) / 256;
         if (nb > SG_IND_BLOCKS) nb = SG_IND_BLOCKS;
         hipLaunchKernelGGL(k_indirect_part<T>, dim3((unsigned)nb), dim3(256), 0, s, nr, nphi, nf, lnrmin,
-                           du, dphi, (const double *)dh, sigma, H, ipart);
+                           du, dphi, (const double *)dh, sigma, H, ipart, lin, g->r_min, dr);
         hipLaunchKernelGGL(k_indirect_fin, dim3(1), dim3(64), 0, s, (const double2 *)ipart, (int)nb, iab);
         SG_HIP(hipGetLastError());
     }
@@ -437,6 +479,7 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     A.nr = nr;
     A.nphi = nphi;
     A.rps = rps;
+    A.lin = lin;
     A.N = N;
     A.rrow = rrow;
     A.sx = sx;
@@ -456,9 +499,10 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     SG_HIP(hipGetLastError());
     const unsigned nb = (unsigned)((N + 255) / 256);
     const double2 *indp = ind ? (const double2 *)iab : nullptr;
+    const int smode = percell ? 1 : (lin ? 2 : 0);
 #define SG_RED(NF)                                                                                      \
-    hipLaunchKernelGGL((k_direct_reduce<T, NF>), dim3(nb), dim3(256), 0, s, partial, S, N, self, percell,  \
-                       with_self, sigma, du * dphi, indp, nphi, gr, gp)
+    hipLaunchKernelGGL((k_direct_reduce<T, NF>), dim3(nb), dim3(256), 0, s, partial, S, N, self, smode,    \
+                       with_self, sigma, du * dphi, indp, nphi, gr, gp, lin, g->r_min, dr)
     switch (nf) {
     case 1: SG_RED(1); break;
     case 2: SG_RED(2); break;
@@ -524,7 +568,7 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
         if (nb > 65536) nb = 65536;
         hipLaunchKernelGGL(k_direct_prep<T>, dim3((unsigned)nb), dim3(256), 0, s, nr, nphi, nf,
                            lnrmin, du, dphi, (const double *)dh, sigma, H, rrow, sx, ex, sph, snp,
-                           mass, H2);
+                           mass, H2, 0, 0.0, 0.0, nullptr);
         SG_HIP(hipGetLastError());
     }
     const int with_self = !(flags & SG_SELF_CELL_EXCLUDE);
@@ -537,6 +581,7 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
         SG_HIP(hipGetLastError());
     }
     DirectArgs<T> A;
+    A.lin = 0;
     A.nr = nr;
     A.nphi = nphi;
     A.rps = rps;

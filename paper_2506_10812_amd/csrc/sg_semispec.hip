@@ -209,20 +209,25 @@ __global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, dou
 // doubled for phi < 0 (both kernels are even in phi).  Output: the table
 // sample I / (wgt dphi) (field, I = int K_r dX dphi) or -I / (wgt dphi)
 // (potential, I = int P dA'), wgt = dr / r; which = 1, 2: the field's
-// derivatives with respect to h_a, h_b instead.
+// derivatives with respect to h_a, h_b instead.  per: cells per ring of H
+// and out (1: one value per ring; n_phi: per cell, for the direct sum with
+// per-cell H), item = pair * n_r * per + cell.
 __global__ void __launch_bounds__(256)
-k_ss_self_lin(const double *H, int nf, int nr, double rmin, double dr, double dphi, int pot, int which,
+k_ss_self_lin(const double *H, int nf, int nr, int per, double rmin, double dr, double dphi, int pot, int which,
               double *out, GLNodes gl)
 {
     __shared__ double wq[FQuad<double>::NODES];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
-    const int item = blockIdx.x;
-    if (item >= nf * nf * nr) return;
-    const int pair = item / nr, ir = item % nr, fa = pair / nf, fb = pair % nf;
+    const int64_t cells = (int64_t)nr * per;
+    const int64_t item = blockIdx.x;
+    if (item >= nf * nf * cells) return;
+    const int pair = (int)(item / cells), fa = pair / nf, fb = pair % nf;
+    const int64_t c = item % cells;
+    const int ir = (int)(c / per);
     const double r = rmin + (ir + 0.5) * dr;
-    const double Ha = H[fa * nr + ir], Hb = H[fb * nr + ir];
+    const double Ha = H[fa * cells + c], Hb = H[fb * cells + c];
     const double ha = Ha / r, hb = Hb / r, Hab = sqrt(0.5 * (Ha * Ha + Hb * Hb));
     const double b = 0.5 * dphi;
     constexpr int NX = SG_PANELS * SG_GLX_N;
@@ -365,7 +370,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
         GLNodes gl;
         sg_gl_nodes(gl);
         if (lin) {
-            hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, grid->r_min, dr,
+            hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1, grid->r_min, dr,
                                dphi, pot ? 1 : 0, 0, self, gl);
         } else if (pot) {
             hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, (const double *)nullptr,
@@ -840,7 +845,7 @@ sg_status sg_ss_grad_run(const sg_disc &d, const double *d_H, const float *lam_r
         for (int which = 1; which <= 2; ++which) {
             double *out = dself + (size_t)(which - 1) * nf * nf * nr;
             if (lin)
-                hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, grid->r_min,
+                hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1, grid->r_min,
                                    A.dr, dphi, 0, which, out, gl);
             else
                 hipLaunchKernelGGL(k_self_cell_ring, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, A.lnrmin,

@@ -28,6 +28,10 @@ sg_status sg_eval_G0_launch(const void *x, void *G, int64_t n, sg_dtype dt, hipS
 
 __global__ void k_twiddles(float2 *tw_u, int nu, float2 *tw_phi, int nphi);
 __global__ void k_self_cell(SelfItems items, double *out, double du, double dphi, GLNodes gl);
+// Own-cell integrals on a uniform radial grid (defined with the semi-spectral
+// path): item = pair * n_r * per + cell, H double [F][n_r * per].
+__global__ void k_ss_self_lin(const double *H, int nf, int nr, int per, double rmin, double dr, double dphi,
+                              int pot, int which, double *out, GLNodes gl);
 __global__ void k_self_cell_ring(const double *H, int nf, int nr, double lnrmin, double du, double dphi, int which,
                                  double *out, GLNodes gl);
 template <typename T>
