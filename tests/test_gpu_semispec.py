@@ -108,6 +108,30 @@ def test_semispectral_wide_grids_sampled(sg, T, W, nr, nphi, nf):
     check(gr, gp, rr, rp, nf, rms=2e-5)
 
 
+def test_semispectral_appD_full_size_sampled(sg, T, W):
+    """The App. D gas disc at its full 1200 x 2048 size, in the launch
+    configuration the benchmark times (banded operators, tuned middle pass),
+    on 24 seeded cells plus the first and last against the pairwise oracle."""
+    say("semi-spectral App. D 1200x2048, tuned, sampled")
+    w = W.flaring()
+    nr, nphi, nf = w["n_r"], w["n_phi"], w["sigma"].shape[0]
+    S = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], nf)
+    S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+    S.refresh(w["H"])
+    S.release_workspace()
+    sg.field_fft_tune([S.disc], S.ws)
+    S.g_r.zero_()
+    S.g_phi.zero_()
+    S.run()
+    torch.cuda.synchronize()
+    cells = W.sample_cells(nr, nphi, 24, seed=12)
+    cells = np.unique(np.concatenate([cells, [0, nr * nphi - 1]]))
+    rr, rp = oracle_field(w, targets=cells)
+    gr = S.g_r.cpu().numpy().astype(np.float64).reshape(nf, -1)[:, cells]
+    gp = S.g_phi.cpu().numpy().astype(np.float64).reshape(nf, -1)[:, cells]
+    check(gr, gp, rr, rp, nf, rms=2e-5)
+
+
 def test_semispectral_equals_fft_path_for_constant_h(sg, T, W):
     """With H_f = h_f r both paths compute the same discrete sum."""
     say("semi-spectral vs FFT path, H = h r")
