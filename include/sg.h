@@ -81,8 +81,9 @@ enum {
  *   K_a(d) = pi^{-1/2} H_a^{-2} (d/4) e^{d^2/4} [K1 - K0](d^2/4),
  *   d_k = r_k / H_a at the source cell,
  * with the cell measure A_k = r_k^2 du dphi.  Accepted by sg_kernel_table
- * (no effect on the table), sg_field_fft and sg_field_direct; sg_field_adjoint
- * returns SG_ERR_UNSUPPORTED for it. */
+ * (no effect on the table), sg_field_fft, sg_field_direct and
+ * sg_field_adjoint (which adds its transpose to dL/dSigma and its h
+ * derivative to dL/dh). */
 
 typedef struct sg_grid {
     int32_t n_r;    /* radial cells                                   */
@@ -379,8 +380,9 @@ sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, 
  * d_dsigma per species [S][n_r][n_phi], each species receiving its
  * group's dL/dSigma (the forward sums a group's species before the
  * transform); d_dh is taken at the group densities, summed in the
- * forward's order.  FFT-path discs with SG_INDIRECT return
- * SG_ERR_UNSUPPORTED.
+ * forward's order.  SG_INDIRECT (FFT path): the transpose of the star's pull
+ * is added to d_dsigma (its coefficient's h_a derivative to d_dh), from two
+ * double reductions over lam and Sigma in a fixed order.
  * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
  * --------------------------------------------------------------------- */
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc);

@@ -22,6 +22,7 @@
 // the phi transforms are those of the FFT-path adjoint.
 #include "sg_adjoint.h"
 #include "sg_fftpath.h"
+#include "sg_kfn.h"
 #include "sg_passes.h"
 
 struct AdjDev {
@@ -354,12 +355,146 @@ __global__ void k_adj_dh_reduce(const double *part, int ncol, int nf, double *dh
 }
 
 // ------------------------------------------------------------------- host
+#define SG_ADJ_IND_BLOCKS 256
+
+// Indirect-term buffers of the FFT-path adjoint: block partials of (L_A, L_B)
+// and their sum, then block partials of the dL/dh sums per fluid.
+static size_t adj_ind_bytes()
+{
+    return sg_align256(sizeof(double2) * (SG_ADJ_IND_BLOCKS + 1)) + sg_align256(sizeof(double) * SG_ADJ_IND_BLOCKS * 2);
+}
+
 static size_t adj_base_bytes(const sg_disc &d)
 {
     const int nf = d.fluids.n_fluids;
     const size_t fs = sg_blk_field_elems(d.grid.n_phi, d.grid.n_r);
     return sg_align256(sizeof(float2) * fs * 2 * nf) + sg_align256(sizeof(float2) * fs * nf) * 2 +
-           sg_align256(sizeof(double) * (d.grid.n_phi / 2 + 1) * nf);
+           sg_align256(sizeof(double) * (d.grid.n_phi / 2 + 1) * nf) + adj_ind_bytes();
+}
+
+// ------------------------------------------------ indirect term, FFT path
+// The forward adds to every target fluid the field of A + i B = sum_a c_a
+// sum_k Sigma_a[k] e^{i phi_k} (c_a in the table header: with H = h r the
+// r_k^2 of the cell measure cancels that of K_a), g_r = -(A cos phi + B sin
+// phi), g_phi = -(-A sin phi + B cos phi).  Its transpose: with
+//   L_A = -sum_{b,i} (lam_r cos phi_i - lam_phi sin phi_i),
+//   L_B = -sum_{b,i} (lam_r sin phi_i + lam_phi cos phi_i),
+// dL/dSigma_a[k] += c_a (L_A cos phi_k + L_B sin phi_k), and dL/dh_a +=
+// c_a' sum_k Sigma_a[k] (L_A cos phi_k + L_B sin phi_k), c_a' the h_a
+// derivative of c_a = sqrt(2) pi^{-1/2} F(x) / (4 h_a^3) du dphi,
+// x = 1/(4 h_a^2): c_a' = sqrt(2) pi^{-1/2} du dphi (-3 F - 2 x F') / (4 h_a^4).
+// Block partials in double are added in a fixed order (deterministic).
+__device__ inline void adj_block_sum2(double &a, double &b, double *ra, double *rb)
+{
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            ra[threadIdx.x] += ra[threadIdx.x + o];
+            rb[threadIdx.x] += rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    a = ra[0];
+    b = rb[0];
+}
+
+__global__ void __launch_bounds__(256) k_adj_ind_lam(const float *lr, const float *lp, int64_t n, int nphi,
+                                                     double2 *part)
+{
+    __shared__ double ra[256], rb[256];
+    const double dphi = 2.0 * SG_PI / nphi;
+    double la = 0.0, lb = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        double sp, cp;
+        sincos(((double)(k % nphi) + 0.5) * dphi, &sp, &cp);
+        const double r = lr[k], p = lp[k];
+        la -= r * cp - p * sp;
+        lb -= r * sp + p * cp;
+    }
+    adj_block_sum2(la, lb, ra, rb);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(la, lb);
+}
+
+__global__ void k_adj_ind_fin(const double2 *part, int nb, double2 *out)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        a += part[i].x;
+        b += part[i].y;
+    }
+    *out = make_double2(a, b);
+}
+
+// dsig[a][k] += c_a (L_A cos phi_k + L_B sin phi_k); with want_dh the block
+// partials of sum_k Sigma_a[k] (L_A cos phi_k + L_B sin phi_k) per fluid.
+__global__ void __launch_bounds__(256) k_adj_ind_sig(const sg_table_header *hd, const double2 *LAB,
+                                                     const float *sig, float *dsig, int nf, int64_t N, int nphi,
+                                                     int want_dh, double *spart)
+{
+    __shared__ double ra[256], rb[256];
+    const double dphi = 2.0 * SG_PI / nphi;
+    const double2 L = *LAB;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < nf * N; k += (int64_t)gridDim.x * 256) {
+        const int a = (int)(k / N);
+        double sp, cp;
+        sincos(((double)((k % N) % nphi) + 0.5) * dphi, &sp, &cp);
+        const double cs = L.x * cp + L.y * sp;
+        dsig[k] += (float)(hd->ind_coef[a] * cs);
+        if (want_dh) {
+            if (a == 0) s0 += (double)sig[k] * cs;
+            else s1 += (double)sig[k] * cs;
+        }
+    }
+    if (!want_dh) return;  // uniform across the launch
+    adj_block_sum2(s0, s1, ra, rb);
+    if (threadIdx.x == 0) {
+        spart[2 * blockIdx.x] = s0;
+        spart[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+__global__ void k_adj_ind_dh(const sg_table_header *hd, const double *spart, int nb, int nf, double *dh)
+{
+    if (threadIdx.x != 0) return;
+    double w[FQuad<double>::NODES];
+    for (int k = 0; k < FQuad<double>::NODES; ++k) {
+        const double v = (k + 1) * FQuad<double>::STEP;
+        w[k] = exp(-v * v);
+    }
+    const double du = log(hd->r_max / hd->r_min) / hd->n_r, dphi = 2.0 * SG_PI / hd->n_phi;
+    for (int a = 0; a < nf; ++a) {
+        double S = 0.0;
+        for (int b = 0; b < nb; ++b) S += spart[2 * b + a];
+        const double h = hd->h[a], x = 0.25 / (h * h);
+        double F, dF;
+        sg_F64_dF(x, w, F, dF);
+        const double cp = SG_SQRT2 / SG_SQRT_PI * du * dphi * (-3.0 * F - 2.0 * x * dF) / (4.0 * h * h * h * h);
+        dh[a] += cp * S;
+    }
+}
+
+static sg_status adjoint_indirect(const sg_disc &d, const float *lam_r, const float *lam_p, float *dsig,
+                                  double *dh, char *buf, hipStream_t s)
+{
+    const int nf = d.fluids.n_fluids;
+    const int64_t N = (int64_t)d.grid.n_r * d.grid.n_phi;
+    double2 *part = (double2 *)buf;
+    double2 *lab = part + SG_ADJ_IND_BLOCKS;
+    double *spart = (double *)(buf + sg_align256(sizeof(double2) * (SG_ADJ_IND_BLOCKS + 1)));
+    const sg_table_header *hd = (const sg_table_header *)d.table;
+    int64_t nb = (nf * N + 255) / 256;
+    if (nb > SG_ADJ_IND_BLOCKS) nb = SG_ADJ_IND_BLOCKS;
+    hipLaunchKernelGGL(k_adj_ind_lam, dim3((unsigned)nb), dim3(256), 0, s, lam_r, lam_p, nf * N, d.grid.n_phi, part);
+    hipLaunchKernelGGL(k_adj_ind_fin, dim3(1), dim3(64), 0, s, (const double2 *)part, (int)nb, lab);
+    hipLaunchKernelGGL(k_adj_ind_sig, dim3((unsigned)nb), dim3(256), 0, s, hd, (const double2 *)lab, d.sigma, dsig,
+                       nf, N, d.grid.n_phi, dh ? 1 : 0, spart);
+    if (dh) hipLaunchKernelGGL(k_adj_ind_dh, dim3(1), dim3(64), 0, s, hd, (const double *)spart, (int)nb, nf, dh);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
 }
 
 // Species discs add the group densities and the group dL/dSigma after the
@@ -613,7 +748,10 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
     o += sg_align256(sizeof(float2) * fs * nf);
     A.part = (double *)o;
     const int ncol = nphi / 2 + 1;
+    o += sg_align256(sizeof(double) * ncol * nf);
     const bool want_dh = dh != nullptr;
-    if (nf == 1) return adj_phi<1>(nphi, 2 * nr, A, want_dh, dh, ncol, s);
-    return adj_phi<2>(nphi, 2 * nr, A, want_dh, dh, ncol, s);
+    const sg_status st = nf == 1 ? adj_phi<1>(nphi, 2 * nr, A, want_dh, dh, ncol, s)
+                                 : adj_phi<2>(nphi, 2 * nr, A, want_dh, dh, ncol, s);
+    if (st != SG_OK || !(d.flags & SG_INDIRECT)) return st;
+    return adjoint_indirect(d, lam_r, lam_p, dsig, dh, o, s);
 }

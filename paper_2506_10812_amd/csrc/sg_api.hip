@@ -296,7 +296,6 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     if (disc->flags & SG_SEMI_SPECTRAL) {
         if (d_dh) return SG_ERR_UNSUPPORTED;  // dL/dSigma only
     } else {
-        if (disc->flags & SG_INDIRECT) return SG_ERR_UNSUPPORTED;
         if (d_dh && !(disc->flags & SG_WITH_DH)) return SG_ERR_TABLE;
     }
     if (!d_ws || ws_bytes < sg_adjoint_ws_bytes(*disc) || ((uintptr_t)d_ws & 255))

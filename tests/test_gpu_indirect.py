@@ -1,7 +1,7 @@
 """The indirect term (SG_INDIRECT) through the C ABI against the CPU FP64
 oracle: FFT path (float, 1e-5 relative RMS per fluid and component, and the
 indirect part alone to 1e-5), direct path in double (1e-12 of max |g|) and in
-float, general per-cell H, and the adjoint's refusal."""
+float, general per-cell H, and the FFT-path adjoint with the term."""
 import numpy as np
 import pytest
 
@@ -107,15 +107,56 @@ def test_direct_indirect_general_H(sg, T, dtype):
         assert err < tol, (b, err)
 
 
-def test_adjoint_refuses_indirect(sg, T, W):
-    w = W.adjoint(n_r=8, n_phi=16)
-    g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
-    f = sg.fluids(w["h"])
-    tab = T.build_table(g, f, sg.WITH_DH | sg.INDIRECT)
-    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda")
-    lam = torch.ones_like(sig)
-    ds = torch.empty_like(sig)
-    disc = sg.make_disc(g, f, sg.WITH_DH | sg.INDIRECT, sig, lam, lam, tab)
-    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
-    with pytest.raises(sg.SGError):
-        sg.field_adjoint(disc, lam, lam, ds, None, ws)
+def test_adjoint_with_indirect(sg, T, W):
+    """FFT-path adjoint with SG_INDIRECT: the transpose identity
+    <lam, g(Sigma)> = <dL/dSigma, Sigma> (the forward is pinned above),
+    dL/dSigma at sampled cells against the oracle's L = <lam, g + g_ind>
+    differenced in Sigma (exact: L is linear in Sigma), and dL/dh against
+    central differences of that L in h (eps = 1e-4 h; 1e-4 relative)."""
+    print("adjoint with the indirect term, fft path 32x64 nf=2", flush=True)
+    w = _lopsided(W.adjoint(n_r=32, n_phi=64), 21)
+    nr, nphi, rmin, rmax, h = w["n_r"], w["n_phi"], w["r_min"], w["r_max"], list(w["h"])
+    F = T.FFTField([w], flags=sg.WITH_DH | sg.INDIRECT)
+    F.set_sigma(0, w["sigma"])
+    F.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(22)
+    lr = rng.standard_normal((2, nr, nphi)).astype(np.float32)
+    lp = rng.standard_normal((2, nr, nphi)).astype(np.float32)
+    lr_t, lp_t = torch.tensor(lr).cuda(), torch.tensor(lp).cuda()
+    ds = torch.empty_like(F.sigma[0])
+    dh = torch.empty(2, dtype=torch.float64, device="cuda")
+    ws = torch.empty(sg.field_adjoint_workspace_bytes(F.discs[0]), dtype=torch.uint8, device="cuda")
+    sg.field_adjoint(F.discs[0], lr_t, lp_t, ds, dh, ws)
+    torch.cuda.synchronize()
+    lhs = float((lr_t.double() * F.g_r[0].double()).sum() + (lp_t.double() * F.g_phi[0].double()).sum())
+    rhs = float((ds.double() * F.sigma[0].double()).sum())
+    print(f"  <lam, g> {lhs:.8e}  <dL/dSigma, Sigma> {rhs:.8e}", flush=True)
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+    sig = F.sigma[0].double().cpu().numpy()
+    lr64, lp64 = lr.astype(np.float64).reshape(2, -1), lp.astype(np.float64).reshape(2, -1)
+
+    def L(sigma, hh):
+        gr, gp = O.field_table(nr, nphi, rmin, rmax, hh, sigma)
+        ir, ip = O.indirect_field(nr, nphi, O.indirect(nr, nphi, rmin, rmax, hh, sigma))
+        return float(np.sum(lr64 * (gr + ir[None, :])) + np.sum(lp64 * (gp + ip[None, :])))
+
+    L0 = L(sig, h)
+    dsn = ds.double().cpu().numpy()
+    scale = np.abs(dsn).max()
+    for a, k in [(0, 0), (1, 5), (0, 777), (1, nr * nphi - 1), (0, 1500), (1, 1234)]:
+        sp = sig.copy()
+        sp.reshape(2, -1)[a, k] += 1.0
+        want = L(sp, h) - L0
+        got = dsn.reshape(2, -1)[a, k]
+        print(f"  dL/dSigma[{a}][{k}] {got:.6e} oracle {want:.6e}", flush=True)
+        assert abs(got - want) < 1e-5 * scale, (a, k, got, want)
+    dhn = dh.cpu().numpy()
+    for a in range(2):
+        e = 1e-4 * h[a]
+        hp_, hm_ = list(h), list(h)
+        hp_[a] += e
+        hm_[a] -= e
+        want = (L(sig, hp_) - L(sig, hm_)) / (2 * e)
+        print(f"  dL/dh[{a}] {dhn[a]:.8e} oracle {want:.8e}", flush=True)
+        assert abs(dhn[a] - want) < 1e-4 * abs(want), (a, dhn[a], want)
