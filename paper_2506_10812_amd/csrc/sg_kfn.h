@@ -256,6 +256,29 @@ __device__ inline void sg_conv_kernel64(double X, double sphi_half, double sphi,
     Kp = dK * dh2 * sphi;
 }
 
+// Both h derivatives at once (one F, F' evaluation): (Kr1, Kp1) = d/dh_a,
+// (Kr2, Kp2) = d/dh_b, as sg_conv_kernel64 with which = 1 and 2.
+__device__ inline void sg_conv_kernel64_dh(double X, double sphi_half, double sphi, double ha, double hb,
+                                           const double *w, double &Kr1, double &Kp1, double &Kr2, double &Kp2)
+{
+    const double eX = exp(X);
+    const double h2 = 0.5 * (ha * ha / eX + hb * hb * eX);
+    const double sxh = sinh(0.5 * X);
+    const double two_s2 = 2.0 * sphi_half * sphi_half;
+    const double cmc = 2.0 * sxh * sxh + two_s2;
+    const double emc = expm1(X) + two_s2;
+    const double x = cmc / (4.0 * h2);
+    const double G = exp(-1.5 * X) * (1.0 / (8.0 * SG_SQRT_PI));
+    double F, dF;
+    sg_F64_dF(x, w, F, dF);
+    const double dK = G / (h2 * h2 * sqrt(h2)) * (-x * dF - 1.5 * F);
+    const double d1 = dK * (ha / eX), d2 = dK * (hb * eX);
+    Kr1 = d1 * emc;
+    Kp1 = d1 * sphi;
+    Kr2 = d2 * emc;
+    Kp2 = d2 * sphi;
+}
+
 // X-symmetrised radial kernel used by the self-cell average.
 __device__ inline double sg_sym_kr64(double X, double phi, double ha, double hb, int which,
                                      const double *w)

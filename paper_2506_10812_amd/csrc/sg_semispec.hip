@@ -691,18 +691,39 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
     const double scale = -(A.lin ? A.dr / rp : A.du) * A.dphi / N;
     const uint32_t fs = (uint32_t)sg_blk_field_elems(N, A.nr);
     __syncthreads();
+    // both derivatives are sampled in one sweep (one F, F' evaluation per
+    // azimuth): d/dh_a goes to the plane, d/dh_b waits in registers (a thread
+    // holds at most P/2 + 1 of the N/2 + 1 azimuths)
+    constexpr int Q = P / 2 + 1;
+    double2 keep[Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        const int q = t + T * u;
+        if (q > N / 2) break;
+        double kr1 = 0.0, kp1 = 0.0, kr2 = 0.0, kp2 = 0.0;
+        if (ic == ip && q == 0) {
+            if (!A.excl) {
+                const size_t o = (size_t)(a * A.nf + b) * A.nr + ic, wst = (size_t)A.nf * A.nf * A.nr;
+                kr1 = dself[o];
+                kr2 = dself[wst + o];
+            }
+        } else {
+            sg_conv_kernel64_dh(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, wq, kr1, kp1, kr2, kp2);
+        }
+        keep[u] = make_double2(kr2, kp2);
+        pl.st(q, make_double2(kr1, kp1));
+        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr1, -kp1));
+    }
     double part[2] = {0.0, 0.0};
     for (int which = 1; which <= 2; ++which) {
-#pragma unroll 1
-        for (int q = t; q <= N / 2; q += T) {
-            double kr = 0.0, kp = 0.0;
-            if (ic == ip && q == 0) {
-                kr = A.excl ? 0.0 : dself[(size_t)(which - 1) * A.nf * A.nf * A.nr + (size_t)(a * A.nf + b) * A.nr + ic];
-            } else {
-                sg_conv_kernel64(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, which, wq, kr, kp);
+        if (which == 2) {
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const int q = t + T * u;
+                if (q > N / 2) break;
+                pl.st(q, keep[u]);
+                if (q != 0 && q != N / 2) pl.st(N - q, make_double2(keep[u].x, -keep[u].y));
             }
-            pl.st(q, make_double2(kr, kp));
-            if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
         }
         __syncthreads();
         double2 z[P];
