@@ -7,7 +7,7 @@ import torch
 
 import ctypes
 
-from . import (F32, F64, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, Fluids, field_adjoint,
+from . import (F32, F64, INDIRECT, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, Fluids, field_adjoint,
                field_adjoint_workspace_bytes, field_fft_tune, potential_direct,
                potential_direct_workspace_bytes, field_direct, field_direct_workspace_bytes, field_fft,
                field_fft_workspace_bytes, fluids, grid, kernel_table, kernel_table_bytes,
@@ -162,17 +162,17 @@ _cache = _TableCache()
 
 
 class SGField(torch.autograd.Function):
-    """g_r, g_phi = SGField.apply(sigma, h, n_r, n_phi, r_min, r_max).
+    """g_r, g_phi = SGField.apply(sigma, h, n_r, n_phi, r_min, r_max[, indirect]).
 
     sigma: float32 CUDA tensor [F][n_r][n_phi]; h: float64 tensor [F] of
-    aspect ratios.  Forward: sg_field_fft.  Backward: sg_field_adjoint
-    (dL/dSigma and dL/dh)."""
+    aspect ratios; indirect: add the indirect term.  Forward: sg_field_fft.
+    Backward: sg_field_adjoint (dL/dSigma and dL/dh)."""
 
     @staticmethod
-    def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max):
+    def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max, indirect=False):
         g = grid(n_r, n_phi, r_min, r_max)
         hs = [float(v) for v in h.detach().cpu().tolist()]
-        flags = WITH_DH
+        flags = WITH_DH | (INDIRECT if indirect else 0)
         table = _cache.get(g, hs, flags, sigma.device)
         sigma_c = sigma.detach().contiguous().to(torch.float32)
         gr = torch.empty_like(sigma_c)
@@ -182,13 +182,13 @@ class SGField(torch.autograd.Function):
         ws = torch.empty(field_fft_workspace_bytes([disc]), dtype=torch.uint8, device=sigma.device)
         field_fft([disc], ws)
         ctx.save_for_backward(sigma_c, table)
-        ctx.meta = (g, hs, flags)
+        ctx.meta = (g, hs, flags, h.device, h.dtype, sigma.dtype)
         return gr, gp
 
     @staticmethod
     def backward(ctx, lam_r, lam_phi):
         sigma_c, table = ctx.saved_tensors
-        g, hs, flags = ctx.meta
+        g, hs, flags, h_device, h_dtype, s_dtype = ctx.meta
         f = fluids(hs)
         lam_r = (lam_r if lam_r is not None else torch.zeros_like(sigma_c)).contiguous().float()
         lam_phi = (lam_phi if lam_phi is not None else torch.zeros_like(sigma_c)).contiguous().float()
@@ -198,4 +198,5 @@ class SGField(torch.autograd.Function):
         ws = torch.empty(field_adjoint_workspace_bytes(disc), dtype=torch.uint8,
                          device=sigma_c.device)
         field_adjoint(disc, lam_r, lam_phi, dsig, dh, ws)
-        return dsig, dh, None, None, None, None
+        # gradients in the dtype (and, for h, the device) of the inputs
+        return dsig.to(s_dtype), dh.to(device=h_device, dtype=h_dtype), None, None, None, None, None

@@ -151,6 +151,14 @@ def test_adjoint_with_indirect(sg, T, W):
         got = dsn.reshape(2, -1)[a, k]
         print(f"  dL/dSigma[{a}][{k}] {got:.6e} oracle {want:.6e}", flush=True)
         assert abs(got - want) < 1e-5 * scale, (a, k, got, want)
+    # the autograd function with indirect=True runs the same adjoint
+    sg_t = F.sigma[0].clone().requires_grad_(True)
+    h_t = torch.tensor(h, dtype=torch.float64, requires_grad=True)
+    gr_t, gp_t = T.SGField.apply(sg_t, h_t, nr, nphi, rmin, rmax, True)
+    ((gr_t.double() * lr_t.double()).sum() + (gp_t.double() * lp_t.double()).sum()).backward()
+    assert torch.equal(gr_t, F.g_r[0]) and torch.equal(gp_t, F.g_phi[0])
+    assert torch.equal(sg_t.grad, ds)
+    assert torch.allclose(h_t.grad, dh.cpu(), rtol=1e-12, atol=0)
     dhn = dh.cpu().numpy()
     for a in range(2):
         e = 1e-4 * h[a]
