@@ -402,9 +402,10 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
  * the phi spectra of lam and Sigma, mode by mode, in double; the derivative
  * operators are sampled and transformed on the fly and never stored, so a
  * call costs about twice a table build.  d_H: the H the disc's table was
- * built from.  disc->table supplies the phi twiddles only.  Discs without
- * SG_SEMI_SPECTRAL, with SG_POTENTIAL or with n_species > 0 return
- * SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
+ * built from.  disc->table supplies the phi twiddles only.  Species discs
+ * (n_species > 0): the derivative at the group densities, summed in the
+ * forward's order.  Discs without SG_SEMI_SPECTRAL, or with SG_POTENTIAL,
+ * return SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
  * 256-byte aligned.  Asynchronous; the result is summed with device
  * atomics, so its last bits vary from call to call.
  * --------------------------------------------------------------------- */

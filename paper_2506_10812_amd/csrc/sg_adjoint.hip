@@ -537,6 +537,28 @@ __global__ void k_species_bcast(const float *gds, SpeciesMap M, size_t cells, fl
     dsig[k] = gds[(size_t)M.group[s] * cells + k % cells];
 }
 
+static SpeciesMap species_map(const sg_disc &d)
+{
+    SpeciesMap M{};
+    M.ns = d.n_species;
+    M.nf = d.fluids.n_fluids;
+    for (int sp = 0; sp < d.n_species; ++sp) {
+        const int g = d.species_group[sp];
+        M.group[sp] = (uint8_t)g;
+        M.gsp[g][M.gcount[g]++] = (uint8_t)sp;
+    }
+    return M;
+}
+
+sg_status sg_species_group_sums(const sg_disc &d, float *gsig, hipStream_t s)
+{
+    const size_t cells = (size_t)d.grid.n_r * d.grid.n_phi, n = (size_t)d.fluids.n_fluids * cells;
+    hipLaunchKernelGGL(k_species_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.sigma, species_map(d),
+                       cells, gsig);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
 static sg_status adjoint_species(const sg_disc &d, const float *lam_r, const float *lam_p, float *dsig,
                                  double *dh, void *ws, hipStream_t s)
 {
@@ -545,14 +567,7 @@ static sg_status adjoint_species(const sg_disc &d, const float *lam_r, const flo
     char *extra = (char *)ws + adj_base_bytes(d);
     float *gsig = (float *)extra;
     float *gds = (float *)(extra + sg_align256(sizeof(float) * nf * cells));
-    SpeciesMap M{};
-    M.ns = d.n_species;
-    M.nf = nf;
-    for (int sp = 0; sp < d.n_species; ++sp) {
-        const int g = d.species_group[sp];
-        M.group[sp] = (uint8_t)g;
-        M.gsp[g][M.gcount[g]++] = (uint8_t)sp;
-    }
+    const SpeciesMap M = species_map(d);
     sg_disc g = d;
     g.n_species = 0;
     g.sigma = gsig;

@@ -305,14 +305,22 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
 
 static bool ss_grad_ok(const sg_disc *d)
 {
-    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL) && !(d->flags & SG_POTENTIAL) &&
-           d->n_species == 0;
+    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL) && !(d->flags & SG_POTENTIAL);
+}
+
+// species discs also hold their group densities
+static size_t ss_grad_bytes(const sg_disc &d)
+{
+    const int nr = d.grid.n_r, nphi = d.grid.n_phi, nf = d.fluids.n_fluids;
+    size_t b = sg_ss_grad_ws_bytes(nr, nphi, nf);
+    if (d.n_species) b += sg_align256(sizeof(float) * nf * (size_t)nr * nphi);
+    return b;
 }
 
 size_t sg_ss_grad_H_workspace_bytes(const sg_disc *disc)
 {
     if (!ss_grad_ok(disc)) return 0;
-    return sg_ss_grad_ws_bytes(disc->grid.n_r, disc->grid.n_phi, disc->fluids.n_fluids);
+    return ss_grad_bytes(*disc);
 }
 
 sg_status sg_ss_grad_H(const sg_disc *disc, const double *d_H, const float *d_lam_r, const float *d_lam_phi,
@@ -323,7 +331,7 @@ sg_status sg_ss_grad_H(const sg_disc *disc, const double *d_H, const float *d_la
     if (s != SG_OK) return s;
     if (!d_H || !d_lam_r || !d_lam_phi || !d_dH) return SG_ERR_ARG;
     if (!ss_grad_ok(disc)) return SG_ERR_UNSUPPORTED;
-    const size_t need = sg_ss_grad_ws_bytes(disc->grid.n_r, disc->grid.n_phi, disc->fluids.n_fluids);
+    const size_t need = ss_grad_bytes(*disc);
     if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
     return sg_ss_grad_run(*disc, d_H, d_lam_r, d_lam_phi, d_dH, d_ws, (hipStream_t)stream);
 }

@@ -45,6 +45,7 @@
 // of the FFT path (phi transforms), and k_ss_pass in place of pass 2.
 #include "sg_kfn.h"
 #include "sg_semispec.h"
+#include "sg_adjoint.h"
 #include "sg_table.h"
 
 // ------------------------------------------------------------ table: rows
@@ -831,9 +832,19 @@ static void launch_ssg(const double *H, const double *dself, const SsRowArgs &A,
     }
 }
 
-sg_status sg_ss_grad_run(const sg_disc &d, const double *d_H, const float *lam_r, const float *lam_p, double *dH,
+sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_r, const float *lam_p, double *dH,
                          void *d_ws, hipStream_t s)
 {
+    // species discs: the derivative of the group disc at the group sums
+    // (placed after the gradient's own workspace)
+    sg_disc d = d0;
+    if (d0.n_species) {
+        float *gsig = (float *)((char *)d_ws + sg_ss_grad_ws_bytes(d0.grid.n_r, d0.grid.n_phi, d0.fluids.n_fluids));
+        const sg_status st = sg_species_group_sums(d0, gsig, s);
+        if (st != SG_OK) return st;
+        d.n_species = 0;
+        d.sigma = gsig;
+    }
     const sg_grid *grid = &d.grid;
     const int nr = grid->n_r, nphi = grid->n_phi, nf = d.fluids.n_fluids;
     const uint32_t flags = d.flags;

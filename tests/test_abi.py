@@ -191,10 +191,12 @@ def test_semispectral_sizes_and_validation(sg):
     assert sg.ss_grad_H_workspace_bytes(fft) == 0
     assert G(ctypes.byref(fft), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED
     d.flags = sg.SEMI_SPECTRAL
+    base = sg.ss_grad_H_workspace_bytes(d)
     d.n_species = 2
     d.species_group[0], d.species_group[1] = 0, 1
     assert sg.field_fft_workspace_bytes([d]) > 0
-    assert sg.ss_grad_H_workspace_bytes(d) == 0
+    # species discs add their group densities (2 x 37 x 32 floats, 256-aligned)
+    assert sg.ss_grad_H_workspace_bytes(d) == base + (2 * 37 * 32 * 4 + 255) // 256 * 256
 
 
 def test_struct_layouts_match_the_header(sg, tmp_path):

@@ -172,8 +172,43 @@ def test_ss_grad_directional_full_size(sg, T, W):
     assert abs(got - fd) < 2e-3 * abs(fd)
 
 
+def test_ss_grad_species_equals_group_disc(sg, T, W):
+    """A species disc's dL/dH is that of the disc of its group sums (formed in
+    the forward's order; only the atomics' summation order differs)."""
+    groups = (0, 1, 1, 0)
+    nr, nphi = 11, 16
+    say(f"semi-spectral dL/dH species {groups} {nr}x{nphi}")
+    w = W.flaring(seed=5, n_r=nr, n_phi=nphi, p=0.25, n_fluids=2)
+    rng = np.random.default_rng(6)
+    sig = np.zeros((len(groups), nr, nphi), dtype=np.float32)
+    for gi in range(2):
+        members = [s for s, g in enumerate(groups) if g == gi]
+        wts = rng.uniform(0.2, 1.0, (len(members), nr, nphi))
+        wts /= wts.sum(axis=0)
+        for k, s in enumerate(members):
+            sig[s] = (w["sigma"][gi] * wts[k]).astype(np.float32)
+    sums = np.zeros((2, nr, nphi), dtype=np.float32)
+    for s, g in enumerate(groups):
+        sums[g] = sums[g] + sig[s]
+    lr, lp = lams((2, nr, nphi), 9)
+    H = torch.tensor(w["H"], dtype=torch.float64, device="cuda")
+    out = []
+    for species, sigma in ((groups, sig), (None, sums)):
+        S = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], 2, 0, species_group=species)
+        S.refresh(w["H"])
+        S.sigma.copy_(torch.tensor(sigma))
+        dH = torch.empty_like(H)
+        ws = torch.empty(sg.ss_grad_H_workspace_bytes(S.disc), dtype=torch.uint8, device="cuda")
+        sg.ss_grad_H(S.disc, H, torch.tensor(lr).cuda(), torch.tensor(lp).cuda(), dH, ws)
+        torch.cuda.synchronize()
+        out.append(dH.cpu().numpy())
+    err = float(np.abs(out[0] - out[1]).max() / np.abs(out[1]).max())
+    say(f"  max/max|dL/dH| {err:.2e}")
+    assert err < 1e-12
+
+
 def test_ss_grad_rejects(sg, T, W):
-    """Potential operators, species and FFT-path discs are refused."""
+    """Potential operators and FFT-path discs are refused."""
     w = W.flaring(seed=2, n_r=8, n_phi=8, p=0.25, n_fluids=1)
     S = T.SemiSpectral(8, 8, w["r_min"], w["r_max"], 1, sg.POTENTIAL)
     S.refresh(w["H"])
