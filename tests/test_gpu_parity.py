@@ -284,6 +284,41 @@ def test_fft_path_two_fluid_1024x2048_sampled(sg, T, W):
     say(f"  rel-RMS {_sampled_check(F, 0, w, 4096)}")
 
 
+def test_fft_path_two_fluid_max_grid_sampled(sg, T, W):
+    """The largest grid the FFT path takes (n_r = n_phi = 2048: length-4096
+    radial transforms), two fluids, 256 sampled cells plus the first and last."""
+    w = W.bifluid_fft(seed=77, n_r=2048, n_phi=2048)
+    say("fft path 2048x2048 two fluids, sampled")
+    F = _fft_run(T, W, [w])
+    say(f"  rel-RMS {_sampled_check(F, 0, w, 256)}")
+    nf = 2
+    idx = np.array([0, 2048 * 2048 - 1])
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(2048, 2048, w["r_min"], w["r_max"], w["h"], sig32, targets=idx)
+    gr = F.g_r[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
+    gp = F.g_phi[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
+    scale = float(np.abs(rr).max())
+    assert np.abs(gr - rr).max() < 1e-4 * scale and np.abs(gp - rp).max() < 1e-4 * scale
+
+
+def test_fft_path_max_rows_min_azimuths(sg, T, W):
+    """n_r = 2048 with the fewest azimuths (n_phi = 4), full field.  Four
+    azimuths barely see the spiral, so |g_phi| is 2e-5 of |g_r| here and
+    its own relative error is float rounding at the scale of g_r: g_r is
+    held to 1e-5 rel-RMS, g_phi to 1e-5 of the vector field's RMS."""
+    w = W.single_fft(seed=78, n_r=2048, n_phi=4)
+    say("fft path 2048x4 single fluid, full field")
+    F = _fft_run(T, W, [w])
+    sig32 = torch.tensor(w["sigma"], dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(2048, 4, w["r_min"], w["r_max"], w["h"], sig32)
+    gr = F.g_r[0].double().cpu().numpy().reshape(1, -1)
+    gp = F.g_phi[0].double().cpu().numpy().reshape(1, -1)
+    vec = float(np.sqrt(np.sum(rr ** 2 + rp ** 2)))
+    e_p = float(np.linalg.norm(gp[0] - rp[0])) / vec
+    say(f"  rel-RMS g_r {rel_rms(gr[0], rr[0]):.2e}; g_phi error / |g| {e_p:.2e}")
+    assert rel_rms(gr[0], rr[0]) < 1e-5 and e_p < 1e-5
+
+
 def test_fft_batch64_equals_single_disc_runs_and_oracle(sg, T, W):
     discs = W.batch64()
     say("fft path batch of 64 uneven discs")
