@@ -93,9 +93,9 @@ typedef struct sg_grid {
 } sg_grid;
 
 typedef struct sg_fluids {
-    int32_t n_fluids; /* 1 (gas) or 2 (gas + dust)                         */
+    int32_t n_fluids; /* 1 to 4 scale-height groups (1: gas, 2: gas + dust) */
     int32_t pad_;
-    double h[2];      /* aspect ratios h_f = H_f / r (constant per fluid)  */
+    double h[4];      /* aspect ratios h_f = H_f / r (constant per fluid)  */
 } sg_fluids;
 
 /* ---------------------------------------------------------------------

@@ -38,7 +38,7 @@ class Grid(ctypes.Structure):
 
 class Fluids(ctypes.Structure):
     _fields_ = [("n_fluids", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("h", ctypes.c_double * 2)]
+                ("h", ctypes.c_double * 4)]
 
 
 class Disc(ctypes.Structure):
@@ -60,7 +60,7 @@ def grid(n_r, n_phi, r_min, r_max) -> Grid:
 
 def fluids(h) -> Fluids:
     h = [float(v) for v in (h if hasattr(h, "__len__") else [h])]
-    arr = (ctypes.c_double * 2)(*(h + [0.0] * (2 - len(h))))
+    arr = (ctypes.c_double * 4)(*(h + [0.0] * (4 - len(h))))
     return Fluids(len(h), 0, arr)
 
 

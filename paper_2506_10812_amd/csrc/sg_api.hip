@@ -30,10 +30,17 @@ static sg_status check_fft_grid(const sg_grid *g)
 static sg_status check_fluids(const sg_fluids *f)
 {
     if (!f) return SG_ERR_ARG;
-    if (f->n_fluids < 1 || f->n_fluids > 2) return SG_ERR_ARG;
+    if (f->n_fluids < 1 || f->n_fluids > 4) return SG_ERR_ARG;
     for (int i = 0; i < f->n_fluids; ++i)
         if (!finite_pos(f->h[i])) return SG_ERR_ARG;
     return SG_OK;
+}
+
+// FFT path beyond two groups: a pass-2 column job takes n_fluids x 2 n_r / 8
+// threads, at most 1024, so n_r <= 1024 there.
+static bool fft_groups_ok(const sg_grid *g, const sg_fluids *f)
+{
+    return f->n_fluids <= 2 || g->n_r <= 1024;
 }
 
 static bool flags_ok(uint32_t flags)
@@ -70,12 +77,14 @@ extern "C" {
 size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
 {
     if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
+    if (!fft_groups_ok(grid, fluids)) return 0;
     return sg_table_layout(grid->n_r, grid->n_phi, fluids->n_fluids, flags).total;
 }
 
 size_t sg_kernel_table_workspace_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
 {
     if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
+    if (!fft_groups_ok(grid, fluids)) return 0;
     return sg_table_ws_bytes(grid->n_r, grid->n_phi);
 }
 
@@ -85,6 +94,7 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
     sg_status s = check_fft_grid(grid);
     if (s != SG_OK) return s;
     if ((s = check_fluids(fluids)) != SG_OK) return s;
+    if (!fft_groups_ok(grid, fluids)) return SG_ERR_UNSUPPORTED;
     if (!flags_ok(flags)) return SG_ERR_ARG;
     if (!d_table || ((uintptr_t)d_table & 255)) return SG_ERR_ARG;
     if (!d_ws || ws_bytes < sg_table_ws_bytes(grid->n_r, grid->n_phi) || ((uintptr_t)d_ws & 255))
@@ -144,6 +154,7 @@ static sg_status check_disc(const sg_disc &d)
     sg_status s = check_fft_grid(&d.grid);
     if (s != SG_OK) return s;
     if ((s = check_fluids(&d.fluids)) != SG_OK) return s;
+    if (!fft_groups_ok(&d.grid, &d.fluids)) return SG_ERR_UNSUPPORTED;
     if (!flags_ok(d.flags)) return SG_ERR_ARG;
     if (!d.sigma || !d.g_r || !d.g_phi || !d.table) return SG_ERR_ARG;
     if ((uintptr_t)d.table & 255) return SG_ERR_ARG;
@@ -280,9 +291,15 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
                             flags, d_ws, (hipStream_t)stream);
 }
 
+// the FFT-path adjoint takes one or two groups
+static bool adjoint_groups_ok(const sg_disc &d)
+{
+    return (d.flags & SG_SEMI_SPECTRAL) || d.fluids.n_fluids <= 2;
+}
+
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
 {
-    if (!disc || check_disc(*disc) != SG_OK) return 0;
+    if (!disc || check_disc(*disc) != SG_OK || !adjoint_groups_ok(*disc)) return 0;
     return sg_adjoint_ws_bytes(*disc);
 }
 
@@ -293,6 +310,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
     sg_status s = check_disc(*disc);
     if (s != SG_OK) return s;
     if (!d_lam_r || !d_lam_phi || !d_dsigma) return SG_ERR_ARG;
+    if (!adjoint_groups_ok(*disc)) return SG_ERR_UNSUPPORTED;
     if (disc->flags & SG_SEMI_SPECTRAL) {
         if (d_dh) return SG_ERR_UNSUPPORTED;  // dL/dSigma only
     } else {

@@ -144,26 +144,38 @@ template <int NU, int NF, int GM> struct P2Shape {
 // packed Sigma~[0] + i Sigma~[n_phi/2] in column slot n_phi/2 + 1, and the
 // table holds (K0 + KN)/2 and (K0 - KN)/2 (K_r of the two columns) in that
 // slot's K_r and K_phi places, so the job loads from slot n_phi/2 + 1.
+template <int NU>
+__device__ inline void p2_load_sh(const DiscDev *D, int m, int h, int t, float2 (&sh)[FftShape<NU>::P / 2])
+{
+    constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T, H = P / 2, NR = NU / 2;
+    const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
+#pragma unroll
+    for (int p = 0; p < H; ++p) sh[p] = gld2(D->st, h * fs + (uint32_t)sg_blk_index(m, t + T * p, NR));
+}
+
+// spectra of source a for target h
+template <int NU, int NF>
+__device__ inline void p2_load_k(const DiscDev *D, int m, int a, int h, int t, float2 (&K)[2][FftShape<NU>::P / 2],
+                                 float2 (&KN)[2])
+{
+    constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T, H = P / 2, NR = NU / 2;
+    constexpr uint32_t kk = NR + 1;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        const uint32_t o = (((uint32_t)m * (NF * NF) + a * NF + h) * 2 + cc) * kk;
+#pragma unroll
+        for (int j = 0; j < H; ++j) K[cc][j] = gld2(D->spec, o + t + T * j);
+        KN[cc] = gld2(D->spec, o + NR);
+    }
+}
+
 template <int NU, int NF>
 __device__ inline void p2_issue(const DiscDev *D, int m, int h, int t, float2 (&sh)[FftShape<NU>::P / 2],
                                 float2 (&K)[NF][2][FftShape<NU>::P / 2], float2 (&KN)[NF][2])
 {
-    constexpr int P = FftShape<NU>::P, T = FftShape<NU>::T, H = P / 2, NR = NU / 2;
-    constexpr uint32_t kk = NR + 1;
-    const uint32_t fs = (uint32_t)sg_blk_field_elems(D->nphi, NR);
-    const float2 *st = D->st;
-    const float2 *spec = D->spec;
+    p2_load_sh<NU>(D, m, h, t, sh);
 #pragma unroll
-    for (int p = 0; p < H; ++p) sh[p] = gld2(st, h * fs + (uint32_t)sg_blk_index(m, t + T * p, NR));
-#pragma unroll
-    for (int a = 0; a < NF; ++a)
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const uint32_t o = (((uint32_t)m * (NF * NF) + a * NF + h) * 2 + cc) * kk;
-#pragma unroll
-            for (int j = 0; j < H; ++j) K[a][cc][j] = gld2(spec, o + t + T * j);
-            KN[a][cc] = gld2(spec, o + NR);
-        }
+    for (int a = 0; a < NF; ++a) p2_load_k<NU, NF>(D, m, a, h, t, K[a], KN[a]);
 }
 
 // Pass 2, one column job m in [0, n_phi/2] per group of NF * T threads (half
@@ -202,9 +214,17 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     const DiscDev *D = discs + cd;
     const int m = g < cn ? cb + g : cb;
     const bool pr = m == 0;  // columns 0 and n_phi/2 as one job
-    // 1. loads
-    float2 sh[H], K[NF][2][H], KN[NF][2];
-    p2_issue<NU, NF>(D, pr ? D->nphi / 2 + 1 : m, h, t, sh, K, KN);
+    const int mm = pr ? D->nphi / 2 + 1 : m;
+    // 1. loads (three or four groups: the spectra of one source at a time,
+    //    the next source's loaded while the current one is multiplied)
+    constexpr int KA = NF <= 2 ? NF : 1;
+    float2 sh[H], K[KA][2][H], KN[KA][2];
+    if constexpr (NF <= 2) {
+        p2_issue<NU, NF>(D, mm, h, t, sh, K, KN);
+    } else {
+        p2_load_sh<NU>(D, mm, h, t, sh);
+        p2_load_k<NU, NF>(D, mm, 0, h, t, K[0], KN[0]);
+    }
     TwRegC<NU, SF> tw;
     tw.load(twu, t);
     // SG_INDIRECT: the workgroup holding column m = 1 also forms the star's
@@ -256,6 +276,8 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
         for (int p = 0; p < P; ++p) pl[1].st(t + T * p, v[0][p]);
     }
     __syncthreads();
+    float2 olo[2][H], ohi[2][H];
+    if constexpr (NF <= 2) {
     float2 slo[NF][H], shi[NF][H];
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
@@ -280,7 +302,6 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
     // B is real and each frequency is its own mirror, conj(a1) and
     // -conj(a2)).  Both parts go to plane 0, whose inverse transform is then
     // y = g0 + i gN.
-    float2 olo[2][H], ohi[2][H];
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
@@ -310,6 +331,60 @@ k_pass2(const DiscDev *discs, const WJob *wj, int nj, const float2 *twu, int kc)
             olo[cc][j] = a1;
             ohi[cc][j] = a2;
         }
+    } else {
+        // three or four groups: the same products accumulated source by source
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                olo[cc][j] = make_float2(0.f, 0.f);
+                ohi[cc][j] = make_float2(0.f, 0.f);
+            }
+#pragma unroll
+        for (int a = 0; a < NF; ++a) {
+            float2 Kn[2][H], KNn[2];
+            if (a + 1 < NF) p2_load_k<NU, NF>(D, mm, a + 1, h, t, Kn, KNn);
+            const LdsPlane<float> X{base + W * (2 * a + 1)};
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const bool ny = j == 0 && t == 0;
+                const int klo = t + T * j;
+                const int khi = ny ? NR : NU - klo;
+                const float2 lo = X.ld(klo), hi = X.ld(khi);
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const float2 k1 = K[0][cc][j];
+                    float2 k2 = ny ? KN[0][cc] : k1;
+                    k2 = cc == 0 ? make_float2(k2.x, -k2.y) : make_float2(-k2.x, k2.y);
+                    olo[cc][j].x += k1.x * lo.x - k1.y * lo.y;
+                    olo[cc][j].y += k1.x * lo.y + k1.y * lo.x;
+                    ohi[cc][j].x += k2.x * hi.x - k2.y * hi.y;
+                    ohi[cc][j].y += k2.x * hi.y + k2.y * hi.x;
+                }
+            }
+            if (a + 1 < NF) {
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+                    for (int j = 0; j < H; ++j) K[0][cc][j] = Kn[cc][j];
+                    KN[0][cc] = KNn[cc];
+                }
+            }
+        }
+        if (pr) {
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const bool ny = j == 0 && t == 0;
+                const float2 a1 = olo[1][j], a2 = ohi[1][j];
+                const float2 c1 = make_float2(a1.x, -a1.y), c2 = make_float2(-a2.x, a2.y);
+                olo[0][j] = c_add(olo[0][j], ny ? c1 : c2);
+                ohi[0][j] = c_add(ohi[0][j], ny ? c2 : c1);
+                olo[1][j] = make_float2(0.f, 0.f);
+                ohi[1][j] = make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();  // every target has read the spectrum planes
+    }
     // 4. back to the transform distribution, inverse pair, first n_r outputs
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc)
@@ -443,7 +518,7 @@ template <int N, int NF, bool SF, int GM> static PassKernel pk1()
 template <int N, int NF, bool SF, int GM> static PassKernel pk2()
 {
     using S = P2Shape<N, NF, GM>;
-    if constexpr (S::WGS > 1024) return PassKernel{nullptr, 0, 0, 0};
+    if constexpr (S::WGS > 1024 || (NF > 2 && GM > 1)) return PassKernel{nullptr, 0, 0, 0};
     else return {k_pass2<N, NF, SF, GM>, S::WGS, S::G, S::K};
 }
 template <int N, int NF, bool SF, int GM> static PassKernel pk3()
@@ -463,6 +538,16 @@ template <bool SF, int GM> static PassKernel pick_kernel(int pass, int n, int nf
     if (pass == 1) {
         switch (n) { SG_SIZES(pk1) }
     } else if (pass == 2) {
+        if (nf > 2) {  // three or four groups (passes 1 and 3 do not depend on the count)
+#define SG_CASE34(L) \
+    case L: return nf == 3 ? pk2<L, 3, SF, GM>() : pk2<L, 4, SF, GM>();
+            switch (n) {
+                SG_CASE34(4) SG_CASE34(8) SG_CASE34(16) SG_CASE34(32) SG_CASE34(64) SG_CASE34(128)
+                SG_CASE34(256) SG_CASE34(512) SG_CASE34(1024) SG_CASE34(2048)
+            }
+#undef SG_CASE34
+            return PassKernel{nullptr, 0, 0, 0};
+        }
         switch (n) { SG_SIZES(pk2) SG_CASE(pk2, 4096) }
     } else {
         switch (n) { SG_SIZES(pk3) }

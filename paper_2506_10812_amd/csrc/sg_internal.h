@@ -143,11 +143,11 @@ struct sg_table_header {
     uint32_t magic, version;
     int32_t n_r, n_phi, n_fluids;
     uint32_t flags;
-    double h[2];
+    double h[4];
     double r_min, r_max;
-    double self_r[4];       // self-cell average per pair (double)
-    double dself_r[4][2];   // its d/dh_a, d/dh_b
-    double ind_coef[2];     // indirect term: sqrt(2) K_a A_k / r_k^2 per source fluid
+    double self_r[16];      // self-cell average per pair (double)
+    double dself_r[16][2];  // its d/dh_a, d/dh_b
+    double ind_coef[4];     // indirect term: sqrt(2) K_a A_k / r_k^2 per source fluid
     uint64_t total_bytes;
 };
 

@@ -338,7 +338,7 @@ __global__ void k_header(sg_table_header *hd, sg_table_header proto, const doubl
     }
     const double du = log(proto.r_max / proto.r_min) / proto.n_r;
     const double dphi = 2.0 * SG_PI / proto.n_phi;
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < 4; ++a) {
         h.ind_coef[a] = 0.0;
         if (a < proto.n_fluids) {
             const double ha = proto.h[a];
@@ -590,8 +590,7 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
     proto.n_phi = nphi;
     proto.n_fluids = nf;
     proto.flags = flags;
-    proto.h[0] = fl->h[0];
-    proto.h[1] = nf > 1 ? fl->h[1] : 0.0;
+    for (int a = 0; a < 4; ++a) proto.h[a] = a < nf ? fl->h[a] : 0.0;
     proto.r_min = grid->r_min;
     proto.r_max = grid->r_max;
     proto.total_bytes = L.total;

@@ -99,7 +99,7 @@ class SemiSpectral:
         self.g_r = torch.empty(shape, dtype=torch.float32, device=dev)
         self.g_phi = torch.empty(shape, dtype=torch.float32, device=dev)
         # the fluid count only (up to four groups here; h is not read)
-        fl = Fluids(self.nf, 0, (ctypes.c_double * 2)(0.0, 0.0))
+        fl = Fluids(self.nf, 0, (ctypes.c_double * 4)(0.0, 0.0, 0.0, 0.0))
         self.disc = make_disc(self.g, fl, self.flags | SEMI_SPECTRAL, self.sigma, self.g_r, self.g_phi,
                               self.table, species_group)
         self.ws = torch.empty(max(1, field_fft_workspace_bytes([self.disc])), dtype=torch.uint8,

@@ -284,3 +284,21 @@ def test_semispectral_band_sizes(sg):
     # the App. D gas disc: about a tenth of the full operators
     g = sg.grid(1200, 2048, 20.0, 250.0)
     assert sg.ss_table_bytes(g, 1) < 0.15 * sg.ss_table_bytes(g, 1, sg.SS_FULL)
+
+
+def test_fft_path_group_limits(sg):
+    """One to four scale-height groups on the FFT path; beyond two the column
+    pass needs n_r <= 1024, and the FFT-path adjoint takes one or two."""
+    g = sg.grid(1024, 2048, 0.2, 5.0)
+    nb2 = sg.kernel_table_bytes(g, sg.fluids([0.05, 0.005]), 0)
+    nb4 = sg.kernel_table_bytes(g, sg.fluids([0.05, 0.005, 0.02, 0.01]), 0)
+    assert nb4 > 3.9 * nb2  # 16 ordered pairs against 4
+    assert sg.kernel_table_bytes(sg.grid(2048, 64, 0.2, 5.0), sg.fluids([0.05, 0.005, 0.02]), 0) == 0
+    assert sg.kernel_table_bytes(sg.grid(2048, 64, 0.2, 5.0), sg.fluids([0.05, 0.005]), 0) > 0
+    f5 = sg.Fluids(5, 0, (ctypes.c_double * 4)(0.05, 0.05, 0.05, 0.05))
+    assert sg.kernel_table_bytes(g, f5, 0) == 0
+    d3 = sg.make_disc(sg.grid(16, 32, 0.2, 5.0), sg.fluids([0.05, 0.01, 0.02]), 0, 256, 512, 768, 1024)
+    assert sg.field_fft_workspace_bytes([d3]) > 0
+    assert sg.field_adjoint_workspace_bytes(d3) == 0
+    assert sg.lib().sg_field_adjoint(ctypes.byref(d3), 256, 512, 768, None, 2048, 1 << 30,
+                                     None) == sg.ERR_UNSUPPORTED

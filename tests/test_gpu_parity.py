@@ -186,7 +186,7 @@ def test_kernel_table_matches_numpy_fft_of_oracle_samples(sg, T):
     off_spec = None
     # offsets: header, tw_u (2 nr float2), tw_phi (nphi float2), all 256-aligned
     al = lambda x: (x + 255) // 256 * 256
-    o = al(256)  # header < 256 bytes
+    o = al(496)  # header: 496 bytes (per-pair self terms for up to 16 ordered pairs)
     o = al(o + 8 * 2 * nr)
     o = al(o + 8 * nphi)
     off_spec = o
@@ -540,3 +540,52 @@ def test_direct_fp32_uniform_radial_grid_matches_semispectral(sg, T, W):
         e = (rel_rms(gr[b], rr[b]), rel_rms(gp[b], rp[b]), rel_rms(gr[b], sr[b]), rel_rms(gp[b], sp[b]))
         say(f"  fluid {b}: vs oracle {e[0]:.2e} {e[1]:.2e}; vs semi-spectral {e[2]:.2e} {e[3]:.2e}")
         assert max(e) < 1e-5, e
+
+
+# ------------------------------------------- FFT path, three and four groups
+@pytest.mark.parametrize("nr,nphi,nf,flags", [(8, 16, 3, 0), (32, 64, 4, 0), (16, 32, 3, 4),
+                                              (64, 128, 4, 1), (4, 8, 4, 0)])
+def test_fft_path_three_and_four_groups(sg, T, W, nr, nphi, nf, flags):
+    """All nf^2 ordered pairs fused in the column pass (one source's spectra
+    at a time), with the indirect term or without the own cell, against the
+    oracle's offset-table sum (1e-5 rel-RMS per group and component)."""
+    say(f"fft path {nf} groups {nr}x{nphi} flags={flags}")
+    base = W.bifluid_fft(seed=nr + nf, n_r=nr, n_phi=nphi)
+    rng = np.random.default_rng(nr * nf)
+    h = [0.05, 0.005, 0.02, 0.01][:nf]
+    sig = np.concatenate([base["sigma"], base["sigma"][1:2] * rng.uniform(0.5, 2.0, (nf - 2, nr, nphi))])
+    if flags & 4:
+        phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+        sig = sig * (1 + 0.3 * np.cos(phi - 0.7))[None, None, :]
+    w = dict(base, h=h, sigma=sig)
+    F = _fft_run(T, W, [w], flags=flags)
+    sig32 = torch.tensor(sig, dtype=torch.float32).double().numpy()
+    rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], h, sig32, flags=O.EXCLUDE_SELF if flags & 1 else 0)
+    if flags & 4:
+        ir, ip = O.indirect_field(nr, nphi, O.indirect(nr, nphi, w["r_min"], w["r_max"], h, sig32))
+        rr = rr + ir[None, :]
+        rp = rp + ip[None, :]
+    gr = F.g_r[0].double().cpu().numpy().reshape(nf, -1)
+    gp = F.g_phi[0].double().cpu().numpy().reshape(nf, -1)
+    for b in range(nf):
+        er, ep = rel_rms(gr[b], rr[b]), rel_rms(gp[b], rp[b])
+        say(f"  group {b}: rel-RMS {er:.2e} {ep:.2e}")
+        assert er < 1e-5 and ep < 1e-5, (b, er, ep)
+
+
+def test_fft_path_four_groups_1024x2048_sampled_and_batch(sg, T, W):
+    """Four groups at the headline grid (sampled), and in one batch with a
+    two-group disc (each launch class keyed by its group count): the batch
+    equals the discs run alone."""
+    w2 = W.bifluid_fft()
+    rng = np.random.default_rng(5)
+    sig4 = np.concatenate([w2["sigma"], w2["sigma"][1:2] * rng.uniform(0.5, 2.0, (2, 1024, 2048))])
+    w4 = dict(w2, h=[0.05, 0.005, 0.02, 0.01], sigma=sig4)
+    say("fft path four groups 1024x2048, sampled; batch with a two-group disc")
+    F = _fft_run(T, W, [w4])
+    say(f"  rel-RMS {_sampled_check(F, 0, w4, 256)}")
+    small = W.bifluid_fft(seed=9, n_r=64, n_phi=128)
+    B = _fft_run(T, W, [small, w4])
+    assert torch.equal(B.g_r[1], F.g_r[0]) and torch.equal(B.g_phi[1], F.g_phi[0])
+    S = _fft_run(T, W, [small])
+    assert torch.equal(B.g_r[0], S.g_r[0]) and torch.equal(B.g_phi[0], S.g_phi[0])
