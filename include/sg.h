@@ -20,10 +20,10 @@
  *              phi_j = (j + 1/2) dphi, dphi = 2 pi / n_phi; cell area
  *              A_i = r_i^2 du dphi.
  *   layout     every device array is row-major [fluid][i_r][j_phi] with phi
- *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 or 2
- *              on the FFT path (sg_fluids), 1 to 4 scale-height groups on
- *              the semi-spectral path and in the direct sums and sg_hsg
- *              (the multi-fluid case of Sect. 5.2: all F^2 ordered pairs).
+ *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 to 4
+ *              scale-height groups (the multi-fluid case of Sect. 5.2: all
+ *              F^2 ordered pairs) on every path; on the FFT path beyond two
+ *              groups n_r <= 1024, and its adjoint takes one or two.
  *   pairs      (a -> b) is source fluid a acting on target fluid b; a
  *              two-fluid disc has the four ordered pairs gg, dg, gd, dd
  *              (Sect. 2.2 lists the four combinations).
@@ -113,7 +113,8 @@ typedef struct sg_fluids {
  * dK/dh_a and dK/dh_b for sg_field_adjoint.
  *
  * Requirements: n_r and n_phi powers of two with 2 <= n_r <= 2048 and
- * 4 <= n_phi <= 2048 (SG_ERR_UNSUPPORTED otherwise); h_f > 0.
+ * 4 <= n_phi <= 2048 (SG_ERR_UNSUPPORTED otherwise); h_f > 0; 1 to 4
+ * fluids (n_r <= 1024 for three or four, SG_ERR_UNSUPPORTED otherwise).
  * d_table: device buffer of sg_kernel_table_bytes() bytes, 256-byte aligned,
  * written completely.  d_ws: device scratch of sg_kernel_table_workspace_bytes()
  * bytes, contents undefined afterwards.  Asynchronous on `stream`.
@@ -382,7 +383,8 @@ sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, 
  * transform); d_dh is taken at the group densities, summed in the
  * forward's order.  SG_INDIRECT (FFT path): the transpose of the star's pull
  * is added to d_dsigma (its coefficient's h_a derivative to d_dh), from two
- * double reductions over lam and Sigma in a fixed order.
+ * double reductions over lam and Sigma in a fixed order.  FFT-path discs
+ * with three or four groups return SG_ERR_UNSUPPORTED.
  * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
  * --------------------------------------------------------------------- */
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc);
