@@ -237,8 +237,8 @@ typedef struct sg_disc {
  * sg_field_fft: g_r, g_phi of every disc in `discs` by the zero-padded
  * log-polar FFT convolution (App. C convolution form, Sect. 5.2 zero
  * padding).  Float arithmetic, float accumulation.  All discs of the batch
- * (any mix of supported sizes, one or two fluids, all four ordered pairs
- * fused per spectral point) run in one HIP-graph launch of three passes:
+ * (any mix of supported sizes, one to four fluids, all ordered pairs fused
+ * per spectral point) run in one HIP-graph launch of three passes:
  * phi transform of Sigma, fused u-transform / spectral multiply / inverse
  * u-transform, inverse phi transform.  The graph and a device copy of the
  * batch descriptors are cached per (sizes, pointers) signature on the first
