@@ -12,6 +12,8 @@ precomputes the kernel once per simulation).  Prints one JSON line.
                                         rocprofv3 FETCH_SIZE / WRITE_SIZE)
   python bench.py --semispectral       (only the semi-spectral App. D measurement,
                                         one JSON line; for its kernel trace)
+  python bench.py --direct             (only the direct sums: FP64 64x128 and FP32
+                                        256x512, one JSON line; for their VALU counters)
   python bench.py --summarize-rocprof DIR
         (CPU only) turns the rocprofv3 CSV output of PROFILE_COMMANDS, run
         with DIR as their output root, into the text summaries in profiles/
@@ -52,7 +54,16 @@ PROFILE_COMMANDS = {
               "python3 {repo}/bench.py --copy-calibration",
     "ss_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/ss_kt -o run -- "
              "python3 {repo}/bench.py --semispectral",
+    "dir_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/dir_kt -o run -- "
+              "python3 {repo}/bench.py --direct",
+    "dir_valu": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 "
+                "SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 "
+                "--output-format csv -d {out}/dir_valu -o run -- python3 {repo}/bench.py --direct",
 }
+# VALU issue: one wave64 instruction per SIMD every 4 cycles (16 lanes),
+# 256 CUs x 4 SIMDs at 2.4 GHz; FP32 (packed instructions disabled in this
+# build) and FP64 both issue at that rate: 78.6 TFLOP/s with FMA
+VALU_SIMDS, VALU_CLOCK_HZ, VALU_PEAK_TFLOPS = 1024, 2.4e9, 78.6
 COPY_BYTES = 4 << 28   # --copy-calibration copies 2^28 floats
 
 
@@ -189,7 +200,74 @@ def summarize_rocprof(out):
                          f"{float(r['Percentage']):.2f} |")
         with open(os.path.join(prof, "kernels_semispectral_flaring_1200x2048.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
+    if os.path.isdir(os.path.join(out, "dir_kt")) and os.path.isdir(os.path.join(out, "dir_valu")):
+        summarize_direct(out, prof, cmd)
     print(json.dumps(tr))
+
+
+def summarize_direct(out, prof, cmd):
+    """profiles/valu_direct_sum.md: VALU instruction mix and issue rate of the
+    direct-sum kernels (the FP64 64x128 and FP32 256x512 workloads)."""
+    stats = {r["Name"].split("(")[0].replace("void ", ""): r for r in _csv_rows(os.path.join(out, "dir_kt"),
+                                                                               "_kernel_stats.csv")}
+    rows = _csv_rows(os.path.join(out, "dir_valu"), "_counter_collection.csv")
+    lines = ["# VALU use of the direct sums (bench.py --direct)", "",
+             "Commands (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
+             "    " + cmd["dir_kt"], "    " + cmd["dir_valu"], "",
+             "Per dispatch (means): VALU instructions are wave64 instructions; issue fraction = "
+             "instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x kernel time); FLOP rate = "
+             "(add + mul + 2 fma) x 64 / kernel time against the 78.6 TFLOP/s vector issue rate "
+             "(FP32 without packed instructions, FP64).", "",
+             "| Kernel | Time (us) | VALU instr. | FP add/mul/fma | Issue fraction | TFLOP/s | of 78.6 |",
+             "|---|---|---|---|---|---|---|"]
+    for kname in ("k_direct<float, 1>", "k_direct<double, 1>"):
+        st = stats.get(kname)
+        vals = {}
+        for r in rows:
+            if r["Kernel_Name"].replace("void ", "").startswith(kname):
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if st is None or not vals:
+            continue
+        mean = {k: sum(v) / len(v) for k, v in vals.items()}
+        t = float(st["AverageNs"]) * 1e-9
+        sfx = "F32" if "float" in kname else "F64"
+        add, mul, fma = (mean.get(f"SQ_INSTS_VALU_{o}_{sfx}", 0.0) for o in ("ADD", "MUL", "FMA"))
+        issue = mean["SQ_INSTS_VALU"] * 4 / (VALU_SIMDS * VALU_CLOCK_HZ * t)
+        tflops = (add + mul + 2 * fma) * 64 / t / 1e12
+        lines.append(f"| `{kname}` | {t * 1e6:.1f} | {mean['SQ_INSTS_VALU']:.4g} | "
+                     f"{add:.3g} / {mul:.3g} / {fma:.3g} | {issue:.2f} | {tflops:.2f} | "
+                     f"{tflops / VALU_PEAK_TFLOPS:.2f} |")
+    with open(os.path.join(prof, "valu_direct_sum.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def direct_measurement(sg, T, W, dev):
+    """The direct sums alone: the FP64 64 x 128 workload and an FP32 256 x 512
+    single-fluid disc (h = 0.05), pairs per second."""
+    import numpy as np
+    import torch
+    out = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w = W.direct_fp64()
+    cases = [("fp64_64x128", w, torch.float64, 10)]
+    ws = W.single_fft(seed=3, n_r=256, n_phi=512)
+    cases.append(("fp32_256x512", dict(ws, sigma=ws["sigma"][0], h=ws["h"][0]), torch.float32, 3))
+    for name, c, dt, reps in cases:
+        g = sg.grid(c["n_r"], c["n_phi"], c["r_min"], c["r_max"])
+        s = torch.tensor(np.asarray(c["sigma"]).reshape(1, c["n_r"], c["n_phi"]), dtype=dt, device=dev)
+        h = [float(np.atleast_1d(c["h"])[0])]
+        T.direct(g, h, s)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            T.direct(g, h, s)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pairs = (c["n_r"] * c["n_phi"]) ** 2
+        out[name] = {"ms": round(ms, 4), "pairs_per_s": round(pairs / ms * 1e3, 1)}
+    return out
 
 
 def main():
@@ -203,6 +281,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
     ap.add_argument("--semispectral", action="store_true")
+    ap.add_argument("--direct", action="store_true")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
@@ -234,6 +313,9 @@ def main():
 
     if args.semispectral:
         print(json.dumps(semispectral_measurement(sg, T, W, dev)))
+        return
+    if args.direct:
+        print(json.dumps(direct_measurement(sg, T, W, dev)))
         return
 
     w = W.bifluid_fft()
