@@ -91,3 +91,31 @@ def test_tuner_mixed_batch(T, W, tmp_path, monkeypatch):
         _oracle_check(F, i, s)
     lines = cache.read_text().split("\n")
     assert len([ln for ln in lines if ln.strip()]) >= len(classes)
+
+
+def test_tuner_three_and_four_groups(T, W):
+    """Launch classes with three and four groups (their column pass holds one
+    source's spectra at a time): every candidate reproduces the reference and
+    the tuned plan matches the oracle."""
+    rng = np.random.default_rng(31)
+    specs = []
+    for nf, nr, nphi in ((3, 32, 64), (4, 64, 32)):
+        base = W.bifluid_fft(seed=nr + nf, n_r=nr, n_phi=nphi)
+        sig = np.concatenate([base["sigma"], base["sigma"][1:2] * rng.uniform(0.5, 2.0, (nf - 2, nr, nphi))])
+        specs.append(dict(base, h=[0.05, 0.005, 0.02, 0.01][:nf], sigma=sig))
+    print("tuner: three- and four-group discs", flush=True)
+    F = T.FFTField(specs)
+    for i, s in enumerate(specs):
+        F.set_sigma(i, s["sigma"])
+    res = F.tune()
+    torch.cuda.synchronize()
+    for r in res:
+        print("  ", r, flush=True)
+        assert r["rejected"] == 0 and r["rel_best"] <= 1e-5, r
+    for i in range(len(specs)):
+        F.g_r[i].zero_()
+        F.g_phi[i].zero_()
+    F.run()
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        _oracle_check(F, i, s)
