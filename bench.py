@@ -125,6 +125,16 @@ def _counter_mean(d, kernel, counter):
     return sum(vals) / len(vals), len(vals), top.split("(")[0].replace("void ", "")
 
 
+def _last_json(path):
+    """The last JSON line a bench.py run printed, or None."""
+    try:
+        with open(path) as fh:
+            rows = [x for x in fh.read().splitlines() if x.startswith("{")]
+        return json.loads(rows[-1]) if rows else None
+    except (OSError, ValueError):
+        return None
+
+
 def summarize_rocprof(out):
     """Writes profiles/kernels_bifluid_1024x2048.md and the pass-2 traffic files."""
     prof = os.path.join(ROOT, "profiles")
@@ -143,6 +153,16 @@ def summarize_rocprof(out):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                      f"{float(r['Percentage']):.2f} |")
+    live = _last_json(os.path.join(out, "kt.out"))
+    if live and "roofline" in live:
+        rl = live["roofline"]
+        avg = [float(r["AverageNs"]) / 1e3 for r in stats
+               if r["Name"].split("(")[0].replace("void ", "") == rl["kernel_name"]]
+        if avg:
+            us = rl["kernel_ms"] * 1e3
+            lines += ["", f"bench.py's own HIP-event timing of `{rl['kernel_name']}` in the same "
+                          f"run (the roofline's kernel time): {us:.2f} us against the trace's "
+                          f"{avg[0]:.2f} us average ({abs(us - avg[0]) / avg[0] * 100:.1f} % apart)."]
     with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
