@@ -460,11 +460,8 @@ __global__ void __launch_bounds__(256) k_adj_ind_sig(const sg_table_header *hd, 
 __global__ void k_adj_ind_dh(const sg_table_header *hd, const double *spart, int nb, int nf, double *dh)
 {
     if (threadIdx.x != 0) return;
-    double w[FQuad<double>::NODES];
-    for (int k = 0; k < FQuad<double>::NODES; ++k) {
-        const double v = (k + 1) * FQuad<double>::STEP;
-        w[k] = exp(-v * v);
-    }
+    double w[FQuad<double>::TABLE];
+    for (int k = 0; k < FQuad<double>::TABLE; ++k) w[k] = sg_weight_entry<double>(k);
     const double du = log(hd->r_max / hd->r_min) / hd->n_r, dphi = 2.0 * SG_PI / hd->n_phi;
     for (int a = 0; a < nf; ++a) {
         double S = 0.0;

@@ -79,13 +79,13 @@ __global__ void k_direct_prep(int nr, int nphi, int nf, double lnrmin, double du
 }
 
 template <typename T> __device__ inline T sg_F_any(T x, const T *w);
-template <> __device__ inline double sg_F_any<double>(double x, const double *w) { return sg_F64(x, w); }
+template <> __device__ inline double sg_F_any<double>(double x, const double *w) { return sg_F64<true>(x, w); }
 template <> __device__ inline float sg_F_any<float>(float x, const float *w) { return sg_F32(x, w); }
 
 template <typename T, int NF>
 __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
 {
-    __shared__ T wq[FQuad<T>::NODES];
+    __shared__ T wq[FQuad<T>::TABLE];
     sg_fill_weights<T>(wq);
     __syncthreads();
     const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_indirect_part(int nr, int nphi, int nf,
                                                        const T *H, double2 *part, int lin, double rmin,
                                                        double dr)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double ra[256], rb[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -265,13 +265,13 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
 // adds Sigma_a[i] times the cell integral of P_ab (k_pot_self).  Same
 // layout and splitting as the field sum; one accumulator per target fluid.
 template <typename T> __device__ inline T sg_G0_any(T x, const T *w);
-template <> __device__ inline double sg_G0_any<double>(double x, const double *w) { return sg_G0_64(x, w); }
+template <> __device__ inline double sg_G0_any<double>(double x, const double *w) { return sg_G0_64<true>(x, w); }
 template <> __device__ inline float sg_G0_any<float>(float x, const float *w) { return sg_G0_32(x, w); }
 
 template <typename T, int NF>
 __global__ void __launch_bounds__(256) k_potential(DirectArgs<T> A)
 {
-    __shared__ T wq[FQuad<T>::NODES];
+    __shared__ T wq[FQuad<T>::TABLE];
     sg_fill_weights<T>(wq);
     __syncthreads();
     const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;

@@ -18,34 +18,78 @@
 //           sqrt(2x) / step): double uses step 1/4 and 26 nodes (error
 //           < 1e-20 for x >= 2), float step 1/2 and 9 nodes (2e-8 at x = 1,
 //           below a float ulp; the tail beyond v = 4.5 is e^{-20}).
-//   x >= 32 (float only) the asymptotic series J = (sqrt(pi)/4) sum_n c_n
-//           x^-n, c_0 = 1, c_n = -c_{n-1} (4 n^2 - 1)/(8 n) (term-by-term
-//           integration of the binomial series; its first three terms are the
-//           expansion printed in Sect. 5.3), truncated after c_5.
-// The trapezoidal weights e^{-v_k^2} are computed once per workgroup into LDS
-// by sg_fill_weights() (exp of the node, no stored constants).
+//   x >= 32 (float), x >= 40 (double) the asymptotic series J = (sqrt(pi)/4)
+//           sum_n c_n x^-n, c_0 = 1, c_n = -c_{n-1} (4 n^2 - 1)/(8 n)
+//           (term-by-term integration of the binomial series; its first three
+//           terms are the expansion printed in Sect. 5.3), truncated after c_5
+//           (float) or c_16 (double).  (1 + t)^{-1/2} is completely monotone, so
+//           the binomial remainder alternates and is bounded by the first
+//           omitted term, and so is J's: |c_17| 40^-17 = 1e-18 for F, and for F'
+//           (series differentiated term by term, two such pieces of one sign)
+//           |c_17| (17 + 3/2) / (3/2) 40^-17 = 1.3e-17 of its leading term.
+// The trapezoidal weights e^{-v_k^2} (and, for double, a copy of the
+// asymptotic coefficients for the rolled series) are computed once per
+// workgroup into LDS by sg_fill_weights().
 #pragma once
 #include "sg_internal.h"
 
 #define SG_EULER_GAMMA 0.57721566490153286061
 
+// Table of TABLE entries: w[k-1] = exp(-(k STEP)^2), k = 1..NODES; for double
+// then c_n (n = 0..ASYM), -(n + 3/2) c_n, and the G0 coefficients a_n.
 template <typename R> struct FQuad;
 template <> struct FQuad<double> {
     static constexpr int NODES = 26;
     static constexpr double STEP = 0.25;
+    static constexpr int ASYM = 16;
+    static constexpr int C = NODES, D = C + ASYM + 1, A = D + ASYM + 1;
+    static constexpr int TABLE = A + ASYM + 1;
 };
 template <> struct FQuad<float> {
     static constexpr int NODES = 9;
     static constexpr float STEP = 0.5f;
+    static constexpr int TABLE = NODES;
 };
 
-// w[k-1] = exp(-(k h)^2), k = 1..NODES.  Call from every thread, then sync.
+// Double asymptotic coefficients, generated at compile time from their
+// recurrences: c_n (F), d_n = -(n + 3/2) c_n (F'), a_n (G0); see the branch
+// comments below.
+struct AsymCoef64 {
+    static constexpr int N = FQuad<double>::ASYM;
+    double c[N + 1], d[N + 1], a[N + 1];
+    constexpr AsymCoef64() : c{}, d{}, a{}
+    {
+        double v = 1.0, g = 1.0;
+        for (int n = 0; n <= N; ++n) {
+            if (n) {
+                v = -v * (4.0 * n * n - 1.0) / (8.0 * n);
+                g = -g * (2.0 * n - 1.0) * (2.0 * n - 1.0) / (8.0 * n);
+            }
+            c[n] = v;
+            d[n] = -v * (n + 1.5);
+            a[n] = g;
+        }
+    }
+};
+
+template <typename R> __device__ inline R sg_weight_entry(int k)
+{
+    if (k < FQuad<R>::NODES) {
+        const double v = (k + 1) * (double)FQuad<R>::STEP;
+        return (R)exp(-v * v);
+    }
+    if constexpr (sizeof(R) == 8) {
+        using Q = FQuad<double>;
+        constexpr AsymCoef64 C;
+        return k >= Q::A ? C.a[k - Q::A] : k >= Q::D ? C.d[k - Q::D] : C.c[k - Q::C];
+    }
+    return R(0);
+}
+
+// Call from every thread, then sync.
 template <typename R> __device__ inline void sg_fill_weights(R *w)
 {
-    for (int k = threadIdx.x; k < FQuad<R>::NODES; k += blockDim.x) {
-        double v = (k + 1) * (double)FQuad<R>::STEP;
-        w[k] = (R)exp(-v * v);
-    }
+    for (int k = threadIdx.x; k < FQuad<R>::TABLE; k += blockDim.x) w[k] = sg_weight_entry<R>(k);
 }
 
 // Series branch, x < 2.  NT terms.
@@ -114,6 +158,41 @@ struct AsymCoef {
     }
 };
 
+// Asymptotic branch (double), x >= 40: F and F' = (sqrt(2 pi)/4) sum_n c_n
+// (-n - 3/2) x^{-n-5/2}.  ROLLED: a rolled Horner loop over the LDS copy of
+// the coefficients.  Unrolled with literal coefficients, the compiler keeps
+// them in registers across the caller's loop, which drops the direct sums
+// from 3 to 1 waves per SIMD; the table and gradient kernels, whose occupancy
+// is set by other state, run fastest that way.
+template <bool ROLLED>
+__device__ inline void sg_F_asym64(double x, const double *w, double &F, double *dF)
+{
+    using Q = FQuad<double>;
+    const double u = 1.0 / x;
+    double s, sd = 0.0;
+    if constexpr (ROLLED) {
+        s = w[Q::C + Q::ASYM];
+        sd = w[Q::D + Q::ASYM];
+#pragma unroll 1
+        for (int n = Q::ASYM - 1; n >= 0; --n) {
+            s = s * u + w[Q::C + n];
+            if (dF) sd = sd * u + w[Q::D + n];
+        }
+    } else {
+        constexpr AsymCoef64 C;
+        s = C.c[Q::ASYM];
+        sd = C.d[Q::ASYM];
+#pragma unroll
+        for (int n = Q::ASYM - 1; n >= 0; --n) {
+            s = s * u + C.c[n];
+            if (dF) sd = sd * u + C.d[n];
+        }
+    }
+    const double pre = (SG_SQRT2 * SG_SQRT_PI * 0.25) * rsqrt(x) * u;
+    F = pre * s;
+    if (dF) *dF = pre * u * sd;
+}
+
 __device__ inline float sg_F_asym(float x)
 {
     constexpr AsymCoef C;
@@ -126,18 +205,22 @@ __device__ inline float sg_F_asym(float x)
     return float(SG_SQRT2) * rx * u * J;
 }
 
-// Full-range evaluators.
-__device__ inline double sg_F64(double x, const double *w)
+// Full-range evaluators.  The double asymptotic branch is taken only when
+// every active lane of the wave has x >= 40 (a wave that straddles 40 runs
+// the trapezoid, which holds for every x >= 2, instead of paying for both).
+template <bool ROLLED = false> __device__ inline double sg_F64(double x, const double *w)
 {
     double F;
-    if (x < 2.0) sg_F_series<double, 14>(x, F, nullptr);
+    if (__all(x >= 40.0)) sg_F_asym64<ROLLED>(x, w, F, nullptr);
+    else if (x < 2.0) sg_F_series<double, 14>(x, F, nullptr);
     else sg_F_quad<double>(x, w, F, nullptr);
     return F;
 }
 
-__device__ inline void sg_F64_dF(double x, const double *w, double &F, double &dF)
+template <bool ROLLED = false> __device__ inline void sg_F64_dF(double x, const double *w, double &F, double &dF)
 {
-    if (x < 2.0) sg_F_series<double, 14>(x, F, &dF);
+    if (__all(x >= 40.0)) sg_F_asym64<ROLLED>(x, w, F, &dF);
+    else if (x < 2.0) sg_F_series<double, 14>(x, F, &dF);
     else sg_F_quad<double>(x, w, F, &dF);
 }
 
@@ -157,8 +240,8 @@ __device__ inline float sg_F32(float x, const float *w)
 //   x >= 2 (float: 1 <= x < 32)  G0 = sqrt(2/x) int_0^inf e^{-v^2}
 //        (1 + v^2/(2x))^{-1/2} dv (the same substitution as for F; the
 //        trapezoid's v = 0 node has value 1 and weight STEP/2);
-//   x >= 32 (float)  sqrt(pi/(2x)) sum_n a_n x^-n, a_0 = 1,
-//        a_n = -a_{n-1} (2n - 1)^2 / (8 n), through a_5.
+//   x >= 32 (float), x >= 40 (double)  sqrt(pi/(2x)) sum_n a_n x^-n, a_0 = 1,
+//        a_n = -a_{n-1} (2n - 1)^2 / (8 n), through a_5 (float) or a_16.
 // ------------------------------------------------------------------------
 template <typename R, int NT> __device__ inline R sg_G0_series(R x)
 {
@@ -200,9 +283,26 @@ struct AsymCoefG0 {
     }
 };
 
-__device__ inline double sg_G0_64(double x, const double *w)
+// double, x >= 40: through a_16 (LDS table); K0's asymptotic remainder for
+// real x is bounded by the first omitted term, |a_17| 40^-17 = 3e-20.
+
+template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const double *w)
 {
-    return x < 2.0 ? sg_G0_series<double, 14>(x) : sg_G0_quad<double>(x, w);
+    if (!__all(x >= 40.0)) return x < 2.0 ? sg_G0_series<double, 14>(x) : sg_G0_quad<double>(x, w);
+    using Q = FQuad<double>;
+    const double u = 1.0 / x;
+    double s;
+    if constexpr (ROLLED) {
+        s = w[Q::A + Q::ASYM];
+#pragma unroll 1
+        for (int n = Q::ASYM - 1; n >= 0; --n) s = s * u + w[Q::A + n];
+    } else {
+        constexpr AsymCoef64 C;
+        s = C.a[Q::ASYM];
+#pragma unroll
+        for (int n = Q::ASYM - 1; n >= 0; --n) s = s * u + C.a[n];
+    }
+    return sqrt(SG_PI * 0.5 * u) * s;
 }
 
 __device__ inline float sg_G0_32(float x, const float *w)

@@ -70,7 +70,7 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
     constexpr int NC = N / 2 + 1;
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     sg_fill_weights<double>(wq);
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const LdsPlane<double> pl{lds + W * g};
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256)
 k_ss_self_lin(const double *H, int nf, int nr, int per, double rmin, double dr, double dphi, int pot, int which,
               double *out, GLNodes gl)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -670,7 +670,7 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
     constexpr int NC = N / 2 + 1;
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[S::WGS];
     sg_fill_weights<double>(wq);
     const int g = threadIdx.x / T, t = threadIdx.x % T;

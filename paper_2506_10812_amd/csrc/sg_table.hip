@@ -79,7 +79,7 @@ __device__ inline double block_sum256(double v, double *red)
 
 __global__ void k_self_cell(SelfItems items, double *out, double du, double dphi, GLNodes gl)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -96,7 +96,7 @@ template <typename T>
 __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double lnrmin, double du,
                                     double dphi, double *out, GLNodes gl)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -119,7 +119,7 @@ __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double
 __global__ void k_self_cell_ring(const double *H, int nf, int nr, double lnrmin, double du, double dphi, int which,
                                  double *out, GLNodes gl)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -180,7 +180,7 @@ template <typename T>
 __global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi, double lnrmin,
                            double du, double dphi, int per_row, double *out, GLNodes gl)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
     sg_fill_weights<double>(wq);
     __syncthreads();
@@ -221,7 +221,7 @@ __global__ void k_fill_f64(double *p, int64_t n, double v)
 __global__ void k_sample(double2 *A, int nr, int nphi, double du, double ha, double hb, int which,
                          const double *self_val)
 {
-    __shared__ double wq[FQuad<double>::NODES];
+    __shared__ double wq[FQuad<double>::TABLE];
     sg_fill_weights<double>(wq);
     __syncthreads();
     const int p = blockIdx.y;
@@ -331,11 +331,8 @@ __global__ void k_header(sg_table_header *hd, sg_table_header proto, const doubl
                          int npair, int with_dh)
 {
     sg_table_header h = proto;
-    double w[FQuad<double>::NODES];
-    for (int k = 0; k < FQuad<double>::NODES; ++k) {
-        const double v = (k + 1) * FQuad<double>::STEP;
-        w[k] = exp(-v * v);
-    }
+    double w[FQuad<double>::TABLE];
+    for (int k = 0; k < FQuad<double>::TABLE; ++k) w[k] = sg_weight_entry<double>(k);
     const double du = log(proto.r_max / proto.r_min) / proto.n_r;
     const double dphi = 2.0 * SG_PI / proto.n_phi;
     for (int a = 0; a < 4; ++a) {
@@ -359,7 +356,7 @@ __global__ void k_header(sg_table_header *hd, sg_table_header proto, const doubl
 template <typename T>
 __global__ void k_eval_F(const T *x, T *F, T *dF, int64_t n)
 {
-    __shared__ T wq[FQuad<T>::NODES];
+    __shared__ T wq[FQuad<T>::TABLE];
     sg_fill_weights<T>(wq);
     __syncthreads();
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -378,7 +375,7 @@ __global__ void k_eval_F(const T *x, T *F, T *dF, int64_t n)
 template <typename T>
 __global__ void k_eval_G0(const T *x, T *G, int64_t n)
 {
-    __shared__ T wq[FQuad<T>::NODES];
+    __shared__ T wq[FQuad<T>::TABLE];
     sg_fill_weights<T>(wq);
     __syncthreads();
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
