@@ -133,8 +133,8 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const T H2ab = T(0.5) * (ha2 + hb2[b]);
-                    const T rH = rsqrt(H2ab);
-                    const T x = s2 * T(0.125) / H2ab;
+                    const T rH = sg_rsqrt(H2ab);
+                    const T x = s2 * T(0.125) * (rH * rH);
                     const T F = self ? T(0) : sg_F_any<T>(self ? T(1) : x, wq);
                     const T c = m * F * rH * rH * rH;
                     accr[b] -= c * emc;
@@ -306,9 +306,10 @@ __global__ void __launch_bounds__(256) k_potential(DirectArgs<T> A)
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const T H2ab = T(0.5) * (ha2 + hb2[b]);
-                    const T y = s2 * T(0.125) / H2ab;
+                    const T rH = sg_rsqrt(H2ab);
+                    const T y = s2 * T(0.125) * (rH * rH);
                     const T G = self ? T(0) : sg_G0_any<T>(self ? T(1) : y, wq);
-                    acc[b] += m * G * rsqrt(H2ab);
+                    acc[b] += m * G * rH;
                 }
             }
         }

@@ -51,6 +51,15 @@ template <> struct FQuad<float> {
     static constexpr int TABLE = NODES;
 };
 
+// Reciprocal and reciprocal square root of the working type.  Float takes the
+// hardware v_rcp_f32 / v_rsq_f32 (about 1 ulp; arguments here are normal and
+// positive): rsqrt() has only a double overload, so a float argument would be
+// promoted to the double sequence, and '/' costs the full IEEE division.
+__device__ inline float sg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double sg_rcp(double x) { return 1.0 / x; }
+__device__ inline float sg_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double sg_rsqrt(double x) { return rsqrt(x); }
+
 // Double asymptotic coefficients, generated at compile time from their
 // recurrences: c_n (F), d_n = -(n + 3/2) c_n (F'), a_n (G0); see the branch
 // comments below.
@@ -107,16 +116,17 @@ __device__ inline void sg_F_series(R x, R &F, R *dF)
         I1s += sk;
         K0s += Hk * tk;
         K1s += (Hk + Hk1) * sk;
-        tk *= y / R((k + 1) * (k + 1));
-        sk *= y / R((k + 1) * (k + 2));
+        tk *= y * (R(1) / R((k + 1) * (k + 1)));  // constant reciprocals, folded
+        sk *= y * (R(1) / R((k + 1) * (k + 2)));
         Hk = Hk1;
     }
+    const R ix = sg_rcp(x);
     const R I1 = x * R(0.5) * I1s;
     const R K0 = -Lg * I0 + K0s;
-    const R K1 = R(1) / x + Lg * I1 - x * R(0.25) * K1s;
+    const R K1 = ix + Lg * I1 - x * R(0.25) * K1s;
     const R ex = exp(x);
     F = ex * (K1 - K0);
-    if (dF) *dF = ex * (R(2) * (K1 - K0) - K1 / x);
+    if (dF) *dF = ex * (R(2) * (K1 - K0) - K1 * ix);
 }
 
 // Trapezoidal branch, x >= 2: F = sqrt(2) x^-3/2 J, F' from J' =
@@ -124,23 +134,23 @@ __device__ inline void sg_F_series(R x, R &F, R *dF)
 template <typename R>
 __device__ inline void sg_F_quad(R x, const R *w, R &F, R *dF)
 {
-    const R i2x = R(0.5) / x;
+    const R ix = sg_rcp(x);
+    const R i2x = R(0.5) * ix;
     R J = R(0), Jd = R(0);
 #pragma unroll
     for (int k = 1; k <= FQuad<R>::NODES; ++k) {
         const R v2 = R(k * k) * (FQuad<R>::STEP * FQuad<R>::STEP);
-        const R rho = rsqrt(R(1) + v2 * i2x);
+        const R rho = sg_rsqrt(R(1) + v2 * i2x);
         const R base = w[k - 1] * v2 * rho;
         J += base;
         if (dF) Jd += base * rho * rho * v2;
     }
     J *= FQuad<R>::STEP;
-    const R rx = rsqrt(x);
-    const R x32 = rx / x;  // x^-3/2
+    const R x32 = sg_rsqrt(x) * ix;  // x^-3/2
     F = R(SG_SQRT2) * x32 * J;
     if (dF) {
-        const R Jp = Jd * FQuad<R>::STEP * R(0.25) / (x * x);
-        *dF = R(SG_SQRT2) * x32 * (Jp - R(1.5) * J / x);
+        const R Jp = Jd * FQuad<R>::STEP * R(0.25) * (ix * ix);
+        *dF = R(SG_SQRT2) * x32 * (Jp - R(1.5) * J * ix);
     }
 }
 
@@ -196,7 +206,7 @@ __device__ inline void sg_F_asym64(double x, const double *w, double &F, double 
 __device__ inline float sg_F_asym(float x)
 {
     constexpr AsymCoef C;
-    const float u = 1.0f / x;
+    const float u = sg_rcp(x);
     float s = C.c[5];
 #pragma unroll
     for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
@@ -224,12 +234,31 @@ template <bool ROLLED = false> __device__ inline void sg_F64_dF(double x, const 
     else sg_F_quad<double>(x, w, F, &dF);
 }
 
+// Float: each branch runs only when some lane of the wave needs it, and each
+// lane keeps its own branch's value (a wave whose lanes all fall in one range
+// pays for one branch).  SG_NO_SPECULATE, an empty asm statement, keeps the
+// compiler from if-converting the wave-uniform branches into straight-line
+// code that evaluates all three; it emits no instruction.
+#define SG_NO_SPECULATE() asm volatile("")
 __device__ inline float sg_F32(float x, const float *w)
 {
-    float F;
-    if (x < 1.0f) sg_F_series<float, 8>(x, F, nullptr);
-    else if (x < 32.0f) sg_F_quad<float>(x, w, F, nullptr);
-    else F = sg_F_asym(x);
+    const bool ser = x < 1.0f, asy = x >= 32.0f, quad = !ser && !asy;
+    float F = 0.0f, t;
+    if (__any(ser)) {
+        SG_NO_SPECULATE();
+        sg_F_series<float, 8>(x, t, nullptr);
+        F = ser ? t : F;
+    }
+    if (__any(quad)) {
+        SG_NO_SPECULATE();
+        sg_F_quad<float>(x, w, t, nullptr);
+        F = quad ? t : F;
+    }
+    if (__any(asy)) {
+        SG_NO_SPECULATE();
+        t = sg_F_asym(x);
+        F = asy ? t : F;
+    }
     return F;
 }
 
@@ -252,7 +281,7 @@ template <typename R, int NT> __device__ inline R sg_G0_series(R x)
     for (int k = 0; k < NT; ++k) {
         I0 += tk;
         K0s += Hk * tk;
-        tk *= y / R((k + 1) * (k + 1));
+        tk *= y * (R(1) / R((k + 1) * (k + 1)));
         Hk += R(1) / R(k + 1);
     }
     return exp(x) * (-Lg * I0 + K0s);
@@ -260,14 +289,14 @@ template <typename R, int NT> __device__ inline R sg_G0_series(R x)
 
 template <typename R> __device__ inline R sg_G0_quad(R x, const R *w)
 {
-    const R i2x = R(0.5) / x;
+    const R i2x = R(0.5) * sg_rcp(x);
     R acc = R(0.5);
 #pragma unroll
     for (int k = 1; k <= FQuad<R>::NODES; ++k) {
         const R v2 = R(k * k) * (FQuad<R>::STEP * FQuad<R>::STEP);
-        acc += w[k - 1] * rsqrt(R(1) + v2 * i2x);
+        acc += w[k - 1] * sg_rsqrt(R(1) + v2 * i2x);
     }
-    return acc * FQuad<R>::STEP * sqrt(R(2) / x);
+    return acc * FQuad<R>::STEP * R(SG_SQRT2) * sg_rsqrt(x);
 }
 
 struct AsymCoefG0 {
@@ -305,16 +334,32 @@ template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const
     return sqrt(SG_PI * 0.5 * u) * s;
 }
 
+// Branches as in sg_F32: run only when some lane of the wave needs them.
 __device__ inline float sg_G0_32(float x, const float *w)
 {
-    if (x < 1.0f) return sg_G0_series<float, 8>(x);
-    if (x < 32.0f) return sg_G0_quad<float>(x, w);
-    constexpr AsymCoefG0 C;
-    const float u = 1.0f / x;
-    float s = C.c[5];
+    const bool ser = x < 1.0f, asy = x >= 32.0f, quad = !ser && !asy;
+    float G = 0.0f;
+    if (__any(ser)) {
+        SG_NO_SPECULATE();
+        const float t = sg_G0_series<float, 8>(x);
+        G = ser ? t : G;
+    }
+    if (__any(quad)) {
+        SG_NO_SPECULATE();
+        const float t = sg_G0_quad<float>(x, w);
+        G = quad ? t : G;
+    }
+    if (__any(asy)) {
+        SG_NO_SPECULATE();
+        constexpr AsymCoefG0 C;
+        const float u = sg_rcp(x);
+        float s = C.c[5];
 #pragma unroll
-    for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
-    return sqrtf(float(SG_PI * 0.5) * u) * s;
+        for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
+        const float t = float(SG_SQRT_PI / SG_SQRT2) * sg_rsqrt(x) * s;
+        G = asy ? t : G;
+    }
+    return G;
 }
 
 // ------------------------------------------------------------------------
