@@ -218,28 +218,57 @@ __device__ inline float sg_F_asym(float x)
 // Full-range evaluators.  The double asymptotic branch is taken only when
 // every active lane of the wave has x >= 40 (a wave that straddles 40 runs
 // the trapezoid, which holds for every x >= 2, instead of paying for both).
+// Below that, the series and the trapezoid each run only when some lane of
+// the wave needs them, every lane keeping its own branch's value.
+// SG_NO_SPECULATE, an empty asm statement that emits no instruction, keeps
+// the compiler from if-converting such wave-uniform branches into
+// straight-line code that evaluates every branch for every lane.
+#define SG_NO_SPECULATE() asm volatile("")
+
+template <bool ROLLED>
+__device__ inline void sg_F64_any(double x, const double *w, double &F, double *dF)
+{
+    if (__all(x >= 40.0)) {
+        sg_F_asym64<ROLLED>(x, w, F, dF);
+        return;
+    }
+    const bool ser = x < 2.0;
+    double t, td = 0.0;
+    F = 0.0;
+    if (dF) *dF = 0.0;
+    if (__any(ser)) {
+        SG_NO_SPECULATE();
+        sg_F_series<double, 14>(x, t, dF ? &td : nullptr);
+        if (ser) {
+            F = t;
+            if (dF) *dF = td;
+        }
+    }
+    if (__any(!ser)) {
+        SG_NO_SPECULATE();
+        sg_F_quad<double>(x, w, t, dF ? &td : nullptr);
+        if (!ser) {
+            F = t;
+            if (dF) *dF = td;
+        }
+    }
+}
+
 template <bool ROLLED = false> __device__ inline double sg_F64(double x, const double *w)
 {
     double F;
-    if (__all(x >= 40.0)) sg_F_asym64<ROLLED>(x, w, F, nullptr);
-    else if (x < 2.0) sg_F_series<double, 14>(x, F, nullptr);
-    else sg_F_quad<double>(x, w, F, nullptr);
+    sg_F64_any<ROLLED>(x, w, F, nullptr);
     return F;
 }
 
 template <bool ROLLED = false> __device__ inline void sg_F64_dF(double x, const double *w, double &F, double &dF)
 {
-    if (__all(x >= 40.0)) sg_F_asym64<ROLLED>(x, w, F, &dF);
-    else if (x < 2.0) sg_F_series<double, 14>(x, F, &dF);
-    else sg_F_quad<double>(x, w, F, &dF);
+    sg_F64_any<ROLLED>(x, w, F, &dF);
 }
 
 // Float: each branch runs only when some lane of the wave needs it, and each
 // lane keeps its own branch's value (a wave whose lanes all fall in one range
-// pays for one branch).  SG_NO_SPECULATE, an empty asm statement, keeps the
-// compiler from if-converting the wave-uniform branches into straight-line
-// code that evaluates all three; it emits no instruction.
-#define SG_NO_SPECULATE() asm volatile("")
+// pays for one branch).
 __device__ inline float sg_F32(float x, const float *w)
 {
     const bool ser = x < 1.0f, asy = x >= 32.0f, quad = !ser && !asy;
@@ -317,7 +346,21 @@ struct AsymCoefG0 {
 
 template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const double *w)
 {
-    if (!__all(x >= 40.0)) return x < 2.0 ? sg_G0_series<double, 14>(x) : sg_G0_quad<double>(x, w);
+    if (!__all(x >= 40.0)) {  // branches as in sg_F64
+        const bool ser = x < 2.0;
+        double G = 0.0;
+        if (__any(ser)) {
+            SG_NO_SPECULATE();
+            const double t = sg_G0_series<double, 14>(x);
+            G = ser ? t : G;
+        }
+        if (__any(!ser)) {
+            SG_NO_SPECULATE();
+            const double t = sg_G0_quad<double>(x, w);
+            G = ser ? G : t;
+        }
+        return G;
+    }
     using Q = FQuad<double>;
     const double u = 1.0 / x;
     double s;
