@@ -115,17 +115,18 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
             SX = A.sx[p];
             EX = A.ex[p];
         }
-        const T rr = ri * rk;
+        const T rr8 = ri * rk * T(0.125);
         const int64_t kbase = (int64_t)kr * nphi;
+        const int lself = kr == ir ? j : -1;  // the own cell: l == j on the own ring
         for (int l = 0; l < nphi; ++l) {
             const int64_t k = kbase + l;
             int q = j - l;
             q += q < 0 ? nphi : 0;
             const T sp = A.sph[q];
-            const T s2 = rr * (SX + sp);
+            const T s2_8 = rr8 * (SX + sp);  // s^2 / 8
             const T emc = EX + T(0.5) * sp;
             const T sn = A.snp[q];
-            const bool self = (k == t);
+            const bool self = l == lself;
 #pragma unroll
             for (int a = 0; a < NF; ++a) {
                 const T m = A.mass[a * A.N + k] * rk * c8;
@@ -133,10 +134,10 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
 #pragma unroll
                 for (int b = 0; b < NF; ++b) {
                     const T H2ab = T(0.5) * (ha2 + hb2[b]);
-                    const T rH = sg_rsqrt(H2ab);
-                    const T x = s2 * T(0.125) * (rH * rH);
+                    const T rH = sg_rsqrt(H2ab), rH2 = rH * rH;
+                    const T x = s2_8 * rH2;
                     const T F = self ? T(0) : sg_F_any<T>(self ? T(1) : x, wq);
-                    const T c = m * F * rH * rH * rH;
+                    const T c = m * F * (rH2 * rH);
                     accr[b] -= c * emc;
                     accp[b] -= c * sn;
                 }

@@ -211,7 +211,7 @@ __device__ inline float sg_F_asym(float x)
 #pragma unroll
     for (int n = 4; n >= 0; --n) s = s * u + C.c[n];
     const float J = float(SG_SQRT_PI * 0.25) * s;
-    const float rx = rsqrtf(x);
+    const float rx = sg_rsqrt(x);
     return float(SG_SQRT2) * rx * u * J;
 }
 
