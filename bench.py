@@ -234,13 +234,17 @@ def summarize_direct(out, prof, cmd):
     lines = ["# VALU use of the direct sums (bench.py --direct)", "",
              "Commands (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
              "    " + cmd["dir_kt"], "    " + cmd["dir_valu"], "",
-             "Per dispatch (means): VALU instructions are wave64 instructions; issue fraction = "
-             "instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x kernel time); FLOP rate = "
-             "(add + mul + 2 fma) x 64 / kernel time against the 78.6 TFLOP/s vector issue rate "
-             "(FP32 without packed instructions, FP64).", "",
-             "| Kernel | Time (us) | VALU instr. | FP add/mul/fma | Issue fraction | TFLOP/s | of 78.6 |",
-             "|---|---|---|---|---|---|---|"]
-    for kname in ("k_direct<float, 1>", "k_direct<double, 1>"):
+             "Per dispatch (means): VALU instructions are wave64 instructions, per pair = "
+             "instructions x 64 / (n_r n_phi)^2 (256x512 float, 64x128 double, one fluid); nominal "
+             "issue ratio = instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x kernel time), which "
+             "is not a hard ceiling (a mix can exceed 1 when some of its instructions do not hold "
+             "the SIMD for four cycles); FLOP rate = (add + mul + 2 fma) x 64 / kernel time "
+             "against the 78.6 TFLOP/s vector issue rate (FP32 without packed instructions, FP64).",
+             "",
+             "| Kernel | Time (us) | VALU instr. | per pair | FP add/mul/fma | Nominal issue ratio "
+             "| TFLOP/s | of 78.6 |",
+             "|---|---|---|---|---|---|---|---|"]
+    for kname, cells in (("k_direct<float, 1>", 256 * 512), ("k_direct<double, 1>", 64 * 128)):
         st = stats.get(kname)
         vals = {}
         for r in rows:
@@ -254,7 +258,8 @@ def summarize_direct(out, prof, cmd):
         add, mul, fma = (mean.get(f"SQ_INSTS_VALU_{o}_{sfx}", 0.0) for o in ("ADD", "MUL", "FMA"))
         issue = mean["SQ_INSTS_VALU"] * 4 / (VALU_SIMDS * VALU_CLOCK_HZ * t)
         tflops = (add + mul + 2 * fma) * 64 / t / 1e12
-        lines.append(f"| `{kname}` | {t * 1e6:.1f} | {mean['SQ_INSTS_VALU']:.4g} | "
+        per_pair = mean["SQ_INSTS_VALU"] * 64 / float(cells) ** 2
+        lines.append(f"| `{kname}` | {t * 1e6:.1f} | {mean['SQ_INSTS_VALU']:.4g} | {per_pair:.1f} | "
                      f"{add:.3g} / {mul:.3g} / {fma:.3g} | {issue:.2f} | {tflops:.2f} | "
                      f"{tflops / VALU_PEAK_TFLOPS:.2f} |")
     with open(os.path.join(prof, "valu_direct_sum.md"), "w") as fh:
