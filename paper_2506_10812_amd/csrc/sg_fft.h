@@ -99,14 +99,6 @@ struct TwTable {
     template <int S> __device__ inline float2 get(int n, int, int) const { return gload2(tab, n); }
 };
 
-template <int N> struct TwExact64 {
-    template <int S> __device__ inline double2 get(int n, int, int) const
-    {
-        double s, c;
-        sincospi(-2.0 * (double)n / (double)N, &s, &c);
-        return make_double2(c, s);
-    }
-};
 
 // ------------------------------------------------------------ LDS exchange
 // One plane of N complex values per transform (plus one pad element per 16),
@@ -211,6 +203,25 @@ template <int N, bool SF = false> struct TwRegC {
 };
 
 // Stage plan of a twiddle provider: its own Plan type, else the default.
+// Double twiddles for the FP64 row transforms of the table builds: one exact
+// base e^{-2 pi i k/(L R)} per butterfly (sincospi), legs j = 2..R-1 as its
+// powers by complex products (a few ulps in double; every caller rounds the
+// result to float or accumulates a derivative checked at 1e-6), so a
+// length-2048 transform evaluates 3 sincospi per thread instead of 17.
+template <int N> struct TwPow64 {
+    using Plan = FftPlan<N>;
+    static constexpr bool POWERS = true;
+    int t;  // thread index within the transform
+    template <int S> __device__ inline double2 base(int beta) const
+    {
+        constexpr int L = Plan::L(S), LR = Plan::L(S) * Plan::RAD(S);
+        const int k = (t + Plan::T * beta) & (L - 1);
+        double s, c;
+        sincospi(-2.0 * (double)k / (double)LR, &s, &c);
+        return make_double2(c, s);
+    }
+};
+
 template <typename TW, int N, typename = void> struct plan_of { using type = FftPlan<N>; };
 template <typename TW, int N> struct plan_of<TW, N, decltype((void)sizeof(typename TW::Plan), void())> {
     using type = typename TW::Plan;

@@ -113,7 +113,7 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
     __syncthreads();
     // 2. transform; Z = T_r - t_phi at m and T_r + t_phi at -m
-    fft<N, false>(z, t, pl, TwExact64<N>{});
+    fft<N, false>(z, t, pl, TwPow64<N>{t});
 #pragma unroll
     for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
     __syncthreads();
@@ -731,7 +731,7 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
 #pragma unroll
         for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
         __syncthreads();
-        fft<N, false>(z, t, pl, TwExact64<N>{});
+        fft<N, false>(z, t, pl, TwPow64<N>{t});
 #pragma unroll
         for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
         __syncthreads();

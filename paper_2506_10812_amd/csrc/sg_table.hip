@@ -258,7 +258,7 @@ __global__ void k_tab_phi(const double2 *A, double2 *B, int rows)
     double2 v[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) v[p] = valid ? A[(size_t)row * N + t + T * p] : make_double2(0, 0);
-    fft<N, false>(v, t, pl, TwExact64<N>{});
+    fft<N, false>(v, t, pl, TwPow64<N>{t});
 #pragma unroll
     for (int p = 0; p < P; ++p) pl.st(t + T * p, v[p]);
     __syncthreads();
@@ -294,7 +294,7 @@ __global__ void k_tab_u(const double2 *B, float2 *dst, int ncol, size_t col_stri
     double2 v[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) v[p] = valid ? B[(size_t)col * NU + t + T * p] : make_double2(0, 0);
-    fft<NU, false>(v, t, pl, TwExact64<NU>{});
+    fft<NU, false>(v, t, pl, TwPow64<NU>{t});
     if (!valid) return;
     const int c = col / ncol, m = col % ncol;
     float2 *out = dst + (size_t)m * col_stride + (c ? comp_off1 : comp_off0);
