@@ -692,11 +692,12 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
     const double scale = -(A.lin ? A.dr / rp : A.du) * A.dphi / N;
     const uint32_t fs = (uint32_t)sg_blk_field_elems(N, A.nr);
     __syncthreads();
-    // both derivatives are sampled in one sweep (one F, F' evaluation per
-    // azimuth): d/dh_a goes to the plane, d/dh_b waits in registers (a thread
-    // holds at most P/2 + 1 of the N/2 + 1 azimuths)
+    // Both derivatives are sampled in one sweep (one F, F' evaluation per
+    // azimuth) and transformed together.  Row d is z_d = K_r,d + i K_phi,d
+    // with K_r even and K_phi odd in phi, so its transform Z_d is real; the
+    // plane holds z = z_1 + i z_2, whose transform carries Z_1 (d/dh_a) in
+    // its real part and Z_2 (d/dh_b) in its imaginary part.
     constexpr int Q = P / 2 + 1;
-    double2 keep[Q];
 #pragma unroll
     for (int u = 0; u < Q; ++u) {
         const int q = t + T * u;
@@ -711,63 +712,49 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
         } else {
             sg_conv_kernel64_dh(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, wq, kr1, kp1, kr2, kp2);
         }
-        keep[u] = make_double2(kr2, kp2);
-        pl.st(q, make_double2(kr1, kp1));
-        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr1, -kp1));
+        pl.st(q, make_double2(kr1 - kp2, kp1 + kr2));
+        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr1 + kp2, kr2 - kp1));
+    }
+    __syncthreads();
+    double2 z[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
+    __syncthreads();
+    fft<N, false>(z, t, pl, TwPow64<N>{t});
+#pragma unroll
+    for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
+    __syncthreads();
+    double dind = 0.0;
+    if (A.ind) {
+        // d/dh_a of r'^2 sqrt(2) K_a(r'/H_a) n_phi / 2, H_a = h_a r':
+        // dK_a/dH = pi^{-1/2} r' / (4 H^4) (-3 F(x) - 2 x F'(x)), x = r'^2 / (4 H^2)
+        const double Ha = ha * rp, x = rp * rp / (4.0 * Ha * Ha);
+        double F, dF;
+        sg_F64_dF(x, wq, F, dF);
+        const double dK = (1.0 / SG_SQRT_PI) * rp / (4.0 * Ha * Ha * Ha * Ha) * (-3.0 * F - 2.0 * x * dF);
+        dind = rp * rp * SG_SQRT2 * dK * rp * (0.5 * N);
     }
     double part[2] = {0.0, 0.0};
-    for (int which = 1; which <= 2; ++which) {
-        if (which == 2) {
-#pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const int q = t + T * u;
-                if (q > N / 2) break;
-                pl.st(q, keep[u]);
-                if (q != 0 && q != N / 2) pl.st(N - q, make_double2(keep[u].x, -keep[u].y));
+    if (live) {
+        for (int m = t; m < NC; m += T) {
+            const double2 zm = pl.ld(m), zn = pl.ld((N - m) & (N - 1));
+            const uint32_t oi = (uint32_t)sg_blk_index(m, ic, A.nr), op = (uint32_t)sg_blk_index(m, ip, A.nr);
+            const float2 lr = gld2(lt, (uint32_t)(2 * b) * fs + oi), lp = gld2(lt, (uint32_t)(2 * b + 1) * fs + oi);
+            const float2 sv = gld2(st, (uint32_t)a * fs + op);
+            // Re[conj(lr) T_r s] + Re[conj(lp) i t_phi s]
+            const double cr = (double)lr.x * sv.x + (double)lr.y * sv.y;
+            const double cp = -(double)lp.x * sv.y + (double)lp.y * sv.x;
+            const double wm = ((m == 0 || m == N / 2) ? 1.0 : 2.0) * scale;
+            double tr = 0.5 * (zm.x + zn.x), tp = 0.5 * (zn.x - zm.x);
+            if (m == 1) {
+                tr += dind;
+                tp += dind;
             }
+            part[0] += wm * (tr * cr + tp * cp);
+            part[1] += wm * (0.5 * (zm.y + zn.y) * cr + 0.5 * (zn.y - zm.y) * cp);
         }
-        __syncthreads();
-        double2 z[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) z[p] = pl.ld(t + T * p);
-        __syncthreads();
-        fft<N, false>(z, t, pl, TwPow64<N>{t});
-#pragma unroll
-        for (int p = 0; p < P; ++p) pl.st(t + T * p, z[p]);
-        __syncthreads();
-        double dind = 0.0;
-        if (A.ind && which == 1) {
-            // d/dh_a of r'^2 sqrt(2) K_a(r'/H_a) n_phi / 2, H_a = h_a r':
-            // dK_a/dH = pi^{-1/2} r' / (4 H^4) (-3 F(x) - 2 x F'(x)), x = r'^2 / (4 H^2)
-            const double Ha = ha * rp, x = rp * rp / (4.0 * Ha * Ha);
-            double F, dF;
-            sg_F64_dF(x, wq, F, dF);
-            const double dK = (1.0 / SG_SQRT_PI) * rp / (4.0 * Ha * Ha * Ha * Ha) * (-3.0 * F - 2.0 * x * dF);
-            dind = rp * rp * SG_SQRT2 * dK * rp * (0.5 * N);
-        }
-        double acc = 0.0;
-        if (live) {
-            for (int m = t; m < NC; m += T) {
-                const double zm = pl.ld(m).x, zn = pl.ld((N - m) & (N - 1)).x;
-                double tr = 0.5 * (zm + zn), tp = 0.5 * (zn - zm);
-                if (m == 1) {
-                    tr += dind;
-                    tp += dind;
-                }
-                tr *= scale;
-                tp *= scale;
-                const uint32_t oi = (uint32_t)sg_blk_index(m, ic, A.nr), op = (uint32_t)sg_blk_index(m, ip, A.nr);
-                const float2 lr = gld2(lt, (uint32_t)(2 * b) * fs + oi), lp = gld2(lt, (uint32_t)(2 * b + 1) * fs + oi);
-                const float2 sv = gld2(st, (uint32_t)a * fs + op);
-                const double wm = (m == 0 || m == N / 2) ? 1.0 : 2.0;
-                // Re[conj(lr) tr s] + Re[conj(lp) i tp s]
-                acc += wm * (tr * ((double)lr.x * sv.x + (double)lr.y * sv.y) +
-                             tp * (-(double)lp.x * sv.y + (double)lp.y * sv.x));
-            }
-        }
-        part[which - 1] = acc;
-        __syncthreads();
     }
+    __syncthreads();
     // per-group sums, then one atomic per row and derivative
     for (int d = 0; d < 2; ++d) {
         red[threadIdx.x] = part[d];
