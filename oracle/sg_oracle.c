@@ -8,9 +8,15 @@
  * CPU-baseline leg use it.  It shares no code, header, table or constant
  * with the HIP library; both sides only receive the same seeded inputs.
  *
- * Everything is plain double precision, written to be checked by eye
- * against the paper.  Speed is obtained only from OpenMP over target cells
- * and from a contiguous inner loop; no blocking or reordering of the sums.
+ * Every term is evaluated in plain double precision, written to be checked
+ * by eye against the paper; the field, potential, adjoint and indirect sums
+ * accumulate those terms in long double (x87 extended precision, 64-bit
+ * significand) in the plain order of the definition, so that the order of
+ * summation adds nothing measurable to the rounding of the terms themselves
+ * (a double running sum over 10^4 - 10^6 terms of both signs sits about
+ * 1e-12 from the exact sum of its terms, which is the size of the FP64
+ * accuracy bar).  Speed is obtained only from OpenMP over target cells and
+ * from a contiguous inner loop; no blocking or reordering of the sums.
  *
  * Discrete problem (readings of points the paper leaves open are marked
  * "reading"):
@@ -327,7 +333,7 @@ double sg_oracle_self_cell_range(double ha, double hb, double xlo, double xhi, d
  * ------------------------------------------------------------------------ */
 typedef struct {
     int nr, nphi, linear;
-    double du, dphi, lnrmin, rmin, dr;
+    double du, dphi, lnrmin, rmin, dr, rmax;
 } orc_grid;
 
 #define ORC_FLAG_EXCLUDE_SELF 1u
@@ -342,6 +348,7 @@ static orc_grid orc_make_grid_f(int nr, int nphi, double rmin, double rmax, unsi
     g.lnrmin = log(rmin);
     g.du = log(rmax / rmin) / nr;
     g.rmin = rmin;
+    g.rmax = rmax;
     g.dr = (rmax - rmin) / nr;
     g.dphi = 2.0 * ORC_PI / nphi;
     return g;
@@ -355,6 +362,24 @@ static double orc_r(const orc_grid *g, int i)
     return g->linear ? g->rmin + (i + 0.5) * g->dr : exp(g->lnrmin + (i + 0.5) * g->du);
 }
 static double orc_phi(const orc_grid *g, int j) { return (j + 0.5) * g->dphi; }
+/* Cell centre in extended precision (pairwise sums): the separation of two
+ * neighbouring cells is a small difference of coordinates of order r, so the
+ * coordinates' own rounding must sit well below a double ulp of the
+ * separation (a double phi_j near 2 pi carries an absolute error of ~4e-16,
+ * a relative error of ~1e-14 in the separation of adjacent cells there). */
+static void orc_centre_l(const orc_grid *g, int i, int j, long double *x, long double *y)
+{
+    const long double pi_l = 3.141592653589793238462643383279502884L;
+    long double r;
+    if (g->linear)
+        r = (long double)g->rmin + (i + 0.5L) * (((long double)g->rmax - g->rmin) / g->nr);
+    else
+        r = expl(logl((long double)g->rmin) +
+                 (i + 0.5L) * (logl((long double)g->rmax / g->rmin) / g->nr));
+    const long double p = (j + 0.5L) * (2.0L * pi_l / g->nphi);
+    *x = r * cosl(p);
+    *y = r * sinl(p);
+}
 static double orc_area(const orc_grid *g, int i)
 {
     const double r = orc_r(g, i);
@@ -515,7 +540,7 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
         const double xi = ri * cos(pi_), yi = ri * sin(pi_);
         for (int b = 0; b < nf; ++b) {
             const double Hb = H ? H[(int64_t)b * N + i] : h[b] * ri;
-            double acc = 0.0;
+            long double acc = 0.0L;
             for (int a = 0; a < nf; ++a) {
                 for (int kr = 0; kr < nr; ++kr) {
                     const double rk = orc_r(&g, kr);
@@ -537,7 +562,7 @@ int sg_oracle_potential_pairwise(int nr, int nphi, double rmin, double rmax, int
                     acc += sigma[(int64_t)a * N + i] * sg_oracle_potential_self_range(ri, Ha, Hb, xlo, xhi, g.dphi);
                 }
             }
-            pot[(int64_t)b * nt + ti] = acc;
+            pot[(int64_t)b * nt + ti] = (double)acc;
         }
     }
     return 0;
@@ -621,7 +646,7 @@ int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const
     orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
     for (int a = 0; a < nf; ++a) {
-        double sa = 0.0, sb = 0.0;
+        long double sa = 0.0L, sb = 0.0L;
         for (int i = 0; i < nr; ++i) {
             const double r = orc_r(&g, i);
             const double area = orc_area(&g, i);
@@ -636,8 +661,8 @@ int sg_oracle_indirect(int nr, int nphi, double rmin, double rmax, int nf, const
                 sb += w * sin(ph);
             }
         }
-        AB[2 * a] = sa;
-        AB[2 * a + 1] = sb;
+        AB[2 * a] = (double)sa;
+        AB[2 * a + 1] = (double)sb;
     }
     return 0;
 }
@@ -666,17 +691,16 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
     orc_gl_init();
     orc_grid g = orc_make_grid_f(nr, nphi, rmin, rmax, flags);
     const int64_t N = (int64_t)nr * nphi;
-    double *xs = malloc(sizeof(double) * N), *ys = malloc(sizeof(double) * N);
+    long double *xs = malloc(sizeof(long double) * N), *ys = malloc(sizeof(long double) * N);
     double *A = malloc(sizeof(double) * N), *Hc = malloc(sizeof(double) * nf * N);
     double *rr = malloc(sizeof(double) * N);
     if (!xs || !ys || !A || !Hc || !rr) return 2;
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < nphi; ++j) {
             int64_t k = (int64_t)i * nphi + j;
-            double r = orc_r(&g, i), p = orc_phi(&g, j);
+            double r = orc_r(&g, i);
             rr[k] = r;
-            xs[k] = r * cos(p);
-            ys[k] = r * sin(p);
+            orc_centre_l(&g, i, j, &xs[k], &ys[k]);
             A[k] = orc_area(&g, i);
             for (int f = 0; f < nf; ++f) Hc[f * N + k] = H ? H[f * N + k] : h[f] * r;
         }
@@ -688,16 +712,22 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
 #pragma omp for schedule(dynamic, 4)
         for (int64_t t = 0; t < nt; ++t) {
             int64_t i = targets ? targets[t] : t;
-            double cp = xs[i] / rr[i], sp = ys[i] / rr[i];
+            /* e_r, e_phi of the target from its extended-precision centre
+             * (g_phi, a small projection of the Cartesian sum, keeps the
+             * digits that a double cos, sin would round away) */
+            long double cx, cy;
+            orc_centre_l(&g, (int)(i / nphi), (int)(i % nphi), &cx, &cy);
+            const long double rl = sqrtl(cx * cx + cy * cy);
+            const long double cp = cx / rl, sp = cy / rl;
             for (int b = 0; b < nf; ++b) {
-                double Gx = 0.0, Gy = 0.0, gself = 0.0;
+                long double Gx = 0.0L, Gy = 0.0L, gself = 0.0L;
                 for (int a = 0; a < nf; ++a) {
                     const double *Sa = sigma + a * N;
                     const double *Ha = Hc + a * N;
                     double Hb = Hc[b * N + i];
                     for (int64_t k = 0; k < N; ++k) {
                         if (k == i) continue;
-                        double dx = xs[i] - xs[k], dy = ys[i] - ys[k];
+                        double dx = (double)(xs[i] - xs[k]), dy = (double)(ys[i] - ys[k]);
                         double s = sqrt(dx * dx + dy * dy);
                         double K = sg_oracle_kernel(s, Ha[k], Hb);
                         double w = Sa[k] * A[k] * K / s;
@@ -715,8 +745,8 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
                         gself -= Sa[i] * orc_self_memo(memo, 64, ha, hb, xlo, xhi, g.dphi, g.linear);
                     }
                 }
-                gr[b * nt + t] = Gx * cp + Gy * sp + gself;
-                gphi[b * nt + t] = -Gx * sp + Gy * cp;
+                gr[b * nt + t] = (double)(Gx * cp + Gy * sp + gself);
+                gphi[b * nt + t] = (double)(-Gx * sp + Gy * cp);
             }
         }
     }
@@ -766,7 +796,11 @@ static int orc_build_table(const orc_grid *g, double ha, double hb, int which, i
                 kr = self;
                 kp = 0.0;
             } else {
-                orc_conv(X, (double)q * g->dphi, ha, hb, which, &kr, &kp);
+                /* offset q and q - N are the same azimuth; the one in
+                 * (-pi, pi] keeps sin(phi) and sin(phi/2) at full relative
+                 * accuracy for the near neighbours across phi = 0 */
+                const int qs = 2 * q <= np ? q : q - np;
+                orc_conv(X, (double)qs * g->dphi, ha, hb, which, &kr, &kp);
             }
             /* T(p, q) goes to every m with (N - m) mod N == q */
             int m0 = (np - q) % np;
@@ -806,21 +840,21 @@ int sg_oracle_field_table(int nr, int nphi, double rmin, double rmax, int nf, co
             for (int64_t t = 0; t < nt; ++t) {
                 int64_t i = targets ? targets[t] : t;
                 int ir = (int)(i / nphi), j = (int)(i % nphi);
-                double sr = 0.0, sp = 0.0;
+                long double sr = 0.0L, sp = 0.0L;
                 for (int ip = 0; ip < nr; ++ip) {
                     const double *row = Sa + (size_t)ip * nphi;
                     const double *Rr = T.Tr + (size_t)(ir - ip + nr - 1) * 2 * nphi + (nphi - j);
                     const double *Rp = T.Tp + (size_t)(ir - ip + nr - 1) * 2 * nphi + (nphi - j);
-                    double ar = 0.0, ap = 0.0;
+                    long double ar = 0.0L, ap = 0.0L;
                     for (int jp = 0; jp < nphi; ++jp) {
-                        ar += row[jp] * Rr[jp];
-                        ap += row[jp] * Rp[jp];
+                        ar += (long double)row[jp] * Rr[jp];
+                        ap += (long double)row[jp] * Rp[jp];
                     }
                     sr += ar;
                     sp += ap;
                 }
-                o_r[t] = scale * sr;
-                o_p[t] = scale * sp;
+                o_r[t] = (double)(scale * sr);
+                o_p[t] = (double)(scale * sp);
             }
             orc_free_table(&T);
         }
@@ -853,21 +887,21 @@ int sg_oracle_adjoint_sigma(int nr, int nphi, double rmin, double rmax, int nf, 
             for (int64_t t = 0; t < nk; ++t) {
                 int64_t k = kidx ? kidx[t] : t;
                 int kr = (int)(k / nphi), kj = (int)(k % nphi);
-                double acc = 0.0;
+                long double acc = 0.0L;
                 for (int ir = 0; ir < nr; ++ir) {
                     /* T(ir - kr, j - kj) = R[ir - kr + nr - 1][kj - j + N];  as j
                      * increases the index decreases, so walk it backwards. */
                     const double *Rr = T.Tr + (size_t)(ir - kr + nr - 1) * 2 * nphi;
                     const double *Rp = T.Tp + (size_t)(ir - kr + nr - 1) * 2 * nphi;
                     const double *l1 = lr + (size_t)ir * nphi, *l2 = lp + (size_t)ir * nphi;
-                    double s = 0.0;
+                    long double s = 0.0L;
                     for (int j = 0; j < nphi; ++j) {
                         int m = kj - j + nphi;
-                        s += l1[j] * Rr[m] + l2[j] * Rp[m];
+                        s += (long double)l1[j] * Rr[m] + (long double)l2[j] * Rp[m];
                     }
                     acc += s;
                 }
-                dsigma[(size_t)a * nk + t] += scale * acc;
+                dsigma[(size_t)a * nk + t] += (double)(scale * acc);
             }
             orc_free_table(&T);
         }

@@ -204,6 +204,68 @@ def test_self_cell_small_cell_limit(ha, hb, du, dphi):
     assert abs(v - lim) < 1e-3 * abs(lim), (v, lim)
 
 
+def _kr_scipy(X, phi, ha, hb):
+    """K_r of the log-polar form rebuilt from the Cartesian geometry (target
+    at r = 1, source at r' = e^-X, azimuth difference phi) with scipy's
+    scaled Bessel functions for F(x) = e^x [K1(x) - K0(x)].  h may be
+    complex (complex-step derivatives); nothing here calls the oracle."""
+    rp = math.exp(-X)
+    sx, sp = math.sinh(0.5 * X), math.sin(0.5 * phi)
+    s2 = 2.0 * rp * (2.0 * sx * sx + 2.0 * sp * sp)  # |x - x'|^2 = 2 r r' (cosh X - cos phi)
+    Hab2 = 0.5 * ((ha * rp) ** 2 + hb * hb)
+    x = s2 / (8.0 * Hab2)
+    F = ss.kve(1, x) - ss.kve(0, x)
+    d = np.sqrt(s2 / Hab2)
+    K = F * (d / 8.0) / (math.sqrt(math.pi) * Hab2)
+    proj = rp * (math.expm1(X) + 2.0 * sp * sp) / math.sqrt(s2)  # e_s . e_r
+    return K * proj * rp * rp  # times the source measure r'^2
+
+
+def _self_cell_adaptive(ha, hb, du, dphi, part=lambda v: v):
+    """Cell average of the X-symmetrised K_r by scipy's adaptive (QUADPACK)
+    quadrature in polar coordinates about the cell centre, each quarter-cell
+    triangle on its own (the symmetrised integrand is bounded)."""
+    a, b = du / 2, dphi / 2
+    f = lambda X, p: part(0.5 * (_kr_scipy(X, p, ha, hb) + _kr_scipy(-X, p, ha, hb)))
+    th_c = math.atan2(b, a)
+    tot = 0.0
+    for th0, th1, edge in ((0.0, th_c, "a"), (th_c, math.pi / 2, "b")):
+        def inner(th):
+            c, s_ = math.cos(th), math.sin(th)
+            rmax = a / c if edge == "a" else b / s_
+            v, _ = si.quad(lambda rho: rho * f(rho * c, rho * s_), 0, rmax, epsabs=0,
+                           epsrel=1e-13, limit=400)
+            return v
+        v, _ = si.quad(inner, th0, th1, epsabs=0, epsrel=1e-12, limit=400)
+        tot += v
+    return tot / (a * b)
+
+
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+@pytest.mark.parametrize("ha,hb,du,dphi", [
+    (0.05, 0.05, math.log(2.5 / 0.2) / 64, 2 * math.pi / 128),   # 64 x 128 disc
+    (0.05, 0.05, math.log(25.0) / 1024, 2 * math.pi / 2048),     # 1024 x 2048: gas-gas
+    (0.005, 0.005, math.log(25.0) / 1024, 2 * math.pi / 2048),   # dust-dust
+    (0.05, 0.005, math.log(25.0) / 1024, 2 * math.pi / 2048),    # gas source, dust target
+    (0.005, 0.05, math.log(25.0) / 1024, 2 * math.pi / 2048),    # dust source, gas target
+    (0.01, 0.01, 0.2, 0.3),                                       # cell much larger than h
+    (0.03, 0.1, 0.05, 0.01)])
+def test_self_cell_independent_adaptive_quadrature(ha, hb, du, dphi):
+    """The own-cell average (reading: principal-value cell average of K_r) and
+    its h_a, h_b derivatives against an independent evaluation: the kernel
+    rebuilt from the Cartesian geometry with scipy's Bessel functions,
+    integrated by adaptive quadrature; derivatives by the complex step
+    (exact to rounding).  Bar 1e-10 relative (seen <= 7e-13)."""
+    ref = _self_cell_adaptive(ha, hb, du, dphi)
+    got = O.self_cell(ha, hb, du, dphi)
+    assert abs(got / ref - 1) < 1e-10, (got, ref)
+    e = 1e-30
+    for which, (za, zb) in ((1, (ha + 1j * e, hb)), (2, (ha, hb + 1j * e))):
+        dref = _self_cell_adaptive(za, zb, du, dphi, part=lambda v: v.imag / e)
+        dgot = O.self_cell(ha, hb, du, dphi, which)
+        assert abs(dgot / dref - 1) < 1e-10, (which, dgot, dref)
+
+
 def test_self_cell_h_derivatives_match_central_differences():
     du, dphi = 0.006, 0.006
     ha, hb, e = 0.05, 0.01, 1e-6
@@ -280,6 +342,72 @@ def test_table_mode_equals_pairwise_sum():
     tr, tp = O.field_table(nr, nphi, rmin, rmax, h, sig)
     assert np.abs(gr - tr).max() < 1e-13 * np.abs(gr).max()
     assert np.abs(gp - tp).max() < 1e-13 * np.abs(gr).max()
+
+
+def test_table_mode_equals_pairwise_sum_per_component_at_fp64_bar_size():
+    """The 64 x 128 FP64 workload (Sigma = r^-1 (1 + 0.01 U), h = 0.05): the
+    App. C offset-table sum and the Cartesian pairwise sum, two routes to the
+    same discrete sum with different terms and rounding, agree per component
+    far below the 1e-12 bar, g_phi (about 0.2 % of |g| here) included.  With
+    double running sums, double cell centres and azimuth offsets taken in
+    [0, 2 pi) the two sat 2.4e-12 apart on g_phi."""
+    rng = np.random.default_rng(1)
+    nr, nphi, rmin, rmax = 64, 128, 0.2, 2.5
+    r, _, _, _ = O.grid(nr, nphi, rmin, rmax)
+    sig = (1.0 / r)[None, :, None] * (1 + 0.01 * rng.uniform(-1, 1, (1, nr, nphi)))
+    idx = np.sort(np.random.default_rng(2).choice(nr * nphi, 1024, replace=False))
+    gr, gp = O.field_pairwise(nr, nphi, rmin, rmax, [0.05], sig, targets=idx)
+    tr, tp = O.field_table(nr, nphi, rmin, rmax, [0.05], sig, targets=idx)
+    e_r = np.linalg.norm(gr - tr) / np.linalg.norm(gr)
+    e_p = np.linalg.norm(gp - tp) / np.linalg.norm(gp)
+    assert e_r < 1e-13 and e_p < 1e-13, (e_r, e_p)  # seen 2.5e-16 and 3.4e-14
+
+
+def test_pairwise_sum_equals_high_precision_sum():
+    """The discrete sum at three seeded targets of a 16 x 32 disc of the FP64
+    workload's recipe, evaluated term by term in 30-digit arithmetic (mpmath
+    Bessel functions, exact cell centres): the oracle's pairwise and table
+    sums agree with it per component to 1e-13 of the component itself
+    (g_phi is about 1e-3 of |g| here, so this bounds the oracle's own
+    rounding, not only its formulas)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 30
+    rng = np.random.default_rng(1)
+    nr, nphi, rmin, rmax, h = 16, 32, 0.2, 2.5, 0.05
+    r, _, _, _ = O.grid(nr, nphi, rmin, rmax)
+    sig = (1.0 / r)[None, :, None] * (1 + 0.01 * rng.uniform(-1, 1, (1, nr, nphi)))
+    targets = np.array([37, 200, 411])
+    pr, pp = O.field_pairwise(nr, nphi, rmin, rmax, [h], sig, targets=targets, flags=O.EXCLUDE_SELF)
+    tr, tp = O.field_table(nr, nphi, rmin, rmax, [h], sig, targets=targets, flags=O.EXCLUDE_SELF)
+    H = mp.mpf(h)
+    lnr0 = mp.log(mp.mpf(rmin))
+    DU = (mp.log(mp.mpf(rmax)) - lnr0) / nr
+    DP = 2 * mp.pi / nphi
+    rad = [mp.e ** (lnr0 + (i + mp.mpf(1) / 2) * DU) for i in range(nr)]
+    ang = [(j + mp.mpf(1) / 2) * DP for j in range(nphi)]
+    for t, i in enumerate(targets):
+        ir, j = divmod(int(i), nphi)
+        ri, pi_ = rad[ir], ang[j]
+        xi, yi = ri * mp.cos(pi_), ri * mp.sin(pi_)
+        Gx = Gy = mp.mpf(0)
+        for kr in range(nr):
+            rk = rad[kr]
+            for kp in range(nphi):
+                if kr == ir and kp == j:
+                    continue
+                dx, dy = xi - rk * mp.cos(ang[kp]), yi - rk * mp.sin(ang[kp])
+                s = mp.sqrt(dx * dx + dy * dy)
+                H2 = (H * H * rk * rk + H * H * ri * ri) / 2
+                x = s * s / (8 * H2)
+                K = mp.e ** x * (mp.besselk(1, x) - mp.besselk(0, x)) * (s / mp.sqrt(H2)) / 8 / (mp.sqrt(mp.pi) * H2)
+                w = mp.mpf(float(sig[0, kr, kp])) * rk * rk * DU * DP * K / s
+                Gx -= w * dx
+                Gy -= w * dy
+        gr = float(Gx * mp.cos(pi_) + Gy * mp.sin(pi_))
+        gp = float(-Gx * mp.sin(pi_) + Gy * mp.cos(pi_))
+        for got_r, got_p in ((pr[0, t], pp[0, t]), (tr[0, t], tp[0, t])):
+            assert abs(got_r / gr - 1) < 1e-13, (i, got_r, gr)
+            assert abs(got_p / gp - 1) < 1e-13, (i, got_p, gp)
 
 
 def test_razor_thin_field_is_newtonian_sum():
