@@ -24,6 +24,17 @@
 // the per-split partial sums are reduced in a fixed order by a second kernel
 // that also adds the self term and, with SG_INDIRECT, the indirect term
 // (deterministic; no atomics).
+//
+// Accumulation (both precisions): the sources of a row are taken in chunks of
+// SG_DCHUNK azimuths, each chunk summed into a fresh partial, and the chunk
+// partials are added to the running total with an error-free transformation
+// (Knuth's TwoSum), whose rounding errors are carried in a second
+// accumulator.  A single running sum over all 2^21 sources of a 1024 x 2048
+// disc would lose about three digits to the cancellation between the pull of
+// the inner and of the outer disc; chunking bounds the plain-sum part to 64
+// terms and the compensated outer sum is exact to first order, so the result
+// sits at the rounding floor of the individual terms.  Each split hands
+// (sum, carried error) to the reduction, which adds them in double.
 #include "sg_direct.h"
 #include "sg_kfn.h"
 #include "sg_table.h"
@@ -33,8 +44,20 @@ template <typename T> struct DirectArgs {
     int lin;             // uniform radial grid
     int64_t N;
     const T *rrow, *sx, *ex, *sph, *snp, *mass, *H2;
-    T *partial;
+    T *partial;          // [split][fluid][component][hi, lo][N]
 };
+
+#define SG_DCHUNK 64
+
+// s + v = (s', e') exactly (Knuth's TwoSum); the error goes into c.  No
+// products, so contraction into FMAs cannot change it.
+template <typename T> __device__ inline void sg_two_sum_acc(T &s, T &c, T v)
+{
+    const T t = s + v;
+    const T bp = t - s;
+    c += (s - (t - bp)) + (v - bp);
+    s = t;
+}
 
 // Ring radius: log grid (lin = 0) or uniform grid (a = r_min, b = dr).
 __device__ inline double dir_radius(int lin, double lnrmin, double du, double rmin, double dr, int i)
@@ -93,12 +116,14 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
     const int nphi = A.nphi, nr = A.nr;
     const int ir = (int)(t / nphi), j = (int)(t % nphi);
     const T ri = A.rrow[ir];
-    T hb2[NF], accr[NF], accp[NF];
+    T hb2[NF], accr[NF], accp[NF], errr[NF], errp[NF];
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
         hb2[b] = A.H2[b * A.N + t];
         accr[b] = T(0);
         accp[b] = T(0);
+        errr[b] = T(0);
+        errp[b] = T(0);
     }
     const T c8 = T(1.0 / (8.0 * SG_SQRT_PI));
     const int r0 = blockIdx.y * A.rps;
@@ -118,36 +143,53 @@ __global__ void __launch_bounds__(256) k_direct(DirectArgs<T> A)
         const T rr8 = ri * rk * T(0.125);
         const int64_t kbase = (int64_t)kr * nphi;
         const int lself = kr == ir ? j : -1;  // the own cell: l == j on the own ring
-        for (int l = 0; l < nphi; ++l) {
-            const int64_t k = kbase + l;
-            int q = j - l;
-            q += q < 0 ? nphi : 0;
-            const T sp = A.sph[q];
-            const T s2_8 = rr8 * (SX + sp);  // s^2 / 8
-            const T emc = EX + T(0.5) * sp;
-            const T sn = A.snp[q];
-            const bool self = l == lself;
+        for (int l0 = 0; l0 < nphi; l0 += SG_DCHUNK) {
+            const int l1 = min(nphi, l0 + SG_DCHUNK);
+            T pr[NF], pp[NF];  // this chunk's partial sums
 #pragma unroll
-            for (int a = 0; a < NF; ++a) {
-                const T m = A.mass[a * A.N + k] * rk * c8;
-                const T ha2 = A.H2[a * A.N + k];
+            for (int b = 0; b < NF; ++b) {
+                pr[b] = T(0);
+                pp[b] = T(0);
+            }
+            for (int l = l0; l < l1; ++l) {
+                const int64_t k = kbase + l;
+                int q = j - l;
+                q += q < 0 ? nphi : 0;
+                const T sp = A.sph[q];
+                const T s2_8 = rr8 * (SX + sp);  // s^2 / 8
+                const T emc = EX + T(0.5) * sp;
+                const T sn = A.snp[q];
+                const bool self = l == lself;
 #pragma unroll
-                for (int b = 0; b < NF; ++b) {
-                    const T H2ab = T(0.5) * (ha2 + hb2[b]);
-                    const T rH = sg_rsqrt(H2ab), rH2 = rH * rH;
-                    const T x = s2_8 * rH2;
-                    const T F = self ? T(0) : sg_F_any<T>(self ? T(1) : x, wq);
-                    const T c = m * F * (rH2 * rH);
-                    accr[b] -= c * emc;
-                    accp[b] -= c * sn;
+                for (int a = 0; a < NF; ++a) {
+                    const T m = A.mass[a * A.N + k] * rk * c8;
+                    const T ha2 = A.H2[a * A.N + k];
+#pragma unroll
+                    for (int b = 0; b < NF; ++b) {
+                        const T H2ab = T(0.5) * (ha2 + hb2[b]);
+                        const T rH = sg_rsqrt(H2ab), rH2 = rH * rH;
+                        const T x = s2_8 * rH2;
+                        const T F = self ? T(0) : sg_F_any<T>(self ? T(1) : x, wq);
+                        const T c = m * F * (rH2 * rH);
+                        pr[b] -= c * emc;
+                        pp[b] -= c * sn;
+                    }
                 }
+            }
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+                sg_two_sum_acc(accr[b], errr[b], pr[b]);
+                sg_two_sum_acc(accp[b], errp[b], pp[b]);
             }
         }
     }
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
-        A.partial[((int64_t)(blockIdx.y * NF + b) * 2 + 0) * A.N + t] = accr[b];
-        A.partial[((int64_t)(blockIdx.y * NF + b) * 2 + 1) * A.N + t] = accp[b];
+        T *o = A.partial + (int64_t)(blockIdx.y * NF + b) * 4 * A.N + t;
+        o[0] = accr[b];
+        o[A.N] = errr[b];
+        o[2 * A.N] = accp[b];
+        o[3 * A.N] = errp[b];
     }
 }
 
@@ -229,11 +271,19 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
     }
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
-        T sr = T(0), sp = T(0);
+        // the splits' (sum, carried error) pairs, added in double in a fixed
+        // order (compensated, so the double pass adds no error of its own
+        // that matters for either precision)
+        double sr = 0.0, er = 0.0, sp = 0.0, ep = 0.0;
         for (int s = 0; s < S; ++s) {
-            sr += partial[((int64_t)(s * NF + b) * 2 + 0) * N + t];
-            sp += partial[((int64_t)(s * NF + b) * 2 + 1) * N + t];
+            const T *pp = partial + (int64_t)(s * NF + b) * 4 * N + t;
+            sg_two_sum_acc(sr, er, (double)pp[0]);
+            sg_two_sum_acc(sr, er, (double)pp[N]);
+            sg_two_sum_acc(sp, ep, (double)pp[2 * N]);
+            sg_two_sum_acc(sp, ep, (double)pp[3 * N]);
         }
+        sr += er;
+        sp += ep;
         if (with_self) {
             const int ir = (int)(t / nphi);
             const double w = lin ? dr / (rmin + (ir + 0.5) * dr) * (2.0 * SG_PI / nphi) : dudphi;
@@ -247,14 +297,14 @@ __global__ void k_direct_reduce(const T *partial, int S, int64_t N, const double
                                                  : self[pair];
                 st -= w * (double)sigma[a * N + t] * kb;
             }
-            sr += (T)st;
+            sr += st;
         }
         if (ind) {
-            sr += (T)ir;
-            sp += (T)ip;
+            sr += ir;
+            sp += ip;
         }
-        gr[b * N + t] = sr;
-        gp[b * N + t] = sp;
+        gr[b * N + t] = (T)sr;
+        gp[b * N + t] = (T)sp;
     }
 }
 
@@ -280,11 +330,12 @@ __global__ void __launch_bounds__(256) k_potential(DirectArgs<T> A)
     const int nphi = A.nphi, nr = A.nr;
     const int ir = (int)(t / nphi), j = (int)(t % nphi);
     const T ri = A.rrow[ir];
-    T hb2[NF], acc[NF];
+    T hb2[NF], acc[NF], err[NF];
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
         hb2[b] = A.H2[b * A.N + t];
         acc[b] = T(0);
+        err[b] = T(0);
     }
     const T c2 = T(-0.5 / SG_SQRT_PI);
     const int r0 = blockIdx.y * A.rps;
@@ -294,29 +345,41 @@ __global__ void __launch_bounds__(256) k_potential(DirectArgs<T> A)
         const T SX = A.sx[p];
         const T rr = ri * A.rrow[kr];
         const int64_t kbase = (int64_t)kr * nphi;
-        for (int l = 0; l < nphi; ++l) {
-            const int64_t k = kbase + l;
-            int q = j - l;
-            q += q < 0 ? nphi : 0;
-            const T s2 = rr * (SX + A.sph[q]);
-            const bool self = (k == t);
+        for (int l0 = 0; l0 < nphi; l0 += SG_DCHUNK) {
+            const int l1 = min(nphi, l0 + SG_DCHUNK);
+            T pc[NF];  // this chunk's partial sums
 #pragma unroll
-            for (int a = 0; a < NF; ++a) {
-                const T m = A.mass[a * A.N + k] * c2;
-                const T ha2 = A.H2[a * A.N + k];
+            for (int b = 0; b < NF; ++b) pc[b] = T(0);
+            for (int l = l0; l < l1; ++l) {
+                const int64_t k = kbase + l;
+                int q = j - l;
+                q += q < 0 ? nphi : 0;
+                const T s2 = rr * (SX + A.sph[q]);
+                const bool self = (k == t);
 #pragma unroll
-                for (int b = 0; b < NF; ++b) {
-                    const T H2ab = T(0.5) * (ha2 + hb2[b]);
-                    const T rH = sg_rsqrt(H2ab);
-                    const T y = s2 * T(0.125) * (rH * rH);
-                    const T G = self ? T(0) : sg_G0_any<T>(self ? T(1) : y, wq);
-                    acc[b] += m * G * rH;
+                for (int a = 0; a < NF; ++a) {
+                    const T m = A.mass[a * A.N + k] * c2;
+                    const T ha2 = A.H2[a * A.N + k];
+#pragma unroll
+                    for (int b = 0; b < NF; ++b) {
+                        const T H2ab = T(0.5) * (ha2 + hb2[b]);
+                        const T rH = sg_rsqrt(H2ab);
+                        const T y = s2 * T(0.125) * (rH * rH);
+                        const T G = self ? T(0) : sg_G0_any<T>(self ? T(1) : y, wq);
+                        pc[b] += m * G * rH;
+                    }
                 }
             }
+#pragma unroll
+            for (int b = 0; b < NF; ++b) sg_two_sum_acc(acc[b], err[b], pc[b]);
         }
     }
 #pragma unroll
-    for (int b = 0; b < NF; ++b) A.partial[((int64_t)(blockIdx.y * NF + b)) * A.N + t] = acc[b];
+    for (int b = 0; b < NF; ++b) {
+        T *o = A.partial + (int64_t)(blockIdx.y * NF + b) * 2 * A.N + t;
+        o[0] = acc[b];
+        o[A.N] = err[b];
+    }
 }
 
 template <typename T, int NF>
@@ -329,15 +392,20 @@ __global__ void k_potential_reduce(const T *partial, int S, int64_t N, int nphi,
     const int64_t per = per_row ? N / nphi : N;
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
-        T sum = T(0);
-        for (int s = 0; s < S; ++s) sum += partial[((int64_t)(s * NF + b)) * N + t];
+        double sum = 0.0, e = 0.0;
+        for (int s = 0; s < S; ++s) {
+            const T *pp = partial + (int64_t)(s * NF + b) * 2 * N + t;
+            sg_two_sum_acc(sum, e, (double)pp[0]);
+            sg_two_sum_acc(sum, e, (double)pp[N]);
+        }
+        sum += e;
         if (with_self) {
             double st = 0.0;
 #pragma unroll
             for (int a = 0; a < NF; ++a) st += (double)sigma[a * N + t] * self[(int64_t)(a * NF + b) * per + si];
-            sum += (T)st;
+            sum += st;
         }
-        pot[b * N + t] = sum;
+        pot[b * N + t] = (T)sum;
     }
 }
 
@@ -387,7 +455,7 @@ size_t sg_direct_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += 2 * sg_align256(es * nphi);
     o += 2 * sg_align256(es * nf * N);
     o += sg_align256(sizeof(double) * nf * nf * (percell ? N : nr));
-    o += sg_align256(es * (size_t)S * nf * 2 * N);
+    o += sg_align256(es * (size_t)S * nf * 4 * N);
     o += sg_align256(sizeof(double) * 4);
     o += sg_align256(sizeof(double2) * (SG_IND_BLOCKS + 1));
     return o;
@@ -421,7 +489,7 @@ static sg_status direct_run(const sg_grid *g, int nf, const double *h, const T *
     T *H2 = (T *)take(sizeof(T) * nf * N);
     const int percell = H != nullptr;
     double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : nr));
-    T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 2 * N);
+    T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 4 * N);
     // uniform grid: double H for the own-cell integrals, per cell or per ring,
     // in the partial-sum buffer (at least nf N doubles; written before the sum)
     double *Hd = (double *)partial;
@@ -527,7 +595,7 @@ size_t sg_potential_ws_bytes(int nr, int nphi, int nf, sg_dtype dt, int percell)
     o += 2 * sg_align256(es * nphi);
     o += 2 * sg_align256(es * nf * N);
     o += sg_align256(sizeof(double) * nf * nf * (percell ? N : nr));
-    o += sg_align256(es * (size_t)S * nf * N);
+    o += sg_align256(es * (size_t)S * nf * 2 * N);
     o += sg_align256(sizeof(double) * 4);
     return o;
 }
@@ -558,7 +626,7 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
     T *H2 = (T *)take(sizeof(T) * nf * N);
     const int percell = H != nullptr;
     double *self = (double *)take(sizeof(double) * nf * nf * (percell ? N : nr));
-    T *partial = (T *)take(sizeof(T) * (size_t)S * nf * N);
+    T *partial = (T *)take(sizeof(T) * (size_t)S * nf * 2 * N);
     double *dh = (double *)take(sizeof(double) * 4);
     for (int f = 0; f < nf; ++f)
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, dh + f, (int64_t)1, h ? h[f] : 0.0);

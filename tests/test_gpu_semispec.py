@@ -105,7 +105,7 @@ def test_semispectral_wide_grids_sampled(sg, T, W, nr, nphi, nf):
     rr, rp = oracle_field(w, targets=cells)
     gr = gr.reshape(nf, -1)[:, cells]
     gp = gp.reshape(nf, -1)[:, cells]
-    check(gr, gp, rr, rp, nf, rms=2e-5)
+    check(gr, gp, rr, rp, nf, rms=1e-5)
 
 
 def test_semispectral_appD_full_size_sampled(sg, T, W):
@@ -129,7 +129,7 @@ def test_semispectral_appD_full_size_sampled(sg, T, W):
     rr, rp = oracle_field(w, targets=cells)
     gr = S.g_r.cpu().numpy().astype(np.float64).reshape(nf, -1)[:, cells]
     gp = S.g_phi.cpu().numpy().astype(np.float64).reshape(nf, -1)[:, cells]
-    check(gr, gp, rr, rp, nf, rms=2e-5)
+    check(gr, gp, rr, rp, nf, rms=1e-5)
 
 
 def test_semispectral_equals_fft_path_for_constant_h(sg, T, W):
@@ -245,7 +245,7 @@ def test_semispectral_tuner(sg, T, W):
     cells = W.sample_cells(300, 16, 40, seed=2)
     rr, rp = oracle_field(w, targets=cells)
     check(S.g_r.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64),
-          S.g_phi.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64), rr, rp, 2, rms=2e-5)
+          S.g_phi.cpu().numpy().reshape(2, -1)[:, cells].astype(np.float64), rr, rp, 2, rms=1e-5)
 
 
 def test_semispectral_banded_equals_full(sg, T, W):
@@ -329,7 +329,7 @@ def test_semispectral_uniform_grid_banded(sg, T, W):
         assert rel_rms(gb_r[f], gf_r[f]) < 1e-6 and rel_rms(gb_p[f], gf_p[f]) < 1e-6
     cells = W.sample_cells(256, 256, 40, seed=8)
     rr, rp = oracle_field_lin(w, targets=cells)
-    check(gb_r.reshape(2, -1)[:, cells], gb_p.reshape(2, -1)[:, cells], rr, rp, 2, rms=2e-5)
+    check(gb_r.reshape(2, -1)[:, cells], gb_p.reshape(2, -1)[:, cells], rr, rp, 2, rms=1e-5)
     g = torch.Generator(device="cpu").manual_seed(3)
     lam_r = torch.randn(Sb.g_r.shape, generator=g).cuda()
     lam_p = torch.randn(Sb.g_r.shape, generator=g).cuda()
