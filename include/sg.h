@@ -58,7 +58,8 @@ typedef enum sg_status {
     SG_ERR_UNSUPPORTED = 2, /* valid but not supported by this path        */
     SG_ERR_HIP = 3,         /* a HIP runtime call failed                    */
     SG_ERR_WORKSPACE = 4,   /* workspace pointer NULL or too small          */
-    SG_ERR_TABLE = 5        /* kernel table does not match the disc         */
+    SG_ERR_TABLE = 5,       /* kernel table does not match the disc         */
+    SG_ERR_SCRATCH = 6      /* larger than the no-allocation scratch array  */
 } sg_status;
 
 typedef enum sg_dtype { SG_F32 = 0, SG_F64 = 1 } sg_dtype;
@@ -329,6 +330,28 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h,
                           const void *d_sigma, const void *d_H, void *d_g_r, void *d_g_phi,
                           sg_dtype dtype, uint32_t flags, void *d_ws, size_t ws_bytes,
                           void *stream);
+
+/* ---------------------------------------------------------------------
+ * sg_field_direct_noalloc: sg_field_direct without a workspace argument,
+ * for callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops, harnesses that forbid hipMalloc).  It calls no
+ * allocating routine: its workspace is a static device array of
+ * SG_NOALLOC_SCRATCH_BYTES (64 MiB) in the library, one per GPU, held from
+ * the library's load until the process ends.  The first call on a device
+ * resolves that array's address (hipGetSymbolAddress, not a stream
+ * operation); make one call before capturing a stream.  Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on the same GPU (other
+ * streams, other host threads) race: the caller serialises them.  Inputs,
+ * outputs, flags and results as for sg_field_direct (same kernels, same
+ * arithmetic, bitwise equal outputs).  SG_ERR_SCRATCH (nothing launched)
+ * when sg_field_direct_workspace_bytes() for the arguments exceeds
+ * SG_NOALLOC_SCRATCH_BYTES: float, h r scale heights, up to about 2.8e6
+ * cells for one fluid (24 bytes per cell) and 1.4e6 for two (48 bytes).
+ * --------------------------------------------------------------------- */
+#define SG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sg_status sg_field_direct_noalloc(const sg_grid *grid, int n_fluids, const double *h,
+                                  const void *d_sigma, const void *d_H, void *d_g_r, void *d_g_phi,
+                                  sg_dtype dtype, uint32_t flags, void *stream);
 
 /* ---------------------------------------------------------------------
  * sg_potential_direct: the conservative 2D potential of Sect. 5.5 (appendix

@@ -14,7 +14,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsg.so")
 
-OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE, ERR_TABLE = range(6)
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE, ERR_TABLE, ERR_SCRATCH = range(7)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 F32, F64 = 0, 1
 SELF_CELL_EXCLUDE = 1
 WITH_DH = 2
@@ -87,6 +88,7 @@ def _load():
                                     ctypes.POINTER(ctypes.c_int)]),
         "sg_field_direct_workspace_bytes": (sz, [GP, i32, i32, i32]),
         "sg_field_direct": (i32, [GP, i32, dp, vp, vp, vp, vp, i32, u32, vp, sz, vp]),
+        "sg_field_direct_noalloc": (i32, [GP, i32, dp, vp, vp, vp, vp, i32, u32, vp]),
         "sg_field_adjoint_workspace_bytes": (sz, [DP]),
         "sg_field_adjoint": (i32, [DP, vp, vp, vp, vp, vp, sz, vp]),
         "sg_ss_grad_H_workspace_bytes": (sz, [DP]),
@@ -114,7 +116,8 @@ EXPORTED = (
     "sg_ss_table_bytes", "sg_ss_table_workspace_bytes", "sg_ss_table",
     "sg_field_fft_workspace_bytes", "sg_field_fft", "sg_field_fft_profile", "sg_field_fft_tune",
     "sg_field_direct_workspace_bytes",
-    "sg_field_direct", "sg_potential_direct_workspace_bytes", "sg_potential_direct",
+    "sg_field_direct", "sg_field_direct_noalloc", "sg_potential_direct_workspace_bytes",
+    "sg_potential_direct",
     "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_ss_grad_H_workspace_bytes",
     "sg_ss_grad_H", "sg_eval_F", "sg_eval_G0", "sg_hsg",
     "sg_self_cell", "sg_release", "sg_status_string", "sg_version")
@@ -256,6 +259,15 @@ def field_direct(g: Grid, n_fluids, h, sigma, H, g_r, g_phi, dtype, flags, ws, w
                                 ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,
                                 _ptr(sigma), _ptr(H), _ptr(g_r), _ptr(g_phi), dtype, flags,
                                 _ptr(ws), ws_bytes, _stream(stream)), "sg_field_direct")
+
+
+def field_direct_noalloc(g: Grid, n_fluids, h, sigma, H, g_r, g_phi, dtype, flags, stream=None):
+    """sg_field_direct on the library's static scratch array (no workspace)."""
+    harr = (ctypes.c_double * 4)(*([float(v) for v in h] + [0.0] * (4 - len(h)))) if h is not None else None
+    _check(_lib.sg_field_direct_noalloc(ctypes.byref(g), n_fluids,
+                                        ctypes.cast(harr, ctypes.POINTER(ctypes.c_double)) if harr else None,
+                                        _ptr(sigma), _ptr(H), _ptr(g_r), _ptr(g_phi), dtype, flags,
+                                        _stream(stream)), "sg_field_direct_noalloc")
 
 
 def potential_direct_workspace_bytes(g: Grid, n_fluids, dtype, per_cell_H) -> int:

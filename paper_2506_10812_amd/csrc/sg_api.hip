@@ -2,6 +2,8 @@
 // sizing and dispatch.  No device work is enqueued before validation passes.
 #include <math.h>
 
+#include <mutex>
+
 #include "sg_adjoint.h"
 #include "sg_direct.h"
 #include "sg_fftpath.h"
@@ -268,9 +270,13 @@ sg_status sg_eval_G0(const void *d_x, void *d_G, int64_t n, sg_dtype dtype, void
     return sg_eval_G0_launch(d_x, d_G, n, dtype, (hipStream_t)stream);
 }
 
-sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
-                          const void *d_H, void *d_g_r, void *d_g_phi, sg_dtype dtype,
-                          uint32_t flags, void *d_ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+// Arguments of sg_field_direct other than the workspace; *need receives the
+// workspace size the call takes.
+static sg_status check_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
+                              const void *d_H, const void *d_g_r, const void *d_g_phi, sg_dtype dtype,
+                              uint32_t flags, size_t *need)
 {
     sg_status s = check_grid(grid);
     if (s != SG_OK) return s;
@@ -284,11 +290,70 @@ sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, co
         for (int f = 0; f < n_fluids; ++f)
             if (!finite_pos(h[f])) return SG_ERR_ARG;
     }
-    const size_t need = sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, d_H ? 1 : 0);
+    *need = sg_direct_ws_bytes(grid->n_r, grid->n_phi, n_fluids, dtype, d_H ? 1 : 0);
+    return SG_OK;
+}
+
+static const double k_ones[4] = {1.0, 1.0, 1.0, 1.0};  // h placeholder when d_H is given
+
+// The no-allocation variant's workspace: one static device array per GPU,
+// held from the library's load until the process ends.  In host code the
+// name `scratch` is a host-side stand-in, not a device address: the device
+// address is resolved once per device with hipGetSymbolAddress and only that
+// pointer is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SG_NOALLOC_SCRATCH_BYTES];
+
+#define SG_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SG_MAX_DEVICES];
+
+// Device address of the current device's scratch array (resolved on the
+// first call on that device, with that device current).
+static sg_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SG_MAX_DEVICES) return SG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SG_OK;
+}
+
+extern "C" {
+
+sg_status sg_field_direct(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
+                          const void *d_H, void *d_g_r, void *d_g_phi, sg_dtype dtype,
+                          uint32_t flags, void *d_ws, size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    sg_status s = check_direct(grid, n_fluids, h, d_sigma, d_H, d_g_r, d_g_phi, dtype, flags, &need);
+    if (s != SG_OK) return s;
     if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws & 255)) return SG_ERR_WORKSPACE;
-    static const double one[4] = {1.0, 1.0, 1.0, 1.0};
-    return sg_direct_launch(grid, n_fluids, d_H ? one : h, d_sigma, d_H, d_g_r, d_g_phi, dtype,
+    return sg_direct_launch(grid, n_fluids, d_H ? k_ones : h, d_sigma, d_H, d_g_r, d_g_phi, dtype,
                             flags, d_ws, (hipStream_t)stream);
+}
+
+sg_status sg_field_direct_noalloc(const sg_grid *grid, int n_fluids, const double *h, const void *d_sigma,
+                                  const void *d_H, void *d_g_r, void *d_g_phi, sg_dtype dtype,
+                                  uint32_t flags, void *stream)
+{
+    size_t need = 0;
+    sg_status s = check_direct(grid, n_fluids, h, d_sigma, d_H, d_g_r, d_g_phi, dtype, flags, &need);
+    if (s != SG_OK) return s;
+    if (need > SG_NOALLOC_SCRATCH_BYTES) return SG_ERR_SCRATCH;
+    void *ws = nullptr;
+    s = scratch_of_current_device(&ws);
+    if (s != SG_OK) return s;
+    // same kernels and workspace layout as sg_field_direct, on the static
+    // array: nothing in the direct sum reads workspace it has not written in
+    // the same call, so the previous call's contents need no clearing
+    return sg_direct_launch(grid, n_fluids, d_H ? k_ones : h, d_sigma, d_H, d_g_r, d_g_phi, dtype,
+                            flags, ws, (hipStream_t)stream);
 }
 
 // the FFT-path adjoint takes one or two groups
@@ -383,6 +448,9 @@ const char *sg_status_string(sg_status s)
     case SG_ERR_HIP: return "SG_ERR_HIP: HIP runtime error";
     case SG_ERR_WORKSPACE: return "SG_ERR_WORKSPACE: workspace missing or too small";
     case SG_ERR_TABLE: return "SG_ERR_TABLE: kernel table does not match";
+    case SG_ERR_SCRATCH:
+        return "SG_ERR_SCRATCH: the call needs more workspace than the no-allocation entry point's "
+               "static scratch (SG_NOALLOC_SCRATCH_BYTES per GPU)";
     }
     return "unknown sg_status";
 }

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(sg):
 
 
 def test_status_strings(sg):
-    for s in range(6):
+    for s in range(7):
         assert sg.status_string(s).startswith("SG_")
     assert sg.version() >= 1
 
@@ -302,3 +302,19 @@ def test_fft_path_group_limits(sg):
     assert sg.field_adjoint_workspace_bytes(d3) == 0
     assert sg.lib().sg_field_adjoint(ctypes.byref(d3), 256, 512, 768, None, 2048, 1 << 30,
                                      None) == sg.ERR_UNSUPPORTED
+
+
+def test_noalloc_direct_refuses_oversized_calls_before_device_work(sg):
+    """sg_field_direct_noalloc checks its workspace need against the static
+    scratch on the host: two float fluids at 1024 x 2048 (96 MiB) are refused
+    with SG_ERR_SCRATCH, one fluid (48 MiB) fits; invalid arguments come
+    back as SG_ERR_ARG.  No GPU is touched (the pointers are never used)."""
+    g = sg.grid(1024, 2048, 0.2, 5.0)
+    h = (ctypes.c_double * 4)(0.05, 0.005, 0.0, 0.0)
+    hp = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+    fake = ctypes.c_void_p(256)
+    assert sg.field_direct_workspace_bytes(g, 1, sg.F32, False) <= sg.NOALLOC_SCRATCH_BYTES
+    st = sg.lib().sg_field_direct_noalloc(ctypes.byref(g), 2, hp, fake, None, fake, fake, sg.F32, 0, None)
+    assert st == sg.ERR_SCRATCH
+    st = sg.lib().sg_field_direct_noalloc(ctypes.byref(g), 2, hp, None, None, fake, fake, sg.F32, 0, None)
+    assert st == sg.ERR_ARG
