@@ -5,7 +5,11 @@ pairs fused), one MI355X.
 A step is one sg_field_fft call (phi transform of Sigma, fused u transform /
 spectral multiply / inverse u transform, inverse phi transform) on inputs
 resident in HBM; the kernel spectra are built once beforehand (the paper
-precomputes the kernel once per simulation).  Prints one JSON line.
+precomputes the kernel once per simulation).  Every timed step starts with
+cold caches: a 512 MiB buffer is rewritten before it, outside its events
+(the disc's 118 MB would otherwise stay in the 256 MB Infinity Cache
+between steps); back-to-back (warm) numbers are reported beside it.
+Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
   python bench.py --copy-calibration   (plain 1 GiB device copy, for scaling
@@ -14,6 +18,8 @@ precomputes the kernel once per simulation).  Prints one JSON line.
                                         one JSON line; for its kernel trace)
   python bench.py --direct             (only the direct sums: FP64 64x128 and FP32
                                         256x512, one JSON line; for their VALU counters)
+  python bench.py --batch              (only the 64-disc batch: warm-up runs, then cold
+                                        runs after a cache flush; for its traffic counters)
   python bench.py --summarize-rocprof DIR
         (CPU only) turns the rocprofv3 CSV output of PROFILE_COMMANDS, run
         with DIR as their output root, into the text summaries in profiles/
@@ -30,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "SG field cells/s at 1024×2048 bi-fluid; %HBM roofline; rel err vs FP64"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass2_bifluid_1024x2048.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_passes_bifluid_1024x2048.json")
 # pass 2 of the two-fluid 1024 x 2048 disc, any tuned variant (radix order,
 # tile shape); the summaries use the variant launched most often, which is
 # the one the tuned plan runs
@@ -52,6 +58,19 @@ PROFILE_COMMANDS = {
               "python3 {repo}/bench.py --copy-calibration",
     "cwrite": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cwrite -o run -- "
               "python3 {repo}/bench.py --copy-calibration",
+    "p2_sq": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
+             "SQ_LDS_BANK_CONFLICT SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE --output-format csv "
+             "-d {out}/p2_sq -o run -- python3 {repo}/bench.py --steps 5 --warmup 2 --no-cpu --no-extra "
+             "--no-tune",
+    "b_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/b_kt -o run -- "
+            "python3 {repo}/bench.py --batch --steps 20 --warmup 5",
+    "b_sq": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
+            "SQ_LDS_BANK_CONFLICT SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE --output-format csv "
+            "-d {out}/b_sq -o run -- python3 {repo}/bench.py --batch --steps 5 --warmup 2",
+    "b_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/b_fetch -o run -- "
+               "python3 {repo}/bench.py --batch --steps 5 --warmup 2 --no-tune",
+    "b_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/b_write -o run -- "
+               "python3 {repo}/bench.py --batch --steps 5 --warmup 2 --no-tune",
     "ss_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/ss_kt -o run -- "
              "python3 {repo}/bench.py --semispectral",
     "dir_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/dir_kt -o run -- "
@@ -65,6 +84,7 @@ PROFILE_COMMANDS = {
 # build) and FP64 both issue at that rate: 78.6 TFLOP/s with FMA
 VALU_SIMDS, VALU_CLOCK_HZ, VALU_PEAK_TFLOPS = 1024, 2.4e9, 78.6
 COPY_BYTES = 4 << 28   # --copy-calibration copies 2^28 floats
+FLUSH_FLOATS = 1 << 27  # 512 MiB rewritten before a cold step (Infinity Cache: 256 MB)
 
 
 def kernel_source_hash():
@@ -135,8 +155,40 @@ def _last_json(path):
         return None
 
 
+def _kname(r):
+    return r["Kernel_Name"].split("(")[0].replace("void ", "")
+
+
+def _cold_dispatch_us(d, prefix, before):
+    """Mean duration (us) of the dispatches of kernels named `prefix...` whose
+    preceding dispatches (in start order) match the name prefixes `before`
+    (nearest first): e.g. pass 2 right after pass 1 right after the cache
+    flush, i.e. the pass 2 of a cold step."""
+    rows = _csv_rows(d, "_kernel_trace.csv")
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [_kname(r) for r in rows]
+    dur = []
+    for i, n in enumerate(names):
+        if not n.startswith(prefix) or i < len(before):
+            continue
+        if all(before[k] in names[i - 1 - k] for k in range(len(before))):
+            dur.append((int(rows[i]["End_Timestamp"]) - int(rows[i]["Start_Timestamp"])) / 1e3)
+    return (sum(dur) / len(dur) if dur else None), len(dur)
+
+
+def _counter_sums(d, prefix):
+    """{counter: [per-dispatch values]} over the dispatches of kernels named
+    `prefix...` (values summed over the counter's dimensions by rocprofv3)."""
+    out = {}
+    for r in _csv_rows(d, "_counter_collection.csv"):
+        if _kname(r).startswith(prefix):
+            out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
 def summarize_rocprof(out):
-    """Writes profiles/kernels_bifluid_1024x2048.md and the pass-2 traffic files."""
+    """Writes the summaries in profiles/ from the rocprofv3 output of
+    PROFILE_COMMANDS under `out` (plus each command's stdout in <key>.out)."""
     prof = os.path.join(ROOT, "profiles")
     os.makedirs(prof, exist_ok=True)
     cmd = {k: v.format(out="<out>", repo="<repo>") for k, v in PROFILE_COMMANDS.items()}
@@ -144,8 +196,10 @@ def summarize_rocprof(out):
     lines = ["# Kernel time, two-fluid 1024x2048 FFT path (bench.py workload)", "",
              "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output "
              "root):", "", "    " + cmd["kt"], "",
-             "Each step is one graph launch of the three passes; the run also launches the "
-             "passes outside the graph for bench.py's per-pass event timing.", "",
+             "The run tunes the plan, times warm steps (graph launches back to back), cold steps "
+             "(each after a 512 MiB cache flush, the headline) and cold steps pass by pass "
+             "(sg_field_fft_profile with reps = 1 after a flush), then warm passes back to back. "
+             "All dispatches of a kernel are averaged in the table.", "",
              "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share (%) |",
              "|---|---|---|---|---|---|"]
     for r in stats:
@@ -156,13 +210,15 @@ def summarize_rocprof(out):
     live = _last_json(os.path.join(out, "kt.out"))
     if live and "roofline" in live:
         rl = live["roofline"]
-        avg = [float(r["AverageNs"]) / 1e3 for r in stats
-               if r["Name"].split("(")[0].replace("void ", "") == rl["kernel_name"]]
-        if avg:
+        cold_us, ncold = _cold_dispatch_us(os.path.join(out, "kt"), rl["kernel_name"],
+                                           ["k_pass1", "FillFunctor"])
+        if cold_us:
             us = rl["kernel_ms"] * 1e3
-            lines += ["", f"bench.py's own HIP-event timing of `{rl['kernel_name']}` in the same "
-                          f"run (the roofline's kernel time): {us:.2f} us against the trace's "
-                          f"{avg[0]:.2f} us average ({abs(us - avg[0]) / avg[0] * 100:.1f} % apart)."]
+            lines += ["", f"Cold pass 2: the {ncold} dispatches of `{rl['kernel_name']}` that follow "
+                          f"pass 1 right after the cache flush (the cold steps, in and out of the "
+                          f"graph) average {cold_us:.2f} us in the trace; bench.py's own HIP-event "
+                          f"timing of the cold pass in the same run (the roofline's kernel time) is "
+                          f"{us:.2f} us ({abs(us - cold_us) / cold_us * 100:.1f} % apart)."]
     with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -170,13 +226,16 @@ def summarize_rocprof(out):
     cw, _, _ = _counter_mean(os.path.join(out, "cwrite"), "__amd_rocclr_copyBuffer", "WRITE_SIZE")
     f_scale = COPY_BYTES / (cf * 1024.0)
     w_scale = COPY_BYTES / (cw * 1024.0)
-    fk, nf_, kname = _counter_mean(os.path.join(out, "fetch"), DOMINANT_PREFIX, "FETCH_SIZE")
-    wk, nw_, kname_w = _counter_mean(os.path.join(out, "write"), DOMINANT_PREFIX, "WRITE_SIZE")
-    if kname_w != kname:
-        raise SystemExit(f"bench.py: FETCH and WRITE runs ran different variants ({kname}, {kname_w})")
-    read_b = fk * 1024.0 * f_scale
-    write_b = wk * 1024.0 * w_scale
-    alg = pass_bytes(1024, 2048, 2)["pass2"]
+    pb = pass_bytes(1024, 2048, 2)
+    per_pass = {}
+    for key, prefix in (("pass1", "k_pass1<"), ("pass2", DOMINANT_PREFIX), ("pass3", "k_pass3<")):
+        fk, nf_, kname = _counter_mean(os.path.join(out, "fetch"), prefix, "FETCH_SIZE")
+        wk, nw_, kname_w = _counter_mean(os.path.join(out, "write"), prefix, "WRITE_SIZE")
+        if kname_w != kname:
+            raise SystemExit(f"bench.py: FETCH and WRITE runs ran different variants ({kname}, {kname_w})")
+        per_pass[key] = (fk, wk, nf_, nw_, kname, fk * 1024.0 * f_scale, wk * 1024.0 * w_scale)
+    fk, wk, nf_, nw_, kname, read_b, write_b = per_pass["pass2"]
+    alg = pb["pass2"]
     tr = {"kernel": "pass2", "kernel_name": kname,
           "kernel_source_hash": kernel_source_hash(),
           "fetch_size_kib": round(fk, 1), "write_size_kib": round(wk, 1),
@@ -185,23 +244,36 @@ def summarize_rocprof(out):
           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
           "bytes_read": round(read_b), "bytes_written": round(write_b),
           "bytes_per_launch": round(read_b + write_b), "algorithmic_bytes": alg,
+          "passes": {k: {"kernel_name": v[4], "bytes_read": round(v[5]), "bytes_written": round(v[6]),
+                         "algorithmic_bytes": pb[k]} for k, v in per_pass.items()},
           "commands": [cmd["fetch"], cmd["write"], cmd["cfetch"], cmd["cwrite"]]}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(tr, fh, indent=1)
         fh.write("\n")
-    md = ["# HBM traffic of pass 2, two-fluid 1024x2048 (bench.py workload)", "",
+    md = ["# HBM traffic of the three passes, two-fluid 1024x2048 (bench.py workload)", "",
           "Commands (from /tmp, TMPDIR=/tmp):", ""] + \
          ["    " + cmd[k] for k in ("fetch", "write", "cfetch", "cwrite")] + \
          ["", f"Copy calibration (1 GiB device copy): FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE "
               f"{cw:.1f} KiB per launch, so FETCH_SIZE is scaled by {f_scale:.4f} and "
-              f"WRITE_SIZE by {w_scale:.4f}.", "",
-          f"`{kname}` per launch (mean of {nf_} / {nw_} dispatches): FETCH_SIZE "
-          f"{fk:.1f} KiB -> {read_b / 1e6:.2f} MB read, WRITE_SIZE {wk:.1f} KiB -> "
-          f"{write_b / 1e6:.2f} MB written; total {(read_b + write_b) / 1e6:.2f} MB against "
-          f"{alg / 1e6:.2f} MB algorithmic ({(read_b + write_b) / alg:.3f}x).", "",
-          f"Kernel sources hash: {tr['kernel_source_hash']}."]
-    with open(os.path.join(prof, "traffic_pass2_bifluid_1024x2048.md"), "w") as fh:
+              f"WRITE_SIZE by {w_scale:.4f}.  Counters count L2 traffic to and from the fabric "
+              f"(Infinity Cache hits included), so they do not depend on the cache's state.", "",
+          "| Pass | Kernel | Dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | Read (MB) | "
+          "Written (MB) | Total / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    for k, v in per_pass.items():
+        md.append(f"| {k[-1]} | `{v[4]}` | {v[2]} / {v[3]} | {v[0]:.1f} | {v[1]:.1f} | "
+                  f"{v[5] / 1e6:.2f} | {v[6] / 1e6:.2f} | {(v[5] + v[6]) / 1e6:.2f} / "
+                  f"{pb[k] / 1e6:.2f} MB = {(v[5] + v[6]) / pb[k]:.3f}x |")
+    md += ["", f"Kernel sources hash: {tr['kernel_source_hash']}."]
+    with open(os.path.join(prof, "traffic_passes_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
+    stale = os.path.join(prof, "traffic_pass2_bifluid_1024x2048.md")
+    if os.path.exists(stale):
+        os.remove(stale)
+
+    if os.path.isdir(os.path.join(out, "p2_sq")):
+        summarize_pass2_sq(out, prof, cmd)
+    if os.path.isdir(os.path.join(out, "b_fetch")) and os.path.isdir(os.path.join(out, "b_write")):
+        summarize_batch_traffic(out, prof, cmd, f_scale, w_scale, cf, cw)
     ss_dir = os.path.join(out, "ss_kt")
     if os.path.isdir(ss_dir):
         stats = _csv_rows(ss_dir, "_kernel_stats.csv")
@@ -223,6 +295,73 @@ def summarize_rocprof(out):
     if os.path.isdir(os.path.join(out, "dir_kt")) and os.path.isdir(os.path.join(out, "dir_valu")):
         summarize_direct(out, prof, cmd)
     print(json.dumps(tr))
+
+
+def summarize_pass2_sq(out, prof, cmd):
+    """profiles/sq_pass2_bifluid_1024x2048.md: VALU, LDS and occupancy counters
+    of pass 2 (per dispatch; rocprofv3's derived-metric formulas applied to
+    the raw counters)."""
+    v = _counter_sums(os.path.join(out, "p2_sq"), DOMINANT_PREFIX)
+    if not v:
+        return
+    m = {k: sum(x) / len(x) for k, x in v.items()}
+    n = len(v.get("SQ_WAVES", []))
+    cu, xcc = 256, 8
+    gui = m["GRBM_GUI_ACTIVE"] / xcc  # summed over the 8 XCDs by rocprofv3; per XCD
+    waves = m["SQ_WAVES"]
+    rows = [("waves per dispatch", f"{waves:.0f}"),
+            ("VALU instructions per wave", f"{m['SQ_INSTS_VALU'] / waves:.0f}"),
+            ("LDS instructions per wave", f"{m['SQ_INSTS_LDS'] / waves:.0f}"),
+            ("GPU-active cycles (GRBM_GUI_ACTIVE per XCD)", f"{gui:.0f}"),
+            ("VALUBusy = 100 SQ_ACTIVE_INST_VALU / CU_NUM / GRBM_GUI_ACTIVE",
+             f"{100 * m['SQ_ACTIVE_INST_VALU'] / cu / gui:.1f} %"),
+            ("VALU issue = 4 SQ_INSTS_VALU / (4 SIMDs x CU_NUM x GRBM_GUI_ACTIVE)",
+             f"{100 * 4 * m['SQ_INSTS_VALU'] / (4 * cu * gui):.1f} %"),
+            ("LDS active = 100 SQ_ACTIVE_INST_LDS / CU_NUM / GRBM_GUI_ACTIVE",
+             f"{100 * m['SQ_ACTIVE_INST_LDS'] / cu / gui:.1f} %"),
+            ("LDSBankConflict = 100 SQ_LDS_BANK_CONFLICT / GRBM_GUI_ACTIVE / CU_NUM",
+             f"{100 * m['SQ_LDS_BANK_CONFLICT'] / gui / cu:.2f} %"),
+            ("OccupancyPercent = 400 SQ_WAVE_CYCLES / GRBM_GUI_ACTIVE / CU_NUM / 32",
+             f"{400 * m['SQ_WAVE_CYCLES'] / gui / cu / 32:.1f} % (of 32 waves per CU)"),
+            ("SQ_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 4 SEs x 8 XCDs)",
+             f"{m['SQ_BUSY_CYCLES'] / (gui * 4 * xcc):.2f}")]
+    kname = [k for k in v][0]
+    lines = ["# Pass 2 execution counters, two-fluid 1024x2048 (bench.py workload)", "",
+             "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
+             "    " + cmd["p2_sq"], "",
+             f"Means over {n} dispatches of the pass-2 kernel (untuned plan).  rocprofv3 sums each "
+             "counter over its dimensions; GRBM_GUI_ACTIVE is divided by the 8 XCDs to give the "
+             "cycles of one XCD (the formulas take its maximum).  Raw means:", ""]
+    lines += [f"    {k} = {m[k]:.6g}" for k in sorted(m)]
+    lines += ["", "| Quantity | Value |", "|---|---|"] + [f"| {a} | {b} |" for a, b in rows]
+    with open(os.path.join(prof, "sq_pass2_bifluid_1024x2048.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_batch_traffic(out, prof, cmd, f_scale, w_scale, cf, cw):
+    """profiles/traffic_batch64.md: HBM bytes of one 64-disc batch run (all
+    pass kernels of the graph) against the algorithmic bytes."""
+    fetch = _counter_sums(os.path.join(out, "b_fetch"), "k_pass")
+    write = _counter_sums(os.path.join(out, "b_write"), "k_pass")
+    meta = _last_json(os.path.join(out, "b_fetch.out"))
+    if not fetch or not write or not meta:
+        return
+    runs = meta["graph_runs"]
+    rd = sum(fetch["FETCH_SIZE"]) * 1024.0 * f_scale / runs
+    wr = sum(write["WRITE_SIZE"]) * 1024.0 * w_scale / runs
+    alg, cells = meta["algorithmic_bytes"], meta["cells"]
+    lines = ["# HBM traffic of the 64-disc batch (bench.py --batch)", "",
+             "Commands (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
+             "    " + cmd["b_fetch"], "    " + cmd["b_write"], "",
+             f"Counters summed over every pass-kernel dispatch of the run and divided by its "
+             f"{runs} graph runs (untuned plan); scaled by the copy calibration of "
+             f"traffic_passes_bifluid_1024x2048.md (FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x "
+             f"{w_scale:.4f}).", "",
+             f"Per run: {rd / 1e6:.1f} MB read, {wr / 1e6:.1f} MB written, {(rd + wr) / 1e6:.1f} MB in "
+             f"all for {cells} cells = {(rd + wr) / cells:.1f} B/cell, against {alg / 1e6:.1f} MB "
+             f"algorithmic ({alg / cells:.1f} B/cell): {(rd + wr) / alg:.2f}x."]
+    with open(os.path.join(prof, "traffic_batch64.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def summarize_direct(out, prof, cmd):
@@ -307,6 +446,7 @@ def main():
     ap.add_argument("--summarize-rocprof", metavar="DIR")
     ap.add_argument("--semispectral", action="store_true")
     ap.add_argument("--direct", action="store_true")
+    ap.add_argument("--batch", action="store_true")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
@@ -342,6 +482,9 @@ def main():
     if args.direct:
         print(json.dumps(direct_measurement(sg, T, W, dev)))
         return
+    if args.batch:
+        print(json.dumps(batch_measurement(sg, T, W, dev, args.steps, args.warmup, not args.no_tune)))
+        return
 
     w = W.bifluid_fft()
     nr, nphi, nf = w["n_r"], w["n_phi"], len(w["h"])
@@ -358,40 +501,57 @@ def main():
     ms_untuned = sg.field_fft_profile(F.discs, F.ws, 20, stream=stream)
     tuned = F.tune(stream=stream) if not args.no_tune else []
 
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    # warm steps: graph launches back to back; the disc's 118 MB working set
+    # then stays in the 256 MB Infinity Cache (reported in extra only)
     for _ in range(args.warmup):
         F.run()
     torch.cuda.synchronize()
-    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
         F.run()
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
-    value = cells / (ms_step * 1e-3)
+    warm_ms = e0.elapsed_time(e1) / args.steps
 
-    # cold steps: a 512 MB buffer is rewritten between launches, evicting the
-    # caches (incl. the 256 MB Infinity Cache); median of single-launch times
-    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    # the timed steps (the headline): every step starts cold.  Before each
+    # one a 512 MiB buffer is rewritten (outside the step's events), which
+    # evicts the L2s and the Infinity Cache; each step is timed alone with
+    # HIP events on the launch stream and the K step times are summed
+    flush = torch.empty(FLUSH_FLOATS, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        flush.fill_(1.0)
+        F.run()
+    print(f"bench: timing {args.steps} cold steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     cold = []
-    for _ in range(30):
+    for _ in range(args.steps):
         flush.fill_(1.0)
         e0.record(stream)
         F.run()
         e1.record(stream)
-        torch.cuda.synchronize()
+        e1.synchronize()
         cold.append(e0.elapsed_time(e1))
-    del flush
-    cold_ms = float(np.median(cold))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = float(np.sum(cold)) / args.steps
+    value = cells / (ms_step * 1e-3)
 
-    # per-pass durations with HIP events on the launch stream (no graph)
+    # one cold step pass by pass (sg_field_fft_profile with reps = 1 runs the
+    # passes once each, in order, with events between them), repeated after
+    # a flush each time: the roofline's kernel time is pass 2's mean here
+    reps_c = max(10, min(args.steps, 50))
+    cp = []
+    for _ in range(reps_c):
+        flush.fill_(1.0)
+        cp.append(sg.field_fft_profile(F.discs, F.ws, 1, stream=stream))
+    ms_pass = [float(v) for v in np.mean(np.array(cp), axis=0)]
+    del flush
+    # warm per-pass durations (each pass's launches back to back)
     reps = max(10, min(args.steps, 200))
-    ms_pass = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
+    ms_pass_warm = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
     pb = pass_bytes(nr, nphi, nf)
     names = ["pass1", "pass2", "pass3"]
     dom = int(np.argmax(ms_pass))
@@ -409,10 +569,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom_name, "kernel_name": pass2_kernel_name(nr, nf, tuned) if dom == 1 else None,
-                "kernel_ms": round(ms_pass[dom], 5),
+                "kernel_ms": round(ms_pass[dom], 5), "cache": "cold",
                 "algorithmic_bytes": pb[dom_name]}
 
-    # accuracy vs the FP64 oracle on 16384 seeded cells (also the CPU baseline)
+    # accuracy vs the FP64 oracle on 16384 seeded cells (also the CPU baseline:
+    # its table build, done once per disc like the library's, is timed on its
+    # own with a one-cell call and taken out of the per-cell rate)
     cpu = None
     acc = None
     if not args.no_cpu:
@@ -421,22 +583,35 @@ def main():
         sig32 = F.sigma[0].double().cpu().numpy()
         print(f"bench: CPU oracle on {len(idx)} sampled cells", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
+        O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, targets=idx[:1])
+        build_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
         rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, targets=idx)
         cpu_s = time.perf_counter() - t0
         gr = F.g_r[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
         gp = F.g_phi[0].double().cpu().numpy().reshape(nf, -1)[:, idx]
         acc = {f"{['gas', 'dust'][b]}_{c}": float(np.linalg.norm(x[b] - y[b]) / np.linalg.norm(y[b]))
                for b in range(nf) for c, x, y in (("g_r", gr, rr), ("g_phi", gp, rp))}
-        cpu = {"value": round(len(idx) / cpu_s, 2), "unit": "cells/s", "cores": O.threads(),
+        sum_s = max(cpu_s - build_s, 1e-9)
+        cpu = {"value": round((len(idx) - 1) / sum_s, 2), "unit": "cells/s", "cores": O.threads(),
                "kind": "oracle",
-               "sample": f"{len(idx)} seeded cells of the same disc, offset-table FP64 oracle "
-                         f"(includes its table build), {cpu_s:.1f} s"}
+               "sample": f"{len(idx)} seeded cells of the same disc, offset-table FP64 oracle: "
+                         f"{cpu_s:.1f} s in all, of which its table build (all four pairs, "
+                         f"once per disc, timed alone) {build_s:.1f} s; value = cells per second "
+                         f"of the summation"}
 
     extra = {"table_build_s": round(table_s, 3), "wall_s_timed": round(wall, 3),
-             "cold_ms_per_step_median": round(cold_ms, 5),
-             "cold_cells_per_s": round(cells / (cold_ms * 1e-3), 1),
-             "ms_per_pass": [round(v, 5) for v in ms_pass],
-             "ms_per_pass_untuned": [round(v, 5) for v in ms_untuned],
+             "cold_ms_per_step_median": round(float(np.median(cold)), 5),
+             "warm_ms_per_step": round(warm_ms, 5),
+             "warm_cells_per_s": round(cells / (warm_ms * 1e-3), 1),
+             "warm_path_hbm_frac": round(pb["path"] / (warm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "ms_per_pass_cold": [round(v, 5) for v in ms_pass],
+             "ms_per_pass_warm": [round(v, 5) for v in ms_pass_warm],
+             "ms_per_pass_warm_untuned": [round(v, 5) for v in ms_untuned],
+             "pass_hbm_frac_cold": [round(pb[k] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                    for k, t in zip(names, ms_pass)],
+             "pass_hbm_frac_warm": [round(pb[k] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                    for k, t in zip(names, ms_pass_warm)],
              "tuned": [{k: r[k] for k in ("pass", "length", "small_radix_first", "groups_per_wg", "cluster",
                                           "candidates", "rejected")} for r in tuned],
              "path_algorithmic_bytes": pb["path"],
@@ -537,6 +712,40 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     return out
 
 
+def batch_measurement(sg, T, W, dev, steps, warmup, tune):
+    """The 64-disc batch alone: `warmup` graph runs, then `steps` runs each
+    after a cache flush (timed alone with HIP events); graph_runs counts
+    every run, for per-run counter totals."""
+    import numpy as np
+    import torch
+    discs = W.batch64()
+    Fb = T.FFTField(discs, device=dev)
+    for i, d in enumerate(discs):
+        Fb.set_sigma(i, d["sigma"])
+    if tune:
+        Fb.tune()
+    for _ in range(warmup):
+        Fb.run()
+    flush = torch.empty(FLUSH_FLOATS, dtype=torch.float32, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(steps):
+        flush.fill_(1.0)
+        e0.record()
+        Fb.run()
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    cells = sum(d["n_r"] * d["n_phi"] for d in discs)
+    byts = sum(pass_bytes(d["n_r"], d["n_phi"], 1)["path"] for d in discs)
+    m = float(np.mean(ms))
+    return {"workload": "64 uneven single-fluid discs", "cells": cells, "algorithmic_bytes": byts,
+            "graph_runs": warmup + steps, "cold_ms": round(m, 4),
+            "cells_per_s": round(cells / m * 1e3, 1),
+            "path_hbm_frac": round(byts / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def extra_measurements(sg, T, W, dev):
     """Secondary numbers: 64-disc batch, adjoint, FP64 direct sum, the
     semi-spectral path."""
@@ -566,6 +775,17 @@ def extra_measurements(sg, T, W, dev):
     Fb.tune()
     tune_s = time.perf_counter() - t0
     ms = timed(Fb.run, 50)
+    flush = torch.empty(FLUSH_FLOATS, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(20):
+        flush.fill_(1.0)
+        e0.record()
+        Fb.run()
+        e1.record()
+        e1.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    del flush
+    ms_cold = sum(cold) / len(cold)
     cells = sum(d["n_r"] * d["n_phi"] for d in discs)
     byts = sum(pass_bytes(d["n_r"], d["n_phi"], 1)["path"] for d in discs)
     # the same discs one call each (plain single-disc path)
@@ -582,8 +802,10 @@ def extra_measurements(sg, T, W, dev):
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / 10
     res["batch64"] = {"cells": cells, "ms": round(ms, 4), "ms_untuned": round(ms_untuned, 4),
-                      "tune_s": round(tune_s, 2), "cells_per_s": round(cells / ms * 1e3, 1),
+                      "ms_cold": round(ms_cold, 4), "tune_s": round(tune_s, 2),
+                      "cells_per_s": round(cells / ms * 1e3, 1),
                       "path_hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "path_hbm_frac_cold": round(byts / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "looped_single_disc_ms": round(ms_loop, 4),
                       "speedup_vs_looped": round(ms_loop / ms, 3)}
     del Fb, singles

@@ -22,8 +22,8 @@
  *   layout     every device array is row-major [fluid][i_r][j_phi] with phi
  *              fastest; fluid 0 is gas, fluid 1 dust.  n_fluids is 1 to 4
  *              scale-height groups (the multi-fluid case of Sect. 5.2: all
- *              F^2 ordered pairs) on every path; on the FFT path beyond two
- *              groups n_r <= 1024, and its adjoint takes one or two.
+ *              F^2 ordered pairs) on every path (adjoints included); on the
+ *              FFT path beyond two groups n_r <= 1024.
  *   pairs      (a -> b) is source fluid a acting on target fluid b; a
  *              two-fluid disc has the four ordered pairs gg, dg, gd, dd
  *              (Sect. 2.2 lists the four combinations).
@@ -33,8 +33,9 @@
  *   ownership  every device buffer is allocated and owned by the caller; the
  *              library reads and writes only the buffers passed in.  The only
  *              device memory the library owns is a per-signature cache of
- *              batch descriptors and instantiated HIP graphs (sg_field_fft);
- *              sg_release() frees it.
+ *              batch descriptors and instantiated HIP graphs (sg_field_fft;
+ *              sg_release() frees it) and the static scratch array of
+ *              sg_field_direct_noalloc.
  *   streams    `stream` is a hipStream_t passed as void* (NULL = default
  *              stream).  Every call is asynchronous on that stream unless
  *              stated otherwise; buffers must stay valid until it completes.
@@ -259,9 +260,13 @@ sg_status sg_field_fft(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_
  * pass 3's, with HIP events between the groups on `stream`; waits for
  * completion (synchronous) and writes the mean milliseconds per launch of
  * pass 1 (phi transform), pass 2 (u transform + spectral multiply + inverse
- * u transform) and pass 3 (inverse phi transform) to ms_per_pass[3].  The
- * outputs hold a complete result afterwards.  For measurement; reps in
- * [1, 10000]. */
+ * u transform) and pass 3 (inverse phi transform) to ms_per_pass[3].  With
+ * reps == 1 the preliminary complete run is left out and every launch of
+ * one step runs once, in order, with events attached to the launch itself
+ * (the kernel's own start and end): ms_per_pass then holds each pass's
+ * summed kernel time, and a caller that evicts the caches first times one
+ * cold step pass by pass.  The outputs hold a complete result afterwards.
+ * For measurement; reps in [1, 10000]. */
 sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, size_t ws_bytes,
                                void *stream, int reps, float *ms_per_pass);
 
@@ -406,8 +411,8 @@ sg_status sg_hsg(int64_t n, int n_fluids, const double *d_H, const double *d_Q, 
  * transform); d_dh is taken at the group densities, summed in the
  * forward's order.  SG_INDIRECT (FFT path): the transpose of the star's pull
  * is added to d_dsigma (its coefficient's h_a derivative to d_dh), from two
- * double reductions over lam and Sigma in a fixed order.  FFT-path discs
- * with three or four groups return SG_ERR_UNSUPPORTED.
+ * double reductions over lam and Sigma in a fixed order.  Every group count
+ * of the forward (one to four) is taken.
  * d_ws: sg_field_adjoint_workspace_bytes() bytes.  Asynchronous.
  * --------------------------------------------------------------------- */
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc);
@@ -462,6 +467,11 @@ sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, 
 
 /* Frees cached graphs and descriptor tables (synchronises the device). */
 void sg_release(void);
+
+/* Number of batch signatures (discs' shapes and buffer addresses, workspace,
+ * device) whose plan and graph sg_field_fft currently caches; a caller that
+ * keeps its buffers sees it stay constant after the first call. */
+int sg_field_fft_cache_entries(void);
 
 const char *sg_status_string(sg_status s);
 int sg_version(void);

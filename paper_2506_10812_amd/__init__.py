@@ -100,6 +100,7 @@ def _load():
         "sg_potential_direct": (i32, [GP, i32, dp, vp, vp, vp, i32, u32, vp, sz, vp]),
         "sg_self_cell": (i32, [GP, dp, dp, i32, i32, vp, vp]),
         "sg_release": (None, []),
+        "sg_field_fft_cache_entries": (i32, []),
         "sg_status_string": (ctypes.c_char_p, [i32]),
         "sg_version": (i32, []),
     }
@@ -120,7 +121,7 @@ EXPORTED = (
     "sg_potential_direct",
     "sg_field_adjoint_workspace_bytes", "sg_field_adjoint", "sg_ss_grad_H_workspace_bytes",
     "sg_ss_grad_H", "sg_eval_F", "sg_eval_G0", "sg_hsg",
-    "sg_self_cell", "sg_release", "sg_status_string", "sg_version")
+    "sg_self_cell", "sg_release", "sg_field_fft_cache_entries", "sg_status_string", "sg_version")
 
 
 def lib():
@@ -319,6 +320,11 @@ def self_cell(g: Grid, ha, hb, which, out, stream=None):
     b = (ctypes.c_double * n)(*[float(v) for v in hb])
     _check(_lib.sg_self_cell(ctypes.byref(g), a, b, n, which, _ptr(out), _stream(stream)),
            "sg_self_cell")
+
+
+def field_fft_cache_entries() -> int:
+    """Batch signatures whose plan and graph sg_field_fft keeps cached."""
+    return int(_lib.sg_field_fft_cache_entries())
 
 
 def release():

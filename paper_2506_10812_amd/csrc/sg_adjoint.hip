@@ -76,7 +76,30 @@ __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_lam(AdjDev A)
                     A.lt + (b * 2 + 1) * fs, i, nr, TwTable{A.D.tw_phi}, t, pl, valid);
 }
 
-// pass 1 on Sigma (only when dh is requested): same pairing as the forward
+// Row pairs of the phi transforms of Sigma (adjoint pass 1) and dSigma (pass
+// 3): fluid pairs (2p, 2p + 1) row by row, then, for an odd fluid count, the
+// last fluid's rows 2q, 2q + 1 (an odd last row pairs with itself).
+template <int NF> __host__ __device__ inline int adj_pairs(int nr)
+{
+    return (NF / 2) * nr + (NF % 2 ? (nr + 1) / 2 : 0);
+}
+
+template <int NF> __device__ inline void adj_pair(int j, int nr, int &f1, int &f2, int &i1, int &i2)
+{
+    const int paired = (NF / 2) * nr;
+    if (j < paired) {
+        f1 = 2 * (j / nr);
+        f2 = f1 + 1;
+        i1 = i2 = j % nr;
+    } else {
+        const int q = j - paired;
+        f1 = f2 = NF - 1;
+        i1 = 2 * q;
+        i2 = min(2 * q + 1, nr - 1);
+    }
+}
+
+// pass 1 on Sigma (only when dh is requested)
 template <int N, int NF>
 __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_sig(AdjDev A)
 {
@@ -92,10 +115,10 @@ __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_sig(AdjDev A)
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     const int j = valid ? idx : 0;
-    const int i1 = NF == 2 ? j : 2 * j, i2 = NF == 2 ? j : 2 * j + 1;
-    const int f2 = NF == 2 ? 1 : 0;
-    phi_fwd_pair<N>(A.D.sigma + (size_t)i1 * N, A.D.sigma + f2 * plane + (size_t)i2 * N, A.st, i1,
-                    A.st + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, t, pl, valid);
+    int f1, f2, i1, i2;
+    adj_pair<NF>(j, nr, f1, f2, i1, i2);
+    phi_fwd_pair<N>(A.D.sigma + f1 * plane + (size_t)i1 * N, A.D.sigma + f2 * plane + (size_t)i2 * N,
+                    A.st + f1 * fs, i1, A.st + f2 * fs, i2, nr, TwTable{A.D.tw_phi}, t, pl, valid);
 }
 
 // pass 2: column m.  dSigma^_a = sum_{b,c} conj(K'_c^{ab}) lam^_{b,c}; with DH,
@@ -201,6 +224,107 @@ __global__ void __launch_bounds__(AdjShape<NU>::WGS) k_adj_col(AdjDev A)
                 double s = 0.0;
                 for (int u = 0; u < T; ++u) s += red[f * S::WGS + g * T + u];
                 A.part[(size_t)m * NF + f] = s;
+            }
+        }
+    }
+}
+
+// pass 2 with three or four groups: the same sums taken target by target, so
+// that only one lam^ (and, with DH, one Sigma^) transform is held at a time
+// next to the NF accumulators: for each (b, c) the transform of lam_{b,c}
+// is added to every dSigma^_a with conj(K'_c^{ab}); with DH the Parseval
+// partials of lam^_{b,c} against D' Sigma^_a are formed with Sigma^_a
+// transformed again for each (b, c) (arithmetic traded for registers).
+template <int NU, int NF, bool DH>
+__global__ void __launch_bounds__(AdjShape<NU>::WGS) k_adj_col_many(AdjDev A)
+{
+    using S = AdjShape<NU>;
+    constexpr int P = S::P, T = S::T, G = S::G;
+    constexpr int W = LdsPlane<float>::elems(NU);
+    constexpr int NR = NU / 2;
+    __shared__ __attribute__((aligned(16))) float2 lds[W * G];
+    __shared__ double red[DH ? S::WGS * NF : 1];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    bool none, valid;
+    const int m = adj_job(G, S::K, g, none, A.count, valid);
+    if (none) return;
+    LdsPlane<float> pl{lds + W * g};
+    const TwTable tw{A.D.tw_u};
+    const size_t fs = sg_blk_field_elems(A.D.nphi, NR);
+    const int mm = valid ? m : 0;
+    const size_t kk = NR + 1;
+    const float2 *col = A.D.spec + (size_t)mm * (NF * NF) * 2 * kk;
+    const float2 *dcol = DH ? A.D.dspec + (size_t)mm * (NF * NF) * 4 * kk : nullptr;
+    float2 acc[NF][P];
+    double dh[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+        dh[a] = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[a][p] = make_float2(0.f, 0.f);
+    }
+    for (int b = 0; b < NF; ++b)
+        for (int c = 0; c < 2; ++c) {
+            float2 lh[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                lh[p] = make_float2(0.f, 0.f);
+                if (valid && p < P / 2) lh[p] = A.lt[(b * 2 + c) * fs + sg_blk_index(mm, t + T * p, NR)];
+            }
+            fft<NU, false>(lh, t, pl, tw);
+#pragma unroll
+            for (int a = 0; a < NF; ++a)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    // conj(K) * lam^
+                    const float2 K = kspec<NU>(col + ((a * NF + b) * 2 + c) * kk, t + T * p, c);
+                    acc[a][p].x += K.x * lh[p].x + K.y * lh[p].y;
+                    acc[a][p].y += K.x * lh[p].y - K.y * lh[p].x;
+                }
+            if constexpr (DH) {
+                for (int a = 0; a < NF; ++a) {
+                    float2 sh[P];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        sh[p] = make_float2(0.f, 0.f);
+                        if (valid && p < P / 2) sh[p] = A.st[a * fs + sg_blk_index(mm, t + T * p, NR)];
+                    }
+                    fft<NU, false>(sh, t, pl, tw);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const int k = t + T * p;
+                        // q = D' Sigma^ ; Re(conj(lam^) q)
+                        const double lr = lh[p].x, li = lh[p].y;
+                        const double sr = sh[p].x, si = sh[p].y;
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            const float2 Dk = kspec<NU>(dcol + (((a * NF + b) * 2 + d) * 2 + c) * kk, k, c);
+                            const double qr = Dk.x * sr - Dk.y * si, qi = Dk.x * si + Dk.y * sr;
+                            const double v = lr * qr + li * qi;
+                            if (d == 0) dh[a] += v;
+                            else dh[b] += v;
+                        }
+                    }
+                }
+            }
+        }
+    for (int a = 0; a < NF; ++a) {
+        fft<NU, true>(acc[a], t, pl, tw);
+        if (valid) {
+#pragma unroll
+            for (int p = 0; p < P / 2; ++p) A.dt[a * fs + sg_blk_index(mm, t + T * p, NR)] = acc[a][p];
+        }
+    }
+    if constexpr (DH) {
+        const double wm = (mm == 0 || mm == A.D.nphi / 2) ? 1.0 : 2.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) red[f * S::WGS + threadIdx.x] = valid ? wm * dh[f] : 0.0;
+        __syncthreads();
+        if (t == 0 && valid) {
+            for (int f = 0; f < NF; ++f) {
+                double sm = 0.0;
+                for (int u = 0; u < T; ++u) sm += red[f * S::WGS + g * T + u];
+                A.part[(size_t)m * NF + f] = sm;
             }
         }
     }
@@ -319,20 +443,8 @@ __global__ void __launch_bounds__(AdjShape<N>::WGS) k_adj_out(AdjDev A)
     const size_t fs = sg_blk_field_elems(N, nr);
     const size_t plane = (size_t)nr * N;
     const int j = valid ? idx : 0;
-    // jobs: fluid pairs (2p, 2p + 1) row by row, then for an odd fluid count
-    // the last fluid's rows 2j, 2j + 1 (an odd last row pairs with itself)
-    const int paired = (NF / 2) * nr;
     int f1, f2, i1, i2;
-    if (j < paired) {
-        f1 = 2 * (j / nr);
-        f2 = f1 + 1;
-        i1 = i2 = j % nr;
-    } else {
-        const int q = j - paired;
-        f1 = f2 = NF - 1;
-        i1 = 2 * q;
-        i2 = min(2 * q + 1, nr - 1);
-    }
+    adj_pair<NF>(j, nr, f1, f2, i1, i2);
     phi_inv_pair<N>(A.dt + f1 * fs, i1, A.dt + f2 * fs, i2, nr, TwTable{A.D.tw_phi},
                     A.dsig + f1 * plane + (size_t)i1 * N, A.dsig + f2 * plane + (size_t)i2 * N, t, pl, valid);
 }
@@ -361,7 +473,7 @@ __global__ void k_adj_dh_reduce(const double *part, int ncol, int nf, double *dh
 // and their sum, then block partials of the dL/dh sums per fluid.
 static size_t adj_ind_bytes()
 {
-    return sg_align256(sizeof(double2) * (SG_ADJ_IND_BLOCKS + 1)) + sg_align256(sizeof(double) * SG_ADJ_IND_BLOCKS * 2);
+    return sg_align256(sizeof(double2) * (SG_ADJ_IND_BLOCKS + 1)) + sg_align256(sizeof(double) * SG_ADJ_IND_BLOCKS * 4);
 }
 
 static size_t adj_base_bytes(const sg_disc &d)
@@ -437,7 +549,7 @@ __global__ void __launch_bounds__(256) k_adj_ind_sig(const sg_table_header *hd, 
     __shared__ double ra[256], rb[256];
     const double dphi = 2.0 * SG_PI / nphi;
     const double2 L = *LAB;
-    double s0 = 0.0, s1 = 0.0;
+    double sa[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < nf * N; k += (int64_t)gridDim.x * 256) {
         const int a = (int)(k / N);
         double sp, cp;
@@ -445,15 +557,19 @@ __global__ void __launch_bounds__(256) k_adj_ind_sig(const sg_table_header *hd, 
         const double cs = L.x * cp + L.y * sp;
         dsig[k] += (float)(hd->ind_coef[a] * cs);
         if (want_dh) {
-            if (a == 0) s0 += (double)sig[k] * cs;
-            else s1 += (double)sig[k] * cs;
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                if (a == f) sa[f] += (double)sig[k] * cs;
         }
     }
     if (!want_dh) return;  // uniform across the launch
-    adj_block_sum2(s0, s1, ra, rb);
-    if (threadIdx.x == 0) {
-        spart[2 * blockIdx.x] = s0;
-        spart[2 * blockIdx.x + 1] = s1;
+    for (int f = 0; f < nf; f += 2) {
+        __syncthreads();  // ra, rb free again
+        adj_block_sum2(sa[f], sa[f + 1], ra, rb);
+        if (threadIdx.x == 0) {
+            spart[4 * blockIdx.x + f] = sa[f];
+            spart[4 * blockIdx.x + f + 1] = sa[f + 1];
+        }
     }
 }
 
@@ -465,7 +581,7 @@ __global__ void k_adj_ind_dh(const sg_table_header *hd, const double *spart, int
     const double du = log(hd->r_max / hd->r_min) / hd->n_r, dphi = 2.0 * SG_PI / hd->n_phi;
     for (int a = 0; a < nf; ++a) {
         double S = 0.0;
-        for (int b = 0; b < nb; ++b) S += spart[2 * b + a];
+        for (int b = 0; b < nb; ++b) S += spart[4 * b + a];
         const double h = hd->h[a], x = 0.25 / (h * h);
         double F, dF;
         sg_F64_dF(x, w, F, dF);
@@ -598,7 +714,7 @@ static sg_status adj_launch(AdjDev A, bool dh, double *d_dh, int ncol, hipStream
     hipLaunchKernelGGL(k_adj_lam<NPHI>, dim3(nwg_for<NPHI>(A.count)), dim3(AdjShape<NPHI>::WGS), 0,
                        s, A);
     SG_HIP(hipGetLastError());
-    const int pairs = NF == 2 ? nr : nr / 2;
+    const int pairs = adj_pairs<NF>(nr);
     if (dh) {
         A.count = pairs;
         hipLaunchKernelGGL((k_adj_sig<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)),
@@ -606,12 +722,21 @@ static sg_status adj_launch(AdjDev A, bool dh, double *d_dh, int ncol, hipStream
         SG_HIP(hipGetLastError());
     }
     A.count = ncol;
-    if (dh)
-        hipLaunchKernelGGL((k_adj_col<NU, NF, true>), dim3(nwg_for<NU>(ncol)),
-                           dim3(AdjShape<NU>::WGS), 0, s, A);
-    else
-        hipLaunchKernelGGL((k_adj_col<NU, NF, false>), dim3(nwg_for<NU>(ncol)),
-                           dim3(AdjShape<NU>::WGS), 0, s, A);
+    if constexpr (NF <= 2) {
+        if (dh)
+            hipLaunchKernelGGL((k_adj_col<NU, NF, true>), dim3(nwg_for<NU>(ncol)),
+                               dim3(AdjShape<NU>::WGS), 0, s, A);
+        else
+            hipLaunchKernelGGL((k_adj_col<NU, NF, false>), dim3(nwg_for<NU>(ncol)),
+                               dim3(AdjShape<NU>::WGS), 0, s, A);
+    } else {
+        if (dh)
+            hipLaunchKernelGGL((k_adj_col_many<NU, NF, true>), dim3(nwg_for<NU>(ncol)),
+                               dim3(AdjShape<NU>::WGS), 0, s, A);
+        else
+            hipLaunchKernelGGL((k_adj_col_many<NU, NF, false>), dim3(nwg_for<NU>(ncol)),
+                               dim3(AdjShape<NU>::WGS), 0, s, A);
+    }
     SG_HIP(hipGetLastError());
     A.count = pairs;
     hipLaunchKernelGGL((k_adj_out<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)),
@@ -638,7 +763,9 @@ static sg_status adj_nu(int nu, AdjDev A, bool dh, double *d_dh, int ncol, hipSt
     case 512: return adj_launch<NPHI, 512, NF>(A, dh, d_dh, ncol, s);
     case 1024: return adj_launch<NPHI, 1024, NF>(A, dh, d_dh, ncol, s);
     case 2048: return adj_launch<NPHI, 2048, NF>(A, dh, d_dh, ncol, s);
-    case 4096: return adj_launch<NPHI, 4096, NF>(A, dh, d_dh, ncol, s);
+    case 4096:
+        if constexpr (NF <= 2) return adj_launch<NPHI, 4096, NF>(A, dh, d_dh, ncol, s);
+        else return SG_ERR_UNSUPPORTED;  // beyond two groups n_r <= 1024
     }
     return SG_ERR_UNSUPPORTED;
 }
@@ -660,7 +787,7 @@ static sg_status adj_ss_launch(AdjDev A, int m0, int ncol, hipStream_t s)
                            ncol);
         SG_HIP(hipGetLastError());
     }
-    const int pairs = (NF / 2) * nr + (NF % 2 ? (nr + 1) / 2 : 0);
+    const int pairs = adj_pairs<NF>(nr);
     A.count = pairs;
     hipLaunchKernelGGL((k_adj_out<NPHI, NF>), dim3(nwg_for<NPHI>(pairs)), dim3(AdjShape<NPHI>::WGS), 0, s, A);
     SG_HIP(hipGetLastError());
@@ -762,8 +889,13 @@ sg_status sg_adjoint_run(const sg_disc &d, const float *lam_r, const float *lam_
     const int ncol = nphi / 2 + 1;
     o += sg_align256(sizeof(double) * ncol * nf);
     const bool want_dh = dh != nullptr;
-    const sg_status st = nf == 1 ? adj_phi<1>(nphi, 2 * nr, A, want_dh, dh, ncol, s)
-                                 : adj_phi<2>(nphi, 2 * nr, A, want_dh, dh, ncol, s);
+    sg_status st = SG_ERR_UNSUPPORTED;
+    switch (nf) {
+    case 1: st = adj_phi<1>(nphi, 2 * nr, A, want_dh, dh, ncol, s); break;
+    case 2: st = adj_phi<2>(nphi, 2 * nr, A, want_dh, dh, ncol, s); break;
+    case 3: st = adj_phi<3>(nphi, 2 * nr, A, want_dh, dh, ncol, s); break;
+    case 4: st = adj_phi<4>(nphi, 2 * nr, A, want_dh, dh, ncol, s); break;
+    }
     if (st != SG_OK || !(d.flags & SG_INDIRECT)) return st;
     return adjoint_indirect(d, lam_r, lam_p, dsig, dh, o, s);
 }

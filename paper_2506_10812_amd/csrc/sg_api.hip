@@ -356,10 +356,11 @@ sg_status sg_field_direct_noalloc(const sg_grid *grid, int n_fluids, const doubl
                             flags, ws, (hipStream_t)stream);
 }
 
-// the FFT-path adjoint takes one or two groups
+// the FFT-path adjoint takes the forward's group counts (beyond two groups
+// n_r <= 1024, as the forward)
 static bool adjoint_groups_ok(const sg_disc &d)
 {
-    return (d.flags & SG_SEMI_SPECTRAL) || d.fluids.n_fluids <= 2;
+    return (d.flags & SG_SEMI_SPECTRAL) || fft_groups_ok(&d.grid, &d.fluids);
 }
 
 size_t sg_field_adjoint_workspace_bytes(const sg_disc *disc)
@@ -438,6 +439,8 @@ sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, 
 }
 
 void sg_release(void) { sg_fft_release(); }
+
+int sg_field_fft_cache_entries(void) { return sg_fft_cache_entries(); }
 
 const char *sg_status_string(sg_status s)
 {

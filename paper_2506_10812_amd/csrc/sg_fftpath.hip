@@ -9,6 +9,8 @@
 #include <mutex>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "sg_fftpath.h"
 #include "sg_semispec.h"
 #include "sg_passes.h"
@@ -860,6 +862,77 @@ static sg_status enqueue(const Cached &C, hipStream_t s)
     return SG_OK;
 }
 
+// Graph capture of a plan: the launch classes of one pass (discs of other
+// transform lengths or fluid counts) do not depend on each other, so each
+// pass forks them onto parallel branches of the graph (auxiliary capture
+// streams joined back before the next pass), and classes whose kernels are
+// too small to fill the GPU on their own (short transforms, few rows) run
+// side by side instead of one after the other.  The caller creates the
+// auxiliary streams and events (fork_resources) before the capture and
+// destroys them after it ends.
+struct ForkRes {
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev;
+    ~ForkRes()
+    {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto a : aux)
+            if (a) (void)hipStreamDestroy(a);
+    }
+};
+
+static sg_status fork_resources(const Cached &C, ForkRes &R)
+{
+    const auto &Ls = C.plan.launches;
+    size_t widest = 1, nev = 0;
+    for (size_t i = 0; i < Ls.size();) {
+        size_t j = i;
+        while (j < Ls.size() && Ls[j].pass == Ls[i].pass) ++j;
+        widest = std::max(widest, j - i);
+        if (j - i > 1) nev += j - i;
+        i = j;
+    }
+    R.aux.assign(widest - 1, nullptr);
+    R.ev.assign(nev, nullptr);
+    for (auto &a : R.aux) SG_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    for (auto &e : R.ev) SG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return SG_OK;
+}
+
+static sg_status enqueue_forked(const Cached &C, hipStream_t s, const ForkRes &R)
+{
+    const auto &Ls = C.plan.launches;
+    const DiscDev *dd = (const DiscDev *)C.dmem;
+    const WJob *wj = cached_wjobs(C);
+    size_t i = 0, e = 0;
+    while (i < Ls.size()) {
+        size_t j = i;
+        while (j < Ls.size() && Ls[j].pass == Ls[i].pass) ++j;
+        const int nb = (int)(j - i);  // classes of this pass
+        if (nb == 1) {
+            const sg_status st = launch_one(dd, wj, Ls[i], s);
+            if (st != SG_OK) return st;
+            i = j;
+            continue;
+        }
+        const hipEvent_t fork = R.ev[e];  // R.ev[e + k]: join of branch k
+        SG_HIP(hipEventRecord(fork, s));
+        for (int k = 1; k < nb; ++k) {
+            SG_HIP(hipStreamWaitEvent(R.aux[k - 1], fork, 0));
+            const sg_status st = launch_one(dd, wj, Ls[i + k], R.aux[k - 1]);
+            if (st != SG_OK) return st;
+            SG_HIP(hipEventRecord(R.ev[e + k], R.aux[k - 1]));
+        }
+        const sg_status st = launch_one(dd, wj, Ls[i], s);
+        if (st != SG_OK) return st;
+        for (int k = 1; k < nb; ++k) SG_HIP(hipStreamWaitEvent(s, R.ev[e + k], 0));
+        e += nb;
+        i = j;
+    }
+    return SG_OK;
+}
+
 static bool use_graph()
 {
     const char *e = getenv("SG_NO_GRAPH");
@@ -917,8 +990,10 @@ static sg_status get_cached(const sg_disc *discs, int n, void *ws, Cached *&out)
             destroy(C);
             return SG_ERR_HIP;
         }
-        bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        sg_status st = ok ? enqueue(*C, cs) : SG_ERR_HIP;
+        ForkRes R;
+        bool ok = fork_resources(*C, R) == SG_OK;
+        ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        sg_status st = ok ? enqueue_forked(*C, cs, R) : SG_ERR_HIP;
         hipGraph_t gph = nullptr;
         ok = hipStreamEndCapture(cs, &gph) == hipSuccess && ok && st == SG_OK;
         if (ok) ok = hipGraphInstantiate(&C->exec, gph, nullptr, nullptr, 0) == hipSuccess;
@@ -947,18 +1022,52 @@ sg_status sg_fft_run(const sg_disc *discs, int n, void *ws, hipStream_t s)
     return enqueue(*C, s);
 }
 
+// One step, every launch in plan order with a start and a stop event
+// attached to the launch itself (hipExtLaunchKernel: the events take the
+// kernel's own start and end, not a marker between launches), with nothing
+// run before it: a caller that evicts the caches first times a cold step.
+// ms[p] = the summed kernel time of pass p's launches.
+static sg_status profile_one_step(const Cached &C, hipStream_t s, float *ms)
+{
+    const size_t nl = C.plan.launches.size();
+    std::vector<hipEvent_t> ev(2 * nl, nullptr);
+    sg_status st = SG_OK;
+    for (auto &e : ev)
+        if (st == SG_OK && hipEventCreate(&e) != hipSuccess) st = SG_ERR_HIP;
+    const DiscDev *dd = (const DiscDev *)C.dmem;
+    const WJob *wj = cached_wjobs(C);
+    for (size_t i = 0; i < nl && st == SG_OK; ++i) {
+        const Launch &L = C.plan.launches[i];
+        hipExtLaunchKernelGGL(L.k.fn, dim3(L.grid), dim3(L.k.wgs), (uint32_t)L.lds, s, ev[2 * i],
+                              ev[2 * i + 1], 0, dd, wj + L.wj_off, L.nj, L.tw, L.K);
+        if (hipGetLastError() != hipSuccess) st = SG_ERR_HIP;
+    }
+    if (st == SG_OK && nl && hipEventSynchronize(ev[2 * nl - 1]) != hipSuccess) st = SG_ERR_HIP;
+    for (int p = 0; p < 3; ++p) ms[p] = 0.f;
+    for (size_t i = 0; i < nl && st == SG_OK; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = SG_ERR_HIP;
+        ms[C.plan.launches[i].pass - 1] += t;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
 // Per-pass timing: each pass's launches are enqueued `reps` times back to
 // back between two HIP events on `s` (no graph), after one untimed complete
 // run; ms[p] is the mean milliseconds per launch of pass p + 1 (all of its
 // launch classes).  Back-to-back launches of the same pass leave each one's
 // duration with only the launch gap added, which is what a kernel trace
 // reports per dispatch.
+// (reps == 1: profile_one_step above.)
 sg_status sg_fft_profile(const sg_disc *discs, int n, void *ws, hipStream_t s, int reps, float *ms)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     Cached *C = nullptr;
     sg_status st = get_cached(discs, n, ws, C);
     if (st != SG_OK) return st;
+    if (reps == 1) return profile_one_step(*C, s, ms);
     st = enqueue(*C, s);
     if (st != SG_OK) return st;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -985,6 +1094,12 @@ static void release_locked()
     (void)hipDeviceSynchronize();
     for (auto &kv : g_cache) destroy(kv.second);
     g_cache.clear();
+}
+
+int sg_fft_cache_entries()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int)g_cache.size();
 }
 
 void sg_fft_release()

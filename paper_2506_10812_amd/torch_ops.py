@@ -145,20 +145,76 @@ def potential(g, h, sigma, H=None, flags=0, stream=None):
     return pot
 
 
-class _TableCache:
-    def __init__(self):
-        self.key = None
-        self.table = None
+class _Slot:
+    """Persistent device state of SGField for one (device, grid, aspect ratios,
+    flags): kernel table, input and output buffers, workspaces.  The library
+    sees the same buffers on every call, so sg_field_fft replays one cached
+    graph and nothing is allocated on the device after the first forward and
+    backward (returned tensors come from torch's caching allocator)."""
+
+    def __init__(self, g, hs, flags, device):
+        nf = len(hs)
+        shape = (nf, g.n_r, g.n_phi)
+        self.g, self.hs, self.flags, self.device = g, hs, flags, device
+        self.f = fluids(hs)
+        self.table = build_table(g, self.f, flags, device)
+        self.sigma = torch.empty(shape, dtype=torch.float32, device=device)
+        self.g_r = torch.empty(shape, dtype=torch.float32, device=device)
+        self.g_phi = torch.empty(shape, dtype=torch.float32, device=device)
+        self.disc = make_disc(g, self.f, flags, self.sigma, self.g_r, self.g_phi, self.table)
+        self.ws = torch.empty(max(1, field_fft_workspace_bytes([self.disc])), dtype=torch.uint8,
+                              device=device)
+        self.adj = None  # reverse-mode buffers, made by the first backward
+
+    def forward(self, sigma):
+        self.sigma.copy_(sigma)
+        field_fft([self.disc], self.ws)
+        return self.g_r.clone(), self.g_phi.clone()
+
+    def backward(self, sigma, lam_r, lam_phi):
+        if self.adj is None:
+            a_sig = torch.empty_like(self.sigma)
+            a_disc = make_disc(self.g, self.f, self.flags, a_sig, self.g_r, self.g_phi, self.table)
+            self.adj = dict(
+                sigma=a_sig, disc=a_disc,
+                lam_r=torch.empty_like(self.sigma), lam_phi=torch.empty_like(self.sigma),
+                dsig=torch.empty_like(self.sigma),
+                dh=torch.empty(len(self.hs), dtype=torch.float64, device=self.device),
+                ws=torch.empty(max(1, field_adjoint_workspace_bytes(a_disc)), dtype=torch.uint8,
+                               device=self.device))
+        A = self.adj
+        A["sigma"].copy_(sigma)
+        if lam_r is None:
+            A["lam_r"].zero_()
+        else:
+            A["lam_r"].copy_(lam_r)
+        if lam_phi is None:
+            A["lam_phi"].zero_()
+        else:
+            A["lam_phi"].copy_(lam_phi)
+        field_adjoint(A["disc"], A["lam_r"], A["lam_phi"], A["dsig"], A["dh"], A["ws"])
+        return A["dsig"].clone(), A["dh"].clone()
+
+
+class _SlotCache:
+    """The most recently used SGField slots (at most `size`)."""
+
+    def __init__(self, size=8):
+        self.size = size
+        self.slots = {}
 
     def get(self, g, hs, flags, device):
-        key = (g.n_r, g.n_phi, g.r_min, g.r_max, tuple(hs), flags, str(device))
-        if key != self.key:
-            self.table = build_table(g, fluids(list(hs)), flags, device)
-            self.key = key
-        return self.table
+        key = (str(device), g.n_r, g.n_phi, g.r_min, g.r_max, tuple(hs), flags)
+        slot = self.slots.pop(key, None)
+        if slot is None:
+            slot = _Slot(g, list(hs), flags, device)
+            if len(self.slots) >= self.size:
+                self.slots.pop(next(iter(self.slots)))
+        self.slots[key] = slot  # most recent last
+        return slot
 
 
-_cache = _TableCache()
+_slots = _SlotCache()
 
 
 class SGField(torch.autograd.Function):
@@ -166,37 +222,26 @@ class SGField(torch.autograd.Function):
 
     sigma: float32 CUDA tensor [F][n_r][n_phi]; h: float64 tensor [F] of
     aspect ratios; indirect: add the indirect term.  Forward: sg_field_fft.
-    Backward: sg_field_adjoint (dL/dSigma and dL/dh)."""
+    Backward: sg_field_adjoint (dL/dSigma and dL/dh).  Repeated calls with the
+    same grid, aspect ratios and flags reuse one persistent slot (table,
+    buffers, workspaces) and therefore one cached graph."""
 
     @staticmethod
     def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max, indirect=False):
         g = grid(n_r, n_phi, r_min, r_max)
         hs = [float(v) for v in h.detach().cpu().tolist()]
         flags = WITH_DH | (INDIRECT if indirect else 0)
-        table = _cache.get(g, hs, flags, sigma.device)
-        sigma_c = sigma.detach().contiguous().to(torch.float32)
-        gr = torch.empty_like(sigma_c)
-        gp = torch.empty_like(sigma_c)
-        f = fluids(hs)
-        disc = make_disc(g, f, flags, sigma_c, gr, gp, table)
-        ws = torch.empty(field_fft_workspace_bytes([disc]), dtype=torch.uint8, device=sigma.device)
-        field_fft([disc], ws)
-        ctx.save_for_backward(sigma_c, table)
-        ctx.meta = (g, hs, flags, h.device, h.dtype, sigma.dtype)
+        slot = _slots.get(g, hs, flags, sigma.device)
+        sig = sigma.detach()
+        gr, gp = slot.forward(sig)
+        ctx.save_for_backward(sig)
+        ctx.meta = (slot, h.device, h.dtype, sigma.dtype)
         return gr, gp
 
     @staticmethod
     def backward(ctx, lam_r, lam_phi):
-        sigma_c, table = ctx.saved_tensors
-        g, hs, flags, h_device, h_dtype, s_dtype = ctx.meta
-        f = fluids(hs)
-        lam_r = (lam_r if lam_r is not None else torch.zeros_like(sigma_c)).contiguous().float()
-        lam_phi = (lam_phi if lam_phi is not None else torch.zeros_like(sigma_c)).contiguous().float()
-        dsig = torch.empty_like(sigma_c)
-        dh = torch.empty(len(hs), dtype=torch.float64, device=sigma_c.device)
-        disc = make_disc(g, f, flags, sigma_c, lam_r, lam_phi, table)  # g_r/g_phi unused
-        ws = torch.empty(field_adjoint_workspace_bytes(disc), dtype=torch.uint8,
-                         device=sigma_c.device)
-        field_adjoint(disc, lam_r, lam_phi, dsig, dh, ws)
+        (sig,) = ctx.saved_tensors
+        slot, h_device, h_dtype, s_dtype = ctx.meta
+        dsig, dh = slot.backward(sig, lam_r, lam_phi)
         # gradients in the dtype (and, for h, the device) of the inputs
         return dsig.to(s_dtype), dh.to(device=h_device, dtype=h_dtype), None, None, None, None, None

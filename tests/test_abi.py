@@ -288,7 +288,8 @@ def test_semispectral_band_sizes(sg):
 
 def test_fft_path_group_limits(sg):
     """One to four scale-height groups on the FFT path; beyond two the column
-    pass needs n_r <= 1024, and the FFT-path adjoint takes one or two."""
+    pass needs n_r <= 1024; the adjoint takes every group count the forward
+    takes."""
     g = sg.grid(1024, 2048, 0.2, 5.0)
     nb2 = sg.kernel_table_bytes(g, sg.fluids([0.05, 0.005]), 0)
     nb4 = sg.kernel_table_bytes(g, sg.fluids([0.05, 0.005, 0.02, 0.01]), 0)
@@ -299,8 +300,10 @@ def test_fft_path_group_limits(sg):
     assert sg.kernel_table_bytes(g, f5, 0) == 0
     d3 = sg.make_disc(sg.grid(16, 32, 0.2, 5.0), sg.fluids([0.05, 0.01, 0.02]), 0, 256, 512, 768, 1024)
     assert sg.field_fft_workspace_bytes([d3]) > 0
-    assert sg.field_adjoint_workspace_bytes(d3) == 0
-    assert sg.lib().sg_field_adjoint(ctypes.byref(d3), 256, 512, 768, None, 2048, 1 << 30,
+    assert sg.field_adjoint_workspace_bytes(d3) > 0
+    d3big = sg.make_disc(sg.grid(2048, 32, 0.2, 5.0), sg.fluids([0.05, 0.01, 0.02]), 0, 256, 512, 768, 1024)
+    assert sg.field_adjoint_workspace_bytes(d3big) == 0
+    assert sg.lib().sg_field_adjoint(ctypes.byref(d3big), 256, 512, 768, None, 2048, 1 << 30,
                                      None) == sg.ERR_UNSUPPORTED
 
 

@@ -622,6 +622,36 @@ def test_adjoint_256x512_dsigma_against_central_differences(cfg5_fd):
         assert e < 1e-4, (a, e)
 
 
+def test_sgfield_replays_one_graph_and_allocates_nothing_after_warm_up(sg, T, W):
+    """Repeated SGField forward + backward on one grid and h: after the first
+    call no new sg_field_fft signature is cached (one graph replayed) and
+    torch's allocator makes no new device allocation; every repetition gives
+    the same outputs and gradients."""
+    w = W.adjoint(n_r=64, n_phi=128)
+    say("SGField: five forward/backward repetitions on one shape")
+    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda", requires_grad=True)
+    h = torch.tensor(w["h"], dtype=torch.float64, device="cuda", requires_grad=True)
+    args = (w["n_r"], w["n_phi"], w["r_min"], w["r_max"])
+
+    def step():
+        sig.grad = None
+        h.grad = None
+        gr, gp = T.SGField.apply(sig, h, *args)
+        ((gr ** 2).sum() + (gp ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        return gr.detach().clone(), sig.grad.clone(), h.grad.clone()
+
+    ref = step()
+    n0 = sg.field_fft_cache_entries()
+    seg0 = torch.cuda.memory_stats()["segment.all.allocated"]
+    for _ in range(5):
+        out = step()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
+    assert sg.field_fft_cache_entries() == n0
+    assert torch.cuda.memory_stats()["segment.all.allocated"] == seg0
+
+
 # ------------------------------------------------- three and four groups
 @pytest.mark.parametrize("nr,nphi,nf,per_cell,flags", [(7, 9, 3, True, 0), (6, 8, 4, False, 0),
                                                        (5, 12, 4, True, 4), (9, 5, 3, False, 1)])
@@ -787,3 +817,77 @@ def test_fft_path_four_groups_1024x2048_sampled_and_batch(sg, T, W):
     assert torch.equal(B.g_r[1], F.g_r[0]) and torch.equal(B.g_phi[1], F.g_phi[0])
     S = _fft_run(T, W, [small])
     assert torch.equal(B.g_r[0], S.g_r[0]) and torch.equal(B.g_phi[0], S.g_phi[0])
+
+
+@pytest.mark.parametrize("nr,nphi,nf,ind", [(8, 16, 3, False), (16, 32, 4, False), (8, 16, 4, True),
+                                            (16, 16, 3, True)])
+def test_adjoint_three_and_four_groups(sg, T, nr, nphi, nf, ind):
+    """FFT-path adjoint with three and four scale-height groups (all nf^2
+    ordered pairs), with and without the indirect term: the transpose
+    identity <lam, g(Sigma)> = <dL/dSigma, Sigma>; dL/dSigma against the
+    oracle's L = <lam, g (+ g_ind)> (the oracle's transposed sum without the
+    term, 1e-5 relative RMS; with it, L differenced in Sigma at sampled cells,
+    exact since L is linear in Sigma); dL/dh against the oracle's
+    differentiated tables (1e-4) or, with the term, central differences of L
+    in h (eps = 1e-4 h; 1e-4)."""
+    say(f"adjoint {nf} groups {nr}x{nphi} indirect={ind}")
+    rng = np.random.default_rng(nr * 10 + nf + (7 if ind else 0))
+    rmin, rmax = 0.2, 5.0
+    h = [0.07, 0.02, 0.01, 0.035][:nf]
+    r, phi, _, _ = O.grid(nr, nphi, rmin, rmax)
+    sig = (1 / r)[None, :, None] * rng.uniform(0.5, 1.5, (nf, nr, nphi))
+    if ind:  # lopsided, so that the m = 1 mode is not small
+        sig = sig * (1 + 0.3 * np.cos(phi - 0.7))[None, None, :]
+    sig = sig.astype(np.float32).astype(np.float64)
+    w = dict(n_r=nr, n_phi=nphi, r_min=rmin, r_max=rmax, h=h)
+    F = T.FFTField([w], flags=sg.WITH_DH | (sg.INDIRECT if ind else 0))
+    F.set_sigma(0, sig)
+    F.run()
+    torch.cuda.synchronize()
+    lr = rng.standard_normal((nf, nr, nphi)).astype(np.float32)
+    lp = rng.standard_normal((nf, nr, nphi)).astype(np.float32)
+    lr_t, lp_t = torch.tensor(lr).cuda(), torch.tensor(lp).cuda()
+    ds = torch.empty_like(F.sigma[0])
+    dh = torch.empty(nf, dtype=torch.float64, device="cuda")
+    ws = torch.empty(sg.field_adjoint_workspace_bytes(F.discs[0]), dtype=torch.uint8, device="cuda")
+    sg.field_adjoint(F.discs[0], lr_t, lp_t, ds, dh, ws)
+    torch.cuda.synchronize()
+    lhs = float((lr_t.double() * F.g_r[0].double()).sum() + (lp_t.double() * F.g_phi[0].double()).sum())
+    rhs = float((ds.double() * F.sigma[0].double()).sum())
+    say(f"  <lam, g> {lhs:.8e}  <dL/dSigma, Sigma> {rhs:.8e}")
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+    dsn = ds.double().cpu().numpy().reshape(nf, -1)
+    dhn = dh.cpu().numpy()
+    lr64, lp64 = lr.astype(np.float64).reshape(nf, -1), lp.astype(np.float64).reshape(nf, -1)
+    if not ind:
+        ref = O.adjoint_sigma(nr, nphi, rmin, rmax, h, lr64, lp64)
+        for a in range(nf):
+            e = rel_rms(dsn[a], ref[a])
+            say(f"  dL/dSigma group {a}: rel-RMS {e:.2e}")
+            assert e < 1e-5, (a, e)
+        refh = O.adjoint_h(nr, nphi, rmin, rmax, h, sig, lr64, lp64)
+        say(f"  dL/dh device {dhn} oracle {refh}")
+        np.testing.assert_allclose(dhn, refh, rtol=1e-4)
+        return
+
+    def L(sigma, hh):
+        gr, gp = O.field_table(nr, nphi, rmin, rmax, hh, sigma)
+        ir, ip = O.indirect_field(nr, nphi, O.indirect(nr, nphi, rmin, rmax, hh, sigma))
+        return float(np.sum(lr64 * (gr + ir[None, :])) + np.sum(lp64 * (gp + ip[None, :])))
+
+    L0 = L(sig, h)
+    scale = np.abs(dsn).max()
+    for a, k in [(0, 0), (1, 5), (2, 77), (nf - 1, nr * nphi - 1), (nf - 1, 33)]:
+        sp = sig.copy()
+        sp.reshape(nf, -1)[a, k] += 1.0
+        want = L(sp, h) - L0
+        say(f"  dL/dSigma[{a}][{k}] {dsn[a, k]:.6e} oracle {want:.6e}")
+        assert abs(dsn[a, k] - want) < 1e-5 * scale, (a, k, dsn[a, k], want)
+    for a in range(nf):
+        e = 1e-4 * h[a]
+        hp_, hm_ = list(h), list(h)
+        hp_[a] += e
+        hm_[a] -= e
+        want = (L(sig, hp_) - L(sig, hm_)) / (2 * e)
+        say(f"  dL/dh[{a}] {dhn[a]:.8e} oracle {want:.8e}")
+        assert abs(dhn[a] - want) < 1e-4 * abs(want), (a, dhn[a], want)
