@@ -428,14 +428,16 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
  *   d_dH[f][i] = dL/dH_f(r_i)   (double, device, [F][n_r]).
  * Every operator entry is differentiated through both of its scale heights
  * (the kernels' h derivatives, the own-cell integral's derivatives, and the
- * folded indirect term through H_a at the source ring) and contracted with
+ * folded indirect term through H_a at the source ring; for SG_POTENTIAL
+ * operators the potential kernel's, dP/dH_ab = -(2 y F(y) - e^y K0(y)) /
+ * (2 sqrt(pi) H_ab^2), and its own-cell integral's) and contracted with
  * the phi spectra of lam and Sigma, mode by mode, in double; the derivative
  * operators are sampled and transformed on the fly and never stored, so a
  * call costs about twice a table build.  d_H: the H the disc's table was
  * built from.  disc->table supplies the phi twiddles only.  Species discs
  * (n_species > 0): the derivative at the group densities, summed in the
- * forward's order.  Discs without SG_SEMI_SPECTRAL, or with SG_POTENTIAL,
- * return SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
+ * forward's order.  Discs without SG_SEMI_SPECTRAL return
+ * SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
  * 256-byte aligned.  Asynchronous; the result is summed with device
  * atomics, so its last bits vary from call to call.
  * --------------------------------------------------------------------- */

@@ -647,7 +647,7 @@ static sg_status potential_run(const sg_grid *g, int nf, const double *h, const 
         sg_gl_nodes(gl);
         const int64_t items = (int64_t)nf * nf * (percell ? N : nr);
         hipLaunchKernelGGL(k_pot_self<T>, dim3((unsigned)items), dim3(256), 0, s, H, (const double *)dh, nf,
-                           nr, nphi, lnrmin, du, dphi, percell ? 0 : 1, self, gl);
+                           nr, nphi, lnrmin, du, dphi, percell ? 0 : 1, self, gl, 0);
         SG_HIP(hipGetLastError());
     }
     DirectArgs<T> A;

@@ -209,8 +209,8 @@ __global__ void k_ss_modes(SsMode *modes, int ncol, int nr, int nrt, int nf, dou
 // the Duffy triangles and geometric panels of the log-cell quadrature, and
 // doubled for phi < 0 (both kernels are even in phi).  Output: the table
 // sample I / (wgt dphi) (field, I = int K_r dX dphi) or -I / (wgt dphi)
-// (potential, I = int P dA'), wgt = dr / r; which = 1, 2: the field's
-// derivatives with respect to h_a, h_b instead.  per: cells per ring of H
+// (potential, I = int P dA'), wgt = dr / r; which = 1, 2: their derivatives
+// with respect to h_a, h_b instead.  per: cells per ring of H
 // and out (1: one value per ring; n_phi: per cell, for the direct sum with
 // per-cell H), item = pair * n_r * per + cell.
 __global__ void __launch_bounds__(256)
@@ -251,7 +251,15 @@ k_ss_self_lin(const double *H, int nf, int nr, int per, double rmin, double dr, 
                 if (pot) {
                     const double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
                     const double s2 = r * r * exp(X) * 4.0 * (sx * sx + sp * sp);
-                    f += -sg_G0_64(s2 / (8.0 * Hab * Hab), wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
+                    const double y = s2 / (8.0 * Hab * Hab);
+                    if (which == 0) {
+                        f += -sg_G0_64(y, wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
+                    } else {
+                        // dP/dH_ab = -(2 y F(y) - G0(y)) / (2 sqrt(pi) H_ab^2), times dH_ab/dh
+                        const double ch = (which == 1 ? Ha : Hb) * r / (2.0 * Hab);
+                        f += -(2.0 * y * sg_F64(y, wq) - sg_G0_64(y, wq)) / (2.0 * SG_SQRT_PI * Hab * Hab) * ch *
+                             r * r * exp(2.0 * X);
+                    }
                 } else {
                     double kr, kp;
                     sg_conv_kernel64(X, sin(0.5 * phi), sin(phi), ha, hb, which, wq, kr, kp);
@@ -375,7 +383,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
                                dphi, pot ? 1 : 0, 0, self, gl);
         } else if (pot) {
             hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H, (const double *)nullptr,
-                               nf, nr, 1, log(grid->r_min), du, dphi, 0, self, gl);
+                               nf, nr, 1, log(grid->r_min), du, dphi, 0, self, gl, 0);
             SG_HIP(hipGetLastError());
             // own-cell integral I of P: the sample -I / (du dphi) scales to I / N
             hipLaunchKernelGGL(k_ss_scale, dim3((nf * nf * nr + 255) / 256), dim3(256), 0, s, self, nf * nf * nr,
@@ -709,6 +717,17 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
                 kr1 = dself[o];
                 kr2 = dself[wst + o];
             }
+        } else if (A.pot) {
+            // d/dh of r'^2 G0(y) / (2 sqrt(pi) H_ab) (the forward's sample):
+            // d(G0/H)/dH = (2 y F(y) - G0(y)) / H^2, dH_ab/dh_a = H_a r' / (2 H_ab),
+            // dH_ab/dh_b = H_b r_i / (2 H_ab); even in phi (no K_phi part)
+            const double sx = sinh(0.5 * X), sp = sinpi((double)q / N);
+            const double s2 = 4.0 * ri * rp * (sx * sx + sp * sp);
+            const double Ha = ha * rp, Hb = hb * ri, Hab2 = 0.5 * (Ha * Ha + Hb * Hb), Hab = sqrt(Hab2);
+            const double y = s2 / (8.0 * Hab2);
+            const double dq = rp * rp * (2.0 * y * sg_F64(y, wq) - sg_G0_64(y, wq)) / (2.0 * SG_SQRT_PI * Hab2);
+            kr1 = dq * Ha * rp / (2.0 * Hab);
+            kr2 = dq * Hb * ri / (2.0 * Hab);
         } else {
             sg_conv_kernel64_dh(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, wq, kr1, kp1, kr2, kp2);
         }
@@ -745,13 +764,13 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
             const double cr = (double)lr.x * sv.x + (double)lr.y * sv.y;
             const double cp = -(double)lp.x * sv.y + (double)lp.y * sv.x;
             const double wm = ((m == 0 || m == N / 2) ? 1.0 : 2.0) * scale;
-            double tr = 0.5 * (zm.x + zn.x), tp = 0.5 * (zn.x - zm.x);
+            double tr = 0.5 * (zm.x + zn.x), tp = A.pot ? 0.0 : 0.5 * (zn.x - zm.x);
             if (m == 1) {
                 tr += dind;
                 tp += dind;
             }
             part[0] += wm * (tr * cr + tp * cp);
-            part[1] += wm * (0.5 * (zm.y + zn.y) * cr + 0.5 * (zn.y - zm.y) * cp);
+            part[1] += wm * (0.5 * (zm.y + zn.y) * cr + (A.pot ? 0.0 : 0.5 * (zn.y - zm.y)) * cp);
         }
     }
     __syncthreads();
@@ -849,7 +868,7 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
     A.nf = nf;
     A.excl = (flags & SG_SELF_CELL_EXCLUDE) ? 1 : 0;
     A.ind = (flags & SG_INDIRECT) ? 1 : 0;
-    A.pot = 0;
+    A.pot = (flags & SG_POTENTIAL) ? 1 : 0;
     A.lin = lin ? 1 : 0;
     A.lnrmin = log(grid->r_min);
     A.du = log(grid->r_max / grid->r_min) / nr;
@@ -863,12 +882,20 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
         sg_gl_nodes(gl);
         for (int which = 1; which <= 2; ++which) {
             double *out = dself + (size_t)(which - 1) * nf * nf * nr;
-            if (lin)
+            if (lin) {
                 hipLaunchKernelGGL(k_ss_self_lin, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, 1, grid->r_min,
-                                   A.dr, dphi, 0, which, out, gl);
-            else
+                                   A.dr, dphi, A.pot, which, out, gl);
+            } else if (A.pot) {
+                hipLaunchKernelGGL(k_pot_self<double>, dim3(nf * nf * nr), dim3(256), 0, s, d_H,
+                                   (const double *)nullptr, nf, nr, 1, A.lnrmin, A.du, dphi, 0, out, gl, which);
+                SG_HIP(hipGetLastError());
+                // as the forward's own-cell sample: -I / (du dphi)
+                hipLaunchKernelGGL(k_ss_scale, dim3((nf * nf * nr + 255) / 256), dim3(256), 0, s, out, nf * nf * nr,
+                                   -1.0 / (A.du * dphi));
+            } else {
                 hipLaunchKernelGGL(k_self_cell_ring, dim3(nf * nf * nr), dim3(256), 0, s, d_H, nf, nr, A.lnrmin,
                                    A.du, dphi, which, out, gl);
+            }
             SG_HIP(hipGetLastError());
         }
     }

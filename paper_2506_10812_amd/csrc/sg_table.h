@@ -39,5 +39,5 @@ __global__ void k_self_cell_percell(const T *H, int nf, int nr, int nphi, double
                                     double dphi, double *out, GLNodes gl);
 template <typename T>
 __global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi, double lnrmin,
-                           double du, double dphi, int per_row, double *out, GLNodes gl);
+                           double du, double dphi, int per_row, double *out, GLNodes gl, int which);
 __global__ void k_fill_f64(double *p, int64_t n, double v);

@@ -144,16 +144,20 @@ template __global__ void k_self_cell_percell<double>(const double *, int, int, i
 // (4 sinh^2(X/2) + 4 sin^2(phi/2)), dA' = r^2 e^{2X} dX dphi; even in phi,
 // so 2 x (X >= 0 and X <= 0 halves) over [0,a]x[0,b] with the same Duffy
 // rule as the force self term (the singularity is logarithmic).
-__device__ inline double pot_integrand(double X, double phi, double r, double Hab, const double *wq)
+// which = 0: P; which = 1: dP/dH_ab (H_ab the r.m.s. height: with
+// G0 = e^y K0(y), dG0/dy = -F(y), so dP/dH = -(2 y F(y) - G0(y)) /
+// (2 sqrt(pi) H^2); like P, logarithmic at s -> 0).
+__device__ inline double pot_integrand(double X, double phi, double r, double Hab, const double *wq, int which = 0)
 {
     const double sx = sinh(0.5 * X), sp = sin(0.5 * phi);
     const double s2 = r * r * exp(X) * 4.0 * (sx * sx + sp * sp);
     const double y = s2 / (8.0 * Hab * Hab);
+    if (which) return -(2.0 * y * sg_F64(y, wq) - sg_G0_64(y, wq)) / (2.0 * SG_SQRT_PI * Hab * Hab) * r * r * exp(2.0 * X);
     return -sg_G0_64(y, wq) / (2.0 * SG_SQRT_PI * Hab) * r * r * exp(2.0 * X);
 }
 
 __device__ inline double pot_self_partial(double r, double Hab, double a, double b, const GLNodes &gl,
-                                          const double *wq)
+                                          const double *wq, int which = 0)
 {
     constexpr int NX = SG_PANELS * SG_GLX_N;
     double acc = 0.0;
@@ -167,18 +171,20 @@ __device__ inline double pot_self_partial(double r, double Hab, double a, double
         const double wgt = (hi - lo) * gl.wr[i] * gl.w[j] * xi * a * b;
         double f = 0.0;
         for (int sg = -1; sg <= 1; sg += 2)
-            f += pot_integrand(sg * a * xi, b * xi * eta, r, Hab, wq) +
-                 pot_integrand(sg * a * xi * eta, b * xi, r, Hab, wq);
+            f += pot_integrand(sg * a * xi, b * xi * eta, r, Hab, wq, which) +
+                 pot_integrand(sg * a * xi * eta, b * xi, r, Hab, wq, which);
         acc += 2.0 * wgt * f;
     }
     return acc;
 }
 
 // Item = (pair, row) when per_row (H_f = h_f r: depends on the row only),
-// else (pair, cell) with the caller's H at that cell.
+// else (pair, cell) with the caller's H at that cell.  which = 1, 2: the
+// integral's derivative with respect to h_a = H_a / r, h_b = H_b / r
+// (dH_ab/dh_a = H_a r / (2 H_ab), likewise for b) instead.
 template <typename T>
 __global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi, double lnrmin,
-                           double du, double dphi, int per_row, double *out, GLNodes gl)
+                           double du, double dphi, int per_row, double *out, GLNodes gl, int which)
 {
     __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
@@ -201,14 +207,15 @@ __global__ void k_pot_self(const T *H, const double *h, int nf, int nr, int nphi
         Hb = (double)H[fb * N + c];
     }
     const double Hab = sqrt(0.5 * (Ha * Ha + Hb * Hb));
-    const double acc = pot_self_partial(r, Hab, 0.5 * du, 0.5 * dphi, gl, wq);
+    const double chain = which == 0 ? 1.0 : (which == 1 ? Ha : Hb) * r / (2.0 * Hab);
+    const double acc = pot_self_partial(r, Hab, 0.5 * du, 0.5 * dphi, gl, wq, which != 0);
     const double tot = block_sum256(acc, red);
-    if (threadIdx.x == 0) out[item] = tot;
+    if (threadIdx.x == 0) out[item] = chain * tot;
 }
 template __global__ void k_pot_self<float>(const float *, const double *, int, int, int, double, double,
-                                           double, int, double *, GLNodes);
+                                           double, int, double *, GLNodes, int);
 template __global__ void k_pot_self<double>(const double *, const double *, int, int, int, double, double,
-                                            double, int, double *, GLNodes);
+                                            double, int, double *, GLNodes, int);
 
 __global__ void k_fill_f64(double *p, int64_t n, double v)
 {

@@ -177,7 +177,7 @@ def test_semispectral_sizes_and_validation(sg):
     # semi-spectral adjoint: dL/dSigma only
     assert sg.field_adjoint_workspace_bytes(d) > 0
     assert L.sg_field_adjoint(ctypes.byref(d), 256, 512, 768, 4096, 2048, 1 << 30, None) == sg.ERR_UNSUPPORTED
-    # dL/dH(r): semi-spectral discs without SG_POTENTIAL or species only
+    # dL/dH(r): semi-spectral discs (field or potential operators, species too)
     need = sg.ss_grad_H_workspace_bytes(d)
     assert need > 0
     G = L.sg_ss_grad_H
@@ -185,8 +185,7 @@ def test_semispectral_sizes_and_validation(sg):
     assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, need - 1, None) == sg.ERR_WORKSPACE
     assert G(ctypes.byref(d), 256, 512, 768, 4096, 8200, need, None) == sg.ERR_WORKSPACE
     d.flags = sg.SEMI_SPECTRAL | sg.POTENTIAL
-    assert sg.ss_grad_H_workspace_bytes(d) == 0
-    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED
+    assert sg.ss_grad_H_workspace_bytes(d) == need
     fft = sg.make_disc(sg.grid(16, 32, 0.2, 5.0), sg.fluids([0.05]), 0, 256, 512, 768, 1024)
     assert sg.ss_grad_H_workspace_bytes(fft) == 0
     assert G(ctypes.byref(fft), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED

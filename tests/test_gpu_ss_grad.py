@@ -5,7 +5,8 @@ Checked against
     sum with per-ring H broadcast to every cell, plus the oracle's indirect
     field where flagged), one ring and fluid at a time, on small log and
     uniform grids with flaring, a temperature gap, odd n_r, up to three
-    groups, the own cell dropped or kept;
+    groups, the own cell dropped or kept; likewise for the potential
+    operators with L = <lam_r, Phi(H)>;
   * the oracle's dL/dh_f for H_f = h_f r: by the chain rule
     sum_i r_i dL/dH_f(r_i) = dL/dh_f (the offset-table derivative sum);
   * at the App. D size, a directional derivative of the GPU forward (itself
@@ -83,6 +84,17 @@ def oracle_L(w, H, flags, lr, lp):
     return L
 
 
+def oracle_L_pot(w, H, flags, lr):
+    """L = <lam_r, Phi(H)> with the oracle's pairwise potential (per-ring H at
+    every cell); the potential operators write Phi to g_r."""
+    nf, nr, nphi = w["sigma"].shape
+    sig = w["sigma"].astype(np.float32).astype(np.float64)
+    Hc = np.repeat(H[:, :, None], nphi, axis=2)
+    of = (O.EXCLUDE_SELF if flags & 1 else 0) | (O.LINEAR_R if flags & 64 else 0)
+    pot = O.potential_pairwise(nr, nphi, w["r_min"], w["r_max"], [0.0] * nf, sig, H=Hc, flags=of)
+    return float(np.sum(lr.reshape(nf, -1).astype(np.float64) * pot))
+
+
 def oracle_fd(w, flags, lr, lp, rel=1e-4):
     H0 = np.array(w["H"], dtype=np.float64)
     out = np.zeros_like(H0)
@@ -93,7 +105,10 @@ def oracle_fd(w, flags, lr, lp, rel=1e-4):
             Hm = H0.copy()
             Hp[f, i] += e
             Hm[f, i] -= e
-            out[f, i] = (oracle_L(w, Hp, flags, lr, lp) - oracle_L(w, Hm, flags, lr, lp)) / (2 * e)
+            if flags & 32:
+                out[f, i] = (oracle_L_pot(w, Hp, flags, lr) - oracle_L_pot(w, Hm, flags, lr)) / (2 * e)
+            else:
+                out[f, i] = (oracle_L(w, Hp, flags, lr, lp) - oracle_L(w, Hm, flags, lr, lp)) / (2 * e)
     return out
 
 
@@ -120,6 +135,26 @@ def test_ss_grad_matches_oracle_differences(sg, T, W, nr, nphi, nf, flags, gap, 
         phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
         w["sigma"] = w["sigma"] * (1 + 0.3 * np.cos(phi - 1.0))[None, None, :]
     lr, lp = lams(w["sigma"].shape, nr + nf)
+    _, d = gpu_grad(sg, T, w, flags, lr, lp)
+    ref = oracle_fd(w, flags, lr, lp)
+    compare(d, ref)
+
+
+@pytest.mark.parametrize("nr,nphi,nf,flags,gap,lin", [
+    (7, 8, 2, 0, 3.0, False),      # odd n_r, two groups, temperature gap
+    (6, 8, 3, 1, None, False),     # three groups, own cell dropped
+    (6, 8, 2, 0, None, True),      # uniform grid: one-sided own-cell integrals
+])
+def test_ss_grad_potential_matches_oracle_differences(sg, T, W, nr, nphi, nf, flags, gap, lin):
+    """dL/dH(r) of the potential operators (SG_POTENTIAL, Sect. 5.5): central
+    differences of the oracle's L = <lam_r, Phi(H)>, one ring and fluid at a
+    time, with the own-cell integral's derivative (or without the own cell)."""
+    say(f"semi-spectral potential dL/dH {nr}x{nphi} nf={nf} flags={flags} gap={gap} linear={lin}")
+    w = W.flaring(seed=nr * 5 + nphi, n_r=nr, n_phi=nphi, p=0.25, gap_w=gap, n_fluids=nf, linear_r=lin)
+    flags |= sg.POTENTIAL
+    if lin:
+        flags |= sg.LINEAR_R
+    lr, lp = lams(w["sigma"].shape, nr + 3 * nf)
     _, d = gpu_grad(sg, T, w, flags, lr, lp)
     ref = oracle_fd(w, flags, lr, lp)
     compare(d, ref)
@@ -208,13 +243,12 @@ def test_ss_grad_species_equals_group_disc(sg, T, W):
 
 
 def test_ss_grad_rejects(sg, T, W):
-    """Potential operators and FFT-path discs are refused."""
-    w = W.flaring(seed=2, n_r=8, n_phi=8, p=0.25, n_fluids=1)
-    S = T.SemiSpectral(8, 8, w["r_min"], w["r_max"], 1, sg.POTENTIAL)
-    S.refresh(w["H"])
-    assert sg.ss_grad_H_workspace_bytes(S.disc) == 0
-    H = torch.tensor(w["H"], dtype=torch.float64, device="cuda")
-    lam = torch.zeros(S.g_r.shape, device="cuda")
+    """FFT-path discs (no radial operators) are refused."""
+    w = W.bifluid_fft(seed=2, n_r=8, n_phi=8)
+    F = T.FFTField([w])
+    assert sg.ss_grad_H_workspace_bytes(F.discs[0]) == 0
+    H = torch.ones((2, 8), dtype=torch.float64, device="cuda")
+    lam = torch.zeros(F.g_r[0].shape, device="cuda")
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     with pytest.raises(RuntimeError):
-        sg.ss_grad_H(S.disc, H, lam, lam, torch.empty_like(H), ws)
+        sg.ss_grad_H(F.discs[0], H, lam, lam, torch.empty_like(H), ws)
