@@ -72,8 +72,24 @@ enum {
     SG_SEMI_SPECTRAL = 8u,     /* disc uses a semi-spectral table (below)     */
     SG_SS_FULL = 16u,          /* semi-spectral: keep every operator entry    */
     SG_POTENTIAL = 32u,        /* semi-spectral: operators of the potential   */
-    SG_LINEAR_R = 64u          /* uniform radial grid (semi-spectral, direct) */
+    SG_LINEAR_R = 64u,         /* uniform radial grid (semi-spectral, direct) */
+    SG_SECOND_ORDER = 128u     /* kernel table: hat-weighted sources (below)  */
 };
+
+/* SG_SECOND_ORDER (sg_kernel_table, FFT path): the sources are taken as the
+ * piecewise-bilinear interpolant of the cell values on the (u, phi) grid
+ * (tensor-product hat functions on the cell centres, periodic in phi; the
+ * first and last rings' hats reach one cell beyond the grid), integrated
+ * exactly against the kernel.  The table then holds
+ *   W_c(P, Q) = int int (1 - |s|)(1 - |t|) K_c((P + s) du, (Q + t) dphi) ds dt,
+ * s, t in [-1, 1], in place of the point samples and the own-cell average:
+ * the discrete field converges at second order in du, dphi to the field of
+ * a smooth density, where the cell-centre sums converge at first order (the
+ * ring kernel's 1/X and log|X| singularities).  The solve, its graph and its
+ * cost are unchanged; the table build integrates each entry (Gauss-Legendre,
+ * polar rules at the singular point).  Not with SG_WITH_DH or
+ * SG_SELF_CELL_EXCLUDE (SG_ERR_UNSUPPORTED); SG_INDIRECT keeps its
+ * point-mass form. */
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
  * fluid also receives the acceleration -sum_a grad Phi_{a,ind} of the frame

@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXCLUDE_SELF = 1
 LINEAR_R = 2
+SECOND_ORDER = 4  # table mode: hat-weighted (piecewise-bilinear source) offsets
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -94,6 +95,8 @@ def lib():
         L.sg_oracle_indirect.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             _dp, _dp, _dp, ctypes.c_uint, _dp]
+        L.sg_oracle_hat_weight.restype = None
+        L.sg_oracle_hat_weight.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
         L.sg_oracle_threads.restype = ctypes.c_int
         L.sg_oracle_threads.argtypes = []
         _lib = L
@@ -191,6 +194,13 @@ def field_table_pairs(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0, whi
     if rc:
         raise RuntimeError(f"sg_oracle_field_table failed ({rc})")
     return out
+
+
+def hat_weight(P, Q, du, dphi, ha, hb):
+    """Second-order offset weights (W_r, W_phi) of offset (P, Q) in cells."""
+    W = np.empty(2)
+    lib().sg_oracle_hat_weight(int(P), int(Q), du, dphi, ha, hb, _ptr(W))
+    return float(W[0]), float(W[1])
 
 
 def field_table(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0):

@@ -24,6 +24,7 @@ SEMI_SPECTRAL = 8
 SS_FULL = 16
 POTENTIAL = 32
 LINEAR_R = 64
+SECOND_ORDER = 128
 
 
 class SGError(RuntimeError):

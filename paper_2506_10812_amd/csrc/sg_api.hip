@@ -47,7 +47,13 @@ static bool fft_groups_ok(const sg_grid *g, const sg_fluids *f)
 
 static bool flags_ok(uint32_t flags)
 {
-    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH | SG_INDIRECT)) == 0;
+    return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH | SG_INDIRECT | SG_SECOND_ORDER)) == 0;
+}
+
+// SG_SECOND_ORDER tables have no d/dh spectra and no separate own-cell term
+static bool second_order_ok(uint32_t flags)
+{
+    return !(flags & SG_SECOND_ORDER) || !(flags & (SG_WITH_DH | SG_SELF_CELL_EXCLUDE));
 }
 
 // Semi-spectral path: n_phi a power of two in [4, 2048], 1 <= n_r <= 2048.
@@ -79,6 +85,7 @@ extern "C" {
 size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
 {
     if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
+    if (!second_order_ok(flags)) return 0;
     if (!fft_groups_ok(grid, fluids)) return 0;
     return sg_table_layout(grid->n_r, grid->n_phi, fluids->n_fluids, flags).total;
 }
@@ -86,7 +93,7 @@ size_t sg_kernel_table_bytes(const sg_grid *grid, const sg_fluids *fluids, uint3
 size_t sg_kernel_table_workspace_bytes(const sg_grid *grid, const sg_fluids *fluids, uint32_t flags)
 {
     if (check_fft_grid(grid) != SG_OK || check_fluids(fluids) != SG_OK || !flags_ok(flags)) return 0;
-    if (!fft_groups_ok(grid, fluids)) return 0;
+    if (!fft_groups_ok(grid, fluids) || !second_order_ok(flags)) return 0;
     return sg_table_ws_bytes(grid->n_r, grid->n_phi);
 }
 
@@ -98,6 +105,7 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
     if ((s = check_fluids(fluids)) != SG_OK) return s;
     if (!fft_groups_ok(grid, fluids)) return SG_ERR_UNSUPPORTED;
     if (!flags_ok(flags)) return SG_ERR_ARG;
+    if (!second_order_ok(flags)) return SG_ERR_UNSUPPORTED;
     if (!d_table || ((uintptr_t)d_table & 255)) return SG_ERR_ARG;
     if (!d_ws || ws_bytes < sg_table_ws_bytes(grid->n_r, grid->n_phi) || ((uintptr_t)d_ws & 255))
         return SG_ERR_WORKSPACE;
@@ -158,6 +166,7 @@ static sg_status check_disc(const sg_disc &d)
     if ((s = check_fluids(&d.fluids)) != SG_OK) return s;
     if (!fft_groups_ok(&d.grid, &d.fluids)) return SG_ERR_UNSUPPORTED;
     if (!flags_ok(d.flags)) return SG_ERR_ARG;
+    if (!second_order_ok(d.flags)) return SG_ERR_UNSUPPORTED;
     if (!d.sigma || !d.g_r || !d.g_phi || !d.table) return SG_ERR_ARG;
     if ((uintptr_t)d.table & 255) return SG_ERR_ARG;
     return SG_OK;

@@ -123,6 +123,35 @@ def test_direct_validation(sg):
     assert sg.field_direct_workspace_bytes(big, 1, sg.F32, False) == 0
 
 
+def test_second_order_flag_combinations(sg):
+    """SG_SECOND_ORDER changes the table's values, not its layout; it cannot
+    be combined with d/dh spectra or the own-cell switch, and only the FFT
+    path's table takes it."""
+    g = sg.grid(16, 32, 0.2, 5.0)
+    f = sg.fluids([0.05, 0.005])
+    L = sg.lib()
+    nb = sg.kernel_table_bytes(g, f, 0)
+    assert sg.kernel_table_bytes(g, f, sg.SECOND_ORDER) == nb
+    assert sg.kernel_table_bytes(g, f, sg.SECOND_ORDER | sg.INDIRECT) == nb
+    assert sg.kernel_table_workspace_bytes(g, f, sg.SECOND_ORDER) > 0
+    for bad in (sg.SECOND_ORDER | sg.WITH_DH, sg.SECOND_ORDER | sg.SELF_CELL_EXCLUDE):
+        assert sg.kernel_table_bytes(g, f, bad) == 0
+        assert sg.kernel_table_workspace_bytes(g, f, bad) == 0
+        st = L.sg_kernel_table(ctypes.byref(g), ctypes.byref(f), bad, ctypes.c_void_p(256),
+                               ctypes.c_void_p(512), 1 << 40, None)
+        assert st == sg.ERR_UNSUPPORTED
+        d = sg.Disc(g, f, bad, 0, 256, 512, 768, 1024)
+        assert sg.field_fft_workspace_bytes([d]) == 0
+    d = sg.Disc(g, f, sg.SECOND_ORDER, 0, 256, 512, 768, 1024)
+    assert sg.field_fft_workspace_bytes([d]) == sg.field_fft_workspace_bytes([sg.Disc(g, f, 0, 0, 256, 512, 768, 1024)])
+    assert sg.ss_table_bytes(g, 1, sg.SECOND_ORDER) == 0
+    need = sg.field_direct_workspace_bytes(g, 1, sg.F64, False)
+    h = (ctypes.c_double * 1)(0.05)
+    hp = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+    assert L.sg_field_direct(ctypes.byref(g), 1, hp, 256, None, 512, 768, sg.F64, sg.SECOND_ORDER, 1024, need,
+                             None) == sg.ERR_ARG
+
+
 def test_adjoint_needs_dh_table(sg):
     g = sg.grid(16, 32, 0.2, 5.0)
     f = sg.fluids([0.05])

@@ -119,6 +119,28 @@ def test_exponential_disc_first_order_convergence(sg, T, W):
         assert 1.6 < a / b < 2.5, meds
 
 
+def test_exponential_disc_second_order_table_reaches_the_floor(sg, T, W):
+    """With SG_SECOND_ORDER (hat-weighted table) the discretisation error is
+    second order, so at h = 0.001 the error against Freeman falls to the
+    continuum floor (about h, test_validation_floor.py) already on the
+    coarser grids and stays there (seen 9.8e-4 to 1.0e-3 from 256 x 512 to
+    1024 x 2048), where the cell-centre sums sit a first-order term above it
+    (3.5e-3 at 1024 x 2048)."""
+    meds = []
+    for nr, nphi in ((256, 512), (512, 1024), (1024, 2048)):
+        w = W.exponential(n_r=nr, n_phi=nphi, h=0.001, q=1)
+        F = T.FFTField([dict(w, h=[0.001])], flags=sg.SECOND_ORDER)
+        F.set_sigma(0, w["sigma"])
+        F.run()
+        torch.cuda.synchronize()
+        med, mx, spread = errors(w, F.g_r[0][0].double().cpu().numpy())
+        print(f"  second order {nr}x{nphi}: median {med:.2e} max {mx:.2e} spread {spread:.1e}", flush=True)
+        assert spread < 1e-5
+        meds.append(med)
+    assert 0.9e-3 < meds[-1] < 1.6e-3, meds
+    assert abs(meds[1] / meds[2] - 1) < 0.15, meds
+
+
 def test_appD_constant_h_error_grows_with_flaring(sg, T, W):
     """App. D: the full FFT method needs H/r constant; on a flaring disc its
     field differs from the semi-spectral reference computed with the true
