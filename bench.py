@@ -66,7 +66,7 @@ PROFILE_COMMANDS = {
             "python3 {repo}/bench.py --batch --steps 20 --warmup 5",
     "b_sq": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
             "SQ_LDS_BANK_CONFLICT SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE --output-format csv "
-            "-d {out}/b_sq -o run -- python3 {repo}/bench.py --batch --steps 5 --warmup 2",
+            "-d {out}/b_sq -o run -- python3 {repo}/bench.py --batch --steps 5 --warmup 2 --no-tune",
     "b_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/b_fetch -o run -- "
                "python3 {repo}/bench.py --batch --steps 5 --warmup 2 --no-tune",
     "b_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/b_write -o run -- "
@@ -274,6 +274,8 @@ def summarize_rocprof(out):
         summarize_pass2_sq(out, prof, cmd)
     if os.path.isdir(os.path.join(out, "b_fetch")) and os.path.isdir(os.path.join(out, "b_write")):
         summarize_batch_traffic(out, prof, cmd, f_scale, w_scale, cf, cw)
+    if os.path.isdir(os.path.join(out, "b_sq")):
+        summarize_batch_sq(out, prof, cmd)
     ss_dir = os.path.join(out, "ss_kt")
     if os.path.isdir(ss_dir):
         stats = _csv_rows(ss_dir, "_kernel_stats.csv")
@@ -361,6 +363,40 @@ def summarize_batch_traffic(out, prof, cmd, f_scale, w_scale, cf, cw):
              f"all for {cells} cells = {(rd + wr) / cells:.1f} B/cell, against {alg / 1e6:.1f} MB "
              f"algorithmic ({alg / cells:.1f} B/cell): {(rd + wr) / alg:.2f}x."]
     with open(os.path.join(prof, "traffic_batch64.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_batch_sq(out, prof, cmd):
+    """profiles/sq_batch64.md: VALU and LDS work of one 64-disc batch run (all
+    pass kernels of the graph) and the time the VALU issue rate alone needs."""
+    v = _counter_sums(os.path.join(out, "b_sq"), "k_pass")
+    meta = _last_json(os.path.join(out, "b_sq.out"))
+    if not v or not meta:
+        return
+    runs = meta["graph_runs"]
+    per = {k: sum(x) / runs for k, x in v.items()}
+    alg, cells = meta["algorithmic_bytes"], meta["cells"]
+    # one wave64 VALU instruction per SIMD every 4 cycles, 1024 SIMDs
+    floor_s = per["SQ_INSTS_VALU"] * 4 / (VALU_SIMDS * VALU_CLOCK_HZ)
+    gui = sum(v["GRBM_GUI_ACTIVE"]) / 8  # summed over the 8 XCDs
+    busy = 100 * sum(v["SQ_ACTIVE_INST_VALU"]) / 256 / gui
+    lines = ["# VALU work of the 64-disc batch (bench.py --batch)", "",
+             "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
+             "    " + cmd["b_sq"], "",
+             f"Counters summed over every pass-kernel dispatch of the run (untuned plan) and divided "
+             f"by its {runs} graph runs.  Per run:", "",
+             "| Quantity | Value |", "|---|---|",
+             f"| waves | {per['SQ_WAVES']:.0f} |",
+             f"| VALU wave-instructions (SQ_INSTS_VALU) | {per['SQ_INSTS_VALU'] / 1e6:.1f} M |",
+             f"| LDS wave-instructions (SQ_INSTS_LDS) | {per['SQ_INSTS_LDS'] / 1e6:.1f} M |",
+             f"| VALU instructions per cell | {per['SQ_INSTS_VALU'] * 64 / cells:.0f} lane-ops |",
+             f"| VALUBusy over the pass kernels (100 SQ_ACTIVE_INST_VALU / CU_NUM / GRBM_GUI_ACTIVE) | "
+             f"{busy:.1f} % |",
+             f"| time at the full VALU issue rate (4 cycles per wave-instruction, "
+             f"{VALU_SIMDS} SIMDs, {VALU_CLOCK_HZ / 1e9:.1f} GHz) | {floor_s * 1e6:.1f} us |",
+             f"| HBM fraction if the run took only that time ({alg / 1e6:.1f} MB algorithmic) | "
+             f"{alg / floor_s / (HBM_PEAK_GBS * 1e9):.2f} |"]
+    with open(os.path.join(prof, "sq_batch64.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 
