@@ -76,11 +76,13 @@ enum {
     SG_SECOND_ORDER = 128u     /* kernel table: hat-weighted sources (below)  */
 };
 
-/* SG_SECOND_ORDER (sg_kernel_table, FFT path): the sources are taken as the
- * piecewise-bilinear interpolant of the cell values on the (u, phi) grid
- * (tensor-product hat functions on the cell centres, periodic in phi; the
- * first and last rings' hats reach one cell beyond the grid), integrated
- * exactly against the kernel.  The table then holds
+/* SG_SECOND_ORDER (sg_kernel_table, FFT path; an option beyond the paper,
+ * whose convolution of Sect. 5.2 samples the App. C kernels at cell-centre
+ * offsets): the sources are taken as the piecewise-bilinear interpolant of
+ * the cell values on the (u, phi) grid (tensor-product hat functions on the
+ * cell centres, periodic in phi; the first and last rings' hats reach half a
+ * cell past the grid's edges), integrated exactly against the App. C
+ * kernels.  The table then holds
  *   W_c(P, Q) = int int (1 - |s|)(1 - |t|) K_c((P + s) du, (Q + t) dphi) ds dt,
  * s, t in [-1, 1], in place of the point samples and the own-cell average:
  * the discrete field converges at second order in du, dphi to the field of
