@@ -196,7 +196,7 @@ def summarize_rocprof(out):
     lines = ["# Kernel time, two-fluid 1024x2048 FFT path (bench.py workload)", "",
              "Command (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output "
              "root):", "", "    " + cmd["kt"], "",
-             "The run tunes the plan, times warm steps (graph launches back to back), cold steps "
+             "The run tunes the plan, times warm steps (launched back to back), cold steps "
              "(each after a 512 MiB cache flush, the headline) and cold steps pass by pass "
              "(sg_field_fft_profile with reps = 1 after a flush), then warm passes back to back. "
              "All dispatches of a kernel are averaged in the table.", "",
@@ -215,8 +215,8 @@ def summarize_rocprof(out):
         if cold_us:
             us = rl["kernel_ms"] * 1e3
             lines += ["", f"Cold pass 2: the {ncold} dispatches of `{rl['kernel_name']}` that follow "
-                          f"pass 1 right after the cache flush (the cold steps, in and out of the "
-                          f"graph) average {cold_us:.2f} us in the trace; bench.py's own HIP-event "
+                          f"pass 1 right after the cache flush (the cold steps, and the cold steps "
+                          f"timed pass by pass) average {cold_us:.2f} us in the trace; bench.py's own HIP-event "
                           f"timing of the cold pass in the same run (the roofline's kernel time) is "
                           f"{us:.2f} us ({abs(us - cold_us) / cold_us * 100:.1f} % apart)."]
     with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
@@ -539,7 +539,7 @@ def main():
 
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    # warm steps: graph launches back to back; the disc's 118 MB working set
+    # warm steps: launched back to back; the disc's 118 MB working set
     # then stays in the 256 MB Infinity Cache (reported in extra only)
     for _ in range(args.warmup):
         F.run()

@@ -258,12 +258,16 @@ typedef struct sg_disc {
  * log-polar FFT convolution (App. C convolution form, Sect. 5.2 zero
  * padding).  Float arithmetic, float accumulation.  All discs of the batch
  * (any mix of supported sizes, one to four fluids, all ordered pairs fused
- * per spectral point) run in one HIP-graph launch of three passes:
- * phi transform of Sigma, fused u-transform / spectral multiply / inverse
- * u-transform, inverse phi transform.  The graph and a device copy of the
- * batch descriptors are cached per (sizes, pointers) signature on the first
- * call (that call allocates and synchronises once); later calls with the
- * same signature only launch.  At most 256 signatures are kept; a new one
+ * per spectral point) run as three passes: phi transform of Sigma, fused
+ * u-transform / spectral multiply / inverse u-transform, inverse phi
+ * transform.  A batch whose discs fall into several launch classes of one
+ * pass (transform lengths, fluid counts) runs as one HIP-graph launch whose
+ * branches run those classes side by side; a batch with one class per pass
+ * enqueues its three kernels directly (a graph launch would only add
+ * latency).  The plan, the graph where used and a device copy of the batch
+ * descriptors are cached per (sizes, pointers) signature on the first call
+ * (that call allocates and synchronises once); later calls with the same
+ * signature only launch.  At most 256 signatures are kept; a new one
  * beyond that releases the least recently used (after a device
  * synchronisation).  d_ws: sg_field_fft_workspace_bytes(discs, n)
  * bytes, 256-byte aligned; its address is part of the signature.
@@ -489,7 +493,7 @@ sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, 
 void sg_release(void);
 
 /* Number of batch signatures (discs' shapes and buffer addresses, workspace,
- * device) whose plan and graph sg_field_fft currently caches; a caller that
+ * device) whose plan (and graph, where used) sg_field_fft currently caches; a caller that
  * keeps its buffers sees it stay constant after the first call. */
 int sg_field_fft_cache_entries(void);
 

@@ -324,7 +324,7 @@ def self_cell(g: Grid, ha, hb, which, out, stream=None):
 
 
 def field_fft_cache_entries() -> int:
-    """Batch signatures whose plan and graph sg_field_fft keeps cached."""
+    """Batch signatures whose plan (and graph, where used) sg_field_fft keeps cached."""
     return int(_lib.sg_field_fft_cache_entries())
 
 

@@ -35,7 +35,7 @@ def build_table(g, f, flags=0, device=None):
 
 class FFTField:
     """A fixed batch of discs for sg_field_fft with persistent tables,
-    workspace and outputs (so the cached graph keeps stable addresses)."""
+    workspace and outputs (so the cached plan keeps stable addresses)."""
 
     def __init__(self, specs, flags=0, device=None):
         """specs: dicts with n_r, n_phi, r_min, r_max, h (one aspect ratio per
@@ -80,7 +80,7 @@ class FFTField:
 class SemiSpectral:
     """One disc on the semi-spectral path (any H_f(r)): a persistent table,
     Sigma and outputs.  refresh(H) rebuilds the radial operators for new
-    scale heights in place (the cached graph stays valid); run() solves."""
+    scale heights in place (the cached plan stays valid); run() solves."""
 
     def __init__(self, n_r, n_phi, r_min, r_max, n_fluids, flags=0, device=None, species_group=None):
         dev = _dev(device)
@@ -148,8 +148,8 @@ def potential(g, h, sigma, H=None, flags=0, stream=None):
 class _Slot:
     """Persistent device state of SGField for one (device, grid, aspect ratios,
     flags): kernel table, input and output buffers, workspaces.  The library
-    sees the same buffers on every call, so sg_field_fft replays one cached
-    graph and nothing is allocated on the device after the first forward and
+    sees the same buffers on every call, so sg_field_fft reuses one cached
+    plan and nothing is allocated on the device after the first forward and
     backward (returned tensors come from torch's caching allocator)."""
 
     def __init__(self, g, hs, flags, device):
@@ -224,7 +224,7 @@ class SGField(torch.autograd.Function):
     aspect ratios; indirect: add the indirect term.  Forward: sg_field_fft.
     Backward: sg_field_adjoint (dL/dSigma and dL/dh).  Repeated calls with the
     same grid, aspect ratios and flags reuse one persistent slot (table,
-    buffers, workspaces) and therefore one cached graph."""
+    buffers, workspaces) and therefore one cached plan."""
 
     @staticmethod
     def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max, indirect=False):

@@ -622,9 +622,9 @@ def test_adjoint_256x512_dsigma_against_central_differences(cfg5_fd):
         assert e < 1e-4, (a, e)
 
 
-def test_sgfield_replays_one_graph_and_allocates_nothing_after_warm_up(sg, T, W):
+def test_sgfield_reuses_one_plan_and_allocates_nothing_after_warm_up(sg, T, W):
     """Repeated SGField forward + backward on one grid and h: after the first
-    call no new sg_field_fft signature is cached (one graph replayed) and
+    call no new sg_field_fft signature is cached (one plan reused) and
     torch's allocator makes no new device allocation; every repetition gives
     the same outputs and gradients."""
     w = W.adjoint(n_r=64, n_phi=128)
