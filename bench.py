@@ -217,8 +217,15 @@ def summarize_rocprof(out):
             lines += ["", f"Cold pass 2: the {ncold} dispatches of `{rl['kernel_name']}` that follow "
                           f"pass 1 right after the cache flush (the cold steps, and the cold steps "
                           f"timed pass by pass) average {cold_us:.2f} us in the trace; bench.py's own HIP-event "
-                          f"timing of the cold pass in the same run (the roofline's kernel time) is "
-                          f"{us:.2f} us ({abs(us - cold_us) / cold_us * 100:.1f} % apart)."]
+                          f"timing of the cold pass in the same, profiled run (the roofline's kernel time) is "
+                          f"{us:.2f} us ({abs(us - cold_us) / cold_us * 100:.1f} % apart; the profiler "
+                          f"delays the events around each launch)."]
+            plain = _last_json(os.path.join(os.path.dirname(os.path.abspath(out)), "bench.json"))
+            if plain and "roofline" in plain and plain["roofline"].get("kernel_name") == rl["kernel_name"]:
+                pu = plain["roofline"]["kernel_ms"] * 1e3
+                lines[-1] += (f"  The plain `python3 bench.py` run of the same session (no profiler) "
+                              f"timed it at {pu:.2f} us ({abs(pu - cold_us) / cold_us * 100:.1f} % from "
+                              f"the trace).")
     with open(os.path.join(prof, "kernels_bifluid_1024x2048.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
