@@ -89,9 +89,11 @@ enum {
  * a smooth density, where the cell-centre sums converge at first order (the
  * ring kernel's 1/X and log|X| singularities).  The solve, its graph and its
  * cost are unchanged; the table build integrates each entry (Gauss-Legendre,
- * polar rules at the singular point).  Not with SG_WITH_DH or
- * SG_SELF_CELL_EXCLUDE (SG_ERR_UNSUPPORTED); SG_INDIRECT keeps its
- * point-mass form. */
+ * polar rules at the singular point), and with SG_WITH_DH the d/dh spectra
+ * integrate the kernel's h derivatives the same way, so sg_field_adjoint's
+ * dL/dh is that of the second-order field.  Not with SG_SELF_CELL_EXCLUDE
+ * (SG_ERR_UNSUPPORTED: the own cell is an entry like any other); SG_INDIRECT
+ * keeps its point-mass form. */
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
  * fluid also receives the acceleration -sum_a grad Phi_{a,ind} of the frame

@@ -52,6 +52,8 @@ def lib():
         L.sg_oracle_F.argtypes = [ctypes.c_double]
         L.sg_oracle_dF.restype = ctypes.c_double
         L.sg_oracle_dF.argtypes = [ctypes.c_double]
+        L.sg_oracle_D.restype = ctypes.c_double
+        L.sg_oracle_D.argtypes = [ctypes.c_double]
         L.sg_oracle_kernel.restype = ctypes.c_double
         L.sg_oracle_kernel.argtypes = [ctypes.c_double] * 3
         L.sg_oracle_conv_kernels.restype = None
@@ -96,7 +98,7 @@ def lib():
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             _dp, _dp, _dp, ctypes.c_uint, _dp]
         L.sg_oracle_hat_weight.restype = None
-        L.sg_oracle_hat_weight.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
+        L.sg_oracle_hat_weight.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_int, _dp]
         L.sg_oracle_threads.restype = ctypes.c_int
         L.sg_oracle_threads.argtypes = []
         _lib = L
@@ -128,6 +130,13 @@ def F(x):
 def dF(x):
     x = np.atleast_1d(_d(x))
     return np.array([lib().sg_oracle_dF(float(v)) for v in x.ravel()]).reshape(x.shape)
+
+
+def D(x):
+    """-x F'(x) - 3/2 F(x), the factor of the kernel's h derivative, from its
+    cancellation-free integral (elementwise)."""
+    x = np.atleast_1d(_d(x))
+    return np.array([lib().sg_oracle_D(float(v)) for v in x.ravel()]).reshape(x.shape)
 
 
 def kernel(s, Ha, Hb):
@@ -196,10 +205,11 @@ def field_table_pairs(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0, whi
     return out
 
 
-def hat_weight(P, Q, du, dphi, ha, hb):
-    """Second-order offset weights (W_r, W_phi) of offset (P, Q) in cells."""
+def hat_weight(P, Q, du, dphi, ha, hb, which=0):
+    """Second-order offset weights (W_r, W_phi) of offset (P, Q) in cells, or
+    their derivatives in h_a (which = 1) or h_b (which = 2)."""
     W = np.empty(2)
-    lib().sg_oracle_hat_weight(int(P), int(Q), du, dphi, ha, hb, _ptr(W))
+    lib().sg_oracle_hat_weight(int(P), int(Q), du, dphi, ha, hb, int(which), _ptr(W))
     return float(W[0]), float(W[1])
 
 

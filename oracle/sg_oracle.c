@@ -86,6 +86,34 @@ static void orc_F_dF(double x, double *F, double *dF)
     if (dF) *dF = -h * sD;
 }
 
+/* D(x) = -x F'(x) - (3/2) F(x), the factor of the kernel's h derivative.
+ * Its two terms cancel to O(x^{-5/2}) against O(x^{-3/2}) at large x, so it
+ * is not formed from F and F'.  With c = cosh t - 1 the representation above
+ * is F(x) = int_0^inf e^{-x c} sqrt(c/(c+2)) dc; integrating -x F' by parts
+ * (x c e^{-xc} = -c d/dc e^{-xc}) gives
+ *     D(x) = int_0^inf e^{-x c} (c g'(c) - g(c)/2) dc,  g = sqrt(c/(c+2)),
+ * and c g' - g/2 = -(1/2) (c/(c+2))^{3/2} = -(1/2) tanh^3(t/2), so
+ *     D(x) = -(1/2) int_0^inf exp(-x c(t)) tanh^3(t/2) sinh t dt,
+ * an integrand of one sign, evaluated with F's trapezoidal rule (tanh(t/2)
+ * is analytic in the same strip).  Parity pinned against -x F' - 3F/2 from
+ * mpmath Bessel values at 40 digits (tests). */
+static double orc_D(double x)
+{
+    double h = 0.2;
+    if (0.4 / sqrt(x) < h) h = 0.4 / sqrt(x);
+    double T = 2.0 * asinh(sqrt(30.0 / x));
+    long n = (long)ceil(T / h);
+    double s = 0.0;
+    for (long k = 1; k <= n; ++k) {
+        double th = tanh(0.5 * (double)k * h);
+        double sh = sinh(0.5 * (double)k * h);
+        s += exp(-x * 2.0 * sh * sh) * th * th * th * sinh((double)k * h);
+    }
+    return -0.5 * h * s;
+}
+
+double sg_oracle_D(double x) { return orc_D(x); }
+
 double sg_oracle_F(double x)
 {
     double F;
@@ -129,8 +157,9 @@ double sg_oracle_kernel(double s, double Ha, double Hb)
  *
  * which = 0: (K_r, K_phi); 1: d/dh_a of both; 2: d/dh_b of both.
  * Derivative: with G = K h^3/F (independent of h), x = (cosh X - cos phi)
- * /(4 h^2), dK/d(h^2) = G (h^2)^{-5/2} [-x F'(x) - 3/2 F(x)], and
- * d(h^2)/dh_a = h_a e^{-X}, d(h^2)/dh_b = h_b e^{X}.
+ * /(4 h^2), dK/d(h^2) = G (h^2)^{-5/2} D(x), D(x) = -x F'(x) - 3/2 F(x)
+ * (orc_D, cancellation-free), and d(h^2)/dh_a = h_a e^{-X},
+ * d(h^2)/dh_b = h_b e^{X}.
  * Parity pinned against the pairwise Cartesian sum (tests) and, for the
  * derivatives, against central differences of which = 0.
  * ------------------------------------------------------------------------ */
@@ -143,9 +172,9 @@ static void orc_conv(double X, double phi, double ha, double hb, int which,
     double eX_m_cos = expm1(X) + 2.0 * sp * sp;
     double d2 = 2.0 * cosh_m_cos / h2;
     double x = d2 / 8.0;
-    double F, dF;
-    orc_F_dF(x, &F, &dF);
     if (which == 0) {
+        double F;
+        orc_F_dF(x, &F, NULL);
         double L = ORC_SQRT_PI * x * F;
         double pref = L / (ORC_PI * d2) * pow(exp(-X) / h2, 1.5);
         *Kr = pref * eX_m_cos;
@@ -154,7 +183,7 @@ static void orc_conv(double X, double phi, double ha, double hb, int which,
     }
     /* G = e^{-3X/2} / (8 sqrt(pi)) times the angular factor */
     double G = exp(-1.5 * X) / (8.0 * ORC_SQRT_PI);
-    double dK_dh2 = G * pow(h2, -2.5) * (-x * dF - 1.5 * F);
+    double dK_dh2 = G * pow(h2, -2.5) * orc_D(x);
     double dh2 = (which == 1) ? ha * exp(-X) : hb * exp(X);
     *Kr = dK_dh2 * dh2 * eX_m_cos;
     *Kphi = dK_dh2 * dh2 * sin(phi);
@@ -779,7 +808,9 @@ int sg_oracle_field_pairwise(int nr, int nphi, double rmin, double rmax, int nf,
  * offset table holds, for all offsets including (0, 0),
  *   W_c(P, Q) = int_{-1}^{1} int_{-1}^{1} Lambda(s) Lambda(t)
  *               K_c((P + s) du, (Q + t) dphi) ds dt,   c = r, phi,
- * in place of the point value K_c(P du, Q dphi) and the own-cell average.
+ * in place of the point value K_c(P du, Q dphi) and the own-cell average;
+ * which = 1, 2 integrates the kernel's h_a, h_b derivatives (orc_conv) the
+ * same way, giving the derivatives of W.
  * Integrated square by square (Lambda(s) Lambda(t) is bilinear on each of
  * the four unit squares of the support).  A square that has the kernel's
  * singular point (s, t) = (-P, -Q) as a corner is integrated in polar
@@ -855,7 +886,7 @@ static double orc_hat(double x) { return fabs(x) < 1.0 ? 1.0 - fabs(x) : 0.0; }
 
 typedef struct {
     double du, dphi, ha, hb;
-    int P, Q;
+    int P, Q, which;
     int sx, sy;     /* singular square: directions of the square seen from the corner */
     double s_lo, t_lo; /* regular square: lower corner */
     double outer;   /* the outer variable (theta, or s) fixed for the inner integral */
@@ -870,7 +901,7 @@ static void orc_hat_point(const orc_hatctx *c, double s, double t, double y[2])
         return;
     }
     double kr, kp;
-    orc_conv((c->P + s) * c->du, (c->Q + t) * c->dphi, c->ha, c->hb, 0, &kr, &kp);
+    orc_conv((c->P + s) * c->du, (c->Q + t) * c->dphi, c->ha, c->hb, c->which, &kr, &kp);
     y[0] = w * kr;
     y[1] = w * kp;
 }
@@ -886,7 +917,7 @@ static void orc_hat_rho(double rho, void *vc, double y[2])
     const double px = rho * cos(c->outer), py = rho * sin(c->outer);
     const double w = (c->P == 0 ? 1.0 - px : px) * (c->Q == 0 ? 1.0 - py : py);
     double kr, kp;
-    orc_conv(c->sx * px * c->du, c->sy * py * c->dphi, c->ha, c->hb, 0, &kr, &kp);
+    orc_conv(c->sx * px * c->du, c->sy * py * c->dphi, c->ha, c->hb, c->which, &kr, &kp);
     y[0] = rho * w * kr;
     y[1] = rho * w * kp;
 }
@@ -919,10 +950,11 @@ static void orc_agl_init(void)
     orc_agl_ready = 1;
 }
 
-/* W_r, W_phi of offset (P, Q) for cell sizes du, dphi (nodes initialised) */
-static void orc_hat_weight(int P, int Q, double du, double dphi, double ha, double hb, double *W)
+/* W_r, W_phi of offset (P, Q) for cell sizes du, dphi, or their h
+ * derivatives (which; nodes initialised) */
+static void orc_hat_weight(int P, int Q, double du, double dphi, double ha, double hb, int which, double *W)
 {
-    orc_hatctx c = {du, dphi, ha, hb, P, Q, 1, 1, 0.0, 0.0, 0.0};
+    orc_hatctx c = {du, dphi, ha, hb, P, Q, which, 1, 1, 0.0, 0.0, 0.0};
     W[0] = W[1] = 0.0;
     for (int s0 = -1; s0 <= 0; ++s0)
         for (int t0 = -1; t0 <= 0; ++t0) {
@@ -946,10 +978,10 @@ static void orc_hat_weight(int P, int Q, double du, double dphi, double ha, doub
         }
 }
 
-void sg_oracle_hat_weight(int P, int Q, double du, double dphi, double ha, double hb, double *W)
+void sg_oracle_hat_weight(int P, int Q, double du, double dphi, double ha, double hb, int which, double *W)
 {
     orc_agl_init();
-    orc_hat_weight(P, Q, du, dphi, ha, hb, W);
+    orc_hat_weight(P, Q, du, dphi, ha, hb, which, W);
 }
 
 typedef struct {
@@ -980,7 +1012,7 @@ static int orc_build_table(const orc_grid *g, double ha, double hb, int which, i
             double kr, kp;
             if (second) {
                 double W[2];
-                orc_hat_weight(p - (nr - 1), 2 * q <= np ? q : q - np, g->du, g->dphi, ha, hb, W);
+                orc_hat_weight(p - (nr - 1), 2 * q <= np ? q : q - np, g->du, g->dphi, ha, hb, which, W);
                 kr = W[0];
                 kp = W[1];
             } else if (p == nr - 1 && q == 0) {
@@ -1017,7 +1049,7 @@ int sg_oracle_field_table(int nr, int nphi, double rmin, double rmax, int nf, co
     if (nr < 1 || nphi < 1 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
     if (which < 0 || which > 2) return 1;
     const int second = (flags & ORC_FLAG_SECOND_ORDER) != 0;
-    if (second && (which != 0 || nphi < 4 || (flags & ORC_FLAG_EXCLUDE_SELF))) return 1;
+    if (second && (nphi < 4 || (flags & ORC_FLAG_EXCLUDE_SELF))) return 1;
     orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
     const int64_t N = (int64_t)nr * nphi;
     const double scale = -g.du * g.dphi;

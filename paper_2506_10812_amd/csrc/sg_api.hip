@@ -50,10 +50,10 @@ static bool flags_ok(uint32_t flags)
     return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_WITH_DH | SG_INDIRECT | SG_SECOND_ORDER)) == 0;
 }
 
-// SG_SECOND_ORDER tables have no d/dh spectra and no separate own-cell term
+// SG_SECOND_ORDER tables have no separate own-cell term to drop
 static bool second_order_ok(uint32_t flags)
 {
-    return !(flags & SG_SECOND_ORDER) || !(flags & (SG_WITH_DH | SG_SELF_CELL_EXCLUDE));
+    return !(flags & SG_SECOND_ORDER) || !(flags & SG_SELF_CELL_EXCLUDE);
 }
 
 // Semi-spectral path: n_phi a power of two in [4, 2048], 1 <= n_r <= 2048.

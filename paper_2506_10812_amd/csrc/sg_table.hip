@@ -250,7 +250,7 @@ __device__ inline double sg_hat(double x) { return fmax(0.0, 1.0 - fabs(x)); }
 // Tensor Gauss-Legendre over pieces k in [k0, k1) (step dk) of the unit square
 // [ds, ds + 1] x [dt, dt + 1] of entry (P, Q), cut into ms x mt sub-squares.
 __device__ inline void sg_hat_square(int P, int Q, int ds, int dt, int ms, int mt, int k0, int k1, int dk,
-                                     double du, double dphi, double ha, double hb, const double *wq,
+                                     double du, double dphi, double ha, double hb, int which, const double *wq,
                                      double &wr, double &wp)
 {
     for (int k = k0; k < k1; k += dk) {
@@ -261,7 +261,7 @@ __device__ inline void sg_hat_square(int P, int Q, int ds, int dt, int ms, int m
         const double w = sg_gl6_w[a] * sg_gl6_w[b] / (ms * mt) * sg_hat(s) * sg_hat(t);
         const double X = (P + s) * du, ph = (Q + t) * dphi;
         double kr, kp;
-        sg_conv_kernel64(X, sin(0.5 * ph), sin(ph), ha, hb, 0, wq, kr, kp);
+        sg_conv_kernel64(X, sin(0.5 * ph), sin(ph), ha, hb, which, wq, kr, kp);
         wr += w * kr;
         wp += w * kp;
     }
@@ -286,7 +286,9 @@ __device__ inline bool sg_hat_singular(int P, int Q, int ds, int dt)
 
 // One thread per entry of the wrapped offset grid (as k_sample): entries with
 // |P| >= 2 or |Q| >= 2 (no singular square); row n_r (offset +-n_r) is zero.
-__global__ void k_sample_hat_far(double2 *A, int nr, int nphi, double du, double ha, double hb)
+// which: 0 the weights, 1 and 2 their derivatives in h_a and h_b (the
+// kernel's derivatives integrated with the same rules).
+__global__ void k_sample_hat_far(double2 *A, int nr, int nphi, double du, double ha, double hb, int which)
 {
     __shared__ double wq[FQuad<double>::TABLE];
     sg_fill_weights<double>(wq);
@@ -306,7 +308,7 @@ __global__ void k_sample_hat_far(double2 *A, int nr, int nphi, double du, double
         for (int dt = -1; dt <= 0; ++dt) {
             int ms, mt;
             sg_hat_split(P, Q, ds, dt, du, dphi, ms, mt);
-            sg_hat_square(P, Q, ds, dt, ms, mt, 0, 36 * ms * mt, 1, du, dphi, ha, hb, wq, wr, wp);
+            sg_hat_square(P, Q, ds, dt, ms, mt, 0, 36 * ms * mt, 1, du, dphi, ha, hb, which, wq, wr, wp);
         }
     A[(size_t)p * nphi + q] = make_double2(wr, wp);
 }
@@ -317,7 +319,8 @@ __global__ void k_sample_hat_far(double2 *A, int nr, int nphi, double du, double
 // the unit square with the corner collapsed (x = xi, y = xi eta and
 // x = xi eta, y = xi; Jacobian xi).  sym: K_r symmetrised in X (entry (0, 0)).
 __device__ inline void sg_hat_corner(int P, int Q, int sx, int sy, bool sym, double du, double dphi, double ha,
-                                     double hb, const GLNodes &gl, const double *wq, double &wr, double &wp)
+                                     double hb, int which, const GLNodes &gl, const double *wq, double &wr,
+                                     double &wp)
 {
     constexpr int NX = SG_PANELS * SG_GLX_N;
     for (int idx = threadIdx.x; idx < NX * SG_GL_N; idx += blockDim.x) {
@@ -335,10 +338,10 @@ __device__ inline void sg_hat_corner(int P, int Q, int sx, int sy, bool sym, dou
             // (not 1 - |-1 + x|, which loses the digits of a small x)
             const double w = wgt * (P == 0 ? 1.0 - x : x) * (Q == 0 ? 1.0 - y : y);
             if (sym) {
-                wr += w * sg_sym_kr64(X, ph, ha, hb, 0, wq);
+                wr += w * sg_sym_kr64(X, ph, ha, hb, which, wq);
             } else {
                 double kr, kp;
-                sg_conv_kernel64(X, sin(0.5 * ph), sin(ph), ha, hb, 0, wq, kr, kp);
+                sg_conv_kernel64(X, sin(0.5 * ph), sin(ph), ha, hb, which, wq, kr, kp);
                 wr += w * kr;
                 wp += w * kp;
             }
@@ -348,7 +351,7 @@ __device__ inline void sg_hat_corner(int P, int Q, int sx, int sy, bool sym, dou
 
 // One 256-thread block per entry with |P|, |Q| <= 1 (nine entries).
 __global__ void __launch_bounds__(256) k_sample_hat_near(double2 *A, int nr, int nphi, double du, double ha,
-                                                          double hb, GLNodes gl)
+                                                          double hb, int which, GLNodes gl)
 {
     __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[256];
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(256) k_sample_hat_near(double2 *A, int nr, int
         // four squares with the singular corner; folded: 2 x 2 x [0,1]^2 with
         // K_r symmetrised in X and even in phi (K_phi contributes 0)
         double r = 0.0, t = 0.0;
-        sg_hat_corner(0, 0, 1, 1, true, du, dphi, ha, hb, gl, wq, r, t);
+        sg_hat_corner(0, 0, 1, 1, true, du, dphi, ha, hb, which, gl, wq, r, t);
         wr = 4.0 * r;
     } else {
         for (int ds = -1; ds <= 0; ++ds)
@@ -369,12 +372,12 @@ __global__ void __launch_bounds__(256) k_sample_hat_near(double2 *A, int nr, int
                 if (sg_hat_singular(P, Q, ds, dt)) {
                     // orientation of the square seen from the corner (-P, -Q)
                     const int sx = (ds == -P) ? 1 : -1, sy = (dt == -Q) ? 1 : -1;
-                    sg_hat_corner(P, Q, sx, sy, false, du, dphi, ha, hb, gl, wq, wr, wp);
+                    sg_hat_corner(P, Q, sx, sy, false, du, dphi, ha, hb, which, gl, wq, wr, wp);
                 } else {
                     int ms, mt;
                     sg_hat_split(P, Q, ds, dt, du, dphi, ms, mt);
                     sg_hat_square(P, Q, ds, dt, ms, mt, threadIdx.x, 36 * ms * mt, blockDim.x, du, dphi, ha, hb,
-                                  wq, wr, wp);
+                                  which, wq, wr, wp);
                 }
             }
     }
@@ -678,7 +681,7 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
     double *selfbuf = (double *)((char *)B + sg_align256(sizeof(double2) * 2 * (size_t)L.ncol * 2 * nr));
     const bool with_dh = (flags & SG_WITH_DH) != 0;
     const bool excl = (flags & SG_SELF_CELL_EXCLUDE) != 0;
-    const bool second = (flags & SG_SECOND_ORDER) != 0;  // no d/dh, no own-cell switch
+    const bool second = (flags & SG_SECOND_ORDER) != 0;  // no own-cell switch
 
     // twiddle tables
     {
@@ -731,11 +734,11 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
                     GLNodes gl;
                     sg_gl_nodes(gl);
                     hipLaunchKernelGGL(k_sample_hat_far, dim3((nphi + 255) / 256, 2 * nr), dim3(256), 0, s, A, nr,
-                                       nphi, du, fl->h[a], fl->h[b]);
+                                       nphi, du, fl->h[a], fl->h[b], w);
                     hipLaunchKernelGGL(k_sample_hat_near, dim3(9), dim3(256), 0, s, A, nr, nphi, du, fl->h[a],
-                                       fl->h[b], gl);
-                    // the header's own-cell value of this pair: W_r(0, 0)
-                    hipLaunchKernelGGL(k_copy_w00, dim3(1), dim3(1), 0, s, (const double2 *)A, selfbuf + pair);
+                                       fl->h[b], w, gl);
+                    // the header's own-cell value of this pair (or its derivative): W_r(0, 0)
+                    hipLaunchKernelGGL(k_copy_w00, dim3(1), dim3(1), 0, s, (const double2 *)A, (double *)sv);
                 } else {
                     hipLaunchKernelGGL(k_sample, dim3((nphi + 255) / 256, 2 * nr), dim3(256), 0, s, A,
                                        nr, nphi, du, fl->h[a], fl->h[b], w, sv);

@@ -7,7 +7,7 @@ import torch
 
 import ctypes
 
-from . import (F32, F64, INDIRECT, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, Fluids, field_adjoint,
+from . import (F32, F64, INDIRECT, SECOND_ORDER, SELF_CELL_EXCLUDE, SEMI_SPECTRAL, WITH_DH, Fluids, field_adjoint,
                field_adjoint_workspace_bytes, field_fft_tune, potential_direct,
                potential_direct_workspace_bytes, field_direct, field_direct_workspace_bytes, field_fft,
                field_fft_workspace_bytes, fluids, grid, kernel_table, kernel_table_bytes,
@@ -218,19 +218,20 @@ _slots = _SlotCache()
 
 
 class SGField(torch.autograd.Function):
-    """g_r, g_phi = SGField.apply(sigma, h, n_r, n_phi, r_min, r_max[, indirect]).
+    """g_r, g_phi = SGField.apply(sigma, h, n_r, n_phi, r_min, r_max[, indirect[, second_order]]).
 
     sigma: float32 CUDA tensor [F][n_r][n_phi]; h: float64 tensor [F] of
-    aspect ratios; indirect: add the indirect term.  Forward: sg_field_fft.
+    aspect ratios; indirect: add the indirect term; second_order: the
+    hat-weighted kernel table (SG_SECOND_ORDER).  Forward: sg_field_fft.
     Backward: sg_field_adjoint (dL/dSigma and dL/dh).  Repeated calls with the
     same grid, aspect ratios and flags reuse one persistent slot (table,
     buffers, workspaces) and therefore one cached plan."""
 
     @staticmethod
-    def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max, indirect=False):
+    def forward(ctx, sigma, h, n_r, n_phi, r_min, r_max, indirect=False, second_order=False):
         g = grid(n_r, n_phi, r_min, r_max)
         hs = [float(v) for v in h.detach().cpu().tolist()]
-        flags = WITH_DH | (INDIRECT if indirect else 0)
+        flags = WITH_DH | (INDIRECT if indirect else 0) | (SECOND_ORDER if second_order else 0)
         slot = _slots.get(g, hs, flags, sigma.device)
         sig = sigma.detach()
         gr, gp = slot.forward(sig)
@@ -244,4 +245,4 @@ class SGField(torch.autograd.Function):
         slot, h_device, h_dtype, s_dtype = ctx.meta
         dsig, dh = slot.backward(sig, lam_r, lam_phi)
         # gradients in the dtype (and, for h, the device) of the inputs
-        return dsig.to(s_dtype), dh.to(device=h_device, dtype=h_dtype), None, None, None, None, None
+        return dsig.to(s_dtype), dh.to(device=h_device, dtype=h_dtype), None, None, None, None, None, None

@@ -124,17 +124,18 @@ def test_direct_validation(sg):
 
 
 def test_second_order_flag_combinations(sg):
-    """SG_SECOND_ORDER changes the table's values, not its layout; it cannot
-    be combined with d/dh spectra or the own-cell switch, and only the FFT
-    path's table takes it."""
+    """SG_SECOND_ORDER changes the table's values, not its layout (with or
+    without d/dh spectra); it cannot be combined with the own-cell switch,
+    and only the FFT path's table takes it."""
     g = sg.grid(16, 32, 0.2, 5.0)
     f = sg.fluids([0.05, 0.005])
     L = sg.lib()
     nb = sg.kernel_table_bytes(g, f, 0)
     assert sg.kernel_table_bytes(g, f, sg.SECOND_ORDER) == nb
     assert sg.kernel_table_bytes(g, f, sg.SECOND_ORDER | sg.INDIRECT) == nb
+    assert sg.kernel_table_bytes(g, f, sg.SECOND_ORDER | sg.WITH_DH) == sg.kernel_table_bytes(g, f, sg.WITH_DH)
     assert sg.kernel_table_workspace_bytes(g, f, sg.SECOND_ORDER) > 0
-    for bad in (sg.SECOND_ORDER | sg.WITH_DH, sg.SECOND_ORDER | sg.SELF_CELL_EXCLUDE):
+    for bad in (sg.SECOND_ORDER | sg.SELF_CELL_EXCLUDE, sg.SECOND_ORDER | sg.SELF_CELL_EXCLUDE | sg.WITH_DH):
         assert sg.kernel_table_bytes(g, f, bad) == 0
         assert sg.kernel_table_workspace_bytes(g, f, bad) == 0
         st = L.sg_kernel_table(ctypes.byref(g), ctypes.byref(f), bad, ctypes.c_void_p(256),

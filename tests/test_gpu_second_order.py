@@ -121,25 +121,59 @@ def test_second_order_indirect_term_is_unchanged(sg, T, W):
 
 
 def test_second_order_adjoint_matches_oracle(sg, T, W):
-    """dL/dSigma on a second-order disc (the transposed hat-weighted
-    convolution) against the oracle's adjoint with the same table."""
+    """dL/dSigma and dL/dh on a second-order disc with d/dh spectra (the
+    transposed hat-weighted convolution, and the Parseval reduction over the
+    hat-weighted derivative tables) against the oracle's adjoint and h
+    derivative with the same table (1e-5 rel-RMS, 1e-4)."""
     nr, nphi = 16, 32
     w = W.adjoint(n_r=nr, n_phi=nphi)
     g = sg.grid(nr, nphi, w["r_min"], w["r_max"])
     f = sg.fluids(w["h"])
-    tab = T.build_table(g, f, sg.SECOND_ORDER)
+    flags = sg.SECOND_ORDER | sg.WITH_DH
+    tab = T.build_table(g, f, flags)
     rng = np.random.default_rng(11)
     lam_r = torch.tensor(rng.normal(size=(2, nr, nphi)), dtype=torch.float32)
     lam_p = torch.tensor(rng.normal(size=(2, nr, nphi)), dtype=torch.float32)
     sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda")
     lr, lp = lam_r.cuda(), lam_p.cuda()
     ds = torch.empty_like(sig)
-    disc = sg.make_disc(g, f, sg.SECOND_ORDER, sig, lr, lp, tab)
+    dh = torch.zeros(2, dtype=torch.float64, device="cuda")
+    disc = sg.make_disc(g, f, flags, sig, lr, lp, tab)
     ws = torch.empty(sg.field_adjoint_workspace_bytes(disc), dtype=torch.uint8, device="cuda")
-    sg.field_adjoint(disc, lr, lp, ds, None, ws)
+    sg.field_adjoint(disc, lr, lp, ds, dh, ws)
     torch.cuda.synchronize()
-    ref = O.adjoint_sigma(nr, nphi, w["r_min"], w["r_max"], w["h"], lam_r.double().numpy(),
-                          lam_p.double().numpy(), flags=O.SECOND_ORDER)
+    lr64, lp64 = lam_r.double().numpy(), lam_p.double().numpy()
+    ref = O.adjoint_sigma(nr, nphi, w["r_min"], w["r_max"], w["h"], lr64, lp64, flags=O.SECOND_ORDER)
     got = ds.double().cpu().numpy().reshape(2, -1)
     for a in range(2):
         assert rel_rms(got[a], ref[a]) < 1e-5, (a, rel_rms(got[a], ref[a]))
+    sig32 = sig.double().cpu().numpy()
+    refh = O.adjoint_h(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, lr64, lp64, flags=O.SECOND_ORDER)
+    say(f"  dL/dh device {dh.cpu().numpy()} oracle {refh}")
+    np.testing.assert_allclose(dh.cpu().numpy(), refh, rtol=1e-4)
+
+
+def test_sgfield_second_order_forward_and_gradients(sg, T, W):
+    """SGField with second_order=True: the forward is the oracle's
+    hat-weighted field, and for L = sum(g_r^2 + g_phi^2) the gradients are the
+    oracle's adjoint and h derivative at lambda = 2 g (1e-5 / 1e-4)."""
+    nr, nphi = 16, 32
+    w = W.adjoint(n_r=nr, n_phi=nphi)
+    sig = torch.tensor(w["sigma"], dtype=torch.float32, device="cuda", requires_grad=True)
+    h = torch.tensor(w["h"], dtype=torch.float64, device="cuda", requires_grad=True)
+    gr, gp = T.SGField.apply(sig, h, nr, nphi, w["r_min"], w["r_max"], False, True)
+    ((gr ** 2).sum() + (gp ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    sig32 = sig.detach().double().cpu().numpy()
+    rr, rp = O.field_table(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, flags=O.SECOND_ORDER)
+    g_r = gr.detach().double().cpu().numpy().reshape(2, -1)
+    g_p = gp.detach().double().cpu().numpy().reshape(2, -1)
+    for b in range(2):
+        assert rel_rms(g_r[b], rr[b]) < 1e-5 and rel_rms(g_p[b], rp[b]) < 1e-5
+    lr, lp = 2 * g_r.reshape(2, nr, nphi), 2 * g_p.reshape(2, nr, nphi)
+    ref = O.adjoint_sigma(nr, nphi, w["r_min"], w["r_max"], w["h"], lr, lp, flags=O.SECOND_ORDER)
+    got = sig.grad.double().cpu().numpy().reshape(2, -1)
+    for a in range(2):
+        assert rel_rms(got[a], ref[a]) < 1e-5, (a, rel_rms(got[a], ref[a]))
+    refh = O.adjoint_h(nr, nphi, w["r_min"], w["r_max"], w["h"], sig32, lr, lp, flags=O.SECOND_ORDER)
+    np.testing.assert_allclose(h.grad.cpu().numpy(), refh, rtol=1e-4)

@@ -47,6 +47,17 @@ def test_dF_matches_arbitrary_precision_bessel():
         assert abs(O.dF(x)[0] - ref) <= 2e-15 * abs(ref), x
 
 
+def test_D_matches_arbitrary_precision_bessel():
+    """D(x) = -x F'(x) - 3/2 F(x), the factor of the kernel's h derivative,
+    from the oracle's one-signed integral vs the two-term form at 40 digits
+    (where its cancellation at large x costs nothing).  At large x it is
+    O(x^-5/2) against terms of O(x^-3/2): in double the two-term form would
+    lose up to log10(x) digits there."""
+    for x in np.logspace(-12, 4.6, 45):
+        ref = float(-mp.mpf(x) * _dF_mp(x) - mp.mpf(1.5) * _F_mp(x))
+        assert abs(O.D(x)[0] - ref) <= 4e-15 * abs(ref), (x, O.D(x)[0], ref)
+
+
 # ------------------------------------------------------------------- kernel
 @pytest.mark.parametrize("s,Ha,Hb", [(0.7, 1.0, 1.0), (2.0, 1.0, 0.4), (5.0, 0.3, 1.2),
                                      (0.35, 0.5, 0.2), (9.0, 1.0, 1.0)])
@@ -355,6 +366,33 @@ def test_hat_weights_far_field_expansion():
                 assert abs(W[1]) <= 1e-12 * abs(W[0]), (P, W)
                 continue
             assert abs((W[c] - k[0]) / corr - 1) < 0.05, (P, Q, c, W[c] - k[0], corr)
+
+
+@pytest.mark.parametrize("du,dphi,ha,hb", [(0.05, 2 * math.pi / 128, 1e-3, 2e-3),
+                                           (math.log(25.0) / 256, 2 * math.pi / 512, 0.05, 0.005)])
+def test_hat_weight_h_derivatives_match_central_differences(du, dphi, ha, hb):
+    """d/dh_a and d/dh_b of the second-order weights (the kernel's h
+    derivatives integrated with the same quadrature) against central
+    differences of the weights themselves with Richardson extrapolation
+    (steps 1e-3 h and 2e-3 h: the plain differences converge as step^2,
+    1e-6 of the entry at 1e-3 h for the own cell); bar 1e-7 of the entry's
+    larger component."""
+    def cd(P, Q, which, e):
+        hp = (ha + e, hb) if which == 1 else (ha, hb + e)
+        hm = (ha - e, hb) if which == 1 else (ha, hb - e)
+        wp = O.hat_weight(P, Q, du, dphi, *hp)
+        wm = O.hat_weight(P, Q, du, dphi, *hm)
+        return [(a - b) / (2 * e) for a, b in zip(wp, wm)]
+
+    for P, Q in ((0, 0), (1, 0), (0, -1), (1, 1), (3, 2), (10, -7)):
+        for which in (1, 2):
+            e = 1e-3 * (ha if which == 1 else hb)
+            d1, d2 = cd(P, Q, which, e), cd(P, Q, which, 2 * e)
+            fd = [(4 * a - b) / 3 for a, b in zip(d1, d2)]
+            got = O.hat_weight(P, Q, du, dphi, ha, hb, which)
+            sc = max(abs(fd[0]), abs(fd[1]))
+            for c in range(2):
+                assert abs(got[c] - fd[c]) < 1e-7 * sc, (P, Q, which, c, got, fd)
 
 
 def _smooth_density(nr, nphi, urange, sig=0.7, kap=1.0):
