@@ -80,8 +80,8 @@ PROFILE_COMMANDS = {
                 "--output-format csv -d {out}/dir_valu -o run -- python3 {repo}/bench.py --direct",
 }
 # VALU issue: one wave64 instruction per SIMD every 4 cycles (16 lanes),
-# 256 CUs x 4 SIMDs at 2.4 GHz; FP32 (packed instructions disabled in this
-# build) and FP64 both issue at that rate: 78.6 TFLOP/s with FMA
+# 256 CUs x 4 SIMDs at 2.4 GHz; FP32 (packed instructions disabled in the
+# library's compile flags) and FP64 both issue at that rate: 78.6 TFLOP/s with FMA
 VALU_SIMDS, VALU_CLOCK_HZ, VALU_PEAK_TFLOPS = 1024, 2.4e9, 78.6
 COPY_BYTES = 4 << 28   # --copy-calibration copies 2^28 floats
 FLUSH_FLOATS = 1 << 27  # 512 MiB rewritten before a cold step (Infinity Cache: 256 MB)
@@ -495,8 +495,8 @@ def main():
         summarize_rocprof(args.summarize_rocprof)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md, not run", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (got --gpus {args.gpus}); "
+              "the path's sharding across GPUs is a design, not implemented here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -606,7 +606,7 @@ def main():
             tr = json.load(fh)
         # every variant of the pass moves the same bytes (radix order and tile
         # shape change the arithmetic order only), so the counters of any
-        # variant of this build describe the timed one
+        # variant of these kernel sources describe the timed one
         if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel") == dom_name:
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -9,7 +9,8 @@
 // Steps (all double precision):
 //   1. sample K_r + i K_phi on the wrapped offset grid X = p du
 //      (p in (-n_r, n_r), stored at p mod 2 n_r; row n_r is zero), phi = q dphi;
-//      offset (0,0) holds the self-cell average;
+//      offset (0,0) holds the self-cell average (SG_SECOND_ORDER: every entry,
+//      (0,0) included, is the hat-weighted integral of the kernel instead);
 //   2. phi transform of each row, split into the spectra of K_r and K_phi
 //      (two real rows in one complex transform);
 //   3. u transform (length 2 n_r) of each column m <= n_phi/2, keep

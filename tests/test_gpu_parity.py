@@ -2,8 +2,8 @@
 
 Tolerances: the FP64 direct sum must agree to 1e-12 (relative RMS and max
 relative to the largest |g|; summation order differs, so not bitwise); every
-float path to 1e-5 relative RMS per fluid and component (the float
-accuracy bound of the build's target), with max-norm bounds stated per test.
+float path to 1e-5 relative RMS per fluid and component, with max-norm
+bounds stated per test.
 """
 import numpy as np
 import pytest
