@@ -93,7 +93,14 @@ enum {
  * integrate the kernel's h derivatives the same way, so sg_field_adjoint's
  * dL/dh is that of the second-order field.  Not with SG_SELF_CELL_EXCLUDE
  * (SG_ERR_UNSUPPORTED: the own cell is an entry like any other); SG_INDIRECT
- * keeps its point-mass form. */
+ * keeps its point-mass form.
+ * sg_ss_table takes the flag too (log radial grid, force operators): each
+ * ring pair's operator uses these weights with the pair's aspect ratios
+ * h_a = H_a(r')/r', h_b = H_b(r)/r held across the hats, integrated within
+ * 32 cells of the singular point and taken as K + (second differences)/12
+ * beyond (remainder below 3e-6 of the entry).  Not with SG_POTENTIAL,
+ * SG_LINEAR_R or SG_SELF_CELL_EXCLUDE; sg_ss_grad_H refuses such discs
+ * (SG_ERR_UNSUPPORTED); sg_field_adjoint gives their dL/dSigma. */
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
  * fluid also receives the acceleration -sum_a grad Phi_{a,ind} of the frame
@@ -210,6 +217,9 @@ sg_status sg_kernel_table(const sg_grid *grid, const sg_fluids *fluids, uint32_t
  * inverse transform, about 1e-7 of |Phi|).  With constant H
  * (the case the paper derives) -grad Phi is the field; not combinable with
  * SG_INDIRECT.
+ *
+ * SG_SECOND_ORDER: the operators of the hat-weighted (second-order) field,
+ * see SG_SECOND_ORDER above; log radial grid and field operators only.
  *
  * Solve with sg_field_fft: a disc whose flags hold SG_SEMI_SPECTRAL (plus
  * the flags the table was built with) and whose table is an sg_ss_table

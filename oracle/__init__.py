@@ -99,6 +99,9 @@ def lib():
             _dp, _dp, _dp, ctypes.c_uint, _dp]
         L.sg_oracle_hat_weight.restype = None
         L.sg_oracle_hat_weight.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_int, _dp]
+        L.sg_oracle_field_ring_hat.restype = ctypes.c_int
+        L.sg_oracle_field_ring_hat.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_int, _dp, _dp, ctypes.c_int64, _i64p, _dp]
         L.sg_oracle_threads.restype = ctypes.c_int
         L.sg_oracle_threads.argtypes = []
         _lib = L
@@ -211,6 +214,23 @@ def hat_weight(P, Q, du, dphi, ha, hb, which=0):
     W = np.empty(2)
     lib().sg_oracle_hat_weight(int(P), int(Q), du, dphi, ha, hb, int(which), _ptr(W))
     return float(W[0]), float(W[1])
+
+
+def field_ring_hat(nr, nphi, rmin, rmax, H, sigma, targets=None):
+    """Second-order field for scale heights H [nf][nr] at the ring centres
+    (hat weights with each ring pair's aspect ratios): (g_r, g_phi), each
+    [nf][n_t], summed over source fluids."""
+    sigma = _d(sigma)
+    nf = sigma.shape[0]
+    H = _d(H).reshape(nf, nr)
+    t = _targets(targets)
+    nt = nr * nphi if t is None else t.size
+    out = np.empty((nf, 2, nt))
+    rc = lib().sg_oracle_field_ring_hat(nr, nphi, rmin, rmax, nf, _ptr(H), _ptr(sigma), nt, _iptr(t),
+                                        _ptr(out))
+    if rc:
+        raise RuntimeError(f"sg_oracle_field_ring_hat failed ({rc})")
+    return out[:, 0, :].copy(), out[:, 1, :].copy()
 
 
 def field_table(nr, nphi, rmin, rmax, h, sigma, targets=None, flags=0):

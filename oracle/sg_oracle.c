@@ -1087,6 +1087,72 @@ int sg_oracle_field_table(int nr, int nphi, double rmin, double rmax, int nf, co
 }
 
 /* ------------------------------------------------------------------------
+ * Second-order field with scale heights that depend on radius (the
+ * semi-spectral path's model, Sect. 5.2, with the weights of
+ * ORC_FLAG_SECOND_ORDER; reading): for target ring i and source ring i' the
+ * weights are W_c(i - i', q) of sg_oracle_hat_weight with the rings' aspect
+ * ratios h_a = H_a(r_i')/r_i', h_b = H_b(r_i)/r_i held across the hats, and
+ *   g_b(i, j) = - du dphi sum_a sum_i' sum_j' Sigma_a[i'][j'] W(i - i', j - j').
+ * H: [nf][nr] at the ring centres.  out: [b][c][nt] summed over sources.
+ * For H = h r it is the offset-table sum with ORC_FLAG_SECOND_ORDER (tests).
+ * ------------------------------------------------------------------------ */
+int sg_oracle_field_ring_hat(int nr, int nphi, double rmin, double rmax, int nf, const double *H,
+                             const double *sigma, int64_t nt, const int64_t *targets, double *out)
+{
+    if (nr < 1 || nphi < 4 || nf < 1 || nf > 4 || !(rmax > rmin) || !(rmin > 0)) return 1;
+    orc_grid g = orc_make_grid(nr, nphi, rmin, rmax);
+    orc_agl_init();
+    const int64_t npr = (int64_t)nf * nf * nr * nr;  /* (a, b, i, i') */
+    double *Wr = malloc(sizeof(double) * (size_t)npr * nphi);
+    double *Wp = malloc(sizeof(double) * (size_t)npr * nphi);
+    if (!Wr || !Wp) {
+        free(Wr);
+        free(Wp);
+        return 2;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < npr * nphi; ++e) {
+        const int q = (int)(e % nphi);
+        int64_t r = e / nphi;
+        const int ip = (int)(r % nr);
+        r /= nr;
+        const int i = (int)(r % nr);
+        r /= nr;
+        const int b = (int)(r % nf), a = (int)(r / nf);
+        const double ha = H[a * nr + ip] / orc_r(&g, ip), hb = H[b * nr + i] / orc_r(&g, i);
+        double W[2];
+        orc_hat_weight(i - ip, 2 * q <= nphi ? q : q - nphi, g.du, g.dphi, ha, hb, 0, W);
+        Wr[e] = W[0];
+        Wp[e] = W[1];
+    }
+    const int64_t N = (int64_t)nr * nphi;
+    const double scale = -g.du * g.dphi;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t k = targets ? targets[t] : t;
+        const int i = (int)(k / nphi), j = (int)(k % nphi);
+        for (int b = 0; b < nf; ++b) {
+            long double sr = 0.0L, sp = 0.0L;
+            for (int a = 0; a < nf; ++a)
+                for (int ip = 0; ip < nr; ++ip) {
+                    const int64_t e0 = ((((int64_t)a * nf + b) * nr + i) * nr + ip) * nphi;
+                    const double *row = sigma + a * N + (int64_t)ip * nphi;
+                    for (int jp = 0; jp < nphi; ++jp) {
+                        const int q = ((j - jp) % nphi + nphi) % nphi;
+                        sr += (long double)row[jp] * Wr[e0 + q];
+                        sp += (long double)row[jp] * Wp[e0 + q];
+                    }
+                }
+            out[((size_t)b * 2 + 0) * nt + t] = (double)(scale * sr);
+            out[((size_t)b * 2 + 1) * nt + t] = (double)(scale * sp);
+        }
+    }
+    free(Wr);
+    free(Wp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Adjoint with respect to Sigma (transposed offset-table sum):
  *   dL/dSigma_a[k] = - du dphi sum_b sum_c sum_i lam_{b,c}[i] T_c^{ab}(i - k)
  * lam: [b][c][N] (c = 0: dL/dg_r, 1: dL/dg_phi).  Output: [a][n_k].

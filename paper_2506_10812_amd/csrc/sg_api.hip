@@ -76,8 +76,10 @@ static bool ss_fluids_ok(const sg_grid *g, int nf)
 static bool ss_flags_ok(uint32_t flags)
 {
     if ((flags & SG_POTENTIAL) && (flags & SG_INDIRECT)) return false;
+    // second-order operators: the force on a log grid, own cell included
+    if ((flags & SG_SECOND_ORDER) && (flags & (SG_POTENTIAL | SG_LINEAR_R | SG_SELF_CELL_EXCLUDE))) return false;
     return (flags & ~(uint32_t)(SG_SELF_CELL_EXCLUDE | SG_INDIRECT | SG_SEMI_SPECTRAL | SG_SS_FULL |
-                                SG_POTENTIAL | SG_LINEAR_R)) == 0;
+                                SG_POTENTIAL | SG_LINEAR_R | SG_SECOND_ORDER)) == 0;
 }
 
 extern "C" {
@@ -398,7 +400,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
 
 static bool ss_grad_ok(const sg_disc *d)
 {
-    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL);
+    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL) && !(d->flags & SG_SECOND_ORDER);
 }
 
 // species discs also hold their group densities

@@ -47,12 +47,30 @@
 #include "sg_semispec.h"
 #include "sg_adjoint.h"
 #include "sg_table.h"
+#include "sg_hat.h"
 
 // ------------------------------------------------------------ table: rows
 struct SsRowArgs {
-    int nr, nrt, nf, excl, ind, pot, lin;
+    int nr, nrt, nf, excl, ind, pot, lin, second;
     double lnrmin, du, dphi, rmin, dr;  // du: log grid; rmin, dr: uniform radial grid
+    GLNodes gl;                         // second: the polar rules' nodes
 };
+
+// SG_SECOND_ORDER rows: the sample at (P, q) = (i - i', q) becomes the
+// hat-weighted weight W_c(P, q) of the FFT path's table with the row's
+// aspect ratios h_a = H_a(r_i')/r_i', h_b = H_b(r_i)/r_i held across the hat
+// (for H = h r this is the FFT path's table; otherwise the variation of h
+// across the hat is odd in s and enters at second order only).  Within
+// SG_SS_HAT_NEAR of the larger cell side from the singular point the weight
+// is integrated (sg_hat_weight1); beyond, it is the point value plus the
+// second moments of the hats, W = K + (D_X^2 K + D_phi^2 K)/12, with central
+// second differences over one cell (D_phi from the neighbouring samples of
+// the row, D_X from two extra samples at X +- du): the remainder is
+// O((cell/distance)^4), below 3e-6 of the entry at 32 cells.  The integrated
+// samples are computed by the whole group, one after the other (each
+// thread takes every T-th quadrature node; the owner of the sample adds the
+// parts in thread order), so that no single lane carries a polar rule.
+#define SG_SS_HAT_NEAR 32.0
 
 template <int N> struct SsRowShape {
     static constexpr int P = FftShape<N>::P, T = FftShape<N>::T;
@@ -62,7 +80,7 @@ template <int N> struct SsRowShape {
 
 // One group of T threads per row R = r0 + row of the (b, a, i', i) order
 // (i fastest).  out: [nrows][ncol] float2 (T_r, t_phi), m = 0 .. N/2.
-template <int N>
+template <int N, bool SO>
 __global__ void __launch_bounds__(SsRowShape<N>::WGS)
 k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows, float2 *out)
 {
@@ -71,6 +89,8 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     constexpr int NC = N / 2 + 1;
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     __shared__ double wq[FQuad<double>::TABLE];
+    __shared__ double2 qres[SO ? NC * G : 1];  // SO: the group's integrated samples
+    __shared__ int qmax_wg;                    // SO: last integrated sample of any group
     sg_fill_weights<double>(wq);
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const LdsPlane<double> pl{lds + W * g};
@@ -89,6 +109,80 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     const double ha = H[a * A.nr + ip] / rp, hb = H[b * A.nr + ic] / ri;
     const double X = A.lin ? log(ri / rp) : (double)(ic - ip) * A.du;
     __syncthreads();
+    if constexpr (SO) {
+        // 1'. hat-weighted samples (see SG_SS_HAT_NEAR): point values of K go
+        // to the plane for the neighbours' second differences, the weights
+        // stay in registers until every neighbour has been read
+        constexpr int J = (N / 2 + 1 + T - 1) / T;
+        double2 val[J];
+        unsigned taylor = 0u;
+        const int Pr = ic - ip;
+        const double rn = SG_SS_HAT_NEAR * fmax(A.du, A.dphi), xq = Pr * A.du;
+        // integrated samples: q <= qn (qn = -1: none); the predicate below is
+        // the one the sample loop uses
+        int qn = -1;
+        if (live && xq * xq < rn * rn)
+            while (qn < N / 2 && xq * xq + ((qn + 1) * A.dphi) * ((qn + 1) * A.dphi) < rn * rn) ++qn;
+        if (threadIdx.x == 0) qmax_wg = -1;
+        __syncthreads();
+        if (t == 0 && qn >= 0) atomicMax(&qmax_wg, qn);
+        __syncthreads();
+        const int qm = qmax_wg;  // uniform over the workgroup: every group meets the same barriers
+        for (int q = 0; q <= qm; ++q) {
+            double wr = 0.0, wp = 0.0;
+            if (q <= qn) sg_hat_weight_part(Pr, q, A.du, A.dphi, ha, hb, 0, A.gl, wq, t, T, wr, wp);
+            pl.st(t, make_double2(wr, wp));
+            __syncthreads();
+            if (q <= qn && t == 0) {
+                double sr = 0.0, sp = 0.0;
+                for (int k = 0; k < T; ++k) {
+                    const double2 v = pl.ld(k);
+                    sr += v.x;
+                    sp += v.y;
+                }
+                qres[g * NC + q] = make_double2(sr, sp);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int q = t + T * j;
+            val[j] = make_double2(0.0, 0.0);
+            if (q > N / 2) continue;
+            const double sh = sinpi((double)q / N), s2 = sinpi(2.0 * q / N);
+            double kr = 0.0, kp = 0.0;
+            if (q <= qn) {
+                val[j] = qres[g * NC + q];
+                if (Pr != 0 || q != 0) sg_conv_kernel64(X, sh, s2, ha, hb, 0, wq, kr, kp);
+            } else {
+                double k1r, k1p, k2r, k2p;
+                sg_conv_kernel64(X, sh, s2, ha, hb, 0, wq, kr, kp);
+                sg_conv_kernel64(X + A.du, sh, s2, ha, hb, 0, wq, k1r, k1p);
+                sg_conv_kernel64(X - A.du, sh, s2, ha, hb, 0, wq, k2r, k2p);
+                val[j] = make_double2(kr + (k1r - 2.0 * kr + k2r) / 12.0, kp + (k1p - 2.0 * kp + k2p) / 12.0);
+                taylor |= 1u << j;
+            }
+            pl.st(q, make_double2(kr, kp));
+            if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int q = t + T * j;
+            if (q > N / 2 || !((taylor >> j) & 1u)) continue;
+            const double2 k0 = pl.ld(q), kl = pl.ld((q + N - 1) & (N - 1)), kh = pl.ld((q + 1) & (N - 1));
+            val[j].x += (kl.x - 2.0 * k0.x + kh.x) / 12.0;
+            val[j].y += (kl.y - 2.0 * k0.y + kh.y) / 12.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int q = t + T * j;
+            if (q > N / 2) continue;
+            pl.st(q, val[j]);
+            if (q != 0 && q != N / 2) pl.st(N - q, make_double2(val[j].x, -val[j].y));
+        }
+    } else {
     // 1. samples q in [0, N/2], mirrored into the upper half
 #pragma unroll 1
     for (int q = t; q <= N / 2; q += T) {
@@ -106,6 +200,7 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
         }
         pl.st(q, make_double2(kr, kp));
         if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
+    }
     }
     __syncthreads();
     double2 z[P];
@@ -325,8 +420,12 @@ static void launch_ss_rows(const double *H, const double *self, const SsRowArgs 
                            float2 *out, hipStream_t s)
 {
     using S = SsRowShape<N>;
-    hipLaunchKernelGGL(k_ss_rows<N>, dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self, A, r0,
-                       nrows, out);
+    if (A.second)  // its own instance: the quadrature's registers stay out of the point-sampled rows
+        hipLaunchKernelGGL((k_ss_rows<N, true>), dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self,
+                           A, r0, nrows, out);
+    else
+        hipLaunchKernelGGL((k_ss_rows<N, false>), dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self,
+                           A, r0, nrows, out);
 }
 
 static bool dispatch_ss_rows(int nphi, const double *H, const double *self, const SsRowArgs &A, size_t r0,
@@ -361,6 +460,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     double *self = (double *)d_ws;
     float2 *chunk = (float2 *)((char *)d_ws + sg_align256(sizeof(double) * (size_t)nf * nf * nr));
     const bool excl = (flags & SG_SELF_CELL_EXCLUDE) != 0;
+    const bool second = (flags & SG_SECOND_ORDER) != 0;  // log grid, force operators
 
     hipLaunchKernelGGL(k_twiddles, dim3((nphi + 255) / 256), dim3(256), 0, s, (float2 *)nullptr, 0,
                        (float2 *)(tb + L.off_tw_phi), nphi);
@@ -374,7 +474,7 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
         SG_HIP(hipGetLastError());
     }
     const bool pot = (flags & SG_POTENTIAL) != 0;
-    if (!excl) {
+    if (!excl && !second) {  // second order: the own cell is a hat weight of the rows
         // one item per (pair, ring): the per-cell quadratures with one cell per ring
         GLNodes gl;
         sg_gl_nodes(gl);
@@ -407,6 +507,8 @@ sg_status sg_ss_table_build(const sg_grid *grid, int nf, const double *d_H, uint
     A.lin = lin ? 1 : 0;
     A.rmin = grid->r_min;
     A.dr = dr;
+    A.second = second ? 1 : 0;
+    sg_gl_nodes(A.gl);
     const size_t crows = ss_chunk_rows(L);
     for (size_t r0 = 0; r0 < L.rows; r0 += crows) {
         const int n = (int)std::min(crows, L.rows - r0);
@@ -875,6 +977,7 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
     A.dphi = dphi;
     A.rmin = grid->r_min;
     A.dr = (grid->r_max - grid->r_min) / nr;
+    A.second = 0;  // dL/dH of point-sampled operators only
     hipLaunchKernelGGL(k_ssg_zero, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf * nr);
     SG_HIP(hipGetLastError());
     if (!A.excl) {

@@ -126,7 +126,8 @@ def test_direct_validation(sg):
 def test_second_order_flag_combinations(sg):
     """SG_SECOND_ORDER changes the table's values, not its layout (with or
     without d/dh spectra); it cannot be combined with the own-cell switch,
-    and only the FFT path's table takes it."""
+    and the direct sums do not take it (the semi-spectral tables: see
+    test_semispectral_sizes_and_validation)."""
     g = sg.grid(16, 32, 0.2, 5.0)
     f = sg.fluids([0.05, 0.005])
     L = sg.lib()
@@ -145,7 +146,6 @@ def test_second_order_flag_combinations(sg):
         assert sg.field_fft_workspace_bytes([d]) == 0
     d = sg.Disc(g, f, sg.SECOND_ORDER, 0, 256, 512, 768, 1024)
     assert sg.field_fft_workspace_bytes([d]) == sg.field_fft_workspace_bytes([sg.Disc(g, f, 0, 0, 256, 512, 768, 1024)])
-    assert sg.ss_table_bytes(g, 1, sg.SECOND_ORDER) == 0
     need = sg.field_direct_workspace_bytes(g, 1, sg.F64, False)
     h = (ctypes.c_double * 1)(0.05)
     hp = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
@@ -216,6 +216,18 @@ def test_semispectral_sizes_and_validation(sg):
     assert G(ctypes.byref(d), 256, 512, 768, 4096, 8200, need, None) == sg.ERR_WORKSPACE
     d.flags = sg.SEMI_SPECTRAL | sg.POTENTIAL
     assert sg.ss_grad_H_workspace_bytes(d) == need
+    # second-order operators: solve and dL/dSigma, not dL/dH
+    d.flags = sg.SEMI_SPECTRAL | sg.SECOND_ORDER
+    assert sg.field_fft_workspace_bytes([d]) > 0
+    assert sg.ss_grad_H_workspace_bytes(d) == 0
+    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, need, None) == sg.ERR_UNSUPPORTED
+    for bad in (sg.POTENTIAL, sg.LINEAR_R, sg.SELF_CELL_EXCLUDE):
+        d.flags = sg.SEMI_SPECTRAL | sg.SECOND_ORDER | bad
+        assert sg.field_fft_workspace_bytes([d]) == 0
+    gs = sg.grid(16, 32, 20.0, 250.0)
+    assert sg.ss_table_bytes(gs, 1, sg.SECOND_ORDER) == sg.ss_table_bytes(gs, 1, 0) > 0
+    for bad in (sg.POTENTIAL, sg.LINEAR_R, sg.SELF_CELL_EXCLUDE):
+        assert sg.ss_table_bytes(gs, 1, sg.SECOND_ORDER | bad) == 0
     fft = sg.make_disc(sg.grid(16, 32, 0.2, 5.0), sg.fluids([0.05]), 0, 256, 512, 768, 1024)
     assert sg.ss_grad_H_workspace_bytes(fft) == 0
     assert G(ctypes.byref(fft), 256, 512, 768, 4096, 8192, 1 << 30, None) == sg.ERR_UNSUPPORTED

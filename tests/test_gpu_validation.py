@@ -176,6 +176,32 @@ def test_exponential_disc_reaches_the_paper_level_with_the_second_order_table(sg
         assert 0.9 < out[(h, sg.SECOND_ORDER)][0] / h < 1.1, out
 
 
+def test_exponential_disc_semispectral_second_order_reaches_the_paper_level(sg, T, W):
+    """The paper's own setting for its ~1e-4 plateau (Sect. 4.2): constant
+    H (q = 0) on the semi-spectral path, N_r = 1200.  With the second-order
+    operators the median error against Freeman falls to about 1e-4 (seen
+    8.3e-5, max 3.1e-4; H / r is below 4e-4 over the compared radii, so the
+    continuum floor is not what remains), where the point-sampled operators
+    give 2.9e-3."""
+    w = W.exponential(n_r=1200, n_phi=2048, h=0.01, q=0)
+    out = {}
+    for fl in (0, sg.SECOND_ORDER):
+        S = T.SemiSpectral(w["n_r"], w["n_phi"], w["r_min"], w["r_max"], 1, fl)
+        S.refresh(w["H"])
+        S.release_workspace()
+        S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+        S.run()
+        torch.cuda.synchronize()
+        med, mx, spread = errors(w, S.g_r[0].double().cpu().numpy())
+        print(f"  {'second-order' if fl else 'point'} operators: median {med:.2e} max {mx:.2e}", flush=True)
+        assert spread < 1e-5
+        out[fl] = (med, mx)
+        del S
+    med, mx = out[sg.SECOND_ORDER]
+    assert med < 1.5e-4 and mx < 5e-4, out
+    assert out[0][0] > 10 * med, out
+
+
 def test_appD_constant_h_error_grows_with_flaring(sg, T, W):
     """App. D: the full FFT method needs H/r constant; on a flaring disc its
     field differs from the semi-spectral reference computed with the true

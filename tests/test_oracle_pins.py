@@ -395,6 +395,22 @@ def test_hat_weight_h_derivatives_match_central_differences(du, dphi, ha, hb):
                 assert abs(got[c] - fd[c]) < 1e-7 * sc, (P, Q, which, c, got, fd)
 
 
+def test_ring_hat_sum_equals_table_mode_for_constant_aspect_ratio():
+    """The second-order sum with per-ring scale heights (ring-pair weights)
+    reduces to the offset-table sum with hat weights when H = h r: every
+    ring pair then has the same aspect ratios.  Two fluids, 5 x 8 (1e-13 of
+    max|g|)."""
+    nr, nphi, rmin, rmax = 5, 8, 0.5, 2.0
+    rng = np.random.default_rng(0)
+    sig = rng.uniform(0.5, 1.5, (2, nr, nphi))
+    h = [0.05, 0.01]
+    r = np.exp(np.log(rmin) + (np.arange(nr) + 0.5) * np.log(rmax / rmin) / nr)
+    a = O.field_ring_hat(nr, nphi, rmin, rmax, np.stack([h[0] * r, h[1] * r]), sig)
+    b = O.field_table(nr, nphi, rmin, rmax, h, sig, flags=O.SECOND_ORDER)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() < 1e-13 * np.abs(y).max()
+
+
 def _smooth_density(nr, nphi, urange, sig=0.7, kap=1.0):
     du = urange / nr
     u = (np.arange(nr) + 0.5) * du
