@@ -3,7 +3,9 @@ SG_SEMI_SPECTRAL): dL/dSigma = M^T lam with the stored radial operators
 transposed mode by mode.  Checked through the C ABI by
   * the transpose identity <lam, g(Sigma)> = <dL/dSigma, Sigma> (the forward
     is pinned to the oracle) on flaring discs, odd n_r, banded modes, the
-    folded indirect term and the potential operators (1e-5 relative);
+    folded indirect term, the potential operators and the second-order
+    operators (SG_SECOND_ORDER = 128, with and without the indirect term)
+    (1e-5 relative);
   * elementwise equality with the FFT path's adjoint when H = h r (both are
     the transpose of the same discrete operator; 1e-5 relative RMS)."""
 import numpy as np
@@ -43,7 +45,8 @@ def adjoint(sg, disc, lam_r, lam_p, nsig):
 
 
 @pytest.mark.parametrize("nr,nphi,nf,flags", [(37, 32, 2, 0), (21, 16, 1, 0), (256, 128, 2, 0),
-                                              (33, 32, 2, 4), (40, 64, 1, 32)])
+                                              (33, 32, 2, 4), (40, 64, 1, 32),
+                                              (37, 32, 2, 128), (256, 128, 2, 128 | 4)])
 def test_ss_adjoint_transpose_identity(sg, T, W, nr, nphi, nf, flags):
     print(f"semi-spectral adjoint {nr}x{nphi} nf={nf} flags={flags}", flush=True)
     w = W.flaring(seed=nr + 11, n_r=nr, n_phi=nphi, p=0.25, gap_w=15.0, n_fluids=nf)
