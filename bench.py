@@ -882,7 +882,50 @@ def extra_measurements(sg, T, W, dev):
     ms = e0.elapsed_time(e1) / 10
     pairs = (w["n_r"] * w["n_phi"]) ** 2
     res["direct_fp64_64x128"] = {"ms": round(ms, 4), "pairs_per_s": round(pairs / ms * 1e3, 1)}
+    res["exponential_disc"] = exponential_disc_accuracy(sg, T, W, dev)
     return res
+
+
+def exponential_disc_accuracy(sg, T, W, dev):
+    """Accuracy against Freeman's closed form (the exponential disc of
+    Sect. 4.2-4.3, radii y = r/(2 r_0) in [0.05, 2.5]), median and max of the
+    relative error of the azimuthally averaged g_r, with point-sampled and
+    second-order (SG_SECOND_ORDER) weights: the FFT path with H = 1e-4 r at
+    1024 x 2048, and the semi-spectral path with constant H = 0.01 at
+    1200 x 2048 (the paper's N_r), whose level the paper gives as ~1e-4."""
+    import numpy as np
+    import torch
+    from scipy import special
+
+    def err(w, gr):
+        r = np.exp(np.log(w["r_min"]) + (np.arange(w["n_r"]) + 0.5) * np.log(w["r_max"] / w["r_min"]) / w["n_r"])
+        y = r / (2 * w["r0"])
+        ref = -2 * np.pi * w["sigma0"] * y * (special.i0e(y) * special.k0e(y) - special.i1e(y) * special.k1e(y))
+        prof = gr.reshape(w["n_r"], w["n_phi"]).mean(axis=1)
+        sel = (y >= 0.05) & (y <= 2.5)
+        rel = np.abs(prof[sel] - ref[sel]) / np.abs(ref[sel])
+        return {"median": float(f"{np.median(rel):.3e}"), "max": float(f"{rel.max():.3e}")}
+
+    out = {}
+    w = W.exponential(n_r=1024, n_phi=2048, h=1e-4, q=1)
+    for name, fl in (("point", 0), ("second_order", sg.SECOND_ORDER)):
+        F = T.FFTField([dict(w, h=[1e-4])], flags=fl, device=dev)
+        F.set_sigma(0, w["sigma"])
+        F.run()
+        torch.cuda.synchronize()
+        out[f"fft_h1e-4_1024x2048_{name}"] = err(w, F.g_r[0][0].double().cpu().numpy())
+        del F
+    w = W.exponential(n_r=1200, n_phi=2048, h=0.01, q=0)
+    for name, fl in (("point", 0), ("second_order", sg.SECOND_ORDER)):
+        S = T.SemiSpectral(w["n_r"], w["n_phi"], w["r_min"], w["r_max"], 1, fl, device=dev)
+        S.refresh(w["H"])
+        S.release_workspace()
+        S.sigma.copy_(torch.tensor(w["sigma"], dtype=torch.float32))
+        S.run()
+        torch.cuda.synchronize()
+        out[f"semispectral_H0.01_1200x2048_{name}"] = err(w, S.g_r[0].double().cpu().numpy())
+        del S
+    return out
 
 
 if __name__ == "__main__":
