@@ -99,8 +99,9 @@ enum {
  * h_a = H_a(r')/r', h_b = H_b(r)/r held across the hats, integrated within
  * 32 cells of the singular point and taken as K + (second differences)/12
  * beyond (remainder below 3e-6 of the entry).  Not with SG_POTENTIAL,
- * SG_LINEAR_R or SG_SELF_CELL_EXCLUDE; sg_ss_grad_H refuses such discs
- * (SG_ERR_UNSUPPORTED); sg_field_adjoint gives their dL/dSigma. */
+ * SG_LINEAR_R or SG_SELF_CELL_EXCLUDE; sg_field_adjoint gives their
+ * dL/dSigma and sg_ss_grad_H their dL/dH (the h derivatives of the same
+ * weights). */
 
 /* SG_INDIRECT (Sect. 5.4 and the appendix "Indirect term"): every target
  * fluid also receives the acceleration -sum_a grad Phi_{a,ind} of the frame

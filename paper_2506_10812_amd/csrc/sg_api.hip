@@ -400,7 +400,7 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
 
 static bool ss_grad_ok(const sg_disc *d)
 {
-    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL) && !(d->flags & SG_SECOND_ORDER);
+    return d && check_disc(*d) == SG_OK && (d->flags & SG_SEMI_SPECTRAL);
 }
 
 // species discs also hold their group densities

@@ -771,7 +771,11 @@ k_ssg_phi(const float *lam_r, const float *lam_p, const float *sigma, const floa
 // One group of T threads per (b, a, i', i) row: for which = 1 (d/dh_a,
 // source) and 2 (d/dh_b, target) the derivative samples are transformed as
 // in k_ss_rows and contracted with lam~ and Sigma~ of the row's mode column.
-template <int N>
+// SO: the rows of second-order operators, whose samples are the h
+// derivatives of the hat weights (k_ss_rows<N, true>: integrated near the
+// singular point, point value plus second moments beyond; both are linear
+// in the kernel, so they apply to its derivatives sample by sample).
+template <int N, bool SO>
 __global__ void __launch_bounds__(SsRowShape<N>::WGS)
 k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, const float2 *st, size_t r0,
            int nrows, double *dldh)
@@ -782,6 +786,8 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double red[S::WGS];
+    __shared__ double2 qres[SO ? 2 * NC * G : 1];  // SO: the group's integrated samples, both derivatives
+    __shared__ int qmax_wg;
     sg_fill_weights<double>(wq);
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const LdsPlane<double> pl{lds + W * g};
@@ -808,6 +814,93 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
     // plane holds z = z_1 + i z_2, whose transform carries Z_1 (d/dh_a) in
     // its real part and Z_2 (d/dh_b) in its imaginary part.
     constexpr int Q = P / 2 + 1;
+    if constexpr (SO) {
+        // integrated samples, cooperatively (as in k_ss_rows<N, true>)
+        const int Pr = ic - ip;
+        const double rn = SG_SS_HAT_NEAR * fmax(A.du, A.dphi), xq = Pr * A.du;
+        int qn = -1;
+        if (live && xq * xq < rn * rn)
+            while (qn < N / 2 && xq * xq + ((qn + 1) * A.dphi) * ((qn + 1) * A.dphi) < rn * rn) ++qn;
+        if (threadIdx.x == 0) qmax_wg = -1;
+        __syncthreads();
+        if (t == 0 && qn >= 0) atomicMax(&qmax_wg, qn);
+        __syncthreads();
+        const int qm = qmax_wg;
+        for (int q = 0; q <= qm; ++q) {
+            for (int d = 1; d <= 2; ++d) {
+                double wr = 0.0, wp = 0.0;
+                if (q <= qn) sg_hat_weight_part(Pr, q, A.du, A.dphi, ha, hb, d, A.gl, wq, t, T, wr, wp);
+                pl.st(t, make_double2(wr, wp));
+                __syncthreads();
+                if (q <= qn && t == 0) {
+                    double sr = 0.0, sp = 0.0;
+                    for (int k = 0; k < T; ++k) {
+                        const double2 v = pl.ld(k);
+                        sr += v.x;
+                        sp += v.y;
+                    }
+                    qres[(g * 2 + (d - 1)) * NC + q] = make_double2(sr, sp);
+                }
+                __syncthreads();
+            }
+        }
+        // point values of the packed derivative rows (for the neighbours),
+        // and the second-order samples in registers: vq at q, vm at N - q
+        double2 vq[Q], vm[Q];
+        unsigned taylor = 0u;
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const int q = t + T * u;
+            vq[u] = make_double2(0.0, 0.0);
+            vm[u] = make_double2(0.0, 0.0);
+            if (q > N / 2) continue;
+            const double sh = sinpi((double)q / N), s2 = sinpi(2.0 * q / N);
+            double kr1 = 0.0, kp1 = 0.0, kr2 = 0.0, kp2 = 0.0;
+            if (Pr != 0 || q != 0) sg_conv_kernel64_dh(X, sh, s2, ha, hb, wq, kr1, kp1, kr2, kp2);
+            if (q <= qn) {
+                const double2 w1 = qres[(g * 2 + 0) * NC + q], w2 = qres[(g * 2 + 1) * NC + q];
+                vq[u] = make_double2(w1.x - w2.y, w1.y + w2.x);
+                vm[u] = make_double2(w1.x + w2.y, w2.x - w1.y);
+            } else {
+                // D_X^2 of the packed rows: samples at X +- du
+                double a1, b1, c1, e1, a2, b2, c2, e2;
+                sg_conv_kernel64_dh(X + A.du, sh, s2, ha, hb, wq, a1, b1, c1, e1);
+                sg_conv_kernel64_dh(X - A.du, sh, s2, ha, hb, wq, a2, b2, c2, e2);
+                const double dr1 = a1 - 2.0 * kr1 + a2, dp1 = b1 - 2.0 * kp1 + b2;
+                const double dr2 = c1 - 2.0 * kr2 + c2, dp2 = e1 - 2.0 * kp2 + e2;
+                vq[u] = make_double2(kr1 - kp2 + (dr1 - dp2) / 12.0, kp1 + kr2 + (dp1 + dr2) / 12.0);
+                vm[u] = make_double2(kr1 + kp2 + (dr1 + dp2) / 12.0, kr2 - kp1 + (dr2 - dp1) / 12.0);
+                taylor |= 1u << u;
+            }
+            pl.st(q, make_double2(kr1 - kp2, kp1 + kr2));
+            if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr1 + kp2, kr2 - kp1));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const int q = t + T * u;
+            if (q > N / 2 || !((taylor >> u) & 1u)) continue;
+            // D_phi^2 at q and at the mirror N - q (the plane holds the
+            // packed rows on the whole circle)
+            const double2 z0 = pl.ld(q), zl = pl.ld((q + N - 1) & (N - 1)), zh = pl.ld((q + 1) & (N - 1));
+            vq[u].x += (zl.x - 2.0 * z0.x + zh.x) / 12.0;
+            vq[u].y += (zl.y - 2.0 * z0.y + zh.y) / 12.0;
+            if (q != 0 && q != N / 2) {
+                const int qm2 = N - q;
+                const double2 y0 = pl.ld(qm2), yl = pl.ld(qm2 - 1), yh = pl.ld((qm2 + 1) & (N - 1));
+                vm[u].x += (yl.x - 2.0 * y0.x + yh.x) / 12.0;
+                vm[u].y += (yl.y - 2.0 * y0.y + yh.y) / 12.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const int q = t + T * u;
+            if (q > N / 2) continue;
+            pl.st(q, vq[u]);
+            if (q != 0 && q != N / 2) pl.st(N - q, vm[u]);
+        }
+    } else {
 #pragma unroll
     for (int u = 0; u < Q; ++u) {
         const int q = t + T * u;
@@ -835,6 +928,7 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
         }
         pl.st(q, make_double2(kr1 - kp2, kp1 + kr2));
         if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr1 + kp2, kr2 - kp1));
+    }
     }
     __syncthreads();
     double2 z[P];
@@ -935,8 +1029,12 @@ static void launch_ssg(const double *H, const double *dself, const SsRowArgs &A,
     const size_t chunk = (size_t)1 << 22;
     for (size_t r0 = 0; r0 < rows; r0 += chunk) {
         const int n = (int)std::min(chunk, rows - r0);
-        hipLaunchKernelGGL(k_ssg_rows<N>, dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself, A, lt, st, r0,
-                           n, dldh);
+        if (A.second)
+            hipLaunchKernelGGL((k_ssg_rows<N, true>), dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself,
+                               A, lt, st, r0, n, dldh);
+        else
+            hipLaunchKernelGGL((k_ssg_rows<N, false>), dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself,
+                               A, lt, st, r0, n, dldh);
     }
 }
 
@@ -977,10 +1075,11 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
     A.dphi = dphi;
     A.rmin = grid->r_min;
     A.dr = (grid->r_max - grid->r_min) / nr;
-    A.second = 0;  // dL/dH of point-sampled operators only
+    A.second = (flags & SG_SECOND_ORDER) ? 1 : 0;
+    sg_gl_nodes(A.gl);
     hipLaunchKernelGGL(k_ssg_zero, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf * nr);
     SG_HIP(hipGetLastError());
-    if (!A.excl) {
+    if (!A.excl && !A.second) {  // second order: the own cell is one of the integrated samples
         GLNodes gl;
         sg_gl_nodes(gl);
         for (int which = 1; which <= 2; ++which) {

@@ -216,11 +216,10 @@ def test_semispectral_sizes_and_validation(sg):
     assert G(ctypes.byref(d), 256, 512, 768, 4096, 8200, need, None) == sg.ERR_WORKSPACE
     d.flags = sg.SEMI_SPECTRAL | sg.POTENTIAL
     assert sg.ss_grad_H_workspace_bytes(d) == need
-    # second-order operators: solve and dL/dSigma, not dL/dH
+    # second-order operators: solve, dL/dSigma and dL/dH
     d.flags = sg.SEMI_SPECTRAL | sg.SECOND_ORDER
     assert sg.field_fft_workspace_bytes([d]) > 0
-    assert sg.ss_grad_H_workspace_bytes(d) == 0
-    assert G(ctypes.byref(d), 256, 512, 768, 4096, 8192, need, None) == sg.ERR_UNSUPPORTED
+    assert sg.ss_grad_H_workspace_bytes(d) == need
     for bad in (sg.POTENTIAL, sg.LINEAR_R, sg.SELF_CELL_EXCLUDE):
         d.flags = sg.SEMI_SPECTRAL | sg.SECOND_ORDER | bad
         assert sg.field_fft_workspace_bytes([d]) == 0

@@ -179,6 +179,67 @@ def test_ss_grad_chain_rule_constant_aspect(sg, T, W):
     assert np.allclose(got, ref, rtol=1e-5, atol=1e-6 * float(np.abs(ref).max()))
 
 
+def oracle_L_hat(w, H, flags, lr, lp):
+    """L = <lam, g(H)> with the oracle's second-order ring-pair sum (and its
+    point-mass indirect term with the ring H at every cell)."""
+    nf, nr, nphi = w["sigma"].shape
+    sig = w["sigma"].astype(np.float32).astype(np.float64)
+    gr, gp = O.field_ring_hat(nr, nphi, w["r_min"], w["r_max"], H, sig)
+    lr = lr.reshape(nf, -1).astype(np.float64)
+    lp = lp.reshape(nf, -1).astype(np.float64)
+    L = float(np.sum(lr * gr) + np.sum(lp * gp))
+    if flags & 4:
+        Hc = np.repeat(H[:, :, None], nphi, axis=2)
+        AB = O.indirect(nr, nphi, w["r_min"], w["r_max"], [0.0] * nf, sig, H=Hc)
+        ir, ip = O.indirect_field(nr, nphi, AB)
+        L += float(np.sum(lr * ir[None, :]) + np.sum(lp * ip[None, :]))
+    return L
+
+
+@pytest.mark.parametrize("nr,nphi,nf,flags,gap", [(5, 8, 1, 0, None), (4, 8, 2, 4, 3.0)])
+def test_ss_grad_second_order_matches_oracle_differences(sg, T, W, nr, nphi, nf, flags, gap):
+    """dL/dH(r) of second-order operators (the h derivatives of the hat
+    weights, integrated near the singular point) against central differences
+    of the oracle's second-order L, ring by ring (1e-6 of max|dL/dH|)."""
+    say(f"semi-spectral second-order dL/dH {nr}x{nphi} nf={nf} flags={flags} gap={gap}")
+    w = W.flaring(seed=nr * 7 + nphi, n_r=nr, n_phi=nphi, p=0.25, gap_w=gap, n_fluids=nf)
+    if flags & sg.INDIRECT:
+        phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+        w["sigma"] = w["sigma"] * (1 + 0.3 * np.cos(phi - 1.0))[None, None, :]
+    lr, lp = lams(w["sigma"].shape, nr + 5 * nf)
+    _, d = gpu_grad(sg, T, w, flags | sg.SECOND_ORDER, lr, lp)
+    H0 = np.array(w["H"], dtype=np.float64)
+    ref = np.zeros_like(H0)
+    for f in range(nf):
+        for i in range(nr):
+            e = 1e-4 * H0[f, i]
+            Hp, Hm = H0.copy(), H0.copy()
+            Hp[f, i] += e
+            Hm[f, i] -= e
+            ref[f, i] = (oracle_L_hat(w, Hp, flags, lr, lp) - oracle_L_hat(w, Hm, flags, lr, lp)) / (2 * e)
+    compare(d, ref)
+
+
+def test_ss_grad_second_order_chain_rule_constant_aspect(sg, T, W):
+    """H_f = h_f r with second-order operators: sum_i r_i dL/dH_f(r_i)
+    against the oracle's dL/dh_f of the second-order offset table (the FFT
+    path's model, which these operators equal for H = h r)."""
+    nr, nphi, nf = 12, 16, 2
+    say(f"semi-spectral second-order dL/dH chain rule {nr}x{nphi} nf={nf}")
+    w = W.flaring(seed=5, n_r=nr, n_phi=nphi, p=0.0, n_fluids=nf)
+    r = np.exp(np.log(w["r_min"]) + (np.arange(nr) + 0.5) * np.log(w["r_max"] / w["r_min"]) / nr)
+    h = w["H"][:, 0] / r[0]
+    w["H"] = h[:, None] * r[None, :]
+    lr, lp = lams(w["sigma"].shape, 9)
+    _, d = gpu_grad(sg, T, w, sg.SECOND_ORDER, lr, lp)
+    got = (d * r[None, :]).sum(axis=1)
+    sig = w["sigma"].astype(np.float32).astype(np.float64)
+    ref = O.adjoint_h(nr, nphi, w["r_min"], w["r_max"], h, sig, lr.astype(np.float64),
+                      lp.astype(np.float64), flags=O.SECOND_ORDER)
+    say(f"  dL/dh gpu {got}  oracle {ref}")
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-6 * float(np.abs(ref).max()))
+
+
 def test_ss_grad_directional_full_size(sg, T, W):
     """App. D size (1200 x 2048): <dL/dH, dH> against the central difference
     of the GPU forward along a smooth dH.  The forward and its table are
