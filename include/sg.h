@@ -473,8 +473,10 @@ sg_status sg_field_adjoint(const sg_disc *disc, const float *d_lam_r, const floa
  * (n_species > 0): the derivative at the group densities, summed in the
  * forward's order.  Discs without SG_SEMI_SPECTRAL return
  * SG_ERR_UNSUPPORTED.  d_ws: sg_ss_grad_H_workspace_bytes() bytes,
- * 256-byte aligned.  Asynchronous; the result is summed with device
- * atomics, so its last bits vary from call to call.
+ * 256-byte aligned (it holds two doubles per ring pair and group pair,
+ * 16 nf^2 n_r^2 bytes, besides the phi spectra).  Asynchronous; each ring
+ * pair's partial sums are stored and added up in a fixed order, so the
+ * result is the same, bit for bit, on every call.
  * --------------------------------------------------------------------- */
 size_t sg_ss_grad_H_workspace_bytes(const sg_disc *disc);
 sg_status sg_ss_grad_H(const sg_disc *disc, const double *d_H, const float *d_lam_r,

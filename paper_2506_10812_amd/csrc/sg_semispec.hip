@@ -778,7 +778,7 @@ k_ssg_phi(const float *lam_r, const float *lam_p, const float *sigma, const floa
 template <int N, bool SO>
 __global__ void __launch_bounds__(SsRowShape<N>::WGS)
 k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, const float2 *st, size_t r0,
-           int nrows, double *dldh)
+           int nrows, double *rowpart)
 {
     using S = SsRowShape<N>;
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
@@ -970,7 +970,8 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
         }
     }
     __syncthreads();
-    // per-group sums, then one atomic per row and derivative
+    // per-group sums, stored per row (part 0 belongs to dL/dh_a at the source
+    // ring, part 1 to dL/dh_b at the target ring); k_ssg_finish adds them up
     for (int d = 0; d < 2; ++d) {
         red[threadIdx.x] = part[d];
         __syncthreads();
@@ -978,39 +979,52 @@ k_ssg_rows(const double *H, const double *dself, SsRowArgs A, const float2 *lt, 
             if (t < o) red[threadIdx.x] += red[threadIdx.x + o];
             __syncthreads();
         }
-        if (t == 0 && live) atomicAdd(d == 0 ? &dldh[a * A.nr + ip] : &dldh[b * A.nr + ic], red[threadIdx.x]);
+        if (t == 0 && live) rowpart[2 * R + d] = red[threadIdx.x];
         __syncthreads();
     }
 }
 
-__global__ void k_ssg_finish(double *dldh, int nf, int nr, SsRowArgs A, double *dH)
+// dL/dH_f(r_k) = (1/r_k) dL/dh_f(r_k): the row partials that touch ring k of
+// group f, in a fixed order (so the result is the same on every call).
+// Row R = ((b nf + a) nr + i') nrt + i; ring k of group f is the source ring
+// of rows (b, f, k, i) and the target ring of rows (f, a, i', k).
+__global__ void __launch_bounds__(256) k_ssg_finish(const double *rowpart, SsRowArgs A, double *dH)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nf * nr) return;
-    const int i = k % nr;
-    const double r = A.lin ? A.rmin + (i + 0.5) * A.dr : exp(A.lnrmin + (i + 0.5) * A.du);
-    dH[k] = dldh[k] / r;
-}
-
-__global__ void k_ssg_zero(double *p, int n)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = 0.0;
+    __shared__ double red[256];
+    const int f = blockIdx.x / A.nr, k = blockIdx.x % A.nr;
+    const int n = A.nf * A.nr;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const int o = j / A.nr, x = j % A.nr;
+        s += rowpart[2 * ((((size_t)o * A.nf + f) * A.nr + k) * A.nrt + x)];
+        s += rowpart[2 * ((((size_t)f * A.nf + o) * A.nr + x) * A.nrt + k) + 1];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double r = A.lin ? A.rmin + (k + 0.5) * A.dr : exp(A.lnrmin + (k + 0.5) * A.du);
+        dH[blockIdx.x] = red[0] / r;
+    }
 }
 
 struct SsGradWs {
-    size_t lt, st, dself, dldh, total;
+    size_t lt, st, dself, rowpart, total;
 };
 
 static SsGradWs ssg_ws(int nr, int nphi, int nf)
 {
     const size_t fs = sg_blk_field_elems(nphi, nr);
+    const size_t rows = (size_t)nf * nf * nr * ((nr + 1) & ~1);
     SsGradWs w;
     w.lt = 0;
     w.st = sg_align256(sizeof(float2) * fs * 2 * nf);
     w.dself = w.st + sg_align256(sizeof(float2) * fs * nf);
-    w.dldh = w.dself + sg_align256(sizeof(double) * 2 * nf * nf * nr);
-    w.total = w.dldh + sg_align256(sizeof(double) * nf * nr);
+    w.rowpart = w.dself + sg_align256(sizeof(double) * 2 * nf * nf * nr);
+    w.total = w.rowpart + sg_align256(sizeof(double) * 2 * rows);
     return w;
 }
 
@@ -1019,7 +1033,7 @@ size_t sg_ss_grad_ws_bytes(int nr, int nphi, int nf) { return ssg_ws(nr, nphi, n
 template <int N>
 static void launch_ssg(const double *H, const double *dself, const SsRowArgs &A, const float *lam_r,
                        const float *lam_p, const float *sigma, const float2 *tw, float2 *lt, float2 *st,
-                       double *dldh, hipStream_t s)
+                       double *rowpart, hipStream_t s)
 {
     using S = SsRowShape<N>;
     const int nphi_jobs = A.nf * A.nr + A.nf * ((A.nr + 1) / 2);
@@ -1031,10 +1045,10 @@ static void launch_ssg(const double *H, const double *dself, const SsRowArgs &A,
         const int n = (int)std::min(chunk, rows - r0);
         if (A.second)
             hipLaunchKernelGGL((k_ssg_rows<N, true>), dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself,
-                               A, lt, st, r0, n, dldh);
+                               A, lt, st, r0, n, rowpart);
         else
             hipLaunchKernelGGL((k_ssg_rows<N, false>), dim3((n + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, dself,
-                               A, lt, st, r0, n, dldh);
+                               A, lt, st, r0, n, rowpart);
     }
 }
 
@@ -1060,7 +1074,7 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
     const SsGradWs W = ssg_ws(nr, nphi, nf);
     char *ws = (char *)d_ws;
     float2 *lt = (float2 *)(ws + W.lt), *st = (float2 *)(ws + W.st);
-    double *dself = (double *)(ws + W.dself), *dldh = (double *)(ws + W.dldh);
+    double *dself = (double *)(ws + W.dself), *rowpart = (double *)(ws + W.rowpart);
     const double dphi = 2.0 * SG_PI / nphi;
     SsRowArgs A;
     A.nr = nr;
@@ -1077,8 +1091,6 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
     A.dr = (grid->r_max - grid->r_min) / nr;
     A.second = (flags & SG_SECOND_ORDER) ? 1 : 0;
     sg_gl_nodes(A.gl);
-    hipLaunchKernelGGL(k_ssg_zero, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf * nr);
-    SG_HIP(hipGetLastError());
     if (!A.excl && !A.second) {  // second order: the own cell is one of the integrated samples
         GLNodes gl;
         sg_gl_nodes(gl);
@@ -1102,20 +1114,20 @@ sg_status sg_ss_grad_run(const sg_disc &d0, const double *d_H, const float *lam_
         }
     }
     switch (nphi) {
-    case 4: launch_ssg<4>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 8: launch_ssg<8>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 16: launch_ssg<16>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 32: launch_ssg<32>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 64: launch_ssg<64>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 128: launch_ssg<128>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 256: launch_ssg<256>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 512: launch_ssg<512>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 1024: launch_ssg<1024>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
-    case 2048: launch_ssg<2048>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, dldh, s); break;
+    case 4: launch_ssg<4>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 8: launch_ssg<8>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 16: launch_ssg<16>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 32: launch_ssg<32>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 64: launch_ssg<64>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 128: launch_ssg<128>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 256: launch_ssg<256>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 512: launch_ssg<512>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 1024: launch_ssg<1024>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
+    case 2048: launch_ssg<2048>(d_H, dself, A, lam_r, lam_p, d.sigma, tw, lt, st, rowpart, s); break;
     default: return SG_ERR_UNSUPPORTED;
     }
     SG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ssg_finish, dim3((nf * nr + 255) / 256), dim3(256), 0, s, dldh, nf, nr, A, dH);
+    hipLaunchKernelGGL(k_ssg_finish, dim3(nf * nr), dim3(256), 0, s, rowpart, A, dH);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

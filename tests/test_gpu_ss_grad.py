@@ -241,7 +241,8 @@ def test_ss_grad_second_order_chain_rule_constant_aspect(sg, T, W):
 
 
 def test_ss_grad_directional_full_size(sg, T, W):
-    """App. D size (1200 x 2048): <dL/dH, dH> against the central difference
+    """App. D size (1200 x 2048): a repeated call is identical bit for bit, and
+    <dL/dH, dH> agrees with the central difference
     of the GPU forward along a smooth dH.  The forward and its table are
     float, so the difference carries their rounding (a few 1e-4 of the
     derivative at eps = 1e-3, less at larger eps); eps = 4e-3 keeps the
@@ -251,6 +252,14 @@ def test_ss_grad_directional_full_size(sg, T, W):
     nr = w["n_r"]
     lr, lp = lams(w["sigma"].shape, 3)
     S, d = gpu_grad(sg, T, w, 0, lr, lp)
+    # the ring-pair partials are summed in a fixed order: a second call is identical
+    H = torch.tensor(w["H"], dtype=torch.float64, device="cuda")
+    d2 = torch.empty_like(H)
+    ws = torch.empty(sg.ss_grad_H_workspace_bytes(S.disc), dtype=torch.uint8, device="cuda")
+    sg.ss_grad_H(S.disc, H, torch.tensor(lr).cuda(), torch.tensor(lp).cuda(), d2, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(d2.cpu().numpy(), d)
+    del ws, d2
     u = np.linspace(0.0, 1.0, nr)
     dH = w["H"] * (0.5 + np.sin(7.0 * u))[None, :]
     lr_t, lp_t = torch.tensor(lr).cuda().double(), torch.tensor(lp).cuda().double()
@@ -270,7 +279,7 @@ def test_ss_grad_directional_full_size(sg, T, W):
 
 def test_ss_grad_species_equals_group_disc(sg, T, W):
     """A species disc's dL/dH is that of the disc of its group sums (formed in
-    the forward's order; only the atomics' summation order differs)."""
+    the forward's order)."""
     groups = (0, 1, 1, 0)
     nr, nphi = 11, 16
     say(f"semi-spectral dL/dH species {groups} {nr}x{nphi}")
