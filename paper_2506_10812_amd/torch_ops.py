@@ -11,8 +11,8 @@ from . import (F32, F64, INDIRECT, SECOND_ORDER, SELF_CELL_EXCLUDE, SEMI_SPECTRA
                field_adjoint_workspace_bytes, field_fft_tune, potential_direct,
                potential_direct_workspace_bytes, field_direct, field_direct_workspace_bytes, field_fft,
                field_fft_workspace_bytes, fluids, grid, kernel_table, kernel_table_bytes,
-               kernel_table_workspace_bytes, make_disc, ss_table, ss_table_bytes,
-               ss_table_workspace_bytes)
+               kernel_table_workspace_bytes, make_disc, ss_grad_H, ss_grad_H_workspace_bytes, ss_table,
+               ss_table_bytes, ss_table_workspace_bytes)
 
 
 def _dev(device):
@@ -246,3 +246,107 @@ class SGField(torch.autograd.Function):
         dsig, dh = slot.backward(sig, lam_r, lam_phi)
         # gradients in the dtype (and, for h, the device) of the inputs
         return dsig.to(s_dtype), dh.to(device=h_device, dtype=h_dtype), None, None, None, None, None, None
+
+
+class _SSSlot:
+    """Persistent device state of SGFieldSS for one (device, grid, fluid
+    count, flags): the semi-spectral disc (table, Sigma, outputs), the H its
+    table was built for, and the reverse-mode buffers.  The table is rebuilt
+    only when H changes, so a fit that holds H fixed solves at plan speed."""
+
+    def __init__(self, g, nf, flags, device):
+        self.nf, self.device = nf, device
+        self.S = SemiSpectral(g.n_r, g.n_phi, g.r_min, g.r_max, nf, flags, device)
+        self.H = None
+        self.adj = None
+
+    def _ensure(self, H):
+        if self.H is None or not torch.equal(self.H, H):
+            self.S.refresh(H)
+            self.H = H.clone()
+
+    def forward(self, sigma, H):
+        self._ensure(H)
+        self.S.sigma.copy_(sigma)
+        self.S.run()
+        return self.S.g_r.clone(), self.S.g_phi.clone()
+
+    def backward(self, sigma, H, lam_r, lam_phi, need_sigma, need_H):
+        S = self.S
+        self._ensure(H)
+        if self.adj is None:
+            self.adj = dict(
+                lam_r=torch.empty_like(S.g_r), lam_phi=torch.empty_like(S.g_phi),
+                dsig=torch.empty_like(S.g_r),
+                dH=torch.empty((self.nf, S.g.n_r), dtype=torch.float64, device=self.device),
+                ws=torch.empty(max(1, field_adjoint_workspace_bytes(S.disc),
+                                   ss_grad_H_workspace_bytes(S.disc)),
+                               dtype=torch.uint8, device=self.device))
+        A = self.adj
+        for name, lam in (("lam_r", lam_r), ("lam_phi", lam_phi)):
+            if lam is None:
+                A[name].zero_()
+            else:
+                A[name].copy_(lam)
+        S.sigma.copy_(sigma)
+        dsig = dH = None
+        if need_sigma:
+            field_adjoint(S.disc, A["lam_r"], A["lam_phi"], A["dsig"], None, A["ws"])
+            dsig = A["dsig"].clone()
+        if need_H:
+            ss_grad_H(S.disc, self.H, A["lam_r"], A["lam_phi"], A["dH"], A["ws"])
+            dH = A["dH"].clone()
+        return dsig, dH
+
+
+class _SSSlotCache(_SlotCache):
+    def get(self, g, nf, flags, device):
+        key = (str(device), g.n_r, g.n_phi, g.r_min, g.r_max, nf, flags)
+        slot = self.slots.pop(key, None)
+        if slot is None:
+            slot = _SSSlot(g, nf, flags, device)
+            if len(self.slots) >= self.size:
+                self.slots.pop(next(iter(self.slots)))
+        self.slots[key] = slot
+        return slot
+
+
+_ss_slots = _SSSlotCache(size=4)
+
+
+class SGFieldSS(torch.autograd.Function):
+    """g_r, g_phi = SGFieldSS.apply(sigma, H, n_r, n_phi, r_min, r_max[, indirect[, second_order]]).
+
+    The semi-spectral solve for scale heights that vary with radius (Sect. 5.2):
+    sigma: float32 CUDA tensor [F][n_r][n_phi]; H: tensor [F][n_r] of scale
+    heights at the ring centres (any float dtype).  Forward: sg_ss_table
+    (only when H changed since the last call on this slot) and sg_field_fft.
+    Backward: sg_field_adjoint for dL/dSigma and sg_ss_grad_H for dL/dH(r),
+    each run only when that input needs a gradient."""
+
+    @staticmethod
+    def forward(ctx, sigma, H, n_r, n_phi, r_min, r_max, indirect=False, second_order=False):
+        g = grid(n_r, n_phi, r_min, r_max)
+        nf = sigma.shape[0]
+        if tuple(H.shape) != (nf, n_r):
+            raise ValueError(f"H must have shape ({nf}, {n_r}), got {tuple(H.shape)}")
+        flags = (INDIRECT if indirect else 0) | (SECOND_ORDER if second_order else 0)
+        slot = _ss_slots.get(g, nf, flags, sigma.device)
+        sig = sigma.detach()
+        Hd = H.detach().to(device=sigma.device, dtype=torch.float64).contiguous()
+        gr, gp = slot.forward(sig, Hd)
+        ctx.save_for_backward(sig, Hd)
+        ctx.meta = (slot, H.device, H.dtype, sigma.dtype)
+        return gr, gp
+
+    @staticmethod
+    def backward(ctx, lam_r, lam_phi):
+        sig, Hd = ctx.saved_tensors
+        slot, H_device, H_dtype, s_dtype = ctx.meta
+        dsig, dH = slot.backward(sig, Hd, lam_r, lam_phi, ctx.needs_input_grad[0],
+                                 ctx.needs_input_grad[1])
+        if dsig is not None:
+            dsig = dsig.to(s_dtype)
+        if dH is not None:
+            dH = dH.to(device=H_device, dtype=H_dtype)
+        return dsig, dH, None, None, None, None, None, None
