@@ -33,7 +33,8 @@
  *   ownership  every device buffer is allocated and owned by the caller; the
  *              library reads and writes only the buffers passed in.  The only
  *              device memory the library owns is a per-signature cache of
- *              batch descriptors and instantiated HIP graphs (sg_field_fft;
+ *              batch plans: descriptors and, for batches with several launch
+ *              classes per pass, instantiated HIP graphs (sg_field_fft;
  *              sg_release() frees it) and the static scratch array of
  *              sg_field_direct_noalloc.
  *   streams    `stream` is a hipStream_t passed as void* (NULL = default
@@ -87,7 +88,7 @@ enum {
  * s, t in [-1, 1], in place of the point samples and the own-cell average:
  * the discrete field converges at second order in du, dphi to the field of
  * a smooth density, where the cell-centre sums converge at first order (the
- * ring kernel's 1/X and log|X| singularities).  The solve, its graph and its
+ * ring kernel's 1/X and log|X| singularities).  The solve, its plan and its
  * cost are unchanged; the table build integrates each entry (Gauss-Legendre,
  * polar rules at the singular point), and with SG_WITH_DH the d/dh spectra
  * integrate the kernel's h derivatives the same way, so sg_field_adjoint's
@@ -325,7 +326,7 @@ sg_status sg_field_fft_profile(const sg_disc *discs, int n_discs, void *d_ws, si
  * environment variable SG_TUNE_CACHE, if set, read on the first tuning call
  * and rewritten after each); later sg_field_fft calls of any batch with the
  * same class shapes use them.  Synchronous; allocates temporary device
- * memory; releases the cached graphs.  On return the outputs hold a complete
+ * memory; releases the cached plans.  On return the outputs hold a complete
  * sg_field_fft result.  results (may be NULL) receives up to `capacity`
  * entries, one per class in pass order; *n_results (may be NULL) the number
  * of classes.  Arguments as for sg_field_fft.
@@ -504,7 +505,7 @@ sg_status sg_eval_G0(const void *d_x, void *d_G, int64_t n, sg_dtype dtype, void
 sg_status sg_self_cell(const sg_grid *grid, const double *ha, const double *hb, int n, int which,
                        double *d_out, void *stream);
 
-/* Frees cached graphs and descriptor tables (synchronises the device). */
+/* Frees the cached plans: graphs and descriptor tables (synchronises the device). */
 void sg_release(void);
 
 /* Number of batch signatures (discs' shapes and buffer addresses, workspace,

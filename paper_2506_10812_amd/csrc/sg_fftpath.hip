@@ -1,5 +1,6 @@
 // sg_fftpath.hip -- sg_field_fft: batched three-pass log-polar FFT
-// convolution, one HIP graph per batch signature.
+// convolution, one cached plan per batch signature (run from a captured HIP
+// graph when a pass has several launch classes, else enqueued directly).
 #include <algorithm>
 #include <cstddef>
 #include <cmath>

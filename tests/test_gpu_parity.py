@@ -377,7 +377,7 @@ def batch64(sg, T, W):
 
 @pytest.mark.parametrize("part", range(4))
 def test_fft_batch64_equals_single_disc_runs_and_oracle(sg, T, W, batch64, part):
-    """The 64-disc batch in one graph: every disc equals its own single-disc
+    """The 64-disc batch in one call (a graph with parallel branches): every disc equals its own single-disc
     run bit for bit (same kernels, same arithmetic) and matches the oracle on
     512 seeded cells (1e-5 relative RMS per component); 16 discs per part."""
     discs, F = batch64
@@ -389,7 +389,7 @@ def test_fft_batch64_equals_single_disc_runs_and_oracle(sg, T, W, batch64, part)
 
 
 def test_fft_path_repeat_launches_are_identical(sg, T, W):
-    say("fft path graph replays")
+    say("fft path repeated launches")
     w = W.bifluid_fft(seed=31, n_r=64, n_phi=128)
     F = _fft_run(T, W, [w])
     ref_r = F.g_r[0].clone()
@@ -401,7 +401,7 @@ def test_fft_path_repeat_launches_are_identical(sg, T, W):
         assert torch.equal(F.g_r[0], ref_r)
 
 
-def test_fft_path_graph_cache_is_bounded(sg, T, W):
+def test_fft_path_plan_cache_is_bounded(sg, T, W):
     say("fft path: 300 signatures (fresh outputs each call), cache keeps 256")
     w = W.bifluid_fft(seed=33, n_r=16, n_phi=32)
     g = sg.grid(w["n_r"], w["n_phi"], w["r_min"], w["r_max"])

@@ -187,7 +187,7 @@ def test_semispectral_indirect(sg, T, W, nr, nphi, nf):
 
 def test_semispectral_refresh_in_place(sg, T, W):
     """A second sg_ss_table into the same table (new H, same buffers: the
-    cached graph is reused) gives the field of the new H."""
+    cached plan is reused) gives the field of the new H."""
     say("semi-spectral refresh of H in place")
     w1 = W.flaring(seed=5, n_r=40, n_phi=32, p=0.0, n_fluids=2)
     w2 = W.flaring(seed=5, n_r=40, n_phi=32, p=0.5, gap_w=20.0, n_fluids=2)
