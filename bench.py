@@ -591,7 +591,26 @@ def main():
         flush.fill_(1.0)
         cp.append(sg.field_fft_profile(F.discs, F.ws, 1, stream=stream))
     ms_pass = [float(v) for v in np.mean(np.array(cp), axis=0)]
-    del flush
+    # the same after a clean eviction (reported in extra only): the rewrite is
+    # followed by a read of a second 512 MiB buffer, which evicts the
+    # rewritten lines, so the step starts with nothing of its own cached and
+    # no dirty lines of the flush left to write back
+    flush2 = torch.ones(FLUSH_FLOATS, dtype=torch.float32, device=dev)
+    cc, cs = [], []
+    for _ in range(reps_c):
+        flush.fill_(1.0)
+        flush2.sum()
+        cc.append(sg.field_fft_profile(F.discs, F.ws, 1, stream=stream))
+        flush.fill_(1.0)
+        flush2.sum()
+        e0.record(stream)
+        F.run()
+        e1.record(stream)
+        e1.synchronize()
+        cs.append(e0.elapsed_time(e1))
+    ms_pass_clean = [float(v) for v in np.mean(np.array(cc), axis=0)]
+    ms_step_clean = float(np.mean(cs))
+    del flush, flush2
     # warm per-pass durations (each pass's launches back to back)
     reps = max(10, min(args.steps, 200))
     ms_pass_warm = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
@@ -649,6 +668,8 @@ def main():
              "warm_cells_per_s": round(cells / (warm_ms * 1e-3), 1),
              "warm_path_hbm_frac": round(pb["path"] / (warm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "ms_per_pass_cold": [round(v, 5) for v in ms_pass],
+             "cold_clean_ms_per_step": round(ms_step_clean, 5),
+             "ms_per_pass_cold_clean": [round(v, 5) for v in ms_pass_clean],
              "ms_per_pass_warm": [round(v, 5) for v in ms_pass_warm],
              "ms_per_pass_warm_untuned": [round(v, 5) for v in ms_untuned],
              "pass_hbm_frac_cold": [round(pb[k] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
