@@ -73,6 +73,10 @@ PROFILE_COMMANDS = {
                "python3 {repo}/bench.py --batch --steps 5 --warmup 2 --no-tune",
     "ss_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/ss_kt -o run -- "
              "python3 {repo}/bench.py --semispectral",
+    "ss_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/ss_fetch -o run -- "
+                "python3 {repo}/bench.py --semispectral",
+    "ss_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/ss_write -o run -- "
+                "python3 {repo}/bench.py --semispectral",
     "dir_kt": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/dir_kt -o run -- "
               "python3 {repo}/bench.py --direct",
     "dir_valu": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 "
@@ -301,6 +305,8 @@ def summarize_rocprof(out):
                          f"{float(r['Percentage']):.2f} |")
         with open(os.path.join(prof, "kernels_semispectral_flaring_1200x2048.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
+    if os.path.isdir(os.path.join(out, "ss_fetch")) and os.path.isdir(os.path.join(out, "ss_write")):
+        summarize_ss_traffic(out, prof, cmd, f_scale, w_scale)
     if os.path.isdir(os.path.join(out, "dir_kt")) and os.path.isdir(os.path.join(out, "dir_valu")):
         summarize_direct(out, prof, cmd)
     print(json.dumps(tr))
@@ -370,6 +376,43 @@ def summarize_batch_traffic(out, prof, cmd, f_scale, w_scale, cf, cw):
              f"all for {cells} cells = {(rd + wr) / cells:.1f} B/cell, against {alg / 1e6:.1f} MB "
              f"algorithmic ({alg / cells:.1f} B/cell): {(rd + wr) / alg:.2f}x."]
     with open(os.path.join(prof, "traffic_batch64.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_ss_traffic(out, prof, cmd, f_scale, w_scale):
+    """profiles/traffic_semispectral_flaring_1200x2048.md: HBM bytes per
+    dispatch of the semi-spectral middle pass, per launch variant (the tuner
+    runs several; each reads the stored operators once) against the
+    algorithmic bytes."""
+    per = {}
+    for key, counter, scale in (("ss_fetch", "FETCH_SIZE", f_scale), ("ss_write", "WRITE_SIZE", w_scale)):
+        for r in _csv_rows(os.path.join(out, key), "_counter_collection.csv"):
+            n = _kname(r)
+            if n.startswith("k_ss_pass") and r["Counter_Name"] == counter:
+                per.setdefault(n, {}).setdefault(counter, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
+    meta = _last_json(os.path.join(out, "ss_fetch.out"))
+    if not per or not meta or "middle_pass" not in meta:
+        return
+    mp = meta["middle_pass"]
+    ar, aw = mp["algorithmic_read"], mp["algorithmic_write"]
+    lines = ["# HBM traffic of the semi-spectral middle pass, App. D flaring gas disc 1200x2048", "",
+             "Commands (from /tmp, TMPDIR=/tmp; `<repo>` = repository root, `<out>` = output root):", "",
+             "    " + cmd["ss_fetch"], "    " + cmd["ss_write"], "",
+             f"Per dispatch of `k_ss_pass`, by launch variant (the run tunes the middle pass, so "
+             f"several variants run); counters scaled by the copy calibration of "
+             f"traffic_passes_bifluid_1024x2048.md (FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x "
+             f"{w_scale:.4f}).  Algorithmic bytes: {ar / 1e6:.1f} MB read (the stored operators, "
+             f"{meta['table_bytes'] / 1e6:.1f} MB, and Sigma~) and {aw / 1e6:.1f} MB written (g^_r, g^_phi).",
+             "", "| Variant | Dispatches | Read (MB) | Read / alg. | Written (MB) | Written / alg. |",
+             "|---|---|---|---|---|---|"]
+    for n in sorted(per):
+        f, w = per[n].get("FETCH_SIZE"), per[n].get("WRITE_SIZE")
+        if not f or not w:
+            continue
+        rd, wr = sum(f) / len(f), sum(w) / len(w)
+        lines.append(f"| `{n}` | {len(f)} / {len(w)} | {rd / 1e6:.1f} | {rd / ar:.3f} | {wr / 1e6:.1f} | "
+                     f"{wr / aw:.3f} |")
+    with open(os.path.join(prof, "traffic_semispectral_flaring_1200x2048.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 
@@ -761,6 +804,7 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     grad_ms = rev_ms(lambda: sg.ss_grad_H(S.disc, Hd, lam_r, lam_p, dH, gws), 3)
     del aws, gws
     mid = ss_bytes(sg, S.g, nf)
+    mid_write = 16 * (nphi // 2 + 1) * nf * nr  # g^_r, g^_phi
     ach = mid / (ms_pass[1] * 1e-3) / 1e9
     out = {"workload": f"App. D flaring gas disc {nr}x{nphi}, r in [20,250], p=0.25",
            "table_bytes": sg.ss_table_bytes(S.g, nf), "table_build_ms": round(build_ms, 2),
@@ -769,7 +813,8 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
            "ms_per_pass_untuned": [round(v, 4) for v in ms_untuned],
            "middle_pass_shape": [r["groups_per_wg"] for r in tuned if r["pass"] == 2],
            "adjoint_dsigma_ms": round(adj_ms, 4), "grad_H_ms": round(grad_ms, 2),
-           "middle_pass": {"bound": "hbm", "algorithmic_bytes": mid, "achieved": round(ach, 1),
+           "middle_pass": {"bound": "hbm", "algorithmic_bytes": mid, "algorithmic_read": mid - mid_write,
+                           "algorithmic_write": mid_write, "achieved": round(ach, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
     del S
     torch.cuda.empty_cache()
