@@ -20,6 +20,8 @@ Prints one JSON line.
                                         256x512, one JSON line; for their VALU counters)
   python bench.py --batch              (only the 64-disc batch: warm-up runs, then cold
                                         runs after a cache flush; for its traffic counters)
+  python bench.py --oracle-rates       (CPU only: the oracle's cells/s on the other
+                                        workloads, full fields or seeded samples)
   python bench.py --summarize-rocprof DIR
         (CPU only) turns the rocprofv3 CSV output of PROFILE_COMMANDS, run
         with DIR as their output root, into the text summaries in profiles/
@@ -520,6 +522,47 @@ def direct_measurement(sg, T, W, dev):
     return out
 
 
+def oracle_rates():
+    """The oracle's own speed on this host (CPU only; offset-table FP64 sum,
+    OpenMP over target cells): the full field of the 64 x 128 FP64 workload,
+    of the 512 x 1024 single-fluid workload and of the 256 x 512 two-fluid
+    adjoint workload, and 512 seeded cells of every disc of the 64-disc batch.
+    Each call builds its disc's tables first; that build is timed alone (a
+    one-cell call) and kept out of the per-cell rate."""
+    import numpy as np
+    import oracle as O
+    from paper_2506_10812_amd import workloads as W
+
+    def timed(w, h, targets=None):
+        nr, nphi = w["n_r"], w["n_phi"]
+        args = (nr, nphi, w["r_min"], w["r_max"], h, np.asarray(w["sigma"], dtype=np.float64))
+        t0 = time.perf_counter()
+        O.field_table(*args, targets=np.zeros(1, dtype=np.int64))
+        build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.field_table(*args, targets=targets)
+        total = time.perf_counter() - t0
+        n = nr * nphi if targets is None else len(targets)
+        return build, max(total - build, 1e-9), n
+
+    out = {"threads": O.threads(), "host_cpus": os.cpu_count(), "kind": "oracle, offset-table FP64"}
+    for name, w in (("fp64_64x128_full", W.direct_fp64()), ("single_fluid_512x1024_full", W.single_fft()),
+                    ("bifluid_256x512_full", W.adjoint())):
+        print(f"bench: oracle rate, {name}", file=sys.stderr, flush=True)
+        b, s, n = timed(w, w["h"])
+        out[name] = {"cells": n, "table_build_s": round(b, 3), "sum_s": round(s, 3),
+                     "cells_per_s": round(n / s, 1)}
+    print("bench: oracle rate, 64-disc batch (512 cells per disc)", file=sys.stderr, flush=True)
+    bs = ss = 0.0
+    nt = 0
+    for i, w in enumerate(W.batch64()):
+        b, s, n = timed(w, w["h"], W.sample_cells(w["n_r"], w["n_phi"], 512, seed=100 + i))
+        bs, ss, nt = bs + b, ss + s, nt + n
+    out["batch64_sampled"] = {"cells": nt, "table_build_s": round(bs, 3), "sum_s": round(ss, 3),
+                              "cells_per_s": round(nt / ss, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,7 +576,11 @@ def main():
     ap.add_argument("--semispectral", action="store_true")
     ap.add_argument("--direct", action="store_true")
     ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--oracle-rates", action="store_true")
     args = ap.parse_args()
+    if args.oracle_rates:
+        print(json.dumps(oracle_rates()))
+        return
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
         return
