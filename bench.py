@@ -701,6 +701,20 @@ def main():
     ms_pass_clean = [float(v) for v in np.mean(np.array(cc), axis=0)]
     ms_step_clean = float(np.mean(cs))
     del flush, flush2
+    # achievable HBM bandwidth for comparison with the 8 TB/s spec: a 1 GiB
+    # device-to-device copy (4x the Infinity Cache), read plus written bytes
+    # over its time, mean of 10 copies between HIP events
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
     # warm per-pass durations (each pass's launches back to back)
     reps = max(10, min(args.steps, 200))
     ms_pass_warm = sg.field_fft_profile(F.discs, F.ws, reps, stream=stream)
@@ -759,6 +773,7 @@ def main():
              "warm_path_hbm_frac": round(pb["path"] / (warm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "ms_per_pass_cold": [round(v, 5) for v in ms_pass],
              "cold_clean_ms_per_step": round(ms_step_clean, 5),
+             "hbm_copy_1gib_gbs": round(copy_gbs, 1),
              "ms_per_pass_cold_clean": [round(v, 5) for v in ms_pass_clean],
              "ms_per_pass_warm": [round(v, 5) for v in ms_pass_warm],
              "ms_per_pass_warm_untuned": [round(v, 5) for v in ms_untuned],
