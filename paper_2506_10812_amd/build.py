@@ -19,9 +19,26 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unused-command-line-argument"]
 
 
+GEN = os.path.join(OBJ, "include")  # generated headers
+
+
+def _generate() -> None:
+    """Host step: build and run gen_cheb64.cpp, which writes sg_cheb64.h (the
+    Chebyshev coefficients of the double mid-range F(x) branch)."""
+    os.makedirs(GEN, exist_ok=True)
+    exe = os.path.join(OBJ, "gen_cheb64")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", os.path.join(CSRC, "gen_cheb64.cpp"), "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise RuntimeError("gen_cheb64 failed")
+    with open(os.path.join(GEN, "sg_cheb64.h"), "w") as fh:
+        fh.write(r.stdout)
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, "-I", GEN, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -31,6 +48,7 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    _generate()
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -6,44 +6,56 @@
 //     K_ab(s) = pi^{-1/2} H_ab^{-2} (d/8) F(d^2/8),  d = s/H_ab.
 // Evaluation never forms e^x K1(x) and e^x K0(x) separately at large x (their
 // difference cancels and e^x overflows, the NaN problem noted in Sect. 5.3):
-//   x < 2   power series of I0, I1, K0, K1 (Abramowitz & Stegun 9.6.10,
-//           9.6.11), F = e^x (K1 - K0) (float: x < 1, where the two
-//           cancellations inside K0 and K1 - K0 cost at most a few ulps);
+//   x < 1/2 (float: x < 1)  power series of I0, I1, K0, K1 (Abramowitz &
+//           Stegun 9.6.10, 9.6.11), F = e^x (K1 - K0), where the two
+//           cancellations inside K0 and K1 - K0 cost at most a few ulps (in
+//           double they grow to 3e-14 just below x = 2, hence the Chebyshev
+//           branch above 1/2);
 //   x >= 2  F = sqrt(2) x^{-3/2} J(x)   (float: x >= 1),  J(x) = int_0^inf v^2 e^{-v^2}
 //           (1 + v^2/(2x))^{-1/2} dv, obtained from the integral
 //           representation K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt by
 //           the substitution sinh(t/2) = v / sqrt(2x).  The integrand is even
 //           and analytic for |Im v| < sqrt(2x), so the trapezoidal rule on a
 //           fixed grid converges geometrically, its error ~ exp(-2 pi
-//           sqrt(2x) / step): double uses step 1/4 and 26 nodes (error
-//           < 1e-20 for x >= 2), float step 1/2 and 9 nodes (2e-8 at x = 1,
-//           below a float ulp; the tail beyond v = 4.5 is e^{-20}).
-//   x >= 32 (float), x >= 40 (double) the asymptotic series J = (sqrt(pi)/4)
+//           sqrt(2x) / step): float uses step 1/2 and 9 nodes (2e-8 at x = 1,
+//           below a float ulp; the tail beyond v = 4.5 is e^{-20}).  Double
+//           (step 1/4, 26 nodes, error < 1e-20) keeps this rule only for the
+//           potential's G0 (below);
+//   1/2 <= x < 32 (double) Chebyshev series of F and F' on the dyadic
+//           intervals [1/2, 1), [1, 2), ..., [16, 32), 27 terms each, their
+//           coefficients computed at build time in long double from the same
+//           integral representation (gen_cheb64.cpp; sg_cheb64.h): within
+//           4e-16 of F and F' over the range, at a tenth of the trapezoid's
+//           instructions (no square roots);
+//   x >= 32 the asymptotic series J = (sqrt(pi)/4)
 //           sum_n c_n x^-n, c_0 = 1, c_n = -c_{n-1} (4 n^2 - 1)/(8 n)
 //           (term-by-term integration of the binomial series; its first three
 //           terms are the expansion printed in Sect. 5.3), truncated after c_5
 //           (float) or c_16 (double).  (1 + t)^{-1/2} is completely monotone, so
 //           the binomial remainder alternates and is bounded by the first
-//           omitted term, and so is J's: |c_17| 40^-17 = 1e-18 for F, and for F'
+//           omitted term, and so is J's: |c_17| 32^-17 = 1.3e-18 for F, and for F'
 //           (series differentiated term by term, two such pieces of one sign)
-//           |c_17| (17 + 3/2) / (3/2) 40^-17 = 1.3e-17 of its leading term.
+//           |c_17| (17 + 3/2) / (3/2) 32^-17 = 1.7e-17 of its leading term.
 // The trapezoidal weights e^{-v_k^2} (and, for double, a copy of the
-// asymptotic coefficients for the rolled series) are computed once per
-// workgroup into LDS by sg_fill_weights().
+// asymptotic coefficients for the rolled series and the Chebyshev
+// coefficients) are copied once per workgroup into LDS by sg_fill_weights().
 #pragma once
 #include "sg_internal.h"
+#include "sg_cheb64.h"
 
 #define SG_EULER_GAMMA 0.57721566490153286061
 
 // Table of TABLE entries: w[k-1] = exp(-(k STEP)^2), k = 1..NODES; for double
-// then c_n (n = 0..ASYM), -(n + 3/2) c_n, and the G0 coefficients a_n.
+// then c_n (n = 0..ASYM), -(n + 3/2) c_n, the G0 coefficients a_n, and the
+// Chebyshev coefficients of F and of F' (SG_CHEB_NI intervals of SG_CHEB_M).
 template <typename R> struct FQuad;
 template <> struct FQuad<double> {
     static constexpr int NODES = 26;
     static constexpr double STEP = 0.25;
     static constexpr int ASYM = 16;
     static constexpr int C = NODES, D = C + ASYM + 1, A = D + ASYM + 1;
-    static constexpr int TABLE = A + ASYM + 1;
+    static constexpr int CH = A + ASYM + 1, CHD = CH + SG_CHEB_NI * SG_CHEB_M;
+    static constexpr int TABLE = CHD + SG_CHEB_NI * SG_CHEB_M;
 };
 template <> struct FQuad<float> {
     static constexpr int NODES = 9;
@@ -89,6 +101,8 @@ template <typename R> __device__ inline R sg_weight_entry(int k)
     }
     if constexpr (sizeof(R) == 8) {
         using Q = FQuad<double>;
+        if (k >= Q::CHD) return sg_cheb_df[k - Q::CHD];
+        if (k >= Q::CH) return sg_cheb_f[k - Q::CH];
         constexpr AsymCoef64 C;
         return k >= Q::A ? C.a[k - Q::A] : k >= Q::D ? C.d[k - Q::D] : C.c[k - Q::C];
     }
@@ -168,7 +182,7 @@ struct AsymCoef {
     }
 };
 
-// Asymptotic branch (double), x >= 40: F and F' = (sqrt(2 pi)/4) sum_n c_n
+// Asymptotic branch (double), x >= 32: F and F' = (sqrt(2 pi)/4) sum_n c_n
 // (-n - 3/2) x^{-n-5/2}.  ROLLED: a rolled Horner loop over the LDS copy of
 // the coefficients.  Unrolled with literal coefficients, the compiler keeps
 // them in registers across the caller's loop, which drops the direct sums
@@ -215,11 +229,41 @@ __device__ inline float sg_F_asym(float x)
     return float(SG_SQRT2) * rx * u * J;
 }
 
-// Full-range evaluators.  The double asymptotic branch is taken only when
-// every active lane of the wave has x >= 40 (a wave that straddles 40 runs
-// the trapezoid, which holds for every x >= 2, instead of paying for both).
-// Below that, the series and the trapezoid each run only when some lane of
-// the wave needs them, every lane keeping its own branch's value.
+// Mid-range branch (double), 1/2 <= x < 32: x = m 2^e with m in [1/2, 1) lies
+// in interval k = e at t = 4 m - 3 in [-1, 1); the series of F (and F')
+// are summed by Clenshaw's recurrence from the LDS copy of the coefficients.
+// Lanes outside the range (whose result is discarded) are clamped to an
+// interval so that every address stays in the table.
+__device__ inline void sg_F_cheb64(double x, const double *w, double &F, double *dF)
+{
+    using Q = FQuad<double>;
+    int e;
+    const double m = frexp(x, &e);
+    const int k = min(max(e, 0), SG_CHEB_NI - 1);
+    const double t = 4.0 * m - 3.0, t2 = 2.0 * t;
+    const double *cf = w + Q::CH + k * SG_CHEB_M;
+    const double *cd = w + Q::CHD + k * SG_CHEB_M;
+    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll 3
+    for (int j = SG_CHEB_M - 1; j > 0; --j) {
+        const double b0 = fma(t2, b1, cf[j] - b2);
+        b2 = b1;
+        b1 = b0;
+        if (dF) {
+            const double d0 = fma(t2, d1, cd[j] - d2);
+            d2 = d1;
+            d1 = d0;
+        }
+    }
+    F = fma(t, b1, cf[0] - b2);
+    if (dF) *dF = fma(t, d1, cd[0] - d2);
+}
+
+// Full-range evaluators.  The double asymptotic branch alone runs when every
+// active lane of the wave has x >= 32.  Otherwise the series (x < 1/2), the
+// double Chebyshev branch (1/2 <= x < 32) or the float trapezoid (x >= 1), and
+// the double asymptotic branch (x >= 32) each run only when some lane of the
+// wave needs them, every lane keeping its own branch's value.
 // SG_NO_SPECULATE, an empty asm statement that emits no instruction, keeps
 // the compiler from if-converting such wave-uniform branches into
 // straight-line code that evaluates every branch for every lane.
@@ -228,26 +272,34 @@ __device__ inline float sg_F_asym(float x)
 template <bool ROLLED>
 __device__ inline void sg_F64_any(double x, const double *w, double &F, double *dF)
 {
-    if (__all(x >= 40.0)) {
+    if (__all(x >= 32.0)) {
         sg_F_asym64<ROLLED>(x, w, F, dF);
         return;
     }
-    const bool ser = x < 2.0;
+    const bool ser = x < 0.5, asy = x >= 32.0, mid = !ser && !asy;
     double t, td = 0.0;
     F = 0.0;
     if (dF) *dF = 0.0;
     if (__any(ser)) {
         SG_NO_SPECULATE();
-        sg_F_series<double, 14>(x, t, dF ? &td : nullptr);
+        sg_F_series<double, 10>(x, t, dF ? &td : nullptr);  // y = x^2/4 < 1/16: y^10/(10!)^2 < 1e-25
         if (ser) {
             F = t;
             if (dF) *dF = td;
         }
     }
-    if (__any(!ser)) {
+    if (__any(mid)) {
         SG_NO_SPECULATE();
-        sg_F_quad<double>(x, w, t, dF ? &td : nullptr);
-        if (!ser) {
+        sg_F_cheb64(x, w, t, dF ? &td : nullptr);
+        if (mid) {
+            F = t;
+            if (dF) *dF = td;
+        }
+    }
+    if (__any(asy)) {
+        SG_NO_SPECULATE();
+        sg_F_asym64<ROLLED>(x, w, t, dF ? &td : nullptr);
+        if (asy) {
             F = t;
             if (dF) *dF = td;
         }
@@ -346,7 +398,7 @@ struct AsymCoefG0 {
 
 template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const double *w)
 {
-    if (!__all(x >= 40.0)) {  // branches as in sg_F64
+    if (!__all(x >= 40.0)) {  // the series below 2, the trapezoid (any x >= 2) above
         const bool ser = x < 2.0;
         double G = 0.0;
         if (__any(ser)) {
