@@ -11,22 +11,21 @@
 //           cancellations inside K0 and K1 - K0 cost at most a few ulps (in
 //           double they grow to 3e-14 just below x = 2, hence the Chebyshev
 //           branch above 1/2);
-//   x >= 2  F = sqrt(2) x^{-3/2} J(x)   (float: x >= 1),  J(x) = int_0^inf v^2 e^{-v^2}
+//   1 <= x < 32 (float)  F = sqrt(2) x^{-3/2} J(x),  J(x) = int_0^inf v^2 e^{-v^2}
 //           (1 + v^2/(2x))^{-1/2} dv, obtained from the integral
 //           representation K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt by
 //           the substitution sinh(t/2) = v / sqrt(2x).  The integrand is even
 //           and analytic for |Im v| < sqrt(2x), so the trapezoidal rule on a
 //           fixed grid converges geometrically, its error ~ exp(-2 pi
-//           sqrt(2x) / step): float uses step 1/2 and 9 nodes (2e-8 at x = 1,
-//           below a float ulp; the tail beyond v = 4.5 is e^{-20}).  Double
-//           (step 1/4, 26 nodes, error < 1e-20) keeps this rule only for the
-//           potential's G0 (below);
+//           sqrt(2x) / step): step 1/2 and 9 nodes (2e-8 at x = 1, below a
+//           float ulp; the tail beyond v = 4.5 is e^{-20});
 //   1/2 <= x < 32 (double) Chebyshev series of F and F' on the dyadic
 //           intervals [1/2, 1), [1, 2), ..., [16, 32), 27 terms each, their
 //           coefficients computed at build time in long double from the same
 //           integral representation (gen_cheb64.cpp; sg_cheb64.h): within
-//           4e-16 of F and F' over the range, at a tenth of the trapezoid's
-//           instructions (no square roots);
+//           7e-16 of F and F' over the range, with no square roots (a
+//           26-node trapezoid in double, used before, took a double
+//           reciprocal square root per node and ten times the instructions);
 //   x >= 32 the asymptotic series J = (sqrt(pi)/4)
 //           sum_n c_n x^-n, c_0 = 1, c_n = -c_{n-1} (4 n^2 - 1)/(8 n)
 //           (term-by-term integration of the binomial series; its first three
@@ -36,26 +35,25 @@
 //           omitted term, and so is J's: |c_17| 32^-17 = 1.3e-18 for F, and for F'
 //           (series differentiated term by term, two such pieces of one sign)
 //           |c_17| (17 + 3/2) / (3/2) 32^-17 = 1.7e-17 of its leading term.
-// The trapezoidal weights e^{-v_k^2} (and, for double, a copy of the
-// asymptotic coefficients for the rolled series and the Chebyshev
-// coefficients) are copied once per workgroup into LDS by sg_fill_weights().
+// The float trapezoidal weights e^{-v_k^2}, and for double the asymptotic
+// coefficients (for the rolled series) and the Chebyshev coefficients, are
+// copied once per workgroup into LDS by sg_fill_weights().
 #pragma once
 #include "sg_internal.h"
 #include "sg_cheb64.h"
 
 #define SG_EULER_GAMMA 0.57721566490153286061
 
-// Table of TABLE entries: w[k-1] = exp(-(k STEP)^2), k = 1..NODES; for double
-// then c_n (n = 0..ASYM), -(n + 3/2) c_n, the G0 coefficients a_n, and the
-// Chebyshev coefficients of F and of F' (SG_CHEB_NI intervals of SG_CHEB_M).
+// Table of TABLE entries.  Float: w[k-1] = exp(-(k STEP)^2), k = 1..NODES.
+// Double: c_n (n = 0..ASYM), -(n + 3/2) c_n, the G0 coefficients a_n, and the
+// Chebyshev coefficients of F, F' and G0 (SG_CHEB_NI intervals of SG_CHEB_M).
 template <typename R> struct FQuad;
 template <> struct FQuad<double> {
-    static constexpr int NODES = 26;
-    static constexpr double STEP = 0.25;
     static constexpr int ASYM = 16;
-    static constexpr int C = NODES, D = C + ASYM + 1, A = D + ASYM + 1;
+    static constexpr int C = 0, D = C + ASYM + 1, A = D + ASYM + 1;
     static constexpr int CH = A + ASYM + 1, CHD = CH + SG_CHEB_NI * SG_CHEB_M;
-    static constexpr int TABLE = CHD + SG_CHEB_NI * SG_CHEB_M;
+    static constexpr int CHG = CHD + SG_CHEB_NI * SG_CHEB_M;
+    static constexpr int TABLE = CHG + SG_CHEB_NI * SG_CHEB_M;
 };
 template <> struct FQuad<float> {
     static constexpr int NODES = 9;
@@ -95,18 +93,17 @@ struct AsymCoef64 {
 
 template <typename R> __device__ inline R sg_weight_entry(int k)
 {
-    if (k < FQuad<R>::NODES) {
-        const double v = (k + 1) * (double)FQuad<R>::STEP;
+    if constexpr (sizeof(R) == 4) {
+        const double v = (k + 1) * (double)FQuad<float>::STEP;
         return (R)exp(-v * v);
-    }
-    if constexpr (sizeof(R) == 8) {
+    } else {
         using Q = FQuad<double>;
+        if (k >= Q::CHG) return sg_cheb_g0[k - Q::CHG];
         if (k >= Q::CHD) return sg_cheb_df[k - Q::CHD];
         if (k >= Q::CH) return sg_cheb_f[k - Q::CH];
         constexpr AsymCoef64 C;
         return k >= Q::A ? C.a[k - Q::A] : k >= Q::D ? C.d[k - Q::D] : C.c[k - Q::C];
     }
-    return R(0);
 }
 
 // Call from every thread, then sync.
@@ -346,12 +343,15 @@ __device__ inline float sg_F32(float x, const float *w)
 // ------------------------------------------------------------------------
 // G0(x) = e^x K0(x), the kernel of the conservative potential (Sect. 5.5,
 // appendix "Conservative force"): P_ab(s) = -G0(d^2/8) / (2 sqrt(pi) H_ab).
-//   x < 2 (float: x < 1)  A&S series of I0 and K0, G0 = e^x K0;
-//   x >= 2 (float: 1 <= x < 32)  G0 = sqrt(2/x) int_0^inf e^{-v^2}
+//   x < 1/2 (float: x < 1)  A&S series of I0 and K0, G0 = e^x K0;
+//   1 <= x < 32 (float)  G0 = sqrt(2/x) int_0^inf e^{-v^2}
 //        (1 + v^2/(2x))^{-1/2} dv (the same substitution as for F; the
 //        trapezoid's v = 0 node has value 1 and weight STEP/2);
-//   x >= 32 (float), x >= 40 (double)  sqrt(pi/(2x)) sum_n a_n x^-n, a_0 = 1,
-//        a_n = -a_{n-1} (2n - 1)^2 / (8 n), through a_5 (float) or a_16.
+//   1/2 <= x < 32 (double)  Chebyshev series on the same dyadic intervals as
+//        F (gen_cheb64.cpp, from G0 = int_0^inf e^{-x (cosh t - 1)} dt);
+//   x >= 32  sqrt(pi/(2x)) sum_n a_n x^-n, a_0 = 1,
+//        a_n = -a_{n-1} (2n - 1)^2 / (8 n), through a_5 (float) or a_16
+//        (double: remainder 1.2e-16 at x = 32).
 // ------------------------------------------------------------------------
 template <typename R, int NT> __device__ inline R sg_G0_series(R x)
 {
@@ -393,26 +393,10 @@ struct AsymCoefG0 {
     }
 };
 
-// double, x >= 40: through a_16 (LDS table); K0's asymptotic remainder for
-// real x is bounded by the first omitted term, |a_17| 40^-17 = 3e-20.
-
-template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const double *w)
+// double, x >= 32: through a_16 (LDS table); K0's asymptotic remainder for
+// real x is bounded by the first omitted term.
+template <bool ROLLED> __device__ inline double sg_G0_asym64(double x, const double *w)
 {
-    if (!__all(x >= 40.0)) {  // the series below 2, the trapezoid (any x >= 2) above
-        const bool ser = x < 2.0;
-        double G = 0.0;
-        if (__any(ser)) {
-            SG_NO_SPECULATE();
-            const double t = sg_G0_series<double, 14>(x);
-            G = ser ? t : G;
-        }
-        if (__any(!ser)) {
-            SG_NO_SPECULATE();
-            const double t = sg_G0_quad<double>(x, w);
-            G = ser ? G : t;
-        }
-        return G;
-    }
     using Q = FQuad<double>;
     const double u = 1.0 / x;
     double s;
@@ -427,6 +411,52 @@ template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const
         for (int n = Q::ASYM - 1; n >= 0; --n) s = s * u + C.a[n];
     }
     return sqrt(SG_PI * 0.5 * u) * s;
+}
+
+// double, 1/2 <= x < 32: Clenshaw's recurrence over the G0 coefficients, with
+// the interval mapping of sg_F_cheb64.
+__device__ inline double sg_G0_cheb64(double x, const double *w)
+{
+    using Q = FQuad<double>;
+    int e;
+    const double m = frexp(x, &e);
+    const int k = min(max(e, 0), SG_CHEB_NI - 1);
+    const double t = 4.0 * m - 3.0, t2 = 2.0 * t;
+    const double *cg = w + Q::CHG + k * SG_CHEB_M;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll 3
+    for (int j = SG_CHEB_M - 1; j > 0; --j) {
+        const double b0 = fma(t2, b1, cg[j] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(t, b1, cg[0] - b2);
+}
+
+// Branches as in sg_F64_any: the asymptotic series alone when the whole wave
+// has x >= 32, else each of series, Chebyshev and asymptotic series runs when
+// some lane needs it.
+template <bool ROLLED = false> __device__ inline double sg_G0_64(double x, const double *w)
+{
+    if (__all(x >= 32.0)) return sg_G0_asym64<ROLLED>(x, w);
+    const bool ser = x < 0.5, asy = x >= 32.0, mid = !ser && !asy;
+    double G = 0.0;
+    if (__any(ser)) {
+        SG_NO_SPECULATE();
+        const double t = sg_G0_series<double, 10>(x);  // y = x^2/4 < 1/16
+        G = ser ? t : G;
+    }
+    if (__any(mid)) {
+        SG_NO_SPECULATE();
+        const double t = sg_G0_cheb64(x, w);
+        G = mid ? t : G;
+    }
+    if (__any(asy)) {
+        SG_NO_SPECULATE();
+        const double t = sg_G0_asym64<ROLLED>(x, w);
+        G = asy ? t : G;
+    }
+    return G;
 }
 
 // Branches as in sg_F32: run only when some lane of the wave needs them.

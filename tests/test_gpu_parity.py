@@ -84,7 +84,7 @@ def test_device_F64_large_argument(sg):
     e2 = float(np.max(np.abs(dF.cpu().numpy() / O.dF(x) - 1)))
     e3 = float(np.max(np.abs(G.cpu().numpy() / O.G0(x) - 1)))
     say(f"  x >= 0.45: max rel err F {e1:.2e} F' {e2:.2e} G0 {e3:.2e}")
-    assert e1 < 5e-15 and e2 < 5e-15 and e3 < 3e-14, (e1, e2, e3)
+    assert e1 < 5e-15 and e2 < 5e-15 and e3 < 5e-15, (e1, e2, e3)
 
 
 def test_device_F32_matches_oracle(sg):

@@ -29,7 +29,7 @@ def test_device_G0_matches_oracle(sg):
     print("G0 device vs oracle", flush=True)
     y = np.logspace(-12, 4.6, 300)
     ref = O.G0(y)
-    for dt, tdt, tol in ((sg.F64, torch.float64, 3e-14), (sg.F32, torch.float32, 1e-6)):
+    for dt, tdt, tol in ((sg.F64, torch.float64, 5e-15), (sg.F32, torch.float32, 1e-6)):
         x = torch.tensor(y, dtype=tdt, device="cuda")
         G = torch.empty_like(x)
         sg.eval_G0(x, G, dt)
