@@ -36,7 +36,8 @@ static void fdf(long double x, long double &F, long double &dF, long double &G)
     long double s = 0.0L, sd = 0.0L, sg = 0.0L;
     for (int k = 0;; ++k) {
         const long double t = k * h;
-        const long double c = coshl(t) - 1.0L;
+        const long double sh = sinhl(0.5L * t);
+        const long double c = 2.0L * sh * sh;  // cosh t - 1 without the cancellation
         const long double e = expl(-x * c);
         const long double wgt = k == 0 ? 0.5L : 1.0L;
         s += wgt * e * c;
