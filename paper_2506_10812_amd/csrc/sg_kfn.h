@@ -500,6 +500,39 @@ __device__ inline float sg_G0_32(float x, const float *w)
 //   d(h^2)/dh_a = h_a e^{-X},  d(h^2)/dh_b = h_b e^{X}.
 // sin(phi/2), sin(phi) are passed in so callers can use exact arguments.
 // ------------------------------------------------------------------------
+// The factors of sg_conv_kernel64 (which = 0) that depend on the row alone
+// (X, h_a, h_b): a semi-spectral operator row samples the kernel at N/2 + 1
+// azimuths with these fixed, so they are formed once per row.
+struct ConvRow64 {
+    double two_sxh2;  // 2 sinh^2(X/2) = cosh X - 1
+    double em1;       // e^X - 1
+    double inv4h2;    // 1 / (4 h_ab^2(X))
+    double pref;      // e^{-3X/2} / (8 sqrt(pi) h_ab^3)
+};
+
+__device__ inline ConvRow64 sg_conv_row64(double X, double ha, double hb)
+{
+    const double eX = exp(X);
+    const double h2 = 0.5 * (ha * ha / eX + hb * hb * eX);
+    const double sxh = sinh(0.5 * X);
+    ConvRow64 c;
+    c.two_sxh2 = 2.0 * sxh * sxh;
+    c.em1 = expm1(X);
+    c.inv4h2 = 1.0 / (4.0 * h2);
+    c.pref = exp(-1.5 * X) * (1.0 / (8.0 * SG_SQRT_PI)) / (h2 * sqrt(h2));
+    return c;
+}
+
+// sg_conv_kernel64 (which = 0) at one azimuth of a row.
+__device__ inline void sg_conv_kernel64_row(const ConvRow64 &c, double sphi_half, double sphi, const double *w,
+                                            double &Kr, double &Kp)
+{
+    const double two_s2 = 2.0 * sphi_half * sphi_half;
+    const double p = sg_F64((c.two_sxh2 + two_s2) * c.inv4h2, w) * c.pref;
+    Kr = p * (c.em1 + two_s2);
+    Kp = p * sphi;
+}
+
 __device__ inline void sg_conv_kernel64(double X, double sphi_half, double sphi, double ha,
                                         double hb, int which, const double *w, double &Kr,
                                         double &Kp)

@@ -183,20 +183,25 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
             if (q != 0 && q != N / 2) pl.st(N - q, make_double2(val[j].x, -val[j].y));
         }
     } else {
-    // 1. samples q in [0, N/2], mirrored into the upper half
+    // 1. samples q in [0, N/2], mirrored into the upper half; the factors that
+    // depend on the row alone are formed once
+    const ConvRow64 cr = sg_conv_row64(X, ha, hb);
+    const double sx = sinh(0.5 * X);
+    const double Hab2 = 0.5 * (ha * rp * ha * rp + hb * ri * hb * ri);
+    const double pot_pref = rp * rp / (2.0 * SG_SQRT_PI * sqrt(Hab2));
 #pragma unroll 1
     for (int q = t; q <= N / 2; q += T) {
         double kr = 0.0, kp = 0.0;
+        double sp, cp;
+        sincospi((double)q / N, &sp, &cp);
         if (ic == ip && q == 0) {
             kr = A.excl ? 0.0 : self[(size_t)(a * A.nf + b) * A.nr + ic];
         } else if (A.pot) {
             // -r'^2 P_ab(s), so that the common scale -du dphi / N gives A_i' P / N
-            const double sx = sinh(0.5 * X), sp = sinpi((double)q / N);
             const double s2 = 4.0 * ri * rp * (sx * sx + sp * sp);
-            const double Ha = ha * rp, Hb = hb * ri, Hab2 = 0.5 * (Ha * Ha + Hb * Hb);
-            kr = rp * rp * sg_G0_64(s2 / (8.0 * Hab2), wq) / (2.0 * SG_SQRT_PI * sqrt(Hab2));
+            kr = pot_pref * sg_G0_64(s2 / (8.0 * Hab2), wq);
         } else {
-            sg_conv_kernel64(X, sinpi((double)q / N), sinpi(2.0 * q / N), ha, hb, 0, wq, kr, kp);
+            sg_conv_kernel64_row(cr, sp, 2.0 * sp * cp, wq, kr, kp);
         }
         pl.st(q, make_double2(kr, kp));
         if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
