@@ -20,8 +20,9 @@
 //   1. self-cell averages Kbar_r per (pair, ring) with h = H/r at the ring
 //      (offset X = 0, phi = 0; zero with SG_SELF_CELL_EXCLUDE);
 //   2. per row (b, a, i', i): samples K_r + i K_phi at phi = q dphi for
-//      q <= n_phi/2, mirrored (K_r even, K_phi odd), one complex transform,
-//      T_r(m) = (Z[m] + Z[-m])/2, t_phi(m) = (Z[-m] - Z[m])/2 (real parts),
+//      q <= n_phi/2, mirrored (K_r even, K_phi odd), one complex transform
+//      (shared by two rows, whose transforms are real),
+//      T_r(m) = (Z[m] + Z[-m])/2, t_phi(m) = (Z[-m] - Z[m])/2,
 //      scaled by -du dphi / n_phi (the inverse transform of the last pass is
 //      unnormalised); rows are written [row][m] to a chunk buffer;
 //   3. a tiled transpose moves each chunk into the table: full modes keep
@@ -78,8 +79,14 @@ template <int N> struct SsRowShape {
     static constexpr int G = WGS / T;
 };
 
-// One group of T threads per row R = r0 + row of the (b, a, i', i) order
-// (i fastest).  out: [nrows][ncol] float2 (T_r, t_phi), m = 0 .. N/2.
+// A group of T threads takes RPG consecutive rows R = r0 + row of the
+// (b, a, i', i) order (i fastest), out: [nrows][ncol] float2 (T_r, t_phi),
+// m = 0 .. N/2.  Point-sampled rows go two to a group (RPG = 2): a row's
+// samples z = K_r + i K_phi are Hermitian in phi, so its transform Z is real,
+// and the group transforms z_A + i z_B once, reading Z_A from the real part
+// and Z_B from the imaginary part.  The row count is even (n_rt is) and so
+// is every chunk, so the two rows are always i and i + 1 of one (b, a, i').
+// Second-order rows (SO) keep one row per group.
 template <int N, bool SO>
 __global__ void __launch_bounds__(SsRowShape<N>::WGS)
 k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows, float2 *out)
@@ -87,6 +94,7 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     using S = SsRowShape<N>;
     constexpr int P = S::P, T = S::T, G = S::G, W = LdsPlane<double>::elems(N);
     constexpr int NC = N / 2 + 1;
+    constexpr int RPG = SO ? 1 : 2;
     __shared__ __attribute__((aligned(16))) double2 lds[W * G];
     __shared__ double wq[FQuad<double>::TABLE];
     __shared__ double2 qres[SO ? NC * G : 1];  // SO: the group's integrated samples
@@ -94,20 +102,33 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
     sg_fill_weights<double>(wq);
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const LdsPlane<double> pl{lds + W * g};
-    const int row = blockIdx.x * G + g;
+    const int row = (blockIdx.x * G + g) * RPG;  // the group's first row
     const bool valid = row < nrows;
     const size_t R = r0 + (size_t)(valid ? row : 0);
-    const int i = (int)(R % A.nrt);
+    const int i0 = (int)(R % A.nrt);
     size_t rest = R / A.nrt;
     const int ip = (int)(rest % A.nr);
     rest /= A.nr;
     const int a = (int)(rest % A.nf), b = (int)(rest / A.nf);
-    const bool live = valid && i < A.nr;  // padding target column stays zero
-    const int ic = i < A.nr ? i : A.nr - 1;
-    const double ri = A.lin ? A.rmin + (ic + 0.5) * A.dr : exp(A.lnrmin + (ic + 0.5) * A.du);
     const double rp = A.lin ? A.rmin + (ip + 0.5) * A.dr : exp(A.lnrmin + (ip + 0.5) * A.du);
-    const double ha = H[a * A.nr + ip] / rp, hb = H[b * A.nr + ic] / ri;
-    const double X = A.lin ? log(ri / rp) : (double)(ic - ip) * A.du;
+    const double ha = H[a * A.nr + ip] / rp;
+    // per row of the group: target ring (padding rows take the last ring and
+    // stay zero), its radius, h_b and X
+    bool live_[RPG];
+    int ic_[RPG];
+    double ri_[RPG], hb_[RPG], X_[RPG];
+#pragma unroll
+    for (int u = 0; u < RPG; ++u) {
+        const int iu = i0 + u;
+        live_[u] = valid && iu < A.nr;
+        ic_[u] = iu < A.nr ? iu : A.nr - 1;
+        ri_[u] = A.lin ? A.rmin + (ic_[u] + 0.5) * A.dr : exp(A.lnrmin + (ic_[u] + 0.5) * A.du);
+        hb_[u] = H[b * A.nr + ic_[u]] / ri_[u];
+        X_[u] = A.lin ? log(ri_[u] / rp) : (double)(ic_[u] - ip) * A.du;
+    }
+    const bool live = live_[0];
+    const int ic = ic_[0];
+    const double ri = ri_[0], hb = hb_[0], X = X_[0];
     __syncthreads();
     if constexpr (SO) {
         // 1'. hat-weighted samples (see SG_SS_HAT_NEAR): point values of K go
@@ -183,28 +204,40 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
             if (q != 0 && q != N / 2) pl.st(N - q, make_double2(val[j].x, -val[j].y));
         }
     } else {
-    // 1. samples q in [0, N/2], mirrored into the upper half; the factors that
-    // depend on the row alone are formed once
-    const ConvRow64 cr = sg_conv_row64(X, ha, hb);
-    const double sx = sinh(0.5 * X);
-    const double Hab2 = 0.5 * (ha * rp * ha * rp + hb * ri * hb * ri);
-    const double pot_pref = rp * rp / (2.0 * SG_SQRT_PI * sqrt(Hab2));
+    // 1. samples q in [0, N/2] of both rows, packed as z_A + i z_B and
+    // mirrored into the upper half (z(-q) = conj z(q) for each row); the
+    // factors that depend on a row alone are formed once
+    ConvRow64 cr[RPG];
+    double sx[RPG], Hab2[RPG], pot_pref[RPG];
+#pragma unroll
+    for (int u = 0; u < RPG; ++u) {
+        cr[u] = sg_conv_row64(X_[u], ha, hb_[u]);
+        sx[u] = sinh(0.5 * X_[u]);
+        Hab2[u] = 0.5 * (ha * rp * ha * rp + hb_[u] * ri_[u] * hb_[u] * ri_[u]);
+        pot_pref[u] = rp * rp / (2.0 * SG_SQRT_PI * sqrt(Hab2[u]));
+    }
 #pragma unroll 1
     for (int q = t; q <= N / 2; q += T) {
-        double kr = 0.0, kp = 0.0;
         double sp, cp;
         sincospi((double)q / N, &sp, &cp);
-        if (ic == ip && q == 0) {
-            kr = A.excl ? 0.0 : self[(size_t)(a * A.nf + b) * A.nr + ic];
-        } else if (A.pot) {
-            // -r'^2 P_ab(s), so that the common scale -du dphi / N gives A_i' P / N
-            const double s2 = 4.0 * ri * rp * (sx * sx + sp * sp);
-            kr = pot_pref * sg_G0_64(s2 / (8.0 * Hab2), wq);
-        } else {
-            sg_conv_kernel64_row(cr, sp, 2.0 * sp * cp, wq, kr, kp);
+        double kr[RPG], kp[RPG];
+#pragma unroll
+        for (int u = 0; u < RPG; ++u) {
+            kr[u] = 0.0;
+            kp[u] = 0.0;
+            if (ic_[u] == ip && q == 0) {
+                kr[u] = A.excl ? 0.0 : self[(size_t)(a * A.nf + b) * A.nr + ic_[u]];
+            } else if (A.pot) {
+                // -r'^2 P_ab(s), so that the common scale -du dphi / N gives A_i' P / N
+                const double s2 = 4.0 * ri_[u] * rp * (sx[u] * sx[u] + sp * sp);
+                kr[u] = pot_pref[u] * sg_G0_64(s2 / (8.0 * Hab2[u]), wq);
+            } else {
+                sg_conv_kernel64_row(cr[u], sp, 2.0 * sp * cp, wq, kr[u], kp[u]);
+            }
         }
-        pl.st(q, make_double2(kr, kp));
-        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr, -kp));
+        // (kr0 + i kp0) + i (kr1 + i kp1), and at -q (kr0 - i kp0) + i (kr1 - i kp1)
+        pl.st(q, make_double2(kr[0] - kp[1], kp[0] + kr[1]));
+        if (q != 0 && q != N / 2) pl.st(N - q, make_double2(kr[0] + kp[1], kr[1] - kp[0]));
     }
     }
     __syncthreads();
@@ -229,19 +262,23 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
         ind = rp * rp * SG_SQRT2 * (1.0 / SG_SQRT_PI) / (Ha * Ha) * (0.25 * d) * sg_F64(0.25 * d * d, wq) *
               (0.5 * N);
     }
-    float2 *o = out + (size_t)row * NC;
-    for (int m = t; m < NC; m += T) {
-        float2 v = make_float2(0.f, 0.f);
-        if (live) {
-            const double zm = pl.ld(m).x, zn = pl.ld((N - m) & (N - 1)).x;
-            double tr = 0.5 * (zm + zn), tp = A.pot ? 0.0 : 0.5 * (zn - zm);
-            if (m == 1) {
-                tr += ind;
-                tp += ind;
+#pragma unroll
+    for (int u = 0; u < RPG; ++u) {
+        float2 *o = out + (size_t)(row + u) * NC;
+        for (int m = t; m < NC; m += T) {
+            float2 v = make_float2(0.f, 0.f);
+            if (live_[u]) {
+                const double2 wm = pl.ld(m), wn = pl.ld((N - m) & (N - 1));
+                const double zm = u == 0 ? wm.x : wm.y, zn = u == 0 ? wn.x : wn.y;
+                double tr = 0.5 * (zm + zn), tp = A.pot ? 0.0 : 0.5 * (zn - zm);
+                if (m == 1) {
+                    tr += ind;
+                    tp += ind;
+                }
+                v = make_float2((float)(scale * tr), (float)(scale * tp));
             }
-            v = make_float2((float)(scale * tr), (float)(scale * tp));
+            gstore2(o, m, v);
         }
-        gstore2(o, m, v);
     }
 }
 
@@ -428,9 +465,9 @@ static void launch_ss_rows(const double *H, const double *self, const SsRowArgs 
     if (A.second)  // its own instance: the quadrature's registers stay out of the point-sampled rows
         hipLaunchKernelGGL((k_ss_rows<N, true>), dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self,
                            A, r0, nrows, out);
-    else
-        hipLaunchKernelGGL((k_ss_rows<N, false>), dim3((nrows + S::G - 1) / S::G), dim3(S::WGS), 0, s, H, self,
-                           A, r0, nrows, out);
+    else  // two rows per group (nrows is even: see k_ss_rows)
+        hipLaunchKernelGGL((k_ss_rows<N, false>), dim3((nrows + 2 * S::G - 1) / (2 * S::G)), dim3(S::WGS), 0, s,
+                           H, self, A, r0, nrows, out);
 }
 
 static bool dispatch_ss_rows(int nphi, const double *H, const double *self, const SsRowArgs &A, size_t r0,
