@@ -869,6 +869,16 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
+    # the second-order operators (hat weights) of the same disc: their build
+    S2 = T.SemiSpectral(nr, nphi, w["r_min"], w["r_max"], nf, sg.SECOND_ORDER, device=dev)
+    S2.refresh(w["H"])
+    torch.cuda.synchronize()
+    e0.record()
+    S2.refresh(w["H"])
+    e1.record()
+    torch.cuda.synchronize()
+    build2_ms = e0.elapsed_time(e1)
+    del S2
     adj_ms = rev_ms(lambda: sg.field_adjoint(S.disc, lam_r, lam_p, dsig, None, aws), 10)
     grad_ms = rev_ms(lambda: sg.ss_grad_H(S.disc, Hd, lam_r, lam_p, dH, gws), 3)
     del aws, gws
@@ -877,6 +887,7 @@ def semispectral_measurement(sg, T, W, dev, steps=20):
     ach = mid / (ms_pass[1] * 1e-3) / 1e9
     out = {"workload": f"App. D flaring gas disc {nr}x{nphi}, r in [20,250], p=0.25",
            "table_bytes": sg.ss_table_bytes(S.g, nf), "table_build_ms": round(build_ms, 2),
+           "second_order_table_build_ms": round(build2_ms, 2),
            "ms_per_step": round(ms, 4), "cells_per_s": round(nr * nphi / ms * 1e3, 1),
            "ms_per_pass": [round(v, 4) for v in ms_pass],
            "ms_per_pass_untuned": [round(v, 4) for v in ms_untuned],

@@ -165,21 +165,26 @@ k_ss_rows(const double *H, const double *self, SsRowArgs A, size_t r0, int nrows
             }
             __syncthreads();
         }
+        // the row-only factors at X and at the D_X neighbours X +- du
+        const ConvRow64 c0 = sg_conv_row64(X, ha, hb), c1 = sg_conv_row64(X + A.du, ha, hb),
+                        c2 = sg_conv_row64(X - A.du, ha, hb);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int q = t + T * j;
             val[j] = make_double2(0.0, 0.0);
             if (q > N / 2) continue;
-            const double sh = sinpi((double)q / N), s2 = sinpi(2.0 * q / N);
+            double sh, ch;
+            sincospi((double)q / N, &sh, &ch);
+            const double s2 = 2.0 * sh * ch;
             double kr = 0.0, kp = 0.0;
             if (q <= qn) {
                 val[j] = qres[g * NC + q];
-                if (Pr != 0 || q != 0) sg_conv_kernel64(X, sh, s2, ha, hb, 0, wq, kr, kp);
+                if (Pr != 0 || q != 0) sg_conv_kernel64_row(c0, sh, s2, wq, kr, kp);
             } else {
                 double k1r, k1p, k2r, k2p;
-                sg_conv_kernel64(X, sh, s2, ha, hb, 0, wq, kr, kp);
-                sg_conv_kernel64(X + A.du, sh, s2, ha, hb, 0, wq, k1r, k1p);
-                sg_conv_kernel64(X - A.du, sh, s2, ha, hb, 0, wq, k2r, k2p);
+                sg_conv_kernel64_row(c0, sh, s2, wq, kr, kp);
+                sg_conv_kernel64_row(c1, sh, s2, wq, k1r, k1p);
+                sg_conv_kernel64_row(c2, sh, s2, wq, k2r, k2p);
                 val[j] = make_double2(kr + (k1r - 2.0 * kr + k2r) / 12.0, kp + (k1p - 2.0 * kp + k2p) / 12.0);
                 taylor |= 1u << j;
             }
