@@ -575,9 +575,11 @@ __global__ void __launch_bounds__(256) k_adj_ind_sig(const sg_table_header *hd, 
 
 __global__ void k_adj_ind_dh(const sg_table_header *hd, const double *spart, int nb, int nf, double *dh)
 {
+    // the wave fills the coefficient table; lane 0 sums
+    __shared__ double w[FQuad<double>::TABLE];
+    sg_fill_weights<double>(w);
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    double w[FQuad<double>::TABLE];
-    for (int k = 0; k < FQuad<double>::TABLE; ++k) w[k] = sg_weight_entry<double>(k);
     const double du = log(hd->r_max / hd->r_min) / hd->n_r, dphi = 2.0 * SG_PI / hd->n_phi;
     for (int a = 0; a < nf; ++a) {
         double S = 0.0;

@@ -414,9 +414,12 @@ __global__ void k_pair_col(float2 *spec, int ncol, int npair, int kk)
 __global__ void k_header(sg_table_header *hd, sg_table_header proto, const double *selfbuf,
                          int npair, int with_dh)
 {
+    // one wave fills the coefficient table; lane 0 writes the header
+    __shared__ double w[FQuad<double>::TABLE];
+    sg_fill_weights<double>(w);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     sg_table_header h = proto;
-    double w[FQuad<double>::TABLE];
-    for (int k = 0; k < FQuad<double>::TABLE; ++k) w[k] = sg_weight_entry<double>(k);
     const double du = log(proto.r_max / proto.r_min) / proto.n_r;
     const double dphi = 2.0 * SG_PI / proto.n_phi;
     for (int a = 0; a < 4; ++a) {
@@ -687,7 +690,7 @@ sg_status sg_table_build(const sg_grid *grid, const sg_fluids *fl, uint32_t flag
     proto.r_min = grid->r_min;
     proto.r_max = grid->r_max;
     proto.total_bytes = L.total;
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(1), 0, s, (sg_table_header *)tb, proto, selfbuf,
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (sg_table_header *)tb, proto, selfbuf,
                        L.npair, with_dh ? 1 : 0);
     SG_HIP(hipGetLastError());
     return SG_OK;
